@@ -1,0 +1,354 @@
+"""FP64 CPU oracle for the Lagrangian-decomposition (LD) bounding step.
+
+TEST INFRASTRUCTURE ONLY.  This module is the plain, slow, obviously-correct
+reference that the GPU library is checked against.  Only the test-suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it; the
+product path never does.  It shares no code with the GPU library.
+
+Everything follows De Palma et al., "Improved Branch and Bound for Neural
+Network Verification via Lagrangian Decomposition":
+
+* the problem (Sec. 2.1, eq:noncvx_pb) with the objective folded as c^T y, i.e.
+  the dummy dual of the output layer is rho_n = -c (App. A / App. B use the same
+  convention with rho_n = -1 for a scalar output);
+* the LD dual q(rho) (Sec. 3.1, eq:nonprox_problem) and its decomposition over
+  the subproblems P_0 and P_k (App. A, eq:dual_decomp_vs_dj);
+* the inner minimisations: box solution of P_0 (Sec. 3.2.1, eq:box_bounds_sol),
+  vertex enumeration for ambiguous ReLUs (Sec. 3.2.2, eq:min-pk) and the box
+  solution for passing / blocking ReLUs (Sec. 3.2.2, "Non-ambiguous ReLUs");
+* the supergradient x_B* - x_A* (Algorithm 1, eq:subgradient_update) driven by
+  Adam with a linearly decaying step (Sec. 3.2 and Sec. 7.2);
+* initialisation from a propagation-based dual assignment (Prop. 2,
+  eq:salman-assignment) with CROWN slopes (Sec. 7.2; footnote of Sec. 4.2);
+* the upper bound from the network output at the last P_0 minimiser (Sec. 5.3.3).
+
+Readings where the paper is silent (all listed in the design doc):
+* Adam uses beta1=0.9, beta2=0.999, eps=1e-8 with bias correction, as ascent.
+* The step decays linearly from lr0 (step 1) to lr_end (step T).
+* ReLU status: passing if l >= 0, else blocking if u <= 0, else ambiguous.
+* Ties in the inner minimisation are broken towards the larger x_B, within a
+  relative band tau (0 gives the pure argmin); the value is always the exact min.
+
+Parity pins: every function here is checked in tests/test_oracle_pins.py against
+closed forms, brute force and the paper's identities (Prop. 1, Prop. 2, weak
+duality, Danskin's supergradient).  The final bound after T Adam steps has no
+value printed in the paper: "parity unpinned" beyond those inequalities.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional, Sequence
+
+import torch
+import torch.nn.functional as F
+
+DT = torch.float64
+TAU_DEFAULT = 2.0 ** -20
+
+
+# ----------------------------------------------------------------------------
+# network
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class OLayer:
+    """One affine layer W_k x + b_k (Sec. 2.1: fully connected or convolutional)."""
+    kind: str
+    W: torch.Tensor            # float64; linear [out, in]; conv [Co, Ci, kh, kw]
+    b: torch.Tensor            # float64 [Co]
+    in_shape: tuple
+    out_shape: tuple
+    stride: int = 1
+    pad: int = 0
+
+    def n_out(self):
+        return int(torch.tensor(self.out_shape).prod())
+
+    def bias_full(self) -> torch.Tensor:
+        """Bias of every output neuron in (C, H, W) order."""
+        if self.kind == "linear":
+            return self.b
+        C, H, W = self.out_shape
+        return self.b.repeat_interleave(H * W)
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        """x: [B, n_in] -> W x + b: [B, n_out]."""
+        if self.kind == "linear":
+            return x @ self.W.T + self.b
+        C, H, W = self.in_shape
+        y = F.conv2d(x.reshape(-1, C, H, W), self.W, self.b, stride=self.stride, padding=self.pad)
+        assert tuple(y.shape[1:]) == tuple(self.out_shape)
+        return y.reshape(x.shape[0], -1)
+
+    def transposed(self, r: torch.Tensor) -> torch.Tensor:
+        """r: [B, n_out] -> W^T r: [B, n_in] (the adjoint of the linear map, no bias)."""
+        if self.kind == "linear":
+            return r @ self.W
+        C, H, W = self.in_shape
+        Co, Ho, Wo = self.out_shape
+        kh = self.W.shape[2]
+        kw = self.W.shape[3]
+        # output_padding makes conv_transpose2d return exactly the input shape
+        oph = H - ((Ho - 1) * self.stride - 2 * self.pad + kh)
+        opw = W - ((Wo - 1) * self.stride - 2 * self.pad + kw)
+        g = F.conv_transpose2d(r.reshape(-1, Co, Ho, Wo), self.W, None, stride=self.stride,
+                               padding=self.pad, output_padding=(oph, opw))
+        assert tuple(g.shape[1:]) == (C, H, W)
+        return g.reshape(r.shape[0], -1)
+
+
+def net_from_specs(specs) -> List[OLayer]:
+    """Build oracle layers from generator LayerSpecs (float32 values taken exactly)."""
+    out = []
+    for s in specs:
+        out.append(OLayer(s.kind, torch.from_numpy(s.W).to(DT), torch.from_numpy(s.b).to(DT),
+                          tuple(s.in_shape), tuple(s.out_shape), int(s.stride), int(s.pad)))
+    return out
+
+
+@dataclasses.dataclass
+class OBatch:
+    """Per-subdomain data: input box C = [l0, u0] (Sec. 3.2.1), intermediate
+    bounds [l_k, u_k] for k = 1..n-1 (Sec. 2.2.1) and objective vector c."""
+    l0: torch.Tensor
+    u0: torch.Tensor
+    l: List[torch.Tensor]
+    u: List[torch.Tensor]
+    c: torch.Tensor
+
+
+def batch_from_instance(inst, idx: Optional[Sequence[int]] = None) -> OBatch:
+    def t(a):
+        x = torch.from_numpy(a).to(DT)
+        return x if idx is None else x[torch.as_tensor(list(idx))]
+    return OBatch(t(inst.l0), t(inst.u0), [t(a) for a in inst.l], [t(a) for a in inst.u], t(inst.c))
+
+
+# ----------------------------------------------------------------------------
+# inner minimisation (Sec. 3.2.1, 3.2.2)
+# ----------------------------------------------------------------------------
+def relu_status(l: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    """0 = passing (l >= 0), 1 = blocking (u <= 0), 2 = ambiguous (Sec. 2.2)."""
+    st = torch.full_like(l, 2, dtype=torch.int8)
+    st[u <= 0] = 1
+    st[l >= 0] = 0
+    return st
+
+
+def inner_min_p0(g0: torch.Tensor, l0: torch.Tensor, u0: torch.Tensor):
+    """min over x0 in [l0, u0] of -g0^T x0, with g0 = W_1^T rho_1 (eq:box_bounds_sol).
+
+    The minimiser takes u0 where g0 >= 0 and l0 where g0 < 0.
+    Returns (x0*, value per subdomain)."""
+    x0 = torch.where(g0 >= 0, u0, l0)
+    return x0, -(g0 * x0).sum(dim=1)
+
+
+def inner_min_pk(rho: torch.Tensor, g: torch.Tensor, l: torch.Tensor, u: torch.Tensor,
+                 tau: float = TAU_DEFAULT):
+    """Per-neuron minimum of  rho*xB - g*x  over the ReLU hull (eq:min-pk, eq:planet-relu-hull),
+    with g = (W_{k+1}^T rho_{k+1}).
+
+    ambiguous: vertices (l,0), (0,0), (u,u)  -> values rho*l, 0, (rho-g)*u
+    passing:   x = xB in [l, u]              -> box minimum of (rho-g)*xB
+    blocking:  x = 0, xB in [l, u]           -> box minimum of rho*xB
+    Returns (xB*, x*, value) elementwise.  Tie rule: the larger xB wins within a
+    band tau * (sum of the magnitudes involved); the value is the exact minimum.
+    """
+    st = relu_status(l, u)
+    zero = torch.zeros_like(rho)
+    # ambiguous
+    Vl = rho * l
+    Vu = (rho - g) * u
+    m = torch.minimum(torch.minimum(Vl, Vu), zero)
+    band = tau * (Vl.abs() + Vu.abs())
+    xb_amb = torch.where(Vu <= m + band, u, torch.where(zero <= m + band, zero, l))
+    # passing: coefficient (rho - g) on xB
+    cp = rho - g
+    xb_pass = torch.where(cp <= tau * (rho.abs() + g.abs()), u, l)
+    val_pass = torch.minimum(cp * l, cp * u)
+    # blocking: coefficient rho on xB
+    xb_blk = torch.where(rho <= 0, u, l)
+    val_blk = torch.minimum(rho * l, rho * u)
+    xb = torch.where(st == 0, xb_pass, torch.where(st == 1, xb_blk, xb_amb))
+    val = torch.where(st == 0, val_pass, torch.where(st == 1, val_blk, m))
+    x = torch.where(st == 1, zero, torch.clamp(xb, min=0.0))
+    return xb, x, val
+
+
+# ----------------------------------------------------------------------------
+# dual function q(rho) and its supergradient (eq:nonprox_problem, Algorithm 1)
+# ----------------------------------------------------------------------------
+def dual_eval(net: List[OLayer], batch: OBatch, rho: List[torch.Tensor], tau: float = TAU_DEFAULT,
+              need_supergrad: bool = True) -> Dict:
+    """q(rho) per subdomain, the inner minimisers and the supergradient.
+
+    rho[k-1] is the dual of hidden layer k (k = 1..n-1); rho_n = -c.
+    Decomposition (App. A): q = min_{P0}(-rho_1^T xA_1) + sum_k min_{P_k}(rho_k^T xB_k - rho_{k+1}^T xA_{k+1}),
+    with xA_{k+1} = W_{k+1} x_k + b_{k+1}; the bias terms give  -sum_{k=1}^{n} rho_k^T b_k.
+    """
+    n = len(net)
+    assert len(rho) == n - 1
+    duals = list(rho) + [-batch.c]                 # rho_1..rho_n
+    g = [net[k].transposed(duals[k]) for k in range(n)]   # g[k] = W_{k+1}^T rho_{k+1}, k = 0..n-1
+    x0, v0 = inner_min_p0(g[0], batch.l0, batch.u0)
+    q = v0.clone()
+    xB, xs, vals = [], [], []
+    for k in range(1, n):
+        xb, x, val = inner_min_pk(duals[k - 1], g[k], batch.l[k - 1], batch.u[k - 1], tau)
+        xB.append(xb)
+        xs.append(x)
+        vals.append(val)
+        q = q + val.sum(dim=1)
+    for k in range(1, n + 1):
+        q = q - (duals[k - 1] * net[k - 1].bias_full()).sum(dim=1)
+    out = dict(q=q, x0=x0, xB=xB, x=xs, vals=vals, v0=v0, g=g)
+    if need_supergrad:
+        prev = [x0] + xs
+        xA = [net[k - 1].forward(prev[k - 1]) for k in range(1, n)]   # xA_k, k = 1..n-1
+        out["xA"] = xA
+        out["s"] = [xB[k] - xA[k] for k in range(n - 1)]
+        out["xA_n"] = (batch.c * net[n - 1].forward(prev[n - 1])).sum(dim=1)
+    return out
+
+
+def q_scale(net: List[OLayer], batch: OBatch, rho: List[torch.Tensor], ev: Dict) -> torch.Tensor:
+    """Magnitude scale of the terms summed into q (used to state relative tolerances)."""
+    n = len(net)
+    duals = list(rho) + [-batch.c]
+    S = ev["v0"].abs()
+    for v in ev["vals"]:
+        S = S + v.abs().sum(dim=1)
+    for k in range(1, n + 1):
+        S = S + (duals[k - 1] * net[k - 1].bias_full()).abs().sum(dim=1)
+    return S
+
+
+# ----------------------------------------------------------------------------
+# initialisation (Prop. 2): dual assignment of a propagation method
+# ----------------------------------------------------------------------------
+def crown_slopes(l: torch.Tensor, u: torch.Tensor):
+    """CROWN relaxation slopes (upper: chord u/(u-l); lower: 1 if u >= -l else 0 for
+    ambiguous ReLUs; 1/1 passing; 0/0 blocking)."""
+    st = relu_status(l, u)
+    den = torch.where(st == 2, u - l, torch.ones_like(u))
+    a_up = torch.where(st == 2, u / den, torch.where(st == 0, torch.ones_like(u), torch.zeros_like(u)))
+    a_lo = torch.where(st == 2, (u >= -l).to(l.dtype), torch.where(st == 0, torch.ones_like(u), torch.zeros_like(u)))
+    return a_up, a_lo
+
+
+def propagation_duals(net: List[OLayer], batch: OBatch, slopes) -> List[torch.Tensor]:
+    """One backward pass (eq:salman-assignment) with the objective folded in:
+    lambda_{n-1} = W_n^T (-rho_n) ... written here directly on the LD duals:
+    rho_k = a_up [g_k]_+ + a_lo [g_k]_-,  g_k = W_{k+1}^T rho_{k+1},  rho_n = -c."""
+    n = len(net)
+    rho = [None] * (n - 1)
+    cur = -batch.c
+    for k in range(n - 1, 0, -1):               # hidden layer k
+        gk = net[k].transposed(cur)             # W_{k+1}^T rho_{k+1}
+        a_up, a_lo = slopes[k - 1]
+        rho[k - 1] = a_up * torch.clamp(gk, min=0) + a_lo * torch.clamp(gk, max=0)
+        cur = rho[k - 1]
+    return rho
+
+
+def crown_init(net: List[OLayer], batch: OBatch) -> List[torch.Tensor]:
+    slopes = [crown_slopes(l, u) for l, u in zip(batch.l, batch.u)]
+    return propagation_duals(net, batch, slopes)
+
+
+def zero_init(net, batch) -> List[torch.Tensor]:
+    return [torch.zeros_like(l) for l in batch.l]
+
+
+# ----------------------------------------------------------------------------
+# Adam supergradient ascent (Algorithm 1 with Adam, Sec. 3.2 / Sec. 7.2)
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class AdamOpts:
+    T: int = 500
+    lr0: float = 1e-2
+    lr_end: float = 1e-4
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    tau: float = TAU_DEFAULT
+    init: str = "crown"          # "crown" | "zero" | "given"
+
+
+def step_size(t: int, T: int, lr0: float, lr_end: float) -> float:
+    """Linear decay: step t (1-based) of T goes from lr0 (t=1) to lr_end (t=T)."""
+    if T <= 1:
+        return lr0
+    return lr0 + (lr_end - lr0) * (t - 1) / (T - 1)
+
+
+def ascent(net: List[OLayer], batch: OBatch, opts: AdamOpts, rho0: Optional[List[torch.Tensor]] = None,
+           state: Optional[Dict] = None, iters: Optional[int] = None, record: bool = False) -> Dict:
+    """Run `iters` Adam steps (default opts.T) of supergradient ascent on q.
+
+    `state` (rho, m, v, t, q0) lets a run continue where a previous call stopped;
+    the step schedule is always taken over opts.T total steps."""
+    if state is None:
+        if opts.init == "given":
+            assert rho0 is not None
+            rho = [r.clone() for r in rho0]
+        elif opts.init == "crown":
+            rho = crown_init(net, batch)
+        else:
+            rho = zero_init(net, batch)
+        q0 = dual_eval(net, batch, rho, opts.tau, need_supergrad=False)["q"]
+        state = dict(rho=rho, m=[torch.zeros_like(r) for r in rho], v=[torch.zeros_like(r) for r in rho],
+                     t=0, q0=q0)
+    else:
+        state = dict(rho=[r.clone() for r in state["rho"]], m=[r.clone() for r in state["m"]],
+                     v=[r.clone() for r in state["v"]], t=state["t"], q0=state["q0"])
+    iters = opts.T if iters is None else iters
+    traj = []
+    for _ in range(iters):
+        ev = dual_eval(net, batch, state["rho"], opts.tau)
+        if record:
+            traj.append(ev["q"].clone())
+        t = state["t"] + 1
+        a = step_size(t, opts.T, opts.lr0, opts.lr_end)
+        bc1 = 1.0 - opts.beta1 ** t
+        bc2 = 1.0 - opts.beta2 ** t
+        for k in range(len(state["rho"])):
+            s = ev["s"][k]
+            state["m"][k] = opts.beta1 * state["m"][k] + (1.0 - opts.beta1) * s
+            state["v"][k] = opts.beta2 * state["v"][k] + (1.0 - opts.beta2) * s * s
+            mh = state["m"][k] / bc1
+            vh = state["v"][k] / bc2
+            state["rho"][k] = state["rho"][k] + a * mh / (torch.sqrt(vh) + opts.eps)
+        state["t"] = t
+    state["traj"] = traj
+    return state
+
+
+def final_bound(net: List[OLayer], batch: OBatch, state: Dict, tau: float = TAU_DEFAULT) -> Dict:
+    """Bound returned by the method: q at the final duals (Algorithm 1 returns q(rho^T)),
+    the best of q(rho^0) and q(rho^T) (both valid by weak duality), and the network
+    value at the final P_0 minimiser (Sec. 5.3.3) with its feasibility flag."""
+    ev = dual_eval(net, batch, state["rho"], tau, need_supergrad=False)
+    p, feas = primal_value(net, batch, ev["x0"])
+    return dict(q_final=ev["q"], bound=torch.maximum(ev["q"], state["q0"]), primal=p, feasible=feas,
+                x0=ev["x0"])
+
+
+def primal_value(net: List[OLayer], batch: OBatch, x0: torch.Tensor):
+    """c^T f(x0) for the true ReLU network, and whether every pre-activation lies
+    within the subdomain's intermediate bounds (then it upper-bounds the subdomain)."""
+    x = x0
+    feas = torch.ones(x0.shape[0], dtype=torch.bool)
+    for k in range(len(net) - 1):
+        xh = net[k].forward(x)
+        feas &= ((xh >= batch.l[k]) & (xh <= batch.u[k])).all(dim=1)
+        x = torch.clamp(xh, min=0.0)
+    y = net[-1].forward(x)
+    return (batch.c * y).sum(dim=1), feas
+
+
+def network_output(net: List[OLayer], x0: torch.Tensor) -> torch.Tensor:
+    x = x0
+    for k in range(len(net) - 1):
+        x = torch.clamp(net[k].forward(x), min=0.0)
+    return net[-1].forward(x)
