@@ -1,0 +1,226 @@
+/*
+ * ld.h -- C ABI of the MI355X (gfx950) Lagrangian-decomposition bounding library.
+ *
+ * The library computes lower bounds for the neural-network verification problem
+ * of De Palma et al., "Improved Branch and Bound for Neural Network Verification
+ * via Lagrangian Decomposition":
+ *
+ *   min  c^T x_n   s.t.  x_0 in [l_0, u_0],
+ *                        xhat_k = W_k x_{k-1} + b_k,      k = 1..n
+ *                        x_k = max(xhat_k, 0),            k = 1..n-1
+ *
+ * (Sec. 2.1, eq:noncvx_pb; the property is folded into the objective vector c,
+ * which is the paper's canonical form with the dummy output dual rho_n = -c).
+ * Each hidden layer k carries intermediate bounds xhat_k in [l_k, u_k]
+ * (Sec. 2.2.3).  The bound is the Lagrangian-decomposition dual q(rho)
+ * (Sec. 3.1, eq:nonprox_problem), maximised by supergradient ascent with Adam
+ * steps (Algorithm 1, Sec. 3.2; Adam and the linear step decay of Sec. 7.2).
+ *
+ * Conventions shared by every entry point
+ *  - A "batch" is B independent subdomains of one network (Sec. 5.2.2: the branch-and-bound
+ *    framework bounds a batch of subproblems at once).  Every per-subdomain
+ *    array is row-major [B, n] with n the width of that layer; conv activations
+ *    are flattened in (C, H, W) order.
+ *  - Array arguments marked "device" are device pointers owned by the caller;
+ *    they must stay valid until the work enqueued on `stream` has completed.
+ *    Arrays marked "host" are read before the call returns.
+ *  - Work is enqueued on `stream` (0 = the null stream).  Functions that return
+ *    values to the host (status of validation) synchronise `stream` first.
+ *  - Every function returns LD_OK (0) or a negative error code; the message of
+ *    the last error on the calling thread is returned by ld_last_error().  No
+ *    C++ exception crosses this boundary.  Arguments are validated on the host
+ *    before anything is enqueued; a failed validation enqueues nothing.
+ *    Asynchronous device faults surface as LD_E_DEVICE on a later call.
+ *  - Calls that share one ld_net (or one ld_state) must not run concurrently:
+ *    the net holds a scratch workspace and the state holds the ascent buffers.
+ */
+#ifndef LD_H_
+#define LD_H_
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------- */
+/* status codes                                                              */
+/* ------------------------------------------------------------------------- */
+enum {
+  LD_OK = 0,
+  LD_E_ARG = -1,         /* null pointer, bad enum value, bad size               */
+  LD_E_SHAPE = -2,       /* inconsistent layer or batch shapes                   */
+  LD_E_NUMERIC = -3,     /* NaN/Inf in an input, or l > u somewhere              */
+  LD_E_NOMEM = -4,       /* device or host allocation failed                     */
+  LD_E_DEVICE = -5,      /* a HIP call failed (includes asynchronous faults)     */
+  LD_E_UNSUPPORTED = -6, /* valid request this build does not implement          */
+  LD_E_STATE = -7        /* state used with a different net or batch size        */
+};
+
+enum { LD_LINEAR = 0, LD_CONV2D = 1 };          /* layer kinds (Sec. 2.1)          */
+enum { LD_FP32 = 0, LD_BF16 = 1 };              /* operand precision of the contractions */
+enum { LD_INIT_CROWN = 0, LD_INIT_ZERO = 1, LD_INIT_GIVEN = 2 };
+
+/* ------------------------------------------------------------------------- */
+/* network                                                                   */
+/* ------------------------------------------------------------------------- */
+/* One affine layer xhat_k = W_k x_{k-1} + b_k (Sec. 2.1, fully connected or
+ * convolutional; Sec. 5.2 keeps convolutions as kernels, never as dense
+ * matrices).
+ *  LD_LINEAR: W is host [out_c, in_c*in_h*in_w] row-major, b host [out_c];
+ *             out_h = out_w = 1.  The input may be a flattened (C,H,W) map.
+ *  LD_CONV2D: W is host [out_c, in_c, kh, kw], b host [out_c] (one bias per
+ *             output channel, broadcast over H x W); zero padding `pad` and
+ *             `stride` on both axes; out_h = (in_h + 2 pad - kh) / stride + 1.
+ * Consecutive layers must agree in size (out of layer k = in of layer k+1).
+ * A ReLU follows every layer but the last. */
+typedef struct ld_layer {
+  int kind;
+  int in_c, in_h, in_w;
+  int out_c, out_h, out_w;
+  int kh, kw, stride, pad;
+  const float* W;
+  const float* b;
+} ld_layer;
+
+typedef struct ld_net ld_net;
+
+/* Validate the layer list (n_layers >= 2, the last layer LD_LINEAR, shapes
+ * chained, output-size formula for convs), copy the weights to the device and
+ * repack them into the tile-major FP32 and BF16 operand layouts the kernels
+ * use.  Synchronous.  *out receives a handle to free with ld_destroy_net. */
+int ld_create_net(const ld_layer* layers, int n_layers, ld_net** out);
+void ld_destroy_net(ld_net* net);
+
+/* Sizes: number of layers n, input width n_0, output width n_out, and the
+ * width of layer k (k = 1..n; width of layer 0 is n_0). */
+int ld_net_layer_width(const ld_net* net, int k, int* width);
+int ld_net_num_layers(const ld_net* net, int* n_layers);
+
+/* ------------------------------------------------------------------------- */
+/* batch of subdomains                                                       */
+/* ------------------------------------------------------------------------- */
+/* l0, u0 : device [B, n_0], the input box C = [l0, u0] (Sec. 3.2.1).
+ * l, u   : host arrays of n-1 device pointers; l[k-1], u[k-1] are [B, n_k],
+ *          the intermediate bounds of hidden layer k (Sec. 2.2.3).  A split
+ *          ReLU is expressed by l = 0 (active) or u = 0 (inactive) (Sec. 2.3.2).
+ * c      : device [B, n_out], the objective c^T x_n of each subdomain
+ *          (e.g. e_t - e_j for a robustness margin, Sec. 7.1).
+ * All values must be finite with l <= u (else LD_E_NUMERIC when validation is
+ * on).  ReLU status follows Sec. 2.3.2: passing if l >= 0, else blocking if
+ * u <= 0, else ambiguous. */
+typedef struct ld_batch {
+  int B;
+  const float* l0;
+  const float* u0;
+  const float* const* l;
+  const float* const* u;
+  const float* c;
+} ld_batch;
+
+/* Turn the device-side validation of batch values (finite, l <= u) on (1,
+ * default) or off (0) for this thread.  Validation costs one extra kernel and
+ * one synchronisation of `stream` per call; shapes are always checked. */
+void ld_set_validation(int on);
+
+/* ------------------------------------------------------------------------- */
+/* ascent state (duals rho_k, Adam moments, step counter)                    */
+/* ------------------------------------------------------------------------- */
+typedef struct ld_state ld_state;
+
+/* Device state for B subdomains of `net`: rho_k, m_k, v_k (FP32, [B, n_k] for
+ * k = 1..n-1), the step counter t, q(rho^0), and the workspace of the ascent.
+ * The state must be used with this net and batch size only (LD_E_STATE). */
+int ld_state_create(const ld_net* net, int B, ld_state** out);
+void ld_state_destroy(ld_state* st);
+/* Copy duals in (rho: host array of n-1 device pointers [B, n_k]); resets the
+ * Adam moments and t to 0 and marks the state as initialised, so that ld_step
+ * with init = LD_INIT_GIVEN continues from these duals (warm start from a
+ * parent subdomain, Sec. 8.2). */
+int ld_state_set_rho(ld_state* st, const float* const* rho, hipStream_t stream);
+/* Copy the current duals out (host array of n-1 device pointers). */
+int ld_state_get_rho(const ld_state* st, float* const* rho, hipStream_t stream);
+/* Number of Adam steps taken so far (synchronises `stream`). */
+int ld_state_get_step(const ld_state* st, hipStream_t stream, int* t);
+
+/* ------------------------------------------------------------------------- */
+/* dual initialisation (Prop. 2)                                              */
+/* ------------------------------------------------------------------------- */
+/* Dual point of the CROWN propagation bound: one backward pass
+ * rho_k = a_up [g_k]_+ + a_lo [g_k]_-,  g_k = W_{k+1}^T rho_{k+1}, rho_n = -c
+ * (eq:salman-assignment; slopes: chord upper slope u/(u-l), lower slope
+ * 1[u >= -l] for ambiguous ReLUs, Sec. 4.2 footnote), at which q equals the
+ * CROWN bound (Prop. 2).  init = LD_INIT_ZERO writes zeros.  rho: host array of
+ * n-1 device pointers [B, n_k] that receive the duals. */
+int ld_init_duals(const ld_net* net, const ld_batch* batch, int init, int precision,
+                  float* const* rho, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* dual evaluation (eq:nonprox_problem)                                       */
+/* ------------------------------------------------------------------------- */
+/* q(rho) for every subdomain, by the closed-form inner minimisations over P_0
+ * (box, eq:box_bounds_sol) and P_k (ReLU hull vertices, eq:min-pk), summed in
+ * FP64 (q: device double [B]).  If `supergrad` is not NULL (host array of n-1
+ * device pointers [B, n_k]) it receives the supergradient
+ * s_k = xhat_B,k* - xhat_A,k* (Algorithm 1).  rho: host array of n-1 device
+ * pointers [B, n_k].  `precision` selects the operand type of the
+ * contractions (the inner minimisation and the sum are FP32/FP64 regardless).
+ * Ties of the inner minimisation are broken towards the larger xhat_B within
+ * the relative band `tie_tau` (0 = exact argmin); the value is exact. */
+int ld_dual_eval(const ld_net* net, const ld_batch* batch, const float* const* rho,
+                 double* q, float* const* supergrad, int precision, float tie_tau,
+                 hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* ascent (Algorithm 1 with Adam)                                             */
+/* ------------------------------------------------------------------------- */
+/* iters       Adam steps to take in this call (>= 0)
+ * total_iters length of the step schedule: step t (1-based, counted over all
+ *             calls on this state) uses lr0 + (lr_end - lr0) (t-1)/(total_iters-1),
+ *             so several calls of k steps equal one call of their sum.
+ * beta1, beta2, eps  Adam constants; the update is an ascent step
+ *             rho += lr_t * mhat / (sqrt(vhat) + eps) with bias correction.
+ * precision   LD_FP32 or LD_BF16 (BF16 operands, FP32 accumulation) for the
+ *             contractions of the ascent; the bound is always re-evaluated with
+ *             FP32 operands and an FP64 sum (ld_final_bound).
+ * init        used on the first call of a state: LD_INIT_CROWN (default of
+ *             the paper, Sec. 7.2), LD_INIT_ZERO, or LD_INIT_GIVEN (duals set
+ *             by ld_state_set_rho).  On that call q(rho^0) is stored.
+ * tie_tau     relative tie band of the inner minimisation (2^-20 suggested). */
+typedef struct ld_opts {
+  int iters;
+  int total_iters;
+  float lr0, lr_end;
+  float beta1, beta2, eps;
+  int precision;
+  int init;
+  float tie_tau;
+} ld_opts;
+
+/* Enqueue `iters` Adam supergradient steps for every subdomain.  The loop is
+ * captured once per (state, batch pointers, options) into a HIP graph and
+ * replayed; capture, instantiation and tile autotuning happen on the first
+ * call with a new configuration. */
+int ld_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opts* opts,
+            hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* final bound (Algorithm 1's return value; upper bound of Sec. 5.1.3)        */
+/* ------------------------------------------------------------------------- */
+/* At the state's current duals: q_final = q(rho^T) with FP32 operands and an
+ * FP64 cross-layer sum; bound = max(q(rho^0), q(rho^T)) (both are valid lower
+ * bounds by weak duality, Sec. 3.1); primal = c^T f(x_0*) for the true ReLU
+ * network at the P_0 minimiser x_0*, an upper bound on the subdomain minimum
+ * when feasible = 1 (every pre-activation within [l_k, u_k]).  All outputs are
+ * device arrays of length B; any of them may be NULL. */
+int ld_final_bound(const ld_net* net, const ld_batch* batch, const ld_state* st, double* bound,
+                   double* q_final, double* primal, int* feasible, float tie_tau,
+                   hipStream_t stream);
+
+/* Message of the last error returned on this thread ("" if none). */
+const char* ld_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LD_H_ */

@@ -4,9 +4,9 @@ This module only builds *inputs*: network weights, input boxes, objective vector
 and intermediate pre-activation bounds.  It contains none of the bounding
 method's arithmetic; the intermediate bounds are produced by interval bound
 propagation from the root input box (the cheap "@root" recipe of the paper's
-branch-and-bound framework, Sec. 5.3.1), then each subdomain fixes a random 5 %
+branch-and-bound framework, Sec. 5.1.1), then each subdomain fixes a random 5 %
 of the root-ambiguous ReLUs to one phase by editing one side of its bound
-(ReLU branching, Sec. 2.2).  Everything is float32-representable so that any
+(ReLU branching, Sec. 2.3.2).  Everything is float32-representable so that any
 two implementations solve the identical instance.
 """
 from .instances import (Instance, LayerSpec, make_instance, CONFIGS, config_names, random_duals,

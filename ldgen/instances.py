@@ -73,7 +73,7 @@ class Instance:
 
 
 # ----------------------------------------------------------------------------
-# configurations (shapes follow the paper's OVAL networks, Sec. 7 / Table 3)
+# configurations (shapes follow the paper's OVAL networks, Sec. 8.1, table tab:oval-nets)
 # ----------------------------------------------------------------------------
 def _conv(ci, co, k, s, p, hw):
     ho = (hw + 2 * p - k) // s + 1

@@ -20,7 +20,7 @@ Network Verification via Lagrangian Decomposition":
   Adam with a linearly decaying step (Sec. 3.2 and Sec. 7.2);
 * initialisation from a propagation-based dual assignment (Prop. 2,
   eq:salman-assignment) with CROWN slopes (Sec. 7.2; footnote of Sec. 4.2);
-* the upper bound from the network output at the last P_0 minimiser (Sec. 5.3.3).
+* the upper bound from the network output at the last P_0 minimiser (Sec. 5.1.3).
 
 Readings where the paper is silent (all listed in the design doc):
 * Adam uses beta1=0.9, beta2=0.999, eps=1e-8 with bias correction, as ascent.
@@ -108,7 +108,7 @@ def net_from_specs(specs) -> List[OLayer]:
 @dataclasses.dataclass
 class OBatch:
     """Per-subdomain data: input box C = [l0, u0] (Sec. 3.2.1), intermediate
-    bounds [l_k, u_k] for k = 1..n-1 (Sec. 2.2.1) and objective vector c."""
+    bounds [l_k, u_k] for k = 1..n-1 (Sec. 2.2.3) and objective vector c."""
     l0: torch.Tensor
     u0: torch.Tensor
     l: List[torch.Tensor]
@@ -127,7 +127,7 @@ def batch_from_instance(inst, idx: Optional[Sequence[int]] = None) -> OBatch:
 # inner minimisation (Sec. 3.2.1, 3.2.2)
 # ----------------------------------------------------------------------------
 def relu_status(l: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
-    """0 = passing (l >= 0), 1 = blocking (u <= 0), 2 = ambiguous (Sec. 2.2)."""
+    """0 = passing (l >= 0), 1 = blocking (u <= 0), 2 = ambiguous (Sec. 2.3.2)."""
     st = torch.full_like(l, 2, dtype=torch.int8)
     st[u <= 0] = 1
     st[l >= 0] = 0
@@ -152,7 +152,8 @@ def inner_min_pk(rho: torch.Tensor, g: torch.Tensor, l: torch.Tensor, u: torch.T
     passing:   x = xB in [l, u]              -> box minimum of (rho-g)*xB
     blocking:  x = 0, xB in [l, u]           -> box minimum of rho*xB
     Returns (xB*, x*, value) elementwise.  Tie rule: the larger xB wins within a
-    band tau * (sum of the magnitudes involved); the value is the exact minimum.
+    band tau * (sum of the magnitudes of the terms compared); the value is the exact
+    minimum.
     """
     st = relu_status(l, u)
     zero = torch.zeros_like(rho)
@@ -160,7 +161,9 @@ def inner_min_pk(rho: torch.Tensor, g: torch.Tensor, l: torch.Tensor, u: torch.T
     Vl = rho * l
     Vu = (rho - g) * u
     m = torch.minimum(torch.minimum(Vl, Vu), zero)
-    band = tau * (Vl.abs() + Vu.abs())
+    # the band scales with the terms entering the values (rho*l, rho*u, g*u), so that
+    # the rounding of rho*u - g*u cannot hide a tie
+    band = tau * (Vl.abs() + (rho * u).abs() + (g * u).abs())
     xb_amb = torch.where(Vu <= m + band, u, torch.where(zero <= m + band, zero, l))
     # passing: coefficient (rho - g) on xB
     cp = rho - g
@@ -327,7 +330,7 @@ def ascent(net: List[OLayer], batch: OBatch, opts: AdamOpts, rho0: Optional[List
 def final_bound(net: List[OLayer], batch: OBatch, state: Dict, tau: float = TAU_DEFAULT) -> Dict:
     """Bound returned by the method: q at the final duals (Algorithm 1 returns q(rho^T)),
     the best of q(rho^0) and q(rho^T) (both valid by weak duality), and the network
-    value at the final P_0 minimiser (Sec. 5.3.3) with its feasibility flag."""
+    value at the final P_0 minimiser (Sec. 5.1.3) with its feasibility flag."""
     ev = dual_eval(net, batch, state["rho"], tau, need_supergrad=False)
     p, feas = primal_value(net, batch, ev["x0"])
     return dict(q_final=ev["q"], bound=torch.maximum(ev["q"], state["q0"]), primal=p, feasible=feas,

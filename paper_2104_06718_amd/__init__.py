@@ -1,0 +1,8 @@
+"""MI355X (gfx950) Lagrangian-decomposition bounding step.
+
+Python binding of the C ABI in include/ld.h: ``Net``, ``Batch``, ``State``,
+``init_duals``, ``dual_eval``, ``step`` and ``final_bound`` call the HIP
+library directly; ``LDDual`` wraps ``dual_eval`` as a torch.autograd.Function.
+"""
+from .binding import (Batch, LDError, Net, State, TAU_DEFAULT, dual_eval, final_bound, init_duals,  # noqa: F401
+                      load_library, set_validation, step)

@@ -1,0 +1,270 @@
+"""ctypes binding of the C ABI in include/ld.h (argument marshalling only).
+
+Every step of the bounding method runs in the HIP library; this module only
+turns torch tensors into device pointers and structs.  It fails loudly when the
+built library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libld_mi355x.so")
+
+LD_OK, LD_E_ARG, LD_E_SHAPE, LD_E_NUMERIC, LD_E_NOMEM, LD_E_DEVICE, LD_E_UNSUPPORTED, LD_E_STATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+LD_LINEAR, LD_CONV2D = 0, 1
+LD_FP32, LD_BF16 = 0, 1
+LD_INIT_CROWN, LD_INIT_ZERO, LD_INIT_GIVEN = 0, 1, 2
+TAU_DEFAULT = 2.0 ** -20
+
+_PREC = {"fp32": LD_FP32, "bf16": LD_BF16, LD_FP32: LD_FP32, LD_BF16: LD_BF16}
+_INIT = {"crown": LD_INIT_CROWN, "zero": LD_INIT_ZERO, "given": LD_INIT_GIVEN}
+
+EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num_layers",
+            "ld_set_validation", "ld_state_create", "ld_state_destroy", "ld_state_set_rho",
+            "ld_state_get_rho", "ld_state_get_step", "ld_init_duals", "ld_dual_eval", "ld_step",
+            "ld_final_bound", "ld_last_error"]
+
+
+class LDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"LD error {code}: {msg}")
+        self.code = code
+
+
+class ld_layer(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("in_c", ctypes.c_int), ("in_h", ctypes.c_int), ("in_w", ctypes.c_int),
+                ("out_c", ctypes.c_int), ("out_h", ctypes.c_int), ("out_w", ctypes.c_int), ("kh", ctypes.c_int),
+                ("kw", ctypes.c_int), ("stride", ctypes.c_int), ("pad", ctypes.c_int),
+                ("W", ctypes.c_void_p), ("b", ctypes.c_void_p)]
+
+
+class ld_batch(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int), ("l0", ctypes.c_void_p), ("u0", ctypes.c_void_p),
+                ("l", ctypes.POINTER(ctypes.c_void_p)), ("u", ctypes.POINTER(ctypes.c_void_p)),
+                ("c", ctypes.c_void_p)]
+
+
+class ld_opts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("total_iters", ctypes.c_int), ("lr0", ctypes.c_float),
+                ("lr_end", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("precision", ctypes.c_int), ("init", ctypes.c_int),
+                ("tie_tau", ctypes.c_float)]
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load the built shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} not found: build the HIP library first "
+                          f"(python -m paper_2104_06718_amd.build or __graft_entry__.build())")
+    lib = ctypes.CDLL(p)
+    V, I, P = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER
+    lib.ld_last_error.restype = ctypes.c_char_p
+    lib.ld_create_net.argtypes = [P(ld_layer), I, P(V)]
+    lib.ld_destroy_net.argtypes = [V]
+    lib.ld_destroy_net.restype = None
+    lib.ld_net_layer_width.argtypes = [V, I, P(I)]
+    lib.ld_net_num_layers.argtypes = [V, P(I)]
+    lib.ld_set_validation.argtypes = [I]
+    lib.ld_set_validation.restype = None
+    lib.ld_state_create.argtypes = [V, I, P(V)]
+    lib.ld_state_destroy.argtypes = [V]
+    lib.ld_state_destroy.restype = None
+    lib.ld_state_set_rho.argtypes = [V, P(V), V]
+    lib.ld_state_get_rho.argtypes = [V, P(V), V]
+    lib.ld_state_get_step.argtypes = [V, V, P(I)]
+    lib.ld_init_duals.argtypes = [V, P(ld_batch), I, I, P(V), V]
+    lib.ld_dual_eval.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
+    lib.ld_step.argtypes = [V, P(ld_batch), V, P(ld_opts), V]
+    lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
+    for name in EXPORTED:
+        getattr(lib, name)
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != LD_OK:
+        raise LDError(rc, load_library().ld_last_error().decode())
+
+
+def _ptrs(tensors: Sequence[Optional[torch.Tensor]]):
+    arr = (ctypes.c_void_p * max(len(tensors), 1))()
+    for i, t in enumerate(tensors):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    return t
+
+
+class Net:
+    """A ReLU network (list of layer dicts/specs), copied to the device by ld_create_net.
+
+    Each layer: kind ('linear' | 'conv'), W, b (host float32 arrays),
+    in_shape (C,H,W), out_shape (C,H,W), stride, pad.
+    """
+
+    def __init__(self, layers):
+        import numpy as np
+        self.lib = load_library()
+        arr = (ld_layer * len(layers))()
+        self._keep = []
+        self.widths = []
+        for i, L in enumerate(layers):
+            get = (lambda k: L[k]) if isinstance(L, dict) else (lambda k: getattr(L, k))
+            W = np.ascontiguousarray(np.asarray(get("W"), dtype=np.float32))
+            b = np.ascontiguousarray(np.asarray(get("b"), dtype=np.float32))
+            self._keep += [W, b]
+            ins, outs = tuple(get("in_shape")), tuple(get("out_shape"))
+            kind = get("kind")
+            a = arr[i]
+            a.kind = LD_LINEAR if kind == "linear" else LD_CONV2D
+            a.in_c, a.in_h, a.in_w = ins
+            a.out_c, a.out_h, a.out_w = outs
+            if kind == "linear":
+                a.kh = a.kw = a.stride = 1
+                a.pad = 0
+            else:
+                a.kh, a.kw = W.shape[2], W.shape[3]
+                a.stride, a.pad = int(get("stride")), int(get("pad"))
+            a.W = W.ctypes.data
+            a.b = b.ctypes.data
+        h = ctypes.c_void_p()
+        _check(self.lib.ld_create_net(arr, len(layers), ctypes.byref(h)))
+        self.handle = h
+        self.n = len(layers)
+        w = ctypes.c_int()
+        self.widths = []
+        for k in range(self.n + 1):
+            _check(self.lib.ld_net_layer_width(h, k, ctypes.byref(w)))
+            self.widths.append(w.value)
+        self._keep = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.ld_destroy_net(h)
+            self.handle = None
+
+
+class Batch:
+    """Device arrays of B subdomains (float32 CUDA tensors; see ld_batch in include/ld.h)."""
+
+    def __init__(self, l0, u0, l, u, c):
+        self.l0 = _dev_f32(l0, "l0")
+        self.u0 = _dev_f32(u0, "u0")
+        self.l = [_dev_f32(t, "l[k]") for t in l]
+        self.u = [_dev_f32(t, "u[k]") for t in u]
+        self.c = _dev_f32(c, "c")
+        self.B = int(l0.shape[0])
+        self._la = _ptrs(self.l)
+        self._ua = _ptrs(self.u)
+        self.struct = ld_batch(self.B, self.l0.data_ptr(), self.u0.data_ptr(),
+                               ctypes.cast(self._la, ctypes.POINTER(ctypes.c_void_p)),
+                               ctypes.cast(self._ua, ctypes.POINTER(ctypes.c_void_p)), self.c.data_ptr())
+
+    @staticmethod
+    def from_instance(inst, device="cuda"):
+        t = lambda a: torch.from_numpy(a).to(device)  # noqa: E731
+        return Batch(t(inst.l0), t(inst.u0), [t(a) for a in inst.l], [t(a) for a in inst.u], t(inst.c))
+
+
+class State:
+    """Ascent state (rho, Adam moments, step counter) of B subdomains."""
+
+    def __init__(self, net: Net, B: int):
+        self.lib = net.lib
+        self.net = net
+        self.B = B
+        h = ctypes.c_void_p()
+        _check(self.lib.ld_state_create(net.handle, B, ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.ld_state_destroy(h)
+            self.handle = None
+
+    def set_rho(self, rho: List[torch.Tensor], stream=None):
+        _check(self.lib.ld_state_set_rho(self.handle, _ptrs([_dev_f32(r, "rho") for r in rho]), _stream(stream)))
+
+    def get_rho(self, stream=None) -> List[torch.Tensor]:
+        out = [torch.empty((self.B, w), device="cuda", dtype=torch.float32) for w in self.net.widths[1:-1]]
+        _check(self.lib.ld_state_get_rho(self.handle, _ptrs(out), _stream(stream)))
+        return out
+
+    def step_count(self, stream=None) -> int:
+        t = ctypes.c_int()
+        _check(self.lib.ld_state_get_step(self.handle, _stream(stream), ctypes.byref(t)))
+        return t.value
+
+
+def set_validation(on: bool):
+    load_library().ld_set_validation(1 if on else 0)
+
+
+def init_duals(net: Net, batch: Batch, init="crown", precision="fp32", stream=None) -> List[torch.Tensor]:
+    out = [torch.empty((batch.B, w), device="cuda", dtype=torch.float32) for w in net.widths[1:-1]]
+    _check(net.lib.ld_init_duals(net.handle, ctypes.byref(batch.struct), _INIT[init], _PREC[precision],
+                                 _ptrs(out), _stream(stream)))
+    return out
+
+
+def dual_eval(net: Net, batch: Batch, rho: List[torch.Tensor], supergrad=True, precision="fp32",
+              tau: float = TAU_DEFAULT, stream=None):
+    """q(rho) [B] (float64) and, if requested, the supergradient per hidden layer."""
+    q = torch.empty(batch.B, device="cuda", dtype=torch.float64)
+    rho = [_dev_f32(r, "rho") for r in rho]
+    s = None
+    sp = None
+    if supergrad:
+        s = [torch.empty_like(r) for r in rho]
+        sp = _ptrs(s)
+    _check(net.lib.ld_dual_eval(net.handle, ctypes.byref(batch.struct), _ptrs(rho), ctypes.c_void_p(q.data_ptr()),
+                                sp, _PREC[precision], ctypes.c_float(tau), _stream(stream)))
+    return q, s
+
+
+def step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional[int] = None, lr0=1e-2,
+         lr_end=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, precision="fp32", init="crown",
+         tau: float = TAU_DEFAULT, stream=None):
+    o = ld_opts(int(iters), int(total_iters if total_iters is not None else iters), lr0, lr_end, beta1, beta2,
+                eps, _PREC[precision], _INIT[init], tau)
+    _check(net.lib.ld_step(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o), _stream(stream)))
+
+
+def final_bound(net: Net, batch: Batch, state: State, tau: float = TAU_DEFAULT, stream=None):
+    B = batch.B
+    d = dict(bound=torch.empty(B, device="cuda", dtype=torch.float64),
+             q_final=torch.empty(B, device="cuda", dtype=torch.float64),
+             primal=torch.empty(B, device="cuda", dtype=torch.float64),
+             feasible=torch.empty(B, device="cuda", dtype=torch.int32))
+    _check(net.lib.ld_final_bound(net.handle, ctypes.byref(batch.struct), state.handle,
+                                  *(ctypes.c_void_p(d[k].data_ptr()) for k in ("bound", "q_final", "primal",
+                                                                               "feasible")),
+                                  ctypes.c_float(tau), _stream(stream)))
+    return d

@@ -1,0 +1,943 @@
+// Host side of the C ABI declared in include/ld.h.
+//
+// Builds the contraction plan of a network (forward and stride-class transposed
+// implicit GEMMs per layer, packed FP32/BF16 weight operands), validates
+// arguments, owns device workspaces, and sequences the kernels of one ascent
+// iteration:
+//   phase A  (Algorithm 1, inner minimisation): g_{k-1} = W_k^T rho_k for every
+//            hidden layer k, each fused with the P_{k-1} minimisation
+//            (P_0: eq:box_bounds_sol; P_k: eq:min-pk); the last hidden layer
+//            uses the constant g_{n-1} = -W_n^T c.
+//   phase B  (supergradient step): xhat_A,k = W_k x*_{k-1} + b_k fused with
+//            s_k = xhat_B,k - xhat_A,k and the Adam ascent step on rho_k.
+// The iterations of ld_step are captured once into a HIP graph and replayed.
+#include "ld.h"
+#include "ld_internal.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace ld;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local int g_validate = 1;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define LD_HIP(expr)                                                                               \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return fail(LD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LD_TRY(expr)          \
+  do {                        \
+    int rc_ = (expr);         \
+    if (rc_ != LD_OK) return rc_; \
+  } while (0)
+
+size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+uint16_t host_f2bf(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// One contraction of a layer: one GemmGeom per stride class (M is set per launch).
+struct Job {
+  std::vector<GemmGeom> geoms;
+};
+
+struct Layer {
+  int kind;
+  int in_c, in_h, in_w, out_c, out_h, out_w, kh, kw, stride, pad;
+  int n_in, n_out;
+  float* bias = nullptr;  // device [out_c]
+  Job fwd, tr;
+};
+
+// Buffers of one evaluation pipeline for a batch of B subdomains.
+struct Workspace {
+  int B = 0;
+  void* base = nullptr;
+  std::vector<void*> xs;      // x*_k, k = 0..n-2 (FP32-sized; BF16 uses the first half)
+  std::vector<float*> xb;     // xB*_k, index k = 1..n-1 (entry 0 unused)
+  std::vector<double*> val;   // per-neuron FP64 values, k = 0..n-1
+  float* gconst = nullptr;    // -W_n^T c   [B, n_{n-1}]
+  double* cb = nullptr;       // c . b_n    [B]
+  float* act0 = nullptr;      // forward-pass activations [B, max width]
+  float* act1 = nullptr;
+  double* qtmp = nullptr;     // [B]
+  int* flag = nullptr;        // [B]
+  int* bad = nullptr;         // [1]
+};
+
+}  // namespace
+
+struct ld_net {
+  int n = 0;
+  int n0 = 0;
+  int max_width = 0;
+  std::vector<Layer> L;
+  std::vector<void*> allocs;
+  Workspace ws;
+  std::map<std::tuple<int, int, int, int>, Tile> tiles;  // (layer, dir, B, mma) -> tile
+  std::mutex mu;
+};
+
+struct ld_state {
+  const ld_net* net = nullptr;
+  int B = 0;
+  void* base = nullptr;
+  std::vector<float*> rho, m, v;  // hidden layers k = 1..n-1 at index k-1
+  int* t_dev = nullptr;
+  float* adam = nullptr;          // 8 floats
+  double* q0 = nullptr;
+  bool initialized = false;
+  Workspace ws;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<double> gkey;
+  int gchunk = 0;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// plan construction
+// ---------------------------------------------------------------------------
+int alloc_dev(ld_net* net, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail(LD_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  net->allocs.push_back(*p);
+  return LD_OK;
+}
+
+// Pack an [N][K] operand (column n holds the K weights reducing into output n),
+// zero padded to [Np][Kp], in FP32 and BF16, plus the gather table.
+int finish_geom(ld_net* net, GemmGeom& g, const std::vector<float>& Bnk, const std::vector<int4>& ktab) {
+  g.Kp = (int)round_up((size_t)std::max(g.K, 1), 64);
+  g.Np = (int)round_up((size_t)std::max(g.N, 1), 128);
+  std::vector<float> bf((size_t)g.Np * g.Kp, 0.f);
+  std::vector<uint16_t> bh((size_t)g.Np * g.Kp, 0);
+  for (int n = 0; n < g.N; ++n)
+    for (int k = 0; k < g.K; ++k) {
+      const float w = Bnk[(size_t)n * g.K + k];
+      bf[(size_t)n * g.Kp + k] = w;
+      bh[(size_t)n * g.Kp + k] = host_f2bf(w);
+    }
+  std::vector<int4> kt((size_t)g.Kp, int4{0, 0, 0, 0});
+  for (int k = 0; k < g.K; ++k) kt[k] = ktab[k];
+  void *pf, *ph, *pk;
+  LD_TRY(alloc_dev(net, &pf, bf.size() * 4));
+  LD_TRY(alloc_dev(net, &ph, bh.size() * 2));
+  LD_TRY(alloc_dev(net, &pk, kt.size() * sizeof(int4)));
+  LD_HIP(hipMemcpy(pf, bf.data(), bf.size() * 4, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(ph, bh.data(), bh.size() * 2, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(pk, kt.data(), kt.size() * sizeof(int4), hipMemcpyHostToDevice));
+  g.Bf = (const float*)pf;
+  g.Bh = (const bf16_t*)ph;
+  g.ktab = (const int4*)pk;
+  return LD_OK;
+}
+
+GemmGeom base_geom() {
+  GemmGeom g;
+  std::memset(&g, 0, sizeof(g));
+  g.HWq = 1;
+  g.Wq = 1;
+  g.src_H = 1;
+  g.src_W = 1;
+  g.dst_HW = 1;
+  g.dst_W = 1;
+  return g;
+}
+
+int build_linear(ld_net* net, Layer& L, const float* W) {
+  const int ni = L.n_in, no = L.n_out;
+  // forward: rows = subdomains, columns = output neurons, k = input neuron
+  {
+    GemmGeom g = base_geom();
+    g.src_n = ni;
+    g.K = ni;
+    g.N = no;
+    g.dst_n = no;
+    g.m_fast = 0;
+    std::vector<float> Bnk((size_t)no * ni);
+    std::vector<int4> kt(ni);
+    for (int o = 0; o < no; ++o)
+      for (int i = 0; i < ni; ++i) Bnk[(size_t)o * ni + i] = W[(size_t)o * ni + i];
+    for (int i = 0; i < ni; ++i) kt[i] = int4{i, 0, 0, 0};
+    LD_TRY(finish_geom(net, g, Bnk, kt));
+    L.fwd.geoms = {g};
+  }
+  // transposed: columns = input neurons, k = output neuron
+  {
+    GemmGeom g = base_geom();
+    g.src_n = no;
+    g.K = no;
+    g.N = ni;
+    g.dst_n = ni;
+    g.m_fast = 0;
+    std::vector<float> Bnk((size_t)ni * no);
+    std::vector<int4> kt(no);
+    for (int i = 0; i < ni; ++i)
+      for (int o = 0; o < no; ++o) Bnk[(size_t)i * no + o] = W[(size_t)o * ni + i];
+    for (int o = 0; o < no; ++o) kt[o] = int4{o, 0, 0, 0};
+    LD_TRY(finish_geom(net, g, Bnk, kt));
+    L.tr.geoms = {g};
+  }
+  return LD_OK;
+}
+
+int build_conv(ld_net* net, Layer& L, const float* W) {
+  const int Ci = L.in_c, H = L.in_h, Wd = L.in_w, Co = L.out_c, OH = L.out_h, OW = L.out_w;
+  const int kh = L.kh, kw = L.kw, s = L.stride, p = L.pad;
+  auto w_at = [&](int co, int ci, int ky, int kx) { return W[(((size_t)co * Ci + ci) * kh + ky) * kw + kx]; };
+  // forward: rows (b, oy, ox), columns co, k = (ci, ky, kx)
+  {
+    GemmGeom g = base_geom();
+    g.HWq = OH * OW;
+    g.Wq = OW;
+    g.iy_mul = s;
+    g.iy_off = -p;
+    g.ix_mul = s;
+    g.ix_off = -p;
+    g.src_H = H;
+    g.src_W = Wd;
+    g.src_n = Ci * H * Wd;
+    g.K = Ci * kh * kw;
+    g.N = Co;
+    g.dst_n = Co * OH * OW;
+    g.dst_HW = OH * OW;
+    g.dst_W = OW;
+    g.oy_mul = 1;
+    g.ox_mul = 1;
+    g.m_fast = 1;
+    std::vector<float> Bnk((size_t)Co * g.K);
+    std::vector<int4> kt(g.K);
+    for (int ci = 0; ci < Ci; ++ci)
+      for (int ky = 0; ky < kh; ++ky)
+        for (int kx = 0; kx < kw; ++kx) {
+          const int k = (ci * kh + ky) * kw + kx;
+          kt[k] = int4{ci * H * Wd, ky, kx, 0};
+          for (int co = 0; co < Co; ++co) Bnk[(size_t)co * g.K + k] = w_at(co, ci, ky, kx);
+        }
+    LD_TRY(finish_geom(net, g, Bnk, kt));
+    L.fwd.geoms = {g};
+  }
+  // transposed, one GEMM per output-pixel class (ry, rx): input pixel y = y'*s + ry receives
+  // the taps ky = ky0 + s*ty with ky0 = (ry + p) mod s, from output row oy = y' + dy - ty,
+  // dy = (ry + p - ky0) / s.
+  L.tr.geoms.clear();
+  for (int ry = 0; ry < s; ++ry)
+    for (int rx = 0; rx < s; ++rx) {
+      const int Hq = (H - ry + s - 1) / s;
+      const int Wq = (Wd - rx + s - 1) / s;
+      if (Hq <= 0 || Wq <= 0) continue;
+      const int ky0 = (ry + p) % s, kx0 = (rx + p) % s;
+      const int dy = (ry + p - ky0) / s, dx = (rx + p - kx0) / s;
+      const int Ty = kh > ky0 ? (kh - ky0 + s - 1) / s : 0;
+      const int Tx = kw > kx0 ? (kw - kx0 + s - 1) / s : 0;
+      GemmGeom g = base_geom();
+      g.HWq = Hq * Wq;
+      g.Wq = Wq;
+      g.iy_mul = 1;
+      g.iy_off = dy;
+      g.ix_mul = 1;
+      g.ix_off = dx;
+      g.src_H = OH;
+      g.src_W = OW;
+      g.src_n = Co * OH * OW;
+      g.K = Co * Ty * Tx;
+      g.N = Ci;
+      g.dst_n = Ci * H * Wd;
+      g.dst_HW = H * Wd;
+      g.dst_W = Wd;
+      g.oy_mul = s;
+      g.oy_off = ry;
+      g.ox_mul = s;
+      g.ox_off = rx;
+      g.m_fast = 1;
+      std::vector<float> Bnk((size_t)Ci * std::max(g.K, 1), 0.f);
+      std::vector<int4> kt(std::max(g.K, 1), int4{0, 0, 0, 0});
+      for (int co = 0; co < Co; ++co)
+        for (int ty = 0; ty < Ty; ++ty)
+          for (int tx = 0; tx < Tx; ++tx) {
+            const int k = (co * Ty + ty) * Tx + tx;
+            kt[k] = int4{co * OH * OW, -ty, -tx, 0};
+            for (int ci = 0; ci < Ci; ++ci) Bnk[(size_t)ci * g.K + k] = w_at(co, ci, ky0 + s * ty, kx0 + s * tx);
+          }
+      LD_TRY(finish_geom(net, g, Bnk, kt));
+      L.tr.geoms.push_back(g);
+    }
+  if ((int)L.tr.geoms.size() > 9) return fail(LD_E_UNSUPPORTED, "conv stride above 3 is not supported");
+  return LD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspaces
+// ---------------------------------------------------------------------------
+int width(const ld_net* net, int k) { return k == 0 ? net->n0 : net->L[k - 1].n_out; }
+
+int ws_alloc(const ld_net* net, Workspace& ws, int B) {
+  if (ws.base && ws.B >= B) return LD_OK;
+  if (ws.base) {
+    (void)hipFree(ws.base);
+    ws.base = nullptr;
+  }
+  const int n = net->n;
+  std::vector<size_t> sizes;
+  auto add = [&](size_t bytes) {
+    sizes.push_back(round_up(std::max<size_t>(bytes, 1), 256));
+    return sizes.size() - 1;
+  };
+  std::vector<size_t> ixs, ixb, ival;
+  for (int k = 0; k <= n - 2; ++k) ixs.push_back(add((size_t)B * width(net, k) * 4));
+  for (int k = 0; k <= n - 1; ++k) ixb.push_back(add(k == 0 ? 4 : (size_t)B * width(net, k) * 4));
+  for (int k = 0; k <= n - 1; ++k) ival.push_back(add((size_t)B * width(net, k) * 8));
+  size_t igc = add((size_t)B * width(net, n - 1) * 4);
+  size_t icb = add((size_t)B * 8);
+  size_t ia0 = add((size_t)B * net->max_width * 4);
+  size_t ia1 = add((size_t)B * net->max_width * 4);
+  size_t iq = add((size_t)B * 8);
+  size_t ifl = add((size_t)B * 4);
+  size_t ibad = add(4);
+  size_t total = 0;
+  std::vector<size_t> off;
+  for (size_t s : sizes) {
+    off.push_back(total);
+    total += s;
+  }
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, total);
+  if (e != hipSuccess) return fail(LD_E_NOMEM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+  char* c = (char*)base;
+  ws.base = base;
+  ws.B = B;
+  ws.xs.assign(n - 1, nullptr);
+  ws.xb.assign(n, nullptr);
+  ws.val.assign(n, nullptr);
+  for (int k = 0; k <= n - 2; ++k) ws.xs[k] = c + off[ixs[k]];
+  for (int k = 1; k <= n - 1; ++k) ws.xb[k] = (float*)(c + off[ixb[k]]);
+  for (int k = 0; k <= n - 1; ++k) ws.val[k] = (double*)(c + off[ival[k]]);
+  ws.gconst = (float*)(c + off[igc]);
+  ws.cb = (double*)(c + off[icb]);
+  ws.act0 = (float*)(c + off[ia0]);
+  ws.act1 = (float*)(c + off[ia1]);
+  ws.qtmp = (double*)(c + off[iq]);
+  ws.flag = (int*)(c + off[ifl]);
+  ws.bad = (int*)(c + off[ibad]);
+  return LD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tiles
+// ---------------------------------------------------------------------------
+Tile heuristic_tile(const Job& J, int B) {
+  int N = J.geoms[0].N;
+  long M = 0;
+  for (auto& g : J.geoms) M = std::max<long>(M, (long)B * g.HWq);
+  Tile t;
+  if (N <= 16) {
+    t.bn = 16;
+    t.bm = M >= 131072 ? 256 : (M >= 16384 ? 128 : 64);
+  } else if (N <= 32) {
+    t.bn = 32;
+    t.bm = M >= 131072 ? 256 : (M >= 16384 ? 128 : 64);
+  } else if (N <= 64) {
+    t.bn = 64;
+    t.bm = M >= 16384 ? 128 : (M >= 2048 ? 64 : 32);
+  } else {
+    t.bn = (N <= 512 || M >= 4096) ? 64 : 128;
+    t.bm = M >= 16384 ? 128 : (M >= 2048 ? 64 : 32);
+  }
+  return t;
+}
+
+Tile pick_tile(const ld_net* net, int layer, int dir, int B, int mma) {
+  ld_net* mnet = const_cast<ld_net*>(net);
+  std::lock_guard<std::mutex> lk(mnet->mu);
+  auto it = mnet->tiles.find(std::make_tuple(layer, dir, B, mma));
+  if (it != mnet->tiles.end()) return it->second;
+  const Layer& L = net->L[layer];
+  return heuristic_tile(dir == 0 ? L.fwd : L.tr, B);
+}
+
+hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, const EpiArgs& e, Tile t,
+                   hipStream_t s) {
+  GemmGeom g[9];
+  const int nc = (int)J.geoms.size();
+  for (int i = 0; i < nc; ++i) {
+    g[i] = J.geoms[i];
+    g[i].M = B * g[i].HWq;
+  }
+  return launch_gemm(g[0], src, src_bf16, mma, e, t, nc, g, s);
+}
+
+EpiArgs epi0() {
+  EpiArgs e;
+  std::memset(&e, 0, sizeof(e));
+  e.scale = 1.f;
+  e.bias_div = 1;
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------
+int check_batch(const ld_net* net, const ld_batch* bt) {
+  if (!net) return fail(LD_E_ARG, "net is NULL");
+  if (!bt) return fail(LD_E_ARG, "batch is NULL");
+  if (bt->B < 0) return fail(LD_E_ARG, "batch size B < 0");
+  if (bt->B == 0) return LD_OK;
+  if (!bt->l0 || !bt->u0 || !bt->c) return fail(LD_E_ARG, "batch l0/u0/c is NULL");
+  if (!bt->l || !bt->u) return fail(LD_E_ARG, "batch l/u pointer arrays are NULL");
+  for (int k = 0; k < net->n - 1; ++k)
+    if (!bt->l[k] || !bt->u[k]) return fail(LD_E_ARG, "batch l[k]/u[k] is NULL for k=" + std::to_string(k + 1));
+  return LD_OK;
+}
+
+int validate_values(const ld_net* net, const ld_batch* bt, Workspace& ws, hipStream_t s) {
+  if (!g_validate || bt->B == 0) return LD_OK;
+  LD_HIP(hipMemsetAsync(ws.bad, 0, 4, s));
+  LD_HIP(launch_validate(bt->B, net->n0, bt->l0, bt->u0, ws.bad, s));
+  for (int k = 1; k <= net->n - 1; ++k) LD_HIP(launch_validate(bt->B, width(net, k), bt->l[k - 1], bt->u[k - 1], ws.bad, s));
+  LD_HIP(launch_validate(bt->B, width(net, net->n), bt->c, bt->c, ws.bad, s));
+  int bad = 0;
+  LD_HIP(hipMemcpyAsync(&bad, ws.bad, 4, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  if (bad) return fail(LD_E_NUMERIC, "batch holds a non-finite value or a lower bound above its upper bound");
+  return LD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pipelines
+// ---------------------------------------------------------------------------
+// g_{n-1} = -W_n^T c (the last hidden layer's constant coefficient) and c . b_n.
+int prepare_objective(const ld_net* net, const ld_batch* bt, Workspace& ws, int mma, hipStream_t s) {
+  const int n = net->n;
+  const Layer& Ln = net->L[n - 1];
+  EpiArgs e = epi0();
+  e.kind = EPI_STORE;
+  e.scale = -1.f;
+  e.out_f = ws.gconst;
+  LD_HIP(run_job(Ln.tr, bt->B, bt->c, 0, mma, e, pick_tile(net, n - 1, 1, bt->B, mma), s));
+  LD_HIP(launch_cdot(bt->B, Ln.n_out, bt->c, nullptr, Ln.bias, ws.cb, s));
+  return LD_OK;
+}
+
+int bias_div(const ld_net* net, int k) {
+  // divisor turning a neuron index of hidden layer k into its bias index
+  const Layer& L = net->L[k - 1];
+  return L.kind == LD_CONV2D ? L.out_h * L.out_w : 1;
+}
+
+// Phase A: inner minimisations of P_0..P_{n-1} at duals rho (rho[k-1] = rho_k).
+int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Workspace& ws, int mma, float tau,
+            int want_val, int* t_dev, float* adam, const ld_opts* o, hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  for (int k = 1; k <= n - 1; ++k) {
+    const Layer& L = net->L[k - 1];
+    EpiArgs e = epi0();
+    e.tau = tau;
+    e.want_val = want_val;
+    e.xs_bf16 = mma;
+    e.xs = ws.xs[k - 1];
+    e.val = ws.val[k - 1];
+    if (k == 1) {
+      e.kind = EPI_P0;
+      e.lo = bt->l0;
+      e.hi = bt->u0;
+    } else {
+      e.kind = EPI_INNER_MIN;
+      e.rho = rho[k - 2];
+      e.lo = bt->l[k - 2];
+      e.hi = bt->u[k - 2];
+      e.bias = net->L[k - 2].bias;
+      e.xb = ws.xb[k - 1];
+      // a linear layer fed by a flattened conv map has one column per neuron of that map
+      e.bias_div = L.kind == LD_LINEAR ? bias_div(net, k - 1) : 1;
+    }
+    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), s));
+  }
+  // last hidden layer: constant coefficient -W_n^T c
+  const int k = n - 1;
+  LD_HIP(launch_inner_min_const(B, width(net, k), ws.gconst, rho[k - 1], bt->l[k - 1], bt->u[k - 1],
+                                net->L[k - 1].bias, bias_div(net, k), tau, ws.xb[k],
+                                want_val ? ws.val[k] : nullptr, t_dev, adam, o ? o->lr0 : 0.0,
+                                o ? o->lr_end : 0.0, o ? o->total_iters : 0, o ? o->beta1 : 0.0,
+                                o ? o->beta2 : 0.0, o ? o->eps : 0.0, s));
+  return LD_OK;
+}
+
+int dual_eval_impl(const ld_net* net, const ld_batch* bt, const float* const* rho, Workspace& ws, double* q,
+                   float* const* supergrad, int mma, float tau, hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  LD_TRY(prepare_objective(net, bt, ws, mma, s));
+  LD_TRY(phase_a(net, bt, rho, ws, mma, tau, 1, nullptr, nullptr, nullptr, s));
+  if (q) {
+    std::vector<const double*> arrs;
+    std::vector<int> sz;
+    for (int k = 0; k <= n - 1; ++k) {
+      arrs.push_back(ws.val[k]);
+      sz.push_back(width(net, k));
+    }
+    LD_HIP(launch_reduce_q(B, (int)arrs.size(), arrs.data(), sz.data(), ws.cb, q, s));
+  }
+  if (supergrad) {
+    for (int k = 1; k <= n - 1; ++k) {
+      if (!supergrad[k - 1]) continue;
+      const Layer& L = net->L[k - 1];
+      EpiArgs e = epi0();
+      e.kind = EPI_SUPERGRAD;
+      e.xb_in = ws.xb[k];
+      e.bias = L.bias;
+      e.out_f = supergrad[k - 1];
+      LD_HIP(run_job(L.fwd, B, ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), s));
+    }
+  }
+  return LD_OK;
+}
+
+// CROWN duals (Prop. 2) or zeros into rho (rho[k-1] = rho_k).
+int init_impl(const ld_net* net, const ld_batch* bt, int init, int mma, float* const* rho, Workspace& ws,
+              hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  if (init == LD_INIT_ZERO) {
+    for (int k = 1; k <= n - 1; ++k) LD_HIP(hipMemsetAsync(rho[k - 1], 0, (size_t)B * width(net, k) * 4, s));
+    return LD_OK;
+  }
+  LD_TRY(prepare_objective(net, bt, ws, mma, s));
+  LD_HIP(launch_crown_const(B, width(net, n - 1), ws.gconst, bt->l[n - 2], bt->u[n - 2], rho[n - 2], s));
+  for (int k = n - 1; k >= 2; --k) {
+    // rho_{k-1} from g_{k-1} = W_k^T rho_k
+    const Layer& L = net->L[k - 1];
+    EpiArgs e = epi0();
+    e.kind = EPI_CROWN;
+    e.lo = bt->l[k - 2];
+    e.hi = bt->u[k - 2];
+    e.out_f = rho[k - 2];
+    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), s));
+  }
+  return LD_OK;
+}
+
+// One ascent iteration (phase A then phase B) on the state.
+int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  const int mma = o->precision == LD_BF16 ? 1 : 0;
+  std::vector<const float*> rho(st->rho.begin(), st->rho.end());
+  LD_TRY(phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, st->t_dev, st->adam, o, s));
+  for (int k = 1; k <= n - 1; ++k) {
+    const Layer& L = net->L[k - 1];
+    EpiArgs e = epi0();
+    e.kind = EPI_ADAM;
+    e.xb_in = st->ws.xb[k];
+    e.bias = L.bias;
+    e.rho_w = st->rho[k - 1];
+    e.m = st->m[k - 1];
+    e.v = st->v[k - 1];
+    e.adam = st->adam;
+    LD_HIP(run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), s));
+  }
+  return LD_OK;
+}
+
+void destroy_graph(ld_state* st) {
+  if (st->gexec) (void)hipGraphExecDestroy(st->gexec);
+  if (st->graph) (void)hipGraphDestroy(st->graph);
+  st->gexec = nullptr;
+  st->graph = nullptr;
+  st->gkey.clear();
+  st->gchunk = 0;
+}
+
+std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int chunk) {
+  std::vector<double> k;
+  auto P = [&](const void* p) { k.push_back((double)(uintptr_t)p); };
+  k.push_back(bt->B);
+  P(bt->l0);
+  P(bt->u0);
+  P(bt->c);
+  for (int i = 0; i < n - 1; ++i) {
+    P(bt->l[i]);
+    P(bt->u[i]);
+  }
+  k.push_back(o->total_iters);
+  k.push_back(o->lr0);
+  k.push_back(o->lr_end);
+  k.push_back(o->beta1);
+  k.push_back(o->beta2);
+  k.push_back(o->eps);
+  k.push_back(o->precision);
+  k.push_back(o->tie_tau);
+  k.push_back(chunk);
+  return k;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* ld_last_error(void) { return g_err.c_str(); }
+
+void ld_set_validation(int on) { g_validate = on ? 1 : 0; }
+
+// Host-only validation of a layer list (no HIP call), so that shape errors are
+// reported identically with or without a device.
+static int check_layers(const ld_layer* layers, int n_layers) {
+  if (n_layers < 2) return fail(LD_E_SHAPE, "a network needs at least one hidden layer (n_layers >= 2)");
+  if (n_layers > 15) return fail(LD_E_UNSUPPORTED, "at most 15 layers are supported");
+  long prev_out = -1;
+  for (int i = 0; i < n_layers; ++i) {
+    const ld_layer& s = layers[i];
+    const std::string at = " (layer " + std::to_string(i + 1) + ")";
+    if (!s.W || !s.b) return fail(LD_E_ARG, "W or b is NULL" + at);
+    if (s.in_c <= 0 || s.in_h <= 0 || s.in_w <= 0 || s.out_c <= 0 || s.out_h <= 0 || s.out_w <= 0)
+      return fail(LD_E_SHAPE, "non-positive size" + at);
+    const long n_in = (long)s.in_c * s.in_h * s.in_w;
+    long n_out;
+    size_t nw;
+    if (s.kind == LD_LINEAR) {
+      if (s.out_h != 1 || s.out_w != 1) return fail(LD_E_SHAPE, "linear layer needs out_h = out_w = 1" + at);
+      n_out = s.out_c;
+      nw = (size_t)n_out * n_in;
+    } else if (s.kind == LD_CONV2D) {
+      if (s.kh <= 0 || s.kw <= 0 || s.stride <= 0 || s.pad < 0) return fail(LD_E_SHAPE, "bad kernel/stride/pad" + at);
+      if (s.stride > 3) return fail(LD_E_UNSUPPORTED, "conv stride above 3" + at);
+      if (s.in_h + 2 * s.pad < s.kh || s.in_w + 2 * s.pad < s.kw ||
+          (s.in_h + 2 * s.pad - s.kh) / s.stride + 1 != s.out_h || (s.in_w + 2 * s.pad - s.kw) / s.stride + 1 != s.out_w)
+        return fail(LD_E_SHAPE, "conv output size does not match (in + 2 pad - k) / stride + 1" + at);
+      n_out = (long)s.out_c * s.out_h * s.out_w;
+      nw = (size_t)s.out_c * s.in_c * s.kh * s.kw;
+      if (i > 0) {
+        const ld_layer& P = layers[i - 1];
+        if (P.kind != LD_CONV2D || P.out_c != s.in_c || P.out_h != s.in_h || P.out_w != s.in_w)
+          return fail(LD_E_SHAPE, "conv input must be the previous conv's (C,H,W) map" + at);
+      }
+    } else {
+      return fail(LD_E_ARG, "unknown layer kind" + at);
+    }
+    if (n_in > (1L << 28) || n_out > (1L << 28)) return fail(LD_E_UNSUPPORTED, "layer too wide" + at);
+    if (i == n_layers - 1 && s.kind != LD_LINEAR) return fail(LD_E_SHAPE, "the last layer must be LD_LINEAR");
+    if (i > 0 && n_in != prev_out) return fail(LD_E_SHAPE, "input size differs from previous output" + at);
+    for (int j = 0; j < s.out_c; ++j)
+      if (!std::isfinite(s.b[j])) return fail(LD_E_NUMERIC, "non-finite bias" + at);
+    for (size_t j = 0; j < nw; ++j)
+      if (!std::isfinite(s.W[j])) return fail(LD_E_NUMERIC, "non-finite weight" + at);
+    prev_out = n_out;
+  }
+  return LD_OK;
+}
+
+int ld_create_net(const ld_layer* layers, int n_layers, ld_net** out) {
+  g_err.clear();
+  if (!layers || !out) return fail(LD_E_ARG, "layers/out is NULL");
+  *out = nullptr;
+  LD_TRY(check_layers(layers, n_layers));
+  ld_net* net = new (std::nothrow) ld_net();
+  if (!net) return fail(LD_E_NOMEM, "host allocation failed");
+  net->n = n_layers;
+  auto cleanup = [&](int rc) {
+    ld_destroy_net(net);
+    return rc;
+  };
+  for (int i = 0; i < n_layers; ++i) {
+    const ld_layer& s = layers[i];
+    Layer L;
+    L.kind = s.kind;
+    L.in_c = s.in_c;
+    L.in_h = s.in_h;
+    L.in_w = s.in_w;
+    L.out_c = s.out_c;
+    L.out_h = s.out_h;
+    L.out_w = s.out_w;
+    L.kh = s.kind == LD_CONV2D ? s.kh : 1;
+    L.kw = s.kind == LD_CONV2D ? s.kw : 1;
+    L.stride = s.kind == LD_CONV2D ? s.stride : 1;
+    L.pad = s.kind == LD_CONV2D ? s.pad : 0;
+    L.n_in = s.in_c * s.in_h * s.in_w;
+    L.n_out = s.kind == LD_LINEAR ? s.out_c : s.out_c * s.out_h * s.out_w;
+    void* pb;
+    int rc = alloc_dev(net, &pb, (size_t)s.out_c * 4);
+    if (rc) return cleanup(rc);
+    if (hipMemcpy(pb, s.b, (size_t)s.out_c * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(LD_E_DEVICE, "bias copy failed"));
+    L.bias = (float*)pb;
+    rc = s.kind == LD_LINEAR ? build_linear(net, L, s.W) : build_conv(net, L, s.W);
+    if (rc) return cleanup(rc);
+    net->L.push_back(L);
+  }
+  net->n0 = net->L[0].n_in;
+  net->max_width = net->n0;
+  for (auto& L : net->L) net->max_width = std::max(net->max_width, L.n_out);
+  *out = net;
+  return LD_OK;
+}
+
+void ld_destroy_net(ld_net* net) {
+  if (!net) return;
+  for (void* p : net->allocs) (void)hipFree(p);
+  if (net->ws.base) (void)hipFree(net->ws.base);
+  delete net;
+}
+
+int ld_net_num_layers(const ld_net* net, int* n_layers) {
+  if (!net || !n_layers) return fail(LD_E_ARG, "NULL argument");
+  *n_layers = net->n;
+  return LD_OK;
+}
+
+int ld_net_layer_width(const ld_net* net, int k, int* w) {
+  if (!net || !w) return fail(LD_E_ARG, "NULL argument");
+  if (k < 0 || k > net->n) return fail(LD_E_ARG, "layer index out of range");
+  *w = width(net, k);
+  return LD_OK;
+}
+
+int ld_state_create(const ld_net* net, int B, ld_state** out) {
+  g_err.clear();
+  if (!net || !out) return fail(LD_E_ARG, "NULL argument");
+  if (B <= 0) return fail(LD_E_ARG, "B must be positive");
+  *out = nullptr;
+  ld_state* st = new (std::nothrow) ld_state();
+  if (!st) return fail(LD_E_NOMEM, "host allocation failed");
+  st->net = net;
+  st->B = B;
+  const int n = net->n;
+  size_t total = 0;
+  std::vector<size_t> off;
+  for (int k = 1; k <= n - 1; ++k)
+    for (int j = 0; j < 3; ++j) {
+      off.push_back(total);
+      total += round_up((size_t)B * width(net, k) * 4, 256);
+    }
+  const size_t o_t = total;
+  total += 256;
+  const size_t o_adam = total;
+  total += 256;
+  const size_t o_q0 = total;
+  total += round_up((size_t)B * 8, 256);
+  if (hipMalloc(&st->base, total) != hipSuccess) {
+    delete st;
+    return fail(LD_E_NOMEM, "state hipMalloc failed");
+  }
+  (void)hipMemset(st->base, 0, total);
+  char* c = (char*)st->base;
+  for (int k = 1; k <= n - 1; ++k) {
+    st->rho.push_back((float*)(c + off[3 * (k - 1)]));
+    st->m.push_back((float*)(c + off[3 * (k - 1) + 1]));
+    st->v.push_back((float*)(c + off[3 * (k - 1) + 2]));
+  }
+  st->t_dev = (int*)(c + o_t);
+  st->adam = (float*)(c + o_adam);
+  st->q0 = (double*)(c + o_q0);
+  int rc = ws_alloc(net, st->ws, B);
+  if (rc) {
+    ld_state_destroy(st);
+    return rc;
+  }
+  if (hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) != hipSuccess) {
+    ld_state_destroy(st);
+    return fail(LD_E_DEVICE, "stream creation failed");
+  }
+  *out = st;
+  return LD_OK;
+}
+
+void ld_state_destroy(ld_state* st) {
+  if (!st) return;
+  destroy_graph(st);
+  if (st->cap) (void)hipStreamDestroy(st->cap);
+  if (st->ws.base) (void)hipFree(st->ws.base);
+  if (st->base) (void)hipFree(st->base);
+  delete st;
+}
+
+int ld_state_set_rho(ld_state* st, const float* const* rho, hipStream_t s) {
+  g_err.clear();
+  if (!st || !rho) return fail(LD_E_ARG, "NULL argument");
+  const ld_net* net = st->net;
+  for (int k = 1; k <= net->n - 1; ++k) {
+    if (!rho[k - 1]) return fail(LD_E_ARG, "rho[k] is NULL");
+    const size_t bytes = (size_t)st->B * width(net, k) * 4;
+    LD_HIP(hipMemcpyAsync(st->rho[k - 1], rho[k - 1], bytes, hipMemcpyDeviceToDevice, s));
+    LD_HIP(hipMemsetAsync(st->m[k - 1], 0, bytes, s));
+    LD_HIP(hipMemsetAsync(st->v[k - 1], 0, bytes, s));
+  }
+  LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
+  st->initialized = false;  // q(rho^0) is computed by the next ld_step (init = LD_INIT_GIVEN)
+  return LD_OK;
+}
+
+int ld_state_get_rho(const ld_state* st, float* const* rho, hipStream_t s) {
+  g_err.clear();
+  if (!st || !rho) return fail(LD_E_ARG, "NULL argument");
+  const ld_net* net = st->net;
+  for (int k = 1; k <= net->n - 1; ++k) {
+    if (!rho[k - 1]) return fail(LD_E_ARG, "rho[k] is NULL");
+    LD_HIP(hipMemcpyAsync(rho[k - 1], st->rho[k - 1], (size_t)st->B * width(net, k) * 4, hipMemcpyDeviceToDevice, s));
+  }
+  return LD_OK;
+}
+
+int ld_state_get_step(const ld_state* st, hipStream_t s, int* t) {
+  g_err.clear();
+  if (!st || !t) return fail(LD_E_ARG, "NULL argument");
+  LD_HIP(hipMemcpyAsync(t, st->t_dev, 4, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  return LD_OK;
+}
+
+int ld_init_duals(const ld_net* net, const ld_batch* bt, int init, int precision, float* const* rho, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_batch(net, bt));
+  if (!rho) return fail(LD_E_ARG, "rho is NULL");
+  if (init != LD_INIT_CROWN && init != LD_INIT_ZERO) return fail(LD_E_ARG, "init must be LD_INIT_CROWN or LD_INIT_ZERO");
+  if (precision != LD_FP32 && precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
+  if (bt->B == 0) return LD_OK;
+  for (int k = 0; k < net->n - 1; ++k)
+    if (!rho[k]) return fail(LD_E_ARG, "rho[k] is NULL");
+  ld_net* mnet = const_cast<ld_net*>(net);
+  LD_TRY(ws_alloc(net, mnet->ws, bt->B));
+  LD_TRY(validate_values(net, bt, mnet->ws, s));
+  return init_impl(net, bt, init, precision, rho, mnet->ws, s);
+}
+
+int ld_dual_eval(const ld_net* net, const ld_batch* bt, const float* const* rho, double* q, float* const* supergrad,
+                 int precision, float tie_tau, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_batch(net, bt));
+  if (!rho) return fail(LD_E_ARG, "rho is NULL");
+  if (precision != LD_FP32 && precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
+  if (!(tie_tau >= 0.f) || !std::isfinite(tie_tau)) return fail(LD_E_ARG, "tie_tau must be finite and >= 0");
+  if (bt->B == 0) return LD_OK;
+  for (int k = 0; k < net->n - 1; ++k)
+    if (!rho[k]) return fail(LD_E_ARG, "rho[k] is NULL");
+  ld_net* mnet = const_cast<ld_net*>(net);
+  LD_TRY(ws_alloc(net, mnet->ws, bt->B));
+  LD_TRY(validate_values(net, bt, mnet->ws, s));
+  return dual_eval_impl(net, bt, rho, mnet->ws, q, supergrad, precision, tie_tau, s);
+}
+
+int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_batch(net, bt));
+  if (!st || !o) return fail(LD_E_ARG, "state/opts is NULL");
+  if (st->net != net || st->B != bt->B) return fail(LD_E_STATE, "state was created for another net or batch size");
+  if (o->iters < 0 || o->total_iters < 1) return fail(LD_E_ARG, "iters must be >= 0 and total_iters >= 1");
+  if (o->precision != LD_FP32 && o->precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
+  if (o->init != LD_INIT_CROWN && o->init != LD_INIT_ZERO && o->init != LD_INIT_GIVEN) return fail(LD_E_ARG, "bad init");
+  if (!std::isfinite(o->lr0) || !std::isfinite(o->lr_end) || !(o->beta1 >= 0.f && o->beta1 < 1.f) ||
+      !(o->beta2 >= 0.f && o->beta2 < 1.f) || !(o->eps > 0.f) || !(o->tie_tau >= 0.f))
+    return fail(LD_E_ARG, "bad Adam constants");
+  LD_TRY(validate_values(net, bt, st->ws, s));
+  const int mma = o->precision == LD_BF16 ? 1 : 0;
+  LD_TRY(prepare_objective(net, bt, st->ws, mma, s));
+  if (!st->initialized) {
+    if (o->init != LD_INIT_GIVEN) {
+      std::vector<float*> r(st->rho.begin(), st->rho.end());
+      LD_TRY(init_impl(net, bt, o->init, mma, r.data(), st->ws, s));
+      for (int k = 1; k <= net->n - 1; ++k) {
+        const size_t bytes = (size_t)st->B * width(net, k) * 4;
+        LD_HIP(hipMemsetAsync(st->m[k - 1], 0, bytes, s));
+        LD_HIP(hipMemsetAsync(st->v[k - 1], 0, bytes, s));
+      }
+      LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
+    }
+    std::vector<const float*> r(st->rho.begin(), st->rho.end());
+    LD_TRY(dual_eval_impl(net, bt, r.data(), st->ws, st->q0, nullptr, LD_FP32, o->tie_tau, s));
+    LD_TRY(prepare_objective(net, bt, st->ws, mma, s));
+    st->initialized = true;
+  }
+  if (o->iters == 0) return LD_OK;
+  const int chunk = std::min(o->iters, 100);
+  std::vector<double> key = graph_key(bt, o, net->n, chunk);
+  if (!st->gexec || key != st->gkey) {
+    destroy_graph(st);
+    LD_HIP(hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal));
+    int rc = LD_OK;
+    for (int i = 0; i < chunk && rc == LD_OK; ++i) rc = iteration(net, bt, st, o, st->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st->cap, &g);
+    if (rc != LD_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(LD_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    st->graph = g;
+    e = hipGraphInstantiate(&st->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      destroy_graph(st);
+      return fail(LD_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    st->gkey = key;
+    st->gchunk = chunk;
+  }
+  const int reps = o->iters / chunk;
+  for (int r = 0; r < reps; ++r) LD_HIP(hipGraphLaunch(st->gexec, s));
+  for (int i = reps * chunk; i < o->iters; ++i) LD_TRY(iteration(net, bt, st, o, s));
+  return LD_OK;
+}
+
+int ld_final_bound(const ld_net* net, const ld_batch* bt, const ld_state* cst, double* bound, double* q_final,
+                   double* primal, int* feasible, float tie_tau, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_batch(net, bt));
+  if (!cst) return fail(LD_E_ARG, "state is NULL");
+  if (cst->net != net || cst->B != bt->B) return fail(LD_E_STATE, "state was created for another net or batch size");
+  if (!cst->initialized) return fail(LD_E_STATE, "state has not been initialised by ld_step");
+  if (!(tie_tau >= 0.f) || !std::isfinite(tie_tau)) return fail(LD_E_ARG, "tie_tau must be finite and >= 0");
+  ld_state* st = const_cast<ld_state*>(cst);
+  const int n = net->n, B = bt->B;
+  Workspace& ws = st->ws;
+  LD_TRY(validate_values(net, bt, ws, s));
+  double* qf = q_final ? q_final : ws.qtmp;
+  std::vector<const float*> r(st->rho.begin(), st->rho.end());
+  LD_TRY(dual_eval_impl(net, bt, r.data(), ws, qf, nullptr, LD_FP32, tie_tau, s));
+  if (bound) LD_HIP(launch_max_f64(B, st->q0, qf, bound, s));
+  if (primal || feasible) {
+    int* flag = feasible ? feasible : ws.flag;
+    LD_HIP(launch_fill_i32(flag, (size_t)B, 1, s));
+    const float* x = (const float*)ws.xs[0];
+    float* bufs[2] = {ws.act0, ws.act1};
+    for (int k = 1; k <= n; ++k) {
+      const Layer& L = net->L[k - 1];
+      EpiArgs e = epi0();
+      e.bias = L.bias;
+      e.out_f = bufs[k & 1];
+      if (k < n) {
+        e.kind = EPI_RELU_FWD;
+        e.lo = bt->l[k - 1];
+        e.hi = bt->u[k - 1];
+        e.flag = flag;
+      } else {
+        e.kind = EPI_BIAS_STORE;
+      }
+      LD_HIP(run_job(L.fwd, B, x, 0, 0, e, pick_tile(net, k - 1, 0, B, 0), s));
+      x = bufs[k & 1];
+    }
+    if (primal) LD_HIP(launch_cdot(B, net->L[n - 1].n_out, bt->c, x, nullptr, primal, s));
+  }
+  return LD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal declarations shared by the kernel and host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ld {
+
+typedef uint16_t bf16_t;   // raw bfloat16 bits
+
+// ---------------------------------------------------------------------------
+// A contraction  C[m, n] = sum_k A[m, k] * B[k, n]  whose A operand is gathered
+// from an activation tensor (implicit GEMM).  Rows m enumerate (subdomain, y', x')
+// positions; the source element of (m, k) sits at spatial position
+// (y'*iy_mul + iy_off + dky[k], x'*ix_mul + ix_off + dkx[k]) of channel plane
+// chan_off[k]; out-of-range positions read as zero (zero padding).  Output
+// column n of row m is neuron n*dst_HW + (y'*oy_mul+oy_off)*dst_W + (x'*ox_mul+ox_off)
+// of the destination layer.  Fully-connected layers use 1x1 geometry.
+// ---------------------------------------------------------------------------
+struct GemmGeom {
+  int M;               // rows = B * HWq
+  int HWq, Wq;         // rows per subdomain, row width
+  int iy_mul, iy_off, ix_mul, ix_off;
+  int src_H, src_W;    // spatial size of the source plane
+  int src_n;           // source elements per subdomain
+  int K, Kp;           // reduction length; padded length (multiple of 64)
+  const int4* ktab;    // [Kp] (chan_off, dky, dkx, 0)
+  int N, Np;           // output columns; padded (multiple of 128)
+  const float* Bf;     // [Np][Kp] FP32 operand, column-major in k ("n-major")
+  const bf16_t* Bh;    // [Np][Kp] BF16 operand
+  int dst_n;           // destination elements per subdomain
+  int dst_HW, dst_W;
+  int oy_mul, oy_off, ox_mul, ox_off;
+  int m_fast;          // 1: epilogue walks rows fastest (conv), 0: columns fastest (FC)
+};
+
+// Epilogue selector (what is done with each accumulated value).
+enum EpiKind : int {
+  EPI_STORE = 0,        // out_f[idx] = scale * acc
+  EPI_P0 = 1,           // box minimiser of P_0 (eq:box_bounds_sol): x0* and its value
+  EPI_INNER_MIN = 2,    // ReLU-hull vertex minimiser of P_k (eq:min-pk): x*, xB*, value
+  EPI_ADAM = 3,         // supergradient xB - (acc + b) and Adam ascent step on rho
+  EPI_SUPERGRAD = 4,    // supergradient xB - (acc + b) stored
+  EPI_CROWN = 5,        // CROWN dual: a_up [g]_+ + a_lo [g]_-
+  EPI_RELU_FWD = 6,     // y = acc + b, feasibility against [l, u], x = relu(y)
+  EPI_BIAS_STORE = 7    // y = acc + b stored
+};
+
+struct EpiArgs {
+  int kind;
+  int xs_bf16;          // x* written as BF16 (1) or FP32 (0)
+  float scale;
+  float tau;            // tie band
+  int want_val;         // write FP64 per-neuron values
+  float* out_f;         // EPI_STORE / EPI_SUPERGRAD / EPI_CROWN / EPI_RELU_FWD / EPI_BIAS_STORE
+  void* xs;             // x* (float or bf16)
+  float* xb;            // xB*
+  double* val;          // per-neuron FP64 values
+  const float* rho;     // dual of the destination layer
+  const float* lo;      // lower bounds (l_k or l_0)
+  const float* hi;      // upper bounds
+  const float* bias;    // bias of the destination layer, index column / bias_div
+  int bias_div;
+  const float* xb_in;   // xB* read by the forward epilogues
+  float* rho_w;         // Adam: rho, m, v (in/out)
+  float* m;
+  float* v;
+  const float* adam;    // device scalars {lr_t, 1/bc1, 1/bc2, eps, beta1, beta2}
+  int* flag;            // feasibility flags [B] (EPI_RELU_FWD)
+};
+
+// Launch-time tile configuration.
+struct Tile {
+  int bm, bn;
+};
+
+// kernels (ld_kernels.hip)
+hipError_t launch_gemm(const GemmGeom& g, const void* src, int src_bf16, int mma_bf16,
+                       const EpiArgs& e, Tile t, int n_classes, const GemmGeom* class_geoms,
+                       hipStream_t s);
+int tile_supported(Tile t, int mma_bf16);
+
+hipError_t launch_inner_min_const(int B, int n, const float* g, const float* rho, const float* lo,
+                                  const float* hi, const float* bias, int bias_hw, float tau, float* xb,
+                                  double* val, int* t_dev, float* adam_scalars, double lr0,
+                                  double lr_end, int total, double beta1, double beta2, double eps,
+                                  hipStream_t s);
+hipError_t launch_crown_const(int B, int n, const float* g, const float* lo, const float* hi,
+                              float* rho, hipStream_t s);
+hipError_t launch_reduce_q(int B, int n_arrays, const double* const* arrays, const int* sizes,
+                           const double* cb, double* q, hipStream_t s);
+hipError_t launch_cdot(int B, int n, const float* c, const float* y, const float* bias, double* out,
+                       hipStream_t s);
+hipError_t launch_validate(int B, int n, const float* lo, const float* hi, int* bad, hipStream_t s);
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
+hipError_t launch_fill_i32(int* p, size_t n, int v, hipStream_t s);
+hipError_t launch_copy_f32(float* dst, const float* src, size_t n, hipStream_t s);
+hipError_t launch_max_f64(int B, const double* a, const double* b, double* out, hipStream_t s);
+
+}  // namespace ld

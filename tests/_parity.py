@@ -1,0 +1,80 @@
+"""Helpers for the GPU-vs-oracle parity tests (tolerances and stability masks).
+
+Tolerances, per the bar "dual value and supergradient at fixed duals match the
+oracle to 1e-5 relative in FP32":
+  q : |q_gpu - q_orc| <= 1e-5 * S, with S the sum of the magnitudes of every
+      term summed into q (reading of "relative" for a sum that can be near 0).
+  s : |s_gpu - s_orc| <= 1e-5 * (|W| |x*| + |b| + |xB|) elementwise, on
+      subdomains whose inner minimisation has no near-tie (several argmins are
+      correct there; q, which is unique, is compared everywhere).
+"""
+import numpy as np
+import torch
+
+from oracle import ld_oracle as O
+
+REL = 1e-5
+TIE_REL = 2e-4   # decisions closer than this (relative to the FP32 error scale) can flip
+ULP32 = 8 * 2.0 ** -24
+
+
+def abs_layer(L):
+    return O.OLayer(L.kind, L.W.abs(), L.b.abs(), L.in_shape, L.out_shape, L.stride, L.pad)
+
+
+def unstable_decisions(net, batch, rho, ev, tau=O.TAU_DEFAULT):
+    """Per-layer boolean masks (layer 0 = P_0, then hidden layers 1..n-1): True where
+    an inner-minimisation decision of the oracle sits within TIE_REL (relative to
+    the FP32 error scale of the contraction feeding it) of flipping."""
+    n = len(net)
+    duals = list(rho) + [-batch.c]
+    absnet = [abs_layer(L) for L in net]
+    G = [absnet[k].transposed(duals[k].abs()) for k in range(n)]   # magnitude of the terms of g_k
+    masks = [(ev["g"][0].abs() <= TIE_REL * G[0]) & (G[0] > 0)]    # P0: sign of g0
+    for k in range(1, n):
+        r, g, l, u = duals[k - 1], ev["g"][k], batch.l[k - 1], batch.u[k - 1]
+        st = O.relu_status(l, u)
+        # passing: the test of cp against its band; the error scale of g is G
+        cp = r - g
+        e_pass = TIE_REL * G[k] + ULP32 * (r.abs() + g.abs())
+        # where the error scale is zero both sides compute the identical exact value
+        ok_pass = ((cp - tau * (r.abs() + g.abs())).abs() > e_pass) | (e_pass == 0)
+        # blocking: the sign of rho is an input, identical on both sides
+        # ambiguous: a vertex at the minimum is always accepted; any other vertex must
+        # not sit near the acceptance threshold m + band
+        Vl, Vu = r * l, (r - g) * u
+        V0 = torch.zeros_like(Vl)
+        m = torch.minimum(torch.minimum(Vl, Vu), V0)
+        thr = m + tau * (Vl.abs() + (r * u).abs() + (g * u).abs())
+        err = 2 * TIE_REL * G[k] * (l.abs() + u.abs()) + ULP32 * (Vl.abs() + Vu.abs())
+
+        def far(V):
+            return (V == m) | ((V - thr).abs() > err) | (err == 0)
+        ok_amb = far(Vl) & far(V0) & far(Vu)
+        ok = torch.where(st == 0, ok_pass, torch.where(st == 1, torch.ones_like(ok_pass), ok_amb))
+        masks.append(~ok)
+    return masks
+
+
+def supergrad_masks(net, masks):
+    """Entries of s_k that a flipped decision can change: the neuron's own decision,
+    or any input of W_k whose decision may flip (receptive field through |W_k|)."""
+    out = []
+    for k in range(1, len(net)):
+        spread = abs_layer(net[k - 1]).forward(masks[k - 1].double()) - abs_layer(net[k - 1]).bias_full()
+        out.append(masks[k] | (spread > 0))
+    return out
+
+
+def q_tol(net, batch, rho, ev):
+    return REL * O.q_scale(net, batch, rho, ev) + 1e-9
+
+
+def s_scale(net, ev):
+    n = len(net)
+    prev = [ev["x0"]] + ev["x"]
+    out = []
+    for k in range(1, n):
+        L = abs_layer(net[k - 1])
+        out.append(L.forward(prev[k - 1].abs()) + ev["xB"][k - 1].abs())
+    return out
