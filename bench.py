@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark of the Lagrangian-decomposition bounding step on one MI355X.
+
+One "step" is one complete bounding run over a batch of B subdomains: CROWN dual
+initialisation, T Adam supergradient iterations (Algorithm 1 with Adam), and the
+final bound re-evaluated with FP32 operands and an FP64 sum plus the primal
+upper bound.  The default workload is the wide conv net (conv 16@4x4/2,
+conv 32@4x4/2, FC 100, FC 10 on 3x32x32 inputs), B = 512, T = 500, with
+synthetic seeded weights and subdomains (see ldgen).  Inputs are resident in
+device memory before the timed region starts.
+
+Prints ONE JSON line.  `value` is bounds/sec of the BF16 form (BF16 operands on
+MFMA, FP32 accumulation) at the iteration count that reaches the FP32 form's
+bound (mean gap <= 1e-3); the FP32 form and the gap are reported beside it.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="wide")
+    ap.add_argument("--B", type=int, default=None)
+    ap.add_argument("--iters", type=int, default=None, help="Adam iterations per bounding run (default: config T)")
+    ap.add_argument("--bf16-iters", type=int, default=None,
+                    help="iterations of the BF16 form (default: searched for equal bound)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=24, help="subdomains timed on the host oracle")
+    ap.add_argument("--quick", action="store_true", help="skip the equal-bound search (profiling runs)")
+    ap.add_argument("--profile-only", choices=["fp32", "bf16"], default=None,
+                    help="for rocprofv3: one 64 MiB device copy (counter calibration), then --reps ascent "
+                         "iterations launched without the graph; prints the per-launch averages")
+    ap.add_argument("--reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def layer_slot_cost(inst, kind, B, prec):
+    """Algorithmic bytes and useful FLOPs of one launch of an iteration slot.
+
+    Bytes are the compulsory traffic of the launch's inputs and outputs, each read
+    or written once (weights included):
+      phase A (100+k): read rho_k; read the bounds (and rho) of layer k-1; write
+                       x*_{k-1} (operand type) and, for k-1 >= 1, xB*_{k-1}
+      200+k          : read g_const, rho_k, l_k, u_k; write xB*_k
+      phase B (300+k): read x*_{k-1} (operand type); read xB*_k; read and write
+                       rho_k, m_k, v_k
+    FLOPs count 2 per multiply-add of the contraction (no structural zeros)."""
+    layers = inst.layers
+    opb = 2 if prec == "bf16" else 4
+    ph, k = divmod(kind, 100)
+    width = lambda j: layers[0].n_in if j == 0 else layers[j - 1].n_out  # noqa: E731
+    def macs(L):
+        if L.kind == "linear":
+            return L.n_in * L.n_out
+        Co, Ho, Wo = L.out_shape
+        return Co * Ho * Wo * L.in_shape[0] * L.W.shape[2] * L.W.shape[3]
+    def wbytes(L):
+        return L.W.size * opb
+    if ph == 1:
+        L = layers[k - 1]
+        nb = width(k) * 4 + (width(0) * (8 + opb) if k == 1 else width(k - 1) * (12 + opb + 4))
+        # transposed conv: taps that fall outside the input are not work
+        flops = 2 * macs(L)
+        return B * nb + wbytes(L), B * flops
+    if ph == 2:
+        return B * width(k) * 20, 0
+    L = layers[k - 1]
+    nb = width(k - 1) * opb + width(k) * 28
+    return B * nb + wbytes(L), B * 2 * macs(L)
+
+
+def run_form(P, net, batch, st, iters, prec, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        st.reset()
+        P.step(net, batch, st, iters=iters, total_iters=iters, precision=prec)
+        P.final_bound(net, batch, st)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    fb = None
+    for _ in range(steps):
+        st.reset()
+        P.step(net, batch, st, iters=iters, total_iters=iters, precision=prec)
+        fb = P.final_bound(net, batch, st)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return dict(ms_per_step=e0.elapsed_time(e1) / steps, wall_ms_per_step=1000 * wall / steps, fb=fb)
+
+
+def cpu_baseline(inst, T, sample):
+    import torch
+    from oracle import ld_oracle as O
+    idx = list(range(sample))
+    onet = O.net_from_specs(inst.layers)
+    ob = O.batch_from_instance(inst, idx)
+    t0 = time.perf_counter()
+    st = O.ascent(onet, ob, O.AdamOpts(T=T))
+    O.final_bound(onet, ob, st)
+    dt = time.perf_counter() - t0
+    return dict(value=sample / dt, unit="bounds/s", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"{sample} of {inst.B} subdomains, {T} iterations each, FP64 torch-CPU oracle, "
+                       f"{dt:.1f} s")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the subdomain batch would be "
+              f"sharded across GPUs with no communication until a final all-gather, which is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import ldgen
+    import paper_2104_06718_amd as P
+
+    inst = ldgen.make_instance(a.config, B=a.B) if a.B else ldgen.make_instance(a.config)
+    T = a.iters or inst.meta["T"] or 500
+    B = inst.B
+    net = P.Net(inst.layers)
+    batch = P.Batch.from_instance(inst)
+    P.set_validation(False)
+
+    if a.profile_only:
+        x = torch.ones(16 << 20, device="cuda", dtype=torch.float32)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        stp = P.State(net, B)
+        P.step(net, batch, stp, iters=2, total_iters=T, precision=a.profile_only)
+        slots = P.profile_iteration(net, batch, stp, reps=a.reps, total_iters=T, precision=a.profile_only)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_only": a.profile_only, "config": a.config, "B": B,
+                          "per_launch_us": {str(k): round(v, 2) for k, v in slots}}), flush=True)
+        return
+
+    st = P.State(net, B)
+    res32 = run_form(P, net, batch, st, T, "fp32", a.steps, a.warmup)
+    b32 = res32["fb"]["bound"].clone()
+
+    # BF16 form: iterations needed to reach the FP32 form's bound (mean gap <= 1e-3)
+    st16 = P.State(net, B)
+    T16 = a.bf16_iters or T
+    tries = []
+    if not a.quick and a.bf16_iters is None:
+        for t in (T, int(1.5 * T), 2 * T, 3 * T):
+            st16.reset()
+            P.step(net, batch, st16, iters=t, total_iters=t, precision="bf16")
+            bb = P.final_bound(net, batch, st16)["bound"]
+            gap = (b32 - bb).mean().item()
+            tries.append((t, gap))
+            T16 = t
+            if gap <= 1e-3:
+                break
+    res16 = run_form(P, net, batch, st16, T16, "bf16", a.steps, a.warmup)
+    b16 = res16["fb"]["bound"]
+    d = (b16 - b32)
+    equal = (b32 - b16).mean().item() <= 1e-3
+
+    # per-launch timing of one iteration (HIP events around every launch, same stream)
+    stp = P.State(net, B)
+    prof = {}
+    for prec in ("fp32", "bf16"):
+        stp.reset()
+        P.step(net, batch, stp, iters=5, total_iters=T, precision=prec)
+        prof[prec] = P.profile_iteration(net, batch, stp, reps=20, total_iters=T, precision=prec)
+    head = "bf16"
+    slots = prof[head]
+    kind, us = max(slots, key=lambda x: x[1])
+    nbytes, flops = layer_slot_cost(inst, kind, B, head)
+    intensity = flops / max(nbytes, 1)
+    ridge = PEAK_TFLOPS[head] * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if intensity < ridge:
+        roof = dict(bound="hbm", achieved=nbytes / (us * 1e-6) / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
+    else:
+        roof = dict(bound="mfma", achieved=flops / (us * 1e-6) / 1e12, peak=PEAK_TFLOPS[head], unit="TFLOP/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"slot {kind} (phase {kind // 100}, layer {kind % 100})"
+    roof["avg_us"] = us
+    roof["algorithmic_bytes"] = nbytes
+    roof["algorithmic_flops"] = flops
+
+    value = B / (res16["ms_per_step"] / 1000.0)
+    out = {
+        "metric": "LD bounds/sec (500 iters, B=512, wide conv net); bf16 vs fp32 at equal bound",
+        "value": value,
+        "unit": "bounds/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": res16["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{a.config} conv net 3x32x32, B={B}, T={T} (bf16: T={T16}), 1 property, "
+                               f"5% random ReLU splits per subdomain", "B": B, "iters": T, "bf16_iters": T16},
+        "fp32": {"value": B / (res32["ms_per_step"] / 1000.0), "ms_per_step": res32["ms_per_step"],
+                 "mean_bound": b32.mean().item()},
+        "bf16": {"value": value, "ms_per_step": res16["ms_per_step"], "mean_bound": b16.mean().item(),
+                 "equal_bound": equal, "gap_mean": d.mean().item(), "gap_absmax": d.abs().max().item(),
+                 "frac_within_1e-3": (d.abs() <= 1e-3).float().mean().item(), "search": tries},
+        "roofline": roof,
+        "per_launch_us": {p: {str(k): round(v, 2) for k, v in prof[p]} for p in prof},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, T, a.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

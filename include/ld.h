@@ -142,6 +142,11 @@ int ld_state_set_rho(ld_state* st, const float* const* rho, hipStream_t stream);
 int ld_state_get_rho(const ld_state* st, float* const* rho, hipStream_t stream);
 /* Number of Adam steps taken so far (synchronises `stream`). */
 int ld_state_get_step(const ld_state* st, hipStream_t stream, int* t);
+/* Mark the state as fresh: the next ld_step initialises the duals again (per its
+ * `init`), zeroes the Adam moments and the step counter and recomputes q(rho^0).
+ * Buffers, tuned tiles and the captured graph are kept, so a bounding run can be
+ * repeated on new subdomain data of the same shape without allocation. */
+int ld_state_reset(ld_state* st, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* dual initialisation (Prop. 2)                                              */
@@ -203,6 +208,18 @@ typedef struct ld_opts {
  * call with a new configuration. */
 int ld_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opts* opts,
             hipStream_t stream);
+
+/* Diagnostic: run `reps` ascent iterations (real steps that advance the state,
+ * launched without the graph) with a HIP event pair around every kernel launch,
+ * and return the average duration in microseconds of each launch slot of one
+ * iteration (avg_us, host [max_slots]) with its kind (kinds, host [max_slots]):
+ * 100+k = transposed product of layer k fused with the inner minimisation of
+ * layer k-1 (phase A), 200+k = inner minimisation of the last hidden layer k,
+ * 300+k = forward product of layer k fused with the supergradient and Adam step
+ * (phase B).  *n_slots receives the number of slots.  Synchronises `stream`. */
+int ld_profile_iteration(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opts* opts,
+                         int reps, double* avg_us, int* kinds, int max_slots, int* n_slots,
+                         hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* final bound (Algorithm 1's return value; upper bound of Sec. 5.1.3)        */

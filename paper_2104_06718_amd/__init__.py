@@ -5,4 +5,4 @@ Python binding of the C ABI in include/ld.h: ``Net``, ``Batch``, ``State``,
 library directly; ``LDDual`` wraps ``dual_eval`` as a torch.autograd.Function.
 """
 from .binding import (Batch, LDError, Net, State, TAU_DEFAULT, dual_eval, final_bound, init_duals,  # noqa: F401
-                      load_library, set_validation, step)
+                      load_library, profile_iteration, set_validation, step)

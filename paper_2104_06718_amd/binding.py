@@ -27,8 +27,8 @@ _INIT = {"crown": LD_INIT_CROWN, "zero": LD_INIT_ZERO, "given": LD_INIT_GIVEN}
 
 EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num_layers",
             "ld_set_validation", "ld_state_create", "ld_state_destroy", "ld_state_set_rho",
-            "ld_state_get_rho", "ld_state_get_step", "ld_init_duals", "ld_dual_eval", "ld_step",
-            "ld_final_bound", "ld_last_error"]
+            "ld_state_get_rho", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval",
+            "ld_step", "ld_profile_iteration", "ld_final_bound", "ld_last_error"]
 
 
 class LDError(RuntimeError):
@@ -85,6 +85,8 @@ def load_library(path: Optional[str] = None):
     lib.ld_state_set_rho.argtypes = [V, P(V), V]
     lib.ld_state_get_rho.argtypes = [V, P(V), V]
     lib.ld_state_get_step.argtypes = [V, V, P(I)]
+    lib.ld_state_reset.argtypes = [V, V]
+    lib.ld_profile_iteration.argtypes = [V, P(ld_batch), V, P(ld_opts), I, P(ctypes.c_double), P(I), I, P(I), V]
     lib.ld_init_duals.argtypes = [V, P(ld_batch), I, I, P(V), V]
     lib.ld_dual_eval.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
     lib.ld_step.argtypes = [V, P(ld_batch), V, P(ld_opts), V]
@@ -217,6 +219,9 @@ class State:
         _check(self.lib.ld_state_get_rho(self.handle, _ptrs(out), _stream(stream)))
         return out
 
+    def reset(self, stream=None):
+        _check(self.lib.ld_state_reset(self.handle, _stream(stream)))
+
     def step_count(self, stream=None) -> int:
         t = ctypes.c_int()
         _check(self.lib.ld_state_get_step(self.handle, _stream(stream), ctypes.byref(t)))
@@ -252,9 +257,26 @@ def dual_eval(net: Net, batch: Batch, rho: List[torch.Tensor], supergrad=True, p
 def step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional[int] = None, lr0=1e-2,
          lr_end=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, precision="fp32", init="crown",
          tau: float = TAU_DEFAULT, stream=None):
-    o = ld_opts(int(iters), int(total_iters if total_iters is not None else iters), lr0, lr_end, beta1, beta2,
-                eps, _PREC[precision], _INIT[init], tau)
+    o = _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau)
     _check(net.lib.ld_step(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o), _stream(stream)))
+
+
+def _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau):
+    return ld_opts(int(iters), int(total_iters if total_iters is not None else iters), lr0, lr_end, beta1, beta2,
+                   eps, _PREC[precision], _INIT[init], tau)
+
+
+def profile_iteration(net: Net, batch: Batch, state: State, reps=10, total_iters=500, lr0=1e-2, lr_end=1e-4,
+                      beta1=0.9, beta2=0.999, eps=1e-8, precision="fp32", init="crown", tau: float = TAU_DEFAULT,
+                      stream=None):
+    """Average duration (us) of every kernel launch of one ascent iteration, with its kind."""
+    o = _opts(reps, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau)
+    avg = (ctypes.c_double * 64)()
+    kinds = (ctypes.c_int * 64)()
+    ns = ctypes.c_int()
+    _check(net.lib.ld_profile_iteration(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o),
+                                        int(reps), avg, kinds, 64, ctypes.byref(ns), _stream(stream)))
+    return [(kinds[i], avg[i]) for i in range(ns.value)]
 
 
 def final_bound(net: Net, batch: Batch, state: State, tau: float = TAU_DEFAULT, stream=None):

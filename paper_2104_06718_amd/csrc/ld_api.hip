@@ -83,7 +83,12 @@ struct Workspace {
   double* qtmp = nullptr;     // [B]
   int* flag = nullptr;        // [B]
   int* bad = nullptr;         // [1]
+  float* partial = nullptr;   // split-K partial tiles
+  int* counters = nullptr;    // split-K arrival counters (kept at zero between launches)
 };
+
+constexpr size_t kPartialCap = (size_t)8 << 20;   // floats (32 MiB)
+constexpr size_t kCounterCap = (size_t)1 << 16;
 
 }  // namespace
 
@@ -142,6 +147,18 @@ int finish_geom(ld_net* net, GemmGeom& g, const std::vector<float>& Bnk, const s
     }
   std::vector<int4> kt((size_t)g.Kp, int4{0, 0, 0, 0});
   for (int k = 0; k < g.K; ++k) kt[k] = ktab[k];
+  if (g.LH > 0) {
+    // offsets into the zero-padded LDS image [C][LH][LW]; padded k read offset 0 (weight is 0)
+    std::vector<int> kl((size_t)g.Kp, 0);
+    for (int k = 0; k < g.K; ++k) {
+      const int c = ktab[k].x / (g.src_H * g.src_W);
+      kl[k] = c * g.LH * g.LW + ktab[k].y * g.LW + ktab[k].z;
+    }
+    void* pl;
+    LD_TRY(alloc_dev(net, &pl, kl.size() * 4));
+    LD_HIP(hipMemcpy(pl, kl.data(), kl.size() * 4, hipMemcpyHostToDevice));
+    g.ktab_lds = (const int*)pl;
+  }
   void *pf, *ph, *pk;
   LD_TRY(alloc_dev(net, &pf, bf.size() * 4));
   LD_TRY(alloc_dev(net, &ph, bh.size() * 2));
@@ -228,6 +245,10 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
     g.oy_mul = 1;
     g.ox_mul = 1;
     g.m_fast = 1;
+    g.pad_t = p;
+    g.pad_l = p;
+    g.LH = p + H + std::max(0, (OH - 1) * s - p + kh - H);
+    g.LW = p + Wd + std::max(0, (OW - 1) * s - p + kw - Wd);
     std::vector<float> Bnk((size_t)Co * g.K);
     std::vector<int4> kt(g.K);
     for (int ci = 0; ci < Ci; ++ci)
@@ -244,6 +265,23 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
   // the taps ky = ky0 + s*ty with ky0 = (ry + p) mod s, from output row oy = y' + dy - ty,
   // dy = (ry + p - ky0) / s.
   L.tr.geoms.clear();
+  int pt = 0, pb = 0, pl = 0, pr = 0;
+  for (int ry = 0; ry < s; ++ry) {
+    const int Hq = (H - ry + s - 1) / s;
+    const int ky0 = (ry + p) % s, dy = (ry + p - ky0) / s;
+    const int Ty = kh > ky0 ? (kh - ky0 + s - 1) / s : 0;
+    if (Hq <= 0 || Ty <= 0) continue;
+    pt = std::max(pt, Ty - 1 - dy);
+    pb = std::max(pb, Hq - 1 + dy - (OH - 1));
+  }
+  for (int rx = 0; rx < s; ++rx) {
+    const int Wq = (Wd - rx + s - 1) / s;
+    const int kx0 = (rx + p) % s, dx = (rx + p - kx0) / s;
+    const int Tx = kw > kx0 ? (kw - kx0 + s - 1) / s : 0;
+    if (Wq <= 0 || Tx <= 0) continue;
+    pl = std::max(pl, Tx - 1 - dx);
+    pr = std::max(pr, Wq - 1 + dx - (OW - 1));
+  }
   for (int ry = 0; ry < s; ++ry)
     for (int rx = 0; rx < s; ++rx) {
       const int Hq = (H - ry + s - 1) / s;
@@ -273,6 +311,10 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
       g.ox_mul = s;
       g.ox_off = rx;
       g.m_fast = 1;
+      g.pad_t = pt;
+      g.pad_l = pl;
+      g.LH = pt + OH + pb;
+      g.LW = pl + OW + pr;
       std::vector<float> Bnk((size_t)Ci * std::max(g.K, 1), 0.f);
       std::vector<int4> kt(std::max(g.K, 1), int4{0, 0, 0, 0});
       for (int co = 0; co < Co; ++co)
@@ -286,6 +328,9 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
       L.tr.geoms.push_back(g);
     }
   if ((int)L.tr.geoms.size() > 9) return fail(LD_E_UNSUPPORTED, "conv stride above 3 is not supported");
+  if (conv_lds_bytes(L.fwd.geoms.data(), 1) > 160 * 1024 ||
+      conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size()) > 160 * 1024)
+    return fail(LD_E_UNSUPPORTED, "conv maps too large for the LDS images of one subdomain");
   return LD_OK;
 }
 
@@ -317,6 +362,8 @@ int ws_alloc(const ld_net* net, Workspace& ws, int B) {
   size_t iq = add((size_t)B * 8);
   size_t ifl = add((size_t)B * 4);
   size_t ibad = add(4);
+  size_t ipart = add(kPartialCap * 4);
+  size_t icnt = add(kCounterCap * 4);
   size_t total = 0;
   std::vector<size_t> off;
   for (size_t s : sizes) {
@@ -342,30 +389,49 @@ int ws_alloc(const ld_net* net, Workspace& ws, int B) {
   ws.qtmp = (double*)(c + off[iq]);
   ws.flag = (int*)(c + off[ifl]);
   ws.bad = (int*)(c + off[ibad]);
+  ws.partial = (float*)(c + off[ipart]);
+  ws.counters = (int*)(c + off[icnt]);
+  e = hipMemset(ws.counters, 0, kCounterCap * 4);
+  if (e != hipSuccess) return fail(LD_E_DEVICE, std::string("workspace memset: ") + hipGetErrorString(e));
   return LD_OK;
 }
 
 // ---------------------------------------------------------------------------
 // tiles
 // ---------------------------------------------------------------------------
-Tile heuristic_tile(const Job& J, int B) {
-  int N = J.geoms[0].N;
-  long M = 0;
-  for (auto& g : J.geoms) M = std::max<long>(M, (long)B * g.HWq);
-  Tile t;
-  if (N <= 16) {
-    t.bn = 16;
-    t.bm = M >= 131072 ? 256 : (M >= 16384 ? 128 : 64);
-  } else if (N <= 32) {
-    t.bn = 32;
-    t.bm = M >= 131072 ? 256 : (M >= 16384 ? 128 : 64);
-  } else if (N <= 64) {
-    t.bn = 64;
-    t.bm = M >= 16384 ? 128 : (M >= 2048 ? 64 : 32);
-  } else {
-    t.bn = (N <= 512 || M >= 4096) ? 64 : 128;
-    t.bm = M >= 16384 ? 128 : (M >= 2048 ? 64 : 32);
+bool job_is_conv(const Job& J) { return J.geoms[0].LH > 0; }
+
+// Columns per wave tile (x16) of a job.  Conv: cover the columns in one pass.
+// FC: the widest tile that still yields >= 1024 blocks (occupancy), else 1.
+int job_tn(const Job& J, int B) {
+  const int N = J.geoms[0].N;
+  if (job_is_conv(J)) return N <= 16 ? 1 : (N <= 32 ? 2 : 4);
+  const long gx = (B + 63) / 64;
+  for (int tn : {4, 2})
+    if (gx * ((N + 16 * tn - 1) / (16 * tn)) >= 1024) return tn;
+  return 1;
+}
+
+// Split count of a fully-connected job: enough blocks to fill the chip, each
+// split at least 128 long, scratch within the workspace's capacity.
+int fc_splits(const Job& J, int B, int tn, int want) {
+  const GemmGeom& g = J.geoms[0];
+  const long gx = (B + 63) / 64, gy = (g.N + 16 * tn - 1) / (16 * tn);
+  const long tiles = gx * gy;
+  if (want <= 0) {
+    want = 1;
+    if (tiles < 1024 && g.K >= 256) want = (int)std::min<long>(std::min<long>((1024 + tiles - 1) / tiles, g.K / 128), 32);
   }
+  int sp = std::max(1, want);
+  while (sp > 1 && (size_t)tiles * sp * 64 * 16 * tn > kPartialCap) --sp;
+  return sp;
+}
+
+Tile heuristic_tile(const Job& J, int B) {
+  Tile t;
+  t.tm = 1;
+  t.tn = job_tn(J, B);
+  t.splits = job_is_conv(J) ? 1 : fc_splits(J, B, t.tn, 0);
   return t;
 }
 
@@ -379,14 +445,16 @@ Tile pick_tile(const ld_net* net, int layer, int dir, int B, int mma) {
 }
 
 hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, const EpiArgs& e, Tile t,
-                   hipStream_t s) {
+                   const Workspace& ws, hipStream_t s) {
   GemmGeom g[9];
   const int nc = (int)J.geoms.size();
   for (int i = 0; i < nc; ++i) {
     g[i] = J.geoms[i];
     g[i].M = B * g[i].HWq;
   }
-  return launch_gemm(g[0], src, src_bf16, mma, e, t, nc, g, s);
+  if (job_is_conv(J)) return launch_conv(g, nc, B, src, src_bf16, mma, e, t.tn, s);
+  SplitArgs sp{fc_splits(J, B, t.tn, t.splits), ws.partial, ws.counters};
+  return launch_fc(g[0], src, src_bf16, mma, e, t.tn, sp, s);
 }
 
 EpiArgs epi0() {
@@ -397,9 +465,41 @@ EpiArgs epi0() {
   return e;
 }
 
+// Optional per-launch timing of one ascent iteration (ld_profile_iteration).
+struct Probe {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;
+  int slot = 0;
+};
+thread_local Probe* g_probe = nullptr;
+
+hipError_t probe_begin(int kind, hipStream_t s) {
+  Probe* p = g_probe;
+  if (!p) return hipSuccess;
+  while ((int)p->ev.size() < 2 * (p->slot + 1)) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    p->ev.push_back(e);
+  }
+  if ((int)p->kind.size() <= p->slot) p->kind.resize(p->slot + 1);
+  p->kind[p->slot] = kind;
+  return hipEventRecord(p->ev[2 * p->slot], s);
+}
+
+hipError_t probe_end(hipStream_t s) {
+  Probe* p = g_probe;
+  if (!p) return hipSuccess;
+  hipError_t r = hipEventRecord(p->ev[2 * p->slot + 1], s);
+  p->slot++;
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // argument checks
 // ---------------------------------------------------------------------------
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 int check_batch(const ld_net* net, const ld_batch* bt) {
   if (!net) return fail(LD_E_ARG, "net is NULL");
   if (!bt) return fail(LD_E_ARG, "batch is NULL");
@@ -409,6 +509,9 @@ int check_batch(const ld_net* net, const ld_batch* bt) {
   if (!bt->l || !bt->u) return fail(LD_E_ARG, "batch l/u pointer arrays are NULL");
   for (int k = 0; k < net->n - 1; ++k)
     if (!bt->l[k] || !bt->u[k]) return fail(LD_E_ARG, "batch l[k]/u[k] is NULL for k=" + std::to_string(k + 1));
+  bool al = aligned16(bt->l0) && aligned16(bt->u0) && aligned16(bt->c);
+  for (int k = 0; k < net->n - 1; ++k) al = al && aligned16(bt->l[k]) && aligned16(bt->u[k]);
+  if (!al) return fail(LD_E_ARG, "batch arrays must be 16-byte aligned");
   return LD_OK;
 }
 
@@ -436,7 +539,7 @@ int prepare_objective(const ld_net* net, const ld_batch* bt, Workspace& ws, int 
   e.kind = EPI_STORE;
   e.scale = -1.f;
   e.out_f = ws.gconst;
-  LD_HIP(run_job(Ln.tr, bt->B, bt->c, 0, mma, e, pick_tile(net, n - 1, 1, bt->B, mma), s));
+  LD_HIP(run_job(Ln.tr, bt->B, bt->c, 0, mma, e, pick_tile(net, n - 1, 1, bt->B, mma), ws, s));
   LD_HIP(launch_cdot(bt->B, Ln.n_out, bt->c, nullptr, Ln.bias, ws.cb, s));
   return LD_OK;
 }
@@ -473,15 +576,19 @@ int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Work
       // a linear layer fed by a flattened conv map has one column per neuron of that map
       e.bias_div = L.kind == LD_LINEAR ? bias_div(net, k - 1) : 1;
     }
-    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), s));
+    LD_HIP(probe_begin(100 + k, s));
+    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, s));
+    LD_HIP(probe_end(s));
   }
   // last hidden layer: constant coefficient -W_n^T c
   const int k = n - 1;
+  LD_HIP(probe_begin(200 + k, s));
   LD_HIP(launch_inner_min_const(B, width(net, k), ws.gconst, rho[k - 1], bt->l[k - 1], bt->u[k - 1],
                                 net->L[k - 1].bias, bias_div(net, k), tau, ws.xb[k],
                                 want_val ? ws.val[k] : nullptr, t_dev, adam, o ? o->lr0 : 0.0,
                                 o ? o->lr_end : 0.0, o ? o->total_iters : 0, o ? o->beta1 : 0.0,
                                 o ? o->beta2 : 0.0, o ? o->eps : 0.0, s));
+  LD_HIP(probe_end(s));
   return LD_OK;
 }
 
@@ -508,7 +615,7 @@ int dual_eval_impl(const ld_net* net, const ld_batch* bt, const float* const* rh
       e.xb_in = ws.xb[k];
       e.bias = L.bias;
       e.out_f = supergrad[k - 1];
-      LD_HIP(run_job(L.fwd, B, ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), s));
+      LD_HIP(run_job(L.fwd, B, ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), ws, s));
     }
   }
   return LD_OK;
@@ -532,7 +639,7 @@ int init_impl(const ld_net* net, const ld_batch* bt, int init, int mma, float* c
     e.lo = bt->l[k - 2];
     e.hi = bt->u[k - 2];
     e.out_f = rho[k - 2];
-    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), s));
+    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, s));
   }
   return LD_OK;
 }
@@ -553,7 +660,9 @@ int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts
     e.m = st->m[k - 1];
     e.v = st->v[k - 1];
     e.adam = st->adam;
-    LD_HIP(run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), s));
+    LD_HIP(probe_begin(300 + k, s));
+    LD_HIP(run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), st->ws, s));
+    LD_HIP(probe_end(s));
   }
   return LD_OK;
 }
@@ -814,8 +923,10 @@ int ld_init_duals(const ld_net* net, const ld_batch* bt, int init, int precision
   if (init != LD_INIT_CROWN && init != LD_INIT_ZERO) return fail(LD_E_ARG, "init must be LD_INIT_CROWN or LD_INIT_ZERO");
   if (precision != LD_FP32 && precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
   if (bt->B == 0) return LD_OK;
-  for (int k = 0; k < net->n - 1; ++k)
+  for (int k = 0; k < net->n - 1; ++k) {
     if (!rho[k]) return fail(LD_E_ARG, "rho[k] is NULL");
+    if (!aligned16(rho[k])) return fail(LD_E_ARG, "rho[k] must be 16-byte aligned");
+  }
   ld_net* mnet = const_cast<ld_net*>(net);
   LD_TRY(ws_alloc(net, mnet->ws, bt->B));
   LD_TRY(validate_values(net, bt, mnet->ws, s));
@@ -830,26 +941,35 @@ int ld_dual_eval(const ld_net* net, const ld_batch* bt, const float* const* rho,
   if (precision != LD_FP32 && precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
   if (!(tie_tau >= 0.f) || !std::isfinite(tie_tau)) return fail(LD_E_ARG, "tie_tau must be finite and >= 0");
   if (bt->B == 0) return LD_OK;
-  for (int k = 0; k < net->n - 1; ++k)
+  for (int k = 0; k < net->n - 1; ++k) {
     if (!rho[k]) return fail(LD_E_ARG, "rho[k] is NULL");
+    if (!aligned16(rho[k])) return fail(LD_E_ARG, "rho[k] must be 16-byte aligned");
+  }
   ld_net* mnet = const_cast<ld_net*>(net);
   LD_TRY(ws_alloc(net, mnet->ws, bt->B));
   LD_TRY(validate_values(net, bt, mnet->ws, s));
+  if (supergrad)
+    for (int k = 0; k < net->n - 1; ++k)
+      if (supergrad[k] && !aligned16(supergrad[k])) return fail(LD_E_ARG, "supergrad[k] must be 16-byte aligned");
   return dual_eval_impl(net, bt, rho, mnet->ws, q, supergrad, precision, tie_tau, s);
 }
 
-int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
-  g_err.clear();
+static int check_step_args(const ld_net* net, const ld_batch* bt, const ld_state* st, const ld_opts* o) {
   LD_TRY(check_batch(net, bt));
   if (!st || !o) return fail(LD_E_ARG, "state/opts is NULL");
   if (st->net != net || st->B != bt->B) return fail(LD_E_STATE, "state was created for another net or batch size");
+  if (bt->B == 0) return fail(LD_E_ARG, "empty batch");
   if (o->iters < 0 || o->total_iters < 1) return fail(LD_E_ARG, "iters must be >= 0 and total_iters >= 1");
   if (o->precision != LD_FP32 && o->precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
   if (o->init != LD_INIT_CROWN && o->init != LD_INIT_ZERO && o->init != LD_INIT_GIVEN) return fail(LD_E_ARG, "bad init");
   if (!std::isfinite(o->lr0) || !std::isfinite(o->lr_end) || !(o->beta1 >= 0.f && o->beta1 < 1.f) ||
-      !(o->beta2 >= 0.f && o->beta2 < 1.f) || !(o->eps > 0.f) || !(o->tie_tau >= 0.f))
+      !(o->beta2 >= 0.f && o->beta2 < 1.f) || !(o->eps > 0.f) || !(o->tie_tau >= 0.f) || !std::isfinite(o->tie_tau))
     return fail(LD_E_ARG, "bad Adam constants");
-  LD_TRY(validate_values(net, bt, st->ws, s));
+  return LD_OK;
+}
+
+// First call on a state: dual initialisation, zeroed moments and q(rho^0).
+static int ensure_initialised(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
   const int mma = o->precision == LD_BF16 ? 1 : 0;
   LD_TRY(prepare_objective(net, bt, st->ws, mma, s));
   if (!st->initialized) {
@@ -868,6 +988,14 @@ int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* 
     LD_TRY(prepare_objective(net, bt, st->ws, mma, s));
     st->initialized = true;
   }
+  return LD_OK;
+}
+
+int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_step_args(net, bt, st, o));
+  LD_TRY(validate_values(net, bt, st->ws, s));
+  LD_TRY(ensure_initialised(net, bt, st, o, s));
   if (o->iters == 0) return LD_OK;
   const int chunk = std::min(o->iters, 100);
   std::vector<double> key = graph_key(bt, o, net->n, chunk);
@@ -895,6 +1023,54 @@ int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* 
   const int reps = o->iters / chunk;
   for (int r = 0; r < reps; ++r) LD_HIP(hipGraphLaunch(st->gexec, s));
   for (int i = reps * chunk; i < o->iters; ++i) LD_TRY(iteration(net, bt, st, o, s));
+  return LD_OK;
+}
+
+int ld_state_reset(ld_state* st, hipStream_t s) {
+  g_err.clear();
+  if (!st) return fail(LD_E_ARG, "state is NULL");
+  LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
+  st->initialized = false;
+  return LD_OK;
+}
+
+int ld_profile_iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, int reps,
+                         double* avg_us, int* kinds, int max_slots, int* n_slots, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_step_args(net, bt, st, o));
+  if (reps <= 0 || !avg_us || !kinds || !n_slots || max_slots <= 0) return fail(LD_E_ARG, "bad profile arguments");
+  LD_TRY(ensure_initialised(net, bt, st, o, s));
+  Probe probe;
+  std::vector<double> acc;
+  int rc = LD_OK;
+  for (int r = 0; r < reps && rc == LD_OK; ++r) {
+    probe.slot = 0;
+    g_probe = &probe;
+    rc = iteration(net, bt, st, o, s);
+    g_probe = nullptr;
+    if (rc != LD_OK) break;
+    if (hipStreamSynchronize(s) != hipSuccess) {
+      rc = fail(LD_E_DEVICE, "stream synchronisation failed");
+      break;
+    }
+    acc.resize(probe.slot, 0.0);
+    for (int i = 0; i < probe.slot; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, probe.ev[2 * i], probe.ev[2 * i + 1]) != hipSuccess) {
+        rc = fail(LD_E_DEVICE, "event timing failed");
+        break;
+      }
+      acc[i] += 1000.0 * ms;
+    }
+  }
+  for (hipEvent_t e : probe.ev) (void)hipEventDestroy(e);
+  if (rc != LD_OK) return rc;
+  const int ns = std::min((int)acc.size(), max_slots);
+  for (int i = 0; i < ns; ++i) {
+    avg_us[i] = acc[i] / reps;
+    kinds[i] = probe.kind[i];
+  }
+  *n_slots = ns;
   return LD_OK;
 }
 
@@ -932,7 +1108,7 @@ int ld_final_bound(const ld_net* net, const ld_batch* bt, const ld_state* cst, d
       } else {
         e.kind = EPI_BIAS_STORE;
       }
-      LD_HIP(run_job(L.fwd, B, x, 0, 0, e, pick_tile(net, k - 1, 0, B, 0), s));
+      LD_HIP(run_job(L.fwd, B, x, 0, 0, e, pick_tile(net, k - 1, 0, B, 0), ws, s));
       x = bufs[k & 1];
     }
     if (primal) LD_HIP(launch_cdot(B, net->L[n - 1].n_out, bt->c, x, nullptr, primal, s));

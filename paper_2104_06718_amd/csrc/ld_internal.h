@@ -31,6 +31,10 @@ struct GemmGeom {
   int dst_HW, dst_W;
   int oy_mul, oy_off, ox_mul, ox_off;
   int m_fast;          // 1: epilogue walks rows fastest (conv), 0: columns fastest (FC)
+  // zero-padded copy of one subdomain's source map in LDS (conv jobs):
+  // [src_n / (src_H*src_W)] x LH x LW with the map at offset (pad_t, pad_l)
+  int pad_t, pad_l, LH, LW;
+  const int* ktab_lds; // [Kp] offset of each k in the padded map (c*LH*LW + dky*LW + dkx)
 };
 
 // Epilogue selector (what is done with each accumulated value).
@@ -68,16 +72,28 @@ struct EpiArgs {
   int* flag;            // feasibility flags [B] (EPI_RELU_FWD)
 };
 
-// Launch-time tile configuration.
+// Launch-time tile configuration: each wave computes tm x tn MFMA tiles of 16x16,
+// a block is 4 waves stacked along M, and K is split `splits` ways.
 struct Tile {
-  int bm, bn;
+  int tm, tn, splits;
+};
+
+// Scratch of split-K launches: partial tiles and one arrival counter per tile
+// (zero before the first launch; the last block of a tile resets it).
+struct SplitArgs {
+  int splits;
+  float* partial;
+  int* counters;
 };
 
 // kernels (ld_kernels.hip)
-hipError_t launch_gemm(const GemmGeom& g, const void* src, int src_bf16, int mma_bf16,
-                       const EpiArgs& e, Tile t, int n_classes, const GemmGeom* class_geoms,
-                       hipStream_t s);
-int tile_supported(Tile t, int mma_bf16);
+// convolution contraction, one block per (subdomain, stride class)
+hipError_t launch_conv(const GemmGeom* geoms, int n_classes, int B, const void* src, int src_bf16,
+                       int mma_bf16, const EpiArgs& e, int tn, hipStream_t s);
+size_t conv_lds_bytes(const GemmGeom* g, int n_classes);
+// fully-connected contraction (G.M = B rows), optional split-K
+hipError_t launch_fc(const GemmGeom& g, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e,
+                     int tn, const SplitArgs& sp, hipStream_t s);
 
 hipError_t launch_inner_min_const(int B, int n, const float* g, const float* rho, const float* lo,
                                   const float* hi, const float* bias, int bias_hw, float tau, float* xb,

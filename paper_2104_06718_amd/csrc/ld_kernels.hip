@@ -71,13 +71,6 @@ __device__ __forceinline__ void inner_min(T r, T g, T l, T u, T tau, T& xb, T& x
   }
 }
 
-__device__ __forceinline__ void store_xs(const EpiArgs& E, size_t idx, float x) {
-  if (E.xs_bf16)
-    ((bf16_t*)E.xs)[idx] = f2bf(x);
-  else
-    ((float*)E.xs)[idx] = x;
-}
-
 // CROWN dual of one neuron from g = (W^T rho_next)[i] (eq:salman-assignment with
 // the slopes of eq:slopes-biases: chord upper slope, lower slope 1[u >= -l]).
 __device__ __forceinline__ float crown_dual(float g, float l, float u) {
@@ -87,283 +80,506 @@ __device__ __forceinline__ float crown_dual(float g, float l, float u) {
   return (u >= -l) ? g : 0.f;
 }
 
-__device__ __forceinline__ void adam_step(const EpiArgs& E, size_t idx, float s) {
-  const float lr = E.adam[0], ibc1 = E.adam[1], ibc2 = E.adam[2], eps = E.adam[3];
-  const float b1 = E.adam[4], b2 = E.adam[5];
-  float m = b1 * E.m[idx] + (1.f - b1) * s;
-  float v = b2 * E.v[idx] + (1.f - b2) * (s * s);
-  E.m[idx] = m;
-  E.v[idx] = v;
-  float mh = m * ibc1;
-  float vh = v * ibc2;
-  E.rho_w[idx] = E.rho_w[idx] + lr * mh / (sqrtf(vh) + eps);
+// ---------------------------------------------------------------------------
+// Batched epilogue: four accumulated values of one output column, at indices
+// i0 + q*st (q < nv).  All loads of the four elements are issued before any
+// arithmetic; with VEC the four elements are contiguous and 16-byte aligned.
+// ---------------------------------------------------------------------------
+template <bool VEC>
+__device__ __forceinline__ void ld4(const float* __restrict__ p, size_t i0, size_t st, int nv, float (&o)[4]) {
+  if (VEC) {
+    const float4 v = *reinterpret_cast<const float4*>(p + i0);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = q < nv ? p[i0 + q * st] : 0.f;
+  }
+}
+template <bool VEC>
+__device__ __forceinline__ void st4(float* __restrict__ p, size_t i0, size_t st, int nv, const float (&o)[4]) {
+  if (VEC) {
+    *reinterpret_cast<float4*>(p + i0) = make_float4(o[0], o[1], o[2], o[3]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < nv) p[i0 + q * st] = o[q];
+  }
+}
+template <bool VEC>
+__device__ __forceinline__ void st4_xs(const EpiArgs& E, size_t i0, size_t st, int nv, const float (&o)[4]) {
+  if (E.xs_bf16) {
+    bf16_t* p = (bf16_t*)E.xs;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (VEC || q < nv) p[i0 + q * st] = f2bf(o[q]);
+  } else {
+    st4<VEC>((float*)E.xs, i0, st, nv, o);
+  }
 }
 
-__device__ __forceinline__ void epilogue(const EpiArgs& E, size_t idx, int b, int col, float acc) {
+template <bool VEC>
+__device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st, int nv, int b0, int bstep, int col,
+                                          const float (&acc)[4]) {
   switch (E.kind) {
-    case EPI_STORE:
-      E.out_f[idx] = E.scale * acc;
-      break;
+    case EPI_STORE: {
+      float o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = E.scale * acc[q];
+      st4<VEC>(E.out_f, i0, st, nv, o);
+    } break;
     case EPI_P0: {
-      const float lo = E.lo[idx], hi = E.hi[idx];
-      const float x = (acc >= 0.f) ? hi : lo;
-      store_xs(E, idx, x);
-      if (E.want_val) E.val[idx] = -(double)acc * (double)x;
+      float lo[4], hi[4], x[4];
+      ld4<VEC>(E.lo, i0, st, nv, lo);
+      ld4<VEC>(E.hi, i0, st, nv, hi);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = acc[q] >= 0.f ? hi[q] : lo[q];
+      st4_xs<VEC>(E, i0, st, nv, x);
+      if (E.want_val)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (VEC || q < nv) E.val[i0 + q * st] = -(double)acc[q] * (double)x[q];
     } break;
     case EPI_INNER_MIN: {
-      const float r = E.rho[idx], lo = E.lo[idx], hi = E.hi[idx];
+      float r[4], lo[4], hi[4], xb[4], x[4];
+      ld4<VEC>(E.rho, i0, st, nv, r);
+      ld4<VEC>(E.lo, i0, st, nv, lo);
+      ld4<VEC>(E.hi, i0, st, nv, hi);
       if (E.want_val) {
-        double xb, x, val;
-        inner_min<double>(r, acc, lo, hi, (double)E.tau, xb, x, val);
-        E.val[idx] = val - (double)r * (double)E.bias[col / E.bias_div];
-        store_xs(E, idx, (float)x);
-        E.xb[idx] = (float)xb;
+        const double bias = (double)E.bias[col / E.bias_div];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double xbd, xd, val;
+          inner_min<double>(r[q], acc[q], lo[q], hi[q], (double)E.tau, xbd, xd, val);
+          xb[q] = (float)xbd;
+          x[q] = (float)xd;
+          if (VEC || q < nv) E.val[i0 + q * st] = val - (double)r[q] * bias;
+        }
       } else {
-        float xb, x, val;
-        inner_min<float>(r, acc, lo, hi, E.tau, xb, x, val);
-        store_xs(E, idx, x);
-        E.xb[idx] = xb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float val;
+          inner_min<float>(r[q], acc[q], lo[q], hi[q], E.tau, xb[q], x[q], val);
+        }
       }
+      st4_xs<VEC>(E, i0, st, nv, x);
+      st4<VEC>(E.xb, i0, st, nv, xb);
     } break;
     case EPI_ADAM: {
-      const float s = E.xb_in[idx] - (acc + E.bias[col]);
-      adam_step(E, idx, s);
+      float xb[4], rho[4], m[4], v[4];
+      ld4<VEC>(E.xb_in, i0, st, nv, xb);
+      ld4<VEC>(E.rho_w, i0, st, nv, rho);
+      ld4<VEC>(E.m, i0, st, nv, m);
+      ld4<VEC>(E.v, i0, st, nv, v);
+      const float lr = E.adam[0], ibc1 = E.adam[1], ibc2 = E.adam[2], eps = E.adam[3];
+      const float b1 = E.adam[4], b2 = E.adam[5];
+      const float bias = E.bias[col];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float s = xb[q] - (acc[q] + bias);
+        m[q] = b1 * m[q] + (1.f - b1) * s;
+        v[q] = b2 * v[q] + (1.f - b2) * (s * s);
+        rho[q] = rho[q] + lr * (m[q] * ibc1) / (sqrtf(v[q] * ibc2) + eps);
+      }
+      st4<VEC>(E.m, i0, st, nv, m);
+      st4<VEC>(E.v, i0, st, nv, v);
+      st4<VEC>(E.rho_w, i0, st, nv, rho);
     } break;
-    case EPI_SUPERGRAD:
-      E.out_f[idx] = E.xb_in[idx] - (acc + E.bias[col]);
-      break;
-    case EPI_CROWN:
-      E.out_f[idx] = crown_dual(acc, E.lo[idx], E.hi[idx]);
-      break;
+    case EPI_SUPERGRAD: {
+      float xb[4], o[4];
+      ld4<VEC>(E.xb_in, i0, st, nv, xb);
+      const float bias = E.bias[col];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = xb[q] - (acc[q] + bias);
+      st4<VEC>(E.out_f, i0, st, nv, o);
+    } break;
+    case EPI_CROWN: {
+      float lo[4], hi[4], o[4];
+      ld4<VEC>(E.lo, i0, st, nv, lo);
+      ld4<VEC>(E.hi, i0, st, nv, hi);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = crown_dual(acc[q], lo[q], hi[q]);
+      st4<VEC>(E.out_f, i0, st, nv, o);
+    } break;
     case EPI_RELU_FWD: {
-      const float y = acc + E.bias[col];
-      if (!(y >= E.lo[idx] && y <= E.hi[idx])) E.flag[b] = 0;
-      E.out_f[idx] = fmaxf(y, 0.f);
+      float lo[4], hi[4], o[4];
+      ld4<VEC>(E.lo, i0, st, nv, lo);
+      ld4<VEC>(E.hi, i0, st, nv, hi);
+      const float bias = E.bias[col];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float y = acc[q] + bias;
+        if ((VEC || q < nv) && !(y >= lo[q] && y <= hi[q])) E.flag[b0 + q * bstep] = 0;
+        o[q] = fmaxf(y, 0.f);
+      }
+      st4<VEC>(E.out_f, i0, st, nv, o);
     } break;
-    case EPI_BIAS_STORE:
-      E.out_f[idx] = acc + E.bias[col];
-      break;
+    case EPI_BIAS_STORE: {
+      float o[4];
+      const float bias = E.bias[col];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = acc[q] + bias;
+      st4<VEC>(E.out_f, i0, st, nv, o);
+    } break;
     default:
       break;
   }
 }
 
 // ---------------------------------------------------------------------------
-// implicit GEMM: block = 4 waves of 64 lanes; tile BM x BN, K step BK.
+// MFMA fragments.  FP32 (v_mfma_f32_16x16x4f32): for a K step of 16, lane l
+// (r = l & 15, g = l >> 4) holds A[r][k0+4g+j] and B[k0+4g+j][r], j = 0..3, and
+// issues one MFMA per j; the 4 MFMAs sum k0..k0+15 once each (the k order inside
+// the step is permuted so both operands are contiguous).  BF16
+// (v_mfma_f32_16x16x32_bf16): lane holds A[r][k0+8g..+7], B[k0+8g..+7][r].
+// Output: lane holds C[4g+q][r], q = 0..3.
 // ---------------------------------------------------------------------------
-template <int BM, int BN, bool MMA_BF16, bool SRC_BF16>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmPack P, const void* __restrict__ src_v, EpiArgs E) {
-  const GemmGeom& G = P.g[blockIdx.z];
-  constexpr int BK = MMA_BF16 ? 32 : 16;
-  constexpr int WM = (BN >= 64) ? 2 : 4;
-  constexpr int WN = 4 / WM;
-  constexpr int WTM = BM / WM;
-  constexpr int WTN = BN / WN;
-  constexpr int TM = WTM / 16;
-  constexpr int TN = WTN / 16;
-  static_assert(TM >= 1 && TN >= 1, "tile too small for the wave layout");
-  using AT = typename std::conditional<MMA_BF16, bf16_t, float>::type;
-  constexpr int LDA = BK + (MMA_BF16 ? 8 : 1);
-  constexpr int LDC = BM + 1;
+template <bool MMA_BF16>
+struct Mma;
+template <>
+struct Mma<false> {
+  static constexpr int KS = 16, VPL = 4;
+  typedef float4 BFrag;
+  __device__ static BFrag loadB(const GemmGeom& G, size_t off) { return *reinterpret_cast<const float4*>(G.Bf + off); }
+  __device__ static void mma(const float (&a)[4], const BFrag& b, f32x4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b.x, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b.y, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b.z, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b.w, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mma<true> {
+  static constexpr int KS = 32, VPL = 8;
+  typedef bf16x8 BFrag;
+  __device__ static BFrag loadB(const GemmGeom& G, size_t off) { return *reinterpret_cast<const bf16x8*>(G.Bh + off); }
+  __device__ static void mma(const float (&a)[8], const BFrag& b, f32x4& c) {
+    bf16x8 av;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) av[j] = (__bf16)a[j];
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, c, 0, 0, 0);
+  }
+};
 
-  __shared__ __attribute__((aligned(16))) AT As[BM * LDA];
-  __shared__ __attribute__((aligned(16))) AT Bs[BN * LDA];
-  __shared__ float Cs[BN * LDC];
-  __shared__ int rowb[BM];
-  __shared__ int rowy[BM];
-  __shared__ int rowx[BM];
-
-  const int m0 = blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
-  if (m0 >= G.M || n0 >= G.N) return;  // uniform per block (classes differ in M)
+// ---------------------------------------------------------------------------
+// Convolution contraction of one subdomain per block, all stride classes.
+//  1. the block copies the subdomain's source map into a zero-padded LDS image
+//     (so the gather needs no bounds tests);
+//  2. waves compute 16-pixel x 16-column MFMA tiles of every class, reading A
+//     from the image and B (packed weights) from memory, and write the results
+//     into an LDS copy of the destination map (classes land on their pixels);
+//  3. all threads stream the epilogue over the destination map in order,
+//     16 bytes per access.
+// ---------------------------------------------------------------------------
+template <bool MMA_BF16, bool SRC_BF16, int TN>
+__global__ __launch_bounds__(256) void conv_plane_kernel(GemmPack P, const void* __restrict__ src_v, EpiArgs E,
+                                                         int img_floats, int dst_hw4, int kp_max) {
+  using M = Mma<MMA_BF16>;
+  constexpr int KS = M::KS, VPL = M::VPL;
+  extern __shared__ float lds[];
+  const GemmGeom& G0 = P.g[0];
+  const int b = blockIdx.x;
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int C = G0.src_n / (G0.src_H * G0.src_W);
+  const int HW = G0.src_H * G0.src_W;
+  const int LHW = G0.LH * G0.LW;
+  float* img = lds;                      // [C][LH][LW]
+  float* outp = lds + img_floats;        // [dst_n]
+  int* kofs = (int*)(outp + G0.dst_n);   // [n classes][kp_max]
 
-  for (int r = tid; r < BM; r += 256) {
-    const int m = m0 + r;
-    if (m < G.M) {
-      const int b = m / G.HWq;
-      const int rem = m - b * G.HWq;
-      const int yq = rem / G.Wq;
-      rowb[r] = b;
-      rowy[r] = yq;
-      rowx[r] = rem - yq * G.Wq;
-    } else {
-      rowb[r] = -1;
-      rowy[r] = 0;
-      rowx[r] = 0;
+  // 1. zero image, then copy the source map (coalesced) into its interior
+  for (int e = tid; e < img_floats; e += 256) img[e] = 0.f;
+  for (int c = 0; c < P.n; ++c)
+    for (int k = tid; k < P.g[c].Kp; k += 256) kofs[c * kp_max + k] = P.g[c].ktab_lds[k];
+  __syncthreads();
+  if (SRC_BF16) {
+    const bf16_t* src = (const bf16_t*)src_v + (size_t)b * G0.src_n;
+    for (int e = tid; e < G0.src_n; e += 256) {
+      const int c = e / HW;
+      const int rem = e - c * HW;
+      const int iy = rem / G0.src_W;
+      const int ix = rem - iy * G0.src_W;
+      img[c * LHW + (iy + G0.pad_t) * G0.LW + ix + G0.pad_l] = bf2f(src[e]);
+    }
+  } else {
+    const float* src = (const float*)src_v + (size_t)b * G0.src_n;
+    for (int e = tid; e < G0.src_n; e += 256) {
+      const int c = e / HW;
+      const int rem = e - c * HW;
+      const int iy = rem / G0.src_W;
+      const int ix = rem - iy * G0.src_W;
+      img[c * LHW + (iy + G0.pad_t) * G0.LW + ix + G0.pad_l] = src[e];
     }
   }
   __syncthreads();
 
-  f32x4 acc[TM][TN];
+  // 2. MFMA tiles of every class into the LDS destination map
+  int tiles_before = 0;
+  for (int cl = 0; cl < P.n; ++cl) {
+    const GemmGeom& G = P.g[cl];
+    const int* ko = kofs + cl * kp_max;
+    const int ntiles = (G.HWq + 15) >> 4;
+    const int nct = (G.N + 16 * TN - 1) / (16 * TN);
+    // distribute (tile, column chunk) pairs over the waves, continuing the rotation across classes
+    const int total = ntiles * nct;
+    int first = (wave - tiles_before) % 4;
+    if (first < 0) first += 4;
+    for (int w = first; w < total; w += 4) {
+      const int tile = w / nct;
+      const int nc = (w - tile * nct) * 16 * TN;
+      const int p = min(tile * 16 + r, G.HWq - 1);
+      const int yq = p / G.Wq;
+      const int xq = p - yq * G.Wq;
+      const int lb = (yq * G.iy_mul + G.iy_off + G.pad_t) * G.LW + xq * G.ix_mul + G.ix_off + G.pad_l;
+      f32x4 acc[TN];
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+      for (int t = 0; t < TN; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int k0 = 0; k0 < G.K; k0 += KS) {
+        const int kl = k0 + VPL * g;
+        float a[VPL];
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  const float* srcf = (const float*)src_v;
-  const bf16_t* srch = (const bf16_t*)src_v;
-  const int wave = tid >> 6;
-  const int lane = tid & 63;
-  const int wm = wave % WM;
-  const int wn = wave / WM;
-
-  for (int k0 = 0; k0 < G.K; k0 += BK) {
-    // gathered A tile (zero outside the source plane and beyond K)
-    for (int e = tid; e < BM * BK; e += 256) {
-      const int r = e / BK;
-      const int kk = e - r * BK;
-      const int k = k0 + kk;
-      const int b = rowb[r];
-      AT a = AT(0);
-      if (b >= 0 && k < G.K) {
-        const int4 t = G.ktab[k];
-        const int iy = rowy[r] * G.iy_mul + G.iy_off + t.y;
-        const int ix = rowx[r] * G.ix_mul + G.ix_off + t.z;
-        if ((unsigned)iy < (unsigned)G.src_H && (unsigned)ix < (unsigned)G.src_W) {
-          const size_t off = (size_t)b * G.src_n + t.x + iy * G.src_W + ix;
-          if constexpr (SRC_BF16) {
-            if constexpr (MMA_BF16)
-              a = srch[off];
-            else
-              a = bf2f(srch[off]);
-          } else {
-            if constexpr (MMA_BF16)
-              a = f2bf(srcf[off]);
-            else
-              a = srcf[off];
+        for (int j = 0; j < VPL; ++j) a[j] = img[lb + ko[kl + j]];
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+          const typename M::BFrag bf = M::loadB(G, (size_t)(nc + 16 * t + r) * G.Kp + kl);
+          M::mma(a, bf, acc[t]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int pq = tile * 16 + 4 * g + q;
+        if (pq < G.HWq) {
+          const int yy = pq / G.Wq;
+          const int xx = pq - yy * G.Wq;
+          const int j0 = (yy * G.oy_mul + G.oy_off) * G.dst_W + xx * G.ox_mul + G.ox_off;
+#pragma unroll
+          for (int t = 0; t < TN; ++t) {
+            const int col = nc + 16 * t + r;
+            if (col < G.N) outp[col * G.dst_HW + j0] = acc[t][q];
           }
         }
       }
-      As[r * LDA + kk] = a;
     }
-    // B tile from the packed [Np][Kp] operand (padding is zero)
-    for (int e = tid; e < BN * BK; e += 256) {
-      const int n = e / BK;
-      const int kk = e - n * BK;
-      const size_t off = (size_t)(n0 + n) * G.Kp + k0 + kk;
-      if constexpr (MMA_BF16)
-        Bs[n * LDA + kk] = G.Bh[off];
-      else
-        Bs[n * LDA + kk] = G.Bf[off];
-    }
-    __syncthreads();
-
-    if constexpr (MMA_BF16) {
-      bf16x8 av[TM], bv[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-        av[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * WTM + i * 16 + (lane & 15)) * LDA + 8 * (lane >> 4)]);
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-        bv[j] = *reinterpret_cast<const bf16x8*>(&Bs[(wn * WTN + j * 16 + (lane & 15)) * LDA + 8 * (lane >> 4)]);
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        float av[TM], bv[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) av[i] = As[(wm * WTM + i * 16 + (lane & 15)) * LDA + kk + (lane >> 4)];
-#pragma unroll
-        for (int j = 0; j < TN; ++j) bv[j] = Bs[(wn * WTN + j * 16 + (lane & 15)) * LDA + kk + (lane >> 4)];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-      }
-    }
-    __syncthreads();
+    tiles_before += total;
   }
-
-  // stage the accumulators through LDS so that the epilogue walks memory in order
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = wm * WTM + i * 16 + 4 * (lane >> 4) + q;
-        const int col = wn * WTN + j * 16 + (lane & 15);
-        Cs[col * LDC + row] = acc[i][j][q];
-      }
   __syncthreads();
 
-  for (int e = tid; e < BM * BN; e += 256) {
-    int r, n;
-    if (G.m_fast) {
-      n = e / BM;
-      r = e - n * BM;
-    } else {
-      r = e / BN;
-      n = e - r * BN;
+  // 3. epilogue over the destination map in memory order
+  const size_t base = (size_t)b * G0.dst_n;
+  if (dst_hw4) {
+    for (int e = 4 * tid; e < G0.dst_n; e += 1024) {
+      const int col = e / G0.dst_HW;  // channel (four consecutive neurons share it)
+      float v4[4] = {outp[e], outp[e + 1], outp[e + 2], outp[e + 3]};
+      epilogue4<true>(E, base + e, 1, 4, b, 0, col, v4);
     }
-    const int b = rowb[r];
-    const int col = n0 + n;
-    if (b < 0 || col >= G.N) continue;
-    const int j = col * G.dst_HW + (rowy[r] * G.oy_mul + G.oy_off) * G.dst_W + rowx[r] * G.ox_mul + G.ox_off;
-    epilogue(E, (size_t)b * G.dst_n + j, b, col, Cs[n * LDC + r]);
+  } else {
+    for (int e = tid; e < G0.dst_n; e += 256) {
+      const int col = e / G0.dst_HW;
+      float v4[4] = {outp[e], 0.f, 0.f, 0.f};
+      epilogue4<false>(E, base + e, 1, 1, b, 0, col, v4);
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// tile dispatch
+// Fully-connected contraction (rows = subdomains, columns = neurons), with both
+// operands loaded register-direct.  Block = 4 waves stacked along rows; each
+// wave owns 16 rows x 16*TN columns.  With splits > 1 (long K) each block writes
+// a partial tile and fc_split_reduce adds the partials in split order and runs
+// the epilogue (deterministic, no cross-block synchronisation).
 // ---------------------------------------------------------------------------
-template <int BM, int BN>
-static hipError_t launch_tile(const GemmPack& P, int max_m, const void* src, int src_bf16, int mma_bf16,
-                              const EpiArgs& e, hipStream_t s) {
-  dim3 grid((max_m + BM - 1) / BM, (P.g[0].N + BN - 1) / BN, P.n);
-  dim3 block(256);
+template <int TN, bool MMA_BF16, bool SRC_BF16>
+__global__ __launch_bounds__(256) void fc_kernel(GemmGeom G, const void* __restrict__ src_v, EpiArgs E, SplitArgs S) {
+  using M = Mma<MMA_BF16>;
+  constexpr int KS = M::KS, VPL = M::VPL;
+  const int split = blockIdx.z;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int m0 = blockIdx.x * 64 + wave * 16;
+  const int n0 = blockIdx.y * (16 * TN);
+  const int ksteps = (G.K + KS - 1) / KS;
+  const int per = (ksteps + S.splits - 1) / S.splits;
+  const int kbeg = split * per * KS;
+  const int kend = min(G.K, (split + 1) * per * KS);
+
+  const int row = m0 + r;
+  const bool rvalid = row < G.M;
+  const size_t base = (size_t)(rvalid ? row : 0) * G.src_n;
+  const float* srcf = (const float*)src_v;
+  const bf16_t* srch = (const bf16_t*)src_v;
+  const bool vec = (G.src_n % (SRC_BF16 ? 8 : 4)) == 0;
+
+  f32x4 acc[TN];
+#pragma unroll
+  for (int t = 0; t < TN; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kbeg; k0 < kend; k0 += KS) {
+    const int kl = k0 + VPL * g;
+    float a[VPL];
+    if (vec && kl + VPL <= G.K) {
+      if (SRC_BF16) {
+        const bf16x8 h = *reinterpret_cast<const bf16x8*>(srch + base + kl);
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) a[j] = (float)h[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < VPL; j += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(srcf + base + kl + j);
+          a[j] = v.x;
+          a[j + 1] = v.y;
+          a[j + 2] = v.z;
+          a[j + 3] = v.w;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < VPL; ++j) {
+        const int k = kl + j;
+        const size_t off = k < G.K ? base + k : base;
+        const float v = SRC_BF16 ? bf2f(srch[off]) : srcf[off];
+        a[j] = k < G.K ? v : 0.f;
+      }
+    }
+    if (!rvalid) {
+#pragma unroll
+      for (int j = 0; j < VPL; ++j) a[j] = 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      const typename M::BFrag bf = M::loadB(G, (size_t)(n0 + 16 * t + r) * G.Kp + kl);
+      M::mma(a, bf, acc[t]);
+    }
+  }
+
+  if (S.splits > 1) {
+    // partial tile layout [tile][split][64 rows][16*TN cols]
+    const size_t tile_id = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    float* mine = S.partial + (tile_id * S.splits + split) * (64 * 16 * TN);
+#pragma unroll
+    for (int t = 0; t < TN; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) mine[(wave * 16 + 4 * g + q) * (16 * TN) + 16 * t + r] = acc[t][q];
+    return;
+  }
+  // epilogue: lane holds rows m0+4g+q (subdomains) of column n0+16t+r
+  const int mrow = m0 + 4 * g;
+  const int nv = min(4, G.M - mrow);
+  if (nv <= 0) return;
+#pragma unroll
+  for (int t = 0; t < TN; ++t) {
+    const int col = n0 + 16 * t + r;
+    if (col >= G.N) continue;
+    float v4[4] = {acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
+    epilogue4<false>(E, (size_t)mrow * G.dst_n + col, (size_t)G.dst_n, nv, mrow, 1, col, v4);
+  }
+}
+
+template <int TN>
+__global__ __launch_bounds__(256) void fc_split_reduce(GemmGeom G, EpiArgs E, SplitArgs S, int gx) {
+  // one thread per output element; columns fastest (coalesced epilogue)
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (size_t)G.M * G.N) return;
+  const int m = (int)(e / G.N);
+  const int col = (int)(e - (size_t)m * G.N);
+  const int cols = 16 * TN;
+  const int bx = m >> 6, by = col / cols;
+  const size_t tile_id = (size_t)by * gx + bx;
+  const float* pt = S.partial + tile_id * S.splits * (64 * cols) + (m & 63) * cols + (col - by * cols);
+  float v = 0.f;
+  for (int sp = 0; sp < S.splits; ++sp) v += pt[(size_t)sp * (64 * cols)];
+  float v4[4] = {v, 0.f, 0.f, 0.f};
+  epilogue4<false>(E, (size_t)m * G.dst_n + col, 1, 1, m, 0, col, v4);
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+static int conv_img_floats(const GemmGeom& g) {
+  const int C = g.src_n / (g.src_H * g.src_W);
+  return C * g.LH * g.LW;
+}
+
+static int max_kp(const GemmGeom* g, int n) {
+  int m = 0;
+  for (int i = 0; i < n; ++i) m = g[i].Kp > m ? g[i].Kp : m;
+  return m;
+}
+
+size_t conv_lds_bytes(const GemmGeom* g, int n_classes) {
+  return ((size_t)conv_img_floats(g[0]) + g[0].dst_n + (size_t)n_classes * max_kp(g, n_classes)) * 4;
+}
+
+template <int TN>
+static hipError_t launch_conv_tn(const GemmPack& P, int B, const void* src, int src_bf16, int mma_bf16,
+                                 const EpiArgs& e, hipStream_t s) {
+  const GemmGeom& G = P.g[0];
+  const size_t lds = conv_lds_bytes(P.g, P.n);
+  const int kpm = max_kp(P.g, P.n);
+  const int img = conv_img_floats(G);
+  const int hw4 = (G.dst_HW % 4) == 0;
+  dim3 grid(B), block(256);
+  if (lds > 64 * 1024) {
+    (void)hipFuncSetAttribute((const void*)conv_plane_kernel<true, true, TN>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)conv_plane_kernel<true, false, TN>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)conv_plane_kernel<false, false, TN>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
   if (mma_bf16) {
     if (src_bf16)
-      hipLaunchKernelGGL((gemm_kernel<BM, BN, true, true>), grid, block, 0, s, P, src, e);
+      hipLaunchKernelGGL((conv_plane_kernel<true, true, TN>), grid, block, lds, s, P, src, e, img, hw4, kpm);
     else
-      hipLaunchKernelGGL((gemm_kernel<BM, BN, true, false>), grid, block, 0, s, P, src, e);
+      hipLaunchKernelGGL((conv_plane_kernel<true, false, TN>), grid, block, lds, s, P, src, e, img, hw4, kpm);
   } else {
     if (src_bf16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, false, false>), grid, block, 0, s, P, src, e);
+    hipLaunchKernelGGL((conv_plane_kernel<false, false, TN>), grid, block, lds, s, P, src, e, img, hw4, kpm);
   }
   return hipGetLastError();
 }
 
-int tile_supported(Tile t, int /*mma_bf16*/) {
-  const int bm = t.bm, bn = t.bn;
-  if (bn == 16 || bn == 32) return bm == 64 || bm == 128 || bm == 256;
-  if (bn == 64 || bn == 128) return bm == 32 || bm == 64 || bm == 128;
-  return 0;
+hipError_t launch_conv(const GemmGeom* geoms, int n, int B, const void* src, int src_bf16, int mma_bf16,
+                       const EpiArgs& e, int tn, hipStream_t s) {
+  GemmPack P;
+  if (n <= 0 || n > kMaxClasses) return hipErrorInvalidValue;
+  P.n = n;
+  for (int i = 0; i < n; ++i) P.g[i] = geoms[i];
+  if (B == 0 || P.g[0].N == 0) return hipSuccess;
+  if (tn == 1) return launch_conv_tn<1>(P, B, src, src_bf16, mma_bf16, e, s);
+  if (tn == 2) return launch_conv_tn<2>(P, B, src, src_bf16, mma_bf16, e, s);
+  if (tn == 4) return launch_conv_tn<4>(P, B, src, src_bf16, mma_bf16, e, s);
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_gemm(const GemmGeom& g0, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e,
-                       Tile t, int n_classes, const GemmGeom* class_geoms, hipStream_t s) {
-  GemmPack P;
-  if (n_classes <= 0) {
-    P.n = 1;
-    P.g[0] = g0;
+template <int TN>
+static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e,
+                               const SplitArgs& sp, hipStream_t s) {
+  const int gx = (G.M + 63) / 64, gy = (G.N + 16 * TN - 1) / (16 * TN);
+  dim3 grid(gx, gy, sp.splits), block(256);
+  if (mma_bf16) {
+    if (src_bf16)
+      hipLaunchKernelGGL((fc_kernel<TN, true, true>), grid, block, 0, s, G, src, e, sp);
+    else
+      hipLaunchKernelGGL((fc_kernel<TN, true, false>), grid, block, 0, s, G, src, e, sp);
   } else {
-    if (n_classes > kMaxClasses) return hipErrorInvalidValue;
-    P.n = n_classes;
-    for (int i = 0; i < n_classes; ++i) P.g[i] = class_geoms[i];
+    if (src_bf16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((fc_kernel<TN, false, false>), grid, block, 0, s, G, src, e, sp);
   }
-  int max_m = 0;
-  for (int i = 0; i < P.n; ++i) max_m = P.g[i].M > max_m ? P.g[i].M : max_m;
-  if (max_m == 0 || P.g[0].N == 0) return hipSuccess;
-#define LD_TILE(BM_, BN_) \
-  if (t.bm == BM_ && t.bn == BN_) return launch_tile<BM_, BN_>(P, max_m, src, src_bf16, mma_bf16, e, s);
-  LD_TILE(64, 16)
-  LD_TILE(128, 16)
-  LD_TILE(256, 16)
-  LD_TILE(64, 32)
-  LD_TILE(128, 32)
-  LD_TILE(256, 32)
-  LD_TILE(32, 64)
-  LD_TILE(64, 64)
-  LD_TILE(128, 64)
-  LD_TILE(32, 128)
-  LD_TILE(64, 128)
-  LD_TILE(128, 128)
-#undef LD_TILE
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || sp.splits <= 1) return err;
+  const size_t outs = (size_t)G.M * G.N;
+  hipLaunchKernelGGL((fc_split_reduce<TN>), dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s, G, e, sp, gx);
+  return hipGetLastError();
+}
+
+hipError_t launch_fc(const GemmGeom& G, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e, int tn,
+                     const SplitArgs& sp, hipStream_t s) {
+  if (G.M == 0 || G.N == 0) return hipSuccess;
+  if (tn == 1) return launch_fc_tn<1>(G, src, src_bf16, mma_bf16, e, sp, s);
+  if (tn == 2) return launch_fc_tn<2>(G, src, src_bf16, mma_bf16, e, sp, s);
+  if (tn == 4) return launch_fc_tn<4>(G, src, src_bf16, mma_bf16, e, sp, s);
   return hipErrorInvalidValue;
 }
 
