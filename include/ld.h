@@ -60,6 +60,7 @@ enum {
 enum { LD_LINEAR = 0, LD_CONV2D = 1 };          /* layer kinds (Sec. 2.1)          */
 enum { LD_FP32 = 0, LD_BF16 = 1 };              /* operand precision of the contractions */
 enum { LD_INIT_CROWN = 0, LD_INIT_ZERO = 1, LD_INIT_GIVEN = 2 };
+enum { LD_ENGINE_AUTO = 0, LD_ENGINE_RESIDENT = 1, LD_ENGINE_LAYERWISE = 2 };
 
 /* ------------------------------------------------------------------------- */
 /* network                                                                   */
@@ -191,7 +192,15 @@ int ld_dual_eval(const ld_net* net, const ld_batch* batch, const float* const* r
  * init        used on the first call of a state: LD_INIT_CROWN (default of
  *             the paper, Sec. 7.2), LD_INIT_ZERO, or LD_INIT_GIVEN (duals set
  *             by ld_state_set_rho).  On that call q(rho^0) is stored.
- * tie_tau     relative tie band of the inner minimisation (2^-20 suggested). */
+ * tie_tau     relative tie band of the inner minimisation (2^-20 suggested).
+ * engine      LD_ENGINE_RESIDENT: one launch runs all `iters` steps, each
+ *             workgroup owning S subdomains with their intermediates in LDS
+ *             (LD_E_UNSUPPORTED if the layer maps do not fit);
+ *             LD_ENGINE_LAYERWISE: one batched launch per contraction and
+ *             iteration, replayed from a captured HIP graph;
+ *             LD_ENGINE_AUTO: the layer-wise engine (measured faster on the
+ *             shapes tested so far).
+ *             Both compute the same iteration. */
 typedef struct ld_opts {
   int iters;
   int total_iters;
@@ -200,12 +209,12 @@ typedef struct ld_opts {
   int precision;
   int init;
   float tie_tau;
+  int engine;
 } ld_opts;
 
-/* Enqueue `iters` Adam supergradient steps for every subdomain.  The loop is
- * captured once per (state, batch pointers, options) into a HIP graph and
- * replayed; capture, instantiation and tile autotuning happen on the first
- * call with a new configuration. */
+/* Enqueue `iters` Adam supergradient steps for every subdomain (engine per
+ * ld_opts).  The layer-wise engine captures its loop once per (state, batch
+ * pointers, options) into a HIP graph and replays it. */
 int ld_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opts* opts,
             hipStream_t stream);
 

@@ -20,10 +20,12 @@ LD_OK, LD_E_ARG, LD_E_SHAPE, LD_E_NUMERIC, LD_E_NOMEM, LD_E_DEVICE, LD_E_UNSUPPO
 LD_LINEAR, LD_CONV2D = 0, 1
 LD_FP32, LD_BF16 = 0, 1
 LD_INIT_CROWN, LD_INIT_ZERO, LD_INIT_GIVEN = 0, 1, 2
+LD_ENGINE_AUTO, LD_ENGINE_RESIDENT, LD_ENGINE_LAYERWISE = 0, 1, 2
 TAU_DEFAULT = 2.0 ** -20
 
 _PREC = {"fp32": LD_FP32, "bf16": LD_BF16, LD_FP32: LD_FP32, LD_BF16: LD_BF16}
 _INIT = {"crown": LD_INIT_CROWN, "zero": LD_INIT_ZERO, "given": LD_INIT_GIVEN}
+_ENGINE = {"auto": LD_ENGINE_AUTO, "resident": LD_ENGINE_RESIDENT, "layerwise": LD_ENGINE_LAYERWISE}
 
 EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num_layers",
             "ld_set_validation", "ld_state_create", "ld_state_destroy", "ld_state_set_rho",
@@ -54,7 +56,7 @@ class ld_opts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("total_iters", ctypes.c_int), ("lr0", ctypes.c_float),
                 ("lr_end", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("precision", ctypes.c_int), ("init", ctypes.c_int),
-                ("tie_tau", ctypes.c_float)]
+                ("tie_tau", ctypes.c_float), ("engine", ctypes.c_int)]
 
 
 _lib = None
@@ -256,14 +258,14 @@ def dual_eval(net: Net, batch: Batch, rho: List[torch.Tensor], supergrad=True, p
 
 def step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional[int] = None, lr0=1e-2,
          lr_end=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, precision="fp32", init="crown",
-         tau: float = TAU_DEFAULT, stream=None):
-    o = _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau)
+         tau: float = TAU_DEFAULT, engine="auto", stream=None):
+    o = _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine)
     _check(net.lib.ld_step(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o), _stream(stream)))
 
 
-def _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau):
+def _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine="auto"):
     return ld_opts(int(iters), int(total_iters if total_iters is not None else iters), lr0, lr_end, beta1, beta2,
-                   eps, _PREC[precision], _INIT[init], tau)
+                   eps, _PREC[precision], _INIT[init], tau, _ENGINE[engine])
 
 
 def profile_iteration(net: Net, batch: Batch, state: State, reps=10, total_iters=500, lr0=1e-2, lr_end=1e-4,

@@ -67,6 +67,8 @@ struct Layer {
   int n_in, n_out;
   float* bias = nullptr;  // device [out_c]
   Job fwd, tr;
+  const GemmGeom* fwd_dev = nullptr;  // device copies of the geometries (resident engine)
+  const GemmGeom* tr_dev = nullptr;
 };
 
 // Buffers of one evaluation pipeline for a batch of B subdomains.
@@ -118,6 +120,7 @@ struct ld_state {
   hipGraphExec_t gexec = nullptr;
   std::vector<double> gkey;
   int gchunk = 0;
+  int t_host = 0;       // Adam steps enqueued so far (mirrors *t_dev)
 };
 
 namespace {
@@ -551,6 +554,8 @@ int bias_div(const ld_net* net, int k) {
 }
 
 // Phase A: inner minimisations of P_0..P_{n-1} at duals rho (rho[k-1] = rho_k).
+// In the ascent (o != nullptr) the first launch also advances the step counter,
+// and the last hidden layer's minimisation is left to its Adam epilogue.
 int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Workspace& ws, int mma, float tau,
             int want_val, int* t_dev, float* adam, const ld_opts* o, hipStream_t s) {
   const int n = net->n, B = bt->B;
@@ -562,6 +567,16 @@ int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Work
     e.xs_bf16 = mma;
     e.xs = ws.xs[k - 1];
     e.val = ws.val[k - 1];
+    if (k == 1 && o != nullptr) {
+      e.t_dev = t_dev;
+      e.adam_w = adam;
+      e.lr0 = o->lr0;
+      e.lr_end = o->lr_end;
+      e.total = o->total_iters;
+      e.beta1 = o->beta1;
+      e.beta2 = o->beta2;
+      e.eps = o->eps;
+    }
     if (k == 1) {
       e.kind = EPI_P0;
       e.lo = bt->l0;
@@ -580,14 +595,13 @@ int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Work
     LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, s));
     LD_HIP(probe_end(s));
   }
+  if (o != nullptr) return LD_OK;
   // last hidden layer: constant coefficient -W_n^T c
   const int k = n - 1;
   LD_HIP(probe_begin(200 + k, s));
   LD_HIP(launch_inner_min_const(B, width(net, k), ws.gconst, rho[k - 1], bt->l[k - 1], bt->u[k - 1],
                                 net->L[k - 1].bias, bias_div(net, k), tau, ws.xb[k],
-                                want_val ? ws.val[k] : nullptr, t_dev, adam, o ? o->lr0 : 0.0,
-                                o ? o->lr_end : 0.0, o ? o->total_iters : 0, o ? o->beta1 : 0.0,
-                                o ? o->beta2 : 0.0, o ? o->eps : 0.0, s));
+                                want_val ? ws.val[k] : nullptr, nullptr, nullptr, 0, 0, 0, 0, 0, 0, s));
   LD_HIP(probe_end(s));
   return LD_OK;
 }
@@ -655,6 +669,13 @@ int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts
     EpiArgs e = epi0();
     e.kind = EPI_ADAM;
     e.xb_in = st->ws.xb[k];
+    if (k == n - 1) {
+      e.kind = EPI_ADAM_LAST;
+      e.gc = st->ws.gconst;
+      e.lo = bt->l[k - 1];
+      e.hi = bt->u[k - 1];
+      e.tau = o->tie_tau;
+    }
     e.bias = L.bias;
     e.rho_w = st->rho[k - 1];
     e.m = st->m[k - 1];
@@ -697,6 +718,156 @@ std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int c
   k.push_back(o->tie_tau);
   k.push_back(chunk);
   return k;
+}
+
+// ---------------------------------------------------------------------------
+// resident engine planning
+// ---------------------------------------------------------------------------
+constexpr size_t kLdsBudget = 160 * 1024;
+
+int conv_img_floats_h(const GemmGeom& g) { return g.src_n / (g.src_H * g.src_W) * g.LH * g.LW; }
+int round4(int x) { return (x + 3) & ~3; }
+
+// K chunks of an FC contraction inside the resident kernel (enough work items
+// for the block's 8 waves, at least 4 K steps per chunk).
+int resident_kc(const GemmGeom& g, int mma) {
+  const int KS = mma ? 32 : 16;
+  const int ntile = (g.N + 15) / 16;
+  const int ksteps = (g.K + KS - 1) / KS;
+  int kc = (32 + ntile - 1) / ntile;
+  kc = std::min(kc, std::max(1, ksteps / 4));
+  return std::max(1, kc);
+}
+
+struct ResidentShape {
+  int S = 0;
+  int xb = 0, xb_odd = 0, img = 0, gx = 0, wb = 0, part = 0;
+  size_t lds = 0;
+};
+
+// Staged weight rows and row stride of a conv contraction in the resident kernel.
+void conv_stage_dims(const Job& J, int B, int* n_eff, int* kp_max) {
+  const int tn = job_tn(J, B);
+  *n_eff = (J.geoms[0].N + 16 * tn - 1) / (16 * tn) * (16 * tn);
+  int kp = 0;
+  for (auto& g : J.geoms) kp = std::max(kp, g.Kp);
+  *kp_max = kp;
+}
+
+int conv_stage_floats(const Job& J, int B, int mma) {
+  int ne, kp;
+  conv_stage_dims(J, B, &ne, &kp);
+  const int ncls = (int)J.geoms.size();
+  return round4(ncls * ne * kp / (mma ? 2 : 1) + ncls * kp);
+}
+
+// Shape of the resident launch for batch size B, or S = 0 when it does not apply.
+ResidentShape resident_shape(const ld_net* net, int B, int mma) {
+  ResidentShape R;
+  const int n = net->n;
+  if (n - 1 > kMaxLayers) return R;
+  int xb_even = 0, xb_odd = 0, img = 0, gx = 0, wb = 0;
+  for (int k = 1; k <= n - 1; ++k) {
+    const Layer& L = net->L[k - 1];
+    if (k & 1)
+      xb_odd = std::max(xb_odd, L.n_out);
+    else
+      xb_even = std::max(xb_even, L.n_out);
+    gx = std::max(gx, std::max(L.n_in, L.n_out));
+    if (L.kind == LD_CONV2D) {
+      img = std::max(img, conv_img_floats_h(L.fwd.geoms[0]));
+      img = std::max(img, conv_img_floats_h(L.tr.geoms[0]));
+      wb = std::max(wb, conv_stage_floats(L.fwd, B, mma));
+      wb = std::max(wb, conv_stage_floats(L.tr, B, mma));
+    } else {
+      img = std::max(img, L.n_in);
+    }
+  }
+  R.xb_odd = round4(xb_even);
+  R.xb = round4(R.xb_odd + xb_odd);
+  R.img = round4(img);
+  R.gx = round4(gx);
+  R.wb = wb;
+  for (int S : {4, 2, 1}) {
+    if (S > 1 && (B + S - 1) / S < 256) continue;  // keep every CU busy first
+    int part = 0;
+    for (int k = 1; k <= n - 1; ++k) {
+      const Layer& L = net->L[k - 1];
+      if (L.kind != LD_LINEAR) continue;
+      for (const GemmGeom* g : {&L.fwd.geoms[0], &L.tr.geoms[0]}) {
+        const int kc = resident_kc(*g, mma);
+        if (kc > 1) part = std::max(part, kc * S * g->N);
+      }
+    }
+    const size_t floats = (size_t)S * (R.xb + R.img + R.gx) + (size_t)std::max(R.wb, round4(part)) + 4;
+    if (floats * 4 <= kLdsBudget) {
+      R.S = S;
+      R.part = part;
+      R.lds = floats * 4;
+      return R;
+    }
+  }
+  R.S = 0;
+  return R;
+}
+
+int run_resident(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, const ResidentShape& R,
+                 hipStream_t s) {
+  const int n = net->n;
+  const int mma = o->precision == LD_BF16 ? 1 : 0;
+  RPlan P;
+  std::memset(&P, 0, sizeof(P));
+  P.n = n;
+  P.B = bt->B;
+  P.S = R.S;
+  P.n0 = net->n0;
+  P.l0 = bt->l0;
+  P.u0 = bt->u0;
+  P.gconst = st->ws.gconst;
+  P.xb_stride = R.xb;
+  P.xb_odd = R.xb_odd;
+  P.img_stride = R.img;
+  P.gx_stride = R.gx;
+  P.wb_floats = R.wb;
+  P.part_floats = R.part;
+  P.t0 = st->t_host;
+  P.iters = o->iters;
+  P.total = o->total_iters;
+  P.lr0 = o->lr0;
+  P.lr_end = o->lr_end;
+  P.beta1 = o->beta1;
+  P.beta2 = o->beta2;
+  P.eps = o->eps;
+  P.tau = o->tie_tau;
+  P.t_dev = st->t_dev;
+  for (int k = 1; k <= n - 1; ++k) {
+    const Layer& L = net->L[k - 1];
+    RLayer& Q = P.L[k - 1];
+    Q.kind = L.kind == LD_CONV2D ? 1 : 0;
+    Q.n_in = L.n_in;
+    Q.n_out = L.n_out;
+    Q.out_hw = L.kind == LD_CONV2D ? L.out_h * L.out_w : 1;
+    Q.bias = L.bias;
+    Q.fwd = L.fwd_dev;
+    Q.tr = L.tr_dev;
+    Q.n_tr = (int)L.tr.geoms.size();
+    Q.tn_fwd = job_tn(L.fwd, bt->B);
+    Q.tn_tr = job_tn(L.tr, bt->B);
+    Q.kc_fwd = L.kind == LD_LINEAR ? resident_kc(L.fwd.geoms[0], mma) : 1;
+    Q.kc_tr = L.kind == LD_LINEAR ? resident_kc(L.tr.geoms[0], mma) : 1;
+    if (L.kind == LD_CONV2D) {
+      conv_stage_dims(L.fwd, bt->B, &Q.neff_fwd, &Q.kpm_fwd);
+      conv_stage_dims(L.tr, bt->B, &Q.neff_tr, &Q.kpm_tr);
+    }
+    Q.rho = st->rho[k - 1];
+    Q.m = st->m[k - 1];
+    Q.v = st->v[k - 1];
+    Q.lo = bt->l[k - 1];
+    Q.hi = bt->u[k - 1];
+  }
+  const int grid = (bt->B + R.S - 1) / R.S;
+  LD_HIP(launch_resident(P, grid, R.lds, mma, s));
+  return LD_OK;
 }
 
 }  // namespace
@@ -793,6 +964,19 @@ int ld_create_net(const ld_layer* layers, int n_layers, ld_net** out) {
     L.bias = (float*)pb;
     rc = s.kind == LD_LINEAR ? build_linear(net, L, s.W) : build_conv(net, L, s.W);
     if (rc) return cleanup(rc);
+    {
+      void* pg;
+      const size_t ng = 1 + L.tr.geoms.size();
+      rc = alloc_dev(net, &pg, ng * sizeof(GemmGeom));
+      if (rc) return cleanup(rc);
+      std::vector<GemmGeom> all;
+      all.push_back(L.fwd.geoms[0]);
+      for (auto& g : L.tr.geoms) all.push_back(g);
+      if (hipMemcpy(pg, all.data(), ng * sizeof(GemmGeom), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(LD_E_DEVICE, "geometry copy failed"));
+      L.fwd_dev = (const GemmGeom*)pg;
+      L.tr_dev = (const GemmGeom*)pg + 1;
+    }
     net->L.push_back(L);
   }
   net->n0 = net->L[0].n_in;
@@ -893,6 +1077,7 @@ int ld_state_set_rho(ld_state* st, const float* const* rho, hipStream_t s) {
     LD_HIP(hipMemsetAsync(st->v[k - 1], 0, bytes, s));
   }
   LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
+  st->t_host = 0;
   st->initialized = false;  // q(rho^0) is computed by the next ld_step (init = LD_INIT_GIVEN)
   return LD_OK;
 }
@@ -962,6 +1147,8 @@ static int check_step_args(const ld_net* net, const ld_batch* bt, const ld_state
   if (o->iters < 0 || o->total_iters < 1) return fail(LD_E_ARG, "iters must be >= 0 and total_iters >= 1");
   if (o->precision != LD_FP32 && o->precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
   if (o->init != LD_INIT_CROWN && o->init != LD_INIT_ZERO && o->init != LD_INIT_GIVEN) return fail(LD_E_ARG, "bad init");
+  if (o->engine != LD_ENGINE_AUTO && o->engine != LD_ENGINE_RESIDENT && o->engine != LD_ENGINE_LAYERWISE)
+    return fail(LD_E_ARG, "bad engine");
   if (!std::isfinite(o->lr0) || !std::isfinite(o->lr_end) || !(o->beta1 >= 0.f && o->beta1 < 1.f) ||
       !(o->beta2 >= 0.f && o->beta2 < 1.f) || !(o->eps > 0.f) || !(o->tie_tau >= 0.f) || !std::isfinite(o->tie_tau))
     return fail(LD_E_ARG, "bad Adam constants");
@@ -982,6 +1169,7 @@ static int ensure_initialised(const ld_net* net, const ld_batch* bt, ld_state* s
         LD_HIP(hipMemsetAsync(st->v[k - 1], 0, bytes, s));
       }
       LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
+      st->t_host = 0;
     }
     std::vector<const float*> r(st->rho.begin(), st->rho.end());
     LD_TRY(dual_eval_impl(net, bt, r.data(), st->ws, st->q0, nullptr, LD_FP32, o->tie_tau, s));
@@ -997,6 +1185,18 @@ int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* 
   LD_TRY(validate_values(net, bt, st->ws, s));
   LD_TRY(ensure_initialised(net, bt, st, o, s));
   if (o->iters == 0) return LD_OK;
+  const int mma_sel = o->precision == LD_BF16 ? 1 : 0;
+  if (o->engine != LD_ENGINE_LAYERWISE) {
+    const ResidentShape R = resident_shape(net, bt->B, mma_sel);
+    const bool use = R.S > 0 && o->engine == LD_ENGINE_RESIDENT;
+    if (o->engine == LD_ENGINE_RESIDENT && R.S == 0)
+      return fail(LD_E_UNSUPPORTED, "the resident engine does not fit this network in LDS");
+    if (use) {
+      LD_TRY(run_resident(net, bt, st, o, R, s));
+      st->t_host += o->iters;
+      return LD_OK;
+    }
+  }
   const int chunk = std::min(o->iters, 100);
   std::vector<double> key = graph_key(bt, o, net->n, chunk);
   if (!st->gexec || key != st->gkey) {
@@ -1023,6 +1223,7 @@ int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* 
   const int reps = o->iters / chunk;
   for (int r = 0; r < reps; ++r) LD_HIP(hipGraphLaunch(st->gexec, s));
   for (int i = reps * chunk; i < o->iters; ++i) LD_TRY(iteration(net, bt, st, o, s));
+  st->t_host += o->iters;
   return LD_OK;
 }
 
@@ -1030,6 +1231,7 @@ int ld_state_reset(ld_state* st, hipStream_t s) {
   g_err.clear();
   if (!st) return fail(LD_E_ARG, "state is NULL");
   LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
+  st->t_host = 0;
   st->initialized = false;
   return LD_OK;
 }
@@ -1048,6 +1250,7 @@ int ld_profile_iteration(const ld_net* net, const ld_batch* bt, ld_state* st, co
     g_probe = &probe;
     rc = iteration(net, bt, st, o, s);
     g_probe = nullptr;
+    st->t_host += 1;
     if (rc != LD_OK) break;
     if (hipStreamSynchronize(s) != hipSuccess) {
       rc = fail(LD_E_DEVICE, "stream synchronisation failed");

@@ -46,7 +46,8 @@ enum EpiKind : int {
   EPI_SUPERGRAD = 4,    // supergradient xB - (acc + b) stored
   EPI_CROWN = 5,        // CROWN dual: a_up [g]_+ + a_lo [g]_-
   EPI_RELU_FWD = 6,     // y = acc + b, feasibility against [l, u], x = relu(y)
-  EPI_BIAS_STORE = 7    // y = acc + b stored
+  EPI_BIAS_STORE = 7,   // y = acc + b stored
+  EPI_ADAM_LAST = 8     // as EPI_ADAM for the last hidden layer: xB from the constant g (gc)
 };
 
 struct EpiArgs {
@@ -70,6 +71,13 @@ struct EpiArgs {
   float* v;
   const float* adam;    // device scalars {lr_t, 1/bc1, 1/bc2, eps, beta1, beta2}
   int* flag;            // feasibility flags [B] (EPI_RELU_FWD)
+  const float* gc;      // constant coefficient -W_n^T c of the last hidden layer (EPI_ADAM_LAST)
+  // step bookkeeping done by one thread of the launch when t_dev != nullptr:
+  // t += 1 and the scalars of that Adam step are written to adam_w
+  int* t_dev;
+  float* adam_w;
+  double lr0, lr_end, beta1, beta2, eps;
+  int total;
 };
 
 // Launch-time tile configuration: each wave computes tm x tn MFMA tiles of 16x16,
@@ -85,6 +93,51 @@ struct SplitArgs {
   float* partial;
   int* counters;
 };
+
+// ---------------------------------------------------------------------------
+// Resident ascent (ld_resident.hip): one block owns S subdomains for a whole
+// call of ld_step; intermediates live in LDS, the state streams once per
+// iteration, and the layers are swept top-down inside each iteration.
+// ---------------------------------------------------------------------------
+constexpr int kMaxLayers = 15;
+
+struct RLayer {
+  int kind;             // 0 linear, 1 conv
+  int n_in, n_out;      // widths of the layer's input and output
+  int out_hw;           // output H*W (conv) or 1: bias index = neuron / out_hw
+  const float* bias;
+  const GemmGeom* fwd;  // device copies of the contraction geometries
+  const GemmGeom* tr;
+  int n_tr;
+  int tn_fwd, tn_tr;    // column tiles (x16) of the conv contractions
+  int kc_fwd, kc_tr;    // K chunks of the FC contractions (partials summed in order)
+  int neff_fwd, neff_tr;  // weight rows staged in LDS (conv): columns rounded to the tile
+  int kpm_fwd, kpm_tr;    // padded K row stride of the staged weights (max over classes)
+  // hidden layer k = this index + 1 (k <= n-1): state and bounds of the batch
+  float* rho;
+  float* m;
+  float* v;
+  const float* lo;
+  const float* hi;
+};
+
+struct RPlan {
+  int n, B, S, n0;
+  const float* l0;
+  const float* u0;
+  const float* gconst;  // [B, n_{n-1}]
+  // LDS regions (floats): per subdomain xB (even layers at 0, odd layers at
+  // xb_odd), x* image, contraction output; per block the staged conv weights,
+  // aliased with the FC chunk partials
+  int xb_stride, xb_odd, img_stride, gx_stride, wb_floats, part_floats;
+  int t0, iters, total;
+  float lr0, lr_end, beta1, beta2, eps, tau;
+  int* t_dev;           // receives t0 + iters at the end of the launch
+  RLayer L[kMaxLayers];
+};
+
+// The plan travels by value in the kernel arguments (no host-device race between calls).
+hipError_t launch_resident(const RPlan& plan, int grid, size_t lds_bytes, int mma_bf16, hipStream_t s);
 
 // kernels (ld_kernels.hip)
 // convolution contraction, one block per (subdomain, stride class)

@@ -11,6 +11,7 @@
 // (Algorithm 1), the CROWN dual assignment (Prop. 2) and the network forward
 // used for the upper bound (Sec. 5.1.3).
 #include "ld_internal.h"
+#include "ld_device.h"
 
 #include <type_traits>
 
@@ -22,62 +23,20 @@ struct GemmPack {
   GemmGeom g[kMaxClasses];
 };
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ bf16_t f2bf(float f) {
-  // round to nearest even (inputs are finite)
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (bf16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
-// ---------------------------------------------------------------------------
-// per-neuron inner minimisation (Sec. 3.2.2): minimise r*xB - g*x over the
-// ReLU hull with bounds [l, u]; ties go to the larger xB within a relative band.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void inner_min(T r, T g, T l, T u, T tau, T& xb, T& x, T& val) {
-  const T zero = T(0);
-  if (l >= zero) {                       // passing: x = xB, coefficient (r - g)
-    T cp = r - g;
-    xb = (cp <= tau * (fabs(r) + fabs(g))) ? u : l;
-    x = xb;
-    T a = cp * l, b = cp * u;
-    val = a < b ? a : b;
-  } else if (u <= zero) {                // blocking: x = 0, coefficient r
-    xb = (r <= zero) ? u : l;
-    x = zero;
-    T a = r * l, b = r * u;
-    val = a < b ? a : b;
-  } else {                               // ambiguous: vertices (l,0), (0,0), (u,u)
-    T Vl = r * l;
-    T Vu = (r - g) * u;
-    T m = Vl < Vu ? Vl : Vu;
-    m = m < zero ? m : zero;
-    T band = tau * (fabs(Vl) + fabs(r * u) + fabs(g * u));
-    if (Vu <= m + band) {
-      xb = u;
-      x = u;
-    } else if (zero <= m + band) {
-      xb = zero;
-      x = zero;
-    } else {
-      xb = l;
-      x = zero;
-    }
-    val = m;
-  }
-}
-
-// CROWN dual of one neuron from g = (W^T rho_next)[i] (eq:salman-assignment with
-// the slopes of eq:slopes-biases: chord upper slope, lower slope 1[u >= -l]).
-__device__ __forceinline__ float crown_dual(float g, float l, float u) {
-  if (l >= 0.f) return g;
-  if (u <= 0.f) return 0.f;
-  if (g > 0.f) return (u / (u - l)) * g;
-  return (u >= -l) ? g : 0.f;
+// One thread per launch advances the step counter and writes the scalars of
+// this iteration's Adam step: step size with linear decay (Sec. 7.2) and the
+// bias corrections 1/(1-beta^t).
+__device__ __forceinline__ void adam_tick(const EpiArgs& E) {
+  if (E.t_dev == nullptr || blockIdx.x != 0 || blockIdx.y != 0 || blockIdx.z != 0 || threadIdx.x != 0) return;
+  const int t = *E.t_dev + 1;
+  *E.t_dev = t;
+  const double lr = E.total > 1 ? E.lr0 + (E.lr_end - E.lr0) * (double)(t - 1) / (double)(E.total - 1) : E.lr0;
+  E.adam_w[0] = (float)lr;
+  E.adam_w[1] = (float)(1.0 / (1.0 - pow(E.beta1, (double)t)));
+  E.adam_w[2] = (float)(1.0 / (1.0 - pow(E.beta2, (double)t)));
+  E.adam_w[3] = (float)E.eps;
+  E.adam_w[4] = (float)E.beta1;
+  E.adam_w[5] = (float)E.beta2;
 }
 
 // ---------------------------------------------------------------------------
@@ -122,7 +81,7 @@ __device__ __forceinline__ void st4_xs(const EpiArgs& E, size_t i0, size_t st, i
 
 template <bool VEC>
 __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st, int nv, int b0, int bstep, int col,
-                                          const float (&acc)[4]) {
+                                          int cstep, const float (&acc)[4]) {
   switch (E.kind) {
     case EPI_STORE: {
       float o[4];
@@ -148,14 +107,16 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
       ld4<VEC>(E.lo, i0, st, nv, lo);
       ld4<VEC>(E.hi, i0, st, nv, hi);
       if (E.want_val) {
-        const double bias = (double)E.bias[col / E.bias_div];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           double xbd, xd, val;
           inner_min<double>(r[q], acc[q], lo[q], hi[q], (double)E.tau, xbd, xd, val);
           xb[q] = (float)xbd;
           x[q] = (float)xd;
-          if (VEC || q < nv) E.val[i0 + q * st] = val - (double)r[q] * bias;
+          if (VEC || q < nv) {
+            const double bias = (double)E.bias[(col + q * cstep) / E.bias_div];
+            E.val[i0 + q * st] = val - (double)r[q] * bias;
+          }
         }
       } else {
 #pragma unroll
@@ -167,17 +128,31 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
       st4_xs<VEC>(E, i0, st, nv, x);
       st4<VEC>(E.xb, i0, st, nv, xb);
     } break;
-    case EPI_ADAM: {
+    case EPI_ADAM:
+    case EPI_ADAM_LAST: {
       float xb[4], rho[4], m[4], v[4];
-      ld4<VEC>(E.xb_in, i0, st, nv, xb);
       ld4<VEC>(E.rho_w, i0, st, nv, rho);
       ld4<VEC>(E.m, i0, st, nv, m);
       ld4<VEC>(E.v, i0, st, nv, v);
+      if (E.kind == EPI_ADAM_LAST) {
+        // inner minimisation of the last hidden layer from its constant coefficient
+        float gcv[4], lo[4], hi[4];
+        ld4<VEC>(E.gc, i0, st, nv, gcv);
+        ld4<VEC>(E.lo, i0, st, nv, lo);
+        ld4<VEC>(E.hi, i0, st, nv, hi);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float x, val;
+          inner_min<float>(rho[q], gcv[q], lo[q], hi[q], E.tau, xb[q], x, val);
+        }
+      } else {
+        ld4<VEC>(E.xb_in, i0, st, nv, xb);
+      }
       const float lr = E.adam[0], ibc1 = E.adam[1], ibc2 = E.adam[2], eps = E.adam[3];
       const float b1 = E.adam[4], b2 = E.adam[5];
-      const float bias = E.bias[col];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        const float bias = E.bias[col + q * cstep];
         const float s = xb[q] - (acc[q] + bias);
         m[q] = b1 * m[q] + (1.f - b1) * s;
         v[q] = b2 * v[q] + (1.f - b2) * (s * s);
@@ -190,9 +165,8 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
     case EPI_SUPERGRAD: {
       float xb[4], o[4];
       ld4<VEC>(E.xb_in, i0, st, nv, xb);
-      const float bias = E.bias[col];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = xb[q] - (acc[q] + bias);
+      for (int q = 0; q < 4; ++q) o[q] = xb[q] - (acc[q] + E.bias[col + q * cstep]);
       st4<VEC>(E.out_f, i0, st, nv, o);
     } break;
     case EPI_CROWN: {
@@ -207,10 +181,9 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
       float lo[4], hi[4], o[4];
       ld4<VEC>(E.lo, i0, st, nv, lo);
       ld4<VEC>(E.hi, i0, st, nv, hi);
-      const float bias = E.bias[col];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float y = acc[q] + bias;
+        const float y = acc[q] + E.bias[col + q * cstep];
         if ((VEC || q < nv) && !(y >= lo[q] && y <= hi[q])) E.flag[b0 + q * bstep] = 0;
         o[q] = fmaxf(y, 0.f);
       }
@@ -218,50 +191,14 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
     } break;
     case EPI_BIAS_STORE: {
       float o[4];
-      const float bias = E.bias[col];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = acc[q] + bias;
+      for (int q = 0; q < 4; ++q) o[q] = acc[q] + E.bias[col + q * cstep];
       st4<VEC>(E.out_f, i0, st, nv, o);
     } break;
     default:
       break;
   }
 }
-
-// ---------------------------------------------------------------------------
-// MFMA fragments.  FP32 (v_mfma_f32_16x16x4f32): for a K step of 16, lane l
-// (r = l & 15, g = l >> 4) holds A[r][k0+4g+j] and B[k0+4g+j][r], j = 0..3, and
-// issues one MFMA per j; the 4 MFMAs sum k0..k0+15 once each (the k order inside
-// the step is permuted so both operands are contiguous).  BF16
-// (v_mfma_f32_16x16x32_bf16): lane holds A[r][k0+8g..+7], B[k0+8g..+7][r].
-// Output: lane holds C[4g+q][r], q = 0..3.
-// ---------------------------------------------------------------------------
-template <bool MMA_BF16>
-struct Mma;
-template <>
-struct Mma<false> {
-  static constexpr int KS = 16, VPL = 4;
-  typedef float4 BFrag;
-  __device__ static BFrag loadB(const GemmGeom& G, size_t off) { return *reinterpret_cast<const float4*>(G.Bf + off); }
-  __device__ static void mma(const float (&a)[4], const BFrag& b, f32x4& c) {
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b.x, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b.y, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b.z, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b.w, c, 0, 0, 0);
-  }
-};
-template <>
-struct Mma<true> {
-  static constexpr int KS = 32, VPL = 8;
-  typedef bf16x8 BFrag;
-  __device__ static BFrag loadB(const GemmGeom& G, size_t off) { return *reinterpret_cast<const bf16x8*>(G.Bh + off); }
-  __device__ static void mma(const float (&a)[8], const BFrag& b, f32x4& c) {
-    bf16x8 av;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) av[j] = (__bf16)a[j];
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, c, 0, 0, 0);
-  }
-};
 
 // ---------------------------------------------------------------------------
 // Convolution contraction of one subdomain per block, all stride classes.
@@ -273,8 +210,11 @@ struct Mma<true> {
 //  3. all threads stream the epilogue over the destination map in order,
 //     16 bytes per access.
 // ---------------------------------------------------------------------------
+constexpr int kConvWaves = 8;
+constexpr int kConvThreads = 64 * kConvWaves;
+
 template <bool MMA_BF16, bool SRC_BF16, int TN>
-__global__ __launch_bounds__(256) void conv_plane_kernel(GemmPack P, const void* __restrict__ src_v, EpiArgs E,
+__global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, const void* __restrict__ src_v, EpiArgs E,
                                                          int img_floats, int dst_hw4, int kp_max) {
   using M = Mma<MMA_BF16>;
   constexpr int KS = M::KS, VPL = M::VPL;
@@ -290,14 +230,15 @@ __global__ __launch_bounds__(256) void conv_plane_kernel(GemmPack P, const void*
   float* outp = lds + img_floats;        // [dst_n]
   int* kofs = (int*)(outp + G0.dst_n);   // [n classes][kp_max]
 
+  adam_tick(E);
   // 1. zero image, then copy the source map (coalesced) into its interior
-  for (int e = tid; e < img_floats; e += 256) img[e] = 0.f;
+  for (int e = tid; e < img_floats; e += kConvThreads) img[e] = 0.f;
   for (int c = 0; c < P.n; ++c)
-    for (int k = tid; k < P.g[c].Kp; k += 256) kofs[c * kp_max + k] = P.g[c].ktab_lds[k];
+    for (int k = tid; k < P.g[c].Kp; k += kConvThreads) kofs[c * kp_max + k] = P.g[c].ktab_lds[k];
   __syncthreads();
   if (SRC_BF16) {
     const bf16_t* src = (const bf16_t*)src_v + (size_t)b * G0.src_n;
-    for (int e = tid; e < G0.src_n; e += 256) {
+    for (int e = tid; e < G0.src_n; e += kConvThreads) {
       const int c = e / HW;
       const int rem = e - c * HW;
       const int iy = rem / G0.src_W;
@@ -306,7 +247,7 @@ __global__ __launch_bounds__(256) void conv_plane_kernel(GemmPack P, const void*
     }
   } else {
     const float* src = (const float*)src_v + (size_t)b * G0.src_n;
-    for (int e = tid; e < G0.src_n; e += 256) {
+    for (int e = tid; e < G0.src_n; e += kConvThreads) {
       const int c = e / HW;
       const int rem = e - c * HW;
       const int iy = rem / G0.src_W;
@@ -325,9 +266,9 @@ __global__ __launch_bounds__(256) void conv_plane_kernel(GemmPack P, const void*
     const int nct = (G.N + 16 * TN - 1) / (16 * TN);
     // distribute (tile, column chunk) pairs over the waves, continuing the rotation across classes
     const int total = ntiles * nct;
-    int first = (wave - tiles_before) % 4;
-    if (first < 0) first += 4;
-    for (int w = first; w < total; w += 4) {
+    int first = (wave - tiles_before) % kConvWaves;
+    if (first < 0) first += kConvWaves;
+    for (int w = first; w < total; w += kConvWaves) {
       const int tile = w / nct;
       const int nc = (w - tile * nct) * 16 * TN;
       const int p = min(tile * 16 + r, G.HWq - 1);
@@ -370,44 +311,48 @@ __global__ __launch_bounds__(256) void conv_plane_kernel(GemmPack P, const void*
   // 3. epilogue over the destination map in memory order
   const size_t base = (size_t)b * G0.dst_n;
   if (dst_hw4) {
-    for (int e = 4 * tid; e < G0.dst_n; e += 1024) {
+    for (int e = 4 * tid; e < G0.dst_n; e += 4 * kConvThreads) {
       const int col = e / G0.dst_HW;  // channel (four consecutive neurons share it)
       float v4[4] = {outp[e], outp[e + 1], outp[e + 2], outp[e + 3]};
-      epilogue4<true>(E, base + e, 1, 4, b, 0, col, v4);
+      epilogue4<true>(E, base + e, 1, 4, b, 0, col, 0, v4);
     }
   } else {
-    for (int e = tid; e < G0.dst_n; e += 256) {
+    for (int e = tid; e < G0.dst_n; e += kConvThreads) {
       const int col = e / G0.dst_HW;
       float v4[4] = {outp[e], 0.f, 0.f, 0.f};
-      epilogue4<false>(E, base + e, 1, 1, b, 0, col, v4);
+      epilogue4<false>(E, base + e, 1, 1, b, 0, col, 0, v4);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Fully-connected contraction (rows = subdomains, columns = neurons), with both
-// operands loaded register-direct.  Block = 4 waves stacked along rows; each
-// wave owns 16 rows x 16*TN columns.  With splits > 1 (long K) each block writes
-// a partial tile and fc_split_reduce adds the partials in split order and runs
-// the epilogue (deterministic, no cross-block synchronisation).
+// Fully-connected contraction, computed transposed: C[neuron][subdomain] =
+// sum_k W[neuron][k] X[subdomain][k], with both operands loaded register-direct
+// (packed weights as the row operand).  A wave owns 16*TN neurons x 16
+// subdomains; a block is 4 waves along subdomains.  A lane ends with four
+// consecutive neurons of one subdomain, so the epilogue moves 16 bytes per
+// access.  With splits > 1 (long K) every block writes a partial tile and
+// fc_split_reduce adds the partials in split order, then runs the epilogue
+// (deterministic, no cross-block synchronisation).
 // ---------------------------------------------------------------------------
 template <int TN, bool MMA_BF16, bool SRC_BF16>
 __global__ __launch_bounds__(256) void fc_kernel(GemmGeom G, const void* __restrict__ src_v, EpiArgs E, SplitArgs S) {
   using M = Mma<MMA_BF16>;
   constexpr int KS = M::KS, VPL = M::VPL;
+  adam_tick(E);
   const int split = blockIdx.z;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
-  const int m0 = blockIdx.x * 64 + wave * 16;
-  const int n0 = blockIdx.y * (16 * TN);
+  const int b0 = blockIdx.x * 64 + wave * 16;   // subdomains of this wave
+  const int n0 = blockIdx.y * (16 * TN);        // neurons of this block
   const int ksteps = (G.K + KS - 1) / KS;
   const int per = (ksteps + S.splits - 1) / S.splits;
   const int kbeg = split * per * KS;
   const int kend = min(G.K, (split + 1) * per * KS);
 
-  const int row = m0 + r;
-  const bool rvalid = row < G.M;
-  const size_t base = (size_t)(rvalid ? row : 0) * G.src_n;
+  const int sub = b0 + r;
+  const bool svalid = sub < G.M;
+  const size_t base = (size_t)(svalid ? sub : 0) * G.src_n;
   const float* srcf = (const float*)src_v;
   const bf16_t* srch = (const bf16_t*)src_v;
   const bool vec = (G.src_n % (SRC_BF16 ? 8 : 4)) == 0;
@@ -415,22 +360,23 @@ __global__ __launch_bounds__(256) void fc_kernel(GemmGeom G, const void* __restr
   f32x4 acc[TN];
 #pragma unroll
   for (int t = 0; t < TN; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
   for (int k0 = kbeg; k0 < kend; k0 += KS) {
     const int kl = k0 + VPL * g;
-    float a[VPL];
+    float x[VPL];
     if (vec && kl + VPL <= G.K) {
       if (SRC_BF16) {
         const bf16x8 h = *reinterpret_cast<const bf16x8*>(srch + base + kl);
 #pragma unroll
-        for (int j = 0; j < VPL; ++j) a[j] = (float)h[j];
+        for (int j = 0; j < VPL; ++j) x[j] = (float)h[j];
       } else {
 #pragma unroll
         for (int j = 0; j < VPL; j += 4) {
           const float4 v = *reinterpret_cast<const float4*>(srcf + base + kl + j);
-          a[j] = v.x;
-          a[j + 1] = v.y;
-          a[j + 2] = v.z;
-          a[j + 3] = v.w;
+          x[j] = v.x;
+          x[j + 1] = v.y;
+          x[j + 2] = v.z;
+          x[j + 3] = v.w;
         }
       }
     } else {
@@ -439,58 +385,64 @@ __global__ __launch_bounds__(256) void fc_kernel(GemmGeom G, const void* __restr
         const int k = kl + j;
         const size_t off = k < G.K ? base + k : base;
         const float v = SRC_BF16 ? bf2f(srch[off]) : srcf[off];
-        a[j] = k < G.K ? v : 0.f;
+        x[j] = k < G.K ? v : 0.f;
       }
     }
-    if (!rvalid) {
+    if (!svalid) {
 #pragma unroll
-      for (int j = 0; j < VPL; ++j) a[j] = 0.f;
+      for (int j = 0; j < VPL; ++j) x[j] = 0.f;
     }
 #pragma unroll
     for (int t = 0; t < TN; ++t) {
-      const typename M::BFrag bf = M::loadB(G, (size_t)(n0 + 16 * t + r) * G.Kp + kl);
-      M::mma(a, bf, acc[t]);
+      const typename M::BFrag w = M::loadB(G, (size_t)(n0 + 16 * t + r) * G.Kp + kl);
+      M::mma_wx(w, x, acc[t]);
     }
   }
-
+  // lane holds neurons n0 + 16t + 4g + q of subdomain b0 + r
   if (S.splits > 1) {
-    // partial tile layout [tile][split][64 rows][16*TN cols]
+    // partial tile layout [tile][split][16*TN neurons][64 subdomains]
     const size_t tile_id = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
     float* mine = S.partial + (tile_id * S.splits + split) * (64 * 16 * TN);
 #pragma unroll
     for (int t = 0; t < TN; ++t)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) mine[(wave * 16 + 4 * g + q) * (16 * TN) + 16 * t + r] = acc[t][q];
+      for (int q = 0; q < 4; ++q) mine[(16 * t + 4 * g + q) * 64 + wave * 16 + r] = acc[t][q];
     return;
   }
-  // epilogue: lane holds rows m0+4g+q (subdomains) of column n0+16t+r
-  const int mrow = m0 + 4 * g;
-  const int nv = min(4, G.M - mrow);
-  if (nv <= 0) return;
+  if (!svalid) return;
+  const bool vec_out = (G.dst_n & 3) == 0;
 #pragma unroll
   for (int t = 0; t < TN; ++t) {
-    const int col = n0 + 16 * t + r;
-    if (col >= G.N) continue;
+    const int j = n0 + 16 * t + 4 * g;
+    const int nv = min(4, G.N - j);
+    if (nv <= 0) continue;
     float v4[4] = {acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
-    epilogue4<false>(E, (size_t)mrow * G.dst_n + col, (size_t)G.dst_n, nv, mrow, 1, col, v4);
+    const size_t i0 = (size_t)sub * G.dst_n + j;
+    if (vec_out && nv == 4)
+      epilogue4<true>(E, i0, 1, 4, sub, 0, j, 1, v4);
+    else
+      epilogue4<false>(E, i0, 1, nv, sub, 0, j, 1, v4);
   }
 }
 
 template <int TN>
 __global__ __launch_bounds__(256) void fc_split_reduce(GemmGeom G, EpiArgs E, SplitArgs S, int gx) {
-  // one thread per output element; columns fastest (coalesced epilogue)
+  // one thread per output element, consecutive threads on consecutive subdomains
+  // of one neuron (the partial tiles store subdomains contiguously)
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (size_t)G.M * G.N) return;
-  const int m = (int)(e / G.N);
-  const int col = (int)(e - (size_t)m * G.N);
+  const int mp = gx * 64;
+  if (e >= (size_t)mp * G.N) return;
+  const int j = (int)(e / mp);
+  const int sub = (int)(e - (size_t)j * mp);
+  if (sub >= G.M) return;
   const int cols = 16 * TN;
-  const int bx = m >> 6, by = col / cols;
+  const int bx = sub >> 6, by = j / cols;
   const size_t tile_id = (size_t)by * gx + bx;
-  const float* pt = S.partial + tile_id * S.splits * (64 * cols) + (m & 63) * cols + (col - by * cols);
+  const float* pt = S.partial + tile_id * S.splits * (64 * cols) + (size_t)(j - by * cols) * 64 + (sub & 63);
   float v = 0.f;
   for (int sp = 0; sp < S.splits; ++sp) v += pt[(size_t)sp * (64 * cols)];
   float v4[4] = {v, 0.f, 0.f, 0.f};
-  epilogue4<false>(E, (size_t)m * G.dst_n + col, 1, 1, m, 0, col, v4);
+  epilogue4<false>(E, (size_t)sub * G.dst_n + j, 1, 1, sub, 0, j, 1, v4);
 }
 
 // ---------------------------------------------------------------------------
@@ -519,7 +471,7 @@ static hipError_t launch_conv_tn(const GemmPack& P, int B, const void* src, int 
   const int kpm = max_kp(P.g, P.n);
   const int img = conv_img_floats(G);
   const int hw4 = (G.dst_HW % 4) == 0;
-  dim3 grid(B), block(256);
+  dim3 grid(B), block(kConvThreads);
   if (lds > 64 * 1024) {
     (void)hipFuncSetAttribute((const void*)conv_plane_kernel<true, true, TN>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -556,7 +508,7 @@ hipError_t launch_conv(const GemmGeom* geoms, int n, int B, const void* src, int
 template <int TN>
 static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e,
                                const SplitArgs& sp, hipStream_t s) {
-  const int gx = (G.M + 63) / 64, gy = (G.N + 16 * TN - 1) / (16 * TN);
+  const int gx = (G.M + 63) / 64, gy = (G.N + 16 * TN - 1) / (16 * TN);  // subdomain blocks, neuron blocks
   dim3 grid(gx, gy, sp.splits), block(256);
   if (mma_bf16) {
     if (src_bf16)
@@ -569,8 +521,10 @@ static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16,
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess || sp.splits <= 1) return err;
-  const size_t outs = (size_t)G.M * G.N;
-  hipLaunchKernelGGL((fc_split_reduce<TN>), dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s, G, e, sp, gx);
+  EpiArgs e2 = e;
+  e2.t_dev = nullptr;  // the step was already counted by the partial launch
+  const size_t outs = (size_t)gx * 64 * G.N;
+  hipLaunchKernelGGL((fc_split_reduce<TN>), dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s, G, e2, sp, gx);
   return hipGetLastError();
 }
 

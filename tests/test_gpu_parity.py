@@ -131,12 +131,16 @@ def _oracle_run(inst, idx, T, lr0=1e-2, lr_end=1e-4):
 FP32_FINAL_REL = 3e-3
 
 
+ENGINES = ["resident", "layerwise"]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("name,T", [("fc_tiny", 500), ("tiny_conv", 200), ("tiny_conv2", 200), ("base", 100)])
-def test_ascent_final_bound_parity_fp32(name, T):
-    _case(f"ascent fp32 {name} T={T}")
+def test_ascent_final_bound_parity_fp32(name, T, engine):
+    _case(f"ascent fp32 {name} T={T} engine={engine}")
     P, inst, net, batch = _setup(name)
     st = P.State(net, inst.B)
-    P.step(net, batch, st, iters=T, total_iters=T, precision="fp32")
+    P.step(net, batch, st, iters=T, total_iters=T, precision="fp32", engine=engine)
     fb = P.final_bound(net, batch, st)
     torch.cuda.synchronize()
     assert st.step_count() == T
@@ -153,17 +157,18 @@ def test_ascent_final_bound_parity_fp32(name, T):
     assert bool((fb["bound"].cpu() >= fb["q_final"].cpu() - 1e-12).all())
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("name", ["fc_tiny", "tiny_conv", "tiny_conv2", "base"])
-def test_first_steps_follow_the_oracle(name):
+def test_first_steps_follow_the_oracle(name, engine):
     """The first Adam steps from the CROWN point track the oracle elementwise: ties at
     the CROWN kinks are resolved by the same rule on both sides."""
-    _case(f"first steps {name}")
+    _case(f"first steps {name} engine={engine}")
     P, inst, net, batch = _setup(name)
     onet = O.net_from_specs(inst.layers)
     ob = O.batch_from_instance(inst)
     for t in (1, 3):
         st = P.State(net, inst.B)
-        P.step(net, batch, st, iters=t, total_iters=50)
+        P.step(net, batch, st, iters=t, total_iters=50, engine=engine)
         rg = st.get_rho()
         ost = O.ascent(onet, ob, O.AdamOpts(T=50), iters=t)
         tot = bad = 0
@@ -176,28 +181,30 @@ def test_first_steps_follow_the_oracle(name):
         assert bad <= 0.02 * tot
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("name", ["tiny_conv", "base"])
-def test_chunked_steps_equal_one_call(name):
-    _case(f"chunked ascent {name}")
+def test_chunked_steps_equal_one_call(name, engine):
+    _case(f"chunked ascent {name} engine={engine}")
     P, inst, net, batch = _setup(name)
     a = P.State(net, inst.B)
-    P.step(net, batch, a, iters=130, total_iters=130)
+    P.step(net, batch, a, iters=130, total_iters=130, engine=engine)
     b = P.State(net, inst.B)
-    P.step(net, batch, b, iters=50, total_iters=130)
-    P.step(net, batch, b, iters=80, total_iters=130)
+    P.step(net, batch, b, iters=50, total_iters=130, engine=engine)
+    P.step(net, batch, b, iters=80, total_iters=130, engine=engine)
     ra, rb = a.get_rho(), b.get_rho()
     for x, y in zip(ra, rb):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("name", ["tiny_conv", "base"])
-def test_bf16_ascent_is_sound_and_close(name):
-    _case(f"bf16 ascent {name}")
+def test_bf16_ascent_is_sound_and_close(name, engine):
+    _case(f"bf16 ascent {name} engine={engine}")
     P, inst, net, batch = _setup(name)
     res = {}
     for prec in ("fp32", "bf16"):
         st = P.State(net, inst.B)
-        P.step(net, batch, st, iters=200, total_iters=200, precision=prec)
+        P.step(net, batch, st, iters=200, total_iters=200, precision=prec, engine=engine)
         res[prec] = P.final_bound(net, batch, st)
     torch.cuda.synchronize()
     # the returned bound is re-evaluated with FP32 operands: weak duality holds regardless
@@ -236,3 +243,22 @@ def test_error_codes_on_bad_input():
     with pytest.raises(P.LDError) as e:
         P.step(net, other, st, iters=1)
     assert e.value.code == -7
+
+
+@pytest.mark.parametrize("name", ["tiny_conv2", "base"])
+def test_engines_agree_over_first_steps(name):
+    """Both engines perform the same iteration (summation order aside)."""
+    _case(f"engines agree {name}")
+    P, inst, net, batch = _setup(name)
+    out = {}
+    for eng in ENGINES:
+        st = P.State(net, inst.B)
+        P.step(net, batch, st, iters=3, total_iters=50, engine=eng)
+        out[eng] = st.get_rho()
+    tot = bad = 0
+    for a, b in zip(out["resident"], out["layerwise"]):
+        diff = (a - b).abs()
+        bad += int((diff > 1e-4 * (b.abs() + 1e-2)).sum())
+        tot += diff.numel()
+    print(f"  duals differing beyond 1e-4 relative: {bad} of {tot}")
+    assert bad <= 0.02 * tot
