@@ -43,6 +43,7 @@ def parse():
                     help="for rocprofv3: one 64 MiB device copy (counter calibration), then --reps ascent "
                          "iterations launched without the graph; prints the per-launch averages")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--engine", choices=["auto", "layerwise", "resident"], default="auto")
     return ap.parse_args()
 
 
@@ -81,11 +82,11 @@ def layer_slot_cost(inst, kind, B, prec):
     return B * nb + wbytes(L), B * 2 * macs(L)
 
 
-def run_form(P, net, batch, st, iters, prec, steps, warmup):
+def run_form(P, net, batch, st, iters, prec, steps, warmup, engine="auto"):
     import torch
     for _ in range(warmup):
         st.reset()
-        P.step(net, batch, st, iters=iters, total_iters=iters, precision=prec)
+        P.step(net, batch, st, iters=iters, total_iters=iters, precision=prec, engine=engine)
         P.final_bound(net, batch, st)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
@@ -96,7 +97,7 @@ def run_form(P, net, batch, st, iters, prec, steps, warmup):
     fb = None
     for _ in range(steps):
         st.reset()
-        P.step(net, batch, st, iters=iters, total_iters=iters, precision=prec)
+        P.step(net, batch, st, iters=iters, total_iters=iters, precision=prec, engine=engine)
         fb = P.final_bound(net, batch, st)
     e1.record(s)
     torch.cuda.synchronize()
@@ -151,7 +152,7 @@ def main():
         return
 
     st = P.State(net, B)
-    res32 = run_form(P, net, batch, st, T, "fp32", a.steps, a.warmup)
+    res32 = run_form(P, net, batch, st, T, "fp32", a.steps, a.warmup, a.engine)
     b32 = res32["fb"]["bound"].clone()
 
     # BF16 form: iterations needed to reach the FP32 form's bound (mean gap <= 1e-3)
@@ -161,14 +162,14 @@ def main():
     if not a.quick and a.bf16_iters is None:
         for t in (T, int(1.5 * T), 2 * T, 3 * T):
             st16.reset()
-            P.step(net, batch, st16, iters=t, total_iters=t, precision="bf16")
+            P.step(net, batch, st16, iters=t, total_iters=t, precision="bf16", engine=a.engine)
             bb = P.final_bound(net, batch, st16)["bound"]
             gap = (b32 - bb).mean().item()
             tries.append((t, gap))
             T16 = t
             if gap <= 1e-3:
                 break
-    res16 = run_form(P, net, batch, st16, T16, "bf16", a.steps, a.warmup)
+    res16 = run_form(P, net, batch, st16, T16, "bf16", a.steps, a.warmup, a.engine)
     b16 = res16["fb"]["bound"]
     d = (b16 - b32)
     equal = (b32 - b16).mean().item() <= 1e-3

@@ -4,5 +4,5 @@ Python binding of the C ABI in include/ld.h: ``Net``, ``Batch``, ``State``,
 ``init_duals``, ``dual_eval``, ``step`` and ``final_bound`` call the HIP
 library directly; ``LDDual`` wraps ``dual_eval`` as a torch.autograd.Function.
 """
-from .binding import (Batch, LDError, Net, State, TAU_DEFAULT, dual_eval, final_bound, init_duals,  # noqa: F401
-                      load_library, profile_iteration, set_validation, step)
+from .binding import (Batch, LDDual, LDError, Net, State, TAU_DEFAULT, dual_eval, final_bound,  # noqa: F401
+                      init_duals, ld_dual, load_library, profile_iteration, set_validation, step)

@@ -292,3 +292,40 @@ def final_bound(net: Net, batch: Batch, state: State, tau: float = TAU_DEFAULT, 
                                                                                "feasible")),
                                   ctypes.c_float(tau), _stream(stream)))
     return d
+
+
+class LDDual(torch.autograd.Function):
+    """q(rho) as a differentiable function of the duals (Section 5.1, eq:nonprox_problem).
+
+    ``LDDual.apply(net, batch, precision, tau, *rho) -> q`` ([B], float64).  The
+    dual is concave and piecewise linear; its supergradient at rho is
+    s_k = xB*_k - (W_k x*_{k-1} + b_k) (Algorithm 1), which backward returns,
+    scaled by the incoming gradient of each subdomain's q.  Forward keeps only
+    the duals: backward recomputes every layer's inner minimisers and forward
+    products in one more library call instead of storing them, so the memory
+    held between forward and backward is the size of rho itself.  Where several
+    minimisers exist (a kink) the returned element is the one the tie rule
+    selects, a valid supergradient.
+    """
+
+    @staticmethod
+    def forward(ctx, net: Net, batch: Batch, precision: str, tau: float, *rho):
+        q, _ = dual_eval(net, batch, list(rho), supergrad=False, precision=precision, tau=tau)
+        ctx.net, ctx.batch, ctx.precision, ctx.tau = net, batch, precision, tau
+        ctx.save_for_backward(*rho)
+        return q
+
+    @staticmethod
+    def backward(ctx, grad_q):
+        rho = ctx.saved_tensors
+        _, s = dual_eval(ctx.net, ctx.batch, list(rho), supergrad=True, precision=ctx.precision, tau=ctx.tau)
+        w = grad_q.to(torch.float32).unsqueeze(1)
+        grads = [(w * sk).to(r.dtype) for sk, r in zip(s, rho)]
+        return (None, None, None, None, *grads)
+
+
+def ld_dual(net: Net, batch: Batch, rho: Sequence[torch.Tensor], precision="fp32",
+            tau: float = TAU_DEFAULT) -> torch.Tensor:
+    """Differentiable q(rho): ``ld_dual(net, batch, rho).sum().backward()`` fills
+    every rho_k.grad with the supergradient s_k."""
+    return LDDual.apply(net, batch, precision, tau, *rho)

@@ -85,11 +85,11 @@ struct Workspace {
   double* qtmp = nullptr;     // [B]
   int* flag = nullptr;        // [B]
   int* bad = nullptr;         // [1]
-  float* partial = nullptr;   // split-K partial tiles
+  float* partial = nullptr;   // split-K partial tiles, kPartialLayer floats per layer
   int* counters = nullptr;    // split-K arrival counters (kept at zero between launches)
 };
 
-constexpr size_t kPartialCap = (size_t)8 << 20;   // floats (32 MiB)
+constexpr size_t kPartialLayer = (size_t)2 << 20;  // split-K partial floats per layer (8 MiB)
 constexpr size_t kCounterCap = (size_t)1 << 16;
 
 }  // namespace
@@ -121,6 +121,11 @@ struct ld_state {
   std::vector<double> gkey;
   int gchunk = 0;
   int t_host = 0;       // Adam steps enqueued so far (mirrors *t_dev)
+  // the layer jobs of one phase are independent: they run on the caller's stream
+  // and two more, forked and joined around each phase
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -365,7 +370,7 @@ int ws_alloc(const ld_net* net, Workspace& ws, int B) {
   size_t iq = add((size_t)B * 8);
   size_t ifl = add((size_t)B * 4);
   size_t ibad = add(4);
-  size_t ipart = add(kPartialCap * 4);
+  size_t ipart = add(kPartialLayer * 4 * n);
   size_t icnt = add(kCounterCap * 4);
   size_t total = 0;
   std::vector<size_t> off;
@@ -426,7 +431,7 @@ int fc_splits(const Job& J, int B, int tn, int want) {
     if (tiles < 1024 && g.K >= 256) want = (int)std::min<long>(std::min<long>((1024 + tiles - 1) / tiles, g.K / 128), 32);
   }
   int sp = std::max(1, want);
-  while (sp > 1 && (size_t)tiles * sp * 64 * 16 * tn > kPartialCap) --sp;
+  while (sp > 1 && (size_t)tiles * sp * 64 * 16 * tn > kPartialLayer) --sp;
   return sp;
 }
 
@@ -447,8 +452,10 @@ Tile pick_tile(const ld_net* net, int layer, int dir, int B, int mma) {
   return heuristic_tile(dir == 0 ? L.fwd : L.tr, B);
 }
 
+// slot: layer index 0..n-1; jobs of different layers may run concurrently, so
+// each layer has its own split-K scratch.
 hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, const EpiArgs& e, Tile t,
-                   const Workspace& ws, hipStream_t s) {
+                   const Workspace& ws, int slot, hipStream_t s) {
   GemmGeom g[9];
   const int nc = (int)J.geoms.size();
   for (int i = 0; i < nc; ++i) {
@@ -456,7 +463,7 @@ hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, 
     g[i].M = B * g[i].HWq;
   }
   if (job_is_conv(J)) return launch_conv(g, nc, B, src, src_bf16, mma, e, t.tn, s);
-  SplitArgs sp{fc_splits(J, B, t.tn, t.splits), ws.partial, ws.counters};
+  SplitArgs sp{fc_splits(J, B, t.tn, t.splits), ws.partial + (size_t)slot * kPartialLayer, ws.counters};
   return launch_fc(g[0], src, src_bf16, mma, e, t.tn, sp, s);
 }
 
@@ -542,9 +549,34 @@ int prepare_objective(const ld_net* net, const ld_batch* bt, Workspace& ws, int 
   e.kind = EPI_STORE;
   e.scale = -1.f;
   e.out_f = ws.gconst;
-  LD_HIP(run_job(Ln.tr, bt->B, bt->c, 0, mma, e, pick_tile(net, n - 1, 1, bt->B, mma), ws, s));
+  LD_HIP(run_job(Ln.tr, bt->B, bt->c, 0, mma, e, pick_tile(net, n - 1, 1, bt->B, mma), ws, n - 1, s));
   LD_HIP(launch_cdot(bt->B, Ln.n_out, bt->c, nullptr, Ln.bias, ws.cb, s));
   return LD_OK;
+}
+
+// Fork/join of the independent layer jobs of a phase (nothing is forked while a
+// per-launch profile is being taken).
+constexpr int kSide = 2;
+bool forking(const ld_state* st) { return st != nullptr && st->side[0] != nullptr && g_probe == nullptr; }
+hipError_t fork_begin(const ld_state* st, hipStream_t s) {
+  if (!forking(st)) return hipSuccess;
+  hipError_t e = hipEventRecord(st->ev_fork, s);
+  for (int i = 0; i < kSide && e == hipSuccess; ++i) e = hipStreamWaitEvent(st->side[i], st->ev_fork, 0);
+  return e;
+}
+hipStream_t fork_stream(const ld_state* st, hipStream_t s, int j) {
+  if (!forking(st)) return s;
+  const int r = j % (kSide + 1);
+  return r == 0 ? s : st->side[r - 1];
+}
+hipError_t fork_end(const ld_state* st, hipStream_t s) {
+  if (!forking(st)) return hipSuccess;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < kSide && e == hipSuccess; ++i) {
+    e = hipEventRecord(st->ev_join[i], st->side[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, st->ev_join[i], 0);
+  }
+  return e;
 }
 
 int bias_div(const ld_net* net, int k) {
@@ -557,8 +589,9 @@ int bias_div(const ld_net* net, int k) {
 // In the ascent (o != nullptr) the first launch also advances the step counter,
 // and the last hidden layer's minimisation is left to its Adam epilogue.
 int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Workspace& ws, int mma, float tau,
-            int want_val, int* t_dev, float* adam, const ld_opts* o, hipStream_t s) {
+            int want_val, int* t_dev, float* adam, const ld_opts* o, hipStream_t s, const ld_state* fk = nullptr) {
   const int n = net->n, B = bt->B;
+  LD_HIP(fork_begin(fk, s));
   for (int k = 1; k <= n - 1; ++k) {
     const Layer& L = net->L[k - 1];
     EpiArgs e = epi0();
@@ -591,10 +624,12 @@ int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Work
       // a linear layer fed by a flattened conv map has one column per neuron of that map
       e.bias_div = L.kind == LD_LINEAR ? bias_div(net, k - 1) : 1;
     }
-    LD_HIP(probe_begin(100 + k, s));
-    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, s));
-    LD_HIP(probe_end(s));
+    const hipStream_t sk = fork_stream(fk, s, k - 1);
+    LD_HIP(probe_begin(100 + k, sk));
+    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, sk));
+    LD_HIP(probe_end(sk));
   }
+  LD_HIP(fork_end(fk, s));
   if (o != nullptr) return LD_OK;
   // last hidden layer: constant coefficient -W_n^T c
   const int k = n - 1;
@@ -629,7 +664,7 @@ int dual_eval_impl(const ld_net* net, const ld_batch* bt, const float* const* rh
       e.xb_in = ws.xb[k];
       e.bias = L.bias;
       e.out_f = supergrad[k - 1];
-      LD_HIP(run_job(L.fwd, B, ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), ws, s));
+      LD_HIP(run_job(L.fwd, B, ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), ws, k - 1, s));
     }
   }
   return LD_OK;
@@ -653,7 +688,7 @@ int init_impl(const ld_net* net, const ld_batch* bt, int init, int mma, float* c
     e.lo = bt->l[k - 2];
     e.hi = bt->u[k - 2];
     e.out_f = rho[k - 2];
-    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, s));
+    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, s));
   }
   return LD_OK;
 }
@@ -663,7 +698,8 @@ int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts
   const int n = net->n, B = bt->B;
   const int mma = o->precision == LD_BF16 ? 1 : 0;
   std::vector<const float*> rho(st->rho.begin(), st->rho.end());
-  LD_TRY(phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, st->t_dev, st->adam, o, s));
+  LD_TRY(phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, st->t_dev, st->adam, o, s, st));
+  LD_HIP(fork_begin(st, s));
   for (int k = 1; k <= n - 1; ++k) {
     const Layer& L = net->L[k - 1];
     EpiArgs e = epi0();
@@ -681,10 +717,12 @@ int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts
     e.m = st->m[k - 1];
     e.v = st->v[k - 1];
     e.adam = st->adam;
-    LD_HIP(probe_begin(300 + k, s));
-    LD_HIP(run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), st->ws, s));
-    LD_HIP(probe_end(s));
+    const hipStream_t sk = fork_stream(st, s, k - 1);
+    LD_HIP(probe_begin(300 + k, sk));
+    LD_HIP(run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), st->ws, k - 1, sk));
+    LD_HIP(probe_end(sk));
   }
+  LD_HIP(fork_end(st, s));
   return LD_OK;
 }
 
@@ -1048,7 +1086,12 @@ int ld_state_create(const ld_net* net, int B, ld_state** out) {
     ld_state_destroy(st);
     return rc;
   }
-  if (hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) != hipSuccess) {
+  bool ok = hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < 2 && ok; ++i)
+    ok = hipStreamCreateWithFlags(&st->side[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&st->ev_join[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
     ld_state_destroy(st);
     return fail(LD_E_DEVICE, "stream creation failed");
   }
@@ -1060,6 +1103,11 @@ void ld_state_destroy(ld_state* st) {
   if (!st) return;
   destroy_graph(st);
   if (st->cap) (void)hipStreamDestroy(st->cap);
+  for (int i = 0; i < 2; ++i) {
+    if (st->side[i]) (void)hipStreamDestroy(st->side[i]);
+    if (st->ev_join[i]) (void)hipEventDestroy(st->ev_join[i]);
+  }
+  if (st->ev_fork) (void)hipEventDestroy(st->ev_fork);
   if (st->ws.base) (void)hipFree(st->ws.base);
   if (st->base) (void)hipFree(st->base);
   delete st;
@@ -1311,7 +1359,7 @@ int ld_final_bound(const ld_net* net, const ld_batch* bt, const ld_state* cst, d
       } else {
         e.kind = EPI_BIAS_STORE;
       }
-      LD_HIP(run_job(L.fwd, B, x, 0, 0, e, pick_tile(net, k - 1, 0, B, 0), ws, s));
+      LD_HIP(run_job(L.fwd, B, x, 0, 0, e, pick_tile(net, k - 1, 0, B, 0), ws, k - 1, s));
       x = bufs[k & 1];
     }
     if (primal) LD_HIP(launch_cdot(B, net->L[n - 1].n_out, bt->c, x, nullptr, primal, s));

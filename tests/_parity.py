@@ -22,10 +22,11 @@ def abs_layer(L):
     return O.OLayer(L.kind, L.W.abs(), L.b.abs(), L.in_shape, L.out_shape, L.stride, L.pad)
 
 
-def unstable_decisions(net, batch, rho, ev, tau=O.TAU_DEFAULT):
+def unstable_decisions(net, batch, rho, ev, tau=O.TAU_DEFAULT, tie_rel=TIE_REL):
     """Per-layer boolean masks (layer 0 = P_0, then hidden layers 1..n-1): True where
-    an inner-minimisation decision of the oracle sits within TIE_REL (relative to
-    the FP32 error scale of the contraction feeding it) of flipping."""
+    an inner-minimisation decision of the oracle sits within tie_rel (relative to
+    the error scale of the contraction feeding it) of flipping."""
+    TIE_REL = tie_rel  # noqa: N806
     n = len(net)
     duals = list(rho) + [-batch.c]
     absnet = [abs_layer(L) for L in net]
@@ -77,4 +78,25 @@ def s_scale(net, ev):
     for k in range(1, n):
         L = abs_layer(net[k - 1])
         out.append(L.forward(prev[k - 1].abs()) + ev["xB"][k - 1].abs())
+    return out
+
+
+def supergrad_bound(net, batch, masks, scale, rel):
+    """Per-entry bound on |s_gpu - s_orc| when the GPU may take a different vertex at
+    every decision flagged in ``masks`` (from unstable_decisions):
+      rel * scale                     contraction rounding (decisions agree)
+    + |W_k| (m_{k-1} * (|l|+|u|))     a flipped x*_{k-1}[j] moves xA_k by |W_k[:, j]| * |dx_j|
+    + m_k * (u - l)                   a flipped xB*_k[i] moves by at most u - l
+    with dx_j <= u0 - l0 for the input layer and <= |l| + |u| for a hidden neuron."""
+    out = []
+    n = len(net)
+    for k in range(1, n):
+        if k == 1:
+            dx = masks[0].double() * (batch.u0 - batch.l0)
+        else:
+            dx = masks[k - 1].double() * (batch.l[k - 2].abs() + batch.u[k - 2].abs())
+        L = abs_layer(net[k - 1])
+        spread = L.forward(dx) - L.bias_full()
+        own = masks[k].double() * (batch.u[k - 1] - batch.l[k - 1])
+        out.append(rel * scale[k - 1] + spread + own)
     return out
