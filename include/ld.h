@@ -198,9 +198,12 @@ int ld_dual_eval(const ld_net* net, const ld_batch* batch, const float* const* r
  *             (LD_E_UNSUPPORTED if the layer maps do not fit);
  *             LD_ENGINE_LAYERWISE: one batched launch per contraction and
  *             iteration, replayed from a captured HIP graph;
- *             LD_ENGINE_AUTO: the layer-wise engine (measured faster on the
- *             shapes tested so far).
- *             Both compute the same iteration. */
+ *             LD_ENGINE_AUTO: the engine and the launch configuration of every
+ *             contraction picked by the autotuner (ld_autotune) for this
+ *             net, batch size and precision; the first AUTO call for a new
+ *             (B, precision) runs the tuner (synchronous, a few hundred
+ *             launches on a scratch state).
+ *             Both engines compute the same iteration. */
 typedef struct ld_opts {
   int iters;
   int total_iters;
@@ -214,9 +217,49 @@ typedef struct ld_opts {
 
 /* Enqueue `iters` Adam supergradient steps for every subdomain (engine per
  * ld_opts).  The layer-wise engine captures its loop once per (state, batch
- * pointers, options) into a HIP graph and replays it. */
+ * pointers, options, tuned configuration) into a HIP graph and replays it. */
 int ld_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opts* opts,
             hipStream_t stream);
+
+/* Autotuner (the batched launches of Sec. 5.2 sized for this device).  On a
+ * scratch state of `batch` (CROWN duals, one iteration done), time every
+ * candidate configuration of every contraction of the ascent iteration with
+ * its real epilogue: 16-column tiles per wave (1, 2, 4 as the width allows),
+ * for transposed strided convs the dense GEMM + col2im form against the
+ * stride-class gather form, for fully-connected products each split of K into
+ * pieces of at least 64.  The fastest configuration of each contraction is
+ * kept for (net, batch->B, opts->precision); then `opts` is used to time a
+ * 20-step ascent with each engine and the faster one becomes the choice of
+ * LD_ENGINE_AUTO.  Replaces earlier choices for the same (B, precision).
+ * Synchronises `stream`; allocates and frees its scratch state.  Only the
+ * precision, tie_tau, Adam constants and total_iters of `opts` are used. */
+int ld_autotune(const ld_net* net, const ld_batch* batch, const ld_opts* opts, hipStream_t stream);
+
+/* The tuned configuration of the contraction of hidden layer k (1..n-1) in
+ * direction dir (0: forward W_k x, 1: transposed W_k^T rho_k) for (B,
+ * precision): column tiles per wave, K splits, form (0: GEMM + col2im, 1:
+ * stride-class gather; convs only) and its measured time in microseconds
+ * (host outputs).  LD_E_STATE if nothing was tuned for (B, precision). */
+int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, int* tn, int* splits, int* form,
+                    double* us);
+
+/* The candidate configurations the autotuner times for the contraction of
+ * hidden layer k in direction dir at batch size B: up to max_count entries
+ * written to tn, splits, form (host arrays); *count receives the number of
+ * candidates. */
+int ld_tile_candidates(const ld_net* net, int B, int k, int dir, int* tn, int* splits, int* form, int max_count,
+                       int* count);
+
+/* Pin the configuration of one contraction for (B, precision), e.g. to restore
+ * a stored tuning; it must be one of ld_tile_candidates (else LD_E_ARG).
+ * Not thread-safe against concurrent calls on the same net. */
+int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, int tn, int splits, int form);
+
+/* The engine chosen by the autotuner for (B, precision) and the measured time
+ * per iteration of each engine in microseconds (us_resident = 0 when the
+ * resident engine does not fit).  LD_E_STATE if nothing was tuned. */
+int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, double* us_layerwise,
+                    double* us_resident);
 
 /* Diagnostic: run `reps` ascent iterations (real steps that advance the state,
  * launched without the graph) with a HIP event pair around every kernel launch,

@@ -30,7 +30,9 @@ _ENGINE = {"auto": LD_ENGINE_AUTO, "resident": LD_ENGINE_RESIDENT, "layerwise": 
 EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num_layers",
             "ld_set_validation", "ld_state_create", "ld_state_destroy", "ld_state_set_rho",
             "ld_state_get_rho", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval",
-            "ld_step", "ld_profile_iteration", "ld_final_bound", "ld_last_error"]
+            "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
+            "ld_set_tuned_config", "ld_profile_iteration",
+            "ld_final_bound", "ld_last_error"]
 
 
 class LDError(RuntimeError):
@@ -92,6 +94,11 @@ def load_library(path: Optional[str] = None):
     lib.ld_init_duals.argtypes = [V, P(ld_batch), I, I, P(V), V]
     lib.ld_dual_eval.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
     lib.ld_step.argtypes = [V, P(ld_batch), V, P(ld_opts), V]
+    lib.ld_autotune.argtypes = [V, P(ld_batch), P(ld_opts), V]
+    lib.ld_tuned_config.argtypes = [V, I, I, I, I, P(I), P(I), P(I), P(ctypes.c_double)]
+    lib.ld_tuned_engine.argtypes = [V, I, I, P(I), P(ctypes.c_double), P(ctypes.c_double)]
+    lib.ld_tile_candidates.argtypes = [V, I, I, I, P(I), P(I), P(I), I, P(I)]
+    lib.ld_set_tuned_config.argtypes = [V, I, I, I, I, I, I, I]
     lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
     for name in EXPORTED:
         getattr(lib, name)
@@ -261,6 +268,52 @@ def step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional
          tau: float = TAU_DEFAULT, engine="auto", stream=None):
     o = _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine)
     _check(net.lib.ld_step(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o), _stream(stream)))
+
+
+def autotune(net: Net, batch: Batch, total_iters=500, lr0=1e-2, lr_end=1e-4, beta1=0.9, beta2=0.999, eps=1e-8,
+             precision="fp32", tau: float = TAU_DEFAULT, stream=None):
+    """Run the autotuner for (batch.B, precision); returns tuning_info()."""
+    o = _opts(1, total_iters, lr0, lr_end, beta1, beta2, eps, precision, "crown", tau)
+    _check(net.lib.ld_autotune(net.handle, ctypes.byref(batch.struct), ctypes.byref(o), _stream(stream)))
+    return tuning_info(net, batch.B, precision)
+
+
+def tuning_info(net: Net, B: int, precision="fp32"):
+    """Tuned engine and per-contraction configuration for (B, precision), or None."""
+    eng, ul, ur = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    rc = net.lib.ld_tuned_engine(net.handle, int(B), _PREC[precision], ctypes.byref(eng), ctypes.byref(ul),
+                                 ctypes.byref(ur))
+    if rc == LD_E_STATE:
+        return None
+    _check(rc)
+    names = {v: k for k, v in _ENGINE.items()}
+    out = dict(engine=names[eng.value], us_per_iter_layerwise=ul.value, us_per_iter_resident=ur.value, layers=[])
+    tn, sp, fm, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    for k in range(1, len(net.widths) - 1):
+        for d, dname in ((1, "transposed"), (0, "forward")):
+            _check(net.lib.ld_tuned_config(net.handle, int(B), _PREC[precision], k, d, ctypes.byref(tn),
+                                           ctypes.byref(sp), ctypes.byref(fm), ctypes.byref(us)))
+            out["layers"].append(dict(layer=k, dir=dname, tn=tn.value, splits=sp.value, form=fm.value,
+                                      us=us.value))
+    return out
+
+
+def tile_candidates(net: Net, B: int, k: int, direction: str):
+    """Candidate (tn, splits, form) configurations of a contraction (direction
+    'forward' or 'transposed' of hidden layer k)."""
+    d = 1 if direction == "transposed" else 0
+    cnt = ctypes.c_int()
+    _check(net.lib.ld_tile_candidates(net.handle, int(B), int(k), d, None, None, None, 0, ctypes.byref(cnt)))
+    n = cnt.value
+    tn, sp, fm = (ctypes.c_int * max(n, 1))(), (ctypes.c_int * max(n, 1))(), (ctypes.c_int * max(n, 1))()
+    _check(net.lib.ld_tile_candidates(net.handle, int(B), int(k), d, tn, sp, fm, n, ctypes.byref(cnt)))
+    return [(tn[i], sp[i], fm[i]) for i in range(n)]
+
+
+def set_tuned_config(net: Net, B: int, precision: str, k: int, direction: str, tn: int, splits: int, form: int):
+    d = 1 if direction == "transposed" else 0
+    _check(net.lib.ld_set_tuned_config(net.handle, int(B), _PREC[precision], int(k), d, int(tn), int(splits),
+                                       int(form)))
 
 
 def _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine="auto"):

@@ -17,6 +17,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <array>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -59,6 +61,8 @@ uint16_t host_f2bf(float f) {
 // One contraction of a layer: one GemmGeom per stride class (M is set per launch).
 struct Job {
   std::vector<GemmGeom> geoms;
+  bool has_col = false;   // transposed strided conv: dense GEMM + col2im form
+  ColGeom col;
 };
 
 struct Layer {
@@ -101,7 +105,12 @@ struct ld_net {
   std::vector<Layer> L;
   std::vector<void*> allocs;
   Workspace ws;
-  std::map<std::tuple<int, int, int, int>, Tile> tiles;  // (layer, dir, B, mma) -> tile
+  // autotuned launch configurations: (layer, dir, B, mma) -> tile and its time (us)
+  std::map<std::tuple<int, int, int, int>, Tile> tiles;
+  std::map<std::tuple<int, int, int, int>, double> tile_us;
+  // autotuned engine: (B, mma) -> {engine, us per iteration layer-wise, resident (0: does not fit)}
+  std::map<std::pair<int, int>, std::array<double, 3>> engines;
+  int tune_gen = 0;  // bumped whenever a tuned choice changes (part of the graph key)
   std::mutex mu;
 };
 
@@ -229,6 +238,106 @@ int build_linear(ld_net* net, Layer& L, const float* W) {
   return LD_OK;
 }
 
+// Transposed product of a strided conv as Y = rho^T W (K = Co) plus a col2im sum
+// over the taps (ColGeom).  Stride-1 convs, and maps whose Y chunk would not fit
+// a modest LDS budget, keep the gather form.
+int build_col(ld_net* net, Layer& L, const float* W) {
+  const int Ci = L.in_c, H = L.in_h, Wd = L.in_w, Co = L.out_c, OH = L.out_h, OW = L.out_w;
+  const int kh = L.kh, kw = L.kw, s = L.stride, p = L.pad, khkw = kh * kw;
+  if (s < 2) return LD_OK;
+  if ((long)Ci * H * Wd >= (1L << 22)) return LD_OK;
+  ColGeom g;
+  std::memset(&g, 0, sizeof(g));
+  g.Co = Co;
+  g.M = OH * OW;
+  g.Ci = Ci;
+  g.H = H;
+  g.W = Wd;
+  g.HW = H * Wd;
+  g.khkw = khkw;
+  g.Mp = (int)round_up((size_t)g.M, 16);
+  auto ns_of = [&](int cc) { return 16 * ((cc * khkw + 15) / 16) + 1; };
+  int Cc = Ci;
+  while (Cc > 1 && (size_t)g.Mp * ns_of(Cc) * 4 > 40 * 1024) --Cc;
+  if ((size_t)g.Mp * ns_of(Cc) * 4 > 64 * 1024) return LD_OK;
+  g.Cc = Cc;
+  g.nchunks = (Ci + Cc - 1) / Cc;
+  g.ntc = (Cc * khkw + 15) / 16;
+  g.Ns = 16 * g.ntc + 1;
+  g.ksf = (Co + 15) / 16;
+  g.ksh = (Co + 31) / 32;
+  g.inv_HW = 1.0f / (float)g.HW;
+  g.inv_W = 1.0f / (float)Wd;
+  // taps reaching each output row / column: k = y + p - s*o for o in [0, OH)
+  std::vector<std::vector<std::pair<int, int>>> tyv(H), txv(Wd);
+  for (int y = 0; y < H; ++y)
+    for (int ky = 0; ky < kh; ++ky) {
+      const int t = y + p - ky;
+      if (t >= 0 && t % s == 0 && t / s < OH) tyv[y].push_back({ky, t / s});
+    }
+  for (int x = 0; x < Wd; ++x)
+    for (int kx = 0; kx < kw; ++kx) {
+      const int t = x + p - kx;
+      if (t >= 0 && t % s == 0 && t / s < OW) txv[x].push_back({kx, t / s});
+    }
+  int Tmax = 1;
+  for (auto& v : tyv) Tmax = std::max(Tmax, (int)v.size());
+  for (auto& v : txv) Tmax = std::max(Tmax, (int)v.size());
+  g.Tmax = Tmax;
+  std::vector<int> toy((size_t)H * Tmax, 0), coy(H), tox((size_t)Wd * Tmax, 0), cox(Wd);
+  for (int y = 0; y < H; ++y) {
+    coy[y] = (int)tyv[y].size();
+    for (int i = 0; i < coy[y]; ++i) toy[(size_t)y * Tmax + i] = tyv[y][i].second * OW * g.Ns + tyv[y][i].first * kw;
+  }
+  for (int x = 0; x < Wd; ++x) {
+    cox[x] = (int)txv[x].size();
+    for (int i = 0; i < cox[x]; ++i) tox[(size_t)x * Tmax + i] = txv[x][i].second * g.Ns + txv[x][i].first;
+  }
+  // B fragments: lane (r, q) of K step st holds W[k][n] for n = 16*nt + r and
+  // k = st*KS + VPL*q + j (the k order inside a step matches the A operand)
+  auto wv = [&](int c, int nt, int k, int r) -> float {
+    const int nl = nt * 16 + r;
+    const int ci = c * Cc + nl / khkw;
+    if (nl >= Cc * khkw || ci >= Ci || k >= Co) return 0.f;
+    return W[((size_t)k * Ci + ci) * khkw + nl % khkw];
+  };
+  std::vector<float> bf((size_t)g.nchunks * g.ntc * g.ksf * 64 * 4);
+  std::vector<uint16_t> bh((size_t)g.nchunks * g.ntc * g.ksh * 64 * 8);
+  for (int c = 0; c < g.nchunks; ++c)
+    for (int nt = 0; nt < g.ntc; ++nt)
+      for (int l = 0; l < 64; ++l) {
+        const int r = l & 15, q = l >> 4;
+        for (int st = 0; st < g.ksf; ++st)
+          for (int j = 0; j < 4; ++j)
+            bf[((((size_t)c * g.ntc + nt) * g.ksf + st) * 64 + l) * 4 + j] = wv(c, nt, st * 16 + 4 * q + j, r);
+        for (int st = 0; st < g.ksh; ++st)
+          for (int j = 0; j < 8; ++j)
+            bh[((((size_t)c * g.ntc + nt) * g.ksh + st) * 64 + l) * 8 + j] = host_f2bf(wv(c, nt, st * 32 + 8 * q + j, r));
+      }
+  void *pbf, *pbh, *pty, *pcy, *ptx, *pcx;
+  LD_TRY(alloc_dev(net, &pbf, bf.size() * 4));
+  LD_TRY(alloc_dev(net, &pbh, bh.size() * 2));
+  LD_TRY(alloc_dev(net, &pty, toy.size() * 4));
+  LD_TRY(alloc_dev(net, &pcy, coy.size() * 4));
+  LD_TRY(alloc_dev(net, &ptx, tox.size() * 4));
+  LD_TRY(alloc_dev(net, &pcx, cox.size() * 4));
+  LD_HIP(hipMemcpy(pbf, bf.data(), bf.size() * 4, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(pbh, bh.data(), bh.size() * 2, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(pty, toy.data(), toy.size() * 4, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(pcy, coy.data(), coy.size() * 4, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(ptx, tox.data(), tox.size() * 4, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(pcx, cox.data(), cox.size() * 4, hipMemcpyHostToDevice));
+  g.Bf = (const float*)pbf;
+  g.Bh = (const bf16_t*)pbh;
+  g.toff_y = (const int*)pty;
+  g.cnt_y = (const int*)pcy;
+  g.toff_x = (const int*)ptx;
+  g.cnt_x = (const int*)pcx;
+  L.tr.col = g;
+  L.tr.has_col = true;
+  return LD_OK;
+}
+
 int build_conv(ld_net* net, Layer& L, const float* W) {
   const int Ci = L.in_c, H = L.in_h, Wd = L.in_w, Co = L.out_c, OH = L.out_h, OW = L.out_w;
   const int kh = L.kh, kw = L.kw, s = L.stride, p = L.pad;
@@ -336,6 +445,7 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
       L.tr.geoms.push_back(g);
     }
   if ((int)L.tr.geoms.size() > 9) return fail(LD_E_UNSUPPORTED, "conv stride above 3 is not supported");
+  LD_TRY(build_col(net, L, W));
   if (conv_lds_bytes(L.fwd.geoms.data(), 1) > 160 * 1024 ||
       conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size()) > 160 * 1024)
     return fail(LD_E_UNSUPPORTED, "conv maps too large for the LDS images of one subdomain");
@@ -438,18 +548,47 @@ int fc_splits(const Job& J, int B, int tn, int want) {
 Tile heuristic_tile(const Job& J, int B) {
   Tile t;
   t.tm = 1;
+  t.form = 0;
   t.tn = job_tn(J, B);
   t.splits = job_is_conv(J) ? 1 : fc_splits(J, B, t.tn, 0);
   return t;
 }
 
+// Launch configurations the autotuner times for a contraction: the column tile
+// widths that the output width allows, both forms of a transposed strided conv,
+// and for fully-connected products every split of K into pieces of >= 64.
+std::vector<Tile> tile_candidates(const Job& J, int B) {
+  std::vector<Tile> c;
+  const int N = J.geoms[0].N, K = J.geoms[0].K;
+  std::vector<int> tns = {1};
+  if (N > 16) tns.push_back(2);
+  if (N > 32) tns.push_back(4);
+  if (job_is_conv(J)) {
+    if (J.has_col) c.push_back(Tile{1, 1, 1, 0});
+    for (int tn : tns) c.push_back(Tile{1, tn, 1, J.has_col ? 1 : 0});
+  } else {
+    for (int tn : tns)
+      for (int sp : {1, 2, 4, 8, 16, 32})
+        if (sp == 1 || (K / sp >= 64 && fc_splits(J, B, tn, sp) == sp)) c.push_back(Tile{1, tn, sp, 0});
+  }
+  return c;
+}
+
+// Form of the transposed strided convs forced for the current thread's launches
+// (-1: as tuned).  The CROWN initialisation of a state that the resident engine
+// will iterate uses the stride-class form, whose summation order the resident
+// kernel repeats: the duals start exactly on kinks of the dual (Prop. 2), so the
+// first iteration must see the very same coefficients as the initialisation.
+thread_local int g_form_override = -1;
+
 Tile pick_tile(const ld_net* net, int layer, int dir, int B, int mma) {
   ld_net* mnet = const_cast<ld_net*>(net);
   std::lock_guard<std::mutex> lk(mnet->mu);
   auto it = mnet->tiles.find(std::make_tuple(layer, dir, B, mma));
-  if (it != mnet->tiles.end()) return it->second;
   const Layer& L = net->L[layer];
-  return heuristic_tile(dir == 0 ? L.fwd : L.tr, B);
+  Tile t = it != mnet->tiles.end() ? it->second : heuristic_tile(dir == 0 ? L.fwd : L.tr, B);
+  if (g_form_override >= 0) t.form = g_form_override;
+  return t;
 }
 
 // slot: layer index 0..n-1; jobs of different layers may run concurrently, so
@@ -462,6 +601,7 @@ hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, 
     g[i] = J.geoms[i];
     g[i].M = B * g[i].HWq;
   }
+  if (J.has_col && t.form == 0) return launch_convT(J.col, B, (const float*)src, mma, e, s);
   if (job_is_conv(J)) return launch_conv(g, nc, B, src, src_bf16, mma, e, t.tn, s);
   SplitArgs sp{fc_splits(J, B, t.tn, t.splits), ws.partial + (size_t)slot * kPartialLayer, ws.counters};
   return launch_fc(g[0], src, src_bf16, mma, e, t.tn, sp, s);
@@ -588,42 +728,49 @@ int bias_div(const ld_net* net, int k) {
 // Phase A: inner minimisations of P_0..P_{n-1} at duals rho (rho[k-1] = rho_k).
 // In the ascent (o != nullptr) the first launch also advances the step counter,
 // and the last hidden layer's minimisation is left to its Adam epilogue.
+EpiArgs epi_phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, const Workspace& ws, int mma,
+                    float tau, int want_val, int* t_dev, float* adam, const ld_opts* o, int k) {
+  const Layer& L = net->L[k - 1];
+  EpiArgs e = epi0();
+  e.tau = tau;
+  e.want_val = want_val;
+  e.xs_bf16 = mma;
+  e.xs = ws.xs[k - 1];
+  e.val = ws.val[k - 1];
+  if (k == 1 && o != nullptr) {
+    e.t_dev = t_dev;
+    e.adam_w = adam;
+    e.lr0 = o->lr0;
+    e.lr_end = o->lr_end;
+    e.total = o->total_iters;
+    e.beta1 = o->beta1;
+    e.beta2 = o->beta2;
+    e.eps = o->eps;
+  }
+  if (k == 1) {
+    e.kind = EPI_P0;
+    e.lo = bt->l0;
+    e.hi = bt->u0;
+  } else {
+    e.kind = EPI_INNER_MIN;
+    e.rho = rho[k - 2];
+    e.lo = bt->l[k - 2];
+    e.hi = bt->u[k - 2];
+    e.bias = net->L[k - 2].bias;
+    e.xb = ws.xb[k - 1];
+    // a linear layer fed by a flattened conv map has one column per neuron of that map
+    e.bias_div = L.kind == LD_LINEAR ? bias_div(net, k - 1) : 1;
+  }
+  return e;
+}
+
 int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Workspace& ws, int mma, float tau,
             int want_val, int* t_dev, float* adam, const ld_opts* o, hipStream_t s, const ld_state* fk = nullptr) {
   const int n = net->n, B = bt->B;
   LD_HIP(fork_begin(fk, s));
   for (int k = 1; k <= n - 1; ++k) {
     const Layer& L = net->L[k - 1];
-    EpiArgs e = epi0();
-    e.tau = tau;
-    e.want_val = want_val;
-    e.xs_bf16 = mma;
-    e.xs = ws.xs[k - 1];
-    e.val = ws.val[k - 1];
-    if (k == 1 && o != nullptr) {
-      e.t_dev = t_dev;
-      e.adam_w = adam;
-      e.lr0 = o->lr0;
-      e.lr_end = o->lr_end;
-      e.total = o->total_iters;
-      e.beta1 = o->beta1;
-      e.beta2 = o->beta2;
-      e.eps = o->eps;
-    }
-    if (k == 1) {
-      e.kind = EPI_P0;
-      e.lo = bt->l0;
-      e.hi = bt->u0;
-    } else {
-      e.kind = EPI_INNER_MIN;
-      e.rho = rho[k - 2];
-      e.lo = bt->l[k - 2];
-      e.hi = bt->u[k - 2];
-      e.bias = net->L[k - 2].bias;
-      e.xb = ws.xb[k - 1];
-      // a linear layer fed by a flattened conv map has one column per neuron of that map
-      e.bias_div = L.kind == LD_LINEAR ? bias_div(net, k - 1) : 1;
-    }
+    const EpiArgs e = epi_phase_a(net, bt, rho, ws, mma, tau, want_val, t_dev, adam, o, k);
     const hipStream_t sk = fork_stream(fk, s, k - 1);
     LD_HIP(probe_begin(100 + k, sk));
     LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, sk));
@@ -694,6 +841,27 @@ int init_impl(const ld_net* net, const ld_batch* bt, int init, int mma, float* c
 }
 
 // One ascent iteration (phase A then phase B) on the state.
+EpiArgs epi_phase_b(const ld_net* net, const ld_batch* bt, const ld_state* st, const ld_opts* o, int k) {
+  const int n = net->n;
+  const Layer& L = net->L[k - 1];
+  EpiArgs e = epi0();
+  e.kind = EPI_ADAM;
+  e.xb_in = st->ws.xb[k];
+  if (k == n - 1) {
+    e.kind = EPI_ADAM_LAST;
+    e.gc = st->ws.gconst;
+    e.lo = bt->l[k - 1];
+    e.hi = bt->u[k - 1];
+    e.tau = o->tie_tau;
+  }
+  e.bias = L.bias;
+  e.rho_w = st->rho[k - 1];
+  e.m = st->m[k - 1];
+  e.v = st->v[k - 1];
+  e.adam = st->adam;
+  return e;
+}
+
 int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
   const int n = net->n, B = bt->B;
   const int mma = o->precision == LD_BF16 ? 1 : 0;
@@ -702,21 +870,7 @@ int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts
   LD_HIP(fork_begin(st, s));
   for (int k = 1; k <= n - 1; ++k) {
     const Layer& L = net->L[k - 1];
-    EpiArgs e = epi0();
-    e.kind = EPI_ADAM;
-    e.xb_in = st->ws.xb[k];
-    if (k == n - 1) {
-      e.kind = EPI_ADAM_LAST;
-      e.gc = st->ws.gconst;
-      e.lo = bt->l[k - 1];
-      e.hi = bt->u[k - 1];
-      e.tau = o->tie_tau;
-    }
-    e.bias = L.bias;
-    e.rho_w = st->rho[k - 1];
-    e.m = st->m[k - 1];
-    e.v = st->v[k - 1];
-    e.adam = st->adam;
+    const EpiArgs e = epi_phase_b(net, bt, st, o, k);
     const hipStream_t sk = fork_stream(st, s, k - 1);
     LD_HIP(probe_begin(300 + k, sk));
     LD_HIP(run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), st->ws, k - 1, sk));
@@ -735,7 +889,7 @@ void destroy_graph(ld_state* st) {
   st->gchunk = 0;
 }
 
-std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int chunk) {
+std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int chunk, int net_tune_gen) {
   std::vector<double> k;
   auto P = [&](const void* p) { k.push_back((double)(uintptr_t)p); };
   k.push_back(bt->B);
@@ -755,6 +909,7 @@ std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int c
   k.push_back(o->precision);
   k.push_back(o->tie_tau);
   k.push_back(chunk);
+  k.push_back(net_tune_gen);
   return k;
 }
 
@@ -1210,7 +1365,11 @@ static int ensure_initialised(const ld_net* net, const ld_batch* bt, ld_state* s
   if (!st->initialized) {
     if (o->init != LD_INIT_GIVEN) {
       std::vector<float*> r(st->rho.begin(), st->rho.end());
-      LD_TRY(init_impl(net, bt, o->init, mma, r.data(), st->ws, s));
+      const bool resident = o->engine == LD_ENGINE_RESIDENT && resident_shape(net, bt->B, mma).S > 0;
+      g_form_override = resident ? 1 : -1;
+      const int rc = init_impl(net, bt, o->init, mma, r.data(), st->ws, s);
+      g_form_override = -1;
+      LD_TRY(rc);
       for (int k = 1; k <= net->n - 1; ++k) {
         const size_t bytes = (size_t)st->B * width(net, k) * 4;
         LD_HIP(hipMemsetAsync(st->m[k - 1], 0, bytes, s));
@@ -1227,11 +1386,8 @@ static int ensure_initialised(const ld_net* net, const ld_batch* bt, ld_state* s
   return LD_OK;
 }
 
-int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
-  g_err.clear();
-  LD_TRY(check_step_args(net, bt, st, o));
-  LD_TRY(validate_values(net, bt, st->ws, s));
-  LD_TRY(ensure_initialised(net, bt, st, o, s));
+// The ascent of one ld_step call on an initialised state, engine already chosen.
+static int step_impl(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
   if (o->iters == 0) return LD_OK;
   const int mma_sel = o->precision == LD_BF16 ? 1 : 0;
   if (o->engine != LD_ENGINE_LAYERWISE) {
@@ -1246,7 +1402,7 @@ int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* 
     }
   }
   const int chunk = std::min(o->iters, 100);
-  std::vector<double> key = graph_key(bt, o, net->n, chunk);
+  std::vector<double> key = graph_key(bt, o, net->n, chunk, net->tune_gen);
   if (!st->gexec || key != st->gkey) {
     destroy_graph(st);
     LD_HIP(hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal));
@@ -1272,6 +1428,208 @@ int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* 
   for (int r = 0; r < reps; ++r) LD_HIP(hipGraphLaunch(st->gexec, s));
   for (int i = reps * chunk; i < o->iters; ++i) LD_TRY(iteration(net, bt, st, o, s));
   st->t_host += o->iters;
+  return LD_OK;
+}
+
+// Best of three timings of `reps` back-to-back calls of f (after one warm-up call).
+static int time_calls(const std::function<int()>& f, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, double* us) {
+  LD_TRY(f());
+  double best = 1e300;
+  for (int trial = 0; trial < 3; ++trial) {
+    LD_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) LD_TRY(f());
+    LD_HIP(hipEventRecord(e1, s));
+    LD_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    LD_HIP(hipEventElapsedTime(&ms, e0, e1));
+    best = std::min(best, 1000.0 * ms / reps);
+  }
+  *us = best;
+  return LD_OK;
+}
+
+// Autotuner: on a scratch state of the same batch, time every candidate launch
+// configuration of every contraction of the iteration (with its real epilogue)
+// and keep the fastest; then time the two engines over a short ascent.
+static int autotune_impl(const ld_net* net, const ld_batch* bt, const ld_opts* o, hipStream_t s) {
+  const int B = bt->B, n = net->n, mma = o->precision == LD_BF16 ? 1 : 0;
+  ld_net* mnet = const_cast<ld_net*>(net);
+  if (B == 0) return LD_OK;
+  {
+    std::lock_guard<std::mutex> lk(mnet->mu);
+    for (auto it = mnet->tiles.begin(); it != mnet->tiles.end();)
+      if (std::get<2>(it->first) == B && std::get<3>(it->first) == mma) {
+        mnet->tile_us.erase(it->first);
+        it = mnet->tiles.erase(it);
+      } else {
+        ++it;
+      }
+    mnet->engines.erase({B, mma});
+    mnet->tune_gen++;
+  }
+  ld_state* tmp = nullptr;
+  LD_TRY(ld_state_create(net, B, &tmp));
+  struct StateGuard {
+    ld_state* p;
+    ~StateGuard() { ld_state_destroy(p); }
+  } guard{tmp};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  LD_HIP(hipEventCreate(&e0));
+  LD_HIP(hipEventCreate(&e1));
+  struct EventGuard {
+    hipEvent_t a, b;
+    ~EventGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } eguard{e0, e1};
+  LD_TRY(validate_values(net, bt, tmp->ws, s));
+  ld_opts to = *o;
+  to.engine = LD_ENGINE_LAYERWISE;
+  to.init = LD_INIT_CROWN;
+  to.iters = 1;
+  LD_TRY(ensure_initialised(net, bt, tmp, &to, s));
+  LD_TRY(iteration(net, bt, tmp, &to, s));  // x* of every layer in the operand precision
+  std::vector<const float*> rho(tmp->rho.begin(), tmp->rho.end());
+  for (int k = 1; k <= n - 1; ++k)
+    for (int dir = 1; dir >= 0; --dir) {
+      const Job& J = dir ? net->L[k - 1].tr : net->L[k - 1].fwd;
+      double best = 1e300;
+      Tile pick = heuristic_tile(J, B);
+      for (const Tile& t : tile_candidates(J, B)) {
+        auto launch = [&]() -> int {
+          if (dir == 1) {
+            const EpiArgs e = epi_phase_a(net, bt, rho.data(), tmp->ws, mma, o->tie_tau, 0, nullptr, nullptr, nullptr, k);
+            LD_HIP(run_job(J, B, rho[k - 1], 0, mma, e, t, tmp->ws, k - 1, s));
+          } else {
+            const EpiArgs e = epi_phase_b(net, bt, tmp, &to, k);
+            LD_HIP(run_job(J, B, tmp->ws.xs[k - 1], mma, mma, e, t, tmp->ws, k - 1, s));
+          }
+          return LD_OK;
+        };
+        double us = 0;
+        LD_TRY(time_calls(launch, s, e0, e1, 3, &us));
+        if (us < best) {
+          best = us;
+          pick = t;
+        }
+      }
+      std::lock_guard<std::mutex> lk(mnet->mu);
+      const auto key = std::make_tuple(k - 1, dir, B, mma);
+      mnet->tiles[key] = pick;
+      mnet->tile_us[key] = best;
+    }
+  {
+    std::lock_guard<std::mutex> lk(mnet->mu);
+    mnet->tune_gen++;
+  }
+  // engines: a short ascent of each (graph replay for the layer-wise engine)
+  const int T = 20;
+  to.iters = T;
+  to.total_iters = std::max(o->total_iters, 2 * T);
+  auto run_engine = [&](int engine) -> int {
+    to.engine = engine;
+    return step_impl(net, bt, tmp, &to, s);
+  };
+  double us_lw = 0, us_res = 0;
+  LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_LAYERWISE); }, s, e0, e1, 1, &us_lw));
+  if (resident_shape(net, B, mma).S > 0) LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_RESIDENT); }, s, e0, e1, 1, &us_res));
+  LD_HIP(hipStreamSynchronize(s));
+  const int eng = (us_res > 0 && us_res < us_lw) ? LD_ENGINE_RESIDENT : LD_ENGINE_LAYERWISE;
+  std::lock_guard<std::mutex> lk(mnet->mu);
+  mnet->engines[{B, mma}] = {(double)eng, us_lw / T, us_res / T};
+  return LD_OK;
+}
+
+static int tuned_engine(const ld_net* net, int B, int mma) {
+  ld_net* mnet = const_cast<ld_net*>(net);
+  std::lock_guard<std::mutex> lk(mnet->mu);
+  auto it = mnet->engines.find({B, mma});
+  return it == mnet->engines.end() ? -1 : (int)it->second[0];
+}
+
+int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_step_args(net, bt, st, o));
+  LD_TRY(validate_values(net, bt, st->ws, s));
+  ld_opts eo = *o;
+  if (eo.engine == LD_ENGINE_AUTO && bt->B > 0) {
+    const int mma = o->precision == LD_BF16 ? 1 : 0;
+    if (tuned_engine(net, bt->B, mma) < 0) LD_TRY(autotune_impl(net, bt, o, s));
+    eo.engine = tuned_engine(net, bt->B, mma);
+  }
+  LD_TRY(ensure_initialised(net, bt, st, &eo, s));
+  return step_impl(net, bt, st, &eo, s);
+}
+
+int ld_autotune(const ld_net* net, const ld_batch* bt, const ld_opts* o, hipStream_t s) {
+  g_err.clear();
+  if (!net || !o) return fail(LD_E_ARG, "NULL argument");
+  LD_TRY(check_batch(net, bt));
+  if (o->precision != LD_FP32 && o->precision != LD_BF16) return fail(LD_E_ARG, "unknown precision");
+  return autotune_impl(net, bt, o, s);
+}
+
+int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, int* tn, int* splits, int* form,
+                    double* us) {
+  g_err.clear();
+  if (!net || !tn || !splits || !form || !us) return fail(LD_E_ARG, "NULL argument");
+  if (k < 1 || k > net->n - 1 || (dir != 0 && dir != 1)) return fail(LD_E_ARG, "layer or direction out of range");
+  ld_net* mnet = const_cast<ld_net*>(net);
+  std::lock_guard<std::mutex> lk(mnet->mu);
+  const auto key = std::make_tuple(k - 1, dir, B, precision == LD_BF16 ? 1 : 0);
+  auto it = mnet->tiles.find(key);
+  if (it == mnet->tiles.end()) return fail(LD_E_STATE, "no tuned configuration for this batch size and precision");
+  *tn = it->second.tn;
+  *splits = it->second.splits;
+  *form = it->second.form;
+  *us = mnet->tile_us[key];
+  return LD_OK;
+}
+
+int ld_tile_candidates(const ld_net* net, int B, int k, int dir, int* tn, int* splits, int* form, int max_count,
+                       int* count) {
+  g_err.clear();
+  if (!net || !count || (max_count > 0 && (!tn || !splits || !form))) return fail(LD_E_ARG, "NULL argument");
+  if (k < 1 || k > net->n - 1 || (dir != 0 && dir != 1) || B < 0) return fail(LD_E_ARG, "layer or direction out of range");
+  const Job& J = dir ? net->L[k - 1].tr : net->L[k - 1].fwd;
+  const std::vector<Tile> c = tile_candidates(J, B);
+  *count = (int)c.size();
+  for (int i = 0; i < std::min(max_count, (int)c.size()); ++i) {
+    tn[i] = c[i].tn;
+    splits[i] = c[i].splits;
+    form[i] = c[i].form;
+  }
+  return LD_OK;
+}
+
+int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, int tn, int splits, int form) {
+  g_err.clear();
+  if (!net) return fail(LD_E_ARG, "NULL argument");
+  if (k < 1 || k > net->n - 1 || (dir != 0 && dir != 1) || B < 0) return fail(LD_E_ARG, "layer or direction out of range");
+  const Job& J = dir ? net->L[k - 1].tr : net->L[k - 1].fwd;
+  for (const Tile& t : tile_candidates(J, B))
+    if (t.tn == tn && t.splits == splits && t.form == form) {
+      std::lock_guard<std::mutex> lk(net->mu);
+      const auto key = std::make_tuple(k - 1, dir, B, precision == LD_BF16 ? 1 : 0);
+      net->tiles[key] = t;
+      net->tile_us[key] = 0.0;
+      net->tune_gen++;
+      return LD_OK;
+    }
+  return fail(LD_E_ARG, "not a candidate configuration of this contraction");
+}
+
+int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, double* us_layerwise, double* us_resident) {
+  g_err.clear();
+  if (!net || !engine || !us_layerwise || !us_resident) return fail(LD_E_ARG, "NULL argument");
+  ld_net* mnet = const_cast<ld_net*>(net);
+  std::lock_guard<std::mutex> lk(mnet->mu);
+  auto it = mnet->engines.find({B, precision == LD_BF16 ? 1 : 0});
+  if (it == mnet->engines.end()) return fail(LD_E_STATE, "no tuned engine for this batch size and precision");
+  *engine = (int)it->second[0];
+  *us_layerwise = it->second[1];
+  *us_resident = it->second[2];
   return LD_OK;
 }
 

@@ -80,10 +80,11 @@ struct EpiArgs {
   int total;
 };
 
-// Launch-time tile configuration: each wave computes tm x tn MFMA tiles of 16x16,
-// a block is 4 waves stacked along M, and K is split `splits` ways.
+// Launch-time configuration of one contraction: tn 16-column MFMA tiles per wave,
+// K split `splits` ways (fully-connected), and for transposed strided convs the
+// form (0: dense GEMM + col2im, 1: stride-class gather).
 struct Tile {
-  int tm, tn, splits;
+  int tm, tn, splits, form;
 };
 
 // Scratch of split-K launches: partial tiles and one arrival counter per tile
@@ -135,6 +136,34 @@ struct RPlan {
   int* t_dev;           // receives t0 + iters at the end of the launch
   RLayer L[kMaxLayers];
 };
+
+// ---------------------------------------------------------------------------
+// Transposed strided convolution as one dense GEMM followed by a col2im sum:
+//   Y[m][n] = sum_co rho[co][m] W[co][n],  m = (oy, ox) position of rho, n = (ci, ky, kx),
+//   g[ci][y][x] = sum of Y[(oy, ox)][(ci, ky, kx)] over the taps with oy*s - p + ky = y
+//   and ox*s - p + kx = x.
+// The reduction is over the Co channels of rho only, every product is a useful one
+// (no stride-class padding), and the A operand is read contiguously.  Input
+// channels are processed in chunks of Cc so that the Y chunk fits in LDS.
+// ---------------------------------------------------------------------------
+struct ColGeom {
+  int Co, M;              // reduction length (channels of rho); positions of rho (OH*OW)
+  int Ci, H, W, HW;       // destination map (the forward layer's input)
+  int khkw;               // taps per channel
+  int Cc, nchunks, ntc;   // channels per chunk, chunks, 16-column tiles per chunk
+  int Ns, Mp;             // LDS row stride of the Y chunk (odd, > 16*ntc); rows (M rounded up to 16)
+  int Tmax;               // taps reaching one output row (column) at most
+  int ksf, ksh;           // K steps: FP32 (16 deep), BF16 (32 deep)
+  float inv_HW, inv_W;    // 1/HW, 1/W for the index split of the epilogue
+  const float* Bf;        // FP32 fragments [nchunks][ntc][ksf][64 lanes][4]
+  const bf16_t* Bh;       // BF16 fragments [nchunks][ntc][ksh][64 lanes][8]
+  const int* toff_y;      // [H][Tmax]  oy*OW*Ns + ky*kw
+  const int* cnt_y;       // [H]
+  const int* toff_x;      // [W][Tmax]  ox*Ns + kx
+  const int* cnt_x;       // [W]
+};
+hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16, const EpiArgs& e, hipStream_t s);
+size_t convT_lds_bytes(const ColGeom& g);
 
 // The plan travels by value in the kernel arguments (no host-device race between calls).
 hipError_t launch_resident(const RPlan& plan, int grid, size_t lds_bytes, int mma_bf16, hipStream_t s);

@@ -538,6 +538,137 @@ hipError_t launch_fc(const GemmGeom& G, const void* src, int src_bf16, int mma_b
 }
 
 // ---------------------------------------------------------------------------
+// Transposed strided convolution, one block per subdomain (see ColGeom):
+//  1. per chunk of input channels, waves compute 16x16 MFMA tiles of
+//     Y = rho^T W (A read straight from rho, contiguous along positions; B from
+//     fragment-ordered weights) into LDS;
+//  2. every output of the chunk sums its taps from Y (tap offsets from small
+//     LDS tables) and goes through the epilogue, four consecutive neurons per
+//     thread.
+// ---------------------------------------------------------------------------
+constexpr int kTThreads = 256;
+
+// e / d for 0 <= e < 2^22 with inv = 1/d: float estimate, then one correction
+__device__ __forceinline__ int fdiv(int e, int d, float inv) {
+  int q = (int)((float)e * inv);
+  const int r = e - q * d;
+  if (r < 0)
+    --q;
+  else if (r >= d)
+    ++q;
+  return q;
+}
+
+template <bool BF>
+__global__ __launch_bounds__(kTThreads) void convT_kernel(ColGeom G, const float* __restrict__ rho, EpiArgs E) {
+  using M = Mma<BF>;
+  typedef typename M::BFrag BFrag;
+  constexpr int KS = M::KS, VPL = M::VPL, NW = kTThreads / 64;
+  extern __shared__ float lds[];
+  float* Y = lds;                                 // [Mp][Ns]
+  int* ty = reinterpret_cast<int*>(Y + G.Mp * G.Ns);  // [H][Tmax]
+  int* cy = ty + G.H * G.Tmax;                    // [H]
+  int* tx = cy + G.H;                             // [W][Tmax]
+  int* cx = tx + G.W * G.Tmax;                    // [W]
+  const int b = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  adam_tick(E);
+  for (int i = tid; i < G.H * G.Tmax; i += kTThreads) ty[i] = G.toff_y[i];
+  for (int i = tid; i < G.H; i += kTThreads) cy[i] = G.cnt_y[i];
+  for (int i = tid; i < G.W * G.Tmax; i += kTThreads) tx[i] = G.toff_x[i];
+  for (int i = tid; i < G.W; i += kTThreads) cx[i] = G.cnt_x[i];
+  const float* src = rho + (size_t)b * G.Co * G.M;
+  const int ks = BF ? G.ksh : G.ksf;
+  const int mtn = G.Mp >> 4;
+  const BFrag* frags = reinterpret_cast<const BFrag*>(BF ? (const void*)G.Bh : (const void*)G.Bf);
+  const size_t dst_base = (size_t)b * G.Ci * G.HW;
+  for (int c = 0; c < G.nchunks; ++c) {
+    const int items = mtn * G.ntc;
+    for (int it = wave; it < items; it += NW) {
+      const int mt = it / G.ntc;
+      const int nt = it - mt * G.ntc;
+      const int m = mt * 16 + r;
+      const bool mv = m < G.M;
+      const BFrag* fb = frags + (size_t)(c * G.ntc + nt) * ks * 64 + lane;
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int st = 0; st < ks; ++st) {
+        float a[VPL];
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) {
+          const int k = st * KS + VPL * g + j;
+          a[j] = (mv && k < G.Co) ? src[(size_t)k * G.M + m] : 0.f;
+        }
+        M::mma(a, fb[(size_t)st * 64], acc);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Y[(mt * 16 + 4 * g + q) * G.Ns + nt * 16 + r] = acc[q];
+    }
+    __syncthreads();
+    const int c0 = c * G.Cc, c1 = min(G.Ci, c0 + G.Cc);
+    const int e0 = c0 * G.HW, e1 = c1 * G.HW;
+    if ((G.HW & 3) == 0) {
+      for (int e = e0 + 4 * tid; e < e1; e += 4 * kTThreads) {
+        const int ci = fdiv(e, G.HW, G.inv_HW);
+        const int rem = e - ci * G.HW;
+        int y = fdiv(rem, G.W, G.inv_W);
+        int x = rem - y * G.W;
+        const int nb = (ci - c0) * G.khkw;
+        float v4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float sum = 0.f;
+          const int ny = cy[y], nx = cx[x];
+          for (int ia = 0; ia < ny; ++ia) {
+            const int oy = ty[y * G.Tmax + ia] + nb;
+            for (int ib = 0; ib < nx; ++ib) sum += Y[oy + tx[x * G.Tmax + ib]];
+          }
+          v4[q] = sum;
+          if (++x == G.W) {
+            x = 0;
+            ++y;
+          }
+        }
+        epilogue4<true>(E, dst_base + e, 1, 4, b, 0, ci, 0, v4);
+      }
+    } else {
+      for (int e = e0 + tid; e < e1; e += kTThreads) {
+        const int ci = fdiv(e, G.HW, G.inv_HW);
+        const int rem = e - ci * G.HW;
+        const int y = fdiv(rem, G.W, G.inv_W);
+        const int x = rem - y * G.W;
+        const int nb = (ci - c0) * G.khkw;
+        float sum = 0.f;
+        for (int ia = 0; ia < cy[y]; ++ia) {
+          const int oy = ty[y * G.Tmax + ia] + nb;
+          for (int ib = 0; ib < cx[x]; ++ib) sum += Y[oy + tx[x * G.Tmax + ib]];
+        }
+        float v4[4] = {sum, 0.f, 0.f, 0.f};
+        epilogue4<false>(E, dst_base + e, 1, 1, b, 0, ci, 0, v4);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+size_t convT_lds_bytes(const ColGeom& g) {
+  return (size_t)4 * ((size_t)g.Mp * g.Ns + (size_t)g.H * g.Tmax + g.H + (size_t)g.W * g.Tmax + g.W);
+}
+
+hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16, const EpiArgs& e, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  const size_t lds = convT_lds_bytes(g);
+  const void* fn = mma_bf16 ? (const void*)convT_kernel<true> : (const void*)convT_kernel<false>;
+  if (lds > 64 * 1024) {
+    hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+  }
+  if (mma_bf16)
+    hipLaunchKernelGGL(convT_kernel<true>, dim3(B), dim3(kTThreads), lds, s, g, rho, e);
+  else
+    hipLaunchKernelGGL(convT_kernel<false>, dim3(B), dim3(kTThreads), lds, s, g, rho, e);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // inner minimisation of the last hidden layer, whose coefficient
 // g_{n-1} = W_n^T rho_n = -W_n^T c is constant over the ascent.  In ascent mode
 // (t_dev != nullptr) thread 0 also advances the step counter and writes the

@@ -1,0 +1,136 @@
+"""Uneven batching at full size: the deep conv net (conv 8@3x3/1, 8@4x4/2, 8@3x3/1,
+8@4x4/2, FC 100, FC 10) with six properties of 37, 150, 600, 1200, 9 and 2048
+subdomains (B = 4044) concatenated along the batch, each property with its own
+input point, objective and splits.
+
+The GPU always runs the whole batch; the oracle checks sampled subdomains: the
+first and last of every property (its boundaries in the batch) and one inside.
+"""
+import numpy as np
+import pytest
+import torch
+
+import ldgen
+from oracle import ld_oracle as O
+from tests import _parity as PT
+
+pytestmark = pytest.mark.gpu
+
+FP32_FINAL_REL = 3e-3
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _sample(inst):
+    idx, off = [], 0
+    for cnt in inst.meta["props"]:
+        idx += sorted({off, off + cnt // 2, off + cnt - 1})
+        off += cnt
+    assert off == inst.B
+    return idx
+
+
+@pytest.fixture(scope="module")
+def deep():
+    import paper_2104_06718_amd as P
+    inst = ldgen.make_instance("deep")
+    assert inst.B == 4044
+    net = P.Net(inst.layers)
+    batch = P.Batch.from_instance(inst)
+    return P, inst, net, batch
+
+
+def test_deep_dual_eval_full_batch_sampled(deep):
+    P, inst, net, batch = deep
+    _case("deep dual_eval B=4044 random duals")
+    rho = ldgen.random_duals(inst, seed=21, scale=0.05)
+    q, s = P.dual_eval(net, batch, [torch.from_numpy(r).cuda() for r in rho], supergrad=True)
+    torch.cuda.synchronize()
+    idx = _sample(inst)
+    onet = O.net_from_specs(inst.layers)
+    ob = O.batch_from_instance(inst, idx)
+    orho = [torch.from_numpy(r[idx]).double() for r in rho]
+    ev = O.dual_eval(onet, ob, orho)
+    tol = PT.q_tol(onet, ob, orho, ev)
+    err = (q.cpu()[idx] - ev["q"]).abs()
+    assert bool((err <= tol).all()), f"q: max err {err.max().item()}"
+    masks = PT.supergrad_masks(onet, PT.unstable_decisions(onet, ob, orho, ev))
+    scale = PT.s_scale(onet, ev)
+    for k in range(len(s)):
+        d = (s[k].cpu().double()[idx] - ev["s"][k]).abs()
+        bad = (d > PT.REL * scale[k] + 1e-7) & ~masks[k]
+        assert not bool(bad.any()), f"layer {k + 1}: {int(bad.sum())} supergradient entries differ"
+
+
+@pytest.mark.parametrize("engine", ["layerwise", "resident"])
+def test_deep_ascent_fp32_full_batch_sampled(deep, engine):
+    """The full 4044-subdomain batch, 300 iterations, against the oracle's own
+    300-iteration run on the sampled subdomains."""
+    P, inst, net, batch = deep
+    T = inst.meta["T"]
+    _case(f"deep fp32 ascent B=4044 T={T} engine={engine}")
+    st = P.State(net, inst.B)
+    try:
+        P.step(net, batch, st, iters=T, total_iters=T, precision="fp32", engine=engine)
+    except P.LDError as e:
+        if e.code == -6:
+            pytest.skip(f"engine {engine} does not fit this network: {e}")
+        raise
+    fb = P.final_bound(net, batch, st)
+    torch.cuda.synchronize()
+    idx = _sample(inst)
+    onet = O.net_from_specs(inst.layers)
+    ob = O.batch_from_instance(inst, idx)
+    ofb = O.final_bound(onet, ob, O.ascent(onet, ob, O.AdamOpts(T=T)))
+    b = fb["bound"].cpu()[idx]
+    d = (b - ofb["bound"]).abs()
+    print(f"  |gpu - oracle| mean {d.mean().item():.2e} max {d.max().item():.2e}")
+    assert bool((d <= FP32_FINAL_REL * ofb["bound"].abs() + 1e-3).all()), (b, ofb["bound"])
+    feas = fb["feasible"].cpu().bool()
+    assert bool((fb["bound"].cpu()[feas] <= fb["primal"].cpu()[feas] + 1e-6).all())
+    assert bool(torch.isfinite(fb["bound"]).all())
+
+
+def test_deep_bf16_full_batch_sound(deep):
+    P, inst, net, batch = deep
+    T = inst.meta["T"]
+    _case(f"deep bf16 ascent B=4044 T={T}")
+    res = {}
+    for prec in ("fp32", "bf16"):
+        st = P.State(net, inst.B)
+        P.step(net, batch, st, iters=T, total_iters=T, precision=prec)
+        res[prec] = P.final_bound(net, batch, st)
+    torch.cuda.synchronize()
+    fb = res["bf16"]
+    feas = fb["feasible"].bool()
+    print(f"  feasible primal points: {int(feas.sum())} of {inst.B}")
+    assert bool((fb["bound"][feas] <= fb["primal"][feas] + 1e-6).all())
+    # the returned bound is max(q(rho^0), q(rho^T)) with both evaluated with FP32 operands
+    assert bool((fb["bound"] >= fb["q_final"] - 1e-12).all())
+    gap = (res["bf16"]["bound"] - res["fp32"]["bound"])
+    print(f"  bf16 - fp32 bound: mean {gap.mean().item():.3e} max |.| {gap.abs().max().item():.3e}")
+    assert gap.abs().mean().item() < 0.05 * res["fp32"]["bound"].abs().mean().item() + 1e-2
+
+
+def test_deep_properties_are_independent(deep):
+    """A subdomain's result does not depend on the rest of the batch: the second
+    property run alone gives the duals it gets inside the full batch (up to the
+    summation order of split fully-connected products, which depends on B)."""
+    P, inst, net, batch = deep
+    _case("deep sub-batch independence")
+    T = 20
+    full = P.State(net, inst.B)
+    P.step(net, batch, full, iters=T, total_iters=T)
+    sub_inst = inst.subset(list(range(37, 37 + 150)))
+    sub_b = P.Batch.from_instance(sub_inst)
+    part = P.State(net, sub_inst.B)
+    P.step(net, sub_b, part, iters=T, total_iters=T)
+    tot = bad = 0
+    for a, b in zip(full.get_rho(), part.get_rho()):
+        diff = (a[37:187] - b).abs()
+        bad += int((diff > 1e-4 * (b.abs() + 1e-2)).sum())
+        tot += diff.numel()
+    print(f"  duals differing beyond 1e-4 relative: {bad} of {tot}")
+    assert bad <= 0.02 * tot
