@@ -11,8 +11,11 @@ device memory before the timed region starts.
 
 Prints ONE JSON line.  `value` is bounds/sec of the BF16 form (BF16 operands on
 MFMA, FP32 accumulation) at the iteration count that reaches the FP32 form's
-bound (mean gap <= 1e-3); the FP32 form and the gap are reported beside it.
+bound (T, then T+50, T+100, ... until the mean gap is <= 1e-3); the FP32 form
+and the gap are reported beside it.  Launch configurations and the engine come
+from the autotuner (run during the warm-up, outside the timed region).
 """
+import hashlib
 import argparse
 import json
 import os
@@ -29,7 +32,7 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="wide")
     ap.add_argument("--B", type=int, default=None)
@@ -37,7 +40,7 @@ def parse():
     ap.add_argument("--bf16-iters", type=int, default=None,
                     help="iterations of the BF16 form (default: searched for equal bound)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=24, help="subdomains timed on the host oracle")
+    ap.add_argument("--cpu-sample", type=int, default=512, help="subdomains timed on the host oracle")
     ap.add_argument("--quick", action="store_true", help="skip the equal-bound search (profiling runs)")
     ap.add_argument("--profile-only", choices=["fp32", "bf16"], default=None,
                     help="for rocprofv3: one 64 MiB device copy (counter calibration), then --reps ascent "
@@ -82,6 +85,21 @@ def layer_slot_cost(inst, kind, B, prec):
     return B * nb + wbytes(L), B * 2 * macs(L)
 
 
+def kernel_name(info, kind, inst):
+    """Name of the kernel launched for an iteration slot under the tuned configuration."""
+    ph, k = divmod(kind, 100)
+    L = inst.layers[k - 1]
+    cfg = None
+    if info is not None:
+        d = "transposed" if ph == 1 else "forward"
+        cfg = next((e for e in info["layers"] if e["layer"] == k and e["dir"] == d), None)
+    if L.kind == "linear":
+        return "fc_kernel"
+    if ph == 1 and L.stride > 1 and (cfg is None or cfg["form"] == 0):
+        return "convT_kernel"
+    return "conv_plane_kernel"
+
+
 def run_form(P, net, batch, st, iters, prec, steps, warmup, engine="auto"):
     import torch
     for _ in range(warmup):
@@ -106,18 +124,47 @@ def run_form(P, net, batch, st, iters, prec, steps, warmup, engine="auto"):
 
 
 def cpu_baseline(inst, T, sample):
+    """The FP64 oracle on the first `sample` subdomains (all T iterations, CROWN
+    init, final bound), timed on the host; also returns its bounds."""
     import torch
     from oracle import ld_oracle as O
-    idx = list(range(sample))
+    idx = list(range(min(sample, inst.B)))
     onet = O.net_from_specs(inst.layers)
     ob = O.batch_from_instance(inst, idx)
     t0 = time.perf_counter()
     st = O.ascent(onet, ob, O.AdamOpts(T=T))
-    O.final_bound(onet, ob, st)
+    fb = O.final_bound(onet, ob, st)
     dt = time.perf_counter() - t0
-    return dict(value=sample / dt, unit="bounds/s", cores=torch.get_num_threads(), kind="oracle",
-                sample=f"{sample} of {inst.B} subdomains, {T} iterations each, FP64 torch-CPU oracle, "
-                       f"{dt:.1f} s")
+    out = dict(value=len(idx) / dt, unit="bounds/s", cores=torch.get_num_threads(), kind="oracle",
+               sample=f"{len(idx)} of {inst.B} subdomains (the first ones), {T} iterations each, "
+                      f"FP64 torch-CPU oracle, {dt:.1f} s")
+    return out, idx, fb["bound"]
+
+
+def src_hash():
+    """Hash of the HIP sources (a stored counter measurement is valid for this build only)."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2104_06718_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, kind, config, B, prec):
+    """HBM bytes per launch of `kernel` from the committed counter measurement
+    (profiles/traffic.json: FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel
+    calibration), if it was taken on the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    key = f"{config}/B={B}/{prec}/{kernel}/slot{kind}"
+    e = rec.get("kernels", {}).get(key)
+    if e is None or rec.get("src_hash") != src_hash():
+        return None
+    return e["bytes_per_launch"]
 
 
 def main():
@@ -139,36 +186,44 @@ def main():
     P.set_validation(False)
 
     if a.profile_only:
-        x = torch.ones(16 << 20, device="cuda", dtype=torch.float32)
+        # counter calibration: a 1 GiB device copy (far larger than L2 and the MALL)
+        x = torch.ones(256 << 20, device="cuda", dtype=torch.float32)
         y = torch.empty_like(x)
+        torch.cuda.synchronize()
         y.copy_(x)
         torch.cuda.synchronize()
+        del x, y
         stp = P.State(net, B)
         P.step(net, batch, stp, iters=2, total_iters=T, precision=a.profile_only)
         slots = P.profile_iteration(net, batch, stp, reps=a.reps, total_iters=T, precision=a.profile_only)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_only": a.profile_only, "config": a.config, "B": B,
-                          "per_launch_us": {str(k): round(v, 2) for k, v in slots}}), flush=True)
+        info = P.tuning_info(net, B, a.profile_only)
+        print(json.dumps({"profile_only": a.profile_only, "config": a.config, "B": B, "reps": a.reps,
+                          "slots": [[k, kernel_name(info, k, inst), round(v, 2)] for k, v in slots],
+                          "tuned": info}), flush=True)
         return
 
     st = P.State(net, B)
     res32 = run_form(P, net, batch, st, T, "fp32", a.steps, a.warmup, a.engine)
     b32 = res32["fb"]["bound"].clone()
 
-    # BF16 form: iterations needed to reach the FP32 form's bound (mean gap <= 1e-3)
+    # BF16 form: iterations needed to reach the FP32 form's bound (mean gap <= 1e-3),
+    # searched upward from T in steps of 50
     st16 = P.State(net, B)
     T16 = a.bf16_iters or T
     tries = []
     if not a.quick and a.bf16_iters is None:
-        for t in (T, int(1.5 * T), 2 * T, 3 * T):
+        t = T
+        while t <= 3 * T:
             st16.reset()
             P.step(net, batch, st16, iters=t, total_iters=t, precision="bf16", engine=a.engine)
             bb = P.final_bound(net, batch, st16)["bound"]
             gap = (b32 - bb).mean().item()
-            tries.append((t, gap))
+            tries.append((t, round(gap, 6)))
             T16 = t
             if gap <= 1e-3:
                 break
+            t += 50
     res16 = run_form(P, net, batch, st16, T16, "bf16", a.steps, a.warmup, a.engine)
     b16 = res16["fb"]["bound"]
     d = (b16 - b32)
@@ -184,6 +239,7 @@ def main():
     head = "bf16"
     slots = prof[head]
     kind, us = max(slots, key=lambda x: x[1])
+    tuned = {p: P.tuning_info(net, B, p) for p in ("fp32", "bf16")}
     nbytes, flops = layer_slot_cost(inst, kind, B, head)
     intensity = flops / max(nbytes, 1)
     ridge = PEAK_TFLOPS[head] * 1e12 / (PEAK_HBM_GBS * 1e9)
@@ -192,8 +248,9 @@ def main():
     else:
         roof = dict(bound="mfma", achieved=flops / (us * 1e-6) / 1e12, peak=PEAK_TFLOPS[head], unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = f"slot {kind} (phase {kind // 100}, layer {kind % 100})"
+    kname = kernel_name(tuned[head], kind, inst)
+    roof["traffic"] = stored_traffic(kname, kind, a.config, B, head)
+    roof["kernel"] = f"{kname}: slot {kind} (phase {kind // 100}, layer {kind % 100})"
     roof["avg_us"] = us
     roof["algorithmic_bytes"] = nbytes
     roof["algorithmic_flops"] = flops
@@ -221,9 +278,15 @@ def main():
                  "frac_within_1e-3": (d.abs() <= 1e-3).float().mean().item(), "search": tries},
         "roofline": roof,
         "per_launch_us": {p: {str(k): round(v, 2) for k, v in prof[p]} for p in prof},
+        "tuned": tuned,
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, T, a.cpu_sample)
+        cb, idx, ob = cpu_baseline(inst, T, a.cpu_sample)
+        out["cpu_baseline"] = cb
+        for p, r in (("fp32", res32), ("bf16", res16)):
+            d = r["fb"]["bound"].cpu()[idx] - ob
+            out[p]["minus_oracle"] = {"mean": d.mean().item(), "max_abs": d.abs().max().item(),
+                                      "subdomains": len(idx), "oracle_iters": T}
     print(json.dumps(out), flush=True)
 
 

@@ -261,14 +261,16 @@ int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, int t
 int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, double* us_layerwise,
                     double* us_resident);
 
-/* Diagnostic: run `reps` ascent iterations (real steps that advance the state,
- * launched without the graph) with a HIP event pair around every kernel launch,
- * and return the average duration in microseconds of each launch slot of one
- * iteration (avg_us, host [max_slots]) with its kind (kinds, host [max_slots]):
- * 100+k = transposed product of layer k fused with the inner minimisation of
- * layer k-1 (phase A), 200+k = inner minimisation of the last hidden layer k,
- * 300+k = forward product of layer k fused with the supergradient and Adam step
- * (phase B).  *n_slots receives the number of slots.  Synchronises `stream`. */
+/* Diagnostic: after one ascent iteration on `st`, time every contraction
+ * launch of the iteration (with its fused epilogue and the tuned
+ * configuration): one warm-up launch, then `reps` back-to-back launches between
+ * a HIP event pair on `stream`.  avg_us (host [max_slots]) receives the average
+ * duration in microseconds and kinds (host [max_slots]) the slot: 100+k =
+ * transposed product of layer k fused with the inner minimisation of layer k-1
+ * (phase A), 300+k = forward product of layer k fused with the supergradient
+ * and Adam step (phase B).  The repeated phase-B launches advance the Adam
+ * state of `st` (a profile is not an ascent).  *n_slots receives the number of
+ * slots.  Synchronises `stream`. */
 int ld_profile_iteration(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opts* opts,
                          int reps, double* avg_us, int* kinds, int max_slots, int* n_slots,
                          hipStream_t stream);

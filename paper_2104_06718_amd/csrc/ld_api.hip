@@ -615,36 +615,6 @@ EpiArgs epi0() {
   return e;
 }
 
-// Optional per-launch timing of one ascent iteration (ld_profile_iteration).
-struct Probe {
-  std::vector<hipEvent_t> ev;
-  std::vector<int> kind;
-  int slot = 0;
-};
-thread_local Probe* g_probe = nullptr;
-
-hipError_t probe_begin(int kind, hipStream_t s) {
-  Probe* p = g_probe;
-  if (!p) return hipSuccess;
-  while ((int)p->ev.size() < 2 * (p->slot + 1)) {
-    hipEvent_t e;
-    hipError_t r = hipEventCreate(&e);
-    if (r != hipSuccess) return r;
-    p->ev.push_back(e);
-  }
-  if ((int)p->kind.size() <= p->slot) p->kind.resize(p->slot + 1);
-  p->kind[p->slot] = kind;
-  return hipEventRecord(p->ev[2 * p->slot], s);
-}
-
-hipError_t probe_end(hipStream_t s) {
-  Probe* p = g_probe;
-  if (!p) return hipSuccess;
-  hipError_t r = hipEventRecord(p->ev[2 * p->slot + 1], s);
-  p->slot++;
-  return r;
-}
-
 // ---------------------------------------------------------------------------
 // argument checks
 // ---------------------------------------------------------------------------
@@ -694,10 +664,9 @@ int prepare_objective(const ld_net* net, const ld_batch* bt, Workspace& ws, int 
   return LD_OK;
 }
 
-// Fork/join of the independent layer jobs of a phase (nothing is forked while a
-// per-launch profile is being taken).
+// Fork/join of the independent layer jobs of a phase.
 constexpr int kSide = 2;
-bool forking(const ld_state* st) { return st != nullptr && st->side[0] != nullptr && g_probe == nullptr; }
+bool forking(const ld_state* st) { return st != nullptr && st->side[0] != nullptr; }
 hipError_t fork_begin(const ld_state* st, hipStream_t s) {
   if (!forking(st)) return hipSuccess;
   hipError_t e = hipEventRecord(st->ev_fork, s);
@@ -772,19 +741,15 @@ int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Work
     const Layer& L = net->L[k - 1];
     const EpiArgs e = epi_phase_a(net, bt, rho, ws, mma, tau, want_val, t_dev, adam, o, k);
     const hipStream_t sk = fork_stream(fk, s, k - 1);
-    LD_HIP(probe_begin(100 + k, sk));
     LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, sk));
-    LD_HIP(probe_end(sk));
   }
   LD_HIP(fork_end(fk, s));
   if (o != nullptr) return LD_OK;
   // last hidden layer: constant coefficient -W_n^T c
   const int k = n - 1;
-  LD_HIP(probe_begin(200 + k, s));
   LD_HIP(launch_inner_min_const(B, width(net, k), ws.gconst, rho[k - 1], bt->l[k - 1], bt->u[k - 1],
                                 net->L[k - 1].bias, bias_div(net, k), tau, ws.xb[k],
                                 want_val ? ws.val[k] : nullptr, nullptr, nullptr, 0, 0, 0, 0, 0, 0, s));
-  LD_HIP(probe_end(s));
   return LD_OK;
 }
 
@@ -872,9 +837,7 @@ int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts
     const Layer& L = net->L[k - 1];
     const EpiArgs e = epi_phase_b(net, bt, st, o, k);
     const hipStream_t sk = fork_stream(st, s, k - 1);
-    LD_HIP(probe_begin(300 + k, sk));
     LD_HIP(run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), st->ws, k - 1, sk));
-    LD_HIP(probe_end(sk));
   }
   LD_HIP(fork_end(st, s));
   return LD_OK;
@@ -1648,37 +1611,46 @@ int ld_profile_iteration(const ld_net* net, const ld_batch* bt, ld_state* st, co
   LD_TRY(check_step_args(net, bt, st, o));
   if (reps <= 0 || !avg_us || !kinds || !n_slots || max_slots <= 0) return fail(LD_E_ARG, "bad profile arguments");
   LD_TRY(ensure_initialised(net, bt, st, o, s));
-  Probe probe;
-  std::vector<double> acc;
-  int rc = LD_OK;
-  for (int r = 0; r < reps && rc == LD_OK; ++r) {
-    probe.slot = 0;
-    g_probe = &probe;
-    rc = iteration(net, bt, st, o, s);
-    g_probe = nullptr;
-    st->t_host += 1;
-    if (rc != LD_OK) break;
-    if (hipStreamSynchronize(s) != hipSuccess) {
-      rc = fail(LD_E_DEVICE, "stream synchronisation failed");
-      break;
+  const int n = net->n, B = bt->B, mma = o->precision == LD_BF16 ? 1 : 0;
+  LD_TRY(iteration(net, bt, st, o, s));  // x* of every layer in the operand precision
+  st->t_host += 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  LD_HIP(hipEventCreate(&e0));
+  LD_HIP(hipEventCreate(&e1));
+  struct EventGuard {
+    hipEvent_t a, b;
+    ~EventGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
     }
-    acc.resize(probe.slot, 0.0);
-    for (int i = 0; i < probe.slot; ++i) {
+  } eguard{e0, e1};
+  std::vector<const float*> rho(st->rho.begin(), st->rho.end());
+  int ns = 0;
+  for (int dir = 1; dir >= 0; --dir)
+    for (int k = 1; k <= n - 1 && ns < max_slots; ++k) {
+      const Job& J = dir ? net->L[k - 1].tr : net->L[k - 1].fwd;
+      const Tile t = pick_tile(net, k - 1, dir, B, mma);
+      auto launch = [&]() -> int {
+        if (dir == 1) {
+          const EpiArgs e = epi_phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, nullptr, nullptr, nullptr, k);
+          LD_HIP(run_job(J, B, rho[k - 1], 0, mma, e, t, st->ws, k - 1, s));
+        } else {
+          const EpiArgs e = epi_phase_b(net, bt, st, o, k);
+          LD_HIP(run_job(J, B, st->ws.xs[k - 1], mma, mma, e, t, st->ws, k - 1, s));
+        }
+        return LD_OK;
+      };
+      LD_TRY(launch());  // warm-up
+      LD_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) LD_TRY(launch());
+      LD_HIP(hipEventRecord(e1, s));
+      LD_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, probe.ev[2 * i], probe.ev[2 * i + 1]) != hipSuccess) {
-        rc = fail(LD_E_DEVICE, "event timing failed");
-        break;
-      }
-      acc[i] += 1000.0 * ms;
+      LD_HIP(hipEventElapsedTime(&ms, e0, e1));
+      avg_us[ns] = 1000.0 * ms / reps;
+      kinds[ns] = (dir ? 100 : 300) + k;
+      ++ns;
     }
-  }
-  for (hipEvent_t e : probe.ev) (void)hipEventDestroy(e);
-  if (rc != LD_OK) return rc;
-  const int ns = std::min((int)acc.size(), max_slots);
-  for (int i = 0; i < ns; ++i) {
-    avg_us[i] = acc[i] / reps;
-    kinds[i] = probe.kind[i];
-  }
   *n_slots = ns;
   return LD_OK;
 }
