@@ -172,7 +172,9 @@ int ld_init_duals(const ld_net* net, const ld_batch* batch, int init, int precis
  * pointers [B, n_k].  `precision` selects the operand type of the
  * contractions (the inner minimisation and the sum are FP32/FP64 regardless).
  * Ties of the inner minimisation are broken towards the larger xhat_B within
- * the relative band `tie_tau` (0 = exact argmin); the value is exact. */
+ * the relative band `tie_tau` (0 = exact argmin); the value is exact.
+ * Uses a workspace owned by the net: calls on one net must not overlap on
+ * different streams (serialise them, or use one net per stream). */
 int ld_dual_eval(const ld_net* net, const ld_batch* batch, const float* const* rho,
                  double* q, float* const* supergrad, int precision, float tie_tau,
                  hipStream_t stream);
@@ -230,35 +232,42 @@ int ld_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opt
  * pieces of at least 64.  The fastest configuration of each contraction is
  * kept for (net, batch->B, opts->precision); then `opts` is used to time a
  * 20-step ascent with each engine and the faster one becomes the choice of
- * LD_ENGINE_AUTO.  Replaces earlier choices for the same (B, precision).
+ * LD_ENGINE_AUTO (the layer-wise engine is timed with its phases forked onto
+ * three streams and in sequence, and the faster mode is kept for every
+ * layer-wise call with this B and precision).  Replaces earlier choices for
+ * the same (B, precision).
  * Synchronises `stream`; allocates and frees its scratch state.  Only the
  * precision, tie_tau, Adam constants and total_iters of `opts` are used. */
 int ld_autotune(const ld_net* net, const ld_batch* batch, const ld_opts* opts, hipStream_t stream);
 
 /* The tuned configuration of the contraction of hidden layer k (1..n-1) in
  * direction dir (0: forward W_k x, 1: transposed W_k^T rho_k) for (B,
- * precision): column tiles per wave, K splits, form (0: GEMM + col2im, 1:
- * stride-class gather; convs only) and its measured time in microseconds
- * (host outputs).  LD_E_STATE if nothing was tuned for (B, precision). */
-int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, int* tn, int* splits, int* form,
-                    double* us);
+ * precision): 16-column tiles per wave, waves of a block along K and blocks
+ * along K (fully-connected only; else 1), form (0: GEMM + col2im, 1:
+ * stride-class gather; transposed strided convs only) and its measured time in
+ * microseconds (host outputs).  LD_E_STATE if nothing was tuned for (B,
+ * precision). */
+int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, int* tn, int* kwaves, int* splits,
+                    int* form, double* us);
 
 /* The candidate configurations the autotuner times for the contraction of
  * hidden layer k in direction dir at batch size B: up to max_count entries
- * written to tn, splits, form (host arrays); *count receives the number of
- * candidates. */
-int ld_tile_candidates(const ld_net* net, int B, int k, int dir, int* tn, int* splits, int* form, int max_count,
-                       int* count);
+ * written to tn, kwaves, splits, form (host arrays); *count receives the
+ * number of candidates. */
+int ld_tile_candidates(const ld_net* net, int B, int k, int dir, int* tn, int* kwaves, int* splits, int* form,
+                       int max_count, int* count);
 
 /* Pin the configuration of one contraction for (B, precision), e.g. to restore
  * a stored tuning; it must be one of ld_tile_candidates (else LD_E_ARG).
  * Not thread-safe against concurrent calls on the same net. */
-int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, int tn, int splits, int form);
+int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, int tn, int kwaves, int splits, int form);
 
-/* The engine chosen by the autotuner for (B, precision) and the measured time
- * per iteration of each engine in microseconds (us_resident = 0 when the
- * resident engine does not fit).  LD_E_STATE if nothing was tuned. */
-int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, double* us_layerwise,
+/* The engine chosen by the autotuner for (B, precision), whether the
+ * layer-wise engine runs the independent layer jobs of a phase concurrently on
+ * forked streams (1) or in sequence (0), and the measured time per iteration of
+ * each engine in microseconds (us_resident = 0 when the resident engine does
+ * not fit).  LD_E_STATE if nothing was tuned. */
+int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, int* concurrent, double* us_layerwise,
                     double* us_resident);
 
 /* Diagnostic: after one ascent iteration on `st`, time every contraction

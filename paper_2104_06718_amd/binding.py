@@ -95,10 +95,10 @@ def load_library(path: Optional[str] = None):
     lib.ld_dual_eval.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
     lib.ld_step.argtypes = [V, P(ld_batch), V, P(ld_opts), V]
     lib.ld_autotune.argtypes = [V, P(ld_batch), P(ld_opts), V]
-    lib.ld_tuned_config.argtypes = [V, I, I, I, I, P(I), P(I), P(I), P(ctypes.c_double)]
-    lib.ld_tuned_engine.argtypes = [V, I, I, P(I), P(ctypes.c_double), P(ctypes.c_double)]
-    lib.ld_tile_candidates.argtypes = [V, I, I, I, P(I), P(I), P(I), I, P(I)]
-    lib.ld_set_tuned_config.argtypes = [V, I, I, I, I, I, I, I]
+    lib.ld_tuned_config.argtypes = [V, I, I, I, I, P(I), P(I), P(I), P(I), P(ctypes.c_double)]
+    lib.ld_tuned_engine.argtypes = [V, I, I, P(I), P(I), P(ctypes.c_double), P(ctypes.c_double)]
+    lib.ld_tile_candidates.argtypes = [V, I, I, I, P(I), P(I), P(I), P(I), I, P(I)]
+    lib.ld_set_tuned_config.argtypes = [V, I, I, I, I, I, I, I, I]
     lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
     for name in EXPORTED:
         getattr(lib, name)
@@ -280,40 +280,42 @@ def autotune(net: Net, batch: Batch, total_iters=500, lr0=1e-2, lr_end=1e-4, bet
 
 def tuning_info(net: Net, B: int, precision="fp32"):
     """Tuned engine and per-contraction configuration for (B, precision), or None."""
-    eng, ul, ur = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
-    rc = net.lib.ld_tuned_engine(net.handle, int(B), _PREC[precision], ctypes.byref(eng), ctypes.byref(ul),
-                                 ctypes.byref(ur))
+    eng, conc, ul, ur = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    rc = net.lib.ld_tuned_engine(net.handle, int(B), _PREC[precision], ctypes.byref(eng), ctypes.byref(conc),
+                                 ctypes.byref(ul), ctypes.byref(ur))
     if rc == LD_E_STATE:
         return None
     _check(rc)
     names = {v: k for k, v in _ENGINE.items()}
-    out = dict(engine=names[eng.value], us_per_iter_layerwise=ul.value, us_per_iter_resident=ur.value, layers=[])
-    tn, sp, fm, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    out = dict(engine=names[eng.value], concurrent_phases=bool(conc.value), us_per_iter_layerwise=ul.value,
+               us_per_iter_resident=ur.value, layers=[])
+    tn, kw, sp, fm, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     for k in range(1, len(net.widths) - 1):
         for d, dname in ((1, "transposed"), (0, "forward")):
             _check(net.lib.ld_tuned_config(net.handle, int(B), _PREC[precision], k, d, ctypes.byref(tn),
-                                           ctypes.byref(sp), ctypes.byref(fm), ctypes.byref(us)))
-            out["layers"].append(dict(layer=k, dir=dname, tn=tn.value, splits=sp.value, form=fm.value,
-                                      us=us.value))
+                                           ctypes.byref(kw), ctypes.byref(sp), ctypes.byref(fm), ctypes.byref(us)))
+            out["layers"].append(dict(layer=k, dir=dname, tn=tn.value, kwaves=kw.value, splits=sp.value,
+                                      form=fm.value, us=us.value))
     return out
 
 
 def tile_candidates(net: Net, B: int, k: int, direction: str):
-    """Candidate (tn, splits, form) configurations of a contraction (direction
-    'forward' or 'transposed' of hidden layer k)."""
+    """Candidate (tn, kwaves, splits, form) configurations of a contraction
+    (direction 'forward' or 'transposed' of hidden layer k)."""
     d = 1 if direction == "transposed" else 0
     cnt = ctypes.c_int()
-    _check(net.lib.ld_tile_candidates(net.handle, int(B), int(k), d, None, None, None, 0, ctypes.byref(cnt)))
+    _check(net.lib.ld_tile_candidates(net.handle, int(B), int(k), d, None, None, None, None, 0, ctypes.byref(cnt)))
     n = cnt.value
-    tn, sp, fm = (ctypes.c_int * max(n, 1))(), (ctypes.c_int * max(n, 1))(), (ctypes.c_int * max(n, 1))()
-    _check(net.lib.ld_tile_candidates(net.handle, int(B), int(k), d, tn, sp, fm, n, ctypes.byref(cnt)))
-    return [(tn[i], sp[i], fm[i]) for i in range(n)]
+    arrs = [(ctypes.c_int * max(n, 1))() for _ in range(4)]
+    _check(net.lib.ld_tile_candidates(net.handle, int(B), int(k), d, *arrs, n, ctypes.byref(cnt)))
+    return [tuple(a[i] for a in arrs) for i in range(n)]
 
 
-def set_tuned_config(net: Net, B: int, precision: str, k: int, direction: str, tn: int, splits: int, form: int):
+def set_tuned_config(net: Net, B: int, precision: str, k: int, direction: str, tn: int, kwaves: int, splits: int,
+                     form: int):
     d = 1 if direction == "transposed" else 0
-    _check(net.lib.ld_set_tuned_config(net.handle, int(B), _PREC[precision], int(k), d, int(tn), int(splits),
-                                       int(form)))
+    _check(net.lib.ld_set_tuned_config(net.handle, int(B), _PREC[precision], int(k), d, int(tn), int(kwaves),
+                                       int(splits), int(form)))
 
 
 def _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine="auto"):

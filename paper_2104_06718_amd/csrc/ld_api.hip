@@ -61,6 +61,7 @@ uint16_t host_f2bf(float f) {
 // One contraction of a layer: one GemmGeom per stride class (M is set per launch).
 struct Job {
   std::vector<GemmGeom> geoms;
+  const GemmGeom* dev = nullptr;  // device copy of geoms
   bool has_col = false;   // transposed strided conv: dense GEMM + col2im form
   ColGeom col;
 };
@@ -108,8 +109,9 @@ struct ld_net {
   // autotuned launch configurations: (layer, dir, B, mma) -> tile and its time (us)
   std::map<std::tuple<int, int, int, int>, Tile> tiles;
   std::map<std::tuple<int, int, int, int>, double> tile_us;
-  // autotuned engine: (B, mma) -> {engine, us per iteration layer-wise, resident (0: does not fit)}
-  std::map<std::pair<int, int>, std::array<double, 3>> engines;
+  // autotuned engine: (B, mma) -> {engine, us per iteration layer-wise (best of forked and
+  // sequential phases), resident (0: does not fit), phases forked (1) or not (0)}
+  std::map<std::pair<int, int>, std::array<double, 4>> engines;
   int tune_gen = 0;  // bumped whenever a tuned choice changes (part of the graph key)
   std::mutex mu;
 };
@@ -133,7 +135,12 @@ struct ld_state {
   // the layer jobs of one phase are independent: they run on the caller's stream
   // and two more, forked and joined around each phase
   hipStream_t side[2] = {nullptr, nullptr};
+  int fork = 1;  // fork the phases onto the side streams (tuned per batch size and precision)
   hipEvent_t ev_fork = nullptr;
+  // recorded after the last work enqueued on the state's memory and graph; waited
+  // on before the graph is replaced or the state is freed (a graph exec or a
+  // buffer must not be released while kernels that use it are in flight)
+  hipEvent_t done = nullptr;
   hipEvent_t ev_join[2] = {nullptr, nullptr};
 };
 
@@ -446,8 +453,8 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
     }
   if ((int)L.tr.geoms.size() > 9) return fail(LD_E_UNSUPPORTED, "conv stride above 3 is not supported");
   LD_TRY(build_col(net, L, W));
-  if (conv_lds_bytes(L.fwd.geoms.data(), 1) > 160 * 1024 ||
-      conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size()) > 160 * 1024)
+  if (conv_lds_bytes(L.fwd.geoms.data(), 1, 1, 0) > 160 * 1024 ||
+      conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size(), 1, 0) > 160 * 1024)
     return fail(LD_E_UNSUPPORTED, "conv maps too large for the LDS images of one subdomain");
   return LD_OK;
 }
@@ -460,6 +467,8 @@ int width(const ld_net* net, int k) { return k == 0 ? net->n0 : net->L[k - 1].n_
 int ws_alloc(const ld_net* net, Workspace& ws, int B) {
   if (ws.base && ws.B >= B) return LD_OK;
   if (ws.base) {
+    // work enqueued earlier (on any stream) may still use the old buffers
+    LD_HIP(hipDeviceSynchronize());
     (void)hipFree(ws.base);
     ws.base = nullptr;
   }
@@ -556,7 +565,8 @@ Tile heuristic_tile(const Job& J, int B) {
 
 // Launch configurations the autotuner times for a contraction: the column tile
 // widths that the output width allows, both forms of a transposed strided conv,
-// and for fully-connected products every split of K into pieces of >= 64.
+// and for fully-connected products every split of K over waves and blocks into
+// pieces of >= 64.
 std::vector<Tile> tile_candidates(const Job& J, int B) {
   std::vector<Tile> c;
   const int N = J.geoms[0].N, K = J.geoms[0].K;
@@ -565,11 +575,15 @@ std::vector<Tile> tile_candidates(const Job& J, int B) {
   if (N > 32) tns.push_back(4);
   if (job_is_conv(J)) {
     if (J.has_col) c.push_back(Tile{1, 1, 1, 0});
-    for (int tn : tns) c.push_back(Tile{1, tn, 1, J.has_col ? 1 : 0});
+    for (int tn : tns)
+      if (conv_lds_bytes(J.geoms.data(), (int)J.geoms.size(), tn, 0) <= 160 * 1024)
+        c.push_back(Tile{1, tn, 1, J.has_col ? 1 : 0});
   } else {
     for (int tn : tns)
-      for (int sp : {1, 2, 4, 8, 16, 32})
-        if (sp == 1 || (K / sp >= 64 && fc_splits(J, B, tn, sp) == sp)) c.push_back(Tile{1, tn, sp, 0});
+      for (int kw : {1, 2, 4})
+        for (int sp : {1, 2, 4, 8, 16, 32})
+          if ((sp == 1 || fc_splits(J, B, tn, sp) == sp) && (sp * kw == 1 || K / (sp * kw) >= 64))
+            c.push_back(Tile{kw, tn, sp, 0});
   }
   return c;
 }
@@ -602,9 +616,9 @@ hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, 
     g[i].M = B * g[i].HWq;
   }
   if (J.has_col && t.form == 0) return launch_convT(J.col, B, (const float*)src, mma, e, s);
-  if (job_is_conv(J)) return launch_conv(g, nc, B, src, src_bf16, mma, e, t.tn, s);
+  if (job_is_conv(J)) return launch_conv(g, J.dev, nc, B, src, src_bf16, mma, e, t.tn, s);
   SplitArgs sp{fc_splits(J, B, t.tn, t.splits), ws.partial + (size_t)slot * kPartialLayer, ws.counters};
-  return launch_fc(g[0], src, src_bf16, mma, e, t.tn, sp, s);
+  return launch_fc(g[0], src, src_bf16, mma, e, t.tn, sp, t.tm, s);
 }
 
 EpiArgs epi0() {
@@ -666,7 +680,7 @@ int prepare_objective(const ld_net* net, const ld_batch* bt, Workspace& ws, int 
 
 // Fork/join of the independent layer jobs of a phase.
 constexpr int kSide = 2;
-bool forking(const ld_state* st) { return st != nullptr && st->side[0] != nullptr; }
+bool forking(const ld_state* st) { return st != nullptr && st->side[0] != nullptr && st->fork != 0; }
 hipError_t fork_begin(const ld_state* st, hipStream_t s) {
   if (!forking(st)) return hipSuccess;
   hipError_t e = hipEventRecord(st->ev_fork, s);
@@ -844,6 +858,7 @@ int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts
 }
 
 void destroy_graph(ld_state* st) {
+  if (st->gexec && st->done) (void)hipEventSynchronize(st->done);
   if (st->gexec) (void)hipGraphExecDestroy(st->gexec);
   if (st->graph) (void)hipGraphDestroy(st->graph);
   st->gexec = nullptr;
@@ -852,7 +867,7 @@ void destroy_graph(ld_state* st) {
   st->gchunk = 0;
 }
 
-std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int chunk, int net_tune_gen) {
+std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int chunk, int net_tune_gen, int fork) {
   std::vector<double> k;
   auto P = [&](const void* p) { k.push_back((double)(uintptr_t)p); };
   k.push_back(bt->B);
@@ -873,6 +888,7 @@ std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int c
   k.push_back(o->tie_tau);
   k.push_back(chunk);
   k.push_back(net_tune_gen);
+  k.push_back(fork);
   return k;
 }
 
@@ -1132,6 +1148,8 @@ int ld_create_net(const ld_layer* layers, int n_layers, ld_net** out) {
         return cleanup(fail(LD_E_DEVICE, "geometry copy failed"));
       L.fwd_dev = (const GemmGeom*)pg;
       L.tr_dev = (const GemmGeom*)pg + 1;
+      L.fwd.dev = L.fwd_dev;
+      L.tr.dev = L.tr_dev;
     }
     net->L.push_back(L);
   }
@@ -1205,7 +1223,8 @@ int ld_state_create(const ld_net* net, int B, ld_state** out) {
     return rc;
   }
   bool ok = hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&st->done, hipEventDisableTiming) == hipSuccess;
   for (int i = 0; i < 2 && ok; ++i)
     ok = hipStreamCreateWithFlags(&st->side[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&st->ev_join[i], hipEventDisableTiming) == hipSuccess;
@@ -1219,6 +1238,7 @@ int ld_state_create(const ld_net* net, int B, ld_state** out) {
 
 void ld_state_destroy(ld_state* st) {
   if (!st) return;
+  if (st->done) (void)hipEventSynchronize(st->done);
   destroy_graph(st);
   if (st->cap) (void)hipStreamDestroy(st->cap);
   for (int i = 0; i < 2; ++i) {
@@ -1226,6 +1246,7 @@ void ld_state_destroy(ld_state* st) {
     if (st->ev_join[i]) (void)hipEventDestroy(st->ev_join[i]);
   }
   if (st->ev_fork) (void)hipEventDestroy(st->ev_fork);
+  if (st->done) (void)hipEventDestroy(st->done);
   if (st->ws.base) (void)hipFree(st->ws.base);
   if (st->base) (void)hipFree(st->base);
   delete st;
@@ -1245,6 +1266,7 @@ int ld_state_set_rho(ld_state* st, const float* const* rho, hipStream_t s) {
   LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
   st->t_host = 0;
   st->initialized = false;  // q(rho^0) is computed by the next ld_step (init = LD_INIT_GIVEN)
+  LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
 }
 
@@ -1256,6 +1278,7 @@ int ld_state_get_rho(const ld_state* st, float* const* rho, hipStream_t s) {
     if (!rho[k - 1]) return fail(LD_E_ARG, "rho[k] is NULL");
     LD_HIP(hipMemcpyAsync(rho[k - 1], st->rho[k - 1], (size_t)st->B * width(net, k) * 4, hipMemcpyDeviceToDevice, s));
   }
+  LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
 }
 
@@ -1361,11 +1384,12 @@ static int step_impl(const ld_net* net, const ld_batch* bt, ld_state* st, const 
     if (use) {
       LD_TRY(run_resident(net, bt, st, o, R, s));
       st->t_host += o->iters;
+      LD_HIP(hipEventRecord(st->done, s));
       return LD_OK;
     }
   }
   const int chunk = std::min(o->iters, 100);
-  std::vector<double> key = graph_key(bt, o, net->n, chunk, net->tune_gen);
+  std::vector<double> key = graph_key(bt, o, net->n, chunk, net->tune_gen, st->fork);
   if (!st->gexec || key != st->gkey) {
     destroy_graph(st);
     LD_HIP(hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal));
@@ -1391,6 +1415,7 @@ static int step_impl(const ld_net* net, const ld_batch* bt, ld_state* st, const 
   for (int r = 0; r < reps; ++r) LD_HIP(hipGraphLaunch(st->gexec, s));
   for (int i = reps * chunk; i < o->iters; ++i) LD_TRY(iteration(net, bt, st, o, s));
   st->t_host += o->iters;
+  LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
 }
 
@@ -1494,20 +1519,26 @@ static int autotune_impl(const ld_net* net, const ld_batch* bt, const ld_opts* o
     to.engine = engine;
     return step_impl(net, bt, tmp, &to, s);
   };
-  double us_lw = 0, us_res = 0;
-  LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_LAYERWISE); }, s, e0, e1, 1, &us_lw));
+  double us_fork = 0, us_seq = 0, us_res = 0;
+  tmp->fork = 1;
+  LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_LAYERWISE); }, s, e0, e1, 1, &us_fork));
+  tmp->fork = 0;
+  LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_LAYERWISE); }, s, e0, e1, 1, &us_seq));
   if (resident_shape(net, B, mma).S > 0) LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_RESIDENT); }, s, e0, e1, 1, &us_res));
   LD_HIP(hipStreamSynchronize(s));
+  const int fork = us_fork <= us_seq ? 1 : 0;
+  const double us_lw = std::min(us_fork, us_seq);
   const int eng = (us_res > 0 && us_res < us_lw) ? LD_ENGINE_RESIDENT : LD_ENGINE_LAYERWISE;
   std::lock_guard<std::mutex> lk(mnet->mu);
-  mnet->engines[{B, mma}] = {(double)eng, us_lw / T, us_res / T};
+  mnet->engines[{B, mma}] = {(double)eng, us_lw / T, us_res / T, (double)fork};
   return LD_OK;
 }
 
-static int tuned_engine(const ld_net* net, int B, int mma) {
+static int tuned_engine(const ld_net* net, int B, int mma, int* fork = nullptr) {
   ld_net* mnet = const_cast<ld_net*>(net);
   std::lock_guard<std::mutex> lk(mnet->mu);
   auto it = mnet->engines.find({B, mma});
+  if (fork) *fork = it == mnet->engines.end() ? 1 : (int)it->second[3];
   return it == mnet->engines.end() ? -1 : (int)it->second[0];
 }
 
@@ -1516,13 +1547,16 @@ int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* 
   LD_TRY(check_step_args(net, bt, st, o));
   LD_TRY(validate_values(net, bt, st->ws, s));
   ld_opts eo = *o;
+  const int mma = o->precision == LD_BF16 ? 1 : 0;
   if (eo.engine == LD_ENGINE_AUTO && bt->B > 0) {
-    const int mma = o->precision == LD_BF16 ? 1 : 0;
     if (tuned_engine(net, bt->B, mma) < 0) LD_TRY(autotune_impl(net, bt, o, s));
     eo.engine = tuned_engine(net, bt->B, mma);
   }
+  (void)tuned_engine(net, bt->B, mma, &st->fork);
   LD_TRY(ensure_initialised(net, bt, st, &eo, s));
-  return step_impl(net, bt, st, &eo, s);
+  const int rc = step_impl(net, bt, st, &eo, s);
+  LD_HIP(hipEventRecord(st->done, s));
+  return rc;
 }
 
 int ld_autotune(const ld_net* net, const ld_batch* bt, const ld_opts* o, hipStream_t s) {
@@ -1533,10 +1567,10 @@ int ld_autotune(const ld_net* net, const ld_batch* bt, const ld_opts* o, hipStre
   return autotune_impl(net, bt, o, s);
 }
 
-int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, int* tn, int* splits, int* form,
-                    double* us) {
+int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, int* tn, int* kwaves, int* splits,
+                    int* form, double* us) {
   g_err.clear();
-  if (!net || !tn || !splits || !form || !us) return fail(LD_E_ARG, "NULL argument");
+  if (!net || !tn || !kwaves || !splits || !form || !us) return fail(LD_E_ARG, "NULL argument");
   if (k < 1 || k > net->n - 1 || (dir != 0 && dir != 1)) return fail(LD_E_ARG, "layer or direction out of range");
   ld_net* mnet = const_cast<ld_net*>(net);
   std::lock_guard<std::mutex> lk(mnet->mu);
@@ -1544,35 +1578,37 @@ int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, int
   auto it = mnet->tiles.find(key);
   if (it == mnet->tiles.end()) return fail(LD_E_STATE, "no tuned configuration for this batch size and precision");
   *tn = it->second.tn;
+  *kwaves = it->second.tm;
   *splits = it->second.splits;
   *form = it->second.form;
   *us = mnet->tile_us[key];
   return LD_OK;
 }
 
-int ld_tile_candidates(const ld_net* net, int B, int k, int dir, int* tn, int* splits, int* form, int max_count,
-                       int* count) {
+int ld_tile_candidates(const ld_net* net, int B, int k, int dir, int* tn, int* kwaves, int* splits, int* form,
+                       int max_count, int* count) {
   g_err.clear();
-  if (!net || !count || (max_count > 0 && (!tn || !splits || !form))) return fail(LD_E_ARG, "NULL argument");
+  if (!net || !count || (max_count > 0 && (!tn || !kwaves || !splits || !form))) return fail(LD_E_ARG, "NULL argument");
   if (k < 1 || k > net->n - 1 || (dir != 0 && dir != 1) || B < 0) return fail(LD_E_ARG, "layer or direction out of range");
   const Job& J = dir ? net->L[k - 1].tr : net->L[k - 1].fwd;
   const std::vector<Tile> c = tile_candidates(J, B);
   *count = (int)c.size();
   for (int i = 0; i < std::min(max_count, (int)c.size()); ++i) {
     tn[i] = c[i].tn;
+    kwaves[i] = c[i].tm;
     splits[i] = c[i].splits;
     form[i] = c[i].form;
   }
   return LD_OK;
 }
 
-int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, int tn, int splits, int form) {
+int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, int tn, int kwaves, int splits, int form) {
   g_err.clear();
   if (!net) return fail(LD_E_ARG, "NULL argument");
   if (k < 1 || k > net->n - 1 || (dir != 0 && dir != 1) || B < 0) return fail(LD_E_ARG, "layer or direction out of range");
   const Job& J = dir ? net->L[k - 1].tr : net->L[k - 1].fwd;
   for (const Tile& t : tile_candidates(J, B))
-    if (t.tn == tn && t.splits == splits && t.form == form) {
+    if (t.tn == tn && t.tm == kwaves && t.splits == splits && t.form == form) {
       std::lock_guard<std::mutex> lk(net->mu);
       const auto key = std::make_tuple(k - 1, dir, B, precision == LD_BF16 ? 1 : 0);
       net->tiles[key] = t;
@@ -1583,14 +1619,16 @@ int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, int t
   return fail(LD_E_ARG, "not a candidate configuration of this contraction");
 }
 
-int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, double* us_layerwise, double* us_resident) {
+int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, int* concurrent, double* us_layerwise,
+                    double* us_resident) {
   g_err.clear();
-  if (!net || !engine || !us_layerwise || !us_resident) return fail(LD_E_ARG, "NULL argument");
+  if (!net || !engine || !concurrent || !us_layerwise || !us_resident) return fail(LD_E_ARG, "NULL argument");
   ld_net* mnet = const_cast<ld_net*>(net);
   std::lock_guard<std::mutex> lk(mnet->mu);
   auto it = mnet->engines.find({B, precision == LD_BF16 ? 1 : 0});
   if (it == mnet->engines.end()) return fail(LD_E_STATE, "no tuned engine for this batch size and precision");
   *engine = (int)it->second[0];
+  *concurrent = (int)it->second[3];
   *us_layerwise = it->second[1];
   *us_resident = it->second[2];
   return LD_OK;
@@ -1602,6 +1640,7 @@ int ld_state_reset(ld_state* st, hipStream_t s) {
   LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
   st->t_host = 0;
   st->initialized = false;
+  LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
 }
 
@@ -1652,6 +1691,7 @@ int ld_profile_iteration(const ld_net* net, const ld_batch* bt, ld_state* st, co
       ++ns;
     }
   *n_slots = ns;
+  LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
 }
 
@@ -1694,6 +1734,7 @@ int ld_final_bound(const ld_net* net, const ld_batch* bt, const ld_state* cst, d
     }
     if (primal) LD_HIP(launch_cdot(B, net->L[n - 1].n_out, bt->c, x, nullptr, primal, s));
   }
+  LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
 }
 

@@ -80,9 +80,10 @@ struct EpiArgs {
   int total;
 };
 
-// Launch-time configuration of one contraction: tn 16-column MFMA tiles per wave,
-// K split `splits` ways (fully-connected), and for transposed strided convs the
-// form (0: dense GEMM + col2im, 1: stride-class gather).
+// Launch-time configuration of one contraction: tn 16-column MFMA tiles per wave;
+// fully-connected: K split over tm waves of a block and over `splits` blocks;
+// transposed strided convs: the form (0: dense GEMM + col2im, 1: stride-class
+// gather).
 struct Tile {
   int tm, tn, splits, form;
 };
@@ -170,12 +171,13 @@ hipError_t launch_resident(const RPlan& plan, int grid, size_t lds_bytes, int mm
 
 // kernels (ld_kernels.hip)
 // convolution contraction, one block per (subdomain, stride class)
-hipError_t launch_conv(const GemmGeom* geoms, int n_classes, int B, const void* src, int src_bf16,
-                       int mma_bf16, const EpiArgs& e, int tn, hipStream_t s);
-size_t conv_lds_bytes(const GemmGeom* g, int n_classes);
+// geo_dev: device copy of the same class geometries (read into LDS by the kernel)
+hipError_t launch_conv(const GemmGeom* geoms, const GemmGeom* geo_dev, int n_classes, int B, const void* src,
+                       int src_bf16, int mma_bf16, const EpiArgs& e, int tn, hipStream_t s);
+size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16);
 // fully-connected contraction (G.M = B rows), optional split-K
 hipError_t launch_fc(const GemmGeom& g, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e,
-                     int tn, const SplitArgs& sp, hipStream_t s);
+                     int tn, const SplitArgs& sp, int kw, hipStream_t s);
 
 hipError_t launch_inner_min_const(int B, int n, const float* g, const float* rho, const float* lo,
                                   const float* hi, const float* bias, int bias_hw, float tau, float* xb,

@@ -79,9 +79,58 @@ __device__ __forceinline__ void st4_xs(const EpiArgs& E, size_t i0, size_t st, i
   }
 }
 
+// Operands an epilogue reads from device memory, four elements per array (the
+// loads are issued before any arithmetic of the epilogue).
+struct EpiIn {
+  f32x4 a0, a1, a2, a3, a4, a5;
+};
+
 template <bool VEC>
-__device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st, int nv, int b0, int bstep, int col,
-                                          int cstep, const float (&acc)[4]) {
+__device__ __forceinline__ f32x4 ld4v(const float* __restrict__ p, size_t i0, size_t st, int nv) {
+  float t[4];
+  ld4<VEC>(p, i0, st, nv, t);
+  return f32x4{t[0], t[1], t[2], t[3]};
+}
+
+template <bool VEC>
+__device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st, int nv, EpiIn& in) {
+  switch (E.kind) {
+    case EPI_P0:
+    case EPI_CROWN:
+    case EPI_RELU_FWD:
+      in.a0 = ld4v<VEC>(E.lo, i0, st, nv);
+      in.a1 = ld4v<VEC>(E.hi, i0, st, nv);
+      break;
+    case EPI_INNER_MIN:
+      in.a0 = ld4v<VEC>(E.rho, i0, st, nv);
+      in.a1 = ld4v<VEC>(E.lo, i0, st, nv);
+      in.a2 = ld4v<VEC>(E.hi, i0, st, nv);
+      break;
+    case EPI_ADAM:
+      in.a0 = ld4v<VEC>(E.rho_w, i0, st, nv);
+      in.a1 = ld4v<VEC>(E.m, i0, st, nv);
+      in.a2 = ld4v<VEC>(E.v, i0, st, nv);
+      in.a3 = ld4v<VEC>(E.xb_in, i0, st, nv);
+      break;
+    case EPI_ADAM_LAST:
+      in.a0 = ld4v<VEC>(E.rho_w, i0, st, nv);
+      in.a1 = ld4v<VEC>(E.m, i0, st, nv);
+      in.a2 = ld4v<VEC>(E.v, i0, st, nv);
+      in.a3 = ld4v<VEC>(E.gc, i0, st, nv);
+      in.a4 = ld4v<VEC>(E.lo, i0, st, nv);
+      in.a5 = ld4v<VEC>(E.hi, i0, st, nv);
+      break;
+    case EPI_SUPERGRAD:
+      in.a0 = ld4v<VEC>(E.xb_in, i0, st, nv);
+      break;
+    default:
+      break;
+  }
+}
+
+template <bool VEC>
+__device__ __forceinline__ void epi_finish(const EpiArgs& E, size_t i0, size_t st, int nv, int b0, int bstep, int col,
+                                           int cstep, const float (&acc)[4], const EpiIn& in) {
   switch (E.kind) {
     case EPI_STORE: {
       float o[4];
@@ -90,11 +139,9 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
       st4<VEC>(E.out_f, i0, st, nv, o);
     } break;
     case EPI_P0: {
-      float lo[4], hi[4], x[4];
-      ld4<VEC>(E.lo, i0, st, nv, lo);
-      ld4<VEC>(E.hi, i0, st, nv, hi);
+      float x[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = acc[q] >= 0.f ? hi[q] : lo[q];
+      for (int q = 0; q < 4; ++q) x[q] = acc[q] >= 0.f ? in.a1[q] : in.a0[q];
       st4_xs<VEC>(E, i0, st, nv, x);
       if (E.want_val)
 #pragma unroll
@@ -102,27 +149,24 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
           if (VEC || q < nv) E.val[i0 + q * st] = -(double)acc[q] * (double)x[q];
     } break;
     case EPI_INNER_MIN: {
-      float r[4], lo[4], hi[4], xb[4], x[4];
-      ld4<VEC>(E.rho, i0, st, nv, r);
-      ld4<VEC>(E.lo, i0, st, nv, lo);
-      ld4<VEC>(E.hi, i0, st, nv, hi);
+      float xb[4], x[4];
       if (E.want_val) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           double xbd, xd, val;
-          inner_min<double>(r[q], acc[q], lo[q], hi[q], (double)E.tau, xbd, xd, val);
+          inner_min<double>(in.a0[q], acc[q], in.a1[q], in.a2[q], (double)E.tau, xbd, xd, val);
           xb[q] = (float)xbd;
           x[q] = (float)xd;
           if (VEC || q < nv) {
             const double bias = (double)E.bias[(col + q * cstep) / E.bias_div];
-            E.val[i0 + q * st] = val - (double)r[q] * bias;
+            E.val[i0 + q * st] = val - (double)in.a0[q] * bias;
           }
         }
       } else {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           float val;
-          inner_min<float>(r[q], acc[q], lo[q], hi[q], E.tau, xb[q], x[q], val);
+          inner_min<float>(in.a0[q], acc[q], in.a1[q], in.a2[q], E.tau, xb[q], x[q], val);
         }
       }
       st4_xs<VEC>(E, i0, st, nv, x);
@@ -131,22 +175,22 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
     case EPI_ADAM:
     case EPI_ADAM_LAST: {
       float xb[4], rho[4], m[4], v[4];
-      ld4<VEC>(E.rho_w, i0, st, nv, rho);
-      ld4<VEC>(E.m, i0, st, nv, m);
-      ld4<VEC>(E.v, i0, st, nv, v);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        rho[q] = in.a0[q];
+        m[q] = in.a1[q];
+        v[q] = in.a2[q];
+      }
       if (E.kind == EPI_ADAM_LAST) {
         // inner minimisation of the last hidden layer from its constant coefficient
-        float gcv[4], lo[4], hi[4];
-        ld4<VEC>(E.gc, i0, st, nv, gcv);
-        ld4<VEC>(E.lo, i0, st, nv, lo);
-        ld4<VEC>(E.hi, i0, st, nv, hi);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           float x, val;
-          inner_min<float>(rho[q], gcv[q], lo[q], hi[q], E.tau, xb[q], x, val);
+          inner_min<float>(rho[q], in.a3[q], in.a4[q], in.a5[q], E.tau, xb[q], x, val);
         }
       } else {
-        ld4<VEC>(E.xb_in, i0, st, nv, xb);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xb[q] = in.a3[q];
       }
       const float lr = E.adam[0], ibc1 = E.adam[1], ibc2 = E.adam[2], eps = E.adam[3];
       const float b1 = E.adam[4], b2 = E.adam[5];
@@ -156,35 +200,32 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
         const float s = xb[q] - (acc[q] + bias);
         m[q] = b1 * m[q] + (1.f - b1) * s;
         v[q] = b2 * v[q] + (1.f - b2) * (s * s);
-        rho[q] = rho[q] + lr * (m[q] * ibc1) / (sqrtf(v[q] * ibc2) + eps);
+        // hardware square root and reciprocal (1 ulp): the step is a sign-like
+        // quantity of size lr, so their rounding is far below the tie band
+        rho[q] = rho[q] + lr * (m[q] * ibc1) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v[q] * ibc2) + eps);
       }
       st4<VEC>(E.m, i0, st, nv, m);
       st4<VEC>(E.v, i0, st, nv, v);
       st4<VEC>(E.rho_w, i0, st, nv, rho);
     } break;
     case EPI_SUPERGRAD: {
-      float xb[4], o[4];
-      ld4<VEC>(E.xb_in, i0, st, nv, xb);
+      float o[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = xb[q] - (acc[q] + E.bias[col + q * cstep]);
+      for (int q = 0; q < 4; ++q) o[q] = in.a0[q] - (acc[q] + E.bias[col + q * cstep]);
       st4<VEC>(E.out_f, i0, st, nv, o);
     } break;
     case EPI_CROWN: {
-      float lo[4], hi[4], o[4];
-      ld4<VEC>(E.lo, i0, st, nv, lo);
-      ld4<VEC>(E.hi, i0, st, nv, hi);
+      float o[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = crown_dual(acc[q], lo[q], hi[q]);
+      for (int q = 0; q < 4; ++q) o[q] = crown_dual(acc[q], in.a0[q], in.a1[q]);
       st4<VEC>(E.out_f, i0, st, nv, o);
     } break;
     case EPI_RELU_FWD: {
-      float lo[4], hi[4], o[4];
-      ld4<VEC>(E.lo, i0, st, nv, lo);
-      ld4<VEC>(E.hi, i0, st, nv, hi);
+      float o[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float y = acc[q] + E.bias[col + q * cstep];
-        if ((VEC || q < nv) && !(y >= lo[q] && y <= hi[q])) E.flag[b0 + q * bstep] = 0;
+        if ((VEC || q < nv) && !(y >= in.a0[q] && y <= in.a1[q])) E.flag[b0 + q * bstep] = 0;
         o[q] = fmaxf(y, 0.f);
       }
       st4<VEC>(E.out_f, i0, st, nv, o);
@@ -200,68 +241,182 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
   }
 }
 
+template <bool VEC>
+__device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st, int nv, int b0, int bstep, int col,
+                                          int cstep, const float (&acc)[4]) {
+  EpiIn in{};
+  epi_load<VEC>(E, i0, st, nv, in);
+  epi_finish<VEC>(E, i0, st, nv, b0, bstep, col, cstep, acc, in);
+}
+
 // ---------------------------------------------------------------------------
 // Convolution contraction of one subdomain per block, all stride classes.
-//  1. the block copies the subdomain's source map into a zero-padded LDS image
-//     (so the gather needs no bounds tests);
-//  2. waves compute 16-pixel x 16-column MFMA tiles of every class, reading A
-//     from the image and B (packed weights) from memory, and write the results
-//     into an LDS copy of the destination map (classes land on their pixels);
+//  1. staging, one barrier: the block zeroes the padding border of an LDS image
+//     of the subdomain's source map and fills its interior (all global loads of
+//     a thread are issued before its LDS writes); the packed weights of every
+//     class and the gather offsets go to LDS as well;
+//  2. waves compute 16-pixel x 16-column MFMA tiles of every class, A gathered
+//     from the image, B read from the staged weights, and write the results into
+//     an LDS copy of the destination map (classes land on their pixels);
 //  3. all threads stream the epilogue over the destination map in order,
 //     16 bytes per access.
 // ---------------------------------------------------------------------------
 constexpr int kConvWaves = 8;
 constexpr int kConvThreads = 64 * kConvWaves;
 
+// e / d for 0 <= e < 2^22 with inv ~ 1/d: float estimate, then one correction
+__device__ __forceinline__ int fdiv(int e, int d, float inv) {
+  int q = (int)((float)e * inv);
+  const int r = e - q * d;
+  if (r < 0)
+    --q;
+  else if (r >= d)
+    ++q;
+  return q;
+}
+
+// LDS words holding the class geometries (copied from device memory at staging)
+constexpr int kGeoWords = (int)((sizeof(GemmGeom) + 15) / 16 * 4);
+
 template <bool MMA_BF16, bool SRC_BF16, int TN>
-__global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, const void* __restrict__ src_v, EpiArgs E,
-                                                         int img_floats, int dst_hw4, int kp_max) {
+__global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, const GemmGeom* __restrict__ geo_dev,
+                                                         const void* __restrict__ src_v, EpiArgs E,
+                                                         int img_floats, int dst_hw4, int kp_max, int n_eff,
+                                                         int bstride) {
   using M = Mma<MMA_BF16>;
-  constexpr int KS = M::KS, VPL = M::VPL;
+  typedef typename M::BFrag BFrag;
+  typedef typename std::conditional<MMA_BF16, bf16_t, float>::type WT;
+  constexpr int KS = M::KS, VPL = M::VPL, EPV = 16 / (int)sizeof(WT);
   extern __shared__ float lds[];
   const GemmGeom& G0 = P.g[0];
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
-  const int C = G0.src_n / (G0.src_H * G0.src_W);
-  const int HW = G0.src_H * G0.src_W;
-  const int LHW = G0.LH * G0.LW;
-  float* img = lds;                      // [C][LH][LW]
-  float* outp = lds + img_floats;        // [dst_n]
-  int* kofs = (int*)(outp + G0.dst_n);   // [n classes][kp_max]
+  const int H = G0.src_H, W = G0.src_W, HW = H * W;
+  const int C = G0.src_n / HW;
+  int* geo = reinterpret_cast<int*>(lds);                  // [n classes][kGeoWords]
+  float* img = lds + P.n * kGeoWords;                      // [C][LH][LW]
+  float* outp = img + img_floats;                          // [dst_n]
+  int* kofs = reinterpret_cast<int*>(outp + G0.dst_n);     // [n classes][kp_max]
+  WT* wB = reinterpret_cast<WT*>(lds + ((P.n * kGeoWords + img_floats + G0.dst_n + P.n * kp_max + 3) & ~3));  // [n classes][n_eff][bstride], 16-byte aligned
 
   adam_tick(E);
-  // 1. zero image, then copy the source map (coalesced) into its interior
-  for (int e = tid; e < img_floats; e += kConvThreads) img[e] = 0.f;
-  for (int c = 0; c < P.n; ++c)
-    for (int k = tid; k < P.g[c].Kp; k += kConvThreads) kofs[c * kp_max + k] = P.g[c].ktab_lds[k];
-  __syncthreads();
-  if (SRC_BF16) {
-    const bf16_t* src = (const bf16_t*)src_v + (size_t)b * G0.src_n;
-    for (int e = tid; e < G0.src_n; e += kConvThreads) {
-      const int c = e / HW;
-      const int rem = e - c * HW;
-      const int iy = rem / G0.src_W;
-      const int ix = rem - iy * G0.src_W;
-      img[c * LHW + (iy + G0.pad_t) * G0.LW + ix + G0.pad_l] = bf2f(src[e]);
+  for (int i = tid; i < P.n * kGeoWords; i += kConvThreads) {
+    const int c = i / kGeoWords, w = i - c * kGeoWords;
+    if (w * 4 < (int)sizeof(GemmGeom)) geo[i] = reinterpret_cast<const int*>(geo_dev + c)[w];
+  }
+  // 1a. source map into the image interior: loads first, then LDS writes
+  {
+    const size_t sbase = (size_t)b * G0.src_n;
+    const float inv_w = 1.0f / (float)W, inv_h = 1.0f / (float)H;
+    if ((W & 3) == 0) {
+      const int n4 = G0.src_n >> 2;
+      constexpr int U = 4;
+      for (int i0 = tid; i0 < n4; i0 += U * kConvThreads) {
+        float v[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * kConvThreads;
+          if (i < n4) {
+            if (SRC_BF16) {
+              const uint2 raw = *reinterpret_cast<const uint2*>((const bf16_t*)src_v + sbase + 4 * (size_t)i);
+              v[u][0] = bf2f((bf16_t)(raw.x & 0xffffu));
+              v[u][1] = bf2f((bf16_t)(raw.x >> 16));
+              v[u][2] = bf2f((bf16_t)(raw.y & 0xffffu));
+              v[u][3] = bf2f((bf16_t)(raw.y >> 16));
+            } else {
+              const float4 f = *reinterpret_cast<const float4*>((const float*)src_v + sbase + 4 * (size_t)i);
+              v[u][0] = f.x;
+              v[u][1] = f.y;
+              v[u][2] = f.z;
+              v[u][3] = f.w;
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * kConvThreads;
+          if (i < n4) {
+            const int e = 4 * i;
+            const int row = fdiv(e, W, inv_w);  // c*H + y
+            const int x = e - row * W;
+            const int c = fdiv(row, H, inv_h);
+            const int y = row - c * H;
+            float* d = img + (c * G0.LH + y + G0.pad_t) * G0.LW + x + G0.pad_l;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) d[q] = v[u][q];
+          }
+        }
+      }
+    } else {
+      for (int e = tid; e < G0.src_n; e += kConvThreads) {
+        const float v = SRC_BF16 ? bf2f(((const bf16_t*)src_v)[sbase + e]) : ((const float*)src_v)[sbase + e];
+        const int row = fdiv(e, W, inv_w);
+        const int x = e - row * W;
+        const int c = fdiv(row, H, inv_h);
+        const int y = row - c * H;
+        img[(c * G0.LH + y + G0.pad_t) * G0.LW + x + G0.pad_l] = v;
+      }
     }
-  } else {
-    const float* src = (const float*)src_v + (size_t)b * G0.src_n;
-    for (int e = tid; e < G0.src_n; e += kConvThreads) {
-      const int c = e / HW;
-      const int rem = e - c * HW;
-      const int iy = rem / G0.src_W;
-      const int ix = rem - iy * G0.src_W;
-      img[c * LHW + (iy + G0.pad_t) * G0.LW + ix + G0.pad_l] = src[e];
+  }
+  // 1b. zero the padding border (disjoint from the interior)
+  {
+    const float inv_lh = 1.0f / (float)G0.LH;
+    for (int rr = tid; rr < C * G0.LH; rr += kConvThreads) {
+      const int c = fdiv(rr, G0.LH, inv_lh);
+      const int yy = rr - c * G0.LH;
+      float* row = img + rr * G0.LW;
+      if (yy < G0.pad_t || yy >= G0.pad_t + H) {
+        for (int x = 0; x < G0.LW; ++x) row[x] = 0.f;
+      } else {
+        for (int x = 0; x < G0.pad_l; ++x) row[x] = 0.f;
+        for (int x = G0.pad_l + W; x < G0.LW; ++x) row[x] = 0.f;
+      }
+    }
+  }
+  // 1c. gather offsets and weights of every class
+  for (int c = 0; c < P.n; ++c) {
+    const GemmGeom& G = P.g[c];
+    for (int k = tid; k < G.Kp; k += kConvThreads) kofs[c * kp_max + k] = G.ktab_lds[k];
+    const int vr = G.Kp / EPV;
+    const float inv_vr = 1.0f / (float)vr;
+    const uint4* srcw = reinterpret_cast<const uint4*>(MMA_BF16 ? (const void*)G.Bh : (const void*)G.Bf);
+    for (int e = tid; e < n_eff * vr; e += kConvThreads) {
+      const int row = fdiv(e, vr, inv_vr);
+      const int v = e - row * vr;
+      *reinterpret_cast<uint4*>(wB + ((size_t)c * n_eff + row) * bstride + v * EPV) = srcw[(size_t)row * vr + v];
     }
   }
   __syncthreads();
 
-  // 2. MFMA tiles of every class into the LDS destination map
+  // 2. MFMA tiles of every class into the LDS destination map (class geometry
+  //    read from LDS, uniform across the block)
   int tiles_before = 0;
   for (int cl = 0; cl < P.n; ++cl) {
-    const GemmGeom& G = P.g[cl];
+    const GemmGeom* Gl = reinterpret_cast<const GemmGeom*>(geo + cl * kGeoWords);
+    struct {
+      int HWq, Wq, iy_mul, iy_off, ix_mul, ix_off, pad_t, pad_l, LW, K, N, dst_HW, dst_W, oy_mul, oy_off, ox_mul, ox_off;
+    } G;
+    G.HWq = __builtin_amdgcn_readfirstlane(Gl->HWq);
+    G.Wq = __builtin_amdgcn_readfirstlane(Gl->Wq);
+    G.iy_mul = __builtin_amdgcn_readfirstlane(Gl->iy_mul);
+    G.iy_off = __builtin_amdgcn_readfirstlane(Gl->iy_off);
+    G.ix_mul = __builtin_amdgcn_readfirstlane(Gl->ix_mul);
+    G.ix_off = __builtin_amdgcn_readfirstlane(Gl->ix_off);
+    G.pad_t = __builtin_amdgcn_readfirstlane(Gl->pad_t);
+    G.pad_l = __builtin_amdgcn_readfirstlane(Gl->pad_l);
+    G.LW = __builtin_amdgcn_readfirstlane(Gl->LW);
+    G.K = __builtin_amdgcn_readfirstlane(Gl->K);
+    G.N = __builtin_amdgcn_readfirstlane(Gl->N);
+    G.dst_HW = __builtin_amdgcn_readfirstlane(Gl->dst_HW);
+    G.dst_W = __builtin_amdgcn_readfirstlane(Gl->dst_W);
+    G.oy_mul = __builtin_amdgcn_readfirstlane(Gl->oy_mul);
+    G.oy_off = __builtin_amdgcn_readfirstlane(Gl->oy_off);
+    G.ox_mul = __builtin_amdgcn_readfirstlane(Gl->ox_mul);
+    G.ox_off = __builtin_amdgcn_readfirstlane(Gl->ox_off);
     const int* ko = kofs + cl * kp_max;
+    const WT* wc = wB + (size_t)cl * n_eff * bstride;
+    const float inv_wq = 1.0f / (float)G.Wq;
     const int ntiles = (G.HWq + 15) >> 4;
     const int nct = (G.N + 16 * TN - 1) / (16 * TN);
     // distribute (tile, column chunk) pairs over the waves, continuing the rotation across classes
@@ -272,12 +427,13 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       const int tile = w / nct;
       const int nc = (w - tile * nct) * 16 * TN;
       const int p = min(tile * 16 + r, G.HWq - 1);
-      const int yq = p / G.Wq;
+      const int yq = fdiv(p, G.Wq, inv_wq);
       const int xq = p - yq * G.Wq;
       const int lb = (yq * G.iy_mul + G.iy_off + G.pad_t) * G.LW + xq * G.ix_mul + G.ix_off + G.pad_l;
       f32x4 acc[TN];
 #pragma unroll
       for (int t = 0; t < TN; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
       for (int k0 = 0; k0 < G.K; k0 += KS) {
         const int kl = k0 + VPL * g;
         float a[VPL];
@@ -285,22 +441,27 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
         for (int j = 0; j < VPL; ++j) a[j] = img[lb + ko[kl + j]];
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
-          const typename M::BFrag bf = M::loadB(G, (size_t)(nc + 16 * t + r) * G.Kp + kl);
+          const BFrag bf = *reinterpret_cast<const BFrag*>(wc + (size_t)(nc + 16 * t + r) * bstride + kl);
           M::mma(a, bf, acc[t]);
         }
       }
+      // the lane's four rows are consecutive pixels of the class grid
+      const int p0 = tile * 16 + 4 * g;
+      int yy = fdiv(p0, G.Wq, inv_wq);
+      int xx = p0 - yy * G.Wq;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int pq = tile * 16 + 4 * g + q;
-        if (pq < G.HWq) {
-          const int yy = pq / G.Wq;
-          const int xx = pq - yy * G.Wq;
+        if (p0 + q < G.HWq) {
           const int j0 = (yy * G.oy_mul + G.oy_off) * G.dst_W + xx * G.ox_mul + G.ox_off;
 #pragma unroll
           for (int t = 0; t < TN; ++t) {
             const int col = nc + 16 * t + r;
             if (col < G.N) outp[col * G.dst_HW + j0] = acc[t][q];
           }
+        }
+        if (++xx == G.Wq) {
+          xx = 0;
+          ++yy;
         }
       }
     }
@@ -310,15 +471,16 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
 
   // 3. epilogue over the destination map in memory order
   const size_t base = (size_t)b * G0.dst_n;
+  const float inv_dhw = 1.0f / (float)G0.dst_HW;
   if (dst_hw4) {
     for (int e = 4 * tid; e < G0.dst_n; e += 4 * kConvThreads) {
-      const int col = e / G0.dst_HW;  // channel (four consecutive neurons share it)
+      const int col = fdiv(e, G0.dst_HW, inv_dhw);  // channel (four consecutive neurons share it)
       float v4[4] = {outp[e], outp[e + 1], outp[e + 2], outp[e + 3]};
       epilogue4<true>(E, base + e, 1, 4, b, 0, col, 0, v4);
     }
   } else {
     for (int e = tid; e < G0.dst_n; e += kConvThreads) {
-      const int col = e / G0.dst_HW;
+      const int col = fdiv(e, G0.dst_HW, inv_dhw);
       float v4[4] = {outp[e], 0.f, 0.f, 0.f};
       epilogue4<false>(E, base + e, 1, 1, b, 0, col, 0, v4);
     }
@@ -329,30 +491,38 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
 // Fully-connected contraction, computed transposed: C[neuron][subdomain] =
 // sum_k W[neuron][k] X[subdomain][k], with both operands loaded register-direct
 // (packed weights as the row operand).  A wave owns 16*TN neurons x 16
-// subdomains; a block is 4 waves along subdomains.  A lane ends with four
+// subdomains; a block is 4 waves along subdomains times kw waves along K, whose
+// partial sums meet in LDS and are added in wave order.  A lane ends with four
 // consecutive neurons of one subdomain, so the epilogue moves 16 bytes per
 // access.  With splits > 1 (long K) every block writes a partial tile and
 // fc_split_reduce adds the partials in split order, then runs the epilogue
 // (deterministic, no cross-block synchronisation).
 // ---------------------------------------------------------------------------
 template <int TN, bool MMA_BF16, bool SRC_BF16>
-__global__ __launch_bounds__(256) void fc_kernel(GemmGeom G, const void* __restrict__ src_v, EpiArgs E, SplitArgs S) {
+__global__ __launch_bounds__(1024) void fc_kernel(GemmGeom G, const void* __restrict__ src_v, EpiArgs E, SplitArgs S,
+                                                  int kw) {
   using M = Mma<MMA_BF16>;
   constexpr int KS = M::KS, VPL = M::VPL;
+  extern __shared__ float red[];  // [kw-1][4 waves][TN][4][64]
   adam_tick(E);
   const int split = blockIdx.z;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int wv = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int wave = wv & 3, wk = wv >> 2;        // position along subdomains, along K
   const int b0 = blockIdx.x * 64 + wave * 16;   // subdomains of this wave
   const int n0 = blockIdx.y * (16 * TN);        // neurons of this block
   const int ksteps = (G.K + KS - 1) / KS;
   const int per = (ksteps + S.splits - 1) / S.splits;
-  const int kbeg = split * per * KS;
-  const int kend = min(G.K, (split + 1) * per * KS);
+  const int sbeg = split * per;
+  const int send = min(ksteps, (split + 1) * per);
+  const int perw = (send - sbeg + kw - 1) / kw;
+  const int kbeg = (sbeg + wk * perw) * KS;
+  const int kend = min(G.K, min(send, sbeg + (wk + 1) * perw) * KS);
 
   const int sub = b0 + r;
   const bool svalid = sub < G.M;
   const size_t base = (size_t)(svalid ? sub : 0) * G.src_n;
+  const bool vec_out = (G.dst_n & 3) == 0;
   const float* srcf = (const float*)src_v;
   const bf16_t* srch = (const bf16_t*)src_v;
   const bool vec = (G.src_n % (SRC_BF16 ? 8 : 4)) == 0;
@@ -398,6 +568,24 @@ __global__ __launch_bounds__(256) void fc_kernel(GemmGeom G, const void* __restr
       M::mma_wx(w, x, acc[t]);
     }
   }
+  if (kw > 1) {
+    float* mine = red + (size_t)((wk - 1) * 4 + wave) * (TN * 4 * 64);
+    if (wk > 0) {
+#pragma unroll
+      for (int t = 0; t < TN; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mine[(t * 4 + q) * 64 + lane] = acc[t][q];
+    }
+    __syncthreads();
+    if (wk > 0) return;
+    for (int w = 1; w < kw; ++w) {
+      const float* other = red + (size_t)((w - 1) * 4 + wave) * (TN * 4 * 64);
+#pragma unroll
+      for (int t = 0; t < TN; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[t][q] += other[(t * 4 + q) * 64 + lane];
+    }
+  }
   // lane holds neurons n0 + 16t + 4g + q of subdomain b0 + r
   if (S.splits > 1) {
     // partial tile layout [tile][split][16*TN neurons][64 subdomains]
@@ -410,7 +598,6 @@ __global__ __launch_bounds__(256) void fc_kernel(GemmGeom G, const void* __restr
     return;
   }
   if (!svalid) return;
-  const bool vec_out = (G.dst_n & 3) == 0;
 #pragma unroll
   for (int t = 0; t < TN; ++t) {
     const int j = n0 + 16 * t + 4 * g;
@@ -439,10 +626,12 @@ __global__ __launch_bounds__(256) void fc_split_reduce(GemmGeom G, EpiArgs E, Sp
   const int bx = sub >> 6, by = j / cols;
   const size_t tile_id = (size_t)by * gx + bx;
   const float* pt = S.partial + tile_id * S.splits * (64 * cols) + (size_t)(j - by * cols) * 64 + (sub & 63);
+  EpiIn in{};
+  epi_load<false>(E, (size_t)sub * G.dst_n + j, 1, 1, in);
   float v = 0.f;
   for (int sp = 0; sp < S.splits; ++sp) v += pt[(size_t)sp * (64 * cols)];
   float v4[4] = {v, 0.f, 0.f, 0.f};
-  epilogue4<false>(E, (size_t)sub * G.dst_n + j, 1, 1, sub, 0, j, 1, v4);
+  epi_finish<false>(E, (size_t)sub * G.dst_n + j, 1, 1, sub, 0, j, 1, v4, in);
 }
 
 // ---------------------------------------------------------------------------
@@ -459,19 +648,29 @@ static int max_kp(const GemmGeom* g, int n) {
   return m;
 }
 
-size_t conv_lds_bytes(const GemmGeom* g, int n_classes) {
-  return ((size_t)conv_img_floats(g[0]) + g[0].dst_n + (size_t)n_classes * max_kp(g, n_classes)) * 4;
+// weight rows staged per class (the columns rounded up to whole tiles) and their
+// LDS row stride (padded by 16 bytes against bank conflicts)
+static int conv_n_eff(const GemmGeom& g, int tn) { return (g.N + 16 * tn - 1) / (16 * tn) * 16 * tn; }
+static int conv_bstride(const GemmGeom* g, int n, int mma_bf16) { return max_kp(g, n) + (mma_bf16 ? 8 : 4); }
+
+size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16) {
+  const size_t wbytes = (size_t)n_classes * conv_n_eff(g[0], tn) * conv_bstride(g, n_classes, mma_bf16) * (mma_bf16 ? 2 : 4);
+  return (((size_t)n_classes * kGeoWords + conv_img_floats(g[0]) + g[0].dst_n + (size_t)n_classes * max_kp(g, n_classes) +
+           3) & ~(size_t)3) * 4 +
+         wbytes;
 }
 
 template <int TN>
-static hipError_t launch_conv_tn(const GemmPack& P, int B, const void* src, int src_bf16, int mma_bf16,
-                                 const EpiArgs& e, hipStream_t s) {
+static hipError_t launch_conv_tn(const GemmPack& P, const GemmGeom* geo_dev, int B, const void* src, int src_bf16,
+                                 int mma_bf16, const EpiArgs& e, hipStream_t s) {
   const GemmGeom& G = P.g[0];
-  const size_t lds = conv_lds_bytes(P.g, P.n);
+  const size_t lds = conv_lds_bytes(P.g, P.n, TN, mma_bf16);
   const int kpm = max_kp(P.g, P.n);
   const int img = conv_img_floats(G);
   const int hw4 = (G.dst_HW % 4) == 0;
+  const int neff = conv_n_eff(G, TN), bst = conv_bstride(P.g, P.n, mma_bf16);
   dim3 grid(B), block(kConvThreads);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     (void)hipFuncSetAttribute((const void*)conv_plane_kernel<true, true, TN>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -482,42 +681,47 @@ static hipError_t launch_conv_tn(const GemmPack& P, int B, const void* src, int 
   }
   if (mma_bf16) {
     if (src_bf16)
-      hipLaunchKernelGGL((conv_plane_kernel<true, true, TN>), grid, block, lds, s, P, src, e, img, hw4, kpm);
+      hipLaunchKernelGGL((conv_plane_kernel<true, true, TN>), grid, block, lds, s, P, geo_dev, src, e, img, hw4, kpm, neff,
+                         bst);
     else
-      hipLaunchKernelGGL((conv_plane_kernel<true, false, TN>), grid, block, lds, s, P, src, e, img, hw4, kpm);
+      hipLaunchKernelGGL((conv_plane_kernel<true, false, TN>), grid, block, lds, s, P, geo_dev, src, e, img, hw4, kpm, neff,
+                         bst);
   } else {
     if (src_bf16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((conv_plane_kernel<false, false, TN>), grid, block, lds, s, P, src, e, img, hw4, kpm);
+    hipLaunchKernelGGL((conv_plane_kernel<false, false, TN>), grid, block, lds, s, P, geo_dev, src, e, img, hw4, kpm, neff,
+                         bst);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_conv(const GemmGeom* geoms, int n, int B, const void* src, int src_bf16, int mma_bf16,
-                       const EpiArgs& e, int tn, hipStream_t s) {
+hipError_t launch_conv(const GemmGeom* geoms, const GemmGeom* geo_dev, int n, int B, const void* src, int src_bf16,
+                       int mma_bf16, const EpiArgs& e, int tn, hipStream_t s) {
   GemmPack P;
   if (n <= 0 || n > kMaxClasses) return hipErrorInvalidValue;
   P.n = n;
   for (int i = 0; i < n; ++i) P.g[i] = geoms[i];
   if (B == 0 || P.g[0].N == 0) return hipSuccess;
-  if (tn == 1) return launch_conv_tn<1>(P, B, src, src_bf16, mma_bf16, e, s);
-  if (tn == 2) return launch_conv_tn<2>(P, B, src, src_bf16, mma_bf16, e, s);
-  if (tn == 4) return launch_conv_tn<4>(P, B, src, src_bf16, mma_bf16, e, s);
+  if (tn == 1) return launch_conv_tn<1>(P, geo_dev, B, src, src_bf16, mma_bf16, e, s);
+  if (tn == 2) return launch_conv_tn<2>(P, geo_dev, B, src, src_bf16, mma_bf16, e, s);
+  if (tn == 4) return launch_conv_tn<4>(P, geo_dev, B, src, src_bf16, mma_bf16, e, s);
   return hipErrorInvalidValue;
 }
 
 template <int TN>
 static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e,
-                               const SplitArgs& sp, hipStream_t s) {
+                               const SplitArgs& sp, int kw, hipStream_t s) {
   const int gx = (G.M + 63) / 64, gy = (G.N + 16 * TN - 1) / (16 * TN);  // subdomain blocks, neuron blocks
-  dim3 grid(gx, gy, sp.splits), block(256);
+  if (kw != 1 && kw != 2 && kw != 4) return hipErrorInvalidValue;
+  dim3 grid(gx, gy, sp.splits), block(256 * kw);
+  const size_t lds = (size_t)(kw - 1) * 4 * TN * 4 * 64 * 4;
   if (mma_bf16) {
     if (src_bf16)
-      hipLaunchKernelGGL((fc_kernel<TN, true, true>), grid, block, 0, s, G, src, e, sp);
+      hipLaunchKernelGGL((fc_kernel<TN, true, true>), grid, block, lds, s, G, src, e, sp, kw);
     else
-      hipLaunchKernelGGL((fc_kernel<TN, true, false>), grid, block, 0, s, G, src, e, sp);
+      hipLaunchKernelGGL((fc_kernel<TN, true, false>), grid, block, lds, s, G, src, e, sp, kw);
   } else {
     if (src_bf16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((fc_kernel<TN, false, false>), grid, block, 0, s, G, src, e, sp);
+    hipLaunchKernelGGL((fc_kernel<TN, false, false>), grid, block, lds, s, G, src, e, sp, kw);
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess || sp.splits <= 1) return err;
@@ -529,11 +733,11 @@ static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16,
 }
 
 hipError_t launch_fc(const GemmGeom& G, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e, int tn,
-                     const SplitArgs& sp, hipStream_t s) {
+                     const SplitArgs& sp, int kw, hipStream_t s) {
   if (G.M == 0 || G.N == 0) return hipSuccess;
-  if (tn == 1) return launch_fc_tn<1>(G, src, src_bf16, mma_bf16, e, sp, s);
-  if (tn == 2) return launch_fc_tn<2>(G, src, src_bf16, mma_bf16, e, sp, s);
-  if (tn == 4) return launch_fc_tn<4>(G, src, src_bf16, mma_bf16, e, sp, s);
+  if (tn == 1) return launch_fc_tn<1>(G, src, src_bf16, mma_bf16, e, sp, kw, s);
+  if (tn == 2) return launch_fc_tn<2>(G, src, src_bf16, mma_bf16, e, sp, kw, s);
+  if (tn == 4) return launch_fc_tn<4>(G, src, src_bf16, mma_bf16, e, sp, kw, s);
   return hipErrorInvalidValue;
 }
 
@@ -547,17 +751,6 @@ hipError_t launch_fc(const GemmGeom& G, const void* src, int src_bf16, int mma_b
 //     thread.
 // ---------------------------------------------------------------------------
 constexpr int kTThreads = 256;
-
-// e / d for 0 <= e < 2^22 with inv = 1/d: float estimate, then one correction
-__device__ __forceinline__ int fdiv(int e, int d, float inv) {
-  int q = (int)((float)e * inv);
-  const int r = e - q * d;
-  if (r < 0)
-    --q;
-  else if (r >= d)
-    ++q;
-  return q;
-}
 
 template <bool BF>
 __global__ __launch_bounds__(kTThreads) void convT_kernel(ColGeom G, const float* __restrict__ rho, EpiArgs E) {

@@ -417,7 +417,7 @@ __global__ __launch_bounds__(kRThreads) void resident_kernel(RPlan P) {
                   xb[s * P.xb_stride + j + q] - (GX[s * P.gx_stride + j + q] + L.bias[(j + q) / L.out_hw]);
               mo[q] = b1 * f4(m4, q) + (1.f - b1) * sg;
               vo[q] = b2 * f4(v4, q) + (1.f - b2) * (sg * sg);
-              ro[q] = f4(r4, q) + lr * (mo[q] * ibc1) / (sqrtf(vo[q] * ibc2) + eps);
+              ro[q] = f4(r4, q) + lr * (mo[q] * ibc1) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vo[q] * ibc2) + eps);
             }
             stg4(L.m + gi, make_float4(mo[0], mo[1], mo[2], mo[3]));
             stg4(L.v + gi, make_float4(vo[0], vo[1], vo[2], vo[3]));
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(kRThreads) void resident_kernel(RPlan P) {
             const float v = b2 * L.v[gi] + (1.f - b2) * (sg * sg);
             L.m[gi] = m;
             L.v[gi] = v;
-            L.rho[gi] = L.rho[gi] + lr * (m * ibc1) / (sqrtf(v * ibc2) + eps);
+            L.rho[gi] = L.rho[gi] + lr * (m * ibc1) * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v * ibc2) + eps);
           }
         }
       }
