@@ -228,10 +228,11 @@ int ld_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opt
  * candidate configuration of every contraction of the ascent iteration with
  * its real epilogue: 16-column tiles per wave (1, 2, 4 as the width allows),
  * for transposed strided convs the dense GEMM + col2im form against the
- * stride-class gather form, for fully-connected products each split of K into
- * pieces of at least 64.  The fastest configuration of each contraction is
- * kept for (net, batch->B, opts->precision); then `opts` is used to time a
- * 20-step ascent with each engine and the faster one becomes the choice of
+ * stride-class gather form, for fully-connected products the shape of a block
+ * (waves along subdomains and along K) and splits of K over blocks.  The
+ * fastest configuration of each contraction is kept for (net, batch->B,
+ * opts->precision); then `opts` is used to time a 20-step ascent with each
+ * engine and the faster one becomes the choice of
  * LD_ENGINE_AUTO (the layer-wise engine is timed with its phases forked onto
  * three streams and in sequence, and the faster mode is kept for every
  * layer-wise call with this B and precision).  Replaces earlier choices for
@@ -240,27 +241,30 @@ int ld_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opt
  * precision, tie_tau, Adam constants and total_iters of `opts` are used. */
 int ld_autotune(const ld_net* net, const ld_batch* batch, const ld_opts* opts, hipStream_t stream);
 
+/* Launch configuration of one contraction (what the autotuner chooses). */
+typedef struct ld_tile {
+  int tn;      /* 16-column MFMA tiles per wave */
+  int mwaves;  /* fully-connected: waves of a block along subdomains (16 each); convs: 1 */
+  int kwaves;  /* fully-connected: waves of a block along K (partial sums added in LDS); convs: 1 */
+  int splits;  /* fully-connected: blocks along K (partials added by a second kernel); convs: 1 */
+  int form;    /* transposed strided convs: 0 dense GEMM + col2im, 1 stride-class gather; else 0 */
+} ld_tile;
+
 /* The tuned configuration of the contraction of hidden layer k (1..n-1) in
  * direction dir (0: forward W_k x, 1: transposed W_k^T rho_k) for (B,
- * precision): 16-column tiles per wave, waves of a block along K and blocks
- * along K (fully-connected only; else 1), form (0: GEMM + col2im, 1:
- * stride-class gather; transposed strided convs only) and its measured time in
- * microseconds (host outputs).  LD_E_STATE if nothing was tuned for (B,
- * precision). */
-int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, int* tn, int* kwaves, int* splits,
-                    int* form, double* us);
+ * precision) and its measured time in microseconds (host outputs).
+ * LD_E_STATE if nothing was tuned for (B, precision). */
+int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, ld_tile* tile, double* us);
 
 /* The candidate configurations the autotuner times for the contraction of
  * hidden layer k in direction dir at batch size B: up to max_count entries
- * written to tn, kwaves, splits, form (host arrays); *count receives the
- * number of candidates. */
-int ld_tile_candidates(const ld_net* net, int B, int k, int dir, int* tn, int* kwaves, int* splits, int* form,
-                       int max_count, int* count);
+ * written to `out` (host array); *count receives the number of candidates. */
+int ld_tile_candidates(const ld_net* net, int B, int k, int dir, ld_tile* out, int max_count, int* count);
 
 /* Pin the configuration of one contraction for (B, precision), e.g. to restore
  * a stored tuning; it must be one of ld_tile_candidates (else LD_E_ARG).
  * Not thread-safe against concurrent calls on the same net. */
-int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, int tn, int kwaves, int splits, int form);
+int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, const ld_tile* tile);
 
 /* The engine chosen by the autotuner for (B, precision), whether the
  * layer-wise engine runs the independent layer jobs of a phase concurrently on

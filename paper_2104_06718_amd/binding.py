@@ -64,6 +64,14 @@ class ld_opts(ctypes.Structure):
 _lib = None
 
 
+class ld_tile(ctypes.Structure):
+    _fields_ = [("tn", ctypes.c_int), ("mwaves", ctypes.c_int), ("kwaves", ctypes.c_int), ("splits", ctypes.c_int),
+                ("form", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 def load_library(path: Optional[str] = None):
     """Load the built shared library (raises if it has not been built)."""
     global _lib
@@ -95,10 +103,10 @@ def load_library(path: Optional[str] = None):
     lib.ld_dual_eval.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
     lib.ld_step.argtypes = [V, P(ld_batch), V, P(ld_opts), V]
     lib.ld_autotune.argtypes = [V, P(ld_batch), P(ld_opts), V]
-    lib.ld_tuned_config.argtypes = [V, I, I, I, I, P(I), P(I), P(I), P(I), P(ctypes.c_double)]
+    lib.ld_tuned_config.argtypes = [V, I, I, I, I, P(ld_tile), P(ctypes.c_double)]
     lib.ld_tuned_engine.argtypes = [V, I, I, P(I), P(I), P(ctypes.c_double), P(ctypes.c_double)]
-    lib.ld_tile_candidates.argtypes = [V, I, I, I, P(I), P(I), P(I), P(I), I, P(I)]
-    lib.ld_set_tuned_config.argtypes = [V, I, I, I, I, I, I, I, I]
+    lib.ld_tile_candidates.argtypes = [V, I, I, I, P(ld_tile), I, P(I)]
+    lib.ld_set_tuned_config.argtypes = [V, I, I, I, I, P(ld_tile)]
     lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
     for name in EXPORTED:
         getattr(lib, name)
@@ -289,33 +297,32 @@ def tuning_info(net: Net, B: int, precision="fp32"):
     names = {v: k for k, v in _ENGINE.items()}
     out = dict(engine=names[eng.value], concurrent_phases=bool(conc.value), us_per_iter_layerwise=ul.value,
                us_per_iter_resident=ur.value, layers=[])
-    tn, kw, sp, fm, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    t, us = ld_tile(), ctypes.c_double()
     for k in range(1, len(net.widths) - 1):
         for d, dname in ((1, "transposed"), (0, "forward")):
-            _check(net.lib.ld_tuned_config(net.handle, int(B), _PREC[precision], k, d, ctypes.byref(tn),
-                                           ctypes.byref(kw), ctypes.byref(sp), ctypes.byref(fm), ctypes.byref(us)))
-            out["layers"].append(dict(layer=k, dir=dname, tn=tn.value, kwaves=kw.value, splits=sp.value,
-                                      form=fm.value, us=us.value))
+            _check(net.lib.ld_tuned_config(net.handle, int(B), _PREC[precision], k, d, ctypes.byref(t),
+                                           ctypes.byref(us)))
+            out["layers"].append(dict(layer=k, dir=dname, us=us.value, **t.as_dict()))
     return out
 
 
 def tile_candidates(net: Net, B: int, k: int, direction: str):
-    """Candidate (tn, kwaves, splits, form) configurations of a contraction
-    (direction 'forward' or 'transposed' of hidden layer k)."""
+    """Candidate launch configurations (dicts with tn, mwaves, kwaves, splits,
+    form) of a contraction (direction 'forward' or 'transposed' of hidden layer k)."""
     d = 1 if direction == "transposed" else 0
     cnt = ctypes.c_int()
-    _check(net.lib.ld_tile_candidates(net.handle, int(B), int(k), d, None, None, None, None, 0, ctypes.byref(cnt)))
+    _check(net.lib.ld_tile_candidates(net.handle, int(B), int(k), d, None, 0, ctypes.byref(cnt)))
     n = cnt.value
-    arrs = [(ctypes.c_int * max(n, 1))() for _ in range(4)]
-    _check(net.lib.ld_tile_candidates(net.handle, int(B), int(k), d, *arrs, n, ctypes.byref(cnt)))
-    return [tuple(a[i] for a in arrs) for i in range(n)]
+    arr = (ld_tile * max(n, 1))()
+    _check(net.lib.ld_tile_candidates(net.handle, int(B), int(k), d, arr, n, ctypes.byref(cnt)))
+    return [arr[i].as_dict() for i in range(n)]
 
 
-def set_tuned_config(net: Net, B: int, precision: str, k: int, direction: str, tn: int, kwaves: int, splits: int,
-                     form: int):
+def set_tuned_config(net: Net, B: int, precision: str, k: int, direction: str, tile: dict):
+    """Pin one contraction's configuration (a dict from tile_candidates)."""
     d = 1 if direction == "transposed" else 0
-    _check(net.lib.ld_set_tuned_config(net.handle, int(B), _PREC[precision], int(k), d, int(tn), int(kwaves),
-                                       int(splits), int(form)))
+    t = ld_tile(**{f: int(tile[f]) for f, _ in ld_tile._fields_})
+    _check(net.lib.ld_set_tuned_config(net.handle, int(B), _PREC[precision], int(k), d, ctypes.byref(t)))
 
 
 def _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine="auto"):

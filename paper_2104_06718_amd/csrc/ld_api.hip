@@ -557,6 +557,7 @@ int fc_splits(const Job& J, int B, int tn, int want) {
 Tile heuristic_tile(const Job& J, int B) {
   Tile t;
   t.tm = 1;
+  t.wm = 4;
   t.form = 0;
   t.tn = job_tn(J, B);
   t.splits = job_is_conv(J) ? 1 : fc_splits(J, B, t.tn, 0);
@@ -574,16 +575,21 @@ std::vector<Tile> tile_candidates(const Job& J, int B) {
   if (N > 16) tns.push_back(2);
   if (N > 32) tns.push_back(4);
   if (job_is_conv(J)) {
-    if (J.has_col) c.push_back(Tile{1, 1, 1, 0});
+    if (J.has_col) c.push_back(Tile{1, 1, 1, 0, 1});
     for (int tn : tns)
       if (conv_lds_bytes(J.geoms.data(), (int)J.geoms.size(), tn, 0) <= 160 * 1024)
-        c.push_back(Tile{1, tn, 1, J.has_col ? 1 : 0});
+        c.push_back(Tile{1, tn, 1, J.has_col ? 1 : 0, 1});
   } else {
+    // one block along K: every (wm, kw) shape of up to 16 waves; several blocks
+    // along K (a second kernel adds the partials): 4 waves along subdomains
+    for (int tn : tns)
+      for (int wm : {1, 2, 4})
+        for (int kw : {1, 2, 4, 8})
+          if (wm * kw <= 16 && (kw == 1 || K / kw >= 32)) c.push_back(Tile{kw, tn, 1, 0, wm});
     for (int tn : tns)
       for (int kw : {1, 2, 4})
-        for (int sp : {1, 2, 4, 8, 16, 32})
-          if ((sp == 1 || fc_splits(J, B, tn, sp) == sp) && (sp * kw == 1 || K / (sp * kw) >= 64))
-            c.push_back(Tile{kw, tn, sp, 0});
+        for (int sp : {2, 4, 8, 16, 32})
+          if (fc_splits(J, B, tn, sp) == sp && K / (sp * kw) >= 64) c.push_back(Tile{kw, tn, sp, 0, 4});
   }
   return c;
 }
@@ -618,7 +624,7 @@ hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, 
   if (J.has_col && t.form == 0) return launch_convT(J.col, B, (const float*)src, mma, e, s);
   if (job_is_conv(J)) return launch_conv(g, J.dev, nc, B, src, src_bf16, mma, e, t.tn, s);
   SplitArgs sp{fc_splits(J, B, t.tn, t.splits), ws.partial + (size_t)slot * kPartialLayer, ws.counters};
-  return launch_fc(g[0], src, src_bf16, mma, e, t.tn, sp, t.tm, s);
+  return launch_fc(g[0], src, src_bf16, mma, e, t.tn, sp, std::max(1, t.wm), t.tm, s);
 }
 
 EpiArgs epi0() {
@@ -1567,48 +1573,47 @@ int ld_autotune(const ld_net* net, const ld_batch* bt, const ld_opts* o, hipStre
   return autotune_impl(net, bt, o, s);
 }
 
-int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, int* tn, int* kwaves, int* splits,
-                    int* form, double* us) {
+static void to_ld_tile(const Tile& t, ld_tile* o) {
+  o->tn = t.tn;
+  o->mwaves = t.wm;
+  o->kwaves = t.tm;
+  o->splits = t.splits;
+  o->form = t.form;
+}
+
+int ld_tuned_config(const ld_net* net, int B, int precision, int k, int dir, ld_tile* tile, double* us) {
   g_err.clear();
-  if (!net || !tn || !kwaves || !splits || !form || !us) return fail(LD_E_ARG, "NULL argument");
+  if (!net || !tile || !us) return fail(LD_E_ARG, "NULL argument");
   if (k < 1 || k > net->n - 1 || (dir != 0 && dir != 1)) return fail(LD_E_ARG, "layer or direction out of range");
   ld_net* mnet = const_cast<ld_net*>(net);
   std::lock_guard<std::mutex> lk(mnet->mu);
   const auto key = std::make_tuple(k - 1, dir, B, precision == LD_BF16 ? 1 : 0);
   auto it = mnet->tiles.find(key);
   if (it == mnet->tiles.end()) return fail(LD_E_STATE, "no tuned configuration for this batch size and precision");
-  *tn = it->second.tn;
-  *kwaves = it->second.tm;
-  *splits = it->second.splits;
-  *form = it->second.form;
+  to_ld_tile(it->second, tile);
   *us = mnet->tile_us[key];
   return LD_OK;
 }
 
-int ld_tile_candidates(const ld_net* net, int B, int k, int dir, int* tn, int* kwaves, int* splits, int* form,
-                       int max_count, int* count) {
+int ld_tile_candidates(const ld_net* net, int B, int k, int dir, ld_tile* out, int max_count, int* count) {
   g_err.clear();
-  if (!net || !count || (max_count > 0 && (!tn || !kwaves || !splits || !form))) return fail(LD_E_ARG, "NULL argument");
+  if (!net || !count || (max_count > 0 && !out)) return fail(LD_E_ARG, "NULL argument");
   if (k < 1 || k > net->n - 1 || (dir != 0 && dir != 1) || B < 0) return fail(LD_E_ARG, "layer or direction out of range");
   const Job& J = dir ? net->L[k - 1].tr : net->L[k - 1].fwd;
   const std::vector<Tile> c = tile_candidates(J, B);
   *count = (int)c.size();
-  for (int i = 0; i < std::min(max_count, (int)c.size()); ++i) {
-    tn[i] = c[i].tn;
-    kwaves[i] = c[i].tm;
-    splits[i] = c[i].splits;
-    form[i] = c[i].form;
-  }
+  for (int i = 0; i < std::min(max_count, (int)c.size()); ++i) to_ld_tile(c[i], out + i);
   return LD_OK;
 }
 
-int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, int tn, int kwaves, int splits, int form) {
+int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, const ld_tile* tile) {
   g_err.clear();
-  if (!net) return fail(LD_E_ARG, "NULL argument");
+  if (!net || !tile) return fail(LD_E_ARG, "NULL argument");
   if (k < 1 || k > net->n - 1 || (dir != 0 && dir != 1) || B < 0) return fail(LD_E_ARG, "layer or direction out of range");
   const Job& J = dir ? net->L[k - 1].tr : net->L[k - 1].fwd;
   for (const Tile& t : tile_candidates(J, B))
-    if (t.tn == tn && t.tm == kwaves && t.splits == splits && t.form == form) {
+    if (t.tn == tile->tn && t.wm == tile->mwaves && t.tm == tile->kwaves && t.splits == tile->splits &&
+        t.form == tile->form) {
       std::lock_guard<std::mutex> lk(net->mu);
       const auto key = std::make_tuple(k - 1, dir, B, precision == LD_BF16 ? 1 : 0);
       net->tiles[key] = t;

@@ -81,11 +81,11 @@ struct EpiArgs {
 };
 
 // Launch-time configuration of one contraction: tn 16-column MFMA tiles per wave;
-// fully-connected: K split over tm waves of a block and over `splits` blocks;
-// transposed strided convs: the form (0: dense GEMM + col2im, 1: stride-class
-// gather).
+// fully-connected: wm waves of a block along subdomains (16 each), K split over
+// tm waves of the block and over `splits` blocks; transposed strided convs: the
+// form (0: dense GEMM + col2im, 1: stride-class gather).
 struct Tile {
-  int tm, tn, splits, form;
+  int tm, tn, splits, form, wm;
 };
 
 // Scratch of split-K launches: partial tiles and one arrival counter per tile
@@ -177,7 +177,7 @@ hipError_t launch_conv(const GemmGeom* geoms, const GemmGeom* geo_dev, int n_cla
 size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16);
 // fully-connected contraction (G.M = B rows), optional split-K
 hipError_t launch_fc(const GemmGeom& g, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e,
-                     int tn, const SplitArgs& sp, int kw, hipStream_t s);
+                     int tn, const SplitArgs& sp, int wm, int kw, hipStream_t s);
 
 hipError_t launch_inner_min_const(int B, int n, const float* g, const float* rho, const float* lo,
                                   const float* hi, const float* bias, int bias_hw, float tau, float* xb,

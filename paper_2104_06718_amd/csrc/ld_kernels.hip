@@ -491,7 +491,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
 // Fully-connected contraction, computed transposed: C[neuron][subdomain] =
 // sum_k W[neuron][k] X[subdomain][k], with both operands loaded register-direct
 // (packed weights as the row operand).  A wave owns 16*TN neurons x 16
-// subdomains; a block is 4 waves along subdomains times kw waves along K, whose
+// subdomains; a block is wm waves along subdomains times kw waves along K, whose
 // partial sums meet in LDS and are added in wave order.  A lane ends with four
 // consecutive neurons of one subdomain, so the epilogue moves 16 bytes per
 // access.  With splits > 1 (long K) every block writes a partial tile and
@@ -500,16 +500,17 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
 // ---------------------------------------------------------------------------
 template <int TN, bool MMA_BF16, bool SRC_BF16>
 __global__ __launch_bounds__(1024) void fc_kernel(GemmGeom G, const void* __restrict__ src_v, EpiArgs E, SplitArgs S,
-                                                  int kw) {
+                                                  int wm, int kw) {
   using M = Mma<MMA_BF16>;
   constexpr int KS = M::KS, VPL = M::VPL;
-  extern __shared__ float red[];  // [kw-1][4 waves][TN][4][64]
+  extern __shared__ float red[];  // [kw-1][wm waves][TN][4][64]
   adam_tick(E);
   const int split = blockIdx.z;
   const int tid = threadIdx.x;
   const int wv = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
-  const int wave = wv & 3, wk = wv >> 2;        // position along subdomains, along K
-  const int b0 = blockIdx.x * 64 + wave * 16;   // subdomains of this wave
+  const int wave = wv % wm, wk = wv / wm;         // position along subdomains, along K
+  const int mt = 16 * wm;                         // subdomains of a block
+  const int b0 = blockIdx.x * mt + wave * 16;     // subdomains of this wave
   const int n0 = blockIdx.y * (16 * TN);        // neurons of this block
   const int ksteps = (G.K + KS - 1) / KS;
   const int per = (ksteps + S.splits - 1) / S.splits;
@@ -569,7 +570,7 @@ __global__ __launch_bounds__(1024) void fc_kernel(GemmGeom G, const void* __rest
     }
   }
   if (kw > 1) {
-    float* mine = red + (size_t)((wk - 1) * 4 + wave) * (TN * 4 * 64);
+    float* mine = red + (size_t)((wk - 1) * wm + wave) * (TN * 4 * 64);
     if (wk > 0) {
 #pragma unroll
       for (int t = 0; t < TN; ++t)
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(1024) void fc_kernel(GemmGeom G, const void* __rest
     __syncthreads();
     if (wk > 0) return;
     for (int w = 1; w < kw; ++w) {
-      const float* other = red + (size_t)((w - 1) * 4 + wave) * (TN * 4 * 64);
+      const float* other = red + (size_t)((w - 1) * wm + wave) * (TN * 4 * 64);
 #pragma unroll
       for (int t = 0; t < TN; ++t)
 #pragma unroll
@@ -588,13 +589,13 @@ __global__ __launch_bounds__(1024) void fc_kernel(GemmGeom G, const void* __rest
   }
   // lane holds neurons n0 + 16t + 4g + q of subdomain b0 + r
   if (S.splits > 1) {
-    // partial tile layout [tile][split][16*TN neurons][64 subdomains]
+    // partial tile layout [tile][split][16*TN neurons][mt subdomains]
     const size_t tile_id = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-    float* mine = S.partial + (tile_id * S.splits + split) * (64 * 16 * TN);
+    float* mine = S.partial + (tile_id * S.splits + split) * (size_t)(mt * 16 * TN);
 #pragma unroll
     for (int t = 0; t < TN; ++t)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) mine[(16 * t + 4 * g + q) * 64 + wave * 16 + r] = acc[t][q];
+      for (int q = 0; q < 4; ++q) mine[(16 * t + 4 * g + q) * mt + wave * 16 + r] = acc[t][q];
     return;
   }
   if (!svalid) return;
@@ -613,23 +614,23 @@ __global__ __launch_bounds__(1024) void fc_kernel(GemmGeom G, const void* __rest
 }
 
 template <int TN>
-__global__ __launch_bounds__(256) void fc_split_reduce(GemmGeom G, EpiArgs E, SplitArgs S, int gx) {
+__global__ __launch_bounds__(256) void fc_split_reduce(GemmGeom G, EpiArgs E, SplitArgs S, int gx, int mt) {
   // one thread per output element, consecutive threads on consecutive subdomains
   // of one neuron (the partial tiles store subdomains contiguously)
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const int mp = gx * 64;
+  const int mp = gx * mt;
   if (e >= (size_t)mp * G.N) return;
   const int j = (int)(e / mp);
   const int sub = (int)(e - (size_t)j * mp);
   if (sub >= G.M) return;
   const int cols = 16 * TN;
-  const int bx = sub >> 6, by = j / cols;
+  const int bx = sub / mt, by = j / cols;
   const size_t tile_id = (size_t)by * gx + bx;
-  const float* pt = S.partial + tile_id * S.splits * (64 * cols) + (size_t)(j - by * cols) * 64 + (sub & 63);
+  const float* pt = S.partial + tile_id * S.splits * (size_t)(mt * cols) + (size_t)(j - by * cols) * mt + (sub - bx * mt);
   EpiIn in{};
   epi_load<false>(E, (size_t)sub * G.dst_n + j, 1, 1, in);
   float v = 0.f;
-  for (int sp = 0; sp < S.splits; ++sp) v += pt[(size_t)sp * (64 * cols)];
+  for (int sp = 0; sp < S.splits; ++sp) v += pt[(size_t)sp * (mt * cols)];
   float v4[4] = {v, 0.f, 0.f, 0.f};
   epi_finish<false>(E, (size_t)sub * G.dst_n + j, 1, 1, sub, 0, j, 1, v4, in);
 }
@@ -709,35 +710,37 @@ hipError_t launch_conv(const GemmGeom* geoms, const GemmGeom* geo_dev, int n, in
 
 template <int TN>
 static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e,
-                               const SplitArgs& sp, int kw, hipStream_t s) {
-  const int gx = (G.M + 63) / 64, gy = (G.N + 16 * TN - 1) / (16 * TN);  // subdomain blocks, neuron blocks
-  if (kw != 1 && kw != 2 && kw != 4) return hipErrorInvalidValue;
-  dim3 grid(gx, gy, sp.splits), block(256 * kw);
-  const size_t lds = (size_t)(kw - 1) * 4 * TN * 4 * 64 * 4;
+                               const SplitArgs& sp, int wm, int kw, hipStream_t s) {
+  if ((wm != 1 && wm != 2 && wm != 4) || (kw != 1 && kw != 2 && kw != 4 && kw != 8) || wm * kw > 16)
+    return hipErrorInvalidValue;
+  const int mt = 16 * wm;
+  const int gx = (G.M + mt - 1) / mt, gy = (G.N + 16 * TN - 1) / (16 * TN);  // subdomain blocks, neuron blocks
+  dim3 grid(gx, gy, sp.splits), block(64 * wm * kw);
+  const size_t lds = (size_t)(kw - 1) * wm * TN * 4 * 64 * 4;
   if (mma_bf16) {
     if (src_bf16)
-      hipLaunchKernelGGL((fc_kernel<TN, true, true>), grid, block, lds, s, G, src, e, sp, kw);
+      hipLaunchKernelGGL((fc_kernel<TN, true, true>), grid, block, lds, s, G, src, e, sp, wm, kw);
     else
-      hipLaunchKernelGGL((fc_kernel<TN, true, false>), grid, block, lds, s, G, src, e, sp, kw);
+      hipLaunchKernelGGL((fc_kernel<TN, true, false>), grid, block, lds, s, G, src, e, sp, wm, kw);
   } else {
     if (src_bf16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((fc_kernel<TN, false, false>), grid, block, lds, s, G, src, e, sp, kw);
+    hipLaunchKernelGGL((fc_kernel<TN, false, false>), grid, block, lds, s, G, src, e, sp, wm, kw);
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess || sp.splits <= 1) return err;
   EpiArgs e2 = e;
   e2.t_dev = nullptr;  // the step was already counted by the partial launch
-  const size_t outs = (size_t)gx * 64 * G.N;
-  hipLaunchKernelGGL((fc_split_reduce<TN>), dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s, G, e2, sp, gx);
+  const size_t outs = (size_t)gx * mt * G.N;
+  hipLaunchKernelGGL((fc_split_reduce<TN>), dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s, G, e2, sp, gx, mt);
   return hipGetLastError();
 }
 
 hipError_t launch_fc(const GemmGeom& G, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e, int tn,
-                     const SplitArgs& sp, int kw, hipStream_t s) {
+                     const SplitArgs& sp, int wm, int kw, hipStream_t s) {
   if (G.M == 0 || G.N == 0) return hipSuccess;
-  if (tn == 1) return launch_fc_tn<1>(G, src, src_bf16, mma_bf16, e, sp, kw, s);
-  if (tn == 2) return launch_fc_tn<2>(G, src, src_bf16, mma_bf16, e, sp, kw, s);
-  if (tn == 4) return launch_fc_tn<4>(G, src, src_bf16, mma_bf16, e, sp, kw, s);
+  if (tn == 1) return launch_fc_tn<1>(G, src, src_bf16, mma_bf16, e, sp, wm, kw, s);
+  if (tn == 2) return launch_fc_tn<2>(G, src, src_bf16, mma_bf16, e, sp, wm, kw, s);
+  if (tn == 4) return launch_fc_tn<4>(G, src, src_bf16, mma_bf16, e, sp, wm, kw, s);
   return hipErrorInvalidValue;
 }
 

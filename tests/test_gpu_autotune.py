@@ -19,9 +19,9 @@ def test_every_candidate_configuration_matches_oracle(name):
     for prec in ("fp32", "bf16"):
         for k in range(1, n_layers):
             for d in ("transposed", "forward"):
-                for tn, kw, sp, form in P.tile_candidates(net, inst.B, k, d):
-                    _case(f"candidate {name} {prec} layer {k} {d} tn={tn} kwaves={kw} splits={sp} form={form}")
-                    P.set_tuned_config(net, inst.B, prec, k, d, tn, kw, sp, form)
+                for tile in P.tile_candidates(net, inst.B, k, d):
+                    _case(f"candidate {name} {prec} layer {k} {d} {tile}")
+                    P.set_tuned_config(net, inst.B, prec, k, d, tile)
                     if prec == "fp32":
                         _check_dual_eval(P, inst, net, batch, rho)
                     else:
@@ -51,9 +51,9 @@ def test_autotuned_auto_ascent(prec):
     print(f"  engine {info['engine']}, us/iter layerwise {info['us_per_iter_layerwise']:.1f} "
           f"resident {info['us_per_iter_resident']:.1f}")
     for e in info["layers"]:
-        print(f"  layer {e['layer']} {e['dir']}: tn={e['tn']} kwaves={e['kwaves']} splits={e['splits']} "
-              f"form={e['form']} {e['us']:.1f} us")
-        assert (e["tn"], e["kwaves"], e["splits"], e["form"]) in P.tile_candidates(net, inst.B, e["layer"], e["dir"])
+        tile = {f: e[f] for f in ("tn", "mwaves", "kwaves", "splits", "form")}
+        print(f"  layer {e['layer']} {e['dir']}: {tile} {e['us']:.1f} us")
+        assert tile in P.tile_candidates(net, inst.B, e["layer"], e["dir"])
         assert e["us"] > 0
     assert info["engine"] in ("layerwise", "resident")
     assert len(info["layers"]) == 2 * (len(inst.layers) - 1)
