@@ -265,7 +265,7 @@ int build_col(ld_net* net, Layer& L, const float* W) {
   g.Mp = (int)round_up((size_t)g.M, 16);
   auto ns_of = [&](int cc) { return 16 * ((cc * khkw + 15) / 16) + 1; };
   int Cc = Ci;
-  while (Cc > 1 && (size_t)g.Mp * ns_of(Cc) * 4 > 40 * 1024) --Cc;
+  while (Cc > 1 && (size_t)g.Mp * ns_of(Cc) * 4 > 52 * 1024) --Cc;
   if ((size_t)g.Mp * ns_of(Cc) * 4 > 64 * 1024) return LD_OK;
   g.Cc = Cc;
   g.nchunks = (Ci + Cc - 1) / Cc;
@@ -340,6 +340,7 @@ int build_col(ld_net* net, Layer& L, const float* W) {
   g.cnt_y = (const int*)pcy;
   g.toff_x = (const int*)ptx;
   g.cnt_x = (const int*)pcx;
+  if (convT_lds_bytes(g) > 160 * 1024) return LD_OK;  // keep the stride-class form
   L.tr.col = g;
   L.tr.has_col = true;
   return LD_OK;

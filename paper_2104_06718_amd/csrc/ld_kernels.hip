@@ -746,9 +746,10 @@ hipError_t launch_fc(const GemmGeom& G, const void* src, int src_bf16, int mma_b
 
 // ---------------------------------------------------------------------------
 // Transposed strided convolution, one block per subdomain (see ColGeom):
+//  0. the subdomain's rho (A operand, [Co][M]) and the fragment-ordered weights
+//     (B operand) are staged in LDS, one round of loads;
 //  1. per chunk of input channels, waves compute 16x16 MFMA tiles of
-//     Y = rho^T W (A read straight from rho, contiguous along positions; B from
-//     fragment-ordered weights) into LDS;
+//     Y = rho^T W into LDS;
 //  2. every output of the chunk sums its taps from Y (tap offsets from small
 //     LDS tables) and goes through the epilogue, four consecutive neurons per
 //     thread.
@@ -761,21 +762,71 @@ __global__ __launch_bounds__(kTThreads) void convT_kernel(ColGeom G, const float
   typedef typename M::BFrag BFrag;
   constexpr int KS = M::KS, VPL = M::VPL, NW = kTThreads / 64;
   extern __shared__ float lds[];
-  float* Y = lds;                                 // [Mp][Ns]
-  int* ty = reinterpret_cast<int*>(Y + G.Mp * G.Ns);  // [H][Tmax]
-  int* cy = ty + G.H * G.Tmax;                    // [H]
-  int* tx = cy + G.H;                             // [W][Tmax]
-  int* cx = tx + G.W * G.Tmax;                    // [W]
+  const int ks = BF ? G.ksh : G.ksf;
+  const int kp = ks * KS;                              // K rounded up to whole steps
+  const int nfrag = G.nchunks * G.ntc * ks * 64;       // fragments (16 bytes each)
+  BFrag* Bl = reinterpret_cast<BFrag*>(lds);           // [nchunks][ntc][ks][64 lanes]
+  float* A = lds + 4 * nfrag;                          // [kp][Mp], rows >= Co and columns >= M zero
+  float* Y = A + kp * G.Mp;                            // [Mp][Ns]
+  int* ty = reinterpret_cast<int*>(Y + G.Mp * G.Ns);   // [H][Tmax]
+  int* cy = ty + G.H * G.Tmax;                         // [H]
+  int* tx = cy + G.H;                                  // [W][Tmax]
+  int* cx = tx + G.W * G.Tmax;                         // [W]
   const int b = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
   adam_tick(E);
+  // 0. staging: rho of the subdomain, weight fragments, tap tables
+  {
+    const float* src = rho + (size_t)b * G.Co * G.M;
+    if ((G.M & 3) == 0) {
+      // rows of rho as 16-byte vectors, eight loads in flight per thread
+      const int m4 = G.M >> 2, n4 = G.Co * m4;
+      const float inv_m4 = 1.0f / (float)m4;
+      constexpr int U = 8;
+      for (int i0 = tid; i0 < n4; i0 += U * kTThreads) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * kTThreads;
+          if (i < n4) v[u] = *reinterpret_cast<const float4*>(src + 4 * (size_t)i);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * kTThreads;
+          if (i < n4) {
+            const int k = fdiv(i, m4, inv_m4);
+            float* d = A + k * G.Mp + 4 * (i - k * m4);
+            d[0] = v[u].x;
+            d[1] = v[u].y;
+            d[2] = v[u].z;
+            d[3] = v[u].w;
+          }
+        }
+      }
+      // zero rows k >= Co, then columns m >= M of the rows below
+      for (int e = G.Co * G.Mp + tid; e < kp * G.Mp; e += kTThreads) A[e] = 0.f;
+      const int padc = G.Mp - G.M;
+      for (int e = tid; e < G.Co * padc; e += kTThreads) {
+        const int k = e / padc;
+        A[k * G.Mp + G.M + (e - k * padc)] = 0.f;
+      }
+    } else {
+      const int cells = kp * G.Mp;
+      const float inv_mp = 1.0f / (float)G.Mp;
+      for (int e = tid; e < cells; e += kTThreads) {
+        const int k = fdiv(e, G.Mp, inv_mp);
+        const int m = e - k * G.Mp;
+        A[e] = (k < G.Co && m < G.M) ? src[(size_t)k * G.M + m] : 0.f;
+      }
+    }
+    const uint4* fsrc = reinterpret_cast<const uint4*>(BF ? (const void*)G.Bh : (const void*)G.Bf);
+    for (int i = tid; i < nfrag; i += kTThreads) reinterpret_cast<uint4*>(Bl)[i] = fsrc[i];
+  }
   for (int i = tid; i < G.H * G.Tmax; i += kTThreads) ty[i] = G.toff_y[i];
   for (int i = tid; i < G.H; i += kTThreads) cy[i] = G.cnt_y[i];
   for (int i = tid; i < G.W * G.Tmax; i += kTThreads) tx[i] = G.toff_x[i];
   for (int i = tid; i < G.W; i += kTThreads) cx[i] = G.cnt_x[i];
-  const float* src = rho + (size_t)b * G.Co * G.M;
-  const int ks = BF ? G.ksh : G.ksf;
+  __syncthreads();
   const int mtn = G.Mp >> 4;
-  const BFrag* frags = reinterpret_cast<const BFrag*>(BF ? (const void*)G.Bh : (const void*)G.Bf);
   const size_t dst_base = (size_t)b * G.Ci * G.HW;
   for (int c = 0; c < G.nchunks; ++c) {
     const int items = mtn * G.ntc;
@@ -783,16 +834,12 @@ __global__ __launch_bounds__(kTThreads) void convT_kernel(ColGeom G, const float
       const int mt = it / G.ntc;
       const int nt = it - mt * G.ntc;
       const int m = mt * 16 + r;
-      const bool mv = m < G.M;
-      const BFrag* fb = frags + (size_t)(c * G.ntc + nt) * ks * 64 + lane;
+      const BFrag* fb = Bl + (size_t)(c * G.ntc + nt) * ks * 64 + lane;
       f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
       for (int st = 0; st < ks; ++st) {
         float a[VPL];
 #pragma unroll
-        for (int j = 0; j < VPL; ++j) {
-          const int k = st * KS + VPL * g + j;
-          a[j] = (mv && k < G.Co) ? src[(size_t)k * G.M + m] : 0.f;
-        }
+        for (int j = 0; j < VPL; ++j) a[j] = A[(st * KS + VPL * g + j) * G.Mp + m];
         M::mma(a, fb[(size_t)st * 64], acc);
       }
 #pragma unroll
@@ -845,13 +892,23 @@ __global__ __launch_bounds__(kTThreads) void convT_kernel(ColGeom G, const float
   }
 }
 
+// LDS of convT_kernel for the operand type: weight fragments, A, Y, tap tables
+static size_t convT_lds_bytes_t(const ColGeom& g, int bf16) {
+  const int ks = bf16 ? g.ksh : g.ksf, kp = ks * (bf16 ? 32 : 16);
+  const size_t nfrag = (size_t)g.nchunks * g.ntc * ks * 64;
+  return (size_t)4 * (4 * nfrag + (size_t)kp * g.Mp + (size_t)g.Mp * g.Ns + (size_t)g.H * g.Tmax + g.H +
+                      (size_t)g.W * g.Tmax + g.W);
+}
+
 size_t convT_lds_bytes(const ColGeom& g) {
-  return (size_t)4 * ((size_t)g.Mp * g.Ns + (size_t)g.H * g.Tmax + g.H + (size_t)g.W * g.Tmax + g.W);
+  const size_t a = convT_lds_bytes_t(g, 0), b = convT_lds_bytes_t(g, 1);
+  return a > b ? a : b;
 }
 
 hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16, const EpiArgs& e, hipStream_t s) {
   if (B == 0) return hipSuccess;
-  const size_t lds = convT_lds_bytes(g);
+  const size_t lds = convT_lds_bytes_t(g, mma_bf16);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   const void* fn = mma_bf16 ? (const void*)convT_kernel<true> : (const void*)convT_kernel<false>;
   if (lds > 64 * 1024) {
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
