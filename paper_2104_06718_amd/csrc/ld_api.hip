@@ -263,14 +263,6 @@ int build_col(ld_net* net, Layer& L, const float* W) {
   g.HW = H * Wd;
   g.khkw = khkw;
   g.Mp = (int)round_up((size_t)g.M, 16);
-  auto ns_of = [&](int cc) { return 16 * ((cc * khkw + 15) / 16) + 1; };
-  int Cc = Ci;
-  while (Cc > 1 && (size_t)g.Mp * ns_of(Cc) * 4 > 52 * 1024) --Cc;
-  if ((size_t)g.Mp * ns_of(Cc) * 4 > 64 * 1024) return LD_OK;
-  g.Cc = Cc;
-  g.nchunks = (Ci + Cc - 1) / Cc;
-  g.ntc = (Cc * khkw + 15) / 16;
-  g.Ns = 16 * g.ntc + 1;
   g.ksf = (Co + 15) / 16;
   g.ksh = (Co + 31) / 32;
   g.inv_HW = 1.0f / (float)g.HW;
@@ -291,7 +283,32 @@ int build_col(ld_net* net, Layer& L, const float* W) {
   for (auto& v : tyv) Tmax = std::max(Tmax, (int)v.size());
   for (auto& v : txv) Tmax = std::max(Tmax, (int)v.size());
   g.Tmax = Tmax;
-  std::vector<int> toy((size_t)H * Tmax, 0), coy(H), tox((size_t)Wd * Tmax, 0), cox(Wd);
+  g.ntab = H * Tmax + H + Wd * Tmax + Wd;
+  // channel chunks: balanced, and as few as keep the block's LDS within half a
+  // CU (two subdomains per CU), else within the whole CU
+  auto with_chunks = [&](int nch) {
+    ColGeom t = g;
+    t.Cc = (Ci + nch - 1) / nch;
+    t.nchunks = (Ci + t.Cc - 1) / t.Cc;
+    t.ntc = (t.Cc * khkw + 15) / 16;
+    t.Ns = 16 * t.ntc + 1;
+    return t;
+  };
+  int pick = 0;
+  for (int pass = 0; pass < 2 && !pick; ++pass)
+    for (int nch = 1; nch <= Ci && !pick; ++nch) {
+      const ColGeom t = with_chunks(nch);
+      if (nch > 1 && t.Cc == with_chunks(nch - 1).Cc) continue;
+      if (convT_lds_bytes(t) <= (pass == 0 ? kConvTHalfCU : kConvTWholeCU)) pick = nch;
+    }
+  if (!pick) return LD_OK;  // keep the stride-class form
+  g = with_chunks(pick);
+  const int Cc = g.Cc;
+  std::vector<int> tab((size_t)g.ntab, 0);
+  int* toy = tab.data();
+  int* coy = toy + (size_t)H * Tmax;
+  int* tox = coy + H;
+  int* cox = tox + (size_t)Wd * Tmax;
   for (int y = 0; y < H; ++y) {
     coy[y] = (int)tyv[y].size();
     for (int i = 0; i < coy[y]; ++i) toy[(size_t)y * Tmax + i] = tyv[y][i].second * OW * g.Ns + tyv[y][i].first * kw;
@@ -321,26 +338,16 @@ int build_col(ld_net* net, Layer& L, const float* W) {
           for (int j = 0; j < 8; ++j)
             bh[((((size_t)c * g.ntc + nt) * g.ksh + st) * 64 + l) * 8 + j] = host_f2bf(wv(c, nt, st * 32 + 8 * q + j, r));
       }
-  void *pbf, *pbh, *pty, *pcy, *ptx, *pcx;
+  void *pbf, *pbh, *ptab;
   LD_TRY(alloc_dev(net, &pbf, bf.size() * 4));
   LD_TRY(alloc_dev(net, &pbh, bh.size() * 2));
-  LD_TRY(alloc_dev(net, &pty, toy.size() * 4));
-  LD_TRY(alloc_dev(net, &pcy, coy.size() * 4));
-  LD_TRY(alloc_dev(net, &ptx, tox.size() * 4));
-  LD_TRY(alloc_dev(net, &pcx, cox.size() * 4));
+  LD_TRY(alloc_dev(net, &ptab, tab.size() * 4));
   LD_HIP(hipMemcpy(pbf, bf.data(), bf.size() * 4, hipMemcpyHostToDevice));
   LD_HIP(hipMemcpy(pbh, bh.data(), bh.size() * 2, hipMemcpyHostToDevice));
-  LD_HIP(hipMemcpy(pty, toy.data(), toy.size() * 4, hipMemcpyHostToDevice));
-  LD_HIP(hipMemcpy(pcy, coy.data(), coy.size() * 4, hipMemcpyHostToDevice));
-  LD_HIP(hipMemcpy(ptx, tox.data(), tox.size() * 4, hipMemcpyHostToDevice));
-  LD_HIP(hipMemcpy(pcx, cox.data(), cox.size() * 4, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(ptab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
   g.Bf = (const float*)pbf;
   g.Bh = (const bf16_t*)pbh;
-  g.toff_y = (const int*)pty;
-  g.cnt_y = (const int*)pcy;
-  g.toff_x = (const int*)ptx;
-  g.cnt_x = (const int*)pcx;
-  if (convT_lds_bytes(g) > 160 * 1024) return LD_OK;  // keep the stride-class form
+  g.tab = (const int*)ptab;
   L.tr.col = g;
   L.tr.has_col = true;
   return LD_OK;

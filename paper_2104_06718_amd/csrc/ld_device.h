@@ -78,8 +78,15 @@ template <>
 struct Mma<false> {
   static constexpr int KS = 16, VPL = 4;
   typedef float4 BFrag;
+  typedef f32x4 AFrag;  // A operand of one lane for one K step, in operand order
   __device__ static BFrag loadB(const GemmGeom& G, size_t off) { return *reinterpret_cast<const float4*>(G.Bf + off); }
   __device__ static void mma(const float (&a)[4], const BFrag& b, f32x4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b.x, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b.y, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b.z, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b.w, c, 0, 0, 0);
+  }
+  __device__ static void mma_frag(const AFrag& a, const BFrag& b, f32x4& c) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b.x, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b.y, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b.z, c, 0, 0, 0);
@@ -97,12 +104,16 @@ template <>
 struct Mma<true> {
   static constexpr int KS = 32, VPL = 8;
   typedef bf16x8 BFrag;
+  typedef bf16x8 AFrag;
   __device__ static BFrag loadB(const GemmGeom& G, size_t off) { return *reinterpret_cast<const bf16x8*>(G.Bh + off); }
   __device__ static void mma(const float (&a)[8], const BFrag& b, f32x4& c) {
     bf16x8 av;
 #pragma unroll
     for (int j = 0; j < 8; ++j) av[j] = (__bf16)a[j];
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, c, 0, 0, 0);
+  }
+  __device__ static void mma_frag(const AFrag& a, const BFrag& b, f32x4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
   __device__ static void mma_wx(const BFrag& w, const float (&x)[8], f32x4& c) {
     bf16x8 xv;

@@ -158,11 +158,13 @@ struct ColGeom {
   float inv_HW, inv_W;    // 1/HW, 1/W for the index split of the epilogue
   const float* Bf;        // FP32 fragments [nchunks][ntc][ksf][64 lanes][4]
   const bf16_t* Bh;       // BF16 fragments [nchunks][ntc][ksh][64 lanes][8]
-  const int* toff_y;      // [H][Tmax]  oy*OW*Ns + ky*kw
-  const int* cnt_y;       // [H]
-  const int* toff_x;      // [W][Tmax]  ox*Ns + kx
-  const int* cnt_x;       // [W]
+  // tap tables, one contiguous array of ntab ints:
+  //   toff_y [H][Tmax] (oy*OW*Ns + ky*kw), cnt_y [H], toff_x [W][Tmax] (ox*Ns + kx), cnt_x [W]
+  const int* tab;
+  int ntab;
 };
+// LDS of one convT block: half a CU (two subdomains resident per CU), a whole CU
+constexpr size_t kConvTHalfCU = 80 * 1024, kConvTWholeCU = 160 * 1024;
 hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16, const EpiArgs& e, hipStream_t s);
 size_t convT_lds_bytes(const ColGeom& g);
 

@@ -746,110 +746,124 @@ hipError_t launch_fc(const GemmGeom& G, const void* src, int src_bf16, int mma_b
 
 // ---------------------------------------------------------------------------
 // Transposed strided convolution, one block per subdomain (see ColGeom):
-//  0. the subdomain's rho (A operand, [Co][M]) and the fragment-ordered weights
-//     (B operand) are staged in LDS, one round of loads;
-//  1. per chunk of input channels, waves compute 16x16 MFMA tiles of
+//  0. staging, one round of loads then one of LDS writes: the subdomain's rho
+//     (A operand) in MFMA operand order, [K/VPL][Mp][VPL] (BF16 for the BF16
+//     product), zero-padded in K and M; the fragment-ordered weights (B
+//     operand); the tap tables;
+//  1. per chunk of input channels, the device-memory operands of the thread's
+//     first epilogue group are loaded, then waves compute 16x16 MFMA tiles of
 //     Y = rho^T W into LDS;
-//  2. every output of the chunk sums its taps from Y (tap offsets from small
-//     LDS tables) and goes through the epilogue, four consecutive neurons per
-//     thread.
+//  2. every output of the chunk sums its taps from Y and goes through the
+//     epilogue, four consecutive neurons per thread, with the operands of the
+//     next group loaded before the current one is finished.
 // ---------------------------------------------------------------------------
 constexpr int kTThreads = 256;
 
+// (the register cap keeps the compiler from spending registers on the staging
+// round that would leave one wave per SIMD)
 template <bool BF>
-__global__ __launch_bounds__(kTThreads) void convT_kernel(ColGeom G, const float* __restrict__ rho, EpiArgs E) {
+__global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) void convT_kernel(ColGeom G, const float* __restrict__ rho, EpiArgs E) {
   using M = Mma<BF>;
   typedef typename M::BFrag BFrag;
+  typedef typename M::AFrag AFrag;
+  typedef typename std::conditional<BF, __bf16, float>::type AT;
   constexpr int KS = M::KS, VPL = M::VPL, NW = kTThreads / 64;
   extern __shared__ float lds[];
   const int ks = BF ? G.ksh : G.ksf;
-  const int kp = ks * KS;                              // K rounded up to whole steps
+  const int kq_n = ks * (KS / VPL);                    // K rounded up to whole steps, in groups of VPL
   const int nfrag = G.nchunks * G.ntc * ks * 64;       // fragments (16 bytes each)
   BFrag* Bl = reinterpret_cast<BFrag*>(lds);           // [nchunks][ntc][ks][64 lanes]
-  float* A = lds + 4 * nfrag;                          // [kp][Mp], rows >= Co and columns >= M zero
-  float* Y = A + kp * G.Mp;                            // [Mp][Ns]
-  int* ty = reinterpret_cast<int*>(Y + G.Mp * G.Ns);   // [H][Tmax]
-  int* cy = ty + G.H * G.Tmax;                         // [H]
-  int* tx = cy + G.H;                                  // [W][Tmax]
-  int* cx = tx + G.W * G.Tmax;                         // [W]
+  AT* A = reinterpret_cast<AT*>(lds + 4 * nfrag);      // [kq_n][Mp][VPL]
+  float* Y = reinterpret_cast<float*>(A + (size_t)kq_n * G.Mp * VPL);  // [Mp][Ns]
+  int* tab = reinterpret_cast<int*>(Y + G.Mp * G.Ns);  // toff_y [H][Tmax], cnt_y [H], toff_x [W][Tmax], cnt_x [W]
+  const int* ty = tab;
+  const int* cy = ty + G.H * G.Tmax;
+  const int* tx = cy + G.H;
+  const int* cx = tx + G.W * G.Tmax;
   const int b = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
   adam_tick(E);
-  // 0. staging: rho of the subdomain, weight fragments, tap tables
+  // 0. staging
   {
+    constexpr int UC = 4, UF = 8;
     const float* src = rho + (size_t)b * G.Co * G.M;
-    if ((G.M & 3) == 0) {
-      // rows of rho as 16-byte vectors, eight loads in flight per thread
-      const int m4 = G.M >> 2, n4 = G.Co * m4;
-      const float inv_m4 = 1.0f / (float)m4;
-      constexpr int U = 8;
-      for (int i0 = tid; i0 < n4; i0 += U * kTThreads) {
-        float4 v[U];
+    const int ncell = kq_n * G.Mp;
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4* fsrc = reinterpret_cast<const u32x4*>(BF ? (const void*)G.Bh : (const void*)G.Bf);
+    const float inv_mp = 1.0f / (float)G.Mp;
+    const int rounds = max((ncell + UC * kTThreads - 1) / (UC * kTThreads), (nfrag + UF * kTThreads - 1) / (UF * kTThreads));
+    for (int rd = 0; rd < rounds; ++rd) {
+      float v[UC][VPL];
+      u32x4 f[UF];
+      int tv = 0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = i0 + u * kTThreads;
-          if (i < n4) v[u] = *reinterpret_cast<const float4*>(src + 4 * (size_t)i);
-        }
+      for (int u = 0; u < UC; ++u) {
+        const int cell = (rd * UC + u) * kTThreads + tid;
+        if (cell < ncell) {
+          const int kq = fdiv(cell, G.Mp, inv_mp), m = cell - kq * G.Mp;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = i0 + u * kTThreads;
-          if (i < n4) {
-            const int k = fdiv(i, m4, inv_m4);
-            float* d = A + k * G.Mp + 4 * (i - k * m4);
-            d[0] = v[u].x;
-            d[1] = v[u].y;
-            d[2] = v[u].z;
-            d[3] = v[u].w;
+          for (int j = 0; j < VPL; ++j) {
+            const int k = kq * VPL + j;
+            v[u][j] = (k < G.Co && m < G.M) ? src[(size_t)k * G.M + m] : 0.f;
           }
         }
       }
-      // zero rows k >= Co, then columns m >= M of the rows below
-      for (int e = G.Co * G.Mp + tid; e < kp * G.Mp; e += kTThreads) A[e] = 0.f;
-      const int padc = G.Mp - G.M;
-      for (int e = tid; e < G.Co * padc; e += kTThreads) {
-        const int k = e / padc;
-        A[k * G.Mp + G.M + (e - k * padc)] = 0.f;
+#pragma unroll
+      for (int u = 0; u < UF; ++u) {
+        const int i = (rd * UF + u) * kTThreads + tid;
+        if (i < nfrag) f[u] = fsrc[i];
       }
-    } else {
-      const int cells = kp * G.Mp;
-      const float inv_mp = 1.0f / (float)G.Mp;
-      for (int e = tid; e < cells; e += kTThreads) {
-        const int k = fdiv(e, G.Mp, inv_mp);
-        const int m = e - k * G.Mp;
-        A[e] = (k < G.Co && m < G.M) ? src[(size_t)k * G.M + m] : 0.f;
+      if (rd == 0 && tid < G.ntab) tv = G.tab[tid];
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        const int cell = (rd * UC + u) * kTThreads + tid;
+        if (cell < ncell) {
+          AFrag a;
+#pragma unroll
+          for (int j = 0; j < VPL; ++j) a[j] = (AT)v[u][j];
+          *reinterpret_cast<AFrag*>(A + (size_t)cell * VPL) = a;
+        }
       }
+#pragma unroll
+      for (int u = 0; u < UF; ++u) {
+        const int i = (rd * UF + u) * kTThreads + tid;
+        if (i < nfrag) reinterpret_cast<u32x4*>(Bl)[i] = f[u];
+      }
+      if (rd == 0 && tid < G.ntab) tab[tid] = tv;
     }
-    const uint4* fsrc = reinterpret_cast<const uint4*>(BF ? (const void*)G.Bh : (const void*)G.Bf);
-    for (int i = tid; i < nfrag; i += kTThreads) reinterpret_cast<uint4*>(Bl)[i] = fsrc[i];
+    for (int i = tid + kTThreads; i < G.ntab; i += kTThreads) tab[i] = G.tab[i];
   }
-  for (int i = tid; i < G.H * G.Tmax; i += kTThreads) ty[i] = G.toff_y[i];
-  for (int i = tid; i < G.H; i += kTThreads) cy[i] = G.cnt_y[i];
-  for (int i = tid; i < G.W * G.Tmax; i += kTThreads) tx[i] = G.toff_x[i];
-  for (int i = tid; i < G.W; i += kTThreads) cx[i] = G.cnt_x[i];
   __syncthreads();
   const int mtn = G.Mp >> 4;
   const size_t dst_base = (size_t)b * G.Ci * G.HW;
+  constexpr int STEP = 4 * kTThreads;
+  const bool vec = (G.HW & 3) == 0;
   for (int c = 0; c < G.nchunks; ++c) {
+    const int c0 = c * G.Cc, c1 = min(G.Ci, c0 + G.Cc);
+    const int e0 = c0 * G.HW, e1 = c1 * G.HW;
+    // operands of the first epilogue group, in flight during the GEMM
+    EpiIn nx{};
+    if (vec) {
+      if (e0 + 4 * tid < e1) epi_load<true>(E, dst_base + e0 + 4 * tid, 1, 4, nx);
+    } else {
+      if (e0 + tid < e1) epi_load<false>(E, dst_base + e0 + tid, 1, 1, nx);
+    }
     const int items = mtn * G.ntc;
     for (int it = wave; it < items; it += NW) {
       const int mt = it / G.ntc;
       const int nt = it - mt * G.ntc;
       const int m = mt * 16 + r;
       const BFrag* fb = Bl + (size_t)(c * G.ntc + nt) * ks * 64 + lane;
+      const AFrag* fa = reinterpret_cast<const AFrag*>(A) + (size_t)g * G.Mp + m;
       f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-      for (int st = 0; st < ks; ++st) {
-        float a[VPL];
-#pragma unroll
-        for (int j = 0; j < VPL; ++j) a[j] = A[(st * KS + VPL * g + j) * G.Mp + m];
-        M::mma(a, fb[(size_t)st * 64], acc);
-      }
+      for (int st = 0; st < ks; ++st) M::mma_frag(fa[(size_t)st * 4 * G.Mp], fb[(size_t)st * 64], acc);
 #pragma unroll
       for (int q = 0; q < 4; ++q) Y[(mt * 16 + 4 * g + q) * G.Ns + nt * 16 + r] = acc[q];
     }
     __syncthreads();
-    const int c0 = c * G.Cc, c1 = min(G.Ci, c0 + G.Cc);
-    const int e0 = c0 * G.HW, e1 = c1 * G.HW;
-    if ((G.HW & 3) == 0) {
-      for (int e = e0 + 4 * tid; e < e1; e += 4 * kTThreads) {
+    if (vec) {
+      for (int e = e0 + 4 * tid; e < e1; e += STEP) {
+        const EpiIn cur = nx;
+        if (e + STEP < e1) epi_load<true>(E, dst_base + e + STEP, 1, 4, nx);
         const int ci = fdiv(e, G.HW, G.inv_HW);
         const int rem = e - ci * G.HW;
         int y = fdiv(rem, G.W, G.inv_W);
@@ -859,10 +873,10 @@ __global__ __launch_bounds__(kTThreads) void convT_kernel(ColGeom G, const float
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           float sum = 0.f;
-          const int ny = cy[y], nx = cx[x];
+          const int ny = cy[y], nxx = cx[x];
           for (int ia = 0; ia < ny; ++ia) {
             const int oy = ty[y * G.Tmax + ia] + nb;
-            for (int ib = 0; ib < nx; ++ib) sum += Y[oy + tx[x * G.Tmax + ib]];
+            for (int ib = 0; ib < nxx; ++ib) sum += Y[oy + tx[x * G.Tmax + ib]];
           }
           v4[q] = sum;
           if (++x == G.W) {
@@ -870,10 +884,12 @@ __global__ __launch_bounds__(kTThreads) void convT_kernel(ColGeom G, const float
             ++y;
           }
         }
-        epilogue4<true>(E, dst_base + e, 1, 4, b, 0, ci, 0, v4);
+        epi_finish<true>(E, dst_base + e, 1, 4, b, 0, ci, 0, v4, cur);
       }
     } else {
       for (int e = e0 + tid; e < e1; e += kTThreads) {
+        const EpiIn cur = nx;
+        if (e + kTThreads < e1) epi_load<false>(E, dst_base + e + kTThreads, 1, 1, nx);
         const int ci = fdiv(e, G.HW, G.inv_HW);
         const int rem = e - ci * G.HW;
         const int y = fdiv(rem, G.W, G.inv_W);
@@ -885,7 +901,7 @@ __global__ __launch_bounds__(kTThreads) void convT_kernel(ColGeom G, const float
           for (int ib = 0; ib < cx[x]; ++ib) sum += Y[oy + tx[x * G.Tmax + ib]];
         }
         float v4[4] = {sum, 0.f, 0.f, 0.f};
-        epilogue4<false>(E, dst_base + e, 1, 1, b, 0, ci, 0, v4);
+        epi_finish<false>(E, dst_base + e, 1, 1, b, 0, ci, 0, v4, cur);
       }
     }
     __syncthreads();
@@ -896,8 +912,7 @@ __global__ __launch_bounds__(kTThreads) void convT_kernel(ColGeom G, const float
 static size_t convT_lds_bytes_t(const ColGeom& g, int bf16) {
   const int ks = bf16 ? g.ksh : g.ksf, kp = ks * (bf16 ? 32 : 16);
   const size_t nfrag = (size_t)g.nchunks * g.ntc * ks * 64;
-  return (size_t)4 * (4 * nfrag + (size_t)kp * g.Mp + (size_t)g.Mp * g.Ns + (size_t)g.H * g.Tmax + g.H +
-                      (size_t)g.W * g.Tmax + g.W);
+  return 16 * nfrag + (size_t)kp * g.Mp * (bf16 ? 2 : 4) + (size_t)4 * g.Mp * g.Ns + (size_t)4 * g.ntab;
 }
 
 size_t convT_lds_bytes(const ColGeom& g) {
