@@ -106,6 +106,10 @@ CONFIGS: Dict[str, Dict] = {
     "tiny_conv2": dict(cfg=7, input=(3, 7, 7), eps=0.05, B=3, props=[2, 1], T=200,
                        arch=[_conv(3, 5, 3, 2, 1, 7), _conv(5, 6, 3, 1, 1, 4),
                              _conv(6, 4, 4, 2, 1, 4), ("linear", 16, 7), ("linear", 7, 4)]),
+    # transposed strided convs with one tap per row (2x2/2) and three (5x5/2)
+    "tiny_conv3": dict(cfg=8, input=(2, 8, 8), eps=0.1, B=5, props=[3, 2], T=200,
+                       arch=[_conv(2, 3, 5, 2, 2, 8), _conv(3, 4, 2, 2, 0, 4),
+                             ("linear", 16, 6), ("linear", 6, 3)]),
     # MLP 784-1024x4-10, box +-0.02
     "mlp": dict(cfg=5, input=(784, 1, 1), eps=0.02, B=1024, props=[1024], T=0,
                 arch=[("linear", 784, 1024), ("linear", 1024, 1024), ("linear", 1024, 1024),

@@ -196,7 +196,7 @@ __device__ __forceinline__ void epi_finish(const EpiArgs& E, size_t i0, size_t s
       const float b1 = E.adam[4], b2 = E.adam[5];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float bias = E.bias[col + q * cstep];
+        const float bias = (VEC || q < nv) ? E.bias[col + q * cstep] : 0.f;
         const float s = xb[q] - (acc[q] + bias);
         m[q] = b1 * m[q] + (1.f - b1) * s;
         v[q] = b2 * v[q] + (1.f - b2) * (s * s);
@@ -211,7 +211,7 @@ __device__ __forceinline__ void epi_finish(const EpiArgs& E, size_t i0, size_t s
     case EPI_SUPERGRAD: {
       float o[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = in.a0[q] - (acc[q] + E.bias[col + q * cstep]);
+      for (int q = 0; q < 4; ++q) o[q] = in.a0[q] - (acc[q] + ((VEC || q < nv) ? E.bias[col + q * cstep] : 0.f));
       st4<VEC>(E.out_f, i0, st, nv, o);
     } break;
     case EPI_CROWN: {
@@ -224,7 +224,7 @@ __device__ __forceinline__ void epi_finish(const EpiArgs& E, size_t i0, size_t s
       float o[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float y = acc[q] + E.bias[col + q * cstep];
+        const float y = acc[q] + ((VEC || q < nv) ? E.bias[col + q * cstep] : 0.f);
         if ((VEC || q < nv) && !(y >= in.a0[q] && y <= in.a1[q])) E.flag[b0 + q * bstep] = 0;
         o[q] = fmaxf(y, 0.f);
       }
@@ -233,7 +233,7 @@ __device__ __forceinline__ void epi_finish(const EpiArgs& E, size_t i0, size_t s
     case EPI_BIAS_STORE: {
       float o[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = acc[q] + E.bias[col + q * cstep];
+      for (int q = 0; q < 4; ++q) o[q] = acc[q] + ((VEC || q < nv) ? E.bias[col + q * cstep] : 0.f);
       st4<VEC>(E.out_f, i0, st, nv, o);
     } break;
     default:
@@ -761,7 +761,7 @@ constexpr int kTThreads = 256;
 
 // (the register cap keeps the compiler from spending registers on the staging
 // round that would leave one wave per SIMD)
-template <bool BF>
+template <bool BF, int TM>
 __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) void convT_kernel(ColGeom G, const float* __restrict__ rho, EpiArgs E) {
   using M = Mma<BF>;
   typedef typename M::BFrag BFrag;
@@ -847,17 +847,40 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     } else {
       if (e0 + tid < e1) epi_load<false>(E, dst_base + e0 + tid, 1, 1, nx);
     }
+    // UT independent tiles per wave at a time (their operand reads overlap)
+    constexpr int UT = 4;
     const int items = mtn * G.ntc;
-    for (int it = wave; it < items; it += NW) {
-      const int mt = it / G.ntc;
-      const int nt = it - mt * G.ntc;
-      const int m = mt * 16 + r;
-      const BFrag* fb = Bl + (size_t)(c * G.ntc + nt) * ks * 64 + lane;
-      const AFrag* fa = reinterpret_cast<const AFrag*>(A) + (size_t)g * G.Mp + m;
-      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-      for (int st = 0; st < ks; ++st) M::mma_frag(fa[(size_t)st * 4 * G.Mp], fb[(size_t)st * 64], acc);
+    for (int it0 = wave; it0 < items; it0 += UT * NW) {
+      const AFrag* fa[UT];
+      const BFrag* fb[UT];
+      int yofs[UT];
+      f32x4 acc[UT];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Y[(mt * 16 + 4 * g + q) * G.Ns + nt * 16 + r] = acc[q];
+      for (int u = 0; u < UT; ++u) {
+        const int it = min(it0 + u * NW, items - 1);
+        const int mt = it / G.ntc;
+        const int nt = it - mt * G.ntc;
+        fa[u] = reinterpret_cast<const AFrag*>(A) + (size_t)g * G.Mp + mt * 16 + r;
+        fb[u] = Bl + (size_t)(c * G.ntc + nt) * ks * 64 + lane;
+        yofs[u] = (mt * 16 + 4 * g) * G.Ns + nt * 16 + r;
+        acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      for (int st = 0; st < ks; ++st) {
+        AFrag av[UT];
+        BFrag bv[UT];
+#pragma unroll
+        for (int u = 0; u < UT; ++u) {
+          av[u] = fa[u][(size_t)st * 4 * G.Mp];
+          bv[u] = fb[u][(size_t)st * 64];
+        }
+#pragma unroll
+        for (int u = 0; u < UT; ++u) M::mma_frag(av[u], bv[u], acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < UT; ++u)
+        if (it0 + u * NW < items)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Y[yofs[u] + q * G.Ns] = acc[u][q];
     }
     __syncthreads();
     if (vec) {
@@ -870,18 +893,51 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         int x = rem - y * G.W;
         const int nb = (ci - c0) * G.khkw;
         float v4[4];
+        if (TM > 0) {
+          // fixed tap loops: table entries past a row's (column's) count hold a
+          // valid offset and their products are masked, so every LDS read of
+          // the group is issued at once
+          int oy[4][TM > 0 ? TM : 1], ox[4][TM > 0 ? TM : 1], ny[4], nxx[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          float sum = 0.f;
-          const int ny = cy[y], nxx = cx[x];
-          for (int ia = 0; ia < ny; ++ia) {
-            const int oy = ty[y * G.Tmax + ia] + nb;
-            for (int ib = 0; ib < nxx; ++ib) sum += Y[oy + tx[x * G.Tmax + ib]];
+          for (int q = 0; q < 4; ++q) {
+            ny[q] = cy[y];
+            nxx[q] = cx[x];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+              oy[q][i] = ty[y * TM + i] + nb;
+              ox[q][i] = tx[x * TM + i];
+            }
+            if (++x == G.W) {
+              x = 0;
+              ++y;
+            }
           }
-          v4[q] = sum;
-          if (++x == G.W) {
-            x = 0;
-            ++y;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float sum = 0.f;
+#pragma unroll
+            for (int ia = 0; ia < TM; ++ia)
+#pragma unroll
+              for (int ib = 0; ib < TM; ++ib) {
+                const float t = Y[oy[q][ia] + ox[q][ib]];
+                sum += (ia < ny[q] && ib < nxx[q]) ? t : 0.f;
+              }
+            v4[q] = sum;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float sum = 0.f;
+            const int ny = cy[y], nxx = cx[x];
+            for (int ia = 0; ia < ny; ++ia) {
+              const int oy = ty[y * G.Tmax + ia] + nb;
+              for (int ib = 0; ib < nxx; ++ib) sum += Y[oy + tx[x * G.Tmax + ib]];
+            }
+            v4[q] = sum;
+            if (++x == G.W) {
+              x = 0;
+              ++y;
+            }
           }
         }
         epi_finish<true>(E, dst_base + e, 1, 4, b, 0, ci, 0, v4, cur);
@@ -924,16 +980,23 @@ hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16,
   if (B == 0) return hipSuccess;
   const size_t lds = convT_lds_bytes_t(g, mma_bf16);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  const void* fn = mma_bf16 ? (const void*)convT_kernel<true> : (const void*)convT_kernel<false>;
+  // tap loops of fixed length where every row and column takes at most one or two taps
+  const void* fn;
+  if (g.Tmax == 1)
+    fn = mma_bf16 ? (const void*)convT_kernel<true, 1> : (const void*)convT_kernel<false, 1>;
+  else if (g.Tmax == 2)
+    fn = mma_bf16 ? (const void*)convT_kernel<true, 2> : (const void*)convT_kernel<false, 2>;
+  else
+    fn = mma_bf16 ? (const void*)convT_kernel<true, 0> : (const void*)convT_kernel<false, 0>;
   if (lds > 64 * 1024) {
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
   }
-  if (mma_bf16)
-    hipLaunchKernelGGL(convT_kernel<true>, dim3(B), dim3(kTThreads), lds, s, g, rho, e);
-  else
-    hipLaunchKernelGGL(convT_kernel<false>, dim3(B), dim3(kTThreads), lds, s, g, rho, e);
-  return hipGetLastError();
+  ColGeom ga = g;
+  const float* ra = rho;
+  EpiArgs ea = e;
+  void* args[] = {(void*)&ga, (void*)&ra, (void*)&ea};
+  return hipLaunchKernel(fn, dim3(B), dim3(kTThreads), args, lds, s);
 }
 
 // ---------------------------------------------------------------------------
