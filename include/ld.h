@@ -268,9 +268,11 @@ int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, const
 
 /* The engine chosen by the autotuner for (B, precision), whether the
  * layer-wise engine runs the independent layer jobs of a phase concurrently on
- * forked streams (1) or in sequence (0), and the measured time per iteration of
- * each engine in microseconds (us_resident = 0 when the resident engine does
- * not fit).  LD_E_STATE if nothing was tuned. */
+ * forked streams (1) or in sequence (0) in iterations launched outside a
+ * captured graph (a captured iteration always runs its jobs in sequence), and
+ * the measured time per iteration of each engine in microseconds (us_resident
+ * = 0 when the resident engine does not fit).  LD_E_STATE if nothing was
+ * tuned. */
 int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, int* concurrent, double* us_layerwise,
                     double* us_resident);
 

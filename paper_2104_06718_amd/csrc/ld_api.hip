@@ -109,8 +109,8 @@ struct ld_net {
   // autotuned launch configurations: (layer, dir, B, mma) -> tile and its time (us)
   std::map<std::tuple<int, int, int, int>, Tile> tiles;
   std::map<std::tuple<int, int, int, int>, double> tile_us;
-  // autotuned engine: (B, mma) -> {engine, us per iteration layer-wise (best of forked and
-  // sequential phases), resident (0: does not fit), phases forked (1) or not (0)}
+  // autotuned engine: (B, mma) -> {engine, us per iteration layer-wise (graph replay),
+  // resident (0: does not fit), phases of eager iterations forked (1) or not (0)}
   std::map<std::pair<int, int>, std::array<double, 4>> engines;
   int tune_gen = 0;  // bumped whenever a tuned choice changes (part of the graph key)
   std::mutex mu;
@@ -135,7 +135,11 @@ struct ld_state {
   // the layer jobs of one phase are independent: they run on the caller's stream
   // and two more, forked and joined around each phase
   hipStream_t side[2] = {nullptr, nullptr};
-  int fork = 1;  // fork the phases onto the side streams (tuned per batch size and precision)
+  int fork = 1;  // fork the phases of eager iterations onto the side streams (tuned per batch size and precision)
+  // set while an iteration is being captured into a graph: the captured phases run
+  // in sequence, so cross-stream events never enter a graph and an event's
+  // lifetime never depends on a graph's
+  bool capturing = false;
   hipEvent_t ev_fork = nullptr;
   // recorded after the last work enqueued on the state's memory and graph; waited
   // on before the graph is replaced or the state is freed (a graph exec or a
@@ -694,7 +698,9 @@ int prepare_objective(const ld_net* net, const ld_batch* bt, Workspace& ws, int 
 
 // Fork/join of the independent layer jobs of a phase.
 constexpr int kSide = 2;
-bool forking(const ld_state* st) { return st != nullptr && st->side[0] != nullptr && st->fork != 0; }
+bool forking(const ld_state* st) {
+  return st != nullptr && st->side[0] != nullptr && st->fork != 0 && !st->capturing;
+}
 hipError_t fork_begin(const ld_state* st, hipStream_t s) {
   if (!forking(st)) return hipSuccess;
   hipError_t e = hipEventRecord(st->ev_fork, s);
@@ -881,7 +887,7 @@ void destroy_graph(ld_state* st) {
   st->gchunk = 0;
 }
 
-std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int chunk, int net_tune_gen, int fork) {
+std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int chunk, int net_tune_gen) {
   std::vector<double> k;
   auto P = [&](const void* p) { k.push_back((double)(uintptr_t)p); };
   k.push_back(bt->B);
@@ -902,7 +908,6 @@ std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int c
   k.push_back(o->tie_tau);
   k.push_back(chunk);
   k.push_back(net_tune_gen);
-  k.push_back(fork);
   return k;
 }
 
@@ -1386,6 +1391,101 @@ static int ensure_initialised(const ld_net* net, const ld_batch* bt, ld_state* s
   return LD_OK;
 }
 
+// Graph of `chunk` ascent iterations, built node by node.  Each layer job of a
+// phase is captured alone (no stream fork, no event) into a scratch graph, a
+// chain of one or two kernel nodes; the parent graph receives copies of those
+// kernel nodes for every iteration: per phase, the first node of every job's
+// chain depends on the last nodes of all jobs of the previous phase, so the jobs
+// of a phase are independent branches and the phases follow one another in the
+// order of iteration().
+static int build_graph(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, int chunk,
+                       hipGraph_t* out) {
+  const int n = net->n, B = bt->B, mma = o->precision == LD_BF16 ? 1 : 0;
+  std::vector<const float*> rho(st->rho.begin(), st->rho.end());
+  std::vector<hipGraph_t> job;                          // [phase A jobs][phase B jobs]
+  std::vector<std::vector<hipKernelNodeParams>> chain;  // kernel nodes of each job, in order
+  hipGraph_t g = nullptr;
+  auto release = [&]() {
+    for (hipGraph_t c : job)
+      if (c) (void)hipGraphDestroy(c);
+    if (g) (void)hipGraphDestroy(g);
+  };
+  auto failed = [&](const char* what, hipError_t e) {
+    release();
+    return fail(LD_E_DEVICE, std::string(what) + hipGetErrorString(e));
+  };
+  for (int phase = 0; phase < 2; ++phase)
+    for (int k = 1; k <= n - 1; ++k) {
+      const Layer& L = net->L[k - 1];
+      hipError_t e = hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return failed("graph capture: ", e);
+      st->capturing = true;
+      if (phase == 0) {
+        const EpiArgs ea = epi_phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, st->t_dev, st->adam, o, k);
+        e = run_job(L.tr, B, rho[k - 1], 0, mma, ea, pick_tile(net, k - 1, 1, B, mma), st->ws, k - 1, st->cap);
+      } else {
+        const EpiArgs eb = epi_phase_b(net, bt, st, o, k);
+        e = run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, eb, pick_tile(net, k - 1, 0, B, mma), st->ws, k - 1, st->cap);
+      }
+      hipGraph_t c = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(st->cap, &c);
+      st->capturing = false;
+      job.push_back(c);
+      if (e != hipSuccess || e2 != hipSuccess) return failed("graph capture: ", e != hipSuccess ? e : e2);
+      // order the job's kernel nodes along their dependencies (a chain)
+      size_t nn = 0;
+      if ((e = hipGraphGetNodes(c, nullptr, &nn)) != hipSuccess) return failed("graph nodes: ", e);
+      std::vector<hipGraphNode_t> nodes(nn);
+      if (nn && (e = hipGraphGetNodes(c, nodes.data(), &nn)) != hipSuccess) return failed("graph nodes: ", e);
+      std::vector<hipKernelNodeParams> ch;
+      hipGraphNode_t prev = nullptr;
+      for (size_t step = 0; step < nn; ++step) {
+        hipGraphNode_t next = nullptr;
+        for (hipGraphNode_t x : nodes) {
+          size_t nd = 0;
+          if ((e = hipGraphNodeGetDependencies(x, nullptr, &nd)) != hipSuccess) return failed("graph nodes: ", e);
+          hipGraphNode_t d = nullptr;
+          if (nd == 1 && (e = hipGraphNodeGetDependencies(x, &d, &nd)) != hipSuccess) return failed("graph nodes: ", e);
+          if ((prev == nullptr && nd == 0) || (prev != nullptr && nd == 1 && d == prev)) {
+            next = x;
+            break;
+          }
+        }
+        hipGraphNodeType type;
+        if (next == nullptr || hipGraphNodeGetType(next, &type) != hipSuccess || type != hipGraphNodeTypeKernel) {
+          release();
+          return fail(LD_E_DEVICE, "a layer job did not capture as a chain of kernel nodes");
+        }
+        hipKernelNodeParams kp;
+        if ((e = hipGraphKernelNodeGetParams(next, &kp)) != hipSuccess) return failed("graph nodes: ", e);
+        ch.push_back(kp);
+        prev = next;
+      }
+      chain.push_back(ch);
+    }
+  hipError_t e = hipGraphCreate(&g, 0);
+  std::vector<hipGraphNode_t> before, last;  // last nodes of the previous phase's jobs, of this phase's
+  for (int it = 0; it < chunk && e == hipSuccess; ++it)
+    for (int phase = 0; phase < 2 && e == hipSuccess; ++phase) {
+      last.clear();
+      for (int j = 0; j < n - 1 && e == hipSuccess; ++j) {
+        std::vector<hipGraphNode_t> deps = before;
+        for (const hipKernelNodeParams& kp : chain[phase * (n - 1) + j]) {
+          hipGraphNode_t node = nullptr;
+          e = hipGraphAddKernelNode(&node, g, deps.empty() ? nullptr : deps.data(), deps.size(), &kp);
+          if (e != hipSuccess) break;
+          deps.assign(1, node);
+        }
+        if (e == hipSuccess && !chain[phase * (n - 1) + j].empty()) last.push_back(deps[0]);
+      }
+      before = last;
+    }
+  if (e != hipSuccess) return failed("graph build: ", e);
+  for (hipGraph_t c : job) (void)hipGraphDestroy(c);  // the parent holds its own copies of the nodes
+  *out = g;
+  return LD_OK;
+}
+
 // The ascent of one ld_step call on an initialised state, engine already chosen.
 static int step_impl(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
   if (o->iters == 0) return LD_OK;
@@ -1403,21 +1503,13 @@ static int step_impl(const ld_net* net, const ld_batch* bt, ld_state* st, const 
     }
   }
   const int chunk = std::min(o->iters, 100);
-  std::vector<double> key = graph_key(bt, o, net->n, chunk, net->tune_gen, st->fork);
+  std::vector<double> key = graph_key(bt, o, net->n, chunk, net->tune_gen);
   if (!st->gexec || key != st->gkey) {
     destroy_graph(st);
-    LD_HIP(hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal));
-    int rc = LD_OK;
-    for (int i = 0; i < chunk && rc == LD_OK; ++i) rc = iteration(net, bt, st, o, st->cap);
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(st->cap, &g);
-    if (rc != LD_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
-    }
-    if (e != hipSuccess) return fail(LD_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    LD_TRY(build_graph(net, bt, st, o, chunk, &g));
     st->graph = g;
-    e = hipGraphInstantiate(&st->gexec, g, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&st->gexec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
       destroy_graph(st);
       return fail(LD_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
@@ -1533,15 +1625,20 @@ static int autotune_impl(const ld_net* net, const ld_batch* bt, const ld_opts* o
     to.engine = engine;
     return step_impl(net, bt, tmp, &to, s);
   };
-  double us_fork = 0, us_seq = 0, us_res = 0;
-  tmp->fork = 1;
-  LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_LAYERWISE); }, s, e0, e1, 1, &us_fork));
-  tmp->fork = 0;
-  LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_LAYERWISE); }, s, e0, e1, 1, &us_seq));
+  double us_lw = 0, us_fork = 0, us_seq = 0, us_res = 0;
+  LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_LAYERWISE); }, s, e0, e1, 1, &us_lw));
+  // phases of eager iterations (outside a captured graph) forked or in sequence
+  auto eager = [&](int f) -> int {
+    tmp->fork = f;
+    for (int i = 0; i < 4; ++i) LD_TRY(iteration(net, bt, tmp, &to, s));
+    return LD_OK;
+  };
+  LD_TRY(time_calls([&]() { return eager(1); }, s, e0, e1, 1, &us_fork));
+  LD_TRY(time_calls([&]() { return eager(0); }, s, e0, e1, 1, &us_seq));
+  LD_HIP(hipEventRecord(tmp->done, s));
   if (resident_shape(net, B, mma).S > 0) LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_RESIDENT); }, s, e0, e1, 1, &us_res));
   LD_HIP(hipStreamSynchronize(s));
   const int fork = us_fork <= us_seq ? 1 : 0;
-  const double us_lw = std::min(us_fork, us_seq);
   const int eng = (us_res > 0 && us_res < us_lw) ? LD_ENGINE_RESIDENT : LD_ENGINE_LAYERWISE;
   std::lock_guard<std::mutex> lk(mnet->mu);
   mnet->engines[{B, mma}] = {(double)eng, us_lw / T, us_res / T, (double)fork};
