@@ -85,8 +85,10 @@ def layer_slot_cost(inst, kind, B, prec):
     return B * nb + wbytes(L), B * 2 * macs(L)
 
 
-def kernel_name(info, kind, inst):
-    """Name of the kernel launched for an iteration slot under the tuned configuration."""
+def kernel_name(info, kind, inst, prec="fp32"):
+    """Name of the kernel launched for an iteration slot under the tuned configuration
+    (in the BF16 form, transposed products of layers k >= 2 are compensated products,
+    which the stride-class form computes)."""
     ph, k = divmod(kind, 100)
     L = inst.layers[k - 1]
     cfg = None
@@ -95,7 +97,8 @@ def kernel_name(info, kind, inst):
         cfg = next((e for e in info["layers"] if e["layer"] == k and e["dir"] == d), None)
     if L.kind == "linear":
         return "fc_kernel"
-    if ph == 1 and L.stride > 1 and (cfg is None or cfg["form"] == 0):
+    compensated = prec == "bf16" and ph == 1 and k >= 2
+    if ph == 1 and L.stride > 1 and (cfg is None or cfg["form"] == 0) and not compensated:
         return "convT_kernel"
     return "conv_plane_kernel"
 
@@ -199,7 +202,7 @@ def main():
         torch.cuda.synchronize()
         info = P.tuning_info(net, B, a.profile_only)
         print(json.dumps({"profile_only": a.profile_only, "config": a.config, "B": B, "reps": a.reps,
-                          "slots": [[k, kernel_name(info, k, inst), round(v, 2)] for k, v in slots],
+                          "slots": [[k, kernel_name(info, k, inst, a.profile_only), round(v, 2)] for k, v in slots],
                           "tuned": info}), flush=True)
         return
 
@@ -207,23 +210,33 @@ def main():
     res32 = run_form(P, net, batch, st, T, "fp32", a.steps, a.warmup, a.engine)
     b32 = res32["fb"]["bound"].clone()
 
-    # BF16 form: iterations needed to reach the FP32 form's bound (mean gap <= 1e-3),
-    # searched upward from T in steps of 50
+    # BF16 form: iterations needed to reach the FP32 form's bound (mean gap <= 1e-3):
+    # bracketed upward from T in steps of 50, then bisected down to 5 iterations
     st16 = P.State(net, B)
     T16 = a.bf16_iters or T
     tries = []
     if not a.quick and a.bf16_iters is None:
-        t = T
-        while t <= 3 * T:
+        def reaches(t):
             st16.reset()
             P.step(net, batch, st16, iters=t, total_iters=t, precision="bf16", engine=a.engine)
             bb = P.final_bound(net, batch, st16)["bound"]
             gap = (b32 - bb).mean().item()
             tries.append((t, round(gap, 6)))
-            T16 = t
-            if gap <= 1e-3:
+            return gap <= 1e-3
+        lo, hi, t = None, None, T
+        while t <= 3 * T:
+            if reaches(t):
+                hi = t
                 break
-            t += 50
+            lo, t = t, t + 50
+        if hi is not None and lo is not None:
+            while hi - lo > 5:
+                mid = (lo + hi) // 2
+                if reaches(mid):
+                    hi = mid
+                else:
+                    lo = mid
+        T16 = hi if hi is not None else tries[-1][0]
     res16 = run_form(P, net, batch, st16, T16, "bf16", a.steps, a.warmup, a.engine)
     b16 = res16["fb"]["bound"]
     d = (b16 - b32)
@@ -248,7 +261,7 @@ def main():
     else:
         roof = dict(bound="mfma", achieved=flops / (us * 1e-6) / 1e12, peak=PEAK_TFLOPS[head], unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    kname = kernel_name(tuned[head], kind, inst)
+    kname = kernel_name(tuned[head], kind, inst, head)
     roof["traffic"] = stored_traffic(kname, kind, a.config, B, head)
     roof["kernel"] = f"{kname}: slot {kind} (phase {kind // 100}, layer {kind % 100})"
     roof["avg_us"] = us

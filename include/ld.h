@@ -188,9 +188,18 @@ int ld_dual_eval(const ld_net* net, const ld_batch* batch, const float* const* r
  *             so several calls of k steps equal one call of their sum.
  * beta1, beta2, eps  Adam constants; the update is an ascent step
  *             rho += lr_t * mhat / (sqrt(vhat) + eps) with bias correction.
- * precision   LD_FP32 or LD_BF16 (BF16 operands, FP32 accumulation) for the
- *             contractions of the ascent; the bound is always re-evaluated with
- *             FP32 operands and an FP64 sum (ld_final_bound).
+ * precision   LD_FP32 or LD_BF16 for the contractions of the ascent.  LD_BF16:
+ *             every contraction runs on BF16 MFMA with FP32 accumulation; the
+ *             forward products W_k x and the product W_1^T rho_1 into the input
+ *             box take plain BF16 operands, while the products W_k^T rho_k
+ *             (k >= 2) whose result decides a ReLU layer's inner minimisation
+ *             are compensated: each operand is a BF16 head plus a BF16
+ *             remainder and three MFMA terms are summed (head*head + head*rem
+ *             + rem*head).  The constant -W_n^T c is formed with FP32 operands
+ *             in both precisions.  The resident engine's BF16 form uses plain
+ *             BF16 throughout (AUTO picks it for FP32 only).  The bound is
+ *             always re-evaluated with FP32 operands and an FP64 sum
+ *             (ld_final_bound).
  * init        used on the first call of a state: LD_INIT_CROWN (default of
  *             the paper, Sec. 7.2), LD_INIT_ZERO, or LD_INIT_GIVEN (duals set
  *             by ld_state_set_rho).  On that call q(rho^0) is stored.

@@ -57,6 +57,12 @@ uint16_t host_f2bf(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
+float host_bf2f(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
 
 // One contraction of a layer: one GemmGeom per stride class (M is set per launch).
 struct Job {
@@ -166,12 +172,14 @@ int finish_geom(ld_net* net, GemmGeom& g, const std::vector<float>& Bnk, const s
   g.Kp = (int)round_up((size_t)std::max(g.K, 1), 64);
   g.Np = (int)round_up((size_t)std::max(g.N, 1), 128);
   std::vector<float> bf((size_t)g.Np * g.Kp, 0.f);
-  std::vector<uint16_t> bh((size_t)g.Np * g.Kp, 0);
+  std::vector<uint16_t> bh((size_t)g.Np * g.Kp, 0), bl((size_t)g.Np * g.Kp, 0);
   for (int n = 0; n < g.N; ++n)
     for (int k = 0; k < g.K; ++k) {
       const float w = Bnk[(size_t)n * g.K + k];
+      const uint16_t h = host_f2bf(w);
       bf[(size_t)n * g.Kp + k] = w;
-      bh[(size_t)n * g.Kp + k] = host_f2bf(w);
+      bh[(size_t)n * g.Kp + k] = h;
+      bl[(size_t)n * g.Kp + k] = host_f2bf(w - host_bf2f(h));  // exact difference, rounded to BF16
     }
   std::vector<int4> kt((size_t)g.Kp, int4{0, 0, 0, 0});
   for (int k = 0; k < g.K; ++k) kt[k] = ktab[k];
@@ -187,15 +195,18 @@ int finish_geom(ld_net* net, GemmGeom& g, const std::vector<float>& Bnk, const s
     LD_HIP(hipMemcpy(pl, kl.data(), kl.size() * 4, hipMemcpyHostToDevice));
     g.ktab_lds = (const int*)pl;
   }
-  void *pf, *ph, *pk;
+  void *pf, *ph, *phl, *pk;
   LD_TRY(alloc_dev(net, &pf, bf.size() * 4));
   LD_TRY(alloc_dev(net, &ph, bh.size() * 2));
+  LD_TRY(alloc_dev(net, &phl, bl.size() * 2));
   LD_TRY(alloc_dev(net, &pk, kt.size() * sizeof(int4)));
   LD_HIP(hipMemcpy(pf, bf.data(), bf.size() * 4, hipMemcpyHostToDevice));
   LD_HIP(hipMemcpy(ph, bh.data(), bh.size() * 2, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(phl, bl.data(), bl.size() * 2, hipMemcpyHostToDevice));
   LD_HIP(hipMemcpy(pk, kt.data(), kt.size() * sizeof(int4), hipMemcpyHostToDevice));
   g.Bf = (const float*)pf;
   g.Bh = (const bf16_t*)ph;
+  g.Bhl = (const bf16_t*)phl;
   g.ktab = (const int4*)pk;
   return LD_OK;
 }
@@ -466,7 +477,8 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
   if ((int)L.tr.geoms.size() > 9) return fail(LD_E_UNSUPPORTED, "conv stride above 3 is not supported");
   LD_TRY(build_col(net, L, W));
   if (conv_lds_bytes(L.fwd.geoms.data(), 1, 1, 0) > 160 * 1024 ||
-      conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size(), 1, 0) > 160 * 1024)
+      std::max(conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size(), 1, 0),
+               conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size(), 1, 2)) > 160 * 1024)
     return fail(LD_E_UNSUPPORTED, "conv maps too large for the LDS images of one subdomain");
   return LD_OK;
 }
@@ -589,7 +601,8 @@ std::vector<Tile> tile_candidates(const Job& J, int B) {
   if (job_is_conv(J)) {
     if (J.has_col) c.push_back(Tile{1, 1, 1, 0, 1});
     for (int tn : tns)
-      if (conv_lds_bytes(J.geoms.data(), (int)J.geoms.size(), tn, 0) <= 160 * 1024)
+      if (std::max(conv_lds_bytes(J.geoms.data(), (int)J.geoms.size(), tn, 0),
+                   conv_lds_bytes(J.geoms.data(), (int)J.geoms.size(), tn, 2)) <= 160 * 1024)
         c.push_back(Tile{1, tn, 1, J.has_col ? 1 : 0, 1});
   } else {
     // one block along K: every (wm, kw) shape of up to 16 waves; several blocks
@@ -633,11 +646,20 @@ hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, 
     g[i] = J.geoms[i];
     g[i].M = B * g[i].HWq;
   }
-  if (J.has_col && t.form == 0) return launch_convT(J.col, B, (const float*)src, mma, e, s);
+  // the dense GEMM + col2im form has no compensated BF16 product: mode 2 takes the stride-class form
+  if (J.has_col && t.form == 0 && mma != 2) return launch_convT(J.col, B, (const float*)src, mma, e, s);
   if (job_is_conv(J)) return launch_conv(g, J.dev, nc, B, src, src_bf16, mma, e, t.tn, s);
   SplitArgs sp{fc_splits(J, B, t.tn, t.splits), ws.partial + (size_t)slot * kPartialLayer, ws.counters};
   return launch_fc(g[0], src, src_bf16, mma, e, t.tn, sp, std::max(1, t.wm), t.tm, s);
 }
+
+// Operand mode of the transposed product W_k^T rho_k (layer k = 1..n) for a precision
+// (0 FP32, 1 BF16): in the BF16 form, the products whose result is the coefficient
+// of a ReLU layer's inner minimisation (k >= 2) use the compensated BF16 product
+// (mode 2: heads and remainders of both operands); the product into the input box
+// (k = 1) uses plain BF16.  The constant -W_n^T c is formed in FP32 (mode 0) by its
+// caller.
+int tr_mode(int mma, int k) { return mma == 1 && k >= 2 ? 2 : mma; }
 
 EpiArgs epi0() {
   EpiArgs e;
@@ -691,7 +713,7 @@ int prepare_objective(const ld_net* net, const ld_batch* bt, Workspace& ws, int 
   e.kind = EPI_STORE;
   e.scale = -1.f;
   e.out_f = ws.gconst;
-  LD_HIP(run_job(Ln.tr, bt->B, bt->c, 0, mma, e, pick_tile(net, n - 1, 1, bt->B, mma), ws, n - 1, s));
+  LD_HIP(run_job(Ln.tr, bt->B, bt->c, 0, 0, e, pick_tile(net, n - 1, 1, bt->B, mma), ws, n - 1, s));
   LD_HIP(launch_cdot(bt->B, Ln.n_out, bt->c, nullptr, Ln.bias, ws.cb, s));
   return LD_OK;
 }
@@ -775,7 +797,7 @@ int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Work
     const Layer& L = net->L[k - 1];
     const EpiArgs e = epi_phase_a(net, bt, rho, ws, mma, tau, want_val, t_dev, adam, o, k);
     const hipStream_t sk = fork_stream(fk, s, k - 1);
-    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, sk));
+    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, tr_mode(mma, k), e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, sk));
   }
   LD_HIP(fork_end(fk, s));
   if (o != nullptr) return LD_OK;
@@ -834,7 +856,7 @@ int init_impl(const ld_net* net, const ld_batch* bt, int init, int mma, float* c
     e.lo = bt->l[k - 2];
     e.hi = bt->u[k - 2];
     e.out_f = rho[k - 2];
-    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, mma, e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, s));
+    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, tr_mode(mma, k), e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, s));
   }
   return LD_OK;
 }
@@ -1422,7 +1444,8 @@ static int build_graph(const ld_net* net, const ld_batch* bt, ld_state* st, cons
       st->capturing = true;
       if (phase == 0) {
         const EpiArgs ea = epi_phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, st->t_dev, st->adam, o, k);
-        e = run_job(L.tr, B, rho[k - 1], 0, mma, ea, pick_tile(net, k - 1, 1, B, mma), st->ws, k - 1, st->cap);
+        e = run_job(L.tr, B, rho[k - 1], 0, tr_mode(mma, k), ea, pick_tile(net, k - 1, 1, B, mma), st->ws, k - 1,
+                    st->cap);
       } else {
         const EpiArgs eb = epi_phase_b(net, bt, st, o, k);
         e = run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, eb, pick_tile(net, k - 1, 0, B, mma), st->ws, k - 1, st->cap);
@@ -1594,7 +1617,7 @@ static int autotune_impl(const ld_net* net, const ld_batch* bt, const ld_opts* o
         auto launch = [&]() -> int {
           if (dir == 1) {
             const EpiArgs e = epi_phase_a(net, bt, rho.data(), tmp->ws, mma, o->tie_tau, 0, nullptr, nullptr, nullptr, k);
-            LD_HIP(run_job(J, B, rho[k - 1], 0, mma, e, t, tmp->ws, k - 1, s));
+            LD_HIP(run_job(J, B, rho[k - 1], 0, tr_mode(mma, k), e, t, tmp->ws, k - 1, s));
           } else {
             const EpiArgs e = epi_phase_b(net, bt, tmp, &to, k);
             LD_HIP(run_job(J, B, tmp->ws.xs[k - 1], mma, mma, e, t, tmp->ws, k - 1, s));
@@ -1636,7 +1659,10 @@ static int autotune_impl(const ld_net* net, const ld_batch* bt, const ld_opts* o
   LD_TRY(time_calls([&]() { return eager(1); }, s, e0, e1, 1, &us_fork));
   LD_TRY(time_calls([&]() { return eager(0); }, s, e0, e1, 1, &us_seq));
   LD_HIP(hipEventRecord(tmp->done, s));
-  if (resident_shape(net, B, mma).S > 0) LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_RESIDENT); }, s, e0, e1, 1, &us_res));
+  // the resident engine's BF16 form uses plain BF16 transposed products (no
+  // compensated product): it is offered to AUTO for FP32 only
+  if (mma == 0 && resident_shape(net, B, mma).S > 0)
+    LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_RESIDENT); }, s, e0, e1, 1, &us_res));
   LD_HIP(hipStreamSynchronize(s));
   const int fork = us_fork <= us_seq ? 1 : 0;
   const int eng = (us_res > 0 && us_res < us_lw) ? LD_ENGINE_RESIDENT : LD_ENGINE_LAYERWISE;
@@ -1782,7 +1808,7 @@ int ld_profile_iteration(const ld_net* net, const ld_batch* bt, ld_state* st, co
       auto launch = [&]() -> int {
         if (dir == 1) {
           const EpiArgs e = epi_phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, nullptr, nullptr, nullptr, k);
-          LD_HIP(run_job(J, B, rho[k - 1], 0, mma, e, t, st->ws, k - 1, s));
+          LD_HIP(run_job(J, B, rho[k - 1], 0, tr_mode(mma, k), e, t, st->ws, k - 1, s));
         } else {
           const EpiArgs e = epi_phase_b(net, bt, st, o, k);
           LD_HIP(run_job(J, B, st->ws.xs[k - 1], mma, mma, e, t, st->ws, k - 1, s));

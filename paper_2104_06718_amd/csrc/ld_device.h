@@ -115,6 +115,30 @@ struct Mma<true> {
   __device__ static void mma_frag(const AFrag& a, const BFrag& b, f32x4& c) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
+  // Compensated product: a and the weights each as a BF16 head plus a BF16
+  // remainder (w = bh + bl), c += a_l*bh + a_h*bl + a_h*bh (the a_l*bl term, of
+  // relative size 2^-16, is dropped); FP32 accumulation, small terms first.
+  __device__ static void split(const float (&a)[8], bf16x8& ah, bf16x8& al) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      ah[j] = (__bf16)a[j];
+      al[j] = (__bf16)(a[j] - (float)ah[j]);
+    }
+  }
+  __device__ static void mma3(const float (&a)[8], const BFrag& bh, const BFrag& bl, f32x4& c) {
+    bf16x8 ah, al;
+    split(a, ah, al);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  }
+  __device__ static void mma3_wx(const BFrag& wh, const BFrag& wl, const float (&x)[8], f32x4& c) {
+    bf16x8 xh, xl;
+    split(x, xh, xl);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, xh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xh, c, 0, 0, 0);
+  }
   __device__ static void mma_wx(const BFrag& w, const float (&x)[8], f32x4& c) {
     bf16x8 xv;
 #pragma unroll

@@ -27,6 +27,7 @@ struct GemmGeom {
   int N, Np;           // output columns; padded (multiple of 128)
   const float* Bf;     // [Np][Kp] FP32 operand, column-major in k ("n-major")
   const bf16_t* Bh;    // [Np][Kp] BF16 operand
+  const bf16_t* Bhl;   // [Np][Kp] BF16 remainder Bf - Bh (compensated BF16 products)
   int dst_n;           // destination elements per subdomain
   int dst_HW, dst_W;
   int oy_mul, oy_off, ox_mul, ox_off;

@@ -278,11 +278,13 @@ __device__ __forceinline__ int fdiv(int e, int d, float inv) {
 // LDS words holding the class geometries (copied from device memory at staging)
 constexpr int kGeoWords = (int)((sizeof(GemmGeom) + 15) / 16 * 4);
 
-template <bool MMA_BF16, bool SRC_BF16, int TN>
+// MM: operands of the product: 0 FP32, 1 BF16, 2 compensated BF16 (FP32 source)
+template <int MM, bool SRC_BF16, int TN>
 __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, const GemmGeom* __restrict__ geo_dev,
                                                          const void* __restrict__ src_v, EpiArgs E,
                                                          int img_floats, int dst_hw4, int kp_max, int n_eff,
                                                          int bstride) {
+  constexpr bool MMA_BF16 = MM != 0;
   using M = Mma<MMA_BF16>;
   typedef typename M::BFrag BFrag;
   typedef typename std::conditional<MMA_BF16, bf16_t, float>::type WT;
@@ -299,6 +301,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   float* outp = img + img_floats;                          // [dst_n]
   int* kofs = reinterpret_cast<int*>(outp + G0.dst_n);     // [n classes][kp_max]
   WT* wB = reinterpret_cast<WT*>(lds + ((P.n * kGeoWords + img_floats + G0.dst_n + P.n * kp_max + 3) & ~3));  // [n classes][n_eff][bstride], 16-byte aligned
+  WT* wBl = wB + (size_t)P.n * n_eff * bstride;  // MM == 2: the BF16 remainders, same layout
 
   adam_tick(E);
   for (int i = tid; i < P.n * kGeoWords; i += kConvThreads) {
@@ -381,10 +384,17 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
     const int vr = G.Kp / EPV;
     const float inv_vr = 1.0f / (float)vr;
     const uint4* srcw = reinterpret_cast<const uint4*>(MMA_BF16 ? (const void*)G.Bh : (const void*)G.Bf);
+    const uint4* srcl = reinterpret_cast<const uint4*>(G.Bhl);
     for (int e = tid; e < n_eff * vr; e += kConvThreads) {
       const int row = fdiv(e, vr, inv_vr);
       const int v = e - row * vr;
-      *reinterpret_cast<uint4*>(wB + ((size_t)c * n_eff + row) * bstride + v * EPV) = srcw[(size_t)row * vr + v];
+      const size_t o = ((size_t)c * n_eff + row) * bstride + v * EPV;
+      const uint4 w = srcw[(size_t)row * vr + v];
+      if (MM == 2) {
+        const uint4 wl = srcl[(size_t)row * vr + v];
+        *reinterpret_cast<uint4*>(wBl + o) = wl;
+      }
+      *reinterpret_cast<uint4*>(wB + o) = w;
     }
   }
   __syncthreads();
@@ -416,6 +426,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
     G.ox_off = __builtin_amdgcn_readfirstlane(Gl->ox_off);
     const int* ko = kofs + cl * kp_max;
     const WT* wc = wB + (size_t)cl * n_eff * bstride;
+    const WT* wcl = wBl + (size_t)cl * n_eff * bstride;
     const float inv_wq = 1.0f / (float)G.Wq;
     const int ntiles = (G.HWq + 15) >> 4;
     const int nct = (G.N + 16 * TN - 1) / (16 * TN);
@@ -441,8 +452,12 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
         for (int j = 0; j < VPL; ++j) a[j] = img[lb + ko[kl + j]];
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
-          const BFrag bf = *reinterpret_cast<const BFrag*>(wc + (size_t)(nc + 16 * t + r) * bstride + kl);
-          M::mma(a, bf, acc[t]);
+          const size_t wo = (size_t)(nc + 16 * t + r) * bstride + kl;
+          const BFrag bf = *reinterpret_cast<const BFrag*>(wc + wo);
+          if constexpr (MM == 2)
+            M::mma3(a, bf, *reinterpret_cast<const BFrag*>(wcl + wo), acc[t]);
+          else
+            M::mma(a, bf, acc[t]);
         }
       }
       // the lane's four rows are consecutive pixels of the class grid
@@ -498,10 +513,10 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
 // fc_split_reduce adds the partials in split order, then runs the epilogue
 // (deterministic, no cross-block synchronisation).
 // ---------------------------------------------------------------------------
-template <int TN, bool MMA_BF16, bool SRC_BF16>
+template <int TN, int MM, bool SRC_BF16>
 __global__ __launch_bounds__(1024) void fc_kernel(GemmGeom G, const void* __restrict__ src_v, EpiArgs E, SplitArgs S,
                                                   int wm, int kw) {
-  using M = Mma<MMA_BF16>;
+  using M = Mma<(MM != 0)>;
   constexpr int KS = M::KS, VPL = M::VPL;
   extern __shared__ float red[];  // [kw-1][wm waves][TN][4][64]
   adam_tick(E);
@@ -565,8 +580,12 @@ __global__ __launch_bounds__(1024) void fc_kernel(GemmGeom G, const void* __rest
     }
 #pragma unroll
     for (int t = 0; t < TN; ++t) {
-      const typename M::BFrag w = M::loadB(G, (size_t)(n0 + 16 * t + r) * G.Kp + kl);
-      M::mma_wx(w, x, acc[t]);
+      const size_t wo = (size_t)(n0 + 16 * t + r) * G.Kp + kl;
+      const typename M::BFrag w = M::loadB(G, wo);
+      if constexpr (MM == 2)
+        M::mma3_wx(w, *reinterpret_cast<const typename M::BFrag*>(G.Bhl + wo), x, acc[t]);
+      else
+        M::mma_wx(w, x, acc[t]);
     }
   }
   if (kw > 1) {
@@ -655,7 +674,8 @@ static int conv_n_eff(const GemmGeom& g, int tn) { return (g.N + 16 * tn - 1) / 
 static int conv_bstride(const GemmGeom* g, int n, int mma_bf16) { return max_kp(g, n) + (mma_bf16 ? 8 : 4); }
 
 size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16) {
-  const size_t wbytes = (size_t)n_classes * conv_n_eff(g[0], tn) * conv_bstride(g, n_classes, mma_bf16) * (mma_bf16 ? 2 : 4);
+  // BF16 weights (mode 1), FP32 (0), or BF16 heads and remainders (2)
+  const size_t wbytes = (size_t)n_classes * conv_n_eff(g[0], tn) * conv_bstride(g, n_classes, mma_bf16) * (mma_bf16 == 1 ? 2 : 4);
   return (((size_t)n_classes * kGeoWords + conv_img_floats(g[0]) + g[0].dst_n + (size_t)n_classes * max_kp(g, n_classes) +
            3) & ~(size_t)3) * 4 +
          wbytes;
@@ -672,27 +692,26 @@ static hipError_t launch_conv_tn(const GemmPack& P, const GemmGeom* geo_dev, int
   const int neff = conv_n_eff(G, TN), bst = conv_bstride(P.g, P.n, mma_bf16);
   dim3 grid(B), block(kConvThreads);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const void* fn;
+  if (mma_bf16 == 1)
+    fn = src_bf16 ? (const void*)conv_plane_kernel<1, true, TN> : (const void*)conv_plane_kernel<1, false, TN>;
+  else if (mma_bf16 == 2 && !src_bf16)
+    fn = (const void*)conv_plane_kernel<2, false, TN>;
+  else if (mma_bf16 == 0 && !src_bf16)
+    fn = (const void*)conv_plane_kernel<0, false, TN>;
+  else
+    return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
-    (void)hipFuncSetAttribute((const void*)conv_plane_kernel<true, true, TN>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)conv_plane_kernel<true, false, TN>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)conv_plane_kernel<false, false, TN>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
   }
-  if (mma_bf16) {
-    if (src_bf16)
-      hipLaunchKernelGGL((conv_plane_kernel<true, true, TN>), grid, block, lds, s, P, geo_dev, src, e, img, hw4, kpm, neff,
-                         bst);
-    else
-      hipLaunchKernelGGL((conv_plane_kernel<true, false, TN>), grid, block, lds, s, P, geo_dev, src, e, img, hw4, kpm, neff,
-                         bst);
-  } else {
-    if (src_bf16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((conv_plane_kernel<false, false, TN>), grid, block, lds, s, P, geo_dev, src, e, img, hw4, kpm, neff,
-                         bst);
-  }
-  return hipGetLastError();
+  GemmPack pa = P;
+  const GemmGeom* ga = geo_dev;
+  const void* sa = src;
+  EpiArgs ea = e;
+  int a0 = img, a1 = hw4, a2 = kpm, a3 = neff, a4 = bst;
+  void* args[] = {(void*)&pa, (void*)&ga, (void*)&sa, (void*)&ea, (void*)&a0, (void*)&a1, (void*)&a2, (void*)&a3, (void*)&a4};
+  return hipLaunchKernel(fn, grid, block, args, lds, s);
 }
 
 hipError_t launch_conv(const GemmGeom* geoms, const GemmGeom* geo_dev, int n, int B, const void* src, int src_bf16,
@@ -717,14 +736,17 @@ static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16,
   const int gx = (G.M + mt - 1) / mt, gy = (G.N + 16 * TN - 1) / (16 * TN);  // subdomain blocks, neuron blocks
   dim3 grid(gx, gy, sp.splits), block(64 * wm * kw);
   const size_t lds = (size_t)(kw - 1) * wm * TN * 4 * 64 * 4;
-  if (mma_bf16) {
+  if (mma_bf16 == 1) {
     if (src_bf16)
-      hipLaunchKernelGGL((fc_kernel<TN, true, true>), grid, block, lds, s, G, src, e, sp, wm, kw);
+      hipLaunchKernelGGL((fc_kernel<TN, 1, true>), grid, block, lds, s, G, src, e, sp, wm, kw);
     else
-      hipLaunchKernelGGL((fc_kernel<TN, true, false>), grid, block, lds, s, G, src, e, sp, wm, kw);
+      hipLaunchKernelGGL((fc_kernel<TN, 1, false>), grid, block, lds, s, G, src, e, sp, wm, kw);
+  } else if (mma_bf16 == 2) {
+    if (src_bf16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((fc_kernel<TN, 2, false>), grid, block, lds, s, G, src, e, sp, wm, kw);
   } else {
     if (src_bf16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((fc_kernel<TN, false, false>), grid, block, lds, s, G, src, e, sp, wm, kw);
+    hipLaunchKernelGGL((fc_kernel<TN, 0, false>), grid, block, lds, s, G, src, e, sp, wm, kw);
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess || sp.splits <= 1) return err;
