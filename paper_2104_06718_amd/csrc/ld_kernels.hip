@@ -92,7 +92,9 @@ __device__ __forceinline__ f32x4 ld4v(const float* __restrict__ p, size_t i0, si
   return f32x4{t[0], t[1], t[2], t[3]};
 }
 
-template <bool VEC>
+// NA: arrays an epilogue of this launch may read (kinds that read more are not
+// launched with NA < 6; the members past NA stay zero)
+template <bool VEC, int NA = 6>
 __device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st, int nv, EpiIn& in) {
   switch (E.kind) {
     case EPI_P0:
@@ -107,18 +109,22 @@ __device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st,
       in.a2 = ld4v<VEC>(E.hi, i0, st, nv);
       break;
     case EPI_ADAM:
-      in.a0 = ld4v<VEC>(E.rho_w, i0, st, nv);
-      in.a1 = ld4v<VEC>(E.m, i0, st, nv);
-      in.a2 = ld4v<VEC>(E.v, i0, st, nv);
-      in.a3 = ld4v<VEC>(E.xb_in, i0, st, nv);
+      if (NA >= 4) {
+        in.a0 = ld4v<VEC>(E.rho_w, i0, st, nv);
+        in.a1 = ld4v<VEC>(E.m, i0, st, nv);
+        in.a2 = ld4v<VEC>(E.v, i0, st, nv);
+        in.a3 = ld4v<VEC>(E.xb_in, i0, st, nv);
+      }
       break;
     case EPI_ADAM_LAST:
-      in.a0 = ld4v<VEC>(E.rho_w, i0, st, nv);
-      in.a1 = ld4v<VEC>(E.m, i0, st, nv);
-      in.a2 = ld4v<VEC>(E.v, i0, st, nv);
-      in.a3 = ld4v<VEC>(E.gc, i0, st, nv);
-      in.a4 = ld4v<VEC>(E.lo, i0, st, nv);
-      in.a5 = ld4v<VEC>(E.hi, i0, st, nv);
+      if (NA >= 6) {
+        in.a0 = ld4v<VEC>(E.rho_w, i0, st, nv);
+        in.a1 = ld4v<VEC>(E.m, i0, st, nv);
+        in.a2 = ld4v<VEC>(E.v, i0, st, nv);
+        in.a3 = ld4v<VEC>(E.gc, i0, st, nv);
+        in.a4 = ld4v<VEC>(E.lo, i0, st, nv);
+        in.a5 = ld4v<VEC>(E.hi, i0, st, nv);
+      }
       break;
     case EPI_SUPERGRAD:
       in.a0 = ld4v<VEC>(E.xb_in, i0, st, nv);
@@ -772,9 +778,10 @@ hipError_t launch_fc(const GemmGeom& G, const void* src, int src_bf16, int mma_b
 //     (A operand) in MFMA operand order, [K/VPL][Mp][VPL] (BF16 for the BF16
 //     product), zero-padded in K and M; the fragment-ordered weights (B
 //     operand); the tap tables;
-//  1. per chunk of input channels, the device-memory operands of the thread's
-//     first epilogue group are loaded, then waves compute 16x16 MFMA tiles of
-//     Y = rho^T W into LDS;
+//  1. per chunk of input channels, waves compute 16x16 MFMA tiles of
+//     Y = rho^T W into LDS, while the device-memory operands of each thread's
+//     first epilogue group of the chunk are in flight (those of the first
+//     chunk are issued before the staging loads);
 //  2. every output of the chunk sums its taps from Y and goes through the
 //     epilogue, four consecutive neurons per thread, with the operands of the
 //     next group loaded before the current one is finished.
@@ -803,6 +810,20 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   const int* tx = cy + G.H;
   const int* cx = tx + G.W * G.Tmax;
   const int b = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const size_t dst_base = (size_t)b * G.Ci * G.HW;
+  constexpr int STEP = 4 * kTThreads;
+  const bool vec = (G.HW & 3) == 0;
+  // operands of the thread's first epilogue group of a chunk: for the first
+  // chunk they are in flight during the staging, for the others during the GEMM
+  EpiIn nx{};
+  auto prefetch = [&](int e0, int e1) {
+    if (vec) {
+      if (e0 + 4 * tid < e1) epi_load<true, 3>(E, dst_base + e0 + 4 * tid, 1, 4, nx);
+    } else {
+      if (e0 + tid < e1) epi_load<false, 3>(E, dst_base + e0 + tid, 1, 1, nx);
+    }
+  };
+  prefetch(0, min(G.Ci, G.Cc) * G.HW);
   adam_tick(E);
   // 0. staging
   {
@@ -856,19 +877,10 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   }
   __syncthreads();
   const int mtn = G.Mp >> 4;
-  const size_t dst_base = (size_t)b * G.Ci * G.HW;
-  constexpr int STEP = 4 * kTThreads;
-  const bool vec = (G.HW & 3) == 0;
   for (int c = 0; c < G.nchunks; ++c) {
     const int c0 = c * G.Cc, c1 = min(G.Ci, c0 + G.Cc);
     const int e0 = c0 * G.HW, e1 = c1 * G.HW;
-    // operands of the first epilogue group, in flight during the GEMM
-    EpiIn nx{};
-    if (vec) {
-      if (e0 + 4 * tid < e1) epi_load<true>(E, dst_base + e0 + 4 * tid, 1, 4, nx);
-    } else {
-      if (e0 + tid < e1) epi_load<false>(E, dst_base + e0 + tid, 1, 1, nx);
-    }
+    if (c > 0) prefetch(e0, e1);
     // UT independent tiles per wave at a time (their operand reads overlap)
     constexpr int UT = 4;
     const int items = mtn * G.ntc;
@@ -908,7 +920,7 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     if (vec) {
       for (int e = e0 + 4 * tid; e < e1; e += STEP) {
         const EpiIn cur = nx;
-        if (e + STEP < e1) epi_load<true>(E, dst_base + e + STEP, 1, 4, nx);
+        if (e + STEP < e1) epi_load<true, 3>(E, dst_base + e + STEP, 1, 4, nx);
         const int ci = fdiv(e, G.HW, G.inv_HW);
         const int rem = e - ci * G.HW;
         int y = fdiv(rem, G.W, G.inv_W);
@@ -967,7 +979,7 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     } else {
       for (int e = e0 + tid; e < e1; e += kTThreads) {
         const EpiIn cur = nx;
-        if (e + kTThreads < e1) epi_load<false>(E, dst_base + e + kTThreads, 1, 1, nx);
+        if (e + kTThreads < e1) epi_load<false, 3>(E, dst_base + e + kTThreads, 1, 1, nx);
         const int ci = fdiv(e, G.HW, G.inv_HW);
         const int rem = e - ci * G.HW;
         const int y = fdiv(rem, G.W, G.inv_W);
@@ -1000,6 +1012,8 @@ size_t convT_lds_bytes(const ColGeom& g) {
 
 hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16, const EpiArgs& e, hipStream_t s) {
   if (B == 0) return hipSuccess;
+  if (e.kind == EPI_ADAM || e.kind == EPI_ADAM_LAST) return hipErrorInvalidValue;  // reads more than 3 arrays
+  if (mma_bf16 != 0 && mma_bf16 != 1) return hipErrorInvalidValue;
   const size_t lds = convT_lds_bytes_t(g, mma_bf16);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   // tap loops of fixed length where every row and column takes at most one or two taps
