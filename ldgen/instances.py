@@ -110,6 +110,10 @@ CONFIGS: Dict[str, Dict] = {
     "tiny_conv3": dict(cfg=8, input=(2, 8, 8), eps=0.1, B=5, props=[3, 2], T=200,
                        arch=[_conv(2, 3, 5, 2, 2, 8), _conv(3, 4, 2, 2, 0, 4),
                              ("linear", 16, 6), ("linear", 6, 3)]),
+    # channel counts that are multiples of 8 (channel-last gather) on odd map sizes
+    "tiny_conv4": dict(cfg=9, input=(8, 5, 5), eps=0.1, B=6, props=[4, 2], T=200,
+                       arch=[_conv(8, 8, 3, 1, 1, 5), _conv(8, 16, 4, 2, 1, 5),
+                             ("linear", 64, 6), ("linear", 6, 3)]),
     # MLP 784-1024x4-10, box +-0.02
     "mlp": dict(cfg=5, input=(784, 1, 1), eps=0.02, B=1024, props=[1024], T=0,
                 arch=[("linear", 784, 1024), ("linear", 1024, 1024), ("linear", 1024, 1024),

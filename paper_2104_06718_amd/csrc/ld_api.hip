@@ -194,6 +194,17 @@ int finish_geom(ld_net* net, GemmGeom& g, const std::vector<float>& Bnk, const s
     LD_TRY(alloc_dev(net, &pl, kl.size() * 4));
     LD_HIP(hipMemcpy(pl, kl.data(), kl.size() * 4, hipMemcpyHostToDevice));
     g.ktab_lds = (const int*)pl;
+    if (g.CP > 0) {
+      std::vector<int> kc((size_t)g.Kp, 0);
+      for (int k = 0; k < g.K; ++k) {
+        const int c = ktab[k].x / (g.src_H * g.src_W);
+        kc[k] = (ktab[k].y * g.LW + ktab[k].z) * g.CP + c;
+      }
+      void* pc;
+      LD_TRY(alloc_dev(net, &pc, kc.size() * 4));
+      LD_HIP(hipMemcpy(pc, kc.data(), kc.size() * 4, hipMemcpyHostToDevice));
+      g.ktab_cl = (const int*)pc;
+    }
   }
   void *pf, *ph, *phl, *pk;
   LD_TRY(alloc_dev(net, &pf, bf.size() * 4));
@@ -398,10 +409,12 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
     g.LW = p + Wd + std::max(0, (OW - 1) * s - p + kw - Wd);
     std::vector<float> Bnk((size_t)Co * g.K);
     std::vector<int4> kt(g.K);
+    // k = (ci, ky, kx), or (ky, kx, ci) with the channel-last map
+    g.CP = Ci % 8 == 0 ? Ci + 4 : 0;
     for (int ci = 0; ci < Ci; ++ci)
       for (int ky = 0; ky < kh; ++ky)
         for (int kx = 0; kx < kw; ++kx) {
-          const int k = (ci * kh + ky) * kw + kx;
+          const int k = g.CP ? (ky * kw + kx) * Ci + ci : (ci * kh + ky) * kw + kx;
           kt[k] = int4{ci * H * Wd, ky, kx, 0};
           for (int co = 0; co < Co; ++co) Bnk[(size_t)co * g.K + k] = w_at(co, ci, ky, kx);
         }
@@ -464,10 +477,12 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
       g.LW = pl + OW + pr;
       std::vector<float> Bnk((size_t)Ci * std::max(g.K, 1), 0.f);
       std::vector<int4> kt(std::max(g.K, 1), int4{0, 0, 0, 0});
+      // k = (co, ty, tx), or (ty, tx, co) with the channel-last map
+      g.CP = Co % 8 == 0 ? Co + 4 : 0;
       for (int co = 0; co < Co; ++co)
         for (int ty = 0; ty < Ty; ++ty)
           for (int tx = 0; tx < Tx; ++tx) {
-            const int k = (co * Ty + ty) * Tx + tx;
+            const int k = g.CP ? (ty * Tx + tx) * Co + co : (co * Ty + ty) * Tx + tx;
             kt[k] = int4{co * OH * OW, -ty, -tx, 0};
             for (int ci = 0; ci < Ci; ++ci) Bnk[(size_t)ci * g.K + k] = w_at(co, ci, ky0 + s * ty, kx0 + s * tx);
           }

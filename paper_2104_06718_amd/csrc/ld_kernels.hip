@@ -285,7 +285,10 @@ __device__ __forceinline__ int fdiv(int e, int d, float inv) {
 constexpr int kGeoWords = (int)((sizeof(GemmGeom) + 15) / 16 * 4);
 
 // MM: operands of the product: 0 FP32, 1 BF16, 2 compensated BF16 (FP32 source)
-template <int MM, bool SRC_BF16, int TN>
+// CL: the LDS image is channel-last ([LH][LW][CP]) and k runs (tap, channel), so a
+// lane's VPL values of one K step are contiguous (16-byte LDS reads, no gather table
+// read per value)
+template <int MM, bool SRC_BF16, int TN, bool CL>
 __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, const GemmGeom* __restrict__ geo_dev,
                                                          const void* __restrict__ src_v, EpiArgs E,
                                                          int img_floats, int dst_hw4, int kp_max, int n_eff,
@@ -303,7 +306,8 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   const int H = G0.src_H, W = G0.src_W, HW = H * W;
   const int C = G0.src_n / HW;
   int* geo = reinterpret_cast<int*>(lds);                  // [n classes][kGeoWords]
-  float* img = lds + P.n * kGeoWords;                      // [C][LH][LW]
+  float* img = lds + P.n * kGeoWords;                      // [C][LH][LW], or [LH][LW][CP] (CL)
+  const int CP = G0.CP;
   float* outp = img + img_floats;                          // [dst_n]
   int* kofs = reinterpret_cast<int*>(outp + G0.dst_n);     // [n classes][kp_max]
   WT* wB = reinterpret_cast<WT*>(lds + ((P.n * kGeoWords + img_floats + G0.dst_n + P.n * kp_max + 3) & ~3));  // [n classes][n_eff][bstride], 16-byte aligned
@@ -351,9 +355,15 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
             const int x = e - row * W;
             const int c = fdiv(row, H, inv_h);
             const int y = row - c * H;
-            float* d = img + (c * G0.LH + y + G0.pad_t) * G0.LW + x + G0.pad_l;
+            if (CL) {
+              float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP + c;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) d[q] = v[u][q];
+              for (int q = 0; q < 4; ++q) d[q * CP] = v[u][q];
+            } else {
+              float* d = img + (c * G0.LH + y + G0.pad_t) * G0.LW + x + G0.pad_l;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) d[q] = v[u][q];
+            }
           }
         }
       }
@@ -364,12 +374,25 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
         const int x = e - row * W;
         const int c = fdiv(row, H, inv_h);
         const int y = row - c * H;
-        img[(c * G0.LH + y + G0.pad_t) * G0.LW + x + G0.pad_l] = v;
+        if (CL)
+          img[((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP + c] = v;
+        else
+          img[(c * G0.LH + y + G0.pad_t) * G0.LW + x + G0.pad_l] = v;
       }
     }
   }
   // 1b. zero the padding border (disjoint from the interior)
-  {
+  if (CL) {
+    // border pixels, all C channels (the CP - C pad floats of a pixel are never read)
+    const float inv_lw = 1.0f / (float)G0.LW;
+    const int c4 = C >> 2;
+    for (int e = tid; e < G0.LH * G0.LW * c4; e += kConvThreads) {
+      const int pix = e / c4, q = e - pix * c4;
+      const int yy = fdiv(pix, G0.LW, inv_lw), xx = pix - yy * G0.LW;
+      if (yy < G0.pad_t || yy >= G0.pad_t + H || xx < G0.pad_l || xx >= G0.pad_l + W)
+        *reinterpret_cast<float4*>(img + pix * CP + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  } else {
     const float inv_lh = 1.0f / (float)G0.LH;
     for (int rr = tid; rr < C * G0.LH; rr += kConvThreads) {
       const int c = fdiv(rr, G0.LH, inv_lh);
@@ -386,7 +409,8 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   // 1c. gather offsets and weights of every class
   for (int c = 0; c < P.n; ++c) {
     const GemmGeom& G = P.g[c];
-    for (int k = tid; k < G.Kp; k += kConvThreads) kofs[c * kp_max + k] = G.ktab_lds[k];
+    const int* kt = CL ? G.ktab_cl : G.ktab_lds;
+    for (int k = tid; k < G.Kp; k += kConvThreads) kofs[c * kp_max + k] = kt[k];
     const int vr = G.Kp / EPV;
     const float inv_vr = 1.0f / (float)vr;
     const uint4* srcw = reinterpret_cast<const uint4*>(MMA_BF16 ? (const void*)G.Bh : (const void*)G.Bf);
@@ -446,7 +470,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       const int p = min(tile * 16 + r, G.HWq - 1);
       const int yq = fdiv(p, G.Wq, inv_wq);
       const int xq = p - yq * G.Wq;
-      const int lb = (yq * G.iy_mul + G.iy_off + G.pad_t) * G.LW + xq * G.ix_mul + G.ix_off + G.pad_l;
+      const int lb = ((yq * G.iy_mul + G.iy_off + G.pad_t) * G.LW + xq * G.ix_mul + G.ix_off + G.pad_l) * (CL ? CP : 1);
       f32x4 acc[TN];
 #pragma unroll
       for (int t = 0; t < TN; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -454,8 +478,21 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       for (int k0 = 0; k0 < G.K; k0 += KS) {
         const int kl = k0 + VPL * g;
         float a[VPL];
+        if (CL) {
+          // VPL consecutive channels of one tap: 16-byte aligned and contiguous
+          const float* ap = img + lb + ko[kl];
 #pragma unroll
-        for (int j = 0; j < VPL; ++j) a[j] = img[lb + ko[kl + j]];
+          for (int j = 0; j < VPL; j += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(ap + j);
+            a[j] = v.x;
+            a[j + 1] = v.y;
+            a[j + 2] = v.z;
+            a[j + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < VPL; ++j) a[j] = img[lb + ko[kl + j]];
+        }
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
           const size_t wo = (size_t)(nc + 16 * t + r) * bstride + kl;
@@ -665,7 +702,7 @@ __global__ __launch_bounds__(256) void fc_split_reduce(GemmGeom G, EpiArgs E, Sp
 // ---------------------------------------------------------------------------
 static int conv_img_floats(const GemmGeom& g) {
   const int C = g.src_n / (g.src_H * g.src_W);
-  return C * g.LH * g.LW;
+  return g.CP > 0 ? g.LH * g.LW * g.CP : C * g.LH * g.LW;
 }
 
 static int max_kp(const GemmGeom* g, int n) {
@@ -699,14 +736,18 @@ static hipError_t launch_conv_tn(const GemmPack& P, const GemmGeom* geo_dev, int
   dim3 grid(B), block(kConvThreads);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   const void* fn;
-  if (mma_bf16 == 1)
-    fn = src_bf16 ? (const void*)conv_plane_kernel<1, true, TN> : (const void*)conv_plane_kernel<1, false, TN>;
+  const bool cl = G.CP > 0;
+  if (mma_bf16 == 1 && src_bf16)
+    fn = cl ? (const void*)conv_plane_kernel<1, true, TN, true> : (const void*)conv_plane_kernel<1, true, TN, false>;
+  else if (mma_bf16 == 1)
+    fn = cl ? (const void*)conv_plane_kernel<1, false, TN, true> : (const void*)conv_plane_kernel<1, false, TN, false>;
   else if (mma_bf16 == 2 && !src_bf16)
-    fn = (const void*)conv_plane_kernel<2, false, TN>;
+    fn = cl ? (const void*)conv_plane_kernel<2, false, TN, true> : (const void*)conv_plane_kernel<2, false, TN, false>;
   else if (mma_bf16 == 0 && !src_bf16)
-    fn = (const void*)conv_plane_kernel<0, false, TN>;
+    fn = cl ? (const void*)conv_plane_kernel<0, false, TN, true> : (const void*)conv_plane_kernel<0, false, TN, false>;
   else
     return hipErrorInvalidValue;
+  if (cl && (G.CP % 4 != 0 || (G.src_n / (G.src_H * G.src_W)) % 8 != 0)) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     const hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;

@@ -13,7 +13,7 @@ from tests import _parity as PT
 
 pytestmark = pytest.mark.gpu
 
-SMALL = ["fc_tiny", "tiny_conv", "tiny_conv2", "tiny_conv3"]
+SMALL = ["fc_tiny", "tiny_conv", "tiny_conv2", "tiny_conv3", "tiny_conv4"]
 
 
 def _lib():
@@ -166,7 +166,7 @@ def test_ascent_final_bound_parity_fp32(name, T, engine):
 
 
 @pytest.mark.parametrize("engine", ENGINES)
-@pytest.mark.parametrize("name", ["fc_tiny", "tiny_conv", "tiny_conv2", "tiny_conv3", "base"])
+@pytest.mark.parametrize("name", ["fc_tiny", "tiny_conv", "tiny_conv2", "tiny_conv3", "tiny_conv4", "base"])
 def test_first_steps_follow_the_oracle(name, engine):
     """The first Adam steps from the CROWN point track the oracle elementwise: ties at
     the CROWN kinks are resolved by the same rule on both sides."""
