@@ -71,9 +71,17 @@ template <bool VEC>
 __device__ __forceinline__ void st4_xs(const EpiArgs& E, size_t i0, size_t st, int nv, const float (&o)[4]) {
   if (E.xs_bf16) {
     bf16_t* p = (bf16_t*)E.xs;
+    if (VEC) {
+      // four contiguous BF16 values, 8-byte aligned: one store
+      uint2 w;
+      w.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
+      w.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
+      *reinterpret_cast<uint2*>(p + i0) = w;
+    } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (VEC || q < nv) p[i0 + q * st] = f2bf(o[q]);
+      for (int q = 0; q < 4; ++q)
+        if (q < nv) p[i0 + q * st] = f2bf(o[q]);
+    }
   } else {
     st4<VEC>((float*)E.xs, i0, st, nv, o);
   }
