@@ -188,7 +188,8 @@ int finish_geom(ld_net* net, GemmGeom& g, const std::vector<float>& Bnk, const s
     std::vector<int> kl((size_t)g.Kp, 0);
     for (int k = 0; k < g.K; ++k) {
       const int c = ktab[k].x / (g.src_H * g.src_W);
-      kl[k] = c * g.LH * g.LW + ktab[k].y * g.LW + ktab[k].z;
+      // .w marks a padding channel of the channel-last order (weight 0): offset 0
+      kl[k] = ktab[k].w ? 0 : c * g.LH * g.LW + ktab[k].y * g.LW + ktab[k].z;
     }
     void* pl;
     LD_TRY(alloc_dev(net, &pl, kl.size() * 4));
@@ -221,6 +222,12 @@ int finish_geom(ld_net* net, GemmGeom& g, const std::vector<float>& Bnk, const s
   g.ktab = (const int4*)pk;
   return LD_OK;
 }
+
+// Channel-last LDS map of a conv source with C channels: channels padded to a
+// multiple of 4 in k, pixel stride CP floats (C + 4 when C is a multiple of 8,
+// which spreads a row's pixels over the LDS banks; else the padded count)
+int cl_channels(int C) { return (C + 3) / 4 * 4; }
+int cl_stride(int C) { return C % 8 == 0 ? C + 4 : cl_channels(C); }
 
 GemmGeom base_geom() {
   GemmGeom g;
@@ -395,7 +402,6 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
     g.src_H = H;
     g.src_W = Wd;
     g.src_n = Ci * H * Wd;
-    g.K = Ci * kh * kw;
     g.N = Co;
     g.dst_n = Co * OH * OW;
     g.dst_HW = OH * OW;
@@ -407,16 +413,19 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
     g.pad_l = p;
     g.LH = p + H + std::max(0, (OH - 1) * s - p + kh - H);
     g.LW = p + Wd + std::max(0, (OW - 1) * s - p + kw - Wd);
-    std::vector<float> Bnk((size_t)Co * g.K);
+    // channel-last map, k = (ky, kx, ci) with ci padded to a multiple of 4 (zero weights)
+    const int Cq = cl_channels(Ci);
+    g.CP = cl_stride(Ci);
+    g.K = kh * kw * Cq;
+    std::vector<float> Bnk((size_t)Co * g.K, 0.f);
     std::vector<int4> kt(g.K);
-    // k = (ci, ky, kx), or (ky, kx, ci) with the channel-last map
-    g.CP = Ci % 8 == 0 ? Ci + 4 : 0;
-    for (int ci = 0; ci < Ci; ++ci)
+    for (int ci = 0; ci < Cq; ++ci)
       for (int ky = 0; ky < kh; ++ky)
         for (int kx = 0; kx < kw; ++kx) {
-          const int k = g.CP ? (ky * kw + kx) * Ci + ci : (ci * kh + ky) * kw + kx;
-          kt[k] = int4{ci * H * Wd, ky, kx, 0};
-          for (int co = 0; co < Co; ++co) Bnk[(size_t)co * g.K + k] = w_at(co, ci, ky, kx);
+          const int k = (ky * kw + kx) * Cq + ci;
+          kt[k] = int4{ci * H * Wd, ky, kx, ci >= Ci ? 1 : 0};
+          if (ci < Ci)
+            for (int co = 0; co < Co; ++co) Bnk[(size_t)co * g.K + k] = w_at(co, ci, ky, kx);
         }
     LD_TRY(finish_geom(net, g, Bnk, kt));
     L.fwd.geoms = {g};
@@ -461,7 +470,9 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
       g.src_H = OH;
       g.src_W = OW;
       g.src_n = Co * OH * OW;
-      g.K = Co * Ty * Tx;
+      const int Cq = cl_channels(Co);  // channel-last map, k = (ty, tx, co), co padded
+      g.CP = cl_stride(Co);
+      g.K = Cq * Ty * Tx;
       g.N = Ci;
       g.dst_n = Ci * H * Wd;
       g.dst_HW = H * Wd;
@@ -477,14 +488,13 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
       g.LW = pl + OW + pr;
       std::vector<float> Bnk((size_t)Ci * std::max(g.K, 1), 0.f);
       std::vector<int4> kt(std::max(g.K, 1), int4{0, 0, 0, 0});
-      // k = (co, ty, tx), or (ty, tx, co) with the channel-last map
-      g.CP = Co % 8 == 0 ? Co + 4 : 0;
-      for (int co = 0; co < Co; ++co)
+      for (int co = 0; co < Cq; ++co)
         for (int ty = 0; ty < Ty; ++ty)
           for (int tx = 0; tx < Tx; ++tx) {
-            const int k = g.CP ? (ty * Tx + tx) * Co + co : (co * Ty + ty) * Tx + tx;
-            kt[k] = int4{co * OH * OW, -ty, -tx, 0};
-            for (int ci = 0; ci < Ci; ++ci) Bnk[(size_t)ci * g.K + k] = w_at(co, ci, ky0 + s * ty, kx0 + s * tx);
+            const int k = (ty * Tx + tx) * Cq + co;
+            kt[k] = int4{co * OH * OW, -ty, -tx, co >= Co ? 1 : 0};
+            if (co < Co)
+              for (int ci = 0; ci < Ci; ++ci) Bnk[(size_t)ci * g.K + k] = w_at(co, ci, ky0 + s * ty, kx0 + s * tx);
           }
       LD_TRY(finish_geom(net, g, Bnk, kt));
       L.tr.geoms.push_back(g);

@@ -36,9 +36,9 @@ struct GemmGeom {
   // [src_n / (src_H*src_W)] x LH x LW with the map at offset (pad_t, pad_l)
   int pad_t, pad_l, LH, LW;
   const int* ktab_lds; // [Kp] offset of each k in the padded map (c*LH*LW + dky*LW + dkx)
-  // channel-last copy of the padded map ([LH][LW][CP], CP = C + 4 floats per pixel),
-  // used when the source has a multiple of 8 channels (CP = 0 otherwise); k is then
-  // ordered (tap, channel), so VPL consecutive k of one K step are contiguous
+  // channel-last copy of the padded map ([LH][LW][CP] floats, CP >= C rounded up to
+  // 4; CP = 0: not used); k is ordered (tap, channel) with the channels padded to a
+  // multiple of 4 (zero weights), so each 4 consecutive k are contiguous in the map
   int CP;
   const int* ktab_cl;  // [Kp] offset of each k in the channel-last map ((dky*LW + dkx)*CP + c)
 };

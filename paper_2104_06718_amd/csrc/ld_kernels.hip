@@ -316,6 +316,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   int* geo = reinterpret_cast<int*>(lds);                  // [n classes][kGeoWords]
   float* img = lds + P.n * kGeoWords;                      // [C][LH][LW], or [LH][LW][CP] (CL)
   const int CP = G0.CP;
+  const int Cq = (C + 3) & ~3;  // CL: channels of a pixel that k reads (the ones past C are zero)
   float* outp = img + img_floats;                          // [dst_n]
   int* kofs = reinterpret_cast<int*>(outp + G0.dst_n);     // [n classes][kp_max]
   WT* wB = reinterpret_cast<WT*>(lds + ((P.n * kGeoWords + img_floats + G0.dst_n + P.n * kp_max + 3) & ~3));  // [n classes][n_eff][bstride], 16-byte aligned
@@ -367,6 +368,10 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
               float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP + c;
 #pragma unroll
               for (int q = 0; q < 4; ++q) d[q * CP] = v[u][q];
+              if (c == C - 1)  // the padding channels of these pixels
+                for (int cc = C; cc < Cq; ++cc)
+#pragma unroll
+                  for (int q = 0; q < 4; ++q) d[q * CP + cc - c] = 0.f;
             } else {
               float* d = img + (c * G0.LH + y + G0.pad_t) * G0.LW + x + G0.pad_l;
 #pragma unroll
@@ -382,18 +387,21 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
         const int x = e - row * W;
         const int c = fdiv(row, H, inv_h);
         const int y = row - c * H;
-        if (CL)
-          img[((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP + c] = v;
-        else
+        if (CL) {
+          float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP;
+          d[c] = v;
+          if (c == C - 1)
+            for (int cc = C; cc < Cq; ++cc) d[cc] = 0.f;
+        } else
           img[(c * G0.LH + y + G0.pad_t) * G0.LW + x + G0.pad_l] = v;
       }
     }
   }
   // 1b. zero the padding border (disjoint from the interior)
   if (CL) {
-    // border pixels, all C channels (the CP - C pad floats of a pixel are never read)
+    // border pixels, all Cq channels (the CP - Cq floats past them are never read)
     const float inv_lw = 1.0f / (float)G0.LW;
-    const int c4 = C >> 2;
+    const int c4 = Cq >> 2;
     for (int e = tid; e < G0.LH * G0.LW * c4; e += kConvThreads) {
       const int pix = e / c4, q = e - pix * c4;
       const int yy = fdiv(pix, G0.LW, inv_lw), xx = pix - yy * G0.LW;
@@ -487,11 +495,11 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
         const int kl = k0 + VPL * g;
         float a[VPL];
         if (CL) {
-          // VPL consecutive channels of one tap: 16-byte aligned and contiguous
-          const float* ap = img + lb + ko[kl];
+          // each group of 4 consecutive k is 4 channels of one tap: 16-byte aligned
+          // and contiguous (VPL = 8 may span two taps)
 #pragma unroll
           for (int j = 0; j < VPL; j += 4) {
-            const float4 v = *reinterpret_cast<const float4*>(ap + j);
+            const float4 v = *reinterpret_cast<const float4*>(img + lb + ko[kl + j]);
             a[j] = v.x;
             a[j + 1] = v.y;
             a[j + 2] = v.z;
@@ -755,7 +763,8 @@ static hipError_t launch_conv_tn(const GemmPack& P, const GemmGeom* geo_dev, int
     fn = cl ? (const void*)conv_plane_kernel<0, false, TN, true> : (const void*)conv_plane_kernel<0, false, TN, false>;
   else
     return hipErrorInvalidValue;
-  if (cl && (G.CP % 4 != 0 || (G.src_n / (G.src_H * G.src_W)) % 8 != 0)) return hipErrorInvalidValue;
+  if (cl && (G.CP % 4 != 0 || G.CP < (((G.src_n / (G.src_H * G.src_W)) + 3) & ~3) || G.K % 4 != 0))
+    return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     const hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
