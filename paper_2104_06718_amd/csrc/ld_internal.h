@@ -35,10 +35,12 @@ struct GemmGeom {
   // zero-padded copy of one subdomain's source map in LDS (conv jobs):
   // [src_n / (src_H*src_W)] x LH x LW with the map at offset (pad_t, pad_l)
   int pad_t, pad_l, LH, LW;
-  const int* ktab_lds; // [Kp] offset of each k in the padded map (c*LH*LW + dky*LW + dkx)
-  // channel-last copy of the padded map ([LH][LW][CP] floats, CP >= C rounded up to
-  // 4; CP = 0: not used); k is ordered (tap, channel) with the channels padded to a
-  // multiple of 4 (zero weights), so each 4 consecutive k are contiguous in the map
+  const int* ktab_lds; // [Kp] offset of each k in the channel-major padded map (c*LH*LW + dky*LW + dkx;
+                       // the resident engine's map); 0 for padding channels
+  // conv: k is ordered (tap, channel) with the channels padded to a multiple of 4
+  // (zero weights); the layer-wise gather kernel keeps the map channel-last,
+  // [LH][LW][CP] floats (CP >= the padded channel count), so each 4 consecutive k
+  // are contiguous in it
   int CP;
   const int* ktab_cl;  // [Kp] offset of each k in the channel-last map ((dky*LW + dkx)*CP + c)
 };

@@ -265,8 +265,8 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
 
 // ---------------------------------------------------------------------------
 // Convolution contraction of one subdomain per block, all stride classes.
-//  1. staging, one barrier: the block zeroes the padding border of an LDS image
-//     of the subdomain's source map and fills its interior (all global loads of
+//  1. staging, one barrier: the block zeroes the padding border of a channel-last
+//     LDS image of the subdomain's source map and fills its interior (all global loads of
 //     a thread are issued before its LDS writes); the packed weights of every
 //     class and the gather offsets go to LDS as well;
 //  2. waves compute 16-pixel x 16-column MFMA tiles of every class, A gathered
@@ -293,10 +293,10 @@ __device__ __forceinline__ int fdiv(int e, int d, float inv) {
 constexpr int kGeoWords = (int)((sizeof(GemmGeom) + 15) / 16 * 4);
 
 // MM: operands of the product: 0 FP32, 1 BF16, 2 compensated BF16 (FP32 source)
-// CL: the LDS image is channel-last ([LH][LW][CP]) and k runs (tap, channel), so a
-// lane's VPL values of one K step are contiguous (16-byte LDS reads, no gather table
-// read per value)
-template <int MM, bool SRC_BF16, int TN, bool CL>
+// The LDS image is channel-last ([LH][LW][CP]) and k runs (tap, channel) with the
+// channels padded to a multiple of 4, so every 4 consecutive k of a lane are one
+// 16-byte LDS read.
+template <int MM, bool SRC_BF16, int TN>
 __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, const GemmGeom* __restrict__ geo_dev,
                                                          const void* __restrict__ src_v, EpiArgs E,
                                                          int img_floats, int dst_hw4, int kp_max, int n_eff,
@@ -314,9 +314,9 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   const int H = G0.src_H, W = G0.src_W, HW = H * W;
   const int C = G0.src_n / HW;
   int* geo = reinterpret_cast<int*>(lds);                  // [n classes][kGeoWords]
-  float* img = lds + P.n * kGeoWords;                      // [C][LH][LW], or [LH][LW][CP] (CL)
+  float* img = lds + P.n * kGeoWords;                      // [LH][LW][CP]
   const int CP = G0.CP;
-  const int Cq = (C + 3) & ~3;  // CL: channels of a pixel that k reads (the ones past C are zero)
+  const int Cq = (C + 3) & ~3;  // channels of a pixel that k reads (the ones past C are zero)
   float* outp = img + img_floats;                          // [dst_n]
   int* kofs = reinterpret_cast<int*>(outp + G0.dst_n);     // [n classes][kp_max]
   WT* wB = reinterpret_cast<WT*>(lds + ((P.n * kGeoWords + img_floats + G0.dst_n + P.n * kp_max + 3) & ~3));  // [n classes][n_eff][bstride], 16-byte aligned
@@ -364,19 +364,13 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
             const int x = e - row * W;
             const int c = fdiv(row, H, inv_h);
             const int y = row - c * H;
-            if (CL) {
-              float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP + c;
+            float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP + c;
 #pragma unroll
-              for (int q = 0; q < 4; ++q) d[q * CP] = v[u][q];
-              if (c == C - 1)  // the padding channels of these pixels
-                for (int cc = C; cc < Cq; ++cc)
+            for (int q = 0; q < 4; ++q) d[q * CP] = v[u][q];
+            if (c == C - 1)  // the padding channels of these pixels
+              for (int cc = C; cc < Cq; ++cc)
 #pragma unroll
-                  for (int q = 0; q < 4; ++q) d[q * CP + cc - c] = 0.f;
-            } else {
-              float* d = img + (c * G0.LH + y + G0.pad_t) * G0.LW + x + G0.pad_l;
-#pragma unroll
-              for (int q = 0; q < 4; ++q) d[q] = v[u][q];
-            }
+                for (int q = 0; q < 4; ++q) d[q * CP + cc - c] = 0.f;
           }
         }
       }
@@ -387,18 +381,15 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
         const int x = e - row * W;
         const int c = fdiv(row, H, inv_h);
         const int y = row - c * H;
-        if (CL) {
-          float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP;
-          d[c] = v;
-          if (c == C - 1)
-            for (int cc = C; cc < Cq; ++cc) d[cc] = 0.f;
-        } else
-          img[(c * G0.LH + y + G0.pad_t) * G0.LW + x + G0.pad_l] = v;
+        float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP;
+        d[c] = v;
+        if (c == C - 1)
+          for (int cc = C; cc < Cq; ++cc) d[cc] = 0.f;
       }
     }
   }
   // 1b. zero the padding border (disjoint from the interior)
-  if (CL) {
+  {
     // border pixels, all Cq channels (the CP - Cq floats past them are never read)
     const float inv_lw = 1.0f / (float)G0.LW;
     const int c4 = Cq >> 2;
@@ -408,25 +399,11 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       if (yy < G0.pad_t || yy >= G0.pad_t + H || xx < G0.pad_l || xx >= G0.pad_l + W)
         *reinterpret_cast<float4*>(img + pix * CP + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-  } else {
-    const float inv_lh = 1.0f / (float)G0.LH;
-    for (int rr = tid; rr < C * G0.LH; rr += kConvThreads) {
-      const int c = fdiv(rr, G0.LH, inv_lh);
-      const int yy = rr - c * G0.LH;
-      float* row = img + rr * G0.LW;
-      if (yy < G0.pad_t || yy >= G0.pad_t + H) {
-        for (int x = 0; x < G0.LW; ++x) row[x] = 0.f;
-      } else {
-        for (int x = 0; x < G0.pad_l; ++x) row[x] = 0.f;
-        for (int x = G0.pad_l + W; x < G0.LW; ++x) row[x] = 0.f;
-      }
-    }
   }
   // 1c. gather offsets and weights of every class
   for (int c = 0; c < P.n; ++c) {
     const GemmGeom& G = P.g[c];
-    const int* kt = CL ? G.ktab_cl : G.ktab_lds;
-    for (int k = tid; k < G.Kp; k += kConvThreads) kofs[c * kp_max + k] = kt[k];
+    for (int k = tid; k < G.Kp; k += kConvThreads) kofs[c * kp_max + k] = G.ktab_cl[k];
     const int vr = G.Kp / EPV;
     const float inv_vr = 1.0f / (float)vr;
     const uint4* srcw = reinterpret_cast<const uint4*>(MMA_BF16 ? (const void*)G.Bh : (const void*)G.Bf);
@@ -486,7 +463,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       const int p = min(tile * 16 + r, G.HWq - 1);
       const int yq = fdiv(p, G.Wq, inv_wq);
       const int xq = p - yq * G.Wq;
-      const int lb = ((yq * G.iy_mul + G.iy_off + G.pad_t) * G.LW + xq * G.ix_mul + G.ix_off + G.pad_l) * (CL ? CP : 1);
+      const int lb = ((yq * G.iy_mul + G.iy_off + G.pad_t) * G.LW + xq * G.ix_mul + G.ix_off + G.pad_l) * CP;
       f32x4 acc[TN];
 #pragma unroll
       for (int t = 0; t < TN; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -494,20 +471,15 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       for (int k0 = 0; k0 < G.K; k0 += KS) {
         const int kl = k0 + VPL * g;
         float a[VPL];
-        if (CL) {
-          // each group of 4 consecutive k is 4 channels of one tap: 16-byte aligned
-          // and contiguous (VPL = 8 may span two taps)
+        // each group of 4 consecutive k is 4 channels of one tap: 16-byte aligned
+        // and contiguous (VPL = 8 may span two taps)
 #pragma unroll
-          for (int j = 0; j < VPL; j += 4) {
-            const float4 v = *reinterpret_cast<const float4*>(img + lb + ko[kl + j]);
-            a[j] = v.x;
-            a[j + 1] = v.y;
-            a[j + 2] = v.z;
-            a[j + 3] = v.w;
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < VPL; ++j) a[j] = img[lb + ko[kl + j]];
+        for (int j = 0; j < VPL; j += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(img + lb + ko[kl + j]);
+          a[j] = v.x;
+          a[j + 1] = v.y;
+          a[j + 2] = v.z;
+          a[j + 3] = v.w;
         }
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
@@ -716,10 +688,7 @@ __global__ __launch_bounds__(256) void fc_split_reduce(GemmGeom G, EpiArgs E, Sp
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-static int conv_img_floats(const GemmGeom& g) {
-  const int C = g.src_n / (g.src_H * g.src_W);
-  return g.CP > 0 ? g.LH * g.LW * g.CP : C * g.LH * g.LW;
-}
+static int conv_img_floats(const GemmGeom& g) { return g.LH * g.LW * g.CP; }
 
 static int max_kp(const GemmGeom* g, int n) {
   int m = 0;
@@ -752,18 +721,18 @@ static hipError_t launch_conv_tn(const GemmPack& P, const GemmGeom* geo_dev, int
   dim3 grid(B), block(kConvThreads);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   const void* fn;
-  const bool cl = G.CP > 0;
   if (mma_bf16 == 1 && src_bf16)
-    fn = cl ? (const void*)conv_plane_kernel<1, true, TN, true> : (const void*)conv_plane_kernel<1, true, TN, false>;
+    fn = (const void*)conv_plane_kernel<1, true, TN>;
   else if (mma_bf16 == 1)
-    fn = cl ? (const void*)conv_plane_kernel<1, false, TN, true> : (const void*)conv_plane_kernel<1, false, TN, false>;
+    fn = (const void*)conv_plane_kernel<1, false, TN>;
   else if (mma_bf16 == 2 && !src_bf16)
-    fn = cl ? (const void*)conv_plane_kernel<2, false, TN, true> : (const void*)conv_plane_kernel<2, false, TN, false>;
+    fn = (const void*)conv_plane_kernel<2, false, TN>;
   else if (mma_bf16 == 0 && !src_bf16)
-    fn = cl ? (const void*)conv_plane_kernel<0, false, TN, true> : (const void*)conv_plane_kernel<0, false, TN, false>;
+    fn = (const void*)conv_plane_kernel<0, false, TN>;
   else
     return hipErrorInvalidValue;
-  if (cl && (G.CP % 4 != 0 || G.CP < (((G.src_n / (G.src_H * G.src_W)) + 3) & ~3) || G.K % 4 != 0))
+  // the channel-last map: 16-byte pixels, every channel k reads inside the pixel
+  if (G.CP % 4 != 0 || G.CP < (((G.src_n / (G.src_H * G.src_W)) + 3) & ~3) || G.K % 4 != 0)
     return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     const hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
