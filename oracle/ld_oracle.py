@@ -20,7 +20,11 @@ Network Verification via Lagrangian Decomposition":
   Adam with a linearly decaying step (Sec. 3.2 and Sec. 7.2);
 * initialisation from a propagation-based dual assignment (Prop. 2,
   eq:salman-assignment) with CROWN slopes (Sec. 7.2; footnote of Sec. 4.2);
-* the upper bound from the network output at the last P_0 minimiser (Sec. 5.1.3).
+* the upper bound from the network output at the last P_0 minimiser (Sec. 5.1.3);
+* the proximal solver (Sec. 3.3, Algorithm 2): the method of multipliers on q, its
+  augmented Lagrangian (eq:z_updates) minimised approximately by J sweeps of
+  block-coordinate Frank-Wolfe with the closed-form step (eq:optimal-gamma-gauss),
+  and momentum on the dual update (App. F, eq:momentum_updates).
 
 Readings where the paper is silent (all listed in the design doc):
 * Adam uses beta1=0.9, beta2=0.999, eps=1e-8 with bias correction, as ascent.
@@ -28,11 +32,17 @@ Readings where the paper is silent (all listed in the design doc):
 * ReLU status: passing if l >= 0, else blocking if u <= 0, else ambiguous.
 * Ties in the inner minimisation are broken towards the larger x_B, within a
   relative band tau (0 gives the pure argmin); the value is always the exact min.
+* Proximal: the weight eta grows linearly from eta0 (iteration 1) to eta_end
+  (iteration T), the same form as the step decay; a block whose step has zero
+  curvature takes gamma = 1 if the segment descends, else 0; the momentum starts at 0.
 
 Parity pins: every function here is checked in tests/test_oracle_pins.py against
 closed forms, brute force and the paper's identities (Prop. 1, Prop. 2, weak
-duality, Danskin's supergradient).  The final bound after T Adam steps has no
-value printed in the paper: "parity unpinned" beyond those inequalities.
+duality, Danskin's supergradient), and the proximal solver in
+tests/test_oracle_prox_pins.py (exact line search, conditional gradient by
+autograd and vertex enumeration, convergence to the Planet LP optimum).  The final
+bound after T Adam steps has no value printed in the paper: "parity unpinned"
+beyond those inequalities.
 """
 from __future__ import annotations
 
@@ -355,3 +365,137 @@ def network_output(net: List[OLayer], x0: torch.Tensor) -> torch.Tensor:
     for k in range(len(net) - 1):
         x = torch.clamp(net[k].forward(x), min=0.0)
     return net[-1].forward(x)
+
+
+# ----------------------------------------------------------------------------
+# proximal solver (Sec. 3.3, Algorithm 2 "Proximal method"; App. F momentum)
+# ----------------------------------------------------------------------------
+# Primal iterates of the method of multipliers, per subdomain:
+#   xB[k-1] = xB_k  (k = 1..n-1), the relaxed pre-activation copy inside P_k;
+#   xA[k-1] = xA_k  (k = 1..n),   the image W_k x_{k-1} + b_k leaving P_{k-1}
+#   (xA_n is the network output vector; the objective is c^T xA_n).
+# Duals: rho[k-1] = lambda_k as in the supergradient method (rho_n = -c).
+@dataclasses.dataclass
+class ProxOpts:
+    T: int = 100                 # outer iterations (dual updates)
+    J: int = 2                   # Frank-Wolfe sweeps per outer iteration (Sec. 7.2)
+    eta0: float = 1e1            # proximal weight, linear from eta0 (iteration 1) ...
+    eta_end: float = 5e2         # ... to eta_end (iteration T) (Sec. 7.2)
+    mu: float = 0.3              # momentum on the dual update (App. F); 0 = eq:lambda_updates
+    tau: float = TAU_DEFAULT
+    init: str = "crown"          # "crown" | "zero" | "given"
+
+
+def prox_eta(t: int, T: int, eta0: float, eta_end: float) -> float:
+    """Weight of the proximal terms at outer iteration t (1-based), linear in t."""
+    return step_size(t, T, eta0, eta_end)
+
+
+def aug_lagrangian(net: List[OLayer], batch: OBatch, rho: List[torch.Tensor], eta: float,
+                   xB: List[torch.Tensor], xA: List[torch.Tensor]) -> torch.Tensor:
+    """The augmented Lagrangian of eq:z_updates per subdomain, written out:
+    c^T xA_n + sum_k lambda_k^T (xB_k - xA_k) + sum_k ||xB_k - xA_k||^2 / (2 eta).
+    (The momentum form of App. F adds a term constant in the primal variables.)"""
+    L = (batch.c * xA[-1]).sum(dim=1)
+    for k in range(len(rho)):
+        d = xB[k] - xA[k]
+        L = L + (rho[k] * d).sum(dim=1) + (d * d).sum(dim=1) / (2.0 * eta)
+    return L
+
+
+def prox_coeff(rho: List[torch.Tensor], batch: OBatch, eta: float, xB: List[torch.Tensor],
+               xA: List[torch.Tensor], k: int) -> torch.Tensor:
+    """Gradient of the augmented Lagrangian with respect to xB_k (k = 1..n-1), which is
+    minus its gradient with respect to xA_k: lambda_k + (xB_k - xA_k) / eta.  For
+    k = n it is -c (the objective's coefficient, eta_n = infinity)."""
+    if k == len(rho) + 1:
+        return -batch.c
+    return rho[k - 1] + (xB[k - 1] - xA[k - 1]) / eta
+
+
+def prox_primal_init(net: List[OLayer], batch: OBatch, rho: List[torch.Tensor], tau: float = TAU_DEFAULT):
+    """Primal start of Algorithm 2: an inner minimiser of q at the initial duals
+    (Sec. 3.2.1 / 3.2.2), xA_k = W_k x*_{k-1} + b_k for k = 1..n."""
+    ev = dual_eval(net, batch, rho, tau, need_supergrad=False)
+    prev = [ev["x0"]] + ev["x"]
+    xA = [net[k].forward(prev[k]) for k in range(len(net))]
+    return [x.clone() for x in ev["xB"]], xA
+
+
+def prox_block(net: List[OLayer], batch: OBatch, rho: List[torch.Tensor], eta: float,
+               xB: List[torch.Tensor], xA: List[torch.Tensor], k: int, tau: float = TAU_DEFAULT) -> Dict:
+    """One block-coordinate Frank-Wolfe step on the block (xB_k, xA_{k+1}), k = 0..n-1
+    (Sec. 3.3.2).  Updates xB[k-1] (k >= 1) and xA[k] in place.
+
+    Conditional gradient: the inner minimisation of P_k with the duals replaced by the
+    gradient coefficients (eq. of the conditional gradient; for k = 0 the box rule).
+    Step: gamma* of eq:optimal-gamma-gauss, clipped to [0, 1]; with a zero curvature the
+    segment is linear and gamma is 1 if it descends, else 0."""
+    n = len(net)
+    r_next = prox_coeff(rho, batch, eta, xB, xA, k + 1)      # coefficient of layer k+1
+    g = net[k].transposed(r_next)                            # W_{k+1}^T r_{k+1}
+    if k == 0:
+        z, _ = inner_min_p0(g, batch.l0, batch.u0)
+        num = torch.zeros(g.shape[0], dtype=g.dtype)
+        den = torch.zeros_like(num)
+        zB = None
+    else:
+        r_k = prox_coeff(rho, batch, eta, xB, xA, k)
+        zB, z, _ = inner_min_pk(r_k, g, batch.l[k - 1], batch.u[k - 1], tau)
+        dB = xB[k - 1] - zB
+        num = (r_k * dB).sum(dim=1)
+        den = (dB * dB).sum(dim=1) / eta
+    zA = net[k].forward(z)                                   # W_{k+1} z_k + b_{k+1}
+    dA = xA[k] - zA
+    # gradient with respect to xA_{k+1} is -r_{k+1}
+    num = num - (r_next * dA).sum(dim=1)
+    if k + 1 < n:
+        den = den + (dA * dA).sum(dim=1) / eta
+    ratio = torch.where(den > 0, num / torch.where(den > 0, den, torch.ones_like(den)), torch.zeros_like(num))
+    gamma = torch.where(den > 0, torch.clamp(ratio, 0.0, 1.0), (num > 0).to(num.dtype))
+    if k >= 1:
+        xB[k - 1] = xB[k - 1] + gamma[:, None] * (zB - xB[k - 1])
+    xA[k] = xA[k] + gamma[:, None] * (zA - xA[k])
+    return dict(gamma=gamma, z=z, zB=zB, zA=zA, num=num, den=den)
+
+
+def proximal(net: List[OLayer], batch: OBatch, opts: ProxOpts, rho0: Optional[List[torch.Tensor]] = None,
+             state: Optional[Dict] = None, iters: Optional[int] = None, record: bool = False) -> Dict:
+    """Algorithm 2: `iters` outer iterations (default opts.T) of the method of
+    multipliers, each running J block-coordinate Frank-Wolfe sweeps (blocks k = 0..n-1
+    in order) on the augmented Lagrangian and then the dual update with momentum
+    (eq:momentum_updates; mu = 0 gives eq:lambda_updates).
+
+    `state` (rho, pi, xB, xA, t, q0) continues a previous call; the eta schedule is
+    taken over opts.T."""
+    n = len(net)
+    if state is None:
+        if opts.init == "given":
+            assert rho0 is not None
+            rho = [r.clone() for r in rho0]
+        elif opts.init == "crown":
+            rho = crown_init(net, batch)
+        else:
+            rho = zero_init(net, batch)
+        q0 = dual_eval(net, batch, rho, opts.tau, need_supergrad=False)["q"]
+        xB, xA = prox_primal_init(net, batch, rho, opts.tau)
+        state = dict(rho=rho, pi=[torch.zeros_like(r) for r in rho], xB=xB, xA=xA, t=0, q0=q0)
+    else:
+        state = {key: ([x.clone() for x in val] if isinstance(val, list) else val) for key, val in state.items()}
+    iters = opts.T if iters is None else iters
+    traj = []
+    for _ in range(iters):
+        t = state["t"] + 1
+        eta = prox_eta(t, opts.T, opts.eta0, opts.eta_end)
+        for _j in range(opts.J):
+            for k in range(n):
+                prox_block(net, batch, state["rho"], eta, state["xB"], state["xA"], k, opts.tau)
+        for k in range(n - 1):
+            d = (state["xB"][k] - state["xA"][k]) / eta
+            state["pi"][k] = opts.mu * state["pi"][k] + d
+            state["rho"][k] = state["rho"][k] + state["pi"][k]
+        state["t"] = t
+        if record:
+            traj.append(dual_eval(net, batch, state["rho"], opts.tau, need_supergrad=False)["q"])
+    state["traj"] = traj
+    return state
