@@ -300,6 +300,51 @@ int ld_profile_iteration(const ld_net* net, const ld_batch* batch, ld_state* st,
                          hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* proximal solver (Sec. 3.3, Algorithm 2; momentum of App. F)                */
+/* ------------------------------------------------------------------------- */
+/* The method of multipliers on the same dual q: each outer iteration runs
+ * inner_iters sweeps of block-coordinate Frank-Wolfe on the augmented
+ * Lagrangian of eq:z_updates (blocks (xB_k, xA_{k+1}), k = 0..n-1 in order;
+ * conditional gradient = the inner minimisation of Sec. 3.2 with the duals
+ * replaced by the gradient coefficients; step = the closed form of
+ * eq:optimal-gamma-gauss, clipped to [0, 1]), then the dual update
+ * pi = mu pi + (xB - xA)/eta, rho += pi (eq:momentum_updates; mu = 0 gives
+ * eq:lambda_updates).
+ * iters        outer iterations run by this call (>= 0)
+ * total_iters  T of the schedule of eta: iteration t (1-based, counted over
+ *              all calls on this state) uses eta0 + (eta_end - eta0)(t-1)/(T-1)
+ * inner_iters  J, Frank-Wolfe sweeps per outer iteration (>= 1; the paper: 2)
+ * eta0, eta_end  weight of the proximal terms (> 0; the paper: 10 -> 500, or
+ *              100 fixed inside branch and bound)
+ * mu           momentum in [0, 1) (the paper: 0.3, or 0 inside branch and bound)
+ * precision    LD_FP32 or LD_BF16 operands of the contractions (as ld_opts)
+ * init, tie_tau  as ld_opts */
+typedef struct ld_prox_opts {
+  int iters;
+  int total_iters;
+  int inner_iters;
+  float eta0, eta_end;
+  float mu;
+  int precision;
+  int init;
+  float tie_tau;
+} ld_prox_opts;
+
+/* Enqueue `iters` outer iterations of the proximal solver on the state's duals.
+ * The state is shared with ld_step: its duals (rho), q(rho^0) and
+ * ld_final_bound have the same meaning.  On the first call of a state (or
+ * after ld_state_set_rho / ld_state_reset, or a change of precision) the duals
+ * are initialised as by ld_step and the primal iterates start at a minimiser
+ * of the Lagrangian at those duals (Algorithm 2), with zero momentum.  Several
+ * calls of k iterations equal one call of their sum.  The library allocates
+ * the solver's buffers (about 7 floats per neuron and subdomain) on the first
+ * call.  Errors: LD_E_ARG (bad options), LD_E_STATE, LD_E_NUMERIC, LD_E_NOMEM. */
+int ld_prox_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_prox_opts* opts,
+                 hipStream_t stream);
+/* Outer iterations of the proximal solver done on this state (0 before the first). */
+int ld_prox_get_step(const ld_state* st, int* t);
+
+/* ------------------------------------------------------------------------- */
 /* final bound (Algorithm 1's return value; upper bound of Sec. 5.1.3)        */
 /* ------------------------------------------------------------------------- */
 /* At the state's current duals: q_final = q(rho^T) with FP32 operands and an

@@ -1,9 +1,9 @@
 """MI355X (gfx950) Lagrangian-decomposition bounding step.
 
 Python binding of the C ABI in include/ld.h: ``Net``, ``Batch``, ``State``,
-``init_duals``, ``dual_eval``, ``step`` and ``final_bound`` call the HIP
+``init_duals``, ``dual_eval``, ``step``, ``prox_step`` and ``final_bound`` call the HIP
 library directly; ``LDDual`` wraps ``dual_eval`` as a torch.autograd.Function.
 """
 from .binding import (Batch, LDDual, LDError, Net, State, TAU_DEFAULT, dual_eval, final_bound,  # noqa: F401
-                      init_duals, ld_dual, load_library, profile_iteration, set_validation, step,
+                      init_duals, ld_dual, load_library, profile_iteration, prox_step, set_validation, step,
                       autotune, tuning_info, tile_candidates, set_tuned_config)

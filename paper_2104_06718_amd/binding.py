@@ -32,7 +32,7 @@ EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num
             "ld_state_get_rho", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
-            "ld_final_bound", "ld_last_error"]
+            "ld_prox_step", "ld_prox_get_step", "ld_final_bound", "ld_last_error"]
 
 
 class LDError(RuntimeError):
@@ -62,6 +62,12 @@ class ld_opts(ctypes.Structure):
 
 
 _lib = None
+
+
+class ld_prox_opts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("total_iters", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("eta0", ctypes.c_float), ("eta_end", ctypes.c_float), ("mu", ctypes.c_float),
+                ("precision", ctypes.c_int), ("init", ctypes.c_int), ("tie_tau", ctypes.c_float)]
 
 
 class ld_tile(ctypes.Structure):
@@ -108,6 +114,8 @@ def load_library(path: Optional[str] = None):
     lib.ld_tile_candidates.argtypes = [V, I, I, I, P(ld_tile), I, P(I)]
     lib.ld_set_tuned_config.argtypes = [V, I, I, I, I, P(ld_tile)]
     lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
+    lib.ld_prox_step.argtypes = [V, P(ld_batch), V, P(ld_prox_opts), V]
+    lib.ld_prox_get_step.argtypes = [V, P(I)]
     for name in EXPORTED:
         getattr(lib, name)
     if path is None:
@@ -244,6 +252,11 @@ class State:
         _check(self.lib.ld_state_get_step(self.handle, _stream(stream), ctypes.byref(t)))
         return t.value
 
+    def prox_step_count(self) -> int:
+        t = ctypes.c_int()
+        _check(self.lib.ld_prox_get_step(self.handle, ctypes.byref(t)))
+        return t.value
+
 
 def set_validation(on: bool):
     load_library().ld_set_validation(1 if on else 0)
@@ -276,6 +289,16 @@ def step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional
          tau: float = TAU_DEFAULT, engine="auto", stream=None):
     o = _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine)
     _check(net.lib.ld_step(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o), _stream(stream)))
+
+
+def prox_step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional[int] = None,
+              inner_iters=2, eta0=10.0, eta_end=500.0, mu=0.3, precision="fp32", init="crown",
+              tau: float = TAU_DEFAULT, stream=None):
+    """`iters` outer iterations of the proximal solver (ld_prox_step)."""
+    o = ld_prox_opts(iters, iters if total_iters is None else total_iters, inner_iters, eta0, eta_end, mu,
+                     _PREC[precision], _INIT[init], tau)
+    _check(net.lib.ld_prox_step(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o),
+                                _stream(stream)))
 
 
 def autotune(net: Net, batch: Batch, total_iters=500, lr0=1e-2, lr_end=1e-4, beta1=0.9, beta2=0.999, eps=1e-8,

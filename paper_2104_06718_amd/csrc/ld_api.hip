@@ -152,6 +152,19 @@ struct ld_state {
   // buffer must not be released while kernels that use it are in flight)
   hipEvent_t done = nullptr;
   hipEvent_t ev_join[2] = {nullptr, nullptr};
+  // proximal solver (allocated by its first call): primal iterates xB_k (k = 1..n-1
+  // at k-1), xA_k (k = 1..n at k-1), coefficients rt_k and momentum pi_k (k-1),
+  // transposed products g_k (k = 1..n-2 at k), the forward product of the current
+  // block zA (widest layer) and the operand z_{n-1} of the objective layer
+  struct Prox {
+    void* base = nullptr;
+    std::vector<float*> xB, xA, rt, pi, g;
+    float* zA = nullptr;
+    void* zlast = nullptr;
+    bool ready = false;  // primal iterates hold a start point (set by the first call)
+    int mma = -1;        // operand precision the start point was formed with
+    int t = 0;           // outer iterations done
+  } px;
 };
 
 namespace {
@@ -1314,6 +1327,7 @@ void ld_state_destroy(ld_state* st) {
   if (st->ev_fork) (void)hipEventDestroy(st->ev_fork);
   if (st->done) (void)hipEventDestroy(st->done);
   if (st->ws.base) (void)hipFree(st->ws.base);
+  if (st->px.base) (void)hipFree(st->px.base);
   if (st->base) (void)hipFree(st->base);
   delete st;
 }
@@ -1332,6 +1346,8 @@ int ld_state_set_rho(ld_state* st, const float* const* rho, hipStream_t s) {
   LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
   st->t_host = 0;
   st->initialized = false;  // q(rho^0) is computed by the next ld_step (init = LD_INIT_GIVEN)
+  st->px.ready = false;     // the proximal solver restarts its primal iterates from these duals
+  st->px.t = 0;
   LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
 }
@@ -1704,6 +1720,238 @@ static int tuned_engine(const ld_net* net, int B, int mma, int* fork = nullptr) 
   return it == mnet->engines.end() ? -1 : (int)it->second[0];
 }
 
+// ---------------------------------------------------------------------------
+// proximal solver (Sec. 3.3, Algorithm 2)
+// ---------------------------------------------------------------------------
+static int prox_alloc(const ld_net* net, ld_state* st) {
+  ld_state::Prox& P = st->px;
+  if (P.base) return LD_OK;
+  const int n = net->n, B = st->B;
+  int wmax = 0;
+  for (int k = 1; k <= n; ++k) wmax = std::max(wmax, width(net, k));
+  std::vector<size_t> sizes;
+  auto add = [&](size_t floats) {
+    sizes.push_back(round_up(std::max<size_t>(floats * 4, 4), 256));
+  };
+  for (int k = 1; k <= n - 1; ++k) add((size_t)B * width(net, k));  // xB
+  for (int k = 1; k <= n; ++k) add((size_t)B * width(net, k));      // xA
+  for (int k = 1; k <= n - 1; ++k) add((size_t)B * width(net, k));  // rt
+  for (int k = 1; k <= n - 1; ++k) add((size_t)B * width(net, k));  // pi
+  for (int k = 1; k <= n - 2; ++k) add((size_t)B * width(net, k));  // g
+  add((size_t)B * wmax);                                             // zA
+  add((size_t)B * width(net, n - 1));                                // z_{n-1}
+  size_t total = 0;
+  for (size_t z : sizes) total += z;
+  void* base = nullptr;
+  if (hipMalloc(&base, total) != hipSuccess) return fail(LD_E_NOMEM, "proximal buffers: hipMalloc failed");
+  char* c = (char*)base;
+  size_t i = 0, off = 0;
+  auto next = [&]() {
+    char* p = c + off;
+    off += sizes[i++];
+    return (float*)p;
+  };
+  P.base = base;
+  for (int k = 1; k <= n - 1; ++k) P.xB.push_back(next());
+  for (int k = 1; k <= n; ++k) P.xA.push_back(next());
+  for (int k = 1; k <= n - 1; ++k) P.rt.push_back(next());
+  for (int k = 1; k <= n - 1; ++k) P.pi.push_back(next());
+  P.g.assign(std::max(n - 1, 1), nullptr);
+  for (int k = 1; k <= n - 2; ++k) P.g[k] = next();
+  P.zA = next();
+  P.zlast = next();
+  return LD_OK;
+}
+
+// eta at outer iteration t (1-based): linear from eta0 (t = 1) to eta_end (t = T).
+static double prox_eta(const ld_prox_opts* o, int t) {
+  if (o->total_iters <= 1) return o->eta0;
+  return (double)o->eta0 + ((double)o->eta_end - (double)o->eta0) * (double)(t - 1) / (double)(o->total_iters - 1);
+}
+
+// Operand of the forward product of layer k+1 (k = 0..n-1): z_k.
+static const void* prox_operand(const ld_net* net, const ld_state* st, int k) {
+  return k <= net->n - 2 ? st->ws.xs[k] : st->px.zlast;
+}
+
+// Start of Algorithm 2: a minimiser of the Lagrangian at the current duals (the
+// inner minimisations of Sec. 3.2), xA_k = W_k x*_{k-1} + b_k for k = 1..n, pi = 0.
+static int prox_start(const ld_net* net, const ld_batch* bt, ld_state* st, int mma, float tau, hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  ld_state::Prox& P = st->px;
+  Workspace& ws = st->ws;
+  std::vector<const float*> r(st->rho.begin(), st->rho.end());
+  LD_TRY(phase_a(net, bt, r.data(), ws, mma, tau, 0, nullptr, nullptr, nullptr, s));
+  LD_HIP(launch_relu_operand((size_t)B * width(net, n - 1), ws.xb[n - 1], P.zlast, mma, s));
+  for (int k = 0; k <= n - 1; ++k) {
+    const Layer& L = net->L[k];
+    EpiArgs e = epi0();
+    e.kind = EPI_BIAS_STORE;
+    e.bias = L.bias;
+    e.out_f = P.xA[k];
+    LD_HIP(run_job(L.fwd, B, prox_operand(net, st, k), mma, mma, e, pick_tile(net, k, 0, B, mma), ws, k, s));
+  }
+  for (int k = 1; k <= n - 1; ++k) {
+    const size_t cnt = (size_t)B * width(net, k);
+    LD_HIP(launch_copy_f32(P.xB[k - 1], ws.xb[k], cnt, s));
+    LD_HIP(launch_fill_f32(P.pi[k - 1], cnt, 0.f, s));
+  }
+  return LD_OK;
+}
+
+static ProxDualPack prox_pack(const ld_net* net, ld_state* st, int first, int count) {
+  ProxDualPack p;
+  std::memset(&p, 0, sizeof(p));
+  p.n = count;
+  for (int i = 0; i < count; ++i) {
+    const int k = first + i;  // hidden layer
+    p.rho[i] = st->rho[k - 1];
+    p.pi[i] = st->px.pi[k - 1];
+    p.xB[i] = st->px.xB[k - 1];
+    p.xA[i] = st->px.xA[k - 1];
+    p.rt[i] = st->px.rt[k - 1];
+    p.cnt[i] = (size_t)st->B * width(net, k);
+  }
+  return p;
+}
+
+// update = 0: rt = rho + (xB - xA) / eta_next; update = 1: first the dual step
+// with momentum at eta, then rt for eta_next.
+static int prox_dual(const ld_net* net, ld_state* st, int update, double eta, double mu, double eta_next,
+                     hipStream_t s) {
+  const int nh = net->n - 1;
+  for (int first = 1; first <= nh; first += kProxPackMax) {
+    const ProxDualPack p = prox_pack(net, st, first, std::min(kProxPackMax, nh - first + 1));
+    LD_HIP(launch_prox_dual(p, update, (float)(1.0 / eta), (float)mu, (float)(1.0 / eta_next), s));
+  }
+  return LD_OK;
+}
+
+// One block-coordinate Frank-Wolfe sweep over the blocks k = 0..n-1.
+static int prox_sweep(const ld_net* net, const ld_batch* bt, ld_state* st, int mma, float tau, double eta,
+                      hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  ld_state::Prox& P = st->px;
+  Workspace& ws = st->ws;
+  // transposed products g_{k-1} = W_k^T rt_k; the one into the input box is fused
+  // with the box rule (the conditional gradient of block 0)
+  for (int k = 1; k <= n - 1; ++k) {
+    const Layer& L = net->L[k - 1];
+    EpiArgs e = epi0();
+    if (k == 1) {
+      e.kind = EPI_P0;
+      e.lo = bt->l0;
+      e.hi = bt->u0;
+      e.xs = ws.xs[0];
+      e.xs_bf16 = mma;
+    } else {
+      e.kind = EPI_STORE;
+      e.out_f = P.g[k - 1];
+    }
+    LD_HIP(run_job(L.tr, B, P.rt[k - 1], 0, tr_mode(mma, k), e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, s));
+  }
+  const double inv_eta = 1.0 / eta;
+  for (int k = 0; k <= n - 1; ++k) {
+    const Layer& L = net->L[k];
+    EpiArgs e = epi0();
+    e.kind = EPI_BIAS_STORE;
+    e.bias = L.bias;
+    e.out_f = P.zA;
+    LD_HIP(run_job(L.fwd, B, prox_operand(net, st, k), mma, mma, e, pick_tile(net, k, 0, B, mma), ws, k, s));
+    ProxBlockArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nB = k >= 1 ? width(net, k) : 0;
+    a.nA = width(net, k + 1);
+    a.last = k + 1 == n ? 1 : 0;
+    a.z_bf16 = mma;
+    a.inv_eta = (float)inv_eta;
+    a.inv_eta_d = inv_eta;
+    a.tau = tau;
+    if (k >= 1) {
+      a.xB = P.xB[k - 1];
+      a.zB = ws.xb[k];
+      a.rtB = P.rt[k - 1];
+      a.rhoB = st->rho[k - 1];
+      a.xAB = P.xA[k - 1];
+    }
+    a.xA = P.xA[k];
+    a.zA = P.zA;
+    if (a.last) {
+      a.c = bt->c;
+    } else {
+      a.rtA = P.rt[k];
+      a.rhoA = st->rho[k];
+      a.xBA = P.xB[k];
+      a.g = k + 1 == n - 1 ? ws.gconst : P.g[k + 1];
+      a.lo = bt->l[k];
+      a.hi = bt->u[k];
+      a.zB_out = ws.xb[k + 1];
+      a.z_out = const_cast<void*>(prox_operand(net, st, k + 1));
+    }
+    LD_HIP(launch_prox_block(a, B, s));
+  }
+  return LD_OK;
+}
+
+static int check_prox_args(const ld_net* net, const ld_batch* bt, const ld_state* st, const ld_prox_opts* o) {
+  LD_TRY(check_batch(net, bt));
+  if (!st || !o) return fail(LD_E_ARG, "state/opts is NULL");
+  if (st->net != net || st->B != bt->B) return fail(LD_E_STATE, "state was created for another net or batch size");
+  if (bt->B == 0) return fail(LD_E_ARG, "empty batch");
+  if (o->iters < 0 || o->total_iters < 1 || o->inner_iters < 1)
+    return fail(LD_E_ARG, "iters must be >= 0, total_iters >= 1 and inner_iters >= 1");
+  if (!(o->eta0 > 0.f) || !(o->eta_end > 0.f) || !std::isfinite(o->eta0) || !std::isfinite(o->eta_end))
+    return fail(LD_E_ARG, "eta0 and eta_end must be finite and > 0");
+  if (!(o->mu >= 0.f && o->mu < 1.f)) return fail(LD_E_ARG, "mu must be in [0, 1)");
+  if (o->precision != LD_FP32 && o->precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
+  if (o->init != LD_INIT_CROWN && o->init != LD_INIT_ZERO && o->init != LD_INIT_GIVEN) return fail(LD_E_ARG, "bad init");
+  if (!(o->tie_tau >= 0.f) || !std::isfinite(o->tie_tau)) return fail(LD_E_ARG, "tie_tau must be finite and >= 0");
+  if (net->n - 1 > 64) return fail(LD_E_UNSUPPORTED, "more than 64 hidden layers");
+  return LD_OK;
+}
+
+int ld_prox_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_prox_opts* o, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_prox_args(net, bt, st, o));
+  LD_TRY(validate_values(net, bt, st->ws, s));
+  const int mma = o->precision == LD_BF16 ? 1 : 0;
+  ld_opts lo;
+  std::memset(&lo, 0, sizeof(lo));
+  lo.iters = 0;
+  lo.total_iters = 1;
+  lo.precision = o->precision;
+  lo.init = o->init;
+  lo.tie_tau = o->tie_tau;
+  lo.engine = LD_ENGINE_LAYERWISE;
+  LD_TRY(ensure_initialised(net, bt, st, &lo, s));
+  LD_TRY(prox_alloc(net, st));
+  ld_state::Prox& P = st->px;
+  if (!P.ready || P.mma != mma) {
+    LD_TRY(prox_start(net, bt, st, mma, o->tie_tau, s));
+    P.ready = true;
+    P.mma = mma;
+    P.t = 0;
+  }
+  // coefficients of the next iteration under this call's schedule
+  LD_TRY(prox_dual(net, st, 0, 1.0, 0.0, prox_eta(o, P.t + 1), s));
+  for (int it = 0; it < o->iters; ++it) {
+    const int t = P.t + 1;
+    const double eta = prox_eta(o, t);
+    for (int j = 0; j < o->inner_iters; ++j) LD_TRY(prox_sweep(net, bt, st, mma, o->tie_tau, eta, s));
+    LD_TRY(prox_dual(net, st, 1, eta, o->mu, prox_eta(o, t + 1), s));
+    P.t = t;
+  }
+  LD_HIP(hipEventRecord(st->done, s));
+  return LD_OK;
+}
+
+int ld_prox_get_step(const ld_state* st, int* t) {
+  g_err.clear();
+  if (!st || !t) return fail(LD_E_ARG, "NULL argument");
+  *t = st->px.ready ? st->px.t : 0;
+  return LD_OK;
+}
+
 int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
   g_err.clear();
   LD_TRY(check_step_args(net, bt, st, o));
@@ -1801,6 +2049,8 @@ int ld_state_reset(ld_state* st, hipStream_t s) {
   LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
   st->t_host = 0;
   st->initialized = false;
+  st->px.ready = false;
+  st->px.t = 0;
   LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
 }

@@ -206,4 +206,50 @@ hipError_t launch_fill_i32(int* p, size_t n, int v, hipStream_t s);
 hipError_t launch_copy_f32(float* dst, const float* src, size_t n, hipStream_t s);
 hipError_t launch_max_f64(int B, const double* a, const double* b, double* out, hipStream_t s);
 
+// proximal solver (ld_prox.hip).  One block of the block-coordinate Frank-Wolfe
+// sweep, layer k: B part over layer k (nB = n_k, 0 for k = 0), A part over layer
+// k+1 (nA = n_{k+1}); `last` when k+1 = n (the objective layer: coefficient -c,
+// no proximal term, no next block).  All arrays are [B, width] row-major.
+struct ProxBlockArgs {
+  int nB, nA, last, z_bf16;
+  float inv_eta, tau;
+  double inv_eta_d;
+  // layer k: iterate xB_k (in/out), conditional gradient zB_k, coefficient rt_k
+  // (in/out), dual rho_k, iterate xA_k (already moved by the previous block)
+  float* xB;
+  const float* zB;
+  float* rtB;
+  const float* rhoB;
+  const float* xAB;
+  // layer k+1: iterate xA_{k+1} (in/out), its conditional gradient zA_{k+1};
+  // not last: rt_{k+1} (out), rho_{k+1}, xB_{k+1}; last: objective c
+  float* xA;
+  const float* zA;
+  float* rtA;
+  const float* rhoA;
+  const float* xBA;
+  const float* c;
+  // conditional gradient of block k+1 (not last): g_{k+1} = W_{k+2}^T rt_{k+2},
+  // bounds of layer k+1, outputs zB_{k+1} (FP32) and z_{k+1} (operand precision)
+  const float* g;
+  const float* lo;
+  const float* hi;
+  float* zB_out;
+  void* z_out;
+};
+constexpr int kProxPackMax = 16;
+struct ProxDualPack {
+  int n;
+  float* rho[kProxPackMax];
+  float* pi[kProxPackMax];
+  const float* xB[kProxPackMax];
+  const float* xA[kProxPackMax];
+  float* rt[kProxPackMax];
+  size_t cnt[kProxPackMax];
+};
+hipError_t launch_prox_block(const ProxBlockArgs& a, int B, hipStream_t s);
+hipError_t launch_prox_dual(const ProxDualPack& p, int update, float inv_eta, float mu, float inv_eta_next,
+                            hipStream_t s);
+hipError_t launch_relu_operand(size_t n, const float* xb, void* out, int bf16, hipStream_t s);
+
 }  // namespace ld

@@ -96,6 +96,8 @@ def test_null_arguments_rejected(lib):
     assert lib.ld_final_bound(None, None, None, None, None, None, None, ctypes.c_float(0.0), None) == -1
     assert lib.ld_init_duals(None, None, 0, 0, None, None) == -1
     assert lib.ld_state_create(None, 4, ctypes.byref(ctypes.c_void_p())) == -1
+    assert lib.ld_prox_step(None, None, None, None, None) == -1
+    assert lib.ld_prox_get_step(None, ctypes.byref(ctypes.c_int())) == -1
     assert "NULL" in lib.ld_last_error().decode()
 
 
