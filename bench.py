@@ -47,6 +47,8 @@ def parse():
                          "iterations launched without the graph; prints the per-launch averages")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--engine", choices=["auto", "layerwise", "resident"], default="auto")
+    ap.add_argument("--solver", choices=["ld", "prox"], default="ld",
+                    help="ld: Adam supergradient ascent (the headline line); prox: the proximal solver")
     return ap.parse_args()
 
 
@@ -83,6 +85,42 @@ def layer_slot_cost(inst, kind, B, prec):
     L = layers[k - 1]
     nb = width(k - 1) * opb + width(k) * 28
     return B * nb + wbytes(L), B * 2 * macs(L)
+
+
+def prox_slot_cost(inst, kind, B, prec):
+    """Algorithmic bytes and FLOPs of one launch of a proximal-iteration slot.
+
+      100+k W_k^T rt_k : read rt_k and W_k; write g_{k-1} (k >= 2) or, for k = 1,
+                         read l_0, u_0 and write z_0 (operand type)
+      300+k forward    : read z_{k-1} (operand type) and W_k; write zA_k
+      400+k block k    : layer k (k >= 1): read xB, zB, rt, rho, xA, write xB, rt;
+                         layer k+1: read xA, zA, rt, rho, xB, g, l, u, write xA, rt,
+                         zB and z (operand type); the objective layer: read xA, zA,
+                         c, write xA
+      500   dual update: per hidden neuron read xB, xA, rho, pi, write pi, rho, rt"""
+    layers = inst.layers
+    n = len(layers)
+    opb = 2 if prec == "bf16" else 4
+    ph, k = divmod(kind, 100)
+    width = lambda j: layers[0].n_in if j == 0 else layers[j - 1].n_out  # noqa: E731
+
+    def macs(L):
+        if L.kind == "linear":
+            return L.n_in * L.n_out
+        Co, Ho, Wo = L.out_shape
+        return Co * Ho * Wo * L.in_shape[0] * L.W.shape[2] * L.W.shape[3]
+    if ph == 1:
+        L = layers[k - 1]
+        nb = width(k) * 4 + (width(0) * (8 + opb) if k == 1 else width(k - 1) * 4)
+        return B * nb + L.W.size * opb, B * 2 * macs(L)
+    if ph == 3:
+        L = layers[k - 1]
+        return B * (width(k - 1) * opb + width(k) * 4) + L.W.size * opb, B * 2 * macs(L)
+    if ph == 4:
+        nb = width(k) * 28 if k >= 1 else 0
+        nb += width(k + 1) * (16 if k + 1 == n else 44 + opb)
+        return B * nb, 0
+    return B * sum(width(j) for j in range(1, n)) * 28, 0
 
 
 def kernel_name(info, kind, inst, prec="fp32"):
@@ -144,6 +182,123 @@ def cpu_baseline(inst, T, sample):
     return out, idx, fb["bound"]
 
 
+def cpu_baseline_prox(inst, T, sample):
+    """The FP64 oracle's proximal solver on the first `sample` subdomains, timed on the host."""
+    import torch
+    from oracle import ld_oracle as O
+    idx = list(range(min(sample, inst.B)))
+    onet = O.net_from_specs(inst.layers)
+    ob = O.batch_from_instance(inst, idx)
+    t0 = time.perf_counter()
+    st = O.proximal(onet, ob, O.ProxOpts(T=T))
+    fb = O.final_bound(onet, ob, st)
+    dt = time.perf_counter() - t0
+    out = dict(value=len(idx) / dt, unit="bounds/s", cores=torch.get_num_threads(), kind="oracle",
+               sample=f"{len(idx)} of {inst.B} subdomains (the first ones), {T} outer iterations each, "
+                      f"FP64 torch-CPU oracle, {dt:.1f} s")
+    return out, idx, fb["bound"]
+
+
+def prox_kernel_name(info, kind, inst, prec):
+    ph, k = divmod(kind, 100)
+    if ph == 1:
+        return kernel_name(info, 100 + k, inst, prec)
+    if ph == 3:
+        return kernel_name(info, 300 + k, inst, prec)
+    return "prox_block_kernel" if ph == 4 else "prox_dual_kernel"
+
+
+def main_prox(a, P, inst, net, batch):
+    """Proximal solver (Algorithm 2, Sec. 7.2 settings: J = 2, mu = 0.3, eta 10 -> 500)
+    on the same workload: CROWN init, T outer iterations, final bound."""
+    import torch
+    B = inst.B
+    T = a.iters or 100
+    kw = dict(total_iters=T, inner_iters=2, eta0=10.0, eta_end=500.0, mu=0.3)
+    res = {}
+    for prec in ("fp32", "bf16"):
+        # launch configurations of the contractions (shared with the supergradient method)
+        P.autotune(net, batch, precision=prec)
+        st = P.State(net, B)
+        for _ in range(a.warmup):
+            st.reset()
+            P.prox_step(net, batch, st, iters=T, precision=prec, **kw)
+            P.final_bound(net, batch, st)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fb = None
+        for _ in range(a.steps):
+            st.reset()
+            P.prox_step(net, batch, st, iters=T, precision=prec, **kw)
+            fb = P.final_bound(net, batch, st)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        # per-launch timing of one outer iteration (HIP events on the launch stream)
+        slots = P.prox_profile_iteration(net, batch, st, reps=a.reps, precision=prec, **kw)
+        torch.cuda.synchronize()
+        res[prec] = dict(ms=ms, fb=fb, slots=slots)
+    # the supergradient method's bound on the same batch (context, not timed)
+    stl = P.State(net, B)
+    P.step(net, batch, stl, iters=500, total_iters=500, precision="fp32")
+    b_ld = P.final_bound(net, batch, stl)["bound"]
+    torch.cuda.synchronize()
+
+    head = "fp32"
+    slots = res[head]["slots"]
+    info = P.tuning_info(net, B, head)
+    kind, us = max(slots, key=lambda x: x[1])
+    nbytes, flops = prox_slot_cost(inst, kind, B, head)
+    ridge = PEAK_TFLOPS[head] * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if flops / max(nbytes, 1) < ridge:
+        roof = dict(bound="hbm", achieved=nbytes / (us * 1e-6) / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
+    else:
+        roof = dict(bound="mfma", achieved=flops / (us * 1e-6) / 1e12, peak=PEAK_TFLOPS[head], unit="TFLOP/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    kname = prox_kernel_name(info, kind, inst, head)
+    roof["traffic"] = stored_traffic(kname, kind, a.config + "/prox", B, head)
+    roof["kernel"] = f"{kname}: slot {kind}"
+    roof["avg_us"] = us
+    roof["algorithmic_bytes"] = nbytes
+    roof["algorithmic_flops"] = flops
+    b32 = res["fp32"]["fb"]["bound"]
+    b16 = res["bf16"]["fb"]["bound"]
+    value = B / (res[head]["ms"] / 1000.0)
+    out = {
+        "metric": f"proximal-solver bounds/sec ({T} outer iters, J=2, B={B}, {a.config} conv net)",
+        "value": value,
+        "unit": "bounds/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": res[head]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.config} conv net 3x32x32, B={B}, proximal T={T}, J=2, mu=0.3, eta 10->500, "
+                               f"1 property, 5% random ReLU splits per subdomain", "B": B, "iters": T},
+        "fp32": {"value": value, "ms_per_step": res["fp32"]["ms"], "mean_bound": b32.mean().item()},
+        "bf16": {"value": B / (res["bf16"]["ms"] / 1000.0), "ms_per_step": res["bf16"]["ms"],
+                 "mean_bound": b16.mean().item(), "gap_mean": (b32 - b16).mean().item()},
+        "supergradient_500_fp32_mean_bound": b_ld.mean().item(),
+        "roofline": roof,
+        "per_launch_us": {p: {str(k): round(v, 2) for k, v in res[p]["slots"]} for p in res},
+    }
+    if not a.no_cpu_baseline:
+        cb, idx, ob = cpu_baseline_prox(inst, T, a.cpu_sample)
+        out["cpu_baseline"] = cb
+        for p in ("fp32", "bf16"):
+            d = res[p]["fb"]["bound"].cpu()[idx] - ob
+            out[p]["minus_oracle"] = {"mean": d.mean().item(), "max_abs": d.abs().max().item(),
+                                      "subdomains": len(idx), "oracle_iters": T}
+    print(json.dumps(out), flush=True)
+
+
 def src_hash():
     """Hash of the HIP sources (a stored counter measurement is valid for this build only)."""
     h = hashlib.sha256()
@@ -188,6 +343,10 @@ def main():
     batch = P.Batch.from_instance(inst)
     P.set_validation(False)
 
+    if a.solver == "prox" and not a.profile_only:
+        main_prox(a, P, inst, net, batch)
+        return
+
     if a.profile_only:
         # counter calibration: a 1 GiB device copy (far larger than L2 and the MALL)
         x = torch.ones(256 << 20, device="cuda", dtype=torch.float32)
@@ -197,12 +356,20 @@ def main():
         torch.cuda.synchronize()
         del x, y
         stp = P.State(net, B)
-        P.step(net, batch, stp, iters=2, total_iters=T, precision=a.profile_only)
-        slots = P.profile_iteration(net, batch, stp, reps=a.reps, total_iters=T, precision=a.profile_only)
+        if a.solver == "prox":
+            P.autotune(net, batch, precision=a.profile_only)
+            Tp = a.iters or 100
+            P.prox_step(net, batch, stp, iters=2, total_iters=Tp, precision=a.profile_only)
+            slots = P.prox_profile_iteration(net, batch, stp, reps=a.reps, total_iters=Tp, precision=a.profile_only)
+            name = lambda info, k: prox_kernel_name(info, k, inst, a.profile_only)  # noqa: E731
+        else:
+            P.step(net, batch, stp, iters=2, total_iters=T, precision=a.profile_only)
+            slots = P.profile_iteration(net, batch, stp, reps=a.reps, total_iters=T, precision=a.profile_only)
+            name = lambda info, k: kernel_name(info, k, inst, a.profile_only)  # noqa: E731
         torch.cuda.synchronize()
         info = P.tuning_info(net, B, a.profile_only)
-        print(json.dumps({"profile_only": a.profile_only, "config": a.config, "B": B, "reps": a.reps,
-                          "slots": [[k, kernel_name(info, k, inst, a.profile_only), round(v, 2)] for k, v in slots],
+        print(json.dumps({"profile_only": a.profile_only, "solver": a.solver, "config": a.config, "B": B,
+                          "reps": a.reps, "slots": [[k, name(info, k), round(v, 2)] for k, v in slots],
                           "tuned": info}), flush=True)
         return
 

@@ -32,7 +32,7 @@ EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num
             "ld_state_get_rho", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
-            "ld_prox_step", "ld_prox_get_step", "ld_final_bound", "ld_last_error"]
+            "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
 
 
 class LDError(RuntimeError):
@@ -116,6 +116,8 @@ def load_library(path: Optional[str] = None):
     lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
     lib.ld_prox_step.argtypes = [V, P(ld_batch), V, P(ld_prox_opts), V]
     lib.ld_prox_get_step.argtypes = [V, P(I)]
+    lib.ld_prox_profile_iteration.argtypes = [V, P(ld_batch), V, P(ld_prox_opts), I, P(ctypes.c_double), P(I), I,
+                                              P(I), V]
     for name in EXPORTED:
         getattr(lib, name)
     if path is None:
@@ -299,6 +301,19 @@ def prox_step(net: Net, batch: Batch, state: State, iters: int, total_iters: Opt
                      _PREC[precision], _INIT[init], tau)
     _check(net.lib.ld_prox_step(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o),
                                 _stream(stream)))
+
+
+def prox_profile_iteration(net: Net, batch: Batch, state: State, reps=20, total_iters=100, inner_iters=2,
+                           eta0=10.0, eta_end=500.0, mu=0.3, precision="fp32", tau: float = TAU_DEFAULT,
+                           stream=None):
+    """[(slot, average us per launch)] of one proximal outer iteration (ld_prox_profile_iteration)."""
+    o = ld_prox_opts(1, total_iters, inner_iters, eta0, eta_end, mu, _PREC[precision], _INIT["crown"], tau)
+    avg = (ctypes.c_double * 64)()
+    kinds = (ctypes.c_int * 64)()
+    ns = ctypes.c_int()
+    _check(net.lib.ld_prox_profile_iteration(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o),
+                                             reps, avg, kinds, 64, ctypes.byref(ns), _stream(stream)))
+    return [(kinds[i], avg[i]) for i in range(ns.value)]
 
 
 def autotune(net: Net, batch: Batch, total_iters=500, lr0=1e-2, lr_end=1e-4, beta1=0.9, beta2=0.999, eps=1e-8,

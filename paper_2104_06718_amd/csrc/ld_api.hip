@@ -1827,9 +1827,13 @@ static int prox_dual(const ld_net* net, ld_state* st, int update, double eta, do
   return LD_OK;
 }
 
-// One block-coordinate Frank-Wolfe sweep over the blocks k = 0..n-1.
-static int prox_sweep(const ld_net* net, const ld_batch* bt, ld_state* st, int mma, float tau, double eta,
-                      hipStream_t s) {
+// The launches of one block-coordinate Frank-Wolfe sweep over the blocks
+// k = 0..n-1, in order, each with its slot: 100+k the transposed product
+// W_k^T rt_k, 300+k the forward product of layer k (block k-1), 400+k the block
+// kernel of block k.
+using Launch = std::pair<int, std::function<int()>>;
+static void prox_sweep_launches(const ld_net* net, const ld_batch* bt, ld_state* st, int mma, float tau, double eta,
+                                hipStream_t s, std::vector<Launch>& out) {
   const int n = net->n, B = bt->B;
   ld_state::Prox& P = st->px;
   Workspace& ws = st->ws;
@@ -1848,7 +1852,12 @@ static int prox_sweep(const ld_net* net, const ld_batch* bt, ld_state* st, int m
       e.kind = EPI_STORE;
       e.out_f = P.g[k - 1];
     }
-    LD_HIP(run_job(L.tr, B, P.rt[k - 1], 0, tr_mode(mma, k), e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, s));
+    const Tile t = pick_tile(net, k - 1, 1, B, mma);
+    const float* src = P.rt[k - 1];
+    out.push_back({100 + k, [=, &L, &ws]() -> int {
+                     LD_HIP(run_job(L.tr, B, src, 0, tr_mode(mma, k), e, t, ws, k - 1, s));
+                     return LD_OK;
+                   }});
   }
   const double inv_eta = 1.0 / eta;
   for (int k = 0; k <= n - 1; ++k) {
@@ -1857,7 +1866,12 @@ static int prox_sweep(const ld_net* net, const ld_batch* bt, ld_state* st, int m
     e.kind = EPI_BIAS_STORE;
     e.bias = L.bias;
     e.out_f = P.zA;
-    LD_HIP(run_job(L.fwd, B, prox_operand(net, st, k), mma, mma, e, pick_tile(net, k, 0, B, mma), ws, k, s));
+    const Tile t = pick_tile(net, k, 0, B, mma);
+    const void* src = prox_operand(net, st, k);
+    out.push_back({300 + k + 1, [=, &L, &ws]() -> int {
+                     LD_HIP(run_job(L.fwd, B, src, mma, mma, e, t, ws, k, s));
+                     return LD_OK;
+                   }});
     ProxBlockArgs a;
     std::memset(&a, 0, sizeof(a));
     a.nB = k >= 1 ? width(net, k) : 0;
@@ -1888,8 +1902,18 @@ static int prox_sweep(const ld_net* net, const ld_batch* bt, ld_state* st, int m
       a.zB_out = ws.xb[k + 1];
       a.z_out = const_cast<void*>(prox_operand(net, st, k + 1));
     }
-    LD_HIP(launch_prox_block(a, B, s));
+    out.push_back({400 + k, [=]() -> int {
+                     LD_HIP(launch_prox_block(a, B, s));
+                     return LD_OK;
+                   }});
   }
+}
+
+static int prox_sweep(const ld_net* net, const ld_batch* bt, ld_state* st, int mma, float tau, double eta,
+                      hipStream_t s) {
+  std::vector<Launch> ls;
+  prox_sweep_launches(net, bt, st, mma, tau, eta, s, ls);
+  for (auto& l : ls) LD_TRY(l.second());
   return LD_OK;
 }
 
@@ -1941,6 +1965,49 @@ int ld_prox_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_p
     LD_TRY(prox_dual(net, st, 1, eta, o->mu, prox_eta(o, t + 1), s));
     P.t = t;
   }
+  LD_HIP(hipEventRecord(st->done, s));
+  return LD_OK;
+}
+
+int ld_prox_profile_iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_prox_opts* o, int reps,
+                              double* avg_us, int* kinds, int max_slots, int* n_slots, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_prox_args(net, bt, st, o));
+  if (reps <= 0 || !avg_us || !kinds || !n_slots || max_slots <= 0) return fail(LD_E_ARG, "bad profile arguments");
+  if (!st->px.ready) return fail(LD_E_STATE, "no proximal iteration has run on this state");
+  const int mma = o->precision == LD_BF16 ? 1 : 0;
+  if (st->px.mma != mma) return fail(LD_E_STATE, "the state's proximal iterates were formed in another precision");
+  const double eta = prox_eta(o, st->px.t + 1);
+  std::vector<Launch> ls;
+  prox_sweep_launches(net, bt, st, mma, o->tie_tau, eta, s, ls);
+  ls.push_back({500, [&]() -> int { return prox_dual(net, st, 1, eta, o->mu, eta, s); }});
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  LD_HIP(hipEventCreate(&e0));
+  LD_HIP(hipEventCreate(&e1));
+  struct EventGuard {
+    hipEvent_t a, b;
+    ~EventGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } eguard{e0, e1};
+  int ns = 0;
+  for (auto& l : ls) {
+    if (ns >= max_slots) break;
+    LD_TRY(l.second());  // warm-up
+    LD_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) LD_TRY(l.second());
+    LD_HIP(hipEventRecord(e1, s));
+    LD_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    LD_HIP(hipEventElapsedTime(&ms, e0, e1));
+    avg_us[ns] = 1000.0 * ms / reps;
+    kinds[ns] = l.first;
+    ++ns;
+  }
+  *n_slots = ns;
+  // the repeated launches moved the iterates: restart them at the next call
+  st->px.ready = false;
   LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
 }

@@ -22,9 +22,12 @@
 
 namespace ld {
 
-// Sum of two doubles over the 256 threads of a block; every thread gets the sums.
+constexpr int kProxThreads = 1024;  // 16 waves per subdomain: enough loads in flight per CU
+
+// Sum of two doubles over the threads of a block; every thread gets the sums.
 __device__ __forceinline__ void block_sum2(double& a, double& b) {
-  __shared__ double sa[4], sb[4];
+  constexpr int NW = kProxThreads / 64;
+  __shared__ double sa[NW], sb[NW];
   for (int o = 32; o > 0; o >>= 1) {
     a += __shfl_xor(a, o, 64);
     b += __shfl_xor(b, o, 64);
@@ -36,28 +39,67 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
   }
   __syncthreads();
   // fixed order: the same sums on every thread and every run
-  a = (sa[0] + sa[1]) + (sa[2] + sa[3]);
-  b = (sb[0] + sb[1]) + (sb[2] + sb[3]);
+  a = 0.0;
+  b = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    a += sa[i];
+    b += sb[i];
+  }
 }
 
-__global__ __launch_bounds__(256) void prox_block_kernel(ProxBlockArgs P) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ float4 ld4f(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void st4f(float* p, float a, float b, float c, float d) {
+  *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
+}
+__device__ __forceinline__ float f4at(const float4& v, int q) { return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w; }
+
+// Elements of a row that thread `tid` owns: where the row's width is a multiple
+// of 4, the 16-byte groups i = 4*tid + 4*kProxThreads*j, else the single
+// elements i = tid + kProxThreads*j.
+__global__ __launch_bounds__(kProxThreads) void prox_block_kernel(ProxBlockArgs P) {
+  const int b = blockIdx.x, tid = threadIdx.x;
   const size_t ob = (size_t)b * P.nB, oa = (size_t)b * P.nA;
+  const bool vB = (P.nB & 3) == 0, vA = (P.nA & 3) == 0;
   // 1. directional derivative and curvature of the augmented Lagrangian along the
   //    segment from the iterate to the conditional gradient
   double num = 0.0, den = 0.0;
-  for (int i = threadIdx.x; i < P.nB; i += 256) {
-    const double d = (double)P.xB[ob + i] - (double)P.zB[ob + i];
-    num += (double)P.rtB[ob + i] * d;
-    den += d * d;
+  if (vB) {
+    for (int i = 4 * tid; i < P.nB; i += 4 * kProxThreads) {
+      const float4 x = ld4f(P.xB + ob + i), z = ld4f(P.zB + ob + i), r = ld4f(P.rtB + ob + i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double d = (double)f4at(x, q) - (double)f4at(z, q);
+        num += (double)f4at(r, q) * d;
+        den += d * d;
+      }
+    }
+  } else {
+    for (int i = tid; i < P.nB; i += kProxThreads) {
+      const double d = (double)P.xB[ob + i] - (double)P.zB[ob + i];
+      num += (double)P.rtB[ob + i] * d;
+      den += d * d;
+    }
   }
-  for (int i = threadIdx.x; i < P.nA; i += 256) {
-    const double e = (double)P.xA[oa + i] - (double)P.zA[oa + i];
-    if (P.last) {
-      num += (double)P.c[oa + i] * e;       // coefficient of xA_n is c (rt_n = -c)
-    } else {
-      num -= (double)P.rtA[oa + i] * e;
-      den += e * e;
+  // coefficient of xA_{k+1}: -rt_{k+1}; of the objective layer's xA_n: c
+  const float* cA = P.last ? P.c : P.rtA;
+  const double sgn = P.last ? 1.0 : -1.0;
+  const double curv = P.last ? 0.0 : 1.0;
+  if (vA) {
+    for (int i = 4 * tid; i < P.nA; i += 4 * kProxThreads) {
+      const float4 x = ld4f(P.xA + oa + i), z = ld4f(P.zA + oa + i), r = ld4f(cA + oa + i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double e = (double)f4at(x, q) - (double)f4at(z, q);
+        num += sgn * (double)f4at(r, q) * e;
+        den += curv * e * e;
+      }
+    }
+  } else {
+    for (int i = tid; i < P.nA; i += kProxThreads) {
+      const double e = (double)P.xA[oa + i] - (double)P.zA[oa + i];
+      num += sgn * (double)cA[oa + i] * e;
+      den += curv * e * e;
     }
   }
   block_sum2(num, den);
@@ -65,28 +107,74 @@ __global__ __launch_bounds__(256) void prox_block_kernel(ProxBlockArgs P) {
   // zero curvature: the segment is linear, take all of it if it descends
   const double gd = den > 0.0 ? fmin(fmax(num / den, 0.0), 1.0) : (num > 0.0 ? 1.0 : 0.0);
   const float g = (float)gd;
+  const float ie = P.inv_eta;
   // 2. Frank-Wolfe step on xB_k and the refreshed coefficient rt_k
-  for (int i = threadIdx.x; i < P.nB; i += 256) {
-    const float x = P.xB[ob + i];
-    const float xn = x + g * (P.zB[ob + i] - x);
-    P.xB[ob + i] = xn;
-    P.rtB[ob + i] = P.rhoB[ob + i] + (xn - P.xAB[ob + i]) * P.inv_eta;
+  if (vB) {
+    for (int i = 4 * tid; i < P.nB; i += 4 * kProxThreads) {
+      const float4 x = ld4f(P.xB + ob + i), z = ld4f(P.zB + ob + i);
+      const float4 r = ld4f(P.rhoB + ob + i), a = ld4f(P.xAB + ob + i);
+      float xn[4], rn[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        xn[q] = f4at(x, q) + g * (f4at(z, q) - f4at(x, q));
+        rn[q] = f4at(r, q) + (xn[q] - f4at(a, q)) * ie;
+      }
+      st4f(P.xB + ob + i, xn[0], xn[1], xn[2], xn[3]);
+      st4f(P.rtB + ob + i, rn[0], rn[1], rn[2], rn[3]);
+    }
+  } else {
+    for (int i = tid; i < P.nB; i += kProxThreads) {
+      const float x = P.xB[ob + i];
+      const float xn = x + g * (P.zB[ob + i] - x);
+      P.xB[ob + i] = xn;
+      P.rtB[ob + i] = P.rhoB[ob + i] + (xn - P.xAB[ob + i]) * ie;
+    }
   }
   // 3. Frank-Wolfe step on xA_{k+1}; rt_{k+1}; conditional gradient of block k+1
-  for (int i = threadIdx.x; i < P.nA; i += 256) {
-    const float x = P.xA[oa + i];
-    const float xn = x + g * (P.zA[oa + i] - x);
-    P.xA[oa + i] = xn;
-    if (P.last) continue;
-    const float r = P.rhoA[oa + i] + (P.xBA[oa + i] - xn) * P.inv_eta;
-    P.rtA[oa + i] = r;
-    float zb, z, val;
-    inner_min<float>(r, P.g[oa + i], P.lo[oa + i], P.hi[oa + i], P.tau, zb, z, val);
-    P.zB_out[oa + i] = zb;
-    if (P.z_bf16)
-      ((bf16_t*)P.z_out)[oa + i] = f2bf(z);
-    else
-      ((float*)P.z_out)[oa + i] = z;
+  if (vA) {
+    for (int i = 4 * tid; i < P.nA; i += 4 * kProxThreads) {
+      const float4 x = ld4f(P.xA + oa + i), z = ld4f(P.zA + oa + i);
+      float xn[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xn[q] = f4at(x, q) + g * (f4at(z, q) - f4at(x, q));
+      st4f(P.xA + oa + i, xn[0], xn[1], xn[2], xn[3]);
+      if (P.last) continue;
+      const float4 r = ld4f(P.rhoA + oa + i), xb = ld4f(P.xBA + oa + i), gg = ld4f(P.g + oa + i);
+      const float4 lo = ld4f(P.lo + oa + i), hi = ld4f(P.hi + oa + i);
+      float rn[4], zb[4], zz[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        rn[q] = f4at(r, q) + (f4at(xb, q) - xn[q]) * ie;
+        float val;
+        inner_min<float>(rn[q], f4at(gg, q), f4at(lo, q), f4at(hi, q), P.tau, zb[q], zz[q], val);
+      }
+      st4f(P.rtA + oa + i, rn[0], rn[1], rn[2], rn[3]);
+      st4f(P.zB_out + oa + i, zb[0], zb[1], zb[2], zb[3]);
+      if (P.z_bf16) {
+        uint2 w;
+        w.x = (uint32_t)f2bf(zz[0]) | ((uint32_t)f2bf(zz[1]) << 16);
+        w.y = (uint32_t)f2bf(zz[2]) | ((uint32_t)f2bf(zz[3]) << 16);
+        *reinterpret_cast<uint2*>((bf16_t*)P.z_out + oa + i) = w;
+      } else {
+        st4f((float*)P.z_out + oa + i, zz[0], zz[1], zz[2], zz[3]);
+      }
+    }
+  } else {
+    for (int i = tid; i < P.nA; i += kProxThreads) {
+      const float x = P.xA[oa + i];
+      const float xn = x + g * (P.zA[oa + i] - x);
+      P.xA[oa + i] = xn;
+      if (P.last) continue;
+      const float r = P.rhoA[oa + i] + (P.xBA[oa + i] - xn) * ie;
+      P.rtA[oa + i] = r;
+      float zb, z, val;
+      inner_min<float>(r, P.g[oa + i], P.lo[oa + i], P.hi[oa + i], P.tau, zb, z, val);
+      P.zB_out[oa + i] = zb;
+      if (P.z_bf16)
+        ((bf16_t*)P.z_out)[oa + i] = f2bf(z);
+      else
+        ((float*)P.z_out)[oa + i] = z;
+    }
   }
 }
 
@@ -101,16 +189,37 @@ __global__ __launch_bounds__(256) void prox_dual_kernel(ProxDualPack P, int upda
   const float* __restrict__ xB = P.xB[L];
   const float* __restrict__ xA = P.xA[L];
   float* __restrict__ rt = P.rt[L];
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const float d = xB[i] - xA[i];
-    float r = rho[i];
+  auto one = [&](float d, float& r, float& p, float& t) {
     if (update) {
-      const float p = mu * pi[i] + d * inv_eta;
-      pi[i] = p;
+      p = mu * p + d * inv_eta;
       r = r + p;
+    }
+    t = r + d * inv_eta_next;
+  };
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t n4 = n / 4;  // 16-byte groups (every array starts 256-byte aligned)
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+    const float4 b = ld4f(xB + 4 * i), a = ld4f(xA + 4 * i);
+    float4 r = ld4f(rho + 4 * i), p = update ? ld4f(pi + 4 * i) : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 t;
+    one(b.x - a.x, r.x, p.x, t.x);
+    one(b.y - a.y, r.y, p.y, t.y);
+    one(b.z - a.z, r.z, p.z, t.z);
+    one(b.w - a.w, r.w, p.w, t.w);
+    if (update) {
+      *reinterpret_cast<float4*>(pi + 4 * i) = p;
+      *reinterpret_cast<float4*>(rho + 4 * i) = r;
+    }
+    *reinterpret_cast<float4*>(rt + 4 * i) = t;
+  }
+  for (size_t i = 4 * n4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    float r = rho[i], p = update ? pi[i] : 0.f, t;
+    one(xB[i] - xA[i], r, p, t);
+    if (update) {
+      pi[i] = p;
       rho[i] = r;
     }
-    rt[i] = r + d * inv_eta_next;
+    rt[i] = t;
   }
 }
 
@@ -141,7 +250,7 @@ hipError_t launch_prox_block(const ProxBlockArgs& a, int B, hipStream_t s) {
                                            !a.z_out)))
     return hipErrorInvalidValue;
   if (a.nB > 0 && (!a.xB || !a.zB || !a.rtB || !a.rhoB || !a.xAB)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(prox_block_kernel, dim3(B), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(prox_block_kernel, dim3(B), dim3(kProxThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -151,7 +260,7 @@ hipError_t launch_prox_dual(const ProxDualPack& p, int update, float inv_eta, fl
   if (p.n > kProxPackMax) return hipErrorInvalidValue;
   size_t mx = 0;
   for (int i = 0; i < p.n; ++i) mx = p.cnt[i] > mx ? p.cnt[i] : mx;
-  hipLaunchKernelGGL(prox_dual_kernel, dim3(grid_1d(mx), p.n), dim3(256), 0, s, p, update, inv_eta, mu,
+  hipLaunchKernelGGL(prox_dual_kernel, dim3(grid_1d(mx / 4 + 1), p.n), dim3(256), 0, s, p, update, inv_eta, mu,
                      inv_eta_next);
   return hipGetLastError();
 }
