@@ -93,11 +93,12 @@ def prox_slot_cost(inst, kind, B, prec):
       100+k W_k^T rt_k : read rt_k and W_k; write g_{k-1} (k >= 2) or, for k = 1,
                          read l_0, u_0 and write z_0 (operand type)
       300+k forward    : read z_{k-1} (operand type) and W_k; write zA_k
-      400+k block k    : layer k (k >= 1): read xB, zB, rt, rho, xA, write xB, rt;
+      400+k block k    : layer k (k >= 1): read xB, zB, rt, rho, xA, pi, write xB,
+                         rt, rho, pi (the last sweep of an outer iteration, timed
+                         here, also takes the dual update);
                          layer k+1: read xA, zA, rt, rho, xB, g, l, u, write xA, rt,
                          zB and z (operand type); the objective layer: read xA, zA,
-                         c, write xA
-      500   dual update: per hidden neuron read xB, xA, rho, pi, write pi, rho, rt"""
+                         c, write xA"""
     layers = inst.layers
     n = len(layers)
     opb = 2 if prec == "bf16" else 4
@@ -116,11 +117,9 @@ def prox_slot_cost(inst, kind, B, prec):
     if ph == 3:
         L = layers[k - 1]
         return B * (width(k - 1) * opb + width(k) * 4) + L.W.size * opb, B * 2 * macs(L)
-    if ph == 4:
-        nb = width(k) * 28 if k >= 1 else 0
-        nb += width(k + 1) * (16 if k + 1 == n else 44 + opb)
-        return B * nb, 0
-    return B * sum(width(j) for j in range(1, n)) * 28, 0
+    nb = width(k) * 40 if k >= 1 else 0
+    nb += width(k + 1) * (16 if k + 1 == n else 44 + opb)
+    return B * nb, 0
 
 
 def kernel_name(info, kind, inst, prec="fp32"):
@@ -205,7 +204,7 @@ def prox_kernel_name(info, kind, inst, prec):
         return kernel_name(info, 100 + k, inst, prec)
     if ph == 3:
         return kernel_name(info, 300 + k, inst, prec)
-    return "prox_block_kernel" if ph == 4 else "prox_dual_kernel"
+    return "prox_block_kernel"
 
 
 def main_prox(a, P, inst, net, batch):

@@ -341,13 +341,14 @@ typedef struct ld_prox_opts {
  * call.  Errors: LD_E_ARG (bad options), LD_E_STATE, LD_E_NUMERIC, LD_E_NOMEM. */
 int ld_prox_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_prox_opts* opts,
                  hipStream_t stream);
-/* Per-launch timing of one outer iteration of the proximal solver (one sweep
- * and the dual update), for profiling: each launch is enqueued reps + 1 times
- * back to back on `stream` and timed with HIP events (the first is a warm-up);
- * slots 100+k: W_k^T rt_k; 300+k: forward product of layer k; 400+k: block
- * kernel of block k; 500: dual update.  Needs a state on which ld_prox_step has
- * run with the same precision; the repeated launches move the iterates, so the
- * next ld_prox_step restarts the primal iterates at the state's duals.
+/* Per-launch timing of the last sweep of an outer iteration of the proximal
+ * solver (its block kernels also take the dual update), for profiling: each
+ * launch is enqueued reps + 1 times back to back on `stream` and timed with HIP
+ * events (the first is a warm-up); slots 100+k: W_k^T rt_k; 300+k: forward
+ * product of layer k; 400+k: block kernel of block k.  Needs a state on which ld_prox_step has
+ * run with the same precision; the repeated launches move the iterates and the
+ * duals (a profile is not a solve), and the next ld_prox_step restarts the
+ * primal iterates at the state's duals.
  * Synchronises `stream`. */
 int ld_prox_profile_iteration(const ld_net* net, const ld_batch* batch, ld_state* st,
                               const ld_prox_opts* opts, int reps, double* avg_us, int* kinds,

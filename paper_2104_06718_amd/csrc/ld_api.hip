@@ -1799,30 +1799,22 @@ static int prox_start(const ld_net* net, const ld_batch* bt, ld_state* st, int m
   return LD_OK;
 }
 
-static ProxDualPack prox_pack(const ld_net* net, ld_state* st, int first, int count) {
-  ProxDualPack p;
-  std::memset(&p, 0, sizeof(p));
-  p.n = count;
-  for (int i = 0; i < count; ++i) {
-    const int k = first + i;  // hidden layer
-    p.rho[i] = st->rho[k - 1];
-    p.pi[i] = st->px.pi[k - 1];
-    p.xB[i] = st->px.xB[k - 1];
-    p.xA[i] = st->px.xA[k - 1];
-    p.rt[i] = st->px.rt[k - 1];
-    p.cnt[i] = (size_t)st->B * width(net, k);
-  }
-  return p;
-}
-
-// update = 0: rt = rho + (xB - xA) / eta_next; update = 1: first the dual step
-// with momentum at eta, then rt for eta_next.
-static int prox_dual(const ld_net* net, ld_state* st, int update, double eta, double mu, double eta_next,
-                     hipStream_t s) {
+// rt = rho + (xB - xA) / eta for every hidden layer.
+static int prox_coeff(const ld_net* net, ld_state* st, double eta, hipStream_t s) {
   const int nh = net->n - 1;
   for (int first = 1; first <= nh; first += kProxPackMax) {
-    const ProxDualPack p = prox_pack(net, st, first, std::min(kProxPackMax, nh - first + 1));
-    LD_HIP(launch_prox_dual(p, update, (float)(1.0 / eta), (float)mu, (float)(1.0 / eta_next), s));
+    ProxDualPack p;
+    std::memset(&p, 0, sizeof(p));
+    p.n = std::min(kProxPackMax, nh - first + 1);
+    for (int i = 0; i < p.n; ++i) {
+      const int k = first + i;  // hidden layer
+      p.rho[i] = st->rho[k - 1];
+      p.xB[i] = st->px.xB[k - 1];
+      p.xA[i] = st->px.xA[k - 1];
+      p.rt[i] = st->px.rt[k - 1];
+      p.cnt[i] = (size_t)st->B * width(net, k);
+    }
+    LD_HIP(launch_prox_coeff(p, (float)(1.0 / eta), s));
   }
   return LD_OK;
 }
@@ -1832,8 +1824,11 @@ static int prox_dual(const ld_net* net, ld_state* st, int update, double eta, do
 // W_k^T rt_k, 300+k the forward product of layer k (block k-1), 400+k the block
 // kernel of block k.
 using Launch = std::pair<int, std::function<int()>>;
+// With `dual` the block kernels also take the dual update of the outer iteration
+// (momentum mu, then rt for eta_next).  Everything runs on one stream: forking the
+// independent transposed products onto side streams made the solve slower.
 static void prox_sweep_launches(const ld_net* net, const ld_batch* bt, ld_state* st, int mma, float tau, double eta,
-                                hipStream_t s, std::vector<Launch>& out) {
+                                bool dual, double mu, double eta_next, hipStream_t s, std::vector<Launch>& out) {
   const int n = net->n, B = bt->B;
   ld_state::Prox& P = st->px;
   Workspace& ws = st->ws;
@@ -1881,7 +1876,11 @@ static void prox_sweep_launches(const ld_net* net, const ld_batch* bt, ld_state*
     a.inv_eta = (float)inv_eta;
     a.inv_eta_d = inv_eta;
     a.tau = tau;
+    a.dual = dual && k >= 1 ? 1 : 0;
+    a.mu = (float)mu;
+    a.inv_eta_next = (float)(1.0 / eta_next);
     if (k >= 1) {
+      a.piB = P.pi[k - 1];
       a.xB = P.xB[k - 1];
       a.zB = ws.xb[k];
       a.rtB = P.rt[k - 1];
@@ -1910,9 +1909,9 @@ static void prox_sweep_launches(const ld_net* net, const ld_batch* bt, ld_state*
 }
 
 static int prox_sweep(const ld_net* net, const ld_batch* bt, ld_state* st, int mma, float tau, double eta,
-                      hipStream_t s) {
+                      bool dual, double mu, double eta_next, hipStream_t s) {
   std::vector<Launch> ls;
-  prox_sweep_launches(net, bt, st, mma, tau, eta, s, ls);
+  prox_sweep_launches(net, bt, st, mma, tau, eta, dual, mu, eta_next, s, ls);
   for (auto& l : ls) LD_TRY(l.second());
   return LD_OK;
 }
@@ -1957,12 +1956,13 @@ int ld_prox_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_p
     P.t = 0;
   }
   // coefficients of the next iteration under this call's schedule
-  LD_TRY(prox_dual(net, st, 0, 1.0, 0.0, prox_eta(o, P.t + 1), s));
+  LD_TRY(prox_coeff(net, st, prox_eta(o, P.t + 1), s));
   for (int it = 0; it < o->iters; ++it) {
     const int t = P.t + 1;
     const double eta = prox_eta(o, t);
-    for (int j = 0; j < o->inner_iters; ++j) LD_TRY(prox_sweep(net, bt, st, mma, o->tie_tau, eta, s));
-    LD_TRY(prox_dual(net, st, 1, eta, o->mu, prox_eta(o, t + 1), s));
+    // the last sweep's block kernels also take the dual update
+    for (int j = 0; j < o->inner_iters; ++j)
+      LD_TRY(prox_sweep(net, bt, st, mma, o->tie_tau, eta, j == o->inner_iters - 1, o->mu, prox_eta(o, t + 1), s));
     P.t = t;
   }
   LD_HIP(hipEventRecord(st->done, s));
@@ -1978,9 +1978,9 @@ int ld_prox_profile_iteration(const ld_net* net, const ld_batch* bt, ld_state* s
   const int mma = o->precision == LD_BF16 ? 1 : 0;
   if (st->px.mma != mma) return fail(LD_E_STATE, "the state's proximal iterates were formed in another precision");
   const double eta = prox_eta(o, st->px.t + 1);
+  // the last sweep of an outer iteration (block kernels with the dual update)
   std::vector<Launch> ls;
-  prox_sweep_launches(net, bt, st, mma, o->tie_tau, eta, s, ls);
-  ls.push_back({500, [&]() -> int { return prox_dual(net, st, 1, eta, o->mu, eta, s); }});
+  prox_sweep_launches(net, bt, st, mma, o->tie_tau, eta, true, o->mu, eta, s, ls);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   LD_HIP(hipEventCreate(&e0));
   LD_HIP(hipEventCreate(&e1));

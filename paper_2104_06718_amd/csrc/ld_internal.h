@@ -214,6 +214,11 @@ struct ProxBlockArgs {
   int nB, nA, last, z_bf16;
   float inv_eta, tau;
   double inv_eta_d;
+  // last sweep of an outer iteration: layer k's dual update with momentum
+  // (piB in/out, rhoB written) and rt_k for the next iteration's eta
+  int dual;
+  float mu, inv_eta_next;
+  float* piB;
   // layer k: iterate xB_k (in/out), conditional gradient zB_k, coefficient rt_k
   // (in/out), dual rho_k, iterate xA_k (already moved by the previous block)
   float* xB;
@@ -237,19 +242,18 @@ struct ProxBlockArgs {
   float* zB_out;
   void* z_out;
 };
+// the hidden layers of one launch computing rt = rho + (xB - xA) / eta
 constexpr int kProxPackMax = 16;
 struct ProxDualPack {
   int n;
-  float* rho[kProxPackMax];
-  float* pi[kProxPackMax];
+  const float* rho[kProxPackMax];
   const float* xB[kProxPackMax];
   const float* xA[kProxPackMax];
   float* rt[kProxPackMax];
   size_t cnt[kProxPackMax];
 };
 hipError_t launch_prox_block(const ProxBlockArgs& a, int B, hipStream_t s);
-hipError_t launch_prox_dual(const ProxDualPack& p, int update, float inv_eta, float mu, float inv_eta_next,
-                            hipStream_t s);
+hipError_t launch_prox_coeff(const ProxDualPack& p, float inv_eta, hipStream_t s);
 hipError_t launch_relu_operand(size_t n, const float* xb, void* out, int bf16, hipStream_t s);
 
 }  // namespace ld

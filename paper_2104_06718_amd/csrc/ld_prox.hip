@@ -14,7 +14,8 @@
 //   gamma* (eq:optimal-gamma-gauss) from two reductions, moves (xB_k, xA_{k+1})
 //   along the Frank-Wolfe segment (eq:fw-update), refreshes rt_k and rt_{k+1},
 //   and takes the conditional gradient of the next block: the inner minimisation
-//   of P_{k+1} (Sec. 3.2.2) with coefficients rt_{k+1} and g_{k+1} = W_{k+2}^T rt_{k+2}.
+//   of P_{k+1} (Sec. 3.2.2) with coefficients rt_{k+1} and g_{k+1} = W_{k+2}^T rt_{k+2};
+//   in the last sweep of an outer iteration it also takes layer k's dual step.
 // The transposed products g of a sweep only depend on the iterates left by the
 // previous sweep (a block never changes the rt that a later block's g reads), so
 // they are all formed at the start of the sweep.
@@ -108,18 +109,33 @@ __global__ __launch_bounds__(kProxThreads) void prox_block_kernel(ProxBlockArgs 
   const double gd = den > 0.0 ? fmin(fmax(num / den, 0.0), 1.0) : (num > 0.0 ? 1.0 : 0.0);
   const float g = (float)gd;
   const float ie = P.inv_eta;
-  // 2. Frank-Wolfe step on xB_k and the refreshed coefficient rt_k
+  // 2. Frank-Wolfe step on xB_k and the refreshed coefficient rt_k; in the last
+  //    sweep of an outer iteration xB_k and xA_k are final here, so layer k's dual
+  //    update (eq:momentum_updates) follows, and rt_k is formed for the next eta
   if (vB) {
     for (int i = 4 * tid; i < P.nB; i += 4 * kProxThreads) {
       const float4 x = ld4f(P.xB + ob + i), z = ld4f(P.zB + ob + i);
       const float4 r = ld4f(P.rhoB + ob + i), a = ld4f(P.xAB + ob + i);
       float xn[4], rn[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        xn[q] = f4at(x, q) + g * (f4at(z, q) - f4at(x, q));
-        rn[q] = f4at(r, q) + (xn[q] - f4at(a, q)) * ie;
-      }
+      for (int q = 0; q < 4; ++q) xn[q] = f4at(x, q) + g * (f4at(z, q) - f4at(x, q));
       st4f(P.xB + ob + i, xn[0], xn[1], xn[2], xn[3]);
+      if (P.dual) {
+        const float4 p = ld4f(P.piB + ob + i);
+        float pn[4], rh[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float d = xn[q] - f4at(a, q);
+          pn[q] = P.mu * f4at(p, q) + d * ie;
+          rh[q] = f4at(r, q) + pn[q];
+          rn[q] = rh[q] + d * P.inv_eta_next;
+        }
+        st4f(P.piB + ob + i, pn[0], pn[1], pn[2], pn[3]);
+        st4f(const_cast<float*>(P.rhoB) + ob + i, rh[0], rh[1], rh[2], rh[3]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rn[q] = f4at(r, q) + (xn[q] - f4at(a, q)) * ie;
+      }
       st4f(P.rtB + ob + i, rn[0], rn[1], rn[2], rn[3]);
     }
   } else {
@@ -127,7 +143,16 @@ __global__ __launch_bounds__(kProxThreads) void prox_block_kernel(ProxBlockArgs 
       const float x = P.xB[ob + i];
       const float xn = x + g * (P.zB[ob + i] - x);
       P.xB[ob + i] = xn;
-      P.rtB[ob + i] = P.rhoB[ob + i] + (xn - P.xAB[ob + i]) * ie;
+      const float d = xn - P.xAB[ob + i];
+      if (P.dual) {
+        const float pn = P.mu * P.piB[ob + i] + d * ie;
+        const float rh = P.rhoB[ob + i] + pn;
+        P.piB[ob + i] = pn;
+        const_cast<float*>(P.rhoB)[ob + i] = rh;
+        P.rtB[ob + i] = rh + d * P.inv_eta_next;
+      } else {
+        P.rtB[ob + i] = P.rhoB[ob + i] + d * ie;
+      }
     }
   }
   // 3. Frank-Wolfe step on xA_{k+1}; rt_{k+1}; conditional gradient of block k+1
@@ -178,49 +203,24 @@ __global__ __launch_bounds__(kProxThreads) void prox_block_kernel(ProxBlockArgs 
   }
 }
 
-// Dual update with momentum (eq:momentum_updates) and the coefficients rt of the
-// next outer iteration; update = 0 only refreshes rt.  blockIdx.y: layer.
-__global__ __launch_bounds__(256) void prox_dual_kernel(ProxDualPack P, int update, float inv_eta, float mu,
-                                                        float inv_eta_next) {
+// Coefficients rt = rho + (xB - xA) * inv_eta of every hidden layer (the start of
+// a call).  blockIdx.y: layer.
+__global__ __launch_bounds__(256) void prox_coeff_kernel(ProxDualPack P, float inv_eta) {
   const int L = blockIdx.y;
   const size_t n = P.cnt[L];
-  float* __restrict__ rho = P.rho[L];
-  float* __restrict__ pi = P.pi[L];
+  const float* __restrict__ rho = P.rho[L];
   const float* __restrict__ xB = P.xB[L];
   const float* __restrict__ xA = P.xA[L];
   float* __restrict__ rt = P.rt[L];
-  auto one = [&](float d, float& r, float& p, float& t) {
-    if (update) {
-      p = mu * p + d * inv_eta;
-      r = r + p;
-    }
-    t = r + d * inv_eta_next;
-  };
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const size_t n4 = n / 4;  // 16-byte groups (every array starts 256-byte aligned)
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-    const float4 b = ld4f(xB + 4 * i), a = ld4f(xA + 4 * i);
-    float4 r = ld4f(rho + 4 * i), p = update ? ld4f(pi + 4 * i) : make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 t;
-    one(b.x - a.x, r.x, p.x, t.x);
-    one(b.y - a.y, r.y, p.y, t.y);
-    one(b.z - a.z, r.z, p.z, t.z);
-    one(b.w - a.w, r.w, p.w, t.w);
-    if (update) {
-      *reinterpret_cast<float4*>(pi + 4 * i) = p;
-      *reinterpret_cast<float4*>(rho + 4 * i) = r;
-    }
-    *reinterpret_cast<float4*>(rt + 4 * i) = t;
+    const float4 b = ld4f(xB + 4 * i), a = ld4f(xA + 4 * i), r = ld4f(rho + 4 * i);
+    *reinterpret_cast<float4*>(rt + 4 * i) = make_float4(r.x + (b.x - a.x) * inv_eta, r.y + (b.y - a.y) * inv_eta,
+                                                         r.z + (b.z - a.z) * inv_eta, r.w + (b.w - a.w) * inv_eta);
   }
-  for (size_t i = 4 * n4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    float r = rho[i], p = update ? pi[i] : 0.f, t;
-    one(xB[i] - xA[i], r, p, t);
-    if (update) {
-      pi[i] = p;
-      rho[i] = r;
-    }
-    rt[i] = t;
-  }
+  for (size_t i = 4 * n4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    rt[i] = rho[i] + (xB[i] - xA[i]) * inv_eta;
 }
 
 // x = max(xB, 0): the ReLU output at a vertex of the hull (every vertex has
@@ -249,19 +249,17 @@ hipError_t launch_prox_block(const ProxBlockArgs& a, int B, hipStream_t s) {
   if (!a.xA || !a.zA || (a.last ? !a.c : (!a.rtA || !a.rhoA || !a.xBA || !a.g || !a.lo || !a.hi || !a.zB_out ||
                                            !a.z_out)))
     return hipErrorInvalidValue;
-  if (a.nB > 0 && (!a.xB || !a.zB || !a.rtB || !a.rhoB || !a.xAB)) return hipErrorInvalidValue;
+  if (a.nB > 0 && (!a.xB || !a.zB || !a.rtB || !a.rhoB || !a.xAB || (a.dual && !a.piB))) return hipErrorInvalidValue;
   hipLaunchKernelGGL(prox_block_kernel, dim3(B), dim3(kProxThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_prox_dual(const ProxDualPack& p, int update, float inv_eta, float mu, float inv_eta_next,
-                            hipStream_t s) {
+hipError_t launch_prox_coeff(const ProxDualPack& p, float inv_eta, hipStream_t s) {
   if (p.n <= 0) return hipSuccess;
   if (p.n > kProxPackMax) return hipErrorInvalidValue;
   size_t mx = 0;
   for (int i = 0; i < p.n; ++i) mx = p.cnt[i] > mx ? p.cnt[i] : mx;
-  hipLaunchKernelGGL(prox_dual_kernel, dim3(grid_1d(mx / 4 + 1), p.n), dim3(256), 0, s, p, update, inv_eta, mu,
-                     inv_eta_next);
+  hipLaunchKernelGGL(prox_coeff_kernel, dim3(grid_1d(mx / 4 + 1), p.n), dim3(256), 0, s, p, inv_eta);
   return hipGetLastError();
 }
 
