@@ -24,7 +24,9 @@ Network Verification via Lagrangian Decomposition":
 * the proximal solver (Sec. 3.3, Algorithm 2): the method of multipliers on q, its
   augmented Lagrangian (eq:z_updates) minimised approximately by J sweeps of
   block-coordinate Frank-Wolfe with the closed-form step (eq:optimal-gamma-gauss),
-  and momentum on the dual update (App. F, eq:momentum_updates).
+  and momentum on the dual update (App. F, eq:momentum_updates);
+* intermediate bounds (Sec. 2.2.3): the same LD step on the sub-network ending at
+  layer j with the objectives +x_j[i] and -x_j[i], batched over neurons (Sec. 5.2).
 
 Readings where the paper is silent (all listed in the design doc):
 * Adam uses beta1=0.9, beta2=0.999, eps=1e-8 with bias correction, as ascent.
@@ -40,7 +42,9 @@ Parity pins: every function here is checked in tests/test_oracle_pins.py against
 closed forms, brute force and the paper's identities (Prop. 1, Prop. 2, weak
 duality, Danskin's supergradient), and the proximal solver in
 tests/test_oracle_prox_pins.py (exact line search, conditional gradient by
-autograd and vertex enumeration, convergence to the Planet LP optimum).  The final
+autograd and vertex enumeration, convergence to the Planet LP optimum), and the
+intermediate bounds in tests/test_oracle_interm_pins.py (sampled pre-activations,
+per-neuron Planet LP optimum).  The final
 bound after T Adam steps has no value printed in the paper: "parity unpinned"
 beyond those inequalities.
 """
@@ -499,3 +503,33 @@ def proximal(net: List[OLayer], batch: OBatch, opts: ProxOpts, rho0: Optional[Li
             traj.append(dual_eval(net, batch, state["rho"], opts.tau, need_supergrad=False)["q"])
     state["traj"] = traj
     return state
+
+
+# ----------------------------------------------------------------------------
+# intermediate bounds (Sec. 2.2.3): LD on the sub-network that ends at layer j
+# ----------------------------------------------------------------------------
+def neuron_batch(batch: OBatch, j: int, n_j: int) -> OBatch:
+    """The 2 B n_j problems bounding the pre-activations of layer j: problem
+    (b, i, s) is subdomain b with the bounds of layers 1..j-1 and the objective
+    c = e_i (s = 0, lower bound) or c = -e_i (s = 1, minus the upper bound),
+    ordered b-major, then i, then s."""
+    B = batch.l0.shape[0]
+    P = 2 * n_j
+    idx = torch.arange(B).repeat_interleave(P)
+    r = torch.arange(P).repeat(B)
+    c = torch.zeros(B * P, n_j, dtype=DT)
+    c[torch.arange(B * P), r // 2] = 1.0 - 2.0 * (r % 2).to(DT)
+    return OBatch(batch.l0[idx], batch.u0[idx], [x[idx] for x in batch.l[:j - 1]],
+                  [x[idx] for x in batch.u[:j - 1]], c)
+
+
+def intermediate_bounds(net: List[OLayer], batch: OBatch, j: int, opts: AdamOpts):
+    """Lower and upper bounds [B, n_j] on the pre-activations of hidden layer j
+    (j >= 2): the bound of the LD step on the network's first j layers with the
+    objectives +x_j[i] and -x_j[i] (the returned bound of each, Sec. 3.1)."""
+    sub = net[:j]
+    n_j = sub[-1].n_out()
+    eb = neuron_batch(batch, j, n_j)
+    st = ascent(sub, eb, opts)
+    b = final_bound(sub, eb, st)["bound"].reshape(-1, n_j, 2)
+    return b[:, :, 0], -b[:, :, 1]
