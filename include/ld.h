@@ -86,8 +86,9 @@ typedef struct ld_layer {
 
 typedef struct ld_net ld_net;
 
-/* Validate the layer list (n_layers >= 2, the last layer LD_LINEAR, shapes
- * chained, output-size formula for convs), copy the weights to the device and
+/* Validate the layer list (n_layers >= 2, shapes chained, output-size formula
+ * for convs; the last layer, whose output the objective c weighs, may be a conv,
+ * as in the sub-network of an intermediate bound), copy the weights to the device and
  * repack them into the tile-major FP32 and BF16 operand layouts the kernels
  * use.  Synchronous.  *out receives a handle to free with ld_destroy_net. */
 int ld_create_net(const ld_layer* layers, int n_layers, ld_net** out);
@@ -298,6 +299,24 @@ int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, int* c
 int ld_profile_iteration(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opts* opts,
                          int reps, double* avg_us, int* kinds, int max_slots, int* n_slots,
                          hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* intermediate bounds (Sec. 2.2.3), batched over neurons (Sec. 5.2)          */
+/* ------------------------------------------------------------------------- */
+/* LD bounds on the pre-activations of a layer j: `sub` is the network of the
+ * first j layers (ld_create_net on them; its last layer, layer j, may be a conv).
+ * For every subdomain b of `batch` and neuron i of layer j, the LD step of
+ * `opts` (ld_step: init CROWN or ZERO, iters, schedule, precision, engine) runs
+ * on the objectives +x_j[i] and -x_j[i]; lo[b, i] receives the lower bound and
+ * hi[b, i] the upper bound (the best of q(rho^0) and q(rho^T), Sec. 3.1),
+ * rounded outward to FP32.  batch->l0/u0 and l[k]/u[k] (the bounds of the
+ * sub-network's hidden layers 1..j-1) are read; batch->c is not.  The
+ * 2 B n_j problems run in chunks of at most max_problems (<= 0: 8192) on a
+ * state the call creates; lo and hi are device arrays [B, n_j].  Synchronous
+ * (the call allocates its chunk buffers and waits for them).  Errors as ld_step;
+ * LD_E_ARG for init = LD_INIT_GIVEN. */
+int ld_intermediate_bounds(const ld_net* sub, const ld_batch* batch, const ld_opts* opts, int max_problems,
+                           float* lo, float* hi, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* proximal solver (Sec. 3.3, Algorithm 2; momentum of App. F)                */

@@ -32,7 +32,7 @@ EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num
             "ld_state_get_rho", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
-            "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
+            "ld_intermediate_bounds", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
 
 
 class LDError(RuntimeError):
@@ -114,6 +114,7 @@ def load_library(path: Optional[str] = None):
     lib.ld_tile_candidates.argtypes = [V, I, I, I, P(ld_tile), I, P(I)]
     lib.ld_set_tuned_config.argtypes = [V, I, I, I, I, P(ld_tile)]
     lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
+    lib.ld_intermediate_bounds.argtypes = [V, P(ld_batch), P(ld_opts), I, V, V, V]
     lib.ld_prox_step.argtypes = [V, P(ld_batch), V, P(ld_prox_opts), V]
     lib.ld_prox_get_step.argtypes = [V, P(I)]
     lib.ld_prox_profile_iteration.argtypes = [V, P(ld_batch), V, P(ld_prox_opts), I, P(ctypes.c_double), P(I), I,
@@ -291,6 +292,22 @@ def step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional
          tau: float = TAU_DEFAULT, engine="auto", stream=None):
     o = _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine)
     _check(net.lib.ld_step(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o), _stream(stream)))
+
+
+def intermediate_bounds(sub: Net, batch: Batch, iters: int, total_iters: Optional[int] = None, lr0=1e-2,
+                        lr_end=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, precision="fp32", init="crown",
+                        tau: float = TAU_DEFAULT, engine="auto", max_problems=0, stream=None):
+    """LD bounds (lo, hi), each [B, n_j] float32, on the pre-activations of the last
+    layer of `sub` (the network of the first j layers) for every subdomain of
+    `batch` (ld_intermediate_bounds; batch.c is not read)."""
+    nj = sub.widths[-1]
+    lo = torch.empty((batch.B, nj), device="cuda", dtype=torch.float32)
+    hi = torch.empty_like(lo)
+    o = _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine)
+    _check(sub.lib.ld_intermediate_bounds(sub.handle, ctypes.byref(batch.struct), ctypes.byref(o), int(max_problems),
+                                          ctypes.c_void_p(lo.data_ptr()), ctypes.c_void_p(hi.data_ptr()),
+                                          _stream(stream)))
+    return lo, hi
 
 
 def prox_step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional[int] = None,

@@ -752,7 +752,8 @@ int prepare_objective(const ld_net* net, const ld_batch* bt, Workspace& ws, int 
   e.scale = -1.f;
   e.out_f = ws.gconst;
   LD_HIP(run_job(Ln.tr, bt->B, bt->c, 0, 0, e, pick_tile(net, n - 1, 1, bt->B, mma), ws, n - 1, s));
-  LD_HIP(launch_cdot(bt->B, Ln.n_out, bt->c, nullptr, Ln.bias, ws.cb, s));
+  LD_HIP(launch_cdot(bt->B, Ln.n_out, bt->c, nullptr, Ln.bias, Ln.kind == LD_CONV2D ? Ln.out_h * Ln.out_w : 1,
+                     ws.cb, s));
   return LD_OK;
 }
 
@@ -1017,6 +1018,7 @@ ResidentShape resident_shape(const ld_net* net, int B, int mma) {
   ResidentShape R;
   const int n = net->n;
   if (n - 1 > kMaxLayers) return R;
+  if (net->L[n - 1].kind != LD_LINEAR) return R;  // the engine's objective layer is fully connected
   int xb_even = 0, xb_odd = 0, img = 0, gx = 0, wb = 0;
   for (int k = 1; k <= n - 1; ++k) {
     const Layer& L = net->L[k - 1];
@@ -1168,7 +1170,6 @@ static int check_layers(const ld_layer* layers, int n_layers) {
       return fail(LD_E_ARG, "unknown layer kind" + at);
     }
     if (n_in > (1L << 28) || n_out > (1L << 28)) return fail(LD_E_UNSUPPORTED, "layer too wide" + at);
-    if (i == n_layers - 1 && s.kind != LD_LINEAR) return fail(LD_E_SHAPE, "the last layer must be LD_LINEAR");
     if (i > 0 && n_in != prev_out) return fail(LD_E_SHAPE, "input size differs from previous output" + at);
     for (int j = 0; j < s.out_c; ++j)
       if (!std::isfinite(s.b[j])) return fail(LD_E_NUMERIC, "non-finite bias" + at);
@@ -2019,6 +2020,95 @@ int ld_prox_get_step(const ld_state* st, int* t) {
   return LD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// intermediate bounds (Sec. 2.2.3; batched over the neurons of a layer, Sec. 5.2)
+// ---------------------------------------------------------------------------
+int ld_intermediate_bounds(const ld_net* sub, const ld_batch* bt, const ld_opts* o, int max_problems, float* lo,
+                           float* hi, hipStream_t s) {
+  g_err.clear();
+  if (!sub || !bt || !o || !lo || !hi) return fail(LD_E_ARG, "NULL argument");
+  const int n = sub->n, B = bt->B;
+  if (B < 0) return fail(LD_E_ARG, "batch size B < 0");
+  if (B == 0) return LD_OK;
+  if (!bt->l0 || !bt->u0 || !bt->l || !bt->u) return fail(LD_E_ARG, "batch l0/u0/l/u is NULL");
+  for (int k = 1; k <= n - 1; ++k)
+    if (!bt->l[k - 1] || !bt->u[k - 1]) return fail(LD_E_ARG, "batch l[k]/u[k] is NULL for k=" + std::to_string(k));
+  if (o->init == LD_INIT_GIVEN) return fail(LD_E_ARG, "init must be LD_INIT_CROWN or LD_INIT_ZERO");
+  if (n - 1 > 32) return fail(LD_E_UNSUPPORTED, "more than 32 hidden layers");
+  const int nj = width(sub, n);
+  const long long P = 2LL * nj;
+  const long long total = (long long)B * P;
+  const long long C = std::min<long long>(max_problems > 0 ? max_problems : 8192, total);
+  // one chunk's expanded batch and its bounds
+  std::vector<int> widths = {sub->n0, sub->n0};
+  for (int k = 1; k <= n - 1; ++k) {
+    widths.push_back(width(sub, k));
+    widths.push_back(width(sub, k));
+  }
+  std::vector<size_t> off;
+  size_t total_bytes = 0;
+  for (int w : widths) {
+    off.push_back(total_bytes);
+    total_bytes += round_up((size_t)C * w * 4, 256);
+  }
+  const size_t off_c = total_bytes;
+  total_bytes += round_up((size_t)C * nj * 4, 256);
+  const size_t off_b = total_bytes;
+  total_bytes += round_up((size_t)C * 8, 256);
+  void* base = nullptr;
+  if (hipMalloc(&base, total_bytes) != hipSuccess) return fail(LD_E_NOMEM, "intermediate bounds: hipMalloc failed");
+  char* cb = (char*)base;
+  IntermPack K;
+  std::memset(&K, 0, sizeof(K));
+  K.n = (int)widths.size();
+  std::vector<const float*> srcs = {bt->l0, bt->u0};
+  for (int k = 1; k <= n - 1; ++k) {
+    srcs.push_back(bt->l[k - 1]);
+    srcs.push_back(bt->u[k - 1]);
+  }
+  for (int a = 0; a < K.n; ++a) {
+    K.src[a] = srcs[a];
+    K.dst[a] = (float*)(cb + off[a]);
+    K.width[a] = widths[a];
+  }
+  K.c = (float*)(cb + off_c);
+  double* bound = (double*)(cb + off_b);
+  std::vector<const float*> dl, du;
+  for (int k = 1; k <= n - 1; ++k) {
+    dl.push_back(K.dst[2 * k]);
+    du.push_back(K.dst[2 * k + 1]);
+  }
+  ld_state* states[2] = {nullptr, nullptr};  // full chunks, the tail chunk
+  int rc = LD_OK;
+  for (long long start = 0; start < total && rc == LD_OK; start += C) {
+    const int cc = (int)std::min<long long>(C, total - start);
+    hipError_t e = launch_interm_expand(K, cc, start, (int)P, nj, s);
+    if (e != hipSuccess) {
+      rc = fail(LD_E_DEVICE, std::string("interm_expand: ") + hipGetErrorString(e));
+      break;
+    }
+    ld_batch cbt;
+    cbt.B = cc;
+    cbt.l0 = K.dst[0];
+    cbt.u0 = K.dst[1];
+    cbt.l = dl.data();
+    cbt.u = du.data();
+    cbt.c = K.c;
+    ld_state*& st = states[cc == C ? 0 : 1];
+    if (!st && (rc = ld_state_create(sub, cc, &st)) != LD_OK) break;
+    if ((rc = ld_state_reset(st, s)) != LD_OK) break;
+    if ((rc = ld_step(sub, &cbt, st, o, s)) != LD_OK) break;
+    if ((rc = ld_final_bound(sub, &cbt, st, bound, nullptr, nullptr, nullptr, o->tie_tau, s)) != LD_OK) break;
+    e = launch_interm_collect(cc, start, (int)P, nj, bound, lo, hi, s);
+    if (e != hipSuccess) rc = fail(LD_E_DEVICE, std::string("interm_collect: ") + hipGetErrorString(e));
+  }
+  const hipError_t es = hipStreamSynchronize(s);
+  for (ld_state* st : states) ld_state_destroy(st);
+  (void)hipFree(base);
+  if (rc == LD_OK && es != hipSuccess) rc = fail(LD_E_DEVICE, std::string("intermediate bounds: ") + hipGetErrorString(es));
+  return rc;
+}
+
 int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
   g_err.clear();
   LD_TRY(check_step_args(net, bt, st, o));
@@ -2210,7 +2300,7 @@ int ld_final_bound(const ld_net* net, const ld_batch* bt, const ld_state* cst, d
       LD_HIP(run_job(L.fwd, B, x, 0, 0, e, pick_tile(net, k - 1, 0, B, 0), ws, k - 1, s));
       x = bufs[k & 1];
     }
-    if (primal) LD_HIP(launch_cdot(B, net->L[n - 1].n_out, bt->c, x, nullptr, primal, s));
+    if (primal) LD_HIP(launch_cdot(B, net->L[n - 1].n_out, bt->c, x, nullptr, 1, primal, s));
   }
   LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;

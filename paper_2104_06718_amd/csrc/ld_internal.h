@@ -198,7 +198,7 @@ hipError_t launch_crown_const(int B, int n, const float* g, const float* lo, con
                               float* rho, hipStream_t s);
 hipError_t launch_reduce_q(int B, int n_arrays, const double* const* arrays, const int* sizes,
                            const double* cb, double* q, hipStream_t s);
-hipError_t launch_cdot(int B, int n, const float* c, const float* y, const float* bias, double* out,
+hipError_t launch_cdot(int B, int n, const float* c, const float* y, const float* bias, int bias_div, double* out,
                        hipStream_t s);
 hipError_t launch_validate(int B, int n, const float* lo, const float* hi, int* bad, hipStream_t s);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
@@ -255,5 +255,19 @@ struct ProxDualPack {
 hipError_t launch_prox_block(const ProxBlockArgs& a, int B, hipStream_t s);
 hipError_t launch_prox_coeff(const ProxDualPack& p, float inv_eta, hipStream_t s);
 hipError_t launch_relu_operand(size_t n, const float* xb, void* out, int bf16, hipStream_t s);
+
+// intermediate bounds (ld_interm.hip): the per-subdomain arrays copied into the
+// expanded batch (l_0, u_0, then l_k, u_k of the sub-network's hidden layers)
+constexpr int kIntermMaxArrays = 66;
+struct IntermPack {
+  int n;
+  const float* src[kIntermMaxArrays];
+  float* dst[kIntermMaxArrays];
+  int width[kIntermMaxArrays];
+  float* c;
+};
+hipError_t launch_interm_expand(const IntermPack& K, int C, long long start, int P, int nj, hipStream_t s);
+hipError_t launch_interm_collect(int C, long long start, int P, int nj, const double* bound, float* lo, float* hi,
+                                 hipStream_t s);
 
 }  // namespace ld

@@ -1132,13 +1132,15 @@ __global__ void reduce_q_kernel(ReducePack P, const double* __restrict__ cb, dou
   if (threadIdx.x == 0) q[b] = (cb ? cb[b] : 0.0) + sh[0];
 }
 
-// out[b] = sum_j c[b, j] * (y ? y[b, j] : bias[j])  (FP64)
+// out[b] = sum_j c[b, j] * (y ? y[b, j] : bias[j / bias_div])  (FP64; a conv layer's
+// bias is per channel, bias_div = H*W)
 __global__ void cdot_kernel(int n, const float* __restrict__ c, const float* __restrict__ y,
-                            const float* __restrict__ bias, double* __restrict__ out) {
+                            const float* __restrict__ bias, int bias_div, double* __restrict__ out) {
   __shared__ double sh[64];
   const int b = blockIdx.x;
   double s = 0.0;
-  for (int j = threadIdx.x; j < n; j += 64) s += (double)c[(size_t)b * n + j] * (double)(y ? y[(size_t)b * n + j] : bias[j]);
+  for (int j = threadIdx.x; j < n; j += 64)
+    s += (double)c[(size_t)b * n + j] * (double)(y ? y[(size_t)b * n + j] : bias[j / bias_div]);
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = 32; w > 0; w >>= 1) {
@@ -1206,8 +1208,10 @@ hipError_t launch_reduce_q(int B, int n_arrays, const double* const* arrays, con
   return hipGetLastError();
 }
 
-hipError_t launch_cdot(int B, int n, const float* c, const float* y, const float* bias, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(cdot_kernel, dim3(B), dim3(64), 0, s, n, c, y, bias, out);
+hipError_t launch_cdot(int B, int n, const float* c, const float* y, const float* bias, int bias_div, double* out,
+                       hipStream_t s) {
+  if (bias_div < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cdot_kernel, dim3(B), dim3(64), 0, s, n, c, y, bias, bias_div, out);
   return hipGetLastError();
 }
 

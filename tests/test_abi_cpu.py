@@ -70,9 +70,9 @@ def test_create_net_rejects_bad_shapes(lib):
     rc, msg = _create(lib, [_layer(1, (3, 8, 8), (4, 5, 5), k=4, s=2, p=1, W=W, b=b),
                             _layer(0, (100, 1, 1), (2, 1, 1), W=W, b=b)])
     assert rc == -2 and "conv output size" in msg
-    # last layer must be linear
+    # a conv objective layer (an intermediate bound's sub-network) whose input is not the previous map
     rc, _ = _create(lib, [_layer(1, (3, 8, 8), (4, 4, 4), k=4, s=2, p=1, W=W, b=b),
-                          _layer(1, (4, 4, 4), (2, 2, 2), k=4, s=2, p=1, W=W, b=b)])
+                          _layer(1, (5, 4, 4), (2, 2, 2), k=4, s=2, p=1, W=W, b=b)])
     assert rc == -2
     # NULL weights
     rc, _ = _create(lib, [_layer(0, (4, 1, 1), (3, 1, 1), W=None, b=b), _layer(0, (3, 1, 1), (2, 1, 1), W=W, b=b)])

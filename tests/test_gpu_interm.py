@@ -1,0 +1,96 @@
+"""Intermediate bounds (Sec. 2.2.3, batched over neurons as in Sec. 5.2) on the GPU
+against the FP64 oracle.
+
+Every test prints the case it is about to run before touching the GPU.  Inputs
+come from the seeded generator only.
+"""
+import pytest
+import torch
+
+import ldgen
+from oracle import ld_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+# the same FP32 spread as the final bound of the supergradient path
+FP32_FINAL_REL = 3e-3
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _sub(name, j, B=None, **kw):
+    import paper_2104_06718_amd as P
+    inst = ldgen.make_instance(name, B=B, **kw) if B else ldgen.make_instance(name, **kw)
+    sub = P.Net(inst.layers[:j])
+    n_j = inst.layers[j - 1].n_out
+    t = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    batch = P.Batch(t(inst.l0), t(inst.u0), [t(a) for a in inst.l[:j - 1]], [t(a) for a in inst.u[:j - 1]],
+                    torch.zeros(inst.B, n_j, device="cuda"))
+    return P, inst, sub, batch
+
+
+def _oracle(inst, j, T):
+    onet = O.net_from_specs(inst.layers)
+    ob = O.batch_from_instance(inst)
+    return O.intermediate_bounds(onet, ob, j, O.AdamOpts(T=T))
+
+
+@pytest.mark.parametrize("name,j,B,T", [("fc_tiny", 2, None, 200), ("tiny_conv", 2, None, 100),
+                                        ("tiny_conv", 3, None, 100), ("tiny_conv3", 2, None, 100),
+                                        ("tiny_conv4", 2, None, 100), ("base", 2, 2, 40)])
+def test_parity_fp32(name, j, B, T):
+    _case(f"intermediate bounds fp32 {name} j={j} B={B} T={T}")
+    P, inst, sub, batch = _sub(name, j, B)
+    lo, hi = P.intermediate_bounds(sub, batch, iters=T, total_iters=T, precision="fp32", engine="layerwise")
+    torch.cuda.synchronize()
+    olo, ohi = _oracle(inst, j, T)
+    for got, want, side in ((lo, olo, "lower"), (hi, ohi, "upper")):
+        d = (got.cpu().double() - want).abs()
+        print(f"  {side}: |gpu - oracle| mean {d.mean().item():.2e} max {d.max().item():.2e} over {d.numel()}")
+        assert bool((d <= FP32_FINAL_REL * want.abs() + 1e-3).all())
+    assert bool((lo <= hi).all())
+
+
+@pytest.mark.parametrize("name,j", [("tiny_conv", 2), ("tiny_conv3", 2), ("tiny_conv", 3)])
+def test_contain_sampled_preactivations(name, j):
+    """Root subdomains (no splits): the true pre-activations of sampled inputs lie
+    inside the bounds (weak duality)."""
+    _case(f"intermediate bounds soundness {name} j={j}")
+    P, inst, sub, batch = _sub(name, j, split_frac=0.0)
+    for prec in ("fp32", "bf16"):
+        lo, hi = P.intermediate_bounds(sub, batch, iters=100, precision=prec)
+        torch.cuda.synchronize()
+        onet = O.net_from_specs(inst.layers)
+        g = torch.Generator().manual_seed(3)
+        for b in range(inst.B):
+            l0 = torch.from_numpy(inst.l0[b]).double()
+            u0 = torch.from_numpy(inst.u0[b]).double()
+            X = l0 + (u0 - l0) * torch.rand(3000, l0.numel(), generator=g, dtype=torch.float64)
+            x = X
+            for k in range(j - 1):
+                x = torch.clamp(onet[k].forward(x), min=0.0)
+            Y = onet[j - 1].forward(x)
+            assert bool((Y >= lo[b].cpu().double() - 1e-6).all()), prec
+            assert bool((Y <= hi[b].cpu().double() + 1e-6).all()), prec
+
+
+def test_chunks_agree_with_one_call():
+    _case("intermediate bounds chunked tiny_conv2 j=3")
+    P, inst, sub, batch = _sub("tiny_conv2", 3)
+    a = P.intermediate_bounds(sub, batch, iters=60, engine="layerwise")
+    b = P.intermediate_bounds(sub, batch, iters=60, engine="layerwise", max_problems=37)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        d = (x - y).abs()
+        print(f"  |one call - chunks of 37| max {d.max().item():.2e}")
+        assert bool((d <= FP32_FINAL_REL * x.abs() + 1e-3).all())
+
+
+def test_given_init_is_rejected():
+    _case("intermediate bounds bad init")
+    P, inst, sub, batch = _sub("tiny_conv", 2)
+    from paper_2104_06718_amd.binding import LDError
+    with pytest.raises(LDError):
+        P.intermediate_bounds(sub, batch, iters=5, init="given")
