@@ -21,6 +21,7 @@ import json
 import os
 import sys
 import time
+import types
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -47,8 +48,10 @@ def parse():
                          "iterations launched without the graph; prints the per-launch averages")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--engine", choices=["auto", "layerwise", "resident"], default="auto")
-    ap.add_argument("--solver", choices=["ld", "prox"], default="ld",
-                    help="ld: Adam supergradient ascent (the headline line); prox: the proximal solver")
+    ap.add_argument("--solver", choices=["ld", "prox", "interm"], default="ld",
+                    help="ld: Adam supergradient ascent (the headline line); prox: the proximal solver; "
+                         "interm: LD intermediate bounds of one layer")
+    ap.add_argument("--layer", type=int, default=2, help="interm: layer j whose pre-activations are bounded")
     return ap.parse_args()
 
 
@@ -298,6 +301,115 @@ def main_prox(a, P, inst, net, batch):
     print(json.dumps(out), flush=True)
 
 
+def main_interm(a, P, inst):
+    """LD intermediate bounds (Sec. 2.2.3) of layer j for a few subdomains: every
+    (subdomain, neuron, sign) is one LD problem on the sub-network of the first j
+    layers (CROWN init, T Adam steps, final bound), run in chunks of 8192."""
+    import torch
+    j = a.layer
+    Bs = a.B or 4
+    T = a.iters or 100
+    layers = inst.layers
+    nj = layers[j - 1].n_out
+    sub = P.Net(layers[:j])
+    t = lambda x: torch.from_numpy(x[:Bs]).cuda()  # noqa: E731
+    batch = P.Batch(t(inst.l0), t(inst.u0), [t(x) for x in inst.l[:j - 1]], [t(x) for x in inst.u[:j - 1]],
+                    torch.zeros(Bs, nj, device="cuda"))
+    nprob = 2 * nj * Bs
+    chunk = 8192
+    res = {}
+    for prec in ("fp32", "bf16"):
+        for _ in range(a.warmup):  # includes the autotuner's run for the chunk sizes
+            P.intermediate_bounds(sub, batch, iters=T, precision=prec, max_problems=chunk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            lo, hi = P.intermediate_bounds(sub, batch, iters=T, precision=prec, max_problems=chunk)
+        torch.cuda.synchronize()
+        ms = 1000 * (time.perf_counter() - t0) / a.steps
+        res[prec] = dict(ms=ms, lo=lo, hi=hi)
+    # per-launch timing of one iteration on a chunk of the expanded batch (problems of
+    # subdomain 0 first, as the library orders them)
+    C = min(chunk, nprob)
+    g = torch.arange(C, device="cuda")
+    b = g // (2 * nj)
+    r = g % (2 * nj)
+    c = torch.zeros(C, nj, device="cuda")
+    c[g, r // 2] = 1.0 - 2.0 * (r % 2).float()
+    eb = P.Batch(batch.l0[b], batch.u0[b], [x[b] for x in batch.l], [x[b] for x in batch.u], c)
+    prof = {}
+    for prec in ("fp32", "bf16"):
+        stp = P.State(sub, C)
+        P.step(sub, eb, stp, iters=2, total_iters=T, precision=prec)
+        prof[prec] = P.profile_iteration(sub, eb, stp, reps=a.reps, total_iters=T, precision=prec)
+    torch.cuda.synchronize()
+    head = "fp32"
+    info = P.tuning_info(sub, C, head)
+    fake = types.SimpleNamespace(layers=layers[:j])
+    kind, us = max(prof[head], key=lambda x: x[1])
+    nbytes, flops = layer_slot_cost(fake, kind, C, head)
+    ridge = PEAK_TFLOPS[head] * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if flops / max(nbytes, 1) < ridge:
+        roof = dict(bound="hbm", achieved=nbytes / (us * 1e-6) / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
+    else:
+        roof = dict(bound="mfma", achieved=flops / (us * 1e-6) / 1e12, peak=PEAK_TFLOPS[head], unit="TFLOP/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    kname = kernel_name(info, kind, fake, head)
+    roof["traffic"] = stored_traffic(kname, kind, f"{a.config}/interm{j}", C, head)
+    roof["kernel"] = f"{kname}: slot {kind} (phase {kind // 100}, layer {kind % 100}) at {C} problems"
+    roof["avg_us"] = us
+    roof["algorithmic_bytes"] = nbytes
+    roof["algorithmic_flops"] = flops
+    ibp_w = (torch.from_numpy(inst.u[j - 1][:Bs]) - torch.from_numpy(inst.l[j - 1][:Bs])).double()
+    out = {
+        "metric": f"LD intermediate bounds/sec (layer {j} of the {a.config} conv net, {T} iters, "
+                  f"{nprob} problems)",
+        "value": nprob / (res[head]["ms"] / 1000.0),
+        "unit": "bounds/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": res[head]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.config} conv net 3x32x32, pre-activation bounds of layer {j} ({nj} neurons) "
+                               f"for {Bs} subdomains: {nprob} LD problems (+-e_i), T={T}, chunks of {chunk}",
+                   "subdomains": Bs, "layer": j, "problems": nprob, "iters": T},
+        "bf16": {"value": nprob / (res["bf16"]["ms"] / 1000.0), "ms_per_step": res["bf16"]["ms"]},
+        "mean_width": {p: (res[p]["hi"] - res[p]["lo"]).double().mean().item() for p in res},
+        "ibp_mean_width": ibp_w.mean().item(),
+        "roofline": roof,
+        "per_launch_us": {p: {str(k): round(v, 2) for k, v in prof[p]} for p in prof},
+    }
+    if not a.no_cpu_baseline:
+        # the oracle on the first neurons of subdomain 0 (both signs)
+        from oracle import ld_oracle as O
+        nn = min(nj, 1024)
+        onet = O.net_from_specs(layers)
+        ob = O.batch_from_instance(inst, [0])
+        ob = O.OBatch(ob.l0, ob.u0, ob.l, ob.u, ob.c)
+        sub_o = onet[:j]
+        eb_o = O.neuron_batch(ob, j, nj)
+        keep = torch.arange(2 * nn)
+        eb_o = O.OBatch(eb_o.l0[keep], eb_o.u0[keep], [x[keep] for x in eb_o.l], [x[keep] for x in eb_o.u],
+                        eb_o.c[keep])
+        t0 = time.perf_counter()
+        st = O.ascent(sub_o, eb_o, O.AdamOpts(T=T))
+        fbo = O.final_bound(sub_o, eb_o, st)["bound"].reshape(nn, 2)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=2 * nn / dt, unit="bounds/s", cores=torch.get_num_threads(), kind="oracle",
+                                   sample=f"{2 * nn} of {nprob} problems (neurons 0..{nn - 1} of subdomain 0, both "
+                                          f"signs), {T} iterations each, FP64 torch-CPU oracle, {dt:.1f} s")
+        d_lo = res[head]["lo"][0, :nn].cpu().double() - fbo[:, 0]
+        d_hi = res[head]["hi"][0, :nn].cpu().double() + fbo[:, 1]
+        out["minus_oracle"] = {"lower_max_abs": d_lo.abs().max().item(), "upper_max_abs": d_hi.abs().max().item(),
+                               "problems": 2 * nn}
+    print(json.dumps(out), flush=True)
+
+
 def src_hash():
     """Hash of the HIP sources (a stored counter measurement is valid for this build only)."""
     h = hashlib.sha256()
@@ -344,6 +456,9 @@ def main():
 
     if a.solver == "prox" and not a.profile_only:
         main_prox(a, P, inst, net, batch)
+        return
+    if a.solver == "interm":
+        main_interm(a, P, inst)
         return
 
     if a.profile_only:
