@@ -26,7 +26,10 @@ Network Verification via Lagrangian Decomposition":
   block-coordinate Frank-Wolfe with the closed-form step (eq:optimal-gamma-gauss),
   and momentum on the dual update (App. F, eq:momentum_updates);
 * intermediate bounds (Sec. 2.2.3): the same LD step on the sub-network ending at
-  layer j with the objectives +x_j[i] and -x_j[i], batched over neurons (Sec. 5.2).
+  layer j with the objectives +x_j[i] and -x_j[i], batched over neurons (Sec. 5.2);
+* Filtered Smart Branching (Sec. 4.2): the scores of eq:fsb-scores and
+  eq:babsr-scores from one backward pass, the candidates of eq:fsb-prefilter and the
+  split whose worse child has the best CROWN-or-WK bound.
 
 Readings where the paper is silent (all listed in the design doc):
 * Adam uses beta1=0.9, beta2=0.999, eps=1e-8 with bias correction, as ascent.
@@ -44,7 +47,9 @@ duality, Danskin's supergradient), and the proximal solver in
 tests/test_oracle_prox_pins.py (exact line search, conditional gradient by
 autograd and vertex enumeration, convergence to the Planet LP optimum), and the
 intermediate bounds in tests/test_oracle_interm_pins.py (sampled pre-activations,
-per-neuron Planet LP optimum).  The final
+per-neuron Planet LP optimum), and branching in tests/test_oracle_fsb_pins.py (bias
+sensitivity of an independent WK bound, chord gap, brute-force candidate search; the
+s_FSB formula itself is "parity unpinned" beyond its support and sign).  The final
 bound after T Adam steps has no value printed in the paper: "parity unpinned"
 beyond those inequalities.
 """
@@ -533,3 +538,105 @@ def intermediate_bounds(net: List[OLayer], batch: OBatch, j: int, opts: AdamOpts
     st = ascent(sub, eb, opts)
     b = final_bound(sub, eb, st)["bound"].reshape(-1, n_j, 2)
     return b[:, :, 0], -b[:, :, 1]
+
+
+# ----------------------------------------------------------------------------
+# Filtered Smart Branching (Sec. 4.2, eq:fsb-scores, eq:fsb-prefilter)
+# ----------------------------------------------------------------------------
+def wk_slopes(l: torch.Tensor, u: torch.Tensor):
+    """Slopes of the WK relaxation: the chord [u]_+ / ([u]_+ - [l]_-) as both the upper
+    and the (parallel) lower slope: 1 passing, 0 blocking (Sec. 4.1)."""
+    st = relu_status(l, u)
+    den = torch.where(st == 2, u - l, torch.ones_like(u))
+    a = torch.where(st == 2, u / den, torch.where(st == 0, torch.ones_like(u), torch.zeros_like(u)))
+    return a, a
+
+
+def fsb_lambdas(net: List[OLayer], batch: OBatch) -> List[torch.Tensor]:
+    """The backward pass of eq:babsr-scores: lambda_{n-1} = -W_n^T c (the objective
+    folded as rho_n = -c) and lambda_{k-1} = W_k^T (a_k lambda_k) with the chord slope
+    a_k, i.e. the coefficients g_k of the WK dual assignment; k = 1..n-1."""
+    rho = propagation_duals(net, batch, [wk_slopes(l, u) for l, u in zip(batch.l, batch.u)])
+    duals = list(rho) + [-batch.c]
+    return [net[k].transposed(duals[k]) for k in range(1, len(net))]
+
+
+def fsb_scores(net: List[OLayer], batch: OBatch):
+    """s_FSB,k and t_SR,k for every hidden layer (eq:fsb-scores, eq:babsr-scores);
+    non-ambiguous neurons score 0."""
+    n = len(net)
+    lams = fsb_lambdas(net, batch)
+    s_out, t_out = [], []
+    for k in range(1, n):
+        lam = lams[k - 1]
+        l, u = batch.l[k - 1], batch.u[k - 1]
+        amb = relu_status(l, u) == 2
+        den = torch.where(amb, u - l, torch.ones_like(u))
+        bias = net[k - 1].bias_full().expand_as(lam)
+        lb = lam * bias
+        s = (torch.minimum(torch.zeros_like(lb), lb) - (u / den) * lb + (u * l / den) * torch.clamp(lam, min=0)).abs()
+        t = (-u * l / den) * torch.clamp(lam, min=0)
+        s_out.append(torch.where(amb, s, torch.zeros_like(s)))
+        t_out.append(torch.where(amb, t, torch.zeros_like(t)))
+    return s_out, t_out
+
+
+def fsb_candidates(batch: OBatch, s: List[torch.Tensor], t: List[torch.Tensor]):
+    """eq:fsb-prefilter: per subdomain and hidden layer k, the ambiguous neuron with the
+    largest s_FSB,k and the one with the largest t_SR,k (the first index on ties);
+    -1 where layer k has no ambiguous neuron.  Returns int64 [B, n-1, 2]."""
+    B = batch.l0.shape[0]
+    out = torch.full((B, len(s), 2), -1, dtype=torch.int64)
+    for k in range(len(s)):
+        amb = relu_status(batch.l[k], batch.u[k]) == 2
+        for col, sc in enumerate((s[k], t[k])):
+            masked = torch.where(amb, sc, torch.full_like(sc, -1.0))
+            best = masked.max(dim=1)
+            # first index attaining the maximum
+            first = (masked == best.values[:, None]).to(torch.int64).argmax(dim=1)
+            out[:, k, col] = torch.where(amb.any(dim=1), first, torch.full_like(first, -1))
+    return out
+
+
+def split_child(batch: OBatch, b: int, k: int, i: int, active: bool) -> OBatch:
+    """Subdomain b with ReLU i of hidden layer k split: active (l := 0, passing) or
+    inactive (u := 0, blocking)."""
+    l = [x[b:b + 1].clone() for x in batch.l]
+    u = [x[b:b + 1].clone() for x in batch.u]
+    if active:
+        l[k - 1][0, i] = 0.0
+    else:
+        u[k - 1][0, i] = 0.0
+    return OBatch(batch.l0[b:b + 1], batch.u0[b:b + 1], l, u, batch.c[b:b + 1])
+
+
+def propagation_bound(net: List[OLayer], batch: OBatch) -> torch.Tensor:
+    """The better of the CROWN and WK bounds: q at their dual assignments (Prop. 2)."""
+    q = []
+    for slopes in ([crown_slopes(l, u) for l, u in zip(batch.l, batch.u)],
+                   [wk_slopes(l, u) for l, u in zip(batch.l, batch.u)]):
+        q.append(dual_eval(net, batch, propagation_duals(net, batch, slopes), need_supergrad=False)["q"])
+    return torch.maximum(q[0], q[1])
+
+
+def fsb_branch(net: List[OLayer], batch: OBatch):
+    """FSB's decision per subdomain: among the candidates of eq:fsb-prefilter, the one
+    whose worse child has the largest bound (best of CROWN and WK); ties go to the
+    first candidate in (layer, s then t) order.  Returns (layer [B], index [B],
+    value [B]); layer = 0 and value = -inf when no ReLU is ambiguous."""
+    s, t = fsb_scores(net, batch)
+    cand = fsb_candidates(batch, s, t)
+    B = batch.l0.shape[0]
+    layer = torch.zeros(B, dtype=torch.int64)
+    index = torch.full((B,), -1, dtype=torch.int64)
+    value = torch.full((B,), -float("inf"), dtype=DT)
+    for b in range(B):
+        for k in range(1, len(net)):
+            for col in range(2):
+                i = int(cand[b, k - 1, col])
+                if i < 0:
+                    continue
+                v = min(propagation_bound(net, split_child(batch, b, k, i, h)).item() for h in (True, False))
+                if v > value[b]:
+                    layer[b], index[b], value[b] = k, i, v
+    return layer, index, value
