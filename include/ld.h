@@ -59,7 +59,9 @@ enum {
 
 enum { LD_LINEAR = 0, LD_CONV2D = 1 };          /* layer kinds (Sec. 2.1)          */
 enum { LD_FP32 = 0, LD_BF16 = 1 };              /* operand precision of the contractions */
-enum { LD_INIT_CROWN = 0, LD_INIT_ZERO = 1, LD_INIT_GIVEN = 2 };
+/* dual initialisation: CROWN's or WK's dual assignment (Prop. 2, Sec. 4.1),
+ * zeros, or duals set by the caller */
+enum { LD_INIT_CROWN = 0, LD_INIT_ZERO = 1, LD_INIT_GIVEN = 2, LD_INIT_WK = 3 };
 enum { LD_ENGINE_AUTO = 0, LD_ENGINE_RESIDENT = 1, LD_ENGINE_LAYERWISE = 2 };
 
 /* ------------------------------------------------------------------------- */
@@ -157,7 +159,8 @@ int ld_state_reset(ld_state* st, hipStream_t stream);
  * rho_k = a_up [g_k]_+ + a_lo [g_k]_-,  g_k = W_{k+1}^T rho_{k+1}, rho_n = -c
  * (eq:salman-assignment; slopes: chord upper slope u/(u-l), lower slope
  * 1[u >= -l] for ambiguous ReLUs, Sec. 4.2 footnote), at which q equals the
- * CROWN bound (Prop. 2).  init = LD_INIT_ZERO writes zeros.  rho: host array of
+ * CROWN bound (Prop. 2).  init = LD_INIT_WK takes the chord as both slopes (the
+ * WK bound's dual point); init = LD_INIT_ZERO writes zeros.  rho: host array of
  * n-1 device pointers [B, n_k] that receive the duals. */
 int ld_init_duals(const ld_net* net, const ld_batch* batch, int init, int precision,
                   float* const* rho, hipStream_t stream);
@@ -202,8 +205,8 @@ int ld_dual_eval(const ld_net* net, const ld_batch* batch, const float* const* r
  *             always re-evaluated with FP32 operands and an FP64 sum
  *             (ld_final_bound).
  * init        used on the first call of a state: LD_INIT_CROWN (default of
- *             the paper, Sec. 7.2), LD_INIT_ZERO, or LD_INIT_GIVEN (duals set
- *             by ld_state_set_rho).  On that call q(rho^0) is stored.
+ *             the paper, Sec. 7.2), LD_INIT_WK, LD_INIT_ZERO, or LD_INIT_GIVEN
+ *             (duals set by ld_state_set_rho).  On that call q(rho^0) is stored.
  * tie_tau     relative tie band of the inner minimisation (2^-20 suggested).
  * engine      LD_ENGINE_RESIDENT: one launch runs all `iters` steps, each
  *             workgroup owning S subdomains with their intermediates in LDS
@@ -299,6 +302,30 @@ int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, int* c
 int ld_profile_iteration(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opts* opts,
                          int reps, double* avg_us, int* kinds, int max_slots, int* n_slots,
                          hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* branching: Filtered Smart Branching (Sec. 4.2)                             */
+/* ------------------------------------------------------------------------- */
+/* For every subdomain of `batch`, the ReLU split FSB picks:
+ *  - the scores s_FSB (eq:fsb-scores) and t_SR (eq:babsr-scores) of every
+ *    ambiguous ReLU, from the backward pass lambda_{n-1} = -W_n^T c,
+ *    lambda_{k-1} = W_k^T (a_k lambda_k) with the chord slope a_k (FP32
+ *    contractions, FP64 scores);
+ *  - per hidden layer the ReLU with the largest s_FSB and the one with the
+ *    largest t_SR (eq:fsb-prefilter; the first index on ties);
+ *  - for each candidate, its two children (l := 0 active, u := 0 inactive),
+ *    each bounded by the better of CROWN and WK (q at their dual assignments,
+ *    Prop. 2, FP32 operands, FP64 sum);
+ *  - the candidate whose worse child has the best bound (the first in layer,
+ *    then s_FSB-before-t_SR order on ties).
+ * layer[b] (1..n-1, 0 if no ReLU is ambiguous), index[b] (neuron in (C,H,W)
+ * order, -1 if none), value[b] (that worse child's bound, -inf if none): device
+ * arrays [B].  candidates: NULL or device int [B, n-1, 2] receiving the
+ * prefilter's indices (-1: no ambiguous ReLU in that layer).  Bounds l <= u
+ * and the objective c are read from `batch`.  Synchronous (allocates a batch of
+ * 4 (n-1) B children).  At most 16 hidden layers (LD_E_UNSUPPORTED). */
+int ld_fsb_branch(const ld_net* net, const ld_batch* batch, int* layer, int* index, double* value,
+                  int* candidates, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* intermediate bounds (Sec. 2.2.3), batched over neurons (Sec. 5.2)          */

@@ -19,12 +19,12 @@ LD_OK, LD_E_ARG, LD_E_SHAPE, LD_E_NUMERIC, LD_E_NOMEM, LD_E_DEVICE, LD_E_UNSUPPO
     0, -1, -2, -3, -4, -5, -6, -7
 LD_LINEAR, LD_CONV2D = 0, 1
 LD_FP32, LD_BF16 = 0, 1
-LD_INIT_CROWN, LD_INIT_ZERO, LD_INIT_GIVEN = 0, 1, 2
+LD_INIT_CROWN, LD_INIT_ZERO, LD_INIT_GIVEN, LD_INIT_WK = 0, 1, 2, 3
 LD_ENGINE_AUTO, LD_ENGINE_RESIDENT, LD_ENGINE_LAYERWISE = 0, 1, 2
 TAU_DEFAULT = 2.0 ** -20
 
 _PREC = {"fp32": LD_FP32, "bf16": LD_BF16, LD_FP32: LD_FP32, LD_BF16: LD_BF16}
-_INIT = {"crown": LD_INIT_CROWN, "zero": LD_INIT_ZERO, "given": LD_INIT_GIVEN}
+_INIT = {"crown": LD_INIT_CROWN, "zero": LD_INIT_ZERO, "given": LD_INIT_GIVEN, "wk": LD_INIT_WK}
 _ENGINE = {"auto": LD_ENGINE_AUTO, "resident": LD_ENGINE_RESIDENT, "layerwise": LD_ENGINE_LAYERWISE}
 
 EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num_layers",
@@ -32,7 +32,7 @@ EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num
             "ld_state_get_rho", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
-            "ld_intermediate_bounds", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
+            "ld_intermediate_bounds", "ld_fsb_branch", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
 
 
 class LDError(RuntimeError):
@@ -115,6 +115,7 @@ def load_library(path: Optional[str] = None):
     lib.ld_set_tuned_config.argtypes = [V, I, I, I, I, P(ld_tile)]
     lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
     lib.ld_intermediate_bounds.argtypes = [V, P(ld_batch), P(ld_opts), I, V, V, V]
+    lib.ld_fsb_branch.argtypes = [V, P(ld_batch), V, V, V, V, V]
     lib.ld_prox_step.argtypes = [V, P(ld_batch), V, P(ld_prox_opts), V]
     lib.ld_prox_get_step.argtypes = [V, P(I)]
     lib.ld_prox_profile_iteration.argtypes = [V, P(ld_batch), V, P(ld_prox_opts), I, P(ctypes.c_double), P(I), I,
@@ -292,6 +293,20 @@ def step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional
          tau: float = TAU_DEFAULT, engine="auto", stream=None):
     o = _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine)
     _check(net.lib.ld_step(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o), _stream(stream)))
+
+
+def fsb_branch(net: Net, batch: Batch, candidates=False, stream=None):
+    """FSB's split per subdomain (ld_fsb_branch): (layer [B] int32, index [B] int32,
+    value [B] float64) and, if asked, the prefilter's candidates [B, n-1, 2]."""
+    B = batch.B
+    layer = torch.empty(B, device="cuda", dtype=torch.int32)
+    index = torch.empty(B, device="cuda", dtype=torch.int32)
+    value = torch.empty(B, device="cuda", dtype=torch.float64)
+    cand = torch.empty((B, len(net.widths) - 2, 2), device="cuda", dtype=torch.int32) if candidates else None
+    _check(net.lib.ld_fsb_branch(net.handle, ctypes.byref(batch.struct), ctypes.c_void_p(layer.data_ptr()),
+                                 ctypes.c_void_p(index.data_ptr()), ctypes.c_void_p(value.data_ptr()),
+                                 ctypes.c_void_p(cand.data_ptr()) if cand is not None else None, _stream(stream)))
+    return (layer, index, value, cand) if candidates else (layer, index, value)
 
 
 def intermediate_bounds(sub: Net, batch: Batch, iters: int, total_iters: Optional[int] = None, lr0=1e-2,

@@ -877,7 +877,7 @@ int dual_eval_impl(const ld_net* net, const ld_batch* bt, const float* const* rh
   return LD_OK;
 }
 
-// CROWN duals (Prop. 2) or zeros into rho (rho[k-1] = rho_k).
+// CROWN or WK duals (Prop. 2) or zeros into rho (rho[k-1] = rho_k).
 int init_impl(const ld_net* net, const ld_batch* bt, int init, int mma, float* const* rho, Workspace& ws,
               hipStream_t s) {
   const int n = net->n, B = bt->B;
@@ -885,13 +885,14 @@ int init_impl(const ld_net* net, const ld_batch* bt, int init, int mma, float* c
     for (int k = 1; k <= n - 1; ++k) LD_HIP(hipMemsetAsync(rho[k - 1], 0, (size_t)B * width(net, k) * 4, s));
     return LD_OK;
   }
+  const int wk = init == LD_INIT_WK ? 1 : 0;
   LD_TRY(prepare_objective(net, bt, ws, mma, s));
-  LD_HIP(launch_crown_const(B, width(net, n - 1), ws.gconst, bt->l[n - 2], bt->u[n - 2], rho[n - 2], s));
+  LD_HIP(launch_crown_const(B, width(net, n - 1), ws.gconst, bt->l[n - 2], bt->u[n - 2], rho[n - 2], wk, s));
   for (int k = n - 1; k >= 2; --k) {
     // rho_{k-1} from g_{k-1} = W_k^T rho_k
     const Layer& L = net->L[k - 1];
     EpiArgs e = epi0();
-    e.kind = EPI_CROWN;
+    e.kind = wk ? EPI_WK : EPI_CROWN;
     e.lo = bt->l[k - 2];
     e.hi = bt->u[k - 2];
     e.out_f = rho[k - 2];
@@ -1377,7 +1378,8 @@ int ld_init_duals(const ld_net* net, const ld_batch* bt, int init, int precision
   g_err.clear();
   LD_TRY(check_batch(net, bt));
   if (!rho) return fail(LD_E_ARG, "rho is NULL");
-  if (init != LD_INIT_CROWN && init != LD_INIT_ZERO) return fail(LD_E_ARG, "init must be LD_INIT_CROWN or LD_INIT_ZERO");
+  if (init != LD_INIT_CROWN && init != LD_INIT_ZERO && init != LD_INIT_WK)
+    return fail(LD_E_ARG, "init must be LD_INIT_CROWN, LD_INIT_ZERO or LD_INIT_WK");
   if (precision != LD_FP32 && precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
   if (bt->B == 0) return LD_OK;
   for (int k = 0; k < net->n - 1; ++k) {
@@ -1418,7 +1420,8 @@ static int check_step_args(const ld_net* net, const ld_batch* bt, const ld_state
   if (bt->B == 0) return fail(LD_E_ARG, "empty batch");
   if (o->iters < 0 || o->total_iters < 1) return fail(LD_E_ARG, "iters must be >= 0 and total_iters >= 1");
   if (o->precision != LD_FP32 && o->precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
-  if (o->init != LD_INIT_CROWN && o->init != LD_INIT_ZERO && o->init != LD_INIT_GIVEN) return fail(LD_E_ARG, "bad init");
+  if (o->init != LD_INIT_CROWN && o->init != LD_INIT_ZERO && o->init != LD_INIT_GIVEN && o->init != LD_INIT_WK)
+    return fail(LD_E_ARG, "bad init");
   if (o->engine != LD_ENGINE_AUTO && o->engine != LD_ENGINE_RESIDENT && o->engine != LD_ENGINE_LAYERWISE)
     return fail(LD_E_ARG, "bad engine");
   if (!std::isfinite(o->lr0) || !std::isfinite(o->lr_end) || !(o->beta1 >= 0.f && o->beta1 < 1.f) ||
@@ -1928,7 +1931,8 @@ static int check_prox_args(const ld_net* net, const ld_batch* bt, const ld_state
     return fail(LD_E_ARG, "eta0 and eta_end must be finite and > 0");
   if (!(o->mu >= 0.f && o->mu < 1.f)) return fail(LD_E_ARG, "mu must be in [0, 1)");
   if (o->precision != LD_FP32 && o->precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
-  if (o->init != LD_INIT_CROWN && o->init != LD_INIT_ZERO && o->init != LD_INIT_GIVEN) return fail(LD_E_ARG, "bad init");
+  if (o->init != LD_INIT_CROWN && o->init != LD_INIT_ZERO && o->init != LD_INIT_GIVEN && o->init != LD_INIT_WK)
+    return fail(LD_E_ARG, "bad init");
   if (!(o->tie_tau >= 0.f) || !std::isfinite(o->tie_tau)) return fail(LD_E_ARG, "tie_tau must be finite and >= 0");
   if (net->n - 1 > 64) return fail(LD_E_UNSUPPORTED, "more than 64 hidden layers");
   return LD_OK;
@@ -2033,7 +2037,7 @@ int ld_intermediate_bounds(const ld_net* sub, const ld_batch* bt, const ld_opts*
   if (!bt->l0 || !bt->u0 || !bt->l || !bt->u) return fail(LD_E_ARG, "batch l0/u0/l/u is NULL");
   for (int k = 1; k <= n - 1; ++k)
     if (!bt->l[k - 1] || !bt->u[k - 1]) return fail(LD_E_ARG, "batch l[k]/u[k] is NULL for k=" + std::to_string(k));
-  if (o->init == LD_INIT_GIVEN) return fail(LD_E_ARG, "init must be LD_INIT_CROWN or LD_INIT_ZERO");
+  if (o->init == LD_INIT_GIVEN) return fail(LD_E_ARG, "init must be LD_INIT_CROWN, LD_INIT_ZERO or LD_INIT_WK");
   if (n - 1 > 32) return fail(LD_E_UNSUPPORTED, "more than 32 hidden layers");
   const int nj = width(sub, n);
   const long long P = 2LL * nj;
@@ -2106,6 +2110,140 @@ int ld_intermediate_bounds(const ld_net* sub, const ld_batch* bt, const ld_opts*
   for (ld_state* st : states) ld_state_destroy(st);
   (void)hipFree(base);
   if (rc == LD_OK && es != hipSuccess) rc = fail(LD_E_DEVICE, std::string("intermediate bounds: ") + hipGetErrorString(es));
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Filtered Smart Branching (Sec. 4.2)
+// ---------------------------------------------------------------------------
+int ld_fsb_branch(const ld_net* net, const ld_batch* bt, int* layer, int* index, double* value, int* candidates,
+                  hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_batch(net, bt));
+  if (!layer || !index || !value) return fail(LD_E_ARG, "NULL output");
+  const int n = net->n, B = bt->B, nh = n - 1;
+  if (B == 0) return LD_OK;
+  if (nh > 16) return fail(LD_E_UNSUPPORTED, "more than 16 hidden layers");
+  const int M = 4 * nh;  // children per subdomain: 2 candidates x 2 phases per hidden layer
+  const long long Bc = (long long)B * M;
+  if (Bc > (1LL << 30)) return fail(LD_E_UNSUPPORTED, "too many children");
+  // device buffers: lambda_k (k = 1..n-2; lambda_{n-1} is the objective constant),
+  // candidates, the children's batch, their duals and bounds
+  std::vector<size_t> sz;
+  auto add = [&](size_t bytes) {
+    sz.push_back(round_up(std::max<size_t>(bytes, 4), 256));
+    return sz.size() - 1;
+  };
+  std::vector<size_t> i_lam, i_cl, i_cu, i_rho;
+  for (int k = 1; k <= n - 2; ++k) i_lam.push_back(add((size_t)B * width(net, k) * 4));
+  const size_t i_cand = add((size_t)B * nh * 2 * 4);
+  const size_t i_l0 = add((size_t)Bc * net->n0 * 4), i_u0 = add((size_t)Bc * net->n0 * 4);
+  for (int k = 1; k <= nh; ++k) {
+    i_cl.push_back(add((size_t)Bc * width(net, k) * 4));
+    i_cu.push_back(add((size_t)Bc * width(net, k) * 4));
+    i_rho.push_back(add((size_t)Bc * width(net, k) * 4));
+  }
+  const size_t i_c = add((size_t)Bc * width(net, n) * 4);
+  const size_t i_qc = add((size_t)Bc * 8), i_qw = add((size_t)Bc * 8);
+  std::vector<size_t> off(sz.size());
+  size_t total = 0;
+  for (size_t i = 0; i < sz.size(); ++i) {
+    off[i] = total;
+    total += sz[i];
+  }
+  void* base = nullptr;
+  if (hipMalloc(&base, total) != hipSuccess) return fail(LD_E_NOMEM, "branching buffers: hipMalloc failed");
+  char* cb = (char*)base;
+  auto F = [&](size_t i) { return (float*)(cb + off[i]); };
+  Workspace ws;
+  int rc = ws_alloc(net, ws, (int)std::max<long long>(Bc, B));
+  if (rc == LD_OK) rc = validate_values(net, bt, ws, s);
+  int* cand = candidates ? candidates : (int*)(cb + off[i_cand]);
+  std::vector<float*> rho(nh);
+  for (int k = 1; k <= nh; ++k) rho[k - 1] = F(i_rho[k - 1]);
+  // 1. parent: WK duals and the backward pass lambda_k = W_{k+1}^T rho_{k+1} (eq:babsr-scores)
+  if (rc == LD_OK) rc = init_impl(net, bt, LD_INIT_WK, 0, rho.data(), ws, s);
+  std::vector<const float*> lam(nh), lo(nh), hi(nh), bias(nh);
+  std::vector<int> bdiv(nh), wid(nh);
+  for (int k = 1; k <= nh && rc == LD_OK; ++k) {
+    if (k <= n - 2) {
+      EpiArgs e = epi0();
+      e.kind = EPI_STORE;
+      e.out_f = F(i_lam[k - 1]);
+      const hipError_t he = run_job(net->L[k].tr, B, rho[k], 0, 0, e, pick_tile(net, k, 1, B, 0), ws, k, s);
+      if (he != hipSuccess) rc = fail(LD_E_DEVICE, std::string("fsb backward pass: ") + hipGetErrorString(he));
+      lam[k - 1] = F(i_lam[k - 1]);
+    } else {
+      lam[k - 1] = ws.gconst;
+    }
+    lo[k - 1] = bt->l[k - 1];
+    hi[k - 1] = bt->u[k - 1];
+    bias[k - 1] = net->L[k - 1].bias;
+    bdiv[k - 1] = bias_div(net, k);
+    wid[k - 1] = width(net, k);
+  }
+  // 2. scores and the candidates of eq:fsb-prefilter
+  if (rc == LD_OK) {
+    const hipError_t he = launch_fsb_scores(B, nh, lam.data(), lo.data(), hi.data(), bias.data(), bdiv.data(),
+                                            wid.data(), cand, s);
+    if (he != hipSuccess) rc = fail(LD_E_DEVICE, std::string("fsb scores: ") + hipGetErrorString(he));
+  }
+  // 3. the children: one batch of B*M subdomains, each with one ReLU split
+  std::vector<const float*> cl(nh), cu(nh);
+  std::vector<float*> clw(nh), cuw(nh);
+  for (int k = 1; k <= nh; ++k) {
+    clw[k - 1] = F(i_cl[k - 1]);
+    cuw[k - 1] = F(i_cu[k - 1]);
+    cl[k - 1] = clw[k - 1];
+    cu[k - 1] = cuw[k - 1];
+  }
+  if (rc == LD_OK) {
+    IntermPack K;
+    std::memset(&K, 0, sizeof(K));
+    std::vector<std::pair<const float*, float*>> arr = {{bt->l0, F(i_l0)}, {bt->u0, F(i_u0)}};
+    std::vector<int> w = {net->n0, net->n0};
+    for (int k = 1; k <= nh; ++k) {
+      arr.push_back({bt->l[k - 1], clw[k - 1]});
+      w.push_back(width(net, k));
+      arr.push_back({bt->u[k - 1], cuw[k - 1]});
+      w.push_back(width(net, k));
+    }
+    arr.push_back({bt->c, F(i_c)});
+    w.push_back(width(net, n));
+    K.n = (int)arr.size();
+    for (int a = 0; a < K.n; ++a) {
+      K.src[a] = arr[a].first;
+      K.dst[a] = arr[a].second;
+      K.width[a] = w[a];
+    }
+    K.c = nullptr;
+    const hipError_t he = launch_fsb_expand(K, B, nh, cand, clw.data(), cuw.data(), wid.data(), s);
+    if (he != hipSuccess) rc = fail(LD_E_DEVICE, std::string("fsb expand: ") + hipGetErrorString(he));
+  }
+  // 4. the children's CROWN and WK bounds (q at the propagation duals, Prop. 2)
+  ld_batch cbt;
+  cbt.B = (int)Bc;
+  cbt.l0 = F(i_l0);
+  cbt.u0 = F(i_u0);
+  cbt.l = cl.data();
+  cbt.u = cu.data();
+  cbt.c = F(i_c);
+  std::vector<const float*> crho(rho.begin(), rho.end());
+  double* qc = (double*)(cb + off[i_qc]);
+  double* qw = (double*)(cb + off[i_qw]);
+  if (rc == LD_OK) rc = init_impl(net, &cbt, LD_INIT_CROWN, 0, rho.data(), ws, s);
+  if (rc == LD_OK) rc = dual_eval_impl(net, &cbt, crho.data(), ws, qc, nullptr, 0, 0.f, s);
+  if (rc == LD_OK) rc = init_impl(net, &cbt, LD_INIT_WK, 0, rho.data(), ws, s);
+  if (rc == LD_OK) rc = dual_eval_impl(net, &cbt, crho.data(), ws, qw, nullptr, 0, 0.f, s);
+  // 5. the candidate whose worse child has the best bound
+  if (rc == LD_OK) {
+    const hipError_t he = launch_fsb_select(B, nh, cand, qc, qw, layer, index, value, s);
+    if (he != hipSuccess) rc = fail(LD_E_DEVICE, std::string("fsb select: ") + hipGetErrorString(he));
+  }
+  const hipError_t es = hipStreamSynchronize(s);
+  if (ws.base) (void)hipFree(ws.base);
+  (void)hipFree(base);
+  if (rc == LD_OK && es != hipSuccess) rc = fail(LD_E_DEVICE, std::string("branching: ") + hipGetErrorString(es));
   return rc;
 }
 

@@ -54,11 +54,12 @@ __device__ __forceinline__ void inner_min(T r, T g, T l, T u, T tau, T& xb, T& x
 }
 
 // CROWN dual of one neuron from g = (W^T rho_next)[i] (eq:salman-assignment with
-// the slopes of eq:slopes-biases: chord upper slope, lower slope 1[u >= -l]).
-__device__ __forceinline__ float crown_dual(float g, float l, float u) {
+// the slopes of eq:slopes-biases: chord upper slope, lower slope 1[u >= -l]);
+// with wk, the WK slopes (the chord as both the upper and the lower slope, Sec. 4.1).
+__device__ __forceinline__ float crown_dual(float g, float l, float u, bool wk = false) {
   if (l >= 0.f) return g;
   if (u <= 0.f) return 0.f;
-  if (g > 0.f) return (u / (u - l)) * g;
+  if (g > 0.f || wk) return (u / (u - l)) * g;
   return (u >= -l) ? g : 0.f;
 }
 

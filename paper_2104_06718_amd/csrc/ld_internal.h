@@ -55,7 +55,8 @@ enum EpiKind : int {
   EPI_CROWN = 5,        // CROWN dual: a_up [g]_+ + a_lo [g]_-
   EPI_RELU_FWD = 6,     // y = acc + b, feasibility against [l, u], x = relu(y)
   EPI_BIAS_STORE = 7,   // y = acc + b stored
-  EPI_ADAM_LAST = 8     // as EPI_ADAM for the last hidden layer: xB from the constant g (gc)
+  EPI_ADAM_LAST = 8,    // as EPI_ADAM for the last hidden layer: xB from the constant g (gc)
+  EPI_WK = 9            // WK dual: chord slope times g
 };
 
 struct EpiArgs {
@@ -64,7 +65,7 @@ struct EpiArgs {
   float scale;
   float tau;            // tie band
   int want_val;         // write FP64 per-neuron values
-  float* out_f;         // EPI_STORE / EPI_SUPERGRAD / EPI_CROWN / EPI_RELU_FWD / EPI_BIAS_STORE
+  float* out_f;         // EPI_STORE / EPI_SUPERGRAD / EPI_CROWN / EPI_WK / EPI_RELU_FWD / EPI_BIAS_STORE
   void* xs;             // x* (float or bf16)
   float* xb;            // xB*
   double* val;          // per-neuron FP64 values
@@ -195,7 +196,7 @@ hipError_t launch_inner_min_const(int B, int n, const float* g, const float* rho
                                   double lr_end, int total, double beta1, double beta2, double eps,
                                   hipStream_t s);
 hipError_t launch_crown_const(int B, int n, const float* g, const float* lo, const float* hi,
-                              float* rho, hipStream_t s);
+                              float* rho, int wk, hipStream_t s);
 hipError_t launch_reduce_q(int B, int n_arrays, const double* const* arrays, const int* sizes,
                            const double* cb, double* q, hipStream_t s);
 hipError_t launch_cdot(int B, int n, const float* c, const float* y, const float* bias, int bias_div, double* out,
@@ -267,6 +268,15 @@ struct IntermPack {
   float* c;
 };
 hipError_t launch_interm_expand(const IntermPack& K, int C, long long start, int P, int nj, hipStream_t s);
+// branching (ld_fsb.hip); at most kFsbMaxHidden hidden layers
+constexpr int kFsbMaxHidden = 16;
+hipError_t launch_fsb_scores(int B, int n_hidden, const float* const* lam, const float* const* lo,
+                             const float* const* hi, const float* const* bias, const int* bias_div,
+                             const int* width, int* cand, hipStream_t s);
+hipError_t launch_fsb_expand(const IntermPack& K, int B, int n_hidden, const int* cand, float* const* lo_child,
+                             float* const* hi_child, const int* width, hipStream_t s);
+hipError_t launch_fsb_select(int B, int n_hidden, const int* cand, const double* q_crown, const double* q_wk,
+                             int* layer, int* index, double* value, hipStream_t s);
 hipError_t launch_interm_collect(int C, long long start, int P, int nj, const double* bound, float* lo, float* hi,
                                  hipStream_t s);
 

@@ -107,6 +107,7 @@ __device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st,
   switch (E.kind) {
     case EPI_P0:
     case EPI_CROWN:
+    case EPI_WK:
     case EPI_RELU_FWD:
       in.a0 = ld4v<VEC>(E.lo, i0, st, nv);
       in.a1 = ld4v<VEC>(E.hi, i0, st, nv);
@@ -228,10 +229,12 @@ __device__ __forceinline__ void epi_finish(const EpiArgs& E, size_t i0, size_t s
       for (int q = 0; q < 4; ++q) o[q] = in.a0[q] - (acc[q] + ((VEC || q < nv) ? E.bias[col + q * cstep] : 0.f));
       st4<VEC>(E.out_f, i0, st, nv, o);
     } break;
-    case EPI_CROWN: {
+    case EPI_CROWN:
+    case EPI_WK: {
       float o[4];
+      const bool wk = E.kind == EPI_WK;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = crown_dual(acc[q], in.a0[q], in.a1[q]);
+      for (int q = 0; q < 4; ++q) o[q] = crown_dual(acc[q], in.a0[q], in.a1[q], wk);
       st4<VEC>(E.out_f, i0, st, nv, o);
     } break;
     case EPI_RELU_FWD: {
@@ -1103,10 +1106,10 @@ __global__ void inner_min_const_kernel(int B, int n, const float* __restrict__ g
 }
 
 __global__ void crown_const_kernel(int B, int n, const float* __restrict__ g, const float* __restrict__ lo,
-                                   const float* __restrict__ hi, float* __restrict__ rho) {
+                                   const float* __restrict__ hi, float* __restrict__ rho, int wk) {
   const size_t total_n = (size_t)B * n;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total_n; i += (size_t)gridDim.x * blockDim.x)
-    rho[i] = crown_dual(g[i], lo[i], hi[i]);
+    rho[i] = crown_dual(g[i], lo[i], hi[i], wk != 0);
 }
 
 // q[b] = cb[b] + sum over arrays of sum_j arr[b, j]; fixed summation order (FP64).
@@ -1189,9 +1192,9 @@ hipError_t launch_inner_min_const(int B, int n, const float* g, const float* rho
   return hipGetLastError();
 }
 
-hipError_t launch_crown_const(int B, int n, const float* g, const float* lo, const float* hi, float* rho,
+hipError_t launch_crown_const(int B, int n, const float* g, const float* lo, const float* hi, float* rho, int wk,
                               hipStream_t s) {
-  hipLaunchKernelGGL(crown_const_kernel, dim3(grid_for((size_t)B * n)), dim3(256), 0, s, B, n, g, lo, hi, rho);
+  hipLaunchKernelGGL(crown_const_kernel, dim3(grid_for((size_t)B * n)), dim3(256), 0, s, B, n, g, lo, hi, rho, wk);
   return hipGetLastError();
 }
 
