@@ -48,9 +48,9 @@ def parse():
                          "iterations launched without the graph; prints the per-launch averages")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--engine", choices=["auto", "layerwise", "resident"], default="auto")
-    ap.add_argument("--solver", choices=["ld", "prox", "interm"], default="ld",
+    ap.add_argument("--solver", choices=["ld", "prox", "interm", "fsb"], default="ld",
                     help="ld: Adam supergradient ascent (the headline line); prox: the proximal solver; "
-                         "interm: LD intermediate bounds of one layer")
+                         "interm: LD intermediate bounds of one layer; fsb: branching decisions")
     ap.add_argument("--layer", type=int, default=2, help="interm: layer j whose pre-activations are bounded")
     return ap.parse_args()
 
@@ -410,6 +410,55 @@ def main_interm(a, P, inst):
     print(json.dumps(out), flush=True)
 
 
+def main_fsb(a, P, inst, net, batch):
+    """Filtered Smart Branching (Sec. 4.2) for every subdomain of the batch: scores,
+    candidates, 4 (n-1) children per subdomain bounded by CROWN and WK, the split."""
+    import torch
+    B = inst.B
+    for _ in range(a.warmup):
+        P.fsb_branch(net, batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        layer, index, value = P.fsb_branch(net, batch)
+    torch.cuda.synchronize()
+    ms = 1000 * (time.perf_counter() - t0) / a.steps
+    out = {
+        "metric": f"FSB branching decisions/sec (B={B}, {a.config} conv net)",
+        "value": B / (ms / 1000.0),
+        "unit": "decisions/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.config} conv net 3x32x32, B={B} subdomains, {4 * (len(inst.layers) - 1)} "
+                               f"children each bounded by CROWN and WK", "B": B},
+        "mean_worse_child_bound": value[torch.isfinite(value)].mean().item(),
+        # the call is one synchronous pipeline (allocation included); its kernels are
+        # timed by rocprofv3 (profiles/), not per launch here
+        "roofline": None,
+    }
+    if not a.no_cpu_baseline:
+        from oracle import ld_oracle as O
+        idx = list(range(min(B, 16)))
+        onet = O.net_from_specs(inst.layers)
+        ob = O.batch_from_instance(inst, idx)
+        t0 = time.perf_counter()
+        ol, oi, ov = O.fsb_branch(onet, ob)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=len(idx) / dt, unit="decisions/s", cores=torch.get_num_threads(),
+                                   kind="oracle", sample=f"{len(idx)} of {B} subdomains (the first ones), "
+                                                         f"FP64 torch-CPU oracle, {dt:.1f} s")
+        same = (layer.cpu().long()[idx] == ol) & (index.cpu().long()[idx] == oi)
+        out["equal_to_oracle"] = f"{int(same.sum())} of {len(idx)} splits"
+    print(json.dumps(out), flush=True)
+
+
 def src_hash():
     """Hash of the HIP sources (a stored counter measurement is valid for this build only)."""
     h = hashlib.sha256()
@@ -459,6 +508,9 @@ def main():
         return
     if a.solver == "interm":
         main_interm(a, P, inst)
+        return
+    if a.solver == "fsb":
+        main_fsb(a, P, inst, net, batch)
         return
 
     if a.profile_only:
