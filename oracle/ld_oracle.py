@@ -640,3 +640,24 @@ def fsb_branch(net: List[OLayer], batch: OBatch):
                 if v > value[b]:
                     layer[b], index[b], value[b] = k, i, v
     return layer, index, value
+
+
+def branch_children(batch: OBatch, layer: torch.Tensor, index: torch.Tensor) -> OBatch:
+    """The two children of every subdomain for its split (layer, index): child 2b has
+    the ReLU fixed active (l := 0), child 2b+1 inactive (u := 0); a subdomain with
+    no split (index < 0) is copied into both.  A child warm-starts from its parent's
+    duals (Sec. 7.3)."""
+    kids = []
+    for b in range(batch.l0.shape[0]):
+        k, i = int(layer[b]), int(index[b])
+        for active in (True, False):
+            if i < 0:
+                kids.append(OBatch(batch.l0[b:b + 1], batch.u0[b:b + 1], [x[b:b + 1] for x in batch.l],
+                                   [x[b:b + 1] for x in batch.u], batch.c[b:b + 1]))
+            else:
+                kids.append(split_child(batch, b, k, i, active))
+    cat = lambda xs: torch.cat(xs, dim=0)  # noqa: E731
+    nh = len(batch.l)
+    return OBatch(cat([c.l0 for c in kids]), cat([c.u0 for c in kids]),
+                  [cat([c.l[k] for c in kids]) for k in range(nh)], [cat([c.u[k] for c in kids]) for k in range(nh)],
+                  cat([c.c for c in kids]))

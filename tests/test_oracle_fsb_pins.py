@@ -126,3 +126,24 @@ def test_decision_is_the_best_worst_child(name):
         k, i = int(layer[b]), int(index[b])
         v = min(_indep_best(_child_inst(inst, b, k, i, act)) for act in (True, False))
         assert abs(v - best) <= 1e-10 * (1 + abs(best))
+
+
+@pytest.mark.parametrize("name", ["fc_tiny", "tiny_conv", "tiny_conv2"])
+def test_children_bound_at_parent_duals_is_not_below_the_parent(name):
+    """A child's feasible set is a subset of its parent's, so at the parent's duals the
+    child's dual value is at least the parent's (the property warm starts rely on)."""
+    inst, net, batch = _setup(name)
+    layer, index, _ = O.fsb_branch(net, batch)
+    kids = O.branch_children(batch, layer, index)
+    rng = np.random.default_rng(5)
+    for rho in (O.crown_init(net, batch),
+                [torch.as_tensor(rng.normal(size=r.shape) * 0.1) for r in O.crown_init(net, batch)]):
+        qp = O.dual_eval(net, batch, rho, need_supergrad=False)["q"]
+        rk = [r.repeat_interleave(2, dim=0) for r in rho]
+        qc = O.dual_eval(net, kids, rk, need_supergrad=False)["q"]
+        assert bool((qc >= qp.repeat_interleave(2) - 1e-12).all())
+    # the split itself: child 2b active (l = 0), child 2b+1 inactive (u = 0)
+    for b in range(inst.B):
+        k, i = int(layer[b]), int(index[b])
+        assert kids.l[k - 1][2 * b, i] == 0.0 and kids.u[k - 1][2 * b + 1, i] == 0.0
+        assert kids.u[k - 1][2 * b, i] == batch.u[k - 1][b, i] and kids.l[k - 1][2 * b + 1, i] == batch.l[k - 1][b, i]
