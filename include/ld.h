@@ -327,6 +327,20 @@ int ld_profile_iteration(const ld_net* net, const ld_batch* batch, ld_state* st,
 int ld_fsb_branch(const ld_net* net, const ld_batch* batch, int* layer, int* index, double* value,
                   int* candidates, hipStream_t stream);
 
+/* The children of every subdomain for its split (layer[b], index[b]), as
+ * ld_fsb_branch returns it: child 2b has the ReLU fixed active (l := 0), child
+ * 2b+1 inactive (u := 0); a subdomain with index < 0 is copied into both.  The
+ * outputs are caller-owned device arrays for 2B subdomains: l0_out, u0_out
+ * [2B, n_0], l_out[k], u_out[k] [2B, n_k] (host arrays of n-1 device pointers),
+ * c_out [2B, n_out].  rho / rho_out (both or neither): the parents' duals [B, n_k]
+ * copied to both children, the warm start of Sec. 7.3 (pass rho_out to
+ * ld_state_set_rho and step with LD_INIT_GIVEN, or to ld_dual_eval; at the
+ * parent's duals a child's q is never below its parent's).  Asynchronous on
+ * `stream`.  layer and index are device int arrays [B]. */
+int ld_branch_children(const ld_net* net, const ld_batch* batch, const int* layer, const int* index,
+                       const float* const* rho, float* l0_out, float* u0_out, float* const* l_out,
+                       float* const* u_out, float* c_out, float* const* rho_out, hipStream_t stream);
+
 /* ------------------------------------------------------------------------- */
 /* intermediate bounds (Sec. 2.2.3), batched over neurons (Sec. 5.2)          */
 /* ------------------------------------------------------------------------- */

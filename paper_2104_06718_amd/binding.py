@@ -32,7 +32,7 @@ EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num
             "ld_state_get_rho", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
-            "ld_intermediate_bounds", "ld_fsb_branch", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
+            "ld_intermediate_bounds", "ld_fsb_branch", "ld_branch_children", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
 
 
 class LDError(RuntimeError):
@@ -116,6 +116,7 @@ def load_library(path: Optional[str] = None):
     lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
     lib.ld_intermediate_bounds.argtypes = [V, P(ld_batch), P(ld_opts), I, V, V, V]
     lib.ld_fsb_branch.argtypes = [V, P(ld_batch), V, V, V, V, V]
+    lib.ld_branch_children.argtypes = [V, P(ld_batch), V, V, P(V), V, V, P(V), P(V), V, P(V), V]
     lib.ld_prox_step.argtypes = [V, P(ld_batch), V, P(ld_prox_opts), V]
     lib.ld_prox_get_step.argtypes = [V, P(I)]
     lib.ld_prox_profile_iteration.argtypes = [V, P(ld_batch), V, P(ld_prox_opts), I, P(ctypes.c_double), P(I), I,
@@ -307,6 +308,32 @@ def fsb_branch(net: Net, batch: Batch, candidates=False, stream=None):
                                  ctypes.c_void_p(index.data_ptr()), ctypes.c_void_p(value.data_ptr()),
                                  ctypes.c_void_p(cand.data_ptr()) if cand is not None else None, _stream(stream)))
     return (layer, index, value, cand) if candidates else (layer, index, value)
+
+
+def branch_children(net: Net, batch: Batch, layer: torch.Tensor, index: torch.Tensor, rho=None, stream=None):
+    """The 2B children of the splits (ld_branch_children): a Batch and, if the
+    parents' duals are given, the children's warm-start duals."""
+    B = batch.B
+    w = net.widths
+    l0 = torch.empty((2 * B, w[0]), device="cuda", dtype=torch.float32)
+    u0 = torch.empty_like(l0)
+    lo = [torch.empty((2 * B, x), device="cuda", dtype=torch.float32) for x in w[1:-1]]
+    hi = [torch.empty_like(x) for x in lo]
+    c = torch.empty((2 * B, w[-1]), device="cuda", dtype=torch.float32)
+    layer = layer.to(device="cuda", dtype=torch.int32).contiguous()
+    index = index.to(device="cuda", dtype=torch.int32).contiguous()
+    rp = ro = None
+    rho_out = None
+    if rho is not None:
+        rho = [_dev_f32(r, "rho") for r in rho]
+        rho_out = [torch.empty((2 * B, r.shape[1]), device="cuda", dtype=torch.float32) for r in rho]
+        rp, ro = _ptrs(rho), _ptrs(rho_out)
+    _check(net.lib.ld_branch_children(net.handle, ctypes.byref(batch.struct), ctypes.c_void_p(layer.data_ptr()),
+                                      ctypes.c_void_p(index.data_ptr()), rp, ctypes.c_void_p(l0.data_ptr()),
+                                      ctypes.c_void_p(u0.data_ptr()), _ptrs(lo), _ptrs(hi),
+                                      ctypes.c_void_p(c.data_ptr()), ro, _stream(stream)))
+    kids = Batch(l0, u0, lo, hi, c)
+    return (kids, rho_out) if rho is not None else kids
 
 
 def intermediate_bounds(sub: Net, batch: Batch, iters: int, total_iters: Optional[int] = None, lr0=1e-2,

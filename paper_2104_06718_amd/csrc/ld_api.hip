@@ -2247,6 +2247,51 @@ int ld_fsb_branch(const ld_net* net, const ld_batch* bt, int* layer, int* index,
   return rc;
 }
 
+int ld_branch_children(const ld_net* net, const ld_batch* bt, const int* layer, const int* index,
+                       const float* const* rho, float* l0_out, float* u0_out, float* const* l_out,
+                       float* const* u_out, float* c_out, float* const* rho_out, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_batch(net, bt));
+  const int n = net->n, B = bt->B, nh = n - 1;
+  if (!layer || !index || !l0_out || !u0_out || !l_out || !u_out || !c_out) return fail(LD_E_ARG, "NULL argument");
+  if ((rho == nullptr) != (rho_out == nullptr)) return fail(LD_E_ARG, "rho and rho_out must both be given or both NULL");
+  if (nh > kFsbMaxHidden) return fail(LD_E_UNSUPPORTED, "more than 16 hidden layers");
+  for (int k = 0; k < nh; ++k) {
+    if (!l_out[k] || !u_out[k]) return fail(LD_E_ARG, "l_out[k]/u_out[k] is NULL");
+    if (rho && (!rho[k] || !rho_out[k])) return fail(LD_E_ARG, "rho[k]/rho_out[k] is NULL");
+  }
+  if (B == 0) return LD_OK;
+  IntermPack K;
+  std::memset(&K, 0, sizeof(K));
+  std::vector<std::pair<const float*, float*>> arr = {{bt->l0, l0_out}, {bt->u0, u0_out}};
+  std::vector<int> w = {net->n0, net->n0}, wid(nh);
+  std::vector<float*> lo(nh), hi(nh);
+  for (int k = 1; k <= nh; ++k) {
+    arr.push_back({bt->l[k - 1], l_out[k - 1]});
+    arr.push_back({bt->u[k - 1], u_out[k - 1]});
+    w.push_back(width(net, k));
+    w.push_back(width(net, k));
+    lo[k - 1] = l_out[k - 1];
+    hi[k - 1] = u_out[k - 1];
+    wid[k - 1] = width(net, k);
+  }
+  arr.push_back({bt->c, c_out});
+  w.push_back(width(net, n));
+  if (rho)
+    for (int k = 1; k <= nh; ++k) {
+      arr.push_back({rho[k - 1], rho_out[k - 1]});
+      w.push_back(width(net, k));
+    }
+  K.n = (int)arr.size();
+  for (int a = 0; a < K.n; ++a) {
+    K.src[a] = arr[a].first;
+    K.dst[a] = arr[a].second;
+    K.width[a] = w[a];
+  }
+  LD_HIP(launch_branch_children(K, B, nh, layer, index, lo.data(), hi.data(), wid.data(), s));
+  return LD_OK;
+}
+
 int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
   g_err.clear();
   LD_TRY(check_step_args(net, bt, st, o));

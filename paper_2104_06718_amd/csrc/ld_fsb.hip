@@ -8,6 +8,7 @@
 // u := 0); every child is one subdomain of an expanded batch whose CROWN and WK
 // bounds (q at the propagation duals, Prop. 2) the contraction kernels compute.
 // The split is the candidate whose worse child has the best of the two bounds.
+// The children of the chosen splits start from their parent's duals (Sec. 7.3).
 //
 // Child g of the expanded batch: subdomain g / M with M = 4 (n-1); r = g % M gives
 // the hidden layer r / 4 + 1, the candidate (r / 2) % 2 (0: s_FSB, 1: t_SR) and the
@@ -109,6 +110,54 @@ __global__ __launch_bounds__(256) void fsb_expand_kernel(FsbExpandArgs A) {
       dst[g * A.width[k] + i] = 0.f;
     }
   }
+}
+
+struct ChildArgs {
+  IntermPack K;  // parent rows copied into both children (l0, u0, l_k, u_k, c, then rho_k)
+  float* lo[kFsbMaxHidden];
+  float* hi[kFsbMaxHidden];
+  int width[kFsbMaxHidden];
+  const int* layer;
+  const int* index;
+};
+
+// One block per child: child 2b (active: l := 0) and 2b+1 (inactive: u := 0) of
+// subdomain b, split on ReLU index[b] of hidden layer layer[b] (no split if < 0).
+__global__ __launch_bounds__(256) void branch_children_kernel(ChildArgs A) {
+  const size_t g = blockIdx.x;
+  const size_t b = g / 2;
+  for (int a = 0; a < A.K.n; ++a) {
+    const int w = A.K.width[a];
+    const float* __restrict__ src = A.K.src[a] + b * w;
+    float* __restrict__ dst = A.K.dst[a] + g * w;
+    for (int i = threadIdx.x; i < w; i += 256) dst[i] = src[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int k = A.layer[b], i = A.index[b];
+    if (i >= 0 && k >= 1) {
+      float* dst = (g & 1) ? A.hi[k - 1] : A.lo[k - 1];
+      dst[g * A.width[k - 1] + i] = 0.f;
+    }
+  }
+}
+
+hipError_t launch_branch_children(const IntermPack& K, int B, int n_hidden, const int* layer, const int* index,
+                                  float* const* lo_child, float* const* hi_child, const int* width, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  if (n_hidden <= 0 || n_hidden > kFsbMaxHidden || K.n > kIntermMaxArrays || !layer || !index)
+    return hipErrorInvalidValue;
+  ChildArgs A;
+  A.K = K;
+  A.layer = layer;
+  A.index = index;
+  for (int k = 0; k < n_hidden; ++k) {
+    A.lo[k] = lo_child[k];
+    A.hi[k] = hi_child[k];
+    A.width[k] = width[k];
+  }
+  hipLaunchKernelGGL(branch_children_kernel, dim3((unsigned)(2 * (size_t)B)), dim3(256), 0, s, A);
+  return hipGetLastError();
 }
 
 // One thread per subdomain: the candidate whose worse child has the best bound.

@@ -275,6 +275,8 @@ hipError_t launch_fsb_scores(int B, int n_hidden, const float* const* lam, const
                              const int* width, int* cand, hipStream_t s);
 hipError_t launch_fsb_expand(const IntermPack& K, int B, int n_hidden, const int* cand, float* const* lo_child,
                              float* const* hi_child, const int* width, hipStream_t s);
+hipError_t launch_branch_children(const IntermPack& K, int B, int n_hidden, const int* layer, const int* index,
+                                  float* const* lo_child, float* const* hi_child, const int* width, hipStream_t s);
 hipError_t launch_fsb_select(int B, int n_hidden, const int* cand, const double* q_crown, const double* q_wk,
                              int* layer, int* index, double* value, hipStream_t s);
 hipError_t launch_interm_collect(int C, long long start, int P, int nj, const double* bound, float* lo, float* hi,

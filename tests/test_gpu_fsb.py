@@ -95,3 +95,31 @@ def test_no_ambiguous_relu():
     torch.cuda.synchronize()
     assert bool((layer == 0).all()) and bool((index == -1).all())
     assert bool(torch.isinf(value).all()) and bool((value < 0).all())
+
+
+@pytest.mark.parametrize("name,B", [("tiny_conv", None), ("tiny_conv2", None), ("base", 8)])
+def test_children_and_warm_start(name, B):
+    """The children of FSB's splits equal the oracle's (copies and one zeroed bound),
+    they inherit the parent's duals (Sec. 7.3), and at those duals a child's q is not
+    below its parent's."""
+    _case(f"children {name} B={B}")
+    P, inst, net, batch = _setup(name, B=B) if B else _setup(name)
+    layer, index, _ = P.fsb_branch(net, batch)
+    rho = P.init_duals(net, batch, "crown")
+    kids, rk = P.branch_children(net, batch, layer, index, rho)
+    qp, _ = P.dual_eval(net, batch, rho, supergrad=False)
+    qc, _ = P.dual_eval(net, kids, rk, supergrad=False)
+    torch.cuda.synchronize()
+    ob = O.batch_from_instance(inst)
+    ok = O.branch_children(ob, layer.cpu().long(), index.cpu().long())
+    assert torch.equal(kids.l0.cpu().double(), ok.l0) and torch.equal(kids.u0.cpu().double(), ok.u0)
+    assert torch.equal(kids.c.cpu().double(), ok.c)
+    for a, b in zip(kids.l + kids.u, ok.l + ok.u):
+        assert torch.equal(a.cpu().double(), b)
+    for a, r in zip(rk, rho):
+        assert torch.equal(a, r.repeat_interleave(2, dim=0))
+    onet = O.net_from_specs(inst.layers)
+    orho = [r.cpu().double() for r in rho]
+    ev = O.dual_eval(onet, ob, orho, need_supergrad=False)
+    tol = PT.q_tol(onet, ob, orho, ev).repeat_interleave(2)
+    assert bool((qc.cpu() >= qp.cpu().repeat_interleave(2) - 2 * tol).all())
