@@ -29,7 +29,10 @@ Network Verification via Lagrangian Decomposition":
   layer j with the objectives +x_j[i] and -x_j[i], batched over neurons (Sec. 5.2);
 * Filtered Smart Branching (Sec. 4.2): the scores of eq:fsb-scores and
   eq:babsr-scores from one backward pass, the candidates of eq:fsb-prefilter and the
-  split whose worse child has the best CROWN-or-WK bound.
+  split whose worse child has the best CROWN-or-WK bound;
+* the P_k inner minimisation for sigmoid activations (App. E): the hull's tangent
+  points, its envelopes and the minimum over the pieces (eq:siglinopt,
+  eq:with_sig_subp).
 
 Readings where the paper is silent (all listed in the design doc):
 * Adam uses beta1=0.9, beta2=0.999, eps=1e-8 with bias correction, as ascent.
@@ -49,7 +52,9 @@ autograd and vertex enumeration, convergence to the Planet LP optimum), and the
 intermediate bounds in tests/test_oracle_interm_pins.py (sampled pre-activations,
 per-neuron Planet LP optimum), and branching in tests/test_oracle_fsb_pins.py (bias
 sensitivity of an independent WK bound, chord gap, brute-force candidate search; the
-s_FSB formula itself is "parity unpinned" beyond its support and sign).  The final
+s_FSB formula itself is "parity unpinned" beyond its support and sign), and the
+sigmoid inner minimisation in tests/test_oracle_sigmoid_pins.py (sampled convex
+hull, dense search, weak duality).  The final
 bound after T Adam steps has no value printed in the paper: "parity unpinned"
 beyond those inequalities.
 """
@@ -661,3 +666,106 @@ def branch_children(batch: OBatch, layer: torch.Tensor, index: torch.Tensor) -> 
     return OBatch(cat([c.l0 for c in kids]), cat([c.u0 for c in kids]),
                   [cat([c.l[k] for c in kids]) for k in range(nh)], [cat([c.u[k] for c in kids]) for k in range(nh)],
                   cat([c.c for c in kids]))
+
+
+# ----------------------------------------------------------------------------
+# sigmoid activations: the P_k inner minimisation over the sigmoid's convex hull
+# (App. E)
+# ----------------------------------------------------------------------------
+def _sig(x):
+    return 1.0 / (1.0 + torch.exp(-x))
+
+
+def _dsig(x):
+    s = _sig(x)
+    return s * (1.0 - s)
+
+
+def _logit(p):
+    return torch.log(p / (1.0 - p))
+
+
+def sigmoid_hull(l: torch.Tensor, u: torch.Tensor, iters: int = 200):
+    """Tangent points of the sigmoid's convex hull on [l, u] (App. E.1).
+
+    Upper (concave) envelope phi: the chord if sigma'(u) >= the chord's slope (Case 1,
+    returned as t_up = u); else the line from (l, sigma(l)) tangent to sigma at
+    t_up > max(l, 0), then sigma on [t_up, u] (Case 2; t_up = l when l >= 0).  The
+    lower (convex) envelope psi is the mirror image: sigma on [l, t_lo], then the line
+    tangent at t_lo to (u, sigma(u)) (t_lo = u when u <= 0; t_lo = l in Case 1).
+    The tangent points are found by bisection on the tangency condition."""
+    sl, su = _sig(l), _sig(u)
+    width = torch.where(u > l, u - l, torch.ones_like(u))
+    chord = torch.where(u > l, (su - sl) / width, _dsig(l))
+    # upper: F(t) = sigma'(t)(t - l) - (sigma(t) - sigma(l)), F >= 0 at max(l, 0), < 0 at u
+    case2_up = _dsig(u) < chord
+    a = torch.clamp(l, min=0.0)
+    b = u.clone()
+    for _ in range(iters):
+        m = 0.5 * (a + b)
+        F = _dsig(m) * (m - l) - (_sig(m) - sl)
+        a = torch.where(F >= 0, m, a)
+        b = torch.where(F >= 0, b, m)
+    t_up = torch.where(l >= 0, l, torch.where(case2_up, 0.5 * (a + b), u))
+    # lower: G(t) = sigma'(t)(u - t) - (sigma(u) - sigma(t)), G >= 0 at min(u, 0), < 0 at l
+    case2_lo = _dsig(l) < chord
+    a = l.clone()
+    b = torch.clamp(u, max=0.0)
+    for _ in range(iters):
+        m = 0.5 * (a + b)
+        G = _dsig(m) * (u - m) - (su - _sig(m))
+        b = torch.where(G >= 0, m, b)
+        a = torch.where(G >= 0, a, m)
+    t_lo = torch.where(u <= 0, u, torch.where(case2_lo, 0.5 * (a + b), l))
+    return t_up, t_lo
+
+
+def sigmoid_upper(x, l, u, t_up):
+    """phi(x): the line from (l, sigma(l)) to (t_up, sigma(t_up)) on [l, t_up], sigma
+    beyond (Case 1 is t_up = u: the chord)."""
+    st = _sig(t_up)
+    slope = torch.where(t_up > l, (st - _sig(l)) / torch.where(t_up > l, t_up - l, torch.ones_like(l)), _dsig(l))
+    return torch.where(x <= t_up, _sig(l) + slope * (x - l), _sig(x))
+
+
+def sigmoid_lower(x, l, u, t_lo):
+    """psi(x): sigma on [l, t_lo], then the line from (t_lo, sigma(t_lo)) to (u, sigma(u))."""
+    st = _sig(t_lo)
+    slope = torch.where(u > t_lo, (_sig(u) - st) / torch.where(u > t_lo, u - t_lo, torch.ones_like(u)), _dsig(u))
+    return torch.where(x >= t_lo, st + slope * (x - t_lo), _sig(x))
+
+
+def inner_min_sigmoid(rho, g, l, u, t_up, t_lo):
+    """Per-neuron minimum of rho*xB - g*x over the sigmoid's hull on [l, u]
+    (eq:siglinopt): x takes the upper envelope where g > 0 and the lower where g < 0
+    (g = 0: x = sigma(xB)); the minimum over xB is taken among the interval's ends,
+    the tangent point and the stationary points sigma^{-1}((1 +- sqrt(1 - 4 rho/g))/2)
+    of the piece where x = sigma(xB) (eq:with_sig_subp).  Ties go to the larger xB.
+    Returns (xB*, x*, value)."""
+    up = g > 0
+    env = lambda x: torch.where(up, sigmoid_upper(x, l, u, t_up), sigmoid_lower(x, l, u, t_lo))  # noqa: E731
+    cands = [l, u, torch.where(up, t_up, t_lo)]
+    ratio = torch.where(g != 0, rho / torch.where(g != 0, g, torch.ones_like(g)), torch.zeros_like(g))
+    disc = 1.0 - 4.0 * ratio
+    ok = (g != 0) & (disc >= 0)
+    sq = torch.sqrt(torch.clamp(disc, min=0.0))
+    for sgn in (1.0, -1.0):
+        p = 0.5 * (1.0 + sgn * sq)
+        inside = ok & (p > 0) & (p < 1)
+        r = _logit(torch.where(inside, p, torch.full_like(p, 0.5)))
+        # the stationary point counts only on the piece where x = sigma(xB)
+        on_curve = torch.where(up, r >= t_up, r <= t_lo)
+        r = torch.where(inside & on_curve & (r >= l) & (r <= u), r, l)
+        cands.append(r)
+    best_x = None
+    best_v = None
+    for c in cands:
+        v = rho * c - g * env(c)
+        if best_v is None:
+            best_x, best_v = c, v
+        else:
+            take = (v < best_v) | ((v == best_v) & (c > best_x))
+            best_x = torch.where(take, c, best_x)
+            best_v = torch.where(take, v, best_v)
+    x = torch.where(g == 0, _sig(best_x), env(best_x))
+    return best_x, x, best_v
