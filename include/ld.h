@@ -304,6 +304,28 @@ int ld_profile_iteration(const ld_net* net, const ld_batch* batch, ld_state* st,
                          hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* sigmoid activations: the P_k inner minimisation over the hull (App. E)    */
+/* ------------------------------------------------------------------------- */
+/* Tangent points of the convex hull of sigma(x) = 1/(1 + e^-x) on [l, u], per
+ * element (App. E.1): t_up, where the upper envelope leaves the line from
+ * (l, sigma(l)) for sigma itself (t_up = u: the chord, Case 1; t_up = l when
+ * l >= 0), and t_lo, where the lower envelope leaves sigma for the line to
+ * (u, sigma(u)) (t_lo = l: the chord; t_lo = u when u <= 0).  Bisection on the
+ * tangency condition in FP64.  They depend on the bounds only: compute them once
+ * per problem.  All arrays are device arrays of `count` elements, l <= u. */
+int ld_sigmoid_hull(long long count, const float* l, const float* u, float* t_up, float* t_lo,
+                    hipStream_t stream);
+/* Per element, the minimum of rho*xB - g*x over the hull (eq:siglinopt): xB* (xb),
+ * x* on the envelope g selects (upper for g > 0, lower for g < 0; sigma(xB*) for
+ * g = 0) and the value (FP64, val), from the ends, the tangent point and the logit
+ * roots of eq:with_sig_subp; ties go to the larger xB.  Inputs as in P_k: rho the
+ * layer's dual, g = (W_{k+1}^T rho_{k+1}), the bounds and the tangent points of
+ * ld_sigmoid_hull.  FP64 arithmetic. */
+int ld_sigmoid_inner_min(long long count, const float* rho, const float* g, const float* l, const float* u,
+                         const float* t_up, const float* t_lo, float* xb, float* x, double* val,
+                         hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
 /* branching: Filtered Smart Branching (Sec. 4.2)                             */
 /* ------------------------------------------------------------------------- */
 /* For every subdomain of `batch`, the ReLU split FSB picks:

@@ -5,5 +5,5 @@ Python binding of the C ABI in include/ld.h: ``Net``, ``Batch``, ``State``,
 library directly; ``LDDual`` wraps ``dual_eval`` as a torch.autograd.Function.
 """
 from .binding import (Batch, LDDual, LDError, Net, State, TAU_DEFAULT, dual_eval, final_bound,  # noqa: F401
-                      branch_children, fsb_branch, init_duals, intermediate_bounds, ld_dual, load_library, profile_iteration, prox_profile_iteration, prox_step, set_validation, step,
+                      branch_children, fsb_branch, init_duals, intermediate_bounds, ld_dual, load_library, profile_iteration, prox_profile_iteration, prox_step, sigmoid_hull, sigmoid_inner_min, set_validation, step,
                       autotune, tuning_info, tile_candidates, set_tuned_config)

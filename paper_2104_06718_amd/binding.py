@@ -32,7 +32,7 @@ EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num
             "ld_state_get_rho", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
-            "ld_intermediate_bounds", "ld_fsb_branch", "ld_branch_children", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
+            "ld_intermediate_bounds", "ld_fsb_branch", "ld_branch_children", "ld_sigmoid_hull", "ld_sigmoid_inner_min", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
 
 
 class LDError(RuntimeError):
@@ -116,6 +116,8 @@ def load_library(path: Optional[str] = None):
     lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
     lib.ld_intermediate_bounds.argtypes = [V, P(ld_batch), P(ld_opts), I, V, V, V]
     lib.ld_fsb_branch.argtypes = [V, P(ld_batch), V, V, V, V, V]
+    lib.ld_sigmoid_hull.argtypes = [ctypes.c_longlong, V, V, V, V, V]
+    lib.ld_sigmoid_inner_min.argtypes = [ctypes.c_longlong, V, V, V, V, V, V, V, V, V, V]
     lib.ld_branch_children.argtypes = [V, P(ld_batch), V, V, P(V), V, V, P(V), P(V), V, P(V), V]
     lib.ld_prox_step.argtypes = [V, P(ld_batch), V, P(ld_prox_opts), V]
     lib.ld_prox_get_step.argtypes = [V, P(I)]
@@ -294,6 +296,30 @@ def step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional
          tau: float = TAU_DEFAULT, engine="auto", stream=None):
     o = _opts(iters, total_iters, lr0, lr_end, beta1, beta2, eps, precision, init, tau, engine)
     _check(net.lib.ld_step(net.handle, ctypes.byref(batch.struct), state.handle, ctypes.byref(o), _stream(stream)))
+
+
+def sigmoid_hull(l: torch.Tensor, u: torch.Tensor, stream=None):
+    """Tangent points (t_up, t_lo) of the sigmoid's hull on [l, u] (ld_sigmoid_hull)."""
+    l, u = _dev_f32(l, "l"), _dev_f32(u, "u")
+    if l.shape != u.shape:
+        raise ValueError("l and u differ in shape")
+    tu, tl = torch.empty_like(l), torch.empty_like(l)
+    _check(load_library().ld_sigmoid_hull(l.numel(), l.data_ptr(), u.data_ptr(), tu.data_ptr(), tl.data_ptr(),
+                                          _stream(stream)))
+    return tu, tl
+
+
+def sigmoid_inner_min(rho, g, l, u, t_up, t_lo, stream=None):
+    """(xB*, x*, value) of the sigmoid P_k inner minimisation (ld_sigmoid_inner_min)."""
+    a = [_dev_f32(t, name) for t, name in ((rho, "rho"), (g, "g"), (l, "l"), (u, "u"), (t_up, "t_up"),
+                                           (t_lo, "t_lo"))]
+    if any(t.shape != a[0].shape for t in a):
+        raise ValueError("operands differ in shape")
+    xb, x = torch.empty_like(a[0]), torch.empty_like(a[0])
+    val = torch.empty(a[0].shape, device="cuda", dtype=torch.float64)
+    _check(load_library().ld_sigmoid_inner_min(a[0].numel(), *[t.data_ptr() for t in a], xb.data_ptr(), x.data_ptr(),
+                                               val.data_ptr(), _stream(stream)))
+    return xb, x, val
 
 
 def fsb_branch(net: Net, batch: Batch, candidates=False, stream=None):

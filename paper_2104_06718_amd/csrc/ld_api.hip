@@ -2292,6 +2292,28 @@ int ld_branch_children(const ld_net* net, const ld_batch* bt, const int* layer, 
   return LD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// sigmoid activations (App. E)
+// ---------------------------------------------------------------------------
+int ld_sigmoid_hull(long long count, const float* l, const float* u, float* t_up, float* t_lo, hipStream_t s) {
+  g_err.clear();
+  if (count < 0) return fail(LD_E_ARG, "count < 0");
+  if (count == 0) return LD_OK;
+  if (!l || !u || !t_up || !t_lo) return fail(LD_E_ARG, "NULL argument");
+  LD_HIP(launch_sigmoid_hull(count, l, u, t_up, t_lo, s));
+  return LD_OK;
+}
+
+int ld_sigmoid_inner_min(long long count, const float* rho, const float* g, const float* l, const float* u,
+                         const float* t_up, const float* t_lo, float* xb, float* x, double* val, hipStream_t s) {
+  g_err.clear();
+  if (count < 0) return fail(LD_E_ARG, "count < 0");
+  if (count == 0) return LD_OK;
+  if (!rho || !g || !l || !u || !t_up || !t_lo || !xb || !x || !val) return fail(LD_E_ARG, "NULL argument");
+  LD_HIP(launch_sigmoid_inner_min(count, rho, g, l, u, t_up, t_lo, xb, x, val, s));
+  return LD_OK;
+}
+
 int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
   g_err.clear();
   LD_TRY(check_step_args(net, bt, st, o));

@@ -268,6 +268,12 @@ struct IntermPack {
   float* c;
 };
 hipError_t launch_interm_expand(const IntermPack& K, int C, long long start, int P, int nj, hipStream_t s);
+// sigmoid activations (ld_sigmoid.hip): hull tangent points, inner minimisation
+hipError_t launch_sigmoid_hull(long long n, const float* l, const float* u, float* t_up, float* t_lo, hipStream_t s);
+hipError_t launch_sigmoid_inner_min(long long n, const float* rho, const float* g, const float* l, const float* u,
+                                    const float* t_up, const float* t_lo, float* xb, float* x, double* val,
+                                    hipStream_t s);
+
 // branching (ld_fsb.hip); at most kFsbMaxHidden hidden layers
 constexpr int kFsbMaxHidden = 16;
 hipError_t launch_fsb_scores(int B, int n_hidden, const float* const* lam, const float* const* lo,
