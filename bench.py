@@ -48,9 +48,10 @@ def parse():
                          "iterations launched without the graph; prints the per-launch averages")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--engine", choices=["auto", "layerwise", "resident"], default="auto")
-    ap.add_argument("--solver", choices=["ld", "prox", "interm", "fsb"], default="ld",
+    ap.add_argument("--solver", choices=["ld", "prox", "interm", "fsb", "sigmoid"], default="ld",
                     help="ld: Adam supergradient ascent (the headline line); prox: the proximal solver; "
-                         "interm: LD intermediate bounds of one layer; fsb: branching decisions")
+                         "interm: LD intermediate bounds of one layer; fsb: branching decisions; "
+                         "sigmoid: the sigmoid inner minimisation")
     ap.add_argument("--layer", type=int, default=2, help="interm: layer j whose pre-activations are bounded")
     return ap.parse_args()
 
@@ -459,6 +460,66 @@ def main_fsb(a, P, inst, net, batch):
     print(json.dumps(out), flush=True)
 
 
+def main_sigmoid(a, P, inst):
+    """The sigmoid P_k inner minimisation (App. E) over every hidden neuron of the
+    batch (B x N_h elements, the wide net's shapes): the hull's tangent points once,
+    then the minimisation, each timed with HIP events on the launch stream."""
+    import numpy as np
+    import torch
+    B = inst.B
+    l = torch.cat([torch.from_numpy(x) for x in inst.l], dim=1).contiguous().cuda()
+    u = torch.cat([torch.from_numpy(x) for x in inst.u], dim=1).contiguous().cuda()
+    n = l.numel()
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    rho = (torch.randn(l.shape, generator=gen, device="cuda") * 0.05).contiguous()
+    g = (torch.randn(l.shape, generator=gen, device="cuda") * 0.5).contiguous()
+    s = torch.cuda.current_stream()
+
+    def timed(f, reps):
+        for _ in range(max(a.warmup, 1)):
+            out = f()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            out = f()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return out, 1000.0 * e0.elapsed_time(e1) / reps
+    (tu, tl), us_hull = timed(lambda: P.sigmoid_hull(l, u), a.reps)
+    (xb, x, val), us_min = timed(lambda: P.sigmoid_inner_min(rho, g, l, u, tu, tl), a.reps)
+    nbytes = n * (6 * 4 + 2 * 4 + 8)   # read rho, g, l, u, t_up, t_lo; write xB, x (FP32), value (FP64)
+    roof = dict(bound="hbm", achieved=nbytes / (us_min * 1e-6) / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof.update(traffic=None, kernel="sigmoid_inner_min_kernel", avg_us=us_min, algorithmic_bytes=nbytes,
+                algorithmic_flops=None)
+    out = {
+        "metric": f"sigmoid inner minimisations/sec ({n} neurons: B={B} x N_h of the {a.config} net)",
+        "value": n / (us_min * 1e-6),
+        "unit": "neurons/s",
+        "n_gpus": 1, "steps": a.reps, "warmup": a.warmup, "ms_per_step": us_min / 1000.0,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{a.config} net bounds, B={B}: {n} sigmoid neurons, rho ~ N(0, 0.05^2), "
+                               f"g ~ N(0, 0.5^2)", "neurons": n},
+        "hull_us": us_hull,
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        from oracle import ld_oracle as O
+        m = min(n, 400000)
+        D = lambda t: t.reshape(-1)[:m].double().cpu()  # noqa: E731
+        t0 = time.perf_counter()
+        otu, otl = O.sigmoid_hull(D(l), D(u))
+        ob = O.inner_min_sigmoid(D(rho), D(g), D(l), D(u), otu, otl)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=m / dt, unit="neurons/s", cores=torch.get_num_threads(), kind="oracle",
+                                   sample=f"{m} of {n} neurons (hull and minimisation), FP64 torch-CPU oracle, "
+                                          f"{dt:.1f} s")
+        out["minus_oracle_max_abs"] = (val.reshape(-1)[:m].cpu() - ob[2]).abs().max().item()
+    print(json.dumps(out), flush=True)
+
+
 def src_hash():
     """Hash of the HIP sources (a stored counter measurement is valid for this build only)."""
     h = hashlib.sha256()
@@ -511,6 +572,9 @@ def main():
         return
     if a.solver == "fsb":
         main_fsb(a, P, inst, net, batch)
+        return
+    if a.solver == "sigmoid":
+        main_sigmoid(a, P, inst)
         return
 
     if a.profile_only:

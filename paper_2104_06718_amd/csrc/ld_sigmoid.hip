@@ -24,7 +24,8 @@ __device__ __forceinline__ double dsgm(double x) {
   return s * (1.0 - s);
 }
 
-constexpr int kHullBisect = 64;  // halvings of an interval of width <= u - l
+// halvings of the bracket (width <= u - l <= 2^5 in practice): far below FP32 spacing
+constexpr int kHullBisect = 44;
 
 __global__ __launch_bounds__(256) void sigmoid_hull_kernel(long long n, const float* __restrict__ lo,
                                                            const float* __restrict__ hi, float* __restrict__ t_up,
@@ -41,7 +42,8 @@ __global__ __launch_bounds__(256) void sigmoid_hull_kernel(long long n, const fl
       double a = 0.0, b = u;
       for (int it = 0; it < kHullBisect; ++it) {
         const double m = 0.5 * (a + b);
-        if (dsgm(m) * (m - l) - (sgm(m) - sl) >= 0.0)
+        const double sm = sgm(m);
+        if (sm * (1.0 - sm) * (m - l) - (sm - sl) >= 0.0)
           a = m;
         else
           b = m;
@@ -55,7 +57,8 @@ __global__ __launch_bounds__(256) void sigmoid_hull_kernel(long long n, const fl
       double a = l, b = 0.0;
       for (int it = 0; it < kHullBisect; ++it) {
         const double m = 0.5 * (a + b);
-        if (dsgm(m) * (u - m) - (su - sgm(m)) >= 0.0)
+        const double sm = sgm(m);
+        if (sm * (1.0 - sm) * (u - m) - (su - sm) >= 0.0)
           b = m;
         else
           a = m;
@@ -67,17 +70,17 @@ __global__ __launch_bounds__(256) void sigmoid_hull_kernel(long long n, const fl
   }
 }
 
-// the envelope that x takes: upper (g > 0) or lower
-__device__ __forceinline__ double sig_env(double x, double l, double u, double t, bool up) {
-  if (up) {
-    if (x > t) return sgm(x);
-    const double slope = t > l ? (sgm(t) - sgm(l)) / (t - l) : dsgm(l);
-    return sgm(l) + slope * (x - l);
+// The envelope x takes (upper for g > 0, lower otherwise) as a line on its linear
+// piece and sigma on the other: the line through (x0, s0) with slope k holds for
+// x <= t (upper) or x >= t (lower).
+struct SigEnv {
+  bool up;
+  double t, x0, s0, k;
+  __device__ double at(double x) const {
+    const bool on_line = up ? x <= t : x >= t;
+    return on_line ? s0 + k * (x - x0) : sgm(x);
   }
-  if (x < t) return sgm(x);
-  const double slope = u > t ? (sgm(u) - sgm(t)) / (u - t) : dsgm(u);
-  return sgm(t) + slope * (x - t);
-}
+};
 
 __global__ __launch_bounds__(256) void sigmoid_inner_min_kernel(long long n, const float* __restrict__ rho_,
                                                                 const float* __restrict__ g_,
@@ -89,13 +92,31 @@ __global__ __launch_bounds__(256) void sigmoid_inner_min_kernel(long long n, con
                                                                 double* __restrict__ val_out) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const double rho = rho_[i], g = g_[i], l = lo[i], u = hi[i];
-    const bool up = g > 0.0;
-    const double t = up ? (double)t_up[i] : (double)t_lo[i];
-    double cand[5];
+    SigEnv E;
+    E.up = g > 0.0;
+    E.t = E.up ? (double)t_up[i] : (double)t_lo[i];
+    // the line: from (l, sigma(l)) to (t, sigma(t)) above, from (t, sigma(t)) to (u, sigma(u)) below
+    const double st = sgm(E.t);
+    if (E.up) {
+      const double sl = sgm(l);
+      E.x0 = l;
+      E.s0 = sl;
+      E.k = E.t > l ? (st - sl) / (E.t - l) : sl * (1.0 - sl);
+    } else {
+      const double su = sgm(u);
+      E.x0 = E.t;
+      E.s0 = st;
+      E.k = u > E.t ? (su - st) / (u - E.t) : su * (1.0 - su);
+    }
+    // candidates and their envelope values (a logit root r has sigma(r) = p)
+    double cx[5], cs[5];
     int nc = 0;
-    cand[nc++] = l;
-    cand[nc++] = u;
-    cand[nc++] = t;
+    cx[nc] = l;
+    cs[nc++] = E.at(l);
+    cx[nc] = u;
+    cs[nc++] = E.at(u);
+    cx[nc] = E.t;
+    cs[nc++] = E.at(E.t);
     if (g != 0.0) {
       const double disc = 1.0 - 4.0 * (rho / g);
       if (disc >= 0.0) {
@@ -104,21 +125,25 @@ __global__ __launch_bounds__(256) void sigmoid_inner_min_kernel(long long n, con
           const double p = 0.5 * (1.0 + (s == 0 ? sq : -sq));
           if (!(p > 0.0 && p < 1.0)) continue;
           const double r = log(p / (1.0 - p));
-          const bool on_curve = up ? r >= t : r <= t;
-          if (on_curve && r >= l && r <= u) cand[nc++] = r;
+          const bool on_curve = E.up ? r >= E.t : r <= E.t;
+          if (on_curve && r >= l && r <= u) {
+            cx[nc] = r;
+            cs[nc++] = p;
+          }
         }
       }
     }
-    double bx = cand[0], bv = rho * cand[0] - g * sig_env(cand[0], l, u, t, up);
+    double bx = cx[0], bs = cs[0], bv = rho * cx[0] - g * cs[0];
     for (int c = 1; c < nc; ++c) {
-      const double v = rho * cand[c] - g * sig_env(cand[c], l, u, t, up);
-      if (v < bv || (v == bv && cand[c] > bx)) {
+      const double v = rho * cx[c] - g * cs[c];
+      if (v < bv || (v == bv && cx[c] > bx)) {
         bv = v;
-        bx = cand[c];
+        bx = cx[c];
+        bs = cs[c];
       }
     }
     xb_out[i] = (float)bx;
-    x_out[i] = (float)(g == 0.0 ? sgm(bx) : sig_env(bx, l, u, t, up));
+    x_out[i] = (float)(g == 0.0 ? sgm(bx) : bs);
     val_out[i] = bv;
   }
 }
