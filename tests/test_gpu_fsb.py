@@ -123,3 +123,22 @@ def test_children_and_warm_start(name, B):
     ev = O.dual_eval(onet, ob, orho, need_supergrad=False)
     tol = PT.q_tol(onet, ob, orho, ev).repeat_interleave(2)
     assert bool((qc.cpu() >= qp.cpu().repeat_interleave(2) - 2 * tol).all())
+
+
+def test_deep_net_branching_matches_the_oracle():
+    """Five hidden layers (3x3 stride-1 and 4x4 stride-2 convs), two properties."""
+    _case("fsb deep props=[2, 2]")
+    P, inst, net, batch = _setup("deep", props=[2, 2])
+    layer, index, value = P.fsb_branch(net, batch)
+    torch.cuda.synchronize()
+    onet = O.net_from_specs(inst.layers)
+    ob = O.batch_from_instance(inst)
+    olayer, oindex, ovalue = O.fsb_branch(onet, ob)
+    scale = 1e-5 * (1 + ovalue.abs())
+    assert bool(((value.cpu() - ovalue).abs() <= scale).all()), (value, ovalue)
+    same = (layer.cpu().long() == olayer) & (index.cpu().long() == oindex)
+    print(f"  splits equal to the oracle's: {int(same.sum())} of {inst.B}")
+    for b in torch.nonzero(~same).flatten().tolist():
+        k, i = int(layer[b]), int(index[b])
+        v = min(O.propagation_bound(onet, O.split_child(ob, b, k, i, h)).item() for h in (True, False))
+        assert abs(v - ovalue[b].item()) <= scale[b].item()

@@ -134,3 +134,23 @@ def test_bad_options_are_rejected():
         with pytest.raises(LDError):
             P.prox_step(net, batch, st, iters=1, total_iters=5, **kw)
     assert st.prox_step_count() == 0
+
+
+def test_deep_net_first_iterations_follow_the_oracle():
+    """Five hidden layers with 3x3 stride-1 and 4x4 stride-2 convs (two properties)."""
+    _case("prox first iterations deep props=[2, 2]")
+    P, inst, net, batch = _setup("deep", props=[2, 2])
+    onet = O.net_from_specs(inst.layers)
+    ob = O.batch_from_instance(inst)
+    st = P.State(net, inst.B)
+    P.prox_step(net, batch, st, iters=2, total_iters=20)
+    rg = st.get_rho()
+    torch.cuda.synchronize()
+    ost = O.proximal(onet, ob, O.ProxOpts(T=20), iters=2)
+    tot = bad = 0
+    for k in range(len(rg)):
+        diff = (rg[k].cpu().double() - ost["rho"][k]).abs()
+        bad += int((diff > 1e-4 * (ost["rho"][k].abs() + 1e-2)).sum())
+        tot += diff.numel()
+    print(f"  duals differing beyond 1e-4 relative: {bad} of {tot}")
+    assert bad <= 0.02 * tot
