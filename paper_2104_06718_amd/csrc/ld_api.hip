@@ -2030,10 +2030,11 @@ int ld_prox_get_step(const ld_state* st, int* t) {
 int ld_intermediate_bounds(const ld_net* sub, const ld_batch* bt, const ld_opts* o, int max_problems, float* lo,
                            float* hi, hipStream_t s) {
   g_err.clear();
-  if (!sub || !bt || !o || !lo || !hi) return fail(LD_E_ARG, "NULL argument");
+  if (!sub || !bt || !o) return fail(LD_E_ARG, "NULL argument");
   const int n = sub->n, B = bt->B;
   if (B < 0) return fail(LD_E_ARG, "batch size B < 0");
   if (B == 0) return LD_OK;
+  if (!lo || !hi) return fail(LD_E_ARG, "NULL output");
   if (!bt->l0 || !bt->u0 || !bt->l || !bt->u) return fail(LD_E_ARG, "batch l0/u0/l/u is NULL");
   for (int k = 1; k <= n - 1; ++k)
     if (!bt->l[k - 1] || !bt->u[k - 1]) return fail(LD_E_ARG, "batch l[k]/u[k] is NULL for k=" + std::to_string(k));
@@ -2120,9 +2121,9 @@ int ld_fsb_branch(const ld_net* net, const ld_batch* bt, int* layer, int* index,
                   hipStream_t s) {
   g_err.clear();
   LD_TRY(check_batch(net, bt));
-  if (!layer || !index || !value) return fail(LD_E_ARG, "NULL output");
   const int n = net->n, B = bt->B, nh = n - 1;
   if (B == 0) return LD_OK;
+  if (!layer || !index || !value) return fail(LD_E_ARG, "NULL output");
   if (nh > 16) return fail(LD_E_UNSUPPORTED, "more than 16 hidden layers");
   const int M = 4 * nh;  // children per subdomain: 2 candidates x 2 phases per hidden layer
   const long long Bc = (long long)B * M;
@@ -2253,6 +2254,7 @@ int ld_branch_children(const ld_net* net, const ld_batch* bt, const int* layer, 
   g_err.clear();
   LD_TRY(check_batch(net, bt));
   const int n = net->n, B = bt->B, nh = n - 1;
+  if (B == 0) return LD_OK;
   if (!layer || !index || !l0_out || !u0_out || !l_out || !u_out || !c_out) return fail(LD_E_ARG, "NULL argument");
   if ((rho == nullptr) != (rho_out == nullptr)) return fail(LD_E_ARG, "rho and rho_out must both be given or both NULL");
   if (nh > kFsbMaxHidden) return fail(LD_E_UNSUPPORTED, "more than 16 hidden layers");
@@ -2260,7 +2262,6 @@ int ld_branch_children(const ld_net* net, const ld_batch* bt, const int* layer, 
     if (!l_out[k] || !u_out[k]) return fail(LD_E_ARG, "l_out[k]/u_out[k] is NULL");
     if (rho && (!rho[k] || !rho_out[k])) return fail(LD_E_ARG, "rho[k]/rho_out[k] is NULL");
   }
-  if (B == 0) return LD_OK;
   IntermPack K;
   std::memset(&K, 0, sizeof(K));
   std::vector<std::pair<const float*, float*>> arr = {{bt->l0, l0_out}, {bt->u0, u0_out}};

@@ -57,7 +57,9 @@ __device__ __forceinline__ float f4at(const float4& v, int q) { return q == 0 ? 
 
 // Elements of a row that thread `tid` owns: where the row's width is a multiple
 // of 4, the 16-byte groups i = 4*tid + 4*kProxThreads*j, else the single
-// elements i = tid + kProxThreads*j.
+// elements i = tid + kProxThreads*j.  The first group's iterate and conditional
+// gradient stay in registers between the two passes (a whole row of up to
+// 4*kProxThreads elements is then read once).
 __global__ __launch_bounds__(kProxThreads) void prox_block_kernel(ProxBlockArgs P) {
   const int b = blockIdx.x, tid = threadIdx.x;
   const size_t ob = (size_t)b * P.nB, oa = (size_t)b * P.nA;
@@ -65,9 +67,15 @@ __global__ __launch_bounds__(kProxThreads) void prox_block_kernel(ProxBlockArgs 
   // 1. directional derivative and curvature of the augmented Lagrangian along the
   //    segment from the iterate to the conditional gradient
   double num = 0.0, den = 0.0;
+  const int i0 = 4 * tid;
+  float4 cxB = make_float4(0.f, 0.f, 0.f, 0.f), czB = cxB, cxA = cxB, czA = cxB;
   if (vB) {
-    for (int i = 4 * tid; i < P.nB; i += 4 * kProxThreads) {
+    for (int i = i0; i < P.nB; i += 4 * kProxThreads) {
       const float4 x = ld4f(P.xB + ob + i), z = ld4f(P.zB + ob + i), r = ld4f(P.rtB + ob + i);
+      if (i == i0) {
+        cxB = x;
+        czB = z;
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const double d = (double)f4at(x, q) - (double)f4at(z, q);
@@ -87,8 +95,12 @@ __global__ __launch_bounds__(kProxThreads) void prox_block_kernel(ProxBlockArgs 
   const double sgn = P.last ? 1.0 : -1.0;
   const double curv = P.last ? 0.0 : 1.0;
   if (vA) {
-    for (int i = 4 * tid; i < P.nA; i += 4 * kProxThreads) {
+    for (int i = i0; i < P.nA; i += 4 * kProxThreads) {
       const float4 x = ld4f(P.xA + oa + i), z = ld4f(P.zA + oa + i), r = ld4f(cA + oa + i);
+      if (i == i0) {
+        cxA = x;
+        czA = z;
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const double e = (double)f4at(x, q) - (double)f4at(z, q);
@@ -113,8 +125,8 @@ __global__ __launch_bounds__(kProxThreads) void prox_block_kernel(ProxBlockArgs 
   //    sweep of an outer iteration xB_k and xA_k are final here, so layer k's dual
   //    update (eq:momentum_updates) follows, and rt_k is formed for the next eta
   if (vB) {
-    for (int i = 4 * tid; i < P.nB; i += 4 * kProxThreads) {
-      const float4 x = ld4f(P.xB + ob + i), z = ld4f(P.zB + ob + i);
+    for (int i = i0; i < P.nB; i += 4 * kProxThreads) {
+      const float4 x = i == i0 ? cxB : ld4f(P.xB + ob + i), z = i == i0 ? czB : ld4f(P.zB + ob + i);
       const float4 r = ld4f(P.rhoB + ob + i), a = ld4f(P.xAB + ob + i);
       float xn[4], rn[4];
 #pragma unroll
@@ -157,8 +169,8 @@ __global__ __launch_bounds__(kProxThreads) void prox_block_kernel(ProxBlockArgs 
   }
   // 3. Frank-Wolfe step on xA_{k+1}; rt_{k+1}; conditional gradient of block k+1
   if (vA) {
-    for (int i = 4 * tid; i < P.nA; i += 4 * kProxThreads) {
-      const float4 x = ld4f(P.xA + oa + i), z = ld4f(P.zA + oa + i);
+    for (int i = i0; i < P.nA; i += 4 * kProxThreads) {
+      const float4 x = i == i0 ? cxA : ld4f(P.xA + oa + i), z = i == i0 ? czA : ld4f(P.zA + oa + i);
       float xn[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) xn[q] = f4at(x, q) + g * (f4at(z, q) - f4at(x, q));

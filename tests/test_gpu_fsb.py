@@ -142,3 +142,16 @@ def test_deep_net_branching_matches_the_oracle():
         k, i = int(layer[b]), int(index[b])
         v = min(O.propagation_bound(onet, O.split_child(ob, b, k, i, h)).item() for h in (True, False))
         assert abs(v - ovalue[b].item()) <= scale[b].item()
+
+
+def test_empty_batch_is_a_no_op():
+    _case("fsb and children B=0")
+    import paper_2104_06718_amd as P
+    inst = ldgen.make_instance("tiny_conv")
+    net = P.Net(inst.layers)
+    z = lambda w: torch.zeros((0, w), device="cuda")  # noqa: E731
+    batch = P.Batch(z(72), z(72), [z(27), z(36), z(8)], [z(27), z(36), z(8)], z(3))
+    layer, index, value = P.fsb_branch(net, batch)
+    assert layer.numel() == 0
+    kids = P.branch_children(net, batch, layer, index)
+    assert kids.B == 0

@@ -94,3 +94,14 @@ def test_given_init_is_rejected():
     from paper_2104_06718_amd.binding import LDError
     with pytest.raises(LDError):
         P.intermediate_bounds(sub, batch, iters=5, init="given")
+
+
+def test_empty_batch_is_a_no_op():
+    _case("intermediate bounds B=0")
+    import paper_2104_06718_amd as P
+    inst = ldgen.make_instance("tiny_conv")
+    sub = P.Net(inst.layers[:2])
+    z = lambda w: torch.zeros((0, w), device="cuda")  # noqa: E731
+    batch = P.Batch(z(72), z(72), [z(27)], [z(27)], z(36))
+    lo, hi = P.intermediate_bounds(sub, batch, iters=5)
+    assert lo.shape == (0, 36) and hi.shape == (0, 36)
