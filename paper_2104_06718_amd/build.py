@@ -31,7 +31,22 @@ def build(verbose: bool = False) -> str:
     if verbose and errs.strip():
         print(errs, file=sys.stderr)
     os.replace(tmp, LIB_PATH)
+    build_abi_program(hipcc)
     return LIB_PATH
+
+
+# A host program that calls the library through include/ld.h only (tests/c).
+ABI_PROGRAM_SRC = os.path.join(ROOT, "tests", "c", "ld_abi_run.cpp")
+ABI_PROGRAM = os.path.join(ROOT, "tests", "c", "ld_abi_run")
+
+
+def build_abi_program(hipcc: str) -> str:
+    cmd = [hipcc, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), ABI_PROGRAM_SRC,
+           "-L", HERE, "-lld_mi355x", "-Wl,-rpath,$ORIGIN/../../paper_2104_06718_amd", "-o", ABI_PROGRAM]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc (C ABI program) failed ({res.returncode}):\n{res.stderr}")
+    return ABI_PROGRAM
 
 
 if __name__ == "__main__":
