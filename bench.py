@@ -446,7 +446,7 @@ def main_fsb(a, P, inst, net, batch):
     }
     if not a.no_cpu_baseline:
         from oracle import ld_oracle as O
-        idx = list(range(min(B, 16)))
+        idx = list(range(min(B, 256)))
         onet = O.net_from_specs(inst.layers)
         ob = O.batch_from_instance(inst, idx)
         t0 = time.perf_counter()
@@ -507,7 +507,7 @@ def main_sigmoid(a, P, inst):
     }
     if not a.no_cpu_baseline:
         from oracle import ld_oracle as O
-        m = min(n, 400000)
+        m = n
         D = lambda t: t.reshape(-1)[:m].double().cpu()  # noqa: E731
         t0 = time.perf_counter()
         otu, otl = O.sigmoid_hull(D(l), D(u))

@@ -351,7 +351,8 @@ int ld_fsb_branch(const ld_net* net, const ld_batch* batch, int* layer, int* ind
 
 /* The children of every subdomain for its split (layer[b], index[b]), as
  * ld_fsb_branch returns it: child 2b has the ReLU fixed active (l := 0), child
- * 2b+1 inactive (u := 0); a subdomain with index < 0 is copied into both.  The
+ * 2b+1 inactive (u := 0); a subdomain whose (layer, index) is out of range
+ * (index < 0, layer outside 1..n-1, index >= n_layer) is copied into both.  The
  * outputs are caller-owned device arrays for 2B subdomains: l0_out, u0_out
  * [2B, n_0], l_out[k], u_out[k] [2B, n_k] (host arrays of n-1 device pointers),
  * c_out [2B, n_out].  rho / rho_out (both or neither): the parents' duals [B, n_k]

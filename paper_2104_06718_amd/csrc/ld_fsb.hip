@@ -117,12 +117,14 @@ struct ChildArgs {
   float* lo[kFsbMaxHidden];
   float* hi[kFsbMaxHidden];
   int width[kFsbMaxHidden];
+  int nh;
   const int* layer;
   const int* index;
 };
 
 // One block per child: child 2b (active: l := 0) and 2b+1 (inactive: u := 0) of
-// subdomain b, split on ReLU index[b] of hidden layer layer[b] (no split if < 0).
+// subdomain b, split on ReLU index[b] of hidden layer layer[b] (no split if the
+// pair is out of range, e.g. index -1).
 __global__ __launch_bounds__(256) void branch_children_kernel(ChildArgs A) {
   const size_t g = blockIdx.x;
   const size_t b = g / 2;
@@ -134,8 +136,9 @@ __global__ __launch_bounds__(256) void branch_children_kernel(ChildArgs A) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    // a split outside the network's hidden layers or widths leaves both children unsplit
     const int k = A.layer[b], i = A.index[b];
-    if (i >= 0 && k >= 1) {
+    if (k >= 1 && k <= A.nh && i >= 0 && i < A.width[k - 1]) {
       float* dst = (g & 1) ? A.hi[k - 1] : A.lo[k - 1];
       dst[g * A.width[k - 1] + i] = 0.f;
     }
@@ -149,6 +152,7 @@ hipError_t launch_branch_children(const IntermPack& K, int B, int n_hidden, cons
     return hipErrorInvalidValue;
   ChildArgs A;
   A.K = K;
+  A.nh = n_hidden;
   A.layer = layer;
   A.index = index;
   for (int k = 0; k < n_hidden; ++k) {

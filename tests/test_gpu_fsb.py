@@ -155,3 +155,15 @@ def test_empty_batch_is_a_no_op():
     assert layer.numel() == 0
     kids = P.branch_children(net, batch, layer, index)
     assert kids.B == 0
+
+
+def test_children_of_out_of_range_splits_are_unsplit():
+    _case("children with out-of-range splits")
+    P, inst, net, batch = _setup("tiny_conv")
+    B = inst.B
+    layer = torch.tensor([0, 5, 2, 1][:B], dtype=torch.int32)
+    index = torch.tensor([3, 0, 10 ** 6, -1][:B], dtype=torch.int32)
+    kids = P.branch_children(net, batch, layer, index)
+    torch.cuda.synchronize()
+    for a, p in zip(kids.l + kids.u, batch.l + batch.u):
+        assert torch.equal(a, p.repeat_interleave(2, dim=0))
