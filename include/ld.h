@@ -344,8 +344,10 @@ int ld_sigmoid_inner_min(long long count, const float* rho, const float* g, cons
  * order, -1 if none), value[b] (that worse child's bound, -inf if none): device
  * arrays [B].  candidates: NULL or device int [B, n-1, 2] receiving the
  * prefilter's indices (-1: no ambiguous ReLU in that layer).  Bounds l <= u
- * and the objective c are read from `batch`.  Synchronous (allocates a batch of
- * 4 (n-1) B children).  At most 16 hidden layers (LD_E_UNSUPPORTED). */
+ * and the objective c are read from `batch`.  Synchronous; the buffers of the
+ * 4 (n-1) B children stay with the net for later calls (grown when B grows,
+ * freed by ld_destroy_net), and calls on one net are serialised.  At most 16
+ * hidden layers (LD_E_UNSUPPORTED). */
 int ld_fsb_branch(const ld_net* net, const ld_batch* batch, int* layer, int* index, double* value,
                   int* candidates, hipStream_t stream);
 

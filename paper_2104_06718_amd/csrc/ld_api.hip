@@ -120,6 +120,13 @@ struct ld_net {
   std::map<std::pair<int, int>, std::array<double, 4>> engines;
   int tune_gen = 0;  // bumped whenever a tuned choice changes (part of the graph key)
   std::mutex mu;
+  // buffers of the branching pipeline, kept between calls (grown, never shrunk)
+  struct FsbBuffers {
+    void* base = nullptr;
+    size_t bytes = 0;
+    Workspace ws;
+    std::mutex mu;  // one branching call on the net at a time
+  } fsb;
 };
 
 struct ld_state {
@@ -1245,6 +1252,8 @@ void ld_destroy_net(ld_net* net) {
   if (!net) return;
   for (void* p : net->allocs) (void)hipFree(p);
   if (net->ws.base) (void)hipFree(net->ws.base);
+  if (net->fsb.base) (void)hipFree(net->fsb.base);
+  if (net->fsb.ws.base) (void)hipFree(net->fsb.ws.base);
   delete net;
 }
 
@@ -2152,11 +2161,21 @@ int ld_fsb_branch(const ld_net* net, const ld_batch* bt, int* layer, int* index,
     off[i] = total;
     total += sz[i];
   }
-  void* base = nullptr;
-  if (hipMalloc(&base, total) != hipSuccess) return fail(LD_E_NOMEM, "branching buffers: hipMalloc failed");
-  char* cb = (char*)base;
+  ld_net* mnet = const_cast<ld_net*>(net);
+  std::lock_guard<std::mutex> lk(mnet->fsb.mu);
+  if (mnet->fsb.bytes < total) {
+    // work of an earlier call may still use the old buffers (the call ends with a
+    // stream synchronisation, so this only waits for other streams)
+    LD_HIP(hipDeviceSynchronize());
+    if (mnet->fsb.base) (void)hipFree(mnet->fsb.base);
+    mnet->fsb.base = nullptr;
+    mnet->fsb.bytes = 0;
+    if (hipMalloc(&mnet->fsb.base, total) != hipSuccess) return fail(LD_E_NOMEM, "branching buffers: hipMalloc failed");
+    mnet->fsb.bytes = total;
+  }
+  char* cb = (char*)mnet->fsb.base;
   auto F = [&](size_t i) { return (float*)(cb + off[i]); };
-  Workspace ws;
+  Workspace& ws = mnet->fsb.ws;
   int rc = ws_alloc(net, ws, (int)std::max<long long>(Bc, B));
   if (rc == LD_OK) rc = validate_values(net, bt, ws, s);
   int* cand = candidates ? candidates : (int*)(cb + off[i_cand]);
@@ -2242,8 +2261,6 @@ int ld_fsb_branch(const ld_net* net, const ld_batch* bt, int* layer, int* index,
     if (he != hipSuccess) rc = fail(LD_E_DEVICE, std::string("fsb select: ") + hipGetErrorString(he));
   }
   const hipError_t es = hipStreamSynchronize(s);
-  if (ws.base) (void)hipFree(ws.base);
-  (void)hipFree(base);
   if (rc == LD_OK && es != hipSuccess) rc = fail(LD_E_DEVICE, std::string("branching: ") + hipGetErrorString(es));
   return rc;
 }
