@@ -521,7 +521,7 @@ def main_sigmoid(a, P, inst):
 
 
 def src_hash():
-    """Hash of the HIP sources (a stored counter measurement is valid for this build only)."""
+    """Hash of the HIP sources (a stored counter measurement is valid for these sources only)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2104_06718_amd", "csrc")
     for f in sorted(os.listdir(d)):
