@@ -53,7 +53,7 @@ enum {
   LD_E_NUMERIC = -3,     /* NaN/Inf in an input, or l > u somewhere              */
   LD_E_NOMEM = -4,       /* device or host allocation failed                     */
   LD_E_DEVICE = -5,      /* a HIP call failed (includes asynchronous faults)     */
-  LD_E_UNSUPPORTED = -6, /* valid request this build does not implement          */
+  LD_E_UNSUPPORTED = -6, /* valid request the library does not implement        */
   LD_E_STATE = -7        /* state used with a different net or batch size        */
 };
 
