@@ -546,6 +546,21 @@ def stored_traffic(kernel, kind, config, B, prec):
     return e["bytes_per_launch"]
 
 
+def make_workload(ldgen, config, B):
+    """The configuration's instance; with B, one GPU's share of it: for a config of
+    several properties, B subdomains split over the properties in proportion to
+    their counts (at least one each)."""
+    if not B:
+        return ldgen.make_instance(config)
+    props = ldgen.CONFIGS[config]["props"]
+    if len(props) == 1:
+        return ldgen.make_instance(config, B=B)
+    total = sum(props)
+    share = [max(1, round(B * p / total)) for p in props]
+    share[share.index(max(share))] += B - sum(share)
+    return ldgen.make_instance(config, props=share)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -557,7 +572,7 @@ def main():
     import ldgen
     import paper_2104_06718_amd as P
 
-    inst = ldgen.make_instance(a.config, B=a.B) if a.B else ldgen.make_instance(a.config)
+    inst = make_workload(ldgen, a.config, a.B)
     T = a.iters or inst.meta["T"] or 500
     B = inst.B
     net = P.Net(inst.layers)
