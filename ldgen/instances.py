@@ -9,7 +9,7 @@ configuration, in this fixed order):
    (distinct, uniform in 0..n_out-1; c = e_t - e_j, or c = (1, -1) when the
    network has two outputs); then that property's subdomain splits.
 
-The input box is [x0 - eps, x0 + eps] (no clipping).  Intermediate bounds are
+The input box is [x0 - eps, x0 + eps] rounded outward to float32 (no clipping).  Intermediate bounds are
 interval bounds propagated from the root box in float64 and rounded outward to
 float32.  Each subdomain draws round(0.05 * A) distinct neurons from the A
 root-ambiguous ReLUs of its property and fixes each one active (lower bound set
@@ -225,8 +225,9 @@ def make_instance(name: str, B: Optional[int] = None, props: Optional[Sequence[i
             cvec = np.zeros(n_out)
             cvec[t] = 1.0
             cvec[j] = -1.0
-        l0 = (x0 - eps).astype(np.float32)[None, :]
-        u0 = (x0 + eps).astype(np.float32)[None, :]
+        # rounded outward, so that the float32 box contains x0 +- eps
+        l0 = _round_down_f32(x0 - eps)[None, :]
+        u0 = _round_up_f32(x0 + eps)[None, :]
         lk, uk = _interval_bounds(layers, l0, u0)
         flat_l = np.concatenate([a[0] for a in lk])
         flat_u = np.concatenate([a[0] for a in uk])

@@ -4,11 +4,13 @@ The backward pass behind the scores is checked against finite differences of an
 independent WK bound (dense matrices, tests/test_oracle_pins.py); the backup score
 against the largest gap between the chord and the ReLU found by sampling; the
 bounds of the children against that independent propagation bound (the better of
-CROWN and WK); the decision against a brute-force search of the candidate set.
-The s_FSB formula itself has no independent value to check against ("parity
-unpinned" beyond its support and sign).
+CROWN and WK); the decision against a brute-force search of the candidate set;
+s_FSB and t_SR against values worked out by hand on a net of two ambiguous ReLUs
+(tests/golden/hand_examples.json, fsb_examples).
 """
 import copy
+import json
+import os
 import types
 
 import numpy as np
@@ -147,3 +149,27 @@ def test_children_bound_at_parent_duals_is_not_below_the_parent(name):
         k, i = int(layer[b]), int(index[b])
         assert kids.l[k - 1][2 * b, i] == 0.0 and kids.u[k - 1][2 * b + 1, i] == 0.0
         assert kids.u[k - 1][2 * b, i] == batch.u[k - 1][b, i] and kids.l[k - 1][2 * b + 1, i] == batch.l[k - 1][b, i]
+
+
+def test_fsb_scores_hand_example():
+    """eq:fsb-scores and eq:babsr-scores on a hand-worked net: the min of the FSB score
+    (the max of the SR score would give 6/13 for neuron a, not 7/13), the chord slope,
+    the lambda of the folded objective, and the prefilter's argmax."""
+    data = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hand_examples.json")))
+    for ex in data["fsb_examples"]:
+        net, batch = [], None
+        n_in = len(ex["l0"])
+        for L in ex["layers"]:
+            W = torch.tensor(L["W"], dtype=torch.float64)
+            net.append(O.OLayer("linear", W, torch.tensor(L["b"], dtype=torch.float64), (n_in, 1, 1),
+                                (W.shape[0], 1, 1)))
+            n_in = W.shape[0]
+        t = lambda a: torch.tensor([a], dtype=torch.float64)  # noqa: E731
+        batch = O.OBatch(t(ex["l0"]), t(ex["u0"]), [t(a) for a in ex["l"]], [t(a) for a in ex["u"]], t(ex["c"]))
+        s, tt = O.fsb_scores(net, batch)
+        for k in range(len(s)):
+            np.testing.assert_allclose(s[k].numpy()[0], ex["s_fsb"][k], rtol=1e-14, atol=1e-15)
+            np.testing.assert_allclose(tt[k].numpy()[0], ex["t_sr"][k], rtol=1e-14, atol=1e-15)
+        cand = O.fsb_candidates(batch, s, tt)
+        assert cand[0].tolist() == ex["candidates"]
+

@@ -171,6 +171,61 @@ def test_golden_hand_examples():
             assert fb["bound"].item() >= ex["lp_optimum"] - 1e-6
 
 
+def test_golden_primal_values():
+    """Sec. 5.1.3: the upper bound is the network's value at the last P_0 minimiser.
+    x0*, c^T f(x0*) and its feasibility against the intermediate bounds, worked out
+    by hand (tests/golden/hand_examples.json, primal_cases)."""
+    data = json.load(open(os.path.join(GOLDEN, "hand_examples.json")))
+    seen = set()
+    for ex in data["examples"]:
+        net, batch = _golden_net(ex)
+        for case in ex.get("primal_cases", []):
+            rho = [_t(r)[None, :] for r in case["rho"]]
+            ev = O.dual_eval(net, batch, rho, tau=0.0)
+            np.testing.assert_array_equal(ev["x0"].numpy()[0], case["x0"])
+            p, feas = O.primal_value(net, batch, ev["x0"])
+            assert abs(p.item() - case["primal"]) < 1e-12, (ex["name"], case, p.item())
+            assert bool(feas.item()) == case["feasible"], (ex["name"], case)
+            seen.add(case["feasible"])
+    assert seen == {True, False}
+
+
+@pytest.mark.parametrize("name", ["fc_tiny", "tiny_conv", "tiny_conv2", "tiny_conv3"])
+def test_primal_value_matches_dense_forward(name):
+    """c^T f(x) and the feasibility flag against the network written as dense matrices
+    (built from the convolution's definition, no oracle code): random points of the
+    box, the box corners the P_0 rule picks, on split and unsplit subdomains."""
+    inst = ldgen.make_instance(name)
+    root = ldgen.make_instance(name, split_frac=0.0)
+    rng = np.random.default_rng(5)
+    Ms = [_brute.dense_matrix(sp) for sp in inst.layers]
+    bs = [_brute.dense_bias(sp) for sp in inst.layers]
+    net = O.net_from_specs(inst.layers)
+    flags = []
+    for it in (inst, root):
+        batch = O.batch_from_instance(it)
+        B = it.B
+        for trial in range(4):
+            w = rng.uniform(size=it.l0.shape) if trial < 2 else (rng.uniform(size=it.l0.shape) < 0.5) * 1.0
+            x0 = it.l0.astype(np.float64) + w * (it.u0.astype(np.float64) - it.l0.astype(np.float64))
+            p, feas = O.primal_value(net, batch, _t(x0))
+            for b in range(B):
+                x = x0[b]
+                ok = True
+                for k in range(len(Ms) - 1):
+                    xh = Ms[k] @ x + bs[k]
+                    ok &= bool(np.all(xh >= it.l[k][b].astype(np.float64)) and
+                               np.all(xh <= it.u[k][b].astype(np.float64)))
+                    x = np.maximum(xh, 0.0)
+                y = Ms[-1] @ x + bs[-1]
+                ref = float(it.c[b].astype(np.float64) @ y)
+                assert abs(p[b].item() - ref) <= 1e-10 * (1.0 + abs(ref)), (b, p[b].item(), ref)
+                assert bool(feas[b].item()) == ok, (name, b)
+                flags.append(ok)
+    # root subdomains: the interval bounds contain every pre-activation of the box
+    assert any(flags) and all(flags[-4 * root.B:])
+
+
 # --------------------------------------------------------------------------
 # P3: q(0) equals interval propagation through the c-folded last layer (Sec. 7.2:
 # IBP corresponds to all duals set to zero)
