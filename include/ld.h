@@ -58,7 +58,9 @@ enum {
 };
 
 enum { LD_LINEAR = 0, LD_CONV2D = 1 };          /* layer kinds (Sec. 2.1)          */
-enum { LD_FP32 = 0, LD_BF16 = 1 };              /* operand precision of the contractions */
+/* arithmetic of the ascent: FP32 or BF16 operands of the contractions (FP32
+ * state), or FP64 operands, accumulations and state (the FP64 engine) */
+enum { LD_FP32 = 0, LD_BF16 = 1, LD_FP64 = 2 };
 /* dual initialisation: CROWN's or WK's dual assignment (Prop. 2, Sec. 4.1),
  * zeros, or duals set by the caller */
 enum { LD_INIT_CROWN = 0, LD_INIT_ZERO = 1, LD_INIT_GIVEN = 2, LD_INIT_WK = 3 };
@@ -142,8 +144,12 @@ void ld_state_destroy(ld_state* st);
  * with init = LD_INIT_GIVEN continues from these duals (warm start from a
  * parent subdomain, Sec. 8.2). */
 int ld_state_set_rho(ld_state* st, const float* const* rho, hipStream_t stream);
-/* Copy the current duals out (host array of n-1 device pointers). */
+/* Copy the current duals out (host array of n-1 device pointers); the duals of
+ * a state stepped in LD_FP64 are rounded to FP32. */
 int ld_state_get_rho(const ld_state* st, float* const* rho, hipStream_t stream);
+/* The current duals in FP64 (host array of n-1 device pointers, double [B, n_k]):
+ * the FP64 engine's duals, or the FP32 duals widened. */
+int ld_state_get_rho_f64(const ld_state* st, double* const* rho, hipStream_t stream);
 /* Number of Adam steps taken so far (synchronises `stream`). */
 int ld_state_get_step(const ld_state* st, hipStream_t stream, int* t);
 /* Mark the state as fresh: the next ld_step initialises the duals again (per its
@@ -161,7 +167,8 @@ int ld_state_reset(ld_state* st, hipStream_t stream);
  * 1[u >= -l] for ambiguous ReLUs, Sec. 4.2 footnote), at which q equals the
  * CROWN bound (Prop. 2).  init = LD_INIT_WK takes the chord as both slopes (the
  * WK bound's dual point); init = LD_INIT_ZERO writes zeros.  rho: host array of
- * n-1 device pointers [B, n_k] that receive the duals. */
+ * n-1 device pointers [B, n_k] that receive the duals.  precision: operand type
+ * of the backward pass (LD_FP64: propagated in FP64, rounded to FP32 on output). */
 int ld_init_duals(const ld_net* net, const ld_batch* batch, int init, int precision,
                   float* const* rho, hipStream_t stream);
 
@@ -174,7 +181,9 @@ int ld_init_duals(const ld_net* net, const ld_batch* batch, int init, int precis
  * device pointers [B, n_k]) it receives the supergradient
  * s_k = xhat_B,k* - xhat_A,k* (Algorithm 1).  rho: host array of n-1 device
  * pointers [B, n_k].  `precision` selects the operand type of the
- * contractions (the inner minimisation and the sum are FP32/FP64 regardless).
+ * contractions (the inner minimisation and the sum are FP32/FP64 regardless);
+ * LD_FP64 widens rho and evaluates everything in FP64 (the supergradient is
+ * rounded to FP32 on output).
  * Ties of the inner minimisation are broken towards the larger xhat_B within
  * the relative band `tie_tau` (0 = exact argmin); the value is exact.
  * Uses a workspace owned by the net: calls on one net must not overlap on
@@ -182,6 +191,10 @@ int ld_init_duals(const ld_net* net, const ld_batch* batch, int init, int precis
 int ld_dual_eval(const ld_net* net, const ld_batch* batch, const float* const* rho,
                  double* q, float* const* supergrad, int precision, float tie_tau,
                  hipStream_t stream);
+/* As ld_dual_eval in FP64 with FP64 duals: rho host array of n-1 device pointers
+ * double [B, n_k]; supergrad (optional) double [B, n_k].  Same workspace rules. */
+int ld_dual_eval_f64(const ld_net* net, const ld_batch* batch, const double* const* rho, double* q,
+                     double* const* supergrad, float tie_tau, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* ascent (Algorithm 1 with Adam)                                             */
@@ -192,7 +205,14 @@ int ld_dual_eval(const ld_net* net, const ld_batch* batch, const float* const* r
  *             so several calls of k steps equal one call of their sum.
  * beta1, beta2, eps  Adam constants; the update is an ascent step
  *             rho += lr_t * mhat / (sqrt(vhat) + eps) with bias correction.
- * precision   LD_FP32 or LD_BF16 for the contractions of the ascent.  LD_BF16:
+ * precision   LD_FP32, LD_BF16 or LD_FP64 for the contractions of the ascent.
+ *             LD_FP64: the FP64 engine; duals, Adam moments, every product,
+ *             sum, square root and division in FP64 (IEEE, no fused
+ *             multiply-adds), the Adam constants and step sizes widened from
+ *             the float fields below; `engine` is ignored.  A state keeps the
+ *             family it was initialised in: an FP64 step on a state initialised
+ *             in FP32/BF16 (or the reverse) returns LD_E_STATE until
+ *             ld_state_reset or ld_state_set_rho.  LD_BF16:
  *             every contraction runs on BF16 MFMA with FP32 accumulation; the
  *             forward products W_k x and the product W_1^T rho_1 into the input
  *             box take plain BF16 operands, while the products W_k^T rho_k
@@ -212,7 +232,9 @@ int ld_dual_eval(const ld_net* net, const ld_batch* batch, const float* const* r
  *             workgroup owning S subdomains with their intermediates in LDS
  *             (LD_E_UNSUPPORTED if the layer maps do not fit);
  *             LD_ENGINE_LAYERWISE: one batched launch per contraction and
- *             iteration, replayed from a captured HIP graph;
+ *             iteration, all `iters` iterations of the call captured in one
+ *             HIP graph (up to 1000 per graph; a longer call replays a graph
+ *             of 1000 and ends with one of the rest) and launched once;
  *             LD_ENGINE_AUTO: the engine and the launch configuration of every
  *             contraction picked by the autotuner (ld_autotune) for this
  *             net, batch size and precision; the first AUTO call for a new
@@ -232,7 +254,8 @@ typedef struct ld_opts {
 
 /* Enqueue `iters` Adam supergradient steps for every subdomain (engine per
  * ld_opts).  The layer-wise engine captures its loop once per (state, batch
- * pointers, options, tuned configuration) into a HIP graph and replays it. */
+ * pointers, options, iteration count, tuned configuration) into a HIP graph and
+ * replays it on later calls with the same key. */
 int ld_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opts* opts,
             hipStream_t stream);
 
@@ -245,11 +268,8 @@ int ld_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opt
  * (waves along subdomains and along K) and splits of K over blocks.  The
  * fastest configuration of each contraction is kept for (net, batch->B,
  * opts->precision); then `opts` is used to time a 20-step ascent with each
- * engine and the faster one becomes the choice of
- * LD_ENGINE_AUTO (the layer-wise engine is timed with its phases forked onto
- * three streams and in sequence, and the faster mode is kept for every
- * layer-wise call with this B and precision).  Replaces earlier choices for
- * the same (B, precision).
+ * engine and the faster one becomes the choice of LD_ENGINE_AUTO.  Replaces
+ * earlier choices for the same (B, precision).
  * Synchronises `stream`; allocates and frees its scratch state.  Only the
  * precision, tie_tau, Adam constants and total_iters of `opts` are used. */
 int ld_autotune(const ld_net* net, const ld_batch* batch, const ld_opts* opts, hipStream_t stream);
@@ -279,13 +299,11 @@ int ld_tile_candidates(const ld_net* net, int B, int k, int dir, ld_tile* out, i
  * Not thread-safe against concurrent calls on the same net. */
 int ld_set_tuned_config(ld_net* net, int B, int precision, int k, int dir, const ld_tile* tile);
 
-/* The engine chosen by the autotuner for (B, precision), whether the
- * layer-wise engine runs the independent layer jobs of a phase concurrently on
- * forked streams (1) or in sequence (0) in iterations launched outside a
- * captured graph (a captured iteration always runs its jobs in sequence), and
- * the measured time per iteration of each engine in microseconds (us_resident
- * = 0 when the resident engine does not fit).  LD_E_STATE if nothing was
- * tuned. */
+/* The engine chosen by the autotuner for (B, precision), *concurrent = 1 (the
+ * independent layer jobs of a phase are separate branches of the layer-wise
+ * engine's captured graph, which the runtime may run concurrently), and the
+ * measured time per iteration of each engine in microseconds (us_resident = 0
+ * when the resident engine does not fit).  LD_E_STATE if nothing was tuned. */
 int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, int* concurrent, double* us_layerwise,
                     double* us_resident);
 
@@ -402,7 +420,8 @@ int ld_intermediate_bounds(const ld_net* sub, const ld_batch* batch, const ld_op
  * eta0, eta_end  weight of the proximal terms (> 0; the paper: 10 -> 500, or
  *              100 fixed inside branch and bound)
  * mu           momentum in [0, 1) (the paper: 0.3, or 0 inside branch and bound)
- * precision    LD_FP32 or LD_BF16 operands of the contractions (as ld_opts)
+ * precision    LD_FP32 or LD_BF16 operands of the contractions (as ld_opts;
+ *              LD_FP64: LD_E_UNSUPPORTED)
  * init, tie_tau  as ld_opts */
 typedef struct ld_prox_opts {
   int iters;
@@ -445,7 +464,8 @@ int ld_prox_get_step(const ld_state* st, int* t);
 /* final bound (Algorithm 1's return value; upper bound of Sec. 5.1.3)        */
 /* ------------------------------------------------------------------------- */
 /* At the state's current duals: q_final = q(rho^T) with FP32 operands and an
- * FP64 cross-layer sum; bound = max(q(rho^0), q(rho^T)) (both are valid lower
+ * FP64 cross-layer sum (all in FP64, with the network forward for the primal
+ * value, for a state stepped in LD_FP64); bound = max(q(rho^0), q(rho^T)) (both are valid lower
  * bounds by weak duality, Sec. 3.1); primal = c^T f(x_0*) for the true ReLU
  * network at the P_0 minimiser x_0*, an upper bound on the subdomain minimum
  * when feasible = 1 (every pre-activation within [l_k, u_k]).  All outputs are

@@ -18,18 +18,18 @@ LIB_PATH = os.path.join(HERE, "libld_mi355x.so")
 LD_OK, LD_E_ARG, LD_E_SHAPE, LD_E_NUMERIC, LD_E_NOMEM, LD_E_DEVICE, LD_E_UNSUPPORTED, LD_E_STATE = \
     0, -1, -2, -3, -4, -5, -6, -7
 LD_LINEAR, LD_CONV2D = 0, 1
-LD_FP32, LD_BF16 = 0, 1
+LD_FP32, LD_BF16, LD_FP64 = 0, 1, 2
 LD_INIT_CROWN, LD_INIT_ZERO, LD_INIT_GIVEN, LD_INIT_WK = 0, 1, 2, 3
 LD_ENGINE_AUTO, LD_ENGINE_RESIDENT, LD_ENGINE_LAYERWISE = 0, 1, 2
 TAU_DEFAULT = 2.0 ** -20
 
-_PREC = {"fp32": LD_FP32, "bf16": LD_BF16, LD_FP32: LD_FP32, LD_BF16: LD_BF16}
+_PREC = {"fp32": LD_FP32, "bf16": LD_BF16, "fp64": LD_FP64, LD_FP32: LD_FP32, LD_BF16: LD_BF16, LD_FP64: LD_FP64}
 _INIT = {"crown": LD_INIT_CROWN, "zero": LD_INIT_ZERO, "given": LD_INIT_GIVEN, "wk": LD_INIT_WK}
 _ENGINE = {"auto": LD_ENGINE_AUTO, "resident": LD_ENGINE_RESIDENT, "layerwise": LD_ENGINE_LAYERWISE}
 
 EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num_layers",
             "ld_set_validation", "ld_state_create", "ld_state_destroy", "ld_state_set_rho",
-            "ld_state_get_rho", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval",
+            "ld_state_get_rho", "ld_state_get_rho_f64", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval", "ld_dual_eval_f64",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
             "ld_intermediate_bounds", "ld_fsb_branch", "ld_branch_children", "ld_sigmoid_hull", "ld_sigmoid_inner_min", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
@@ -102,11 +102,13 @@ def load_library(path: Optional[str] = None):
     lib.ld_state_destroy.restype = None
     lib.ld_state_set_rho.argtypes = [V, P(V), V]
     lib.ld_state_get_rho.argtypes = [V, P(V), V]
+    lib.ld_state_get_rho_f64.argtypes = [V, P(V), V]
     lib.ld_state_get_step.argtypes = [V, V, P(I)]
     lib.ld_state_reset.argtypes = [V, V]
     lib.ld_profile_iteration.argtypes = [V, P(ld_batch), V, P(ld_opts), I, P(ctypes.c_double), P(I), I, P(I), V]
     lib.ld_init_duals.argtypes = [V, P(ld_batch), I, I, P(V), V]
     lib.ld_dual_eval.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
+    lib.ld_dual_eval_f64.argtypes = [V, P(ld_batch), P(V), V, P(V), ctypes.c_float, V]
     lib.ld_step.argtypes = [V, P(ld_batch), V, P(ld_opts), V]
     lib.ld_autotune.argtypes = [V, P(ld_batch), P(ld_opts), V]
     lib.ld_tuned_config.argtypes = [V, I, I, I, I, P(ld_tile), P(ctypes.c_double)]
@@ -251,6 +253,12 @@ class State:
         _check(self.lib.ld_state_get_rho(self.handle, _ptrs(out), _stream(stream)))
         return out
 
+    def get_rho64(self, stream=None) -> List[torch.Tensor]:
+        """The duals in FP64 (the FP64 engine's own, or the FP32 duals widened)."""
+        out = [torch.empty((self.B, w), device="cuda", dtype=torch.float64) for w in self.net.widths[1:-1]]
+        _check(self.lib.ld_state_get_rho_f64(self.handle, _ptrs(out), _stream(stream)))
+        return out
+
     def reset(self, stream=None):
         _check(self.lib.ld_state_reset(self.handle, _stream(stream)))
 
@@ -288,6 +296,22 @@ def dual_eval(net: Net, batch: Batch, rho: List[torch.Tensor], supergrad=True, p
         sp = _ptrs(s)
     _check(net.lib.ld_dual_eval(net.handle, ctypes.byref(batch.struct), _ptrs(rho), ctypes.c_void_p(q.data_ptr()),
                                 sp, _PREC[precision], ctypes.c_float(tau), _stream(stream)))
+    return q, s
+
+
+def dual_eval_f64(net: Net, batch: Batch, rho: List[torch.Tensor], supergrad=True, tau: float = TAU_DEFAULT,
+                  stream=None):
+    """q(rho) [B] and, if requested, the supergradient, both in FP64, at FP64 duals."""
+    q = torch.empty(batch.B, device="cuda", dtype=torch.float64)
+    for r in rho:
+        if not (r.is_cuda and r.dtype == torch.float64 and r.is_contiguous()):
+            raise ValueError("rho must be contiguous float64 CUDA tensors")
+    s = sp = None
+    if supergrad:
+        s = [torch.empty_like(r) for r in rho]
+        sp = _ptrs(s)
+    _check(net.lib.ld_dual_eval_f64(net.handle, ctypes.byref(batch.struct), _ptrs(list(rho)),
+                                    ctypes.c_void_p(q.data_ptr()), sp, ctypes.c_float(tau), _stream(stream)))
     return q, s
 
 
@@ -504,8 +528,8 @@ class LDDual(torch.autograd.Function):
     def backward(ctx, grad_q):
         rho = ctx.saved_tensors
         _, s = dual_eval(ctx.net, ctx.batch, list(rho), supergrad=True, precision=ctx.precision, tau=ctx.tau)
-        w = grad_q.to(torch.float32).unsqueeze(1)
-        grads = [(w * sk).to(r.dtype) for sk, r in zip(s, rho)]
+        w = grad_q.to(torch.float64).unsqueeze(1)
+        grads = [(w * sk.to(torch.float64)).to(r.dtype) for sk, r in zip(s, rho)]
         return (None, None, None, None, *grads)
 
 

@@ -80,6 +80,26 @@ struct Layer {
   Job fwd, tr;
   const GemmGeom* fwd_dev = nullptr;  // device copies of the geometries (resident engine)
   const GemmGeom* tr_dev = nullptr;
+  // FP64 engine: the weights as given (and W^T of a linear layer) and the bias, in FP64
+  F64Layer f64;
+  const double* b64 = nullptr;
+};
+
+// Buffers of an FP64 evaluation pipeline for a batch of B subdomains.
+struct Workspace64 {
+  int B = 0;
+  void* base = nullptr;
+  std::vector<double*> xs;   // x*_k, k = 0..n-1
+  std::vector<double*> xb;   // xB*_k, index k = 1..n-1 (entry 0 unused)
+  std::vector<double*> val;  // per-neuron values, k = 0..n-1 (layer k >= 1: minimum - rho_k b_k)
+  std::vector<double*> rho;  // duals widened from FP32, hidden layers k = 1..n-1 at k-1
+  double* c64 = nullptr;     // c widened [B, n_out]
+  double* gconst = nullptr;  // -W_n^T c [B, n_{n-1}]
+  double* cb = nullptr;      // c . b_n [B]
+  double* act0 = nullptr;    // forward-pass activations [B, max width]
+  double* act1 = nullptr;
+  double* qtmp = nullptr;    // [B]
+  int* flag = nullptr;       // [B]
 };
 
 // Buffers of one evaluation pipeline for a batch of B subdomains.
@@ -116,10 +136,11 @@ struct ld_net {
   std::map<std::tuple<int, int, int, int>, Tile> tiles;
   std::map<std::tuple<int, int, int, int>, double> tile_us;
   // autotuned engine: (B, mma) -> {engine, us per iteration layer-wise (graph replay),
-  // resident (0: does not fit), phases of eager iterations forked (1) or not (0)}
-  std::map<std::pair<int, int>, std::array<double, 4>> engines;
+  // resident (0: does not fit)}
+  std::map<std::pair<int, int>, std::array<double, 3>> engines;
   int tune_gen = 0;  // bumped whenever a tuned choice changes (part of the graph key)
   std::mutex mu;
+  Workspace64 ws64;  // FP64 dual evaluations (ld_dual_eval with LD_FP64, ld_init_duals)
   // buffers of the branching pipeline, kept between calls (grown, never shrunk)
   struct FsbBuffers {
     void* base = nullptr;
@@ -139,26 +160,33 @@ struct ld_state {
   double* q0 = nullptr;
   bool initialized = false;
   Workspace ws;
+  // stream on which the graphs are captured (no work is ever enqueued on it)
   hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  std::vector<double> gkey;
-  int gchunk = 0;
+  // captured ascents of ld_step: graphs of `chunk` iterations each, keyed by the
+  // batch pointers, options and tuned configuration (one for the full chunks of a
+  // call, one for its remainder)
+  struct Graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<double> key;
+  };
+  Graph graphs[2];
   int t_host = 0;       // Adam steps enqueued so far (mirrors *t_dev)
-  // the layer jobs of one phase are independent: they run on the caller's stream
-  // and two more, forked and joined around each phase
-  hipStream_t side[2] = {nullptr, nullptr};
-  int fork = 1;  // fork the phases of eager iterations onto the side streams (tuned per batch size and precision)
-  // set while an iteration is being captured into a graph: the captured phases run
-  // in sequence, so cross-stream events never enter a graph and an event's
-  // lifetime never depends on a graph's
-  bool capturing = false;
-  hipEvent_t ev_fork = nullptr;
-  // recorded after the last work enqueued on the state's memory and graph; waited
-  // on before the graph is replaced or the state is freed (a graph exec or a
+  // recorded after the last work enqueued on the state's memory and graphs; waited
+  // on before a graph is replaced or the state is freed (a graph exec or a
   // buffer must not be released while kernels that use it are in flight)
   hipEvent_t done = nullptr;
-  hipEvent_t ev_join[2] = {nullptr, nullptr};
+  // FP64 engine (allocated by its first call): duals and Adam moments in FP64;
+  // `active` when the state was initialised by an FP64 ld_step (its duals are
+  // then these, and ld_final_bound evaluates in FP64)
+  struct F64 {
+    void* base = nullptr;
+    std::vector<double*> rho, m, v;  // hidden layers k = 1..n-1 at k-1
+    double* q0 = nullptr;
+    Workspace64 ws;
+    bool active = false;
+    int t = 0;
+  } f64;
   // proximal solver (allocated by its first call): primal iterates xB_k (k = 1..n-1
   // at k-1), xA_k (k = 1..n at k-1), coefficients rt_k and momentum pi_k (k-1),
   // transposed products g_k (k = 1..n-2 at k), the forward product of the current
@@ -764,32 +792,6 @@ int prepare_objective(const ld_net* net, const ld_batch* bt, Workspace& ws, int 
   return LD_OK;
 }
 
-// Fork/join of the independent layer jobs of a phase.
-constexpr int kSide = 2;
-bool forking(const ld_state* st) {
-  return st != nullptr && st->side[0] != nullptr && st->fork != 0 && !st->capturing;
-}
-hipError_t fork_begin(const ld_state* st, hipStream_t s) {
-  if (!forking(st)) return hipSuccess;
-  hipError_t e = hipEventRecord(st->ev_fork, s);
-  for (int i = 0; i < kSide && e == hipSuccess; ++i) e = hipStreamWaitEvent(st->side[i], st->ev_fork, 0);
-  return e;
-}
-hipStream_t fork_stream(const ld_state* st, hipStream_t s, int j) {
-  if (!forking(st)) return s;
-  const int r = j % (kSide + 1);
-  return r == 0 ? s : st->side[r - 1];
-}
-hipError_t fork_end(const ld_state* st, hipStream_t s) {
-  if (!forking(st)) return hipSuccess;
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < kSide && e == hipSuccess; ++i) {
-    e = hipEventRecord(st->ev_join[i], st->side[i]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, st->ev_join[i], 0);
-  }
-  return e;
-}
-
 int bias_div(const ld_net* net, int k) {
   // divisor turning a neuron index of hidden layer k into its bias index
   const Layer& L = net->L[k - 1];
@@ -836,16 +838,13 @@ EpiArgs epi_phase_a(const ld_net* net, const ld_batch* bt, const float* const* r
 }
 
 int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Workspace& ws, int mma, float tau,
-            int want_val, int* t_dev, float* adam, const ld_opts* o, hipStream_t s, const ld_state* fk = nullptr) {
+            int want_val, int* t_dev, float* adam, const ld_opts* o, hipStream_t s) {
   const int n = net->n, B = bt->B;
-  LD_HIP(fork_begin(fk, s));
   for (int k = 1; k <= n - 1; ++k) {
     const Layer& L = net->L[k - 1];
     const EpiArgs e = epi_phase_a(net, bt, rho, ws, mma, tau, want_val, t_dev, adam, o, k);
-    const hipStream_t sk = fork_stream(fk, s, k - 1);
-    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, tr_mode(mma, k), e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, sk));
+    LD_HIP(run_job(L.tr, B, rho[k - 1], 0, tr_mode(mma, k), e, pick_tile(net, k - 1, 1, B, mma), ws, k - 1, s));
   }
-  LD_HIP(fork_end(fk, s));
   if (o != nullptr) return LD_OK;
   // last hidden layer: constant coefficient -W_n^T c
   const int k = n - 1;
@@ -934,26 +933,23 @@ int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts
   const int n = net->n, B = bt->B;
   const int mma = o->precision == LD_BF16 ? 1 : 0;
   std::vector<const float*> rho(st->rho.begin(), st->rho.end());
-  LD_TRY(phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, st->t_dev, st->adam, o, s, st));
-  LD_HIP(fork_begin(st, s));
+  LD_TRY(phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, st->t_dev, st->adam, o, s));
   for (int k = 1; k <= n - 1; ++k) {
     const Layer& L = net->L[k - 1];
     const EpiArgs e = epi_phase_b(net, bt, st, o, k);
-    const hipStream_t sk = fork_stream(st, s, k - 1);
-    LD_HIP(run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), st->ws, k - 1, sk));
+    LD_HIP(run_job(L.fwd, B, st->ws.xs[k - 1], mma, mma, e, pick_tile(net, k - 1, 0, B, mma), st->ws, k - 1, s));
   }
-  LD_HIP(fork_end(st, s));
   return LD_OK;
 }
 
-void destroy_graph(ld_state* st) {
-  if (st->gexec && st->done) (void)hipEventSynchronize(st->done);
-  if (st->gexec) (void)hipGraphExecDestroy(st->gexec);
-  if (st->graph) (void)hipGraphDestroy(st->graph);
-  st->gexec = nullptr;
-  st->graph = nullptr;
-  st->gkey.clear();
-  st->gchunk = 0;
+void destroy_graph(ld_state* st, int i) {
+  ld_state::Graph& G = st->graphs[i];
+  if (G.exec && st->done) (void)hipEventSynchronize(st->done);
+  if (G.exec) (void)hipGraphExecDestroy(G.exec);
+  if (G.graph) (void)hipGraphDestroy(G.graph);
+  G.exec = nullptr;
+  G.graph = nullptr;
+  G.key.clear();
 }
 
 std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int chunk, int net_tune_gen) {
@@ -978,6 +974,349 @@ std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int c
   k.push_back(chunk);
   k.push_back(net_tune_gen);
   return k;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 engine (precision LD_FP64): the same iteration with FP64 operands,
+// accumulations and state
+// ---------------------------------------------------------------------------
+// FP64 copies of a layer's weights (as given, plus W^T of a linear layer) and bias.
+int upload_f64(ld_net* net, Layer& L, const ld_layer& s) {
+  F64Layer& F = L.f64;
+  F.kind = s.kind == LD_CONV2D ? 1 : 0;
+  F.Ci = L.in_c;
+  F.H = L.in_h;
+  F.W_ = L.in_w;
+  F.Co = L.out_c;
+  F.Ho = L.out_h;
+  F.Wo = L.out_w;
+  F.kh = L.kh;
+  F.kw = L.kw;
+  F.stride = L.stride;
+  F.pad = L.pad;
+  F.n_in = L.n_in;
+  F.n_out = L.n_out;
+  const size_t nw = s.kind == LD_LINEAR ? (size_t)L.n_out * L.n_in : (size_t)s.out_c * s.in_c * s.kh * s.kw;
+  std::vector<double> w(nw), b(s.out_c);
+  for (size_t i = 0; i < nw; ++i) w[i] = s.W[i];
+  for (int i = 0; i < s.out_c; ++i) b[i] = s.b[i];
+  void* pw;
+  void* pb;
+  LD_TRY(alloc_dev(net, &pw, nw * 8));
+  LD_TRY(alloc_dev(net, &pb, (size_t)s.out_c * 8));
+  LD_HIP(hipMemcpy(pw, w.data(), nw * 8, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(pb, b.data(), (size_t)s.out_c * 8, hipMemcpyHostToDevice));
+  F.W = (const double*)pw;
+  L.b64 = (const double*)pb;
+  F.WT = nullptr;
+  if (s.kind == LD_LINEAR) {
+    std::vector<double> wt(nw);
+    for (int i = 0; i < L.n_out; ++i)
+      for (int j = 0; j < L.n_in; ++j) wt[(size_t)j * L.n_out + i] = w[(size_t)i * L.n_in + j];
+    void* pt;
+    LD_TRY(alloc_dev(net, &pt, nw * 8));
+    LD_HIP(hipMemcpy(pt, wt.data(), nw * 8, hipMemcpyHostToDevice));
+    F.WT = (const double*)pt;
+  }
+  return LD_OK;
+}
+
+int ws64_alloc(const ld_net* net, Workspace64& ws, int B) {
+  if (ws.base && ws.B >= B) return LD_OK;
+  if (ws.base) {
+    // work enqueued earlier (on any stream) may still use the old buffers
+    LD_HIP(hipDeviceSynchronize());
+    (void)hipFree(ws.base);
+    ws.base = nullptr;
+  }
+  const int n = net->n;
+  std::vector<size_t> sizes;
+  auto add = [&](size_t bytes) {
+    sizes.push_back(round_up(std::max<size_t>(bytes, 1), 256));
+    return sizes.size() - 1;
+  };
+  std::vector<size_t> ixs, ixb, ival;
+  for (int k = 0; k <= n - 1; ++k) ixs.push_back(add((size_t)B * width(net, k) * 8));
+  for (int k = 0; k <= n - 1; ++k) ixb.push_back(add(k == 0 ? 8 : (size_t)B * width(net, k) * 8));
+  for (int k = 0; k <= n - 1; ++k) ival.push_back(add((size_t)B * width(net, k) * 8));
+  std::vector<size_t> irho;
+  for (int k = 1; k <= n - 1; ++k) irho.push_back(add((size_t)B * width(net, k) * 8));
+  const size_t ic = add((size_t)B * width(net, n) * 8);
+  const size_t igc = add((size_t)B * width(net, n - 1) * 8);
+  const size_t icb = add((size_t)B * 8);
+  const size_t ia0 = add((size_t)B * net->max_width * 8);
+  const size_t ia1 = add((size_t)B * net->max_width * 8);
+  const size_t iq = add((size_t)B * 8);
+  const size_t ifl = add((size_t)B * 4);
+  size_t total = 0;
+  std::vector<size_t> off;
+  for (size_t sz : sizes) {
+    off.push_back(total);
+    total += sz;
+  }
+  void* base = nullptr;
+  const hipError_t e = hipMalloc(&base, total);
+  if (e != hipSuccess) return fail(LD_E_NOMEM, std::string("FP64 workspace hipMalloc: ") + hipGetErrorString(e));
+  char* c = (char*)base;
+  ws.base = base;
+  ws.B = B;
+  ws.xs.assign(n, nullptr);
+  ws.xb.assign(n, nullptr);
+  ws.val.assign(n, nullptr);
+  for (int k = 0; k <= n - 1; ++k) ws.xs[k] = (double*)(c + off[ixs[k]]);
+  for (int k = 1; k <= n - 1; ++k) ws.xb[k] = (double*)(c + off[ixb[k]]);
+  for (int k = 0; k <= n - 1; ++k) ws.val[k] = (double*)(c + off[ival[k]]);
+  ws.rho.assign(n - 1, nullptr);
+  for (int k = 1; k <= n - 1; ++k) ws.rho[k - 1] = (double*)(c + off[irho[k - 1]]);
+  ws.c64 = (double*)(c + off[ic]);
+  ws.gconst = (double*)(c + off[igc]);
+  ws.cb = (double*)(c + off[icb]);
+  ws.act0 = (double*)(c + off[ia0]);
+  ws.act1 = (double*)(c + off[ia1]);
+  ws.qtmp = (double*)(c + off[iq]);
+  ws.flag = (int*)(c + off[ifl]);
+  return LD_OK;
+}
+
+F64Epi epi64() {
+  F64Epi e;
+  std::memset(&e, 0, sizeof(e));
+  e.bias_div = 1;
+  e.scale = 1.0;
+  return e;
+}
+
+// c widened, g_{n-1} = -W_n^T c and c . b_n.
+int f64_prepare_objective(const ld_net* net, const ld_batch* bt, Workspace64& ws, hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  const Layer& Ln = net->L[n - 1];
+  LD_HIP(launch_f64_widen((size_t)B * Ln.n_out, bt->c, ws.c64, s));
+  F64Epi e = epi64();
+  e.kind = F64_STORE;
+  e.scale = -1.0;
+  e.out = ws.gconst;
+  LD_HIP(launch_f64_transposed(Ln.f64, B, ws.c64, nullptr, Ln.n_in, e, s));
+  LD_HIP(launch_cdot(B, Ln.n_out, bt->c, nullptr, Ln.bias, Ln.kind == LD_CONV2D ? Ln.out_h * Ln.out_w : 1, ws.cb, s));
+  return LD_OK;
+}
+
+// Inner minimisations of P_0..P_{n-1} at the FP64 duals rho (rho[k-1] = rho_k).
+int f64_phase_a(const ld_net* net, const ld_batch* bt, const double* const* rho, Workspace64& ws, double tau,
+                hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  for (int k = 1; k <= n; ++k) {
+    // g_{k-1} = W_k^T rho_k fused with P_{k-1}; the last hidden layer's g is the constant
+    F64Epi e = epi64();
+    e.tau = tau;
+    e.xs = ws.xs[k - 1];
+    e.val = ws.val[k - 1];
+    if (k == 1) {
+      e.kind = F64_P0;
+      e.lo = bt->l0;
+      e.hi = bt->u0;
+    } else {
+      e.kind = F64_INNER;
+      e.rho = rho[k - 2];
+      e.lo = bt->l[k - 2];
+      e.hi = bt->u[k - 2];
+      e.bias = net->L[k - 2].b64;
+      e.bias_div = bias_div(net, k - 1);
+      e.xb = ws.xb[k - 1];
+    }
+    const Layer& L = net->L[k - 1];
+    if (k < n)
+      LD_HIP(launch_f64_transposed(L.f64, B, rho[k - 1], nullptr, L.n_in, e, s));
+    else
+      LD_HIP(launch_f64_transposed(L.f64, B, nullptr, ws.gconst, L.n_in, e, s));
+  }
+  return LD_OK;
+}
+
+int f64_reduce_q(const ld_net* net, int B, Workspace64& ws, double* q, hipStream_t s) {
+  std::vector<const double*> arrs;
+  std::vector<int> sz;
+  for (int k = 0; k <= net->n - 1; ++k) {
+    arrs.push_back(ws.val[k]);
+    sz.push_back(width(net, k));
+  }
+  LD_HIP(launch_reduce_q(B, (int)arrs.size(), arrs.data(), sz.data(), ws.cb, q, s));
+  return LD_OK;
+}
+
+// q(rho) and, if asked, the supergradient (FP64 and/or FP32 outputs per layer).
+int f64_dual_eval_impl(const ld_net* net, const ld_batch* bt, const double* const* rho, Workspace64& ws, double* q,
+                       double* const* sg64, float* const* sg32, double tau, hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  LD_TRY(f64_prepare_objective(net, bt, ws, s));
+  LD_TRY(f64_phase_a(net, bt, rho, ws, tau, s));
+  if (q) LD_TRY(f64_reduce_q(net, B, ws, q, s));
+  for (int k = 1; k <= n - 1; ++k) {
+    double* o64 = sg64 ? sg64[k - 1] : nullptr;
+    float* o32 = sg32 ? sg32[k - 1] : nullptr;
+    if (!o64 && !o32) continue;
+    const Layer& L = net->L[k - 1];
+    F64Epi e = epi64();
+    e.kind = F64_SUPERGRAD;
+    e.xb_in = ws.xb[k];
+    e.bias = L.b64;
+    e.bias_div = bias_div(net, k);
+    e.out = o64;
+    e.out_f = o32;
+    LD_HIP(launch_f64_forward(L.f64, B, ws.xs[k - 1], e, s));
+  }
+  return LD_OK;
+}
+
+// CROWN or WK duals (Prop. 2) or zeros, in FP64, into rho (rho[k-1] = rho_k).
+int f64_init_impl(const ld_net* net, const ld_batch* bt, int init, double* const* rho, Workspace64& ws,
+                  hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  if (init == LD_INIT_ZERO) {
+    for (int k = 1; k <= n - 1; ++k) LD_HIP(hipMemsetAsync(rho[k - 1], 0, (size_t)B * width(net, k) * 8, s));
+    return LD_OK;
+  }
+  LD_TRY(f64_prepare_objective(net, bt, ws, s));
+  for (int k = n - 1; k >= 1; --k) {
+    // rho_k from g_k = W_{k+1}^T rho_{k+1} (the constant -W_n^T c for k = n-1)
+    const Layer& L = net->L[k];
+    F64Epi e = epi64();
+    e.kind = F64_CROWN;
+    e.wk = init == LD_INIT_WK ? 1 : 0;
+    e.lo = bt->l[k - 1];
+    e.hi = bt->u[k - 1];
+    e.out = rho[k - 1];
+    if (k == n - 1)
+      LD_HIP(launch_f64_transposed(L.f64, B, nullptr, ws.gconst, L.n_in, e, s));
+    else
+      LD_HIP(launch_f64_transposed(L.f64, B, rho[k], nullptr, L.n_in, e, s));
+  }
+  return LD_OK;
+}
+
+// FP64 duals, Adam moments and q(rho^0) of a state (allocated once).
+int f64_state_alloc(const ld_net* net, ld_state* st) {
+  ld_state::F64& F = st->f64;
+  if (F.base) return LD_OK;
+  const int n = net->n, B = st->B;
+  size_t total = 0;
+  std::vector<size_t> off;
+  for (int k = 1; k <= n - 1; ++k)
+    for (int j = 0; j < 3; ++j) {
+      off.push_back(total);
+      total += round_up((size_t)B * width(net, k) * 8, 256);
+    }
+  const size_t o_q0 = total;
+  total += round_up((size_t)B * 8, 256);
+  if (hipMalloc(&F.base, total) != hipSuccess) {
+    F.base = nullptr;
+    return fail(LD_E_NOMEM, "FP64 state hipMalloc failed");
+  }
+  char* c = (char*)F.base;
+  F.rho.clear();
+  F.m.clear();
+  F.v.clear();
+  for (int k = 1; k <= n - 1; ++k) {
+    F.rho.push_back((double*)(c + off[3 * (k - 1)]));
+    F.m.push_back((double*)(c + off[3 * (k - 1) + 1]));
+    F.v.push_back((double*)(c + off[3 * (k - 1) + 2]));
+  }
+  F.q0 = (double*)(c + o_q0);
+  return ws64_alloc(net, F.ws, B);
+}
+
+// First FP64 call on a state: duals (CROWN/WK/zero, or the FP32 duals of
+// ld_state_set_rho widened), zero moments and q(rho^0).
+int f64_ensure_initialised(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
+  if (st->initialized) {
+    if (!st->f64.active) return fail(LD_E_STATE, "state was initialised in FP32/BF16: reset it to step in FP64");
+    return LD_OK;
+  }
+  LD_TRY(f64_state_alloc(net, st));
+  ld_state::F64& F = st->f64;
+  const int n = net->n, B = bt->B;
+  if (o->init == LD_INIT_GIVEN) {
+    for (int k = 1; k <= n - 1; ++k) LD_HIP(launch_f64_widen((size_t)B * width(net, k), st->rho[k - 1], F.rho[k - 1], s));
+  } else {
+    LD_TRY(f64_init_impl(net, bt, o->init, F.rho.data(), F.ws, s));
+  }
+  for (int k = 1; k <= n - 1; ++k) {
+    const size_t bytes = (size_t)B * width(net, k) * 8;
+    LD_HIP(hipMemsetAsync(F.m[k - 1], 0, bytes, s));
+    LD_HIP(hipMemsetAsync(F.v[k - 1], 0, bytes, s));
+  }
+  std::vector<const double*> r(F.rho.begin(), F.rho.end());
+  LD_TRY(f64_dual_eval_impl(net, bt, r.data(), F.ws, F.q0, nullptr, nullptr, o->tie_tau, s));
+  F.t = 0;
+  F.active = true;
+  st->initialized = true;
+  st->t_host = 0;
+  LD_HIP(launch_fill_i32(st->t_dev, 1, 0, s));
+  return LD_OK;
+}
+
+// One FP64 ascent iteration: phase A at the current duals, then per hidden layer
+// the forward product with the supergradient and the Adam step (t -> t+1).
+int f64_iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
+  ld_state::F64& F = st->f64;
+  const int n = net->n, B = bt->B;
+  std::vector<const double*> r(F.rho.begin(), F.rho.end());
+  LD_TRY(f64_phase_a(net, bt, r.data(), F.ws, o->tie_tau, s));
+  const int t = F.t + 1;
+  const double lr0 = o->lr0, lr_end = o->lr_end, b1 = o->beta1, b2 = o->beta2;
+  const int T = o->total_iters;
+  const double lr = T <= 1 ? lr0 : lr0 + (lr_end - lr0) * (double)(t - 1) / (double)(T - 1);
+  for (int k = 1; k <= n - 1; ++k) {
+    const Layer& L = net->L[k - 1];
+    F64Epi e = epi64();
+    e.kind = F64_ADAM;
+    e.xb_in = F.ws.xb[k];
+    e.bias = L.b64;
+    e.bias_div = bias_div(net, k);
+    e.rho_w = F.rho[k - 1];
+    e.m = F.m[k - 1];
+    e.v = F.v[k - 1];
+    e.lr = lr;
+    e.beta1 = b1;
+    e.beta2 = b2;
+    e.omb1 = 1.0 - b1;
+    e.omb2 = 1.0 - b2;
+    e.bc1 = 1.0 - std::pow(b1, (double)t);
+    e.bc2 = 1.0 - std::pow(b2, (double)t);
+    e.eps = o->eps;
+    LD_HIP(launch_f64_forward(L.f64, B, F.ws.xs[k - 1], e, s));
+  }
+  F.t = t;
+  return LD_OK;
+}
+
+// primal = c^T f(x0*) with f the ReLU network in FP64 and the feasibility flag
+// (every pre-activation within [l_k, u_k]), x0* in ws.xs[0].
+int f64_primal(const ld_net* net, const ld_batch* bt, Workspace64& ws, double* primal, int* feasible,
+               hipStream_t s) {
+  const int n = net->n, B = bt->B;
+  int* flag = feasible ? feasible : ws.flag;
+  LD_HIP(launch_fill_i32(flag, (size_t)B, 1, s));
+  const double* x = ws.xs[0];
+  double* bufs[2] = {ws.act0, ws.act1};
+  for (int k = 1; k <= n; ++k) {
+    const Layer& L = net->L[k - 1];
+    F64Epi e = epi64();
+    e.bias = L.b64;
+    e.bias_div = bias_div(net, k);
+    e.out = bufs[k & 1];
+    if (k < n) {
+      e.kind = F64_RELU_FWD;
+      e.lo = bt->l[k - 1];
+      e.hi = bt->u[k - 1];
+      e.flag = flag;
+    } else {
+      e.kind = F64_BIAS;
+    }
+    LD_HIP(launch_f64_forward(L.f64, B, x, e, s));
+    x = bufs[k & 1];
+  }
+  if (primal) LD_HIP(launch_f64_cdot(B, net->L[n - 1].n_out, bt->c, x, primal, s));
+  return LD_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1224,6 +1563,8 @@ int ld_create_net(const ld_layer* layers, int n_layers, ld_net** out) {
     L.bias = (float*)pb;
     rc = s.kind == LD_LINEAR ? build_linear(net, L, s.W) : build_conv(net, L, s.W);
     if (rc) return cleanup(rc);
+    rc = upload_f64(net, L, s);
+    if (rc) return cleanup(rc);
     {
       void* pg;
       const size_t ng = 1 + L.tr.geoms.size();
@@ -1252,6 +1593,7 @@ void ld_destroy_net(ld_net* net) {
   if (!net) return;
   for (void* p : net->allocs) (void)hipFree(p);
   if (net->ws.base) (void)hipFree(net->ws.base);
+  if (net->ws64.base) (void)hipFree(net->ws64.base);
   if (net->fsb.base) (void)hipFree(net->fsb.base);
   if (net->fsb.ws.base) (void)hipFree(net->fsb.ws.base);
   delete net;
@@ -1312,12 +1654,8 @@ int ld_state_create(const ld_net* net, int B, ld_state** out) {
     ld_state_destroy(st);
     return rc;
   }
-  bool ok = hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&st->done, hipEventDisableTiming) == hipSuccess;
-  for (int i = 0; i < 2 && ok; ++i)
-    ok = hipStreamCreateWithFlags(&st->side[i], hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&st->ev_join[i], hipEventDisableTiming) == hipSuccess;
+  const bool ok = hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&st->done, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     ld_state_destroy(st);
     return fail(LD_E_DEVICE, "stream creation failed");
@@ -1329,16 +1667,14 @@ int ld_state_create(const ld_net* net, int B, ld_state** out) {
 void ld_state_destroy(ld_state* st) {
   if (!st) return;
   if (st->done) (void)hipEventSynchronize(st->done);
-  destroy_graph(st);
+  destroy_graph(st, 0);
+  destroy_graph(st, 1);
   if (st->cap) (void)hipStreamDestroy(st->cap);
-  for (int i = 0; i < 2; ++i) {
-    if (st->side[i]) (void)hipStreamDestroy(st->side[i]);
-    if (st->ev_join[i]) (void)hipEventDestroy(st->ev_join[i]);
-  }
-  if (st->ev_fork) (void)hipEventDestroy(st->ev_fork);
   if (st->done) (void)hipEventDestroy(st->done);
   if (st->ws.base) (void)hipFree(st->ws.base);
   if (st->px.base) (void)hipFree(st->px.base);
+  if (st->f64.base) (void)hipFree(st->f64.base);
+  if (st->f64.ws.base) (void)hipFree(st->f64.ws.base);
   if (st->base) (void)hipFree(st->base);
   delete st;
 }
@@ -1357,6 +1693,7 @@ int ld_state_set_rho(ld_state* st, const float* const* rho, hipStream_t s) {
   LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
   st->t_host = 0;
   st->initialized = false;  // q(rho^0) is computed by the next ld_step (init = LD_INIT_GIVEN)
+  st->f64.active = false;
   st->px.ready = false;     // the proximal solver restarts its primal iterates from these duals
   st->px.t = 0;
   LD_HIP(hipEventRecord(st->done, s));
@@ -1369,7 +1706,27 @@ int ld_state_get_rho(const ld_state* st, float* const* rho, hipStream_t s) {
   const ld_net* net = st->net;
   for (int k = 1; k <= net->n - 1; ++k) {
     if (!rho[k - 1]) return fail(LD_E_ARG, "rho[k] is NULL");
-    LD_HIP(hipMemcpyAsync(rho[k - 1], st->rho[k - 1], (size_t)st->B * width(net, k) * 4, hipMemcpyDeviceToDevice, s));
+    const size_t cnt = (size_t)st->B * width(net, k);
+    if (st->f64.active)
+      LD_HIP(launch_f64_narrow(cnt, st->f64.rho[k - 1], rho[k - 1], s));
+    else
+      LD_HIP(hipMemcpyAsync(rho[k - 1], st->rho[k - 1], cnt * 4, hipMemcpyDeviceToDevice, s));
+  }
+  LD_HIP(hipEventRecord(st->done, s));
+  return LD_OK;
+}
+
+int ld_state_get_rho_f64(const ld_state* st, double* const* rho, hipStream_t s) {
+  g_err.clear();
+  if (!st || !rho) return fail(LD_E_ARG, "NULL argument");
+  const ld_net* net = st->net;
+  for (int k = 1; k <= net->n - 1; ++k) {
+    if (!rho[k - 1]) return fail(LD_E_ARG, "rho[k] is NULL");
+    const size_t cnt = (size_t)st->B * width(net, k);
+    if (st->f64.active)
+      LD_HIP(launch_f64_copy(cnt, st->f64.rho[k - 1], rho[k - 1], s));
+    else
+      LD_HIP(launch_f64_widen(cnt, st->rho[k - 1], rho[k - 1], s));
   }
   LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
@@ -1389,7 +1746,7 @@ int ld_init_duals(const ld_net* net, const ld_batch* bt, int init, int precision
   if (!rho) return fail(LD_E_ARG, "rho is NULL");
   if (init != LD_INIT_CROWN && init != LD_INIT_ZERO && init != LD_INIT_WK)
     return fail(LD_E_ARG, "init must be LD_INIT_CROWN, LD_INIT_ZERO or LD_INIT_WK");
-  if (precision != LD_FP32 && precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
+  if (precision != LD_FP32 && precision != LD_BF16 && precision != LD_FP64) return fail(LD_E_ARG, "bad precision");
   if (bt->B == 0) return LD_OK;
   for (int k = 0; k < net->n - 1; ++k) {
     if (!rho[k]) return fail(LD_E_ARG, "rho[k] is NULL");
@@ -1398,6 +1755,15 @@ int ld_init_duals(const ld_net* net, const ld_batch* bt, int init, int precision
   ld_net* mnet = const_cast<ld_net*>(net);
   LD_TRY(ws_alloc(net, mnet->ws, bt->B));
   LD_TRY(validate_values(net, bt, mnet->ws, s));
+  if (precision == LD_FP64) {
+    // FP64 propagation, rounded to the FP32 outputs
+    LD_TRY(ws64_alloc(net, mnet->ws64, bt->B));
+    Workspace64& w = mnet->ws64;
+    LD_TRY(f64_init_impl(net, bt, init, w.rho.data(), w, s));
+    for (int k = 1; k <= net->n - 1; ++k)
+      LD_HIP(launch_f64_narrow((size_t)bt->B * width(net, k), w.rho[k - 1], rho[k - 1], s));
+    return LD_OK;
+  }
   return init_impl(net, bt, init, precision, rho, mnet->ws, s);
 }
 
@@ -1406,7 +1772,7 @@ int ld_dual_eval(const ld_net* net, const ld_batch* bt, const float* const* rho,
   g_err.clear();
   LD_TRY(check_batch(net, bt));
   if (!rho) return fail(LD_E_ARG, "rho is NULL");
-  if (precision != LD_FP32 && precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
+  if (precision != LD_FP32 && precision != LD_BF16 && precision != LD_FP64) return fail(LD_E_ARG, "bad precision");
   if (!(tie_tau >= 0.f) || !std::isfinite(tie_tau)) return fail(LD_E_ARG, "tie_tau must be finite and >= 0");
   if (bt->B == 0) return LD_OK;
   for (int k = 0; k < net->n - 1; ++k) {
@@ -1419,7 +1785,31 @@ int ld_dual_eval(const ld_net* net, const ld_batch* bt, const float* const* rho,
   if (supergrad)
     for (int k = 0; k < net->n - 1; ++k)
       if (supergrad[k] && !aligned16(supergrad[k])) return fail(LD_E_ARG, "supergrad[k] must be 16-byte aligned");
+  if (precision == LD_FP64) {
+    LD_TRY(ws64_alloc(net, mnet->ws64, bt->B));
+    Workspace64& w = mnet->ws64;
+    for (int k = 1; k <= net->n - 1; ++k)
+      LD_HIP(launch_f64_widen((size_t)bt->B * width(net, k), rho[k - 1], w.rho[k - 1], s));
+    std::vector<const double*> r(w.rho.begin(), w.rho.end());
+    return f64_dual_eval_impl(net, bt, r.data(), w, q, nullptr, supergrad, tie_tau, s);
+  }
   return dual_eval_impl(net, bt, rho, mnet->ws, q, supergrad, precision, tie_tau, s);
+}
+
+int ld_dual_eval_f64(const ld_net* net, const ld_batch* bt, const double* const* rho, double* q,
+                     double* const* supergrad, float tie_tau, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_batch(net, bt));
+  if (!rho) return fail(LD_E_ARG, "rho is NULL");
+  if (!(tie_tau >= 0.f) || !std::isfinite(tie_tau)) return fail(LD_E_ARG, "tie_tau must be finite and >= 0");
+  if (bt->B == 0) return LD_OK;
+  for (int k = 0; k < net->n - 1; ++k)
+    if (!rho[k]) return fail(LD_E_ARG, "rho[k] is NULL");
+  ld_net* mnet = const_cast<ld_net*>(net);
+  LD_TRY(ws64_alloc(net, mnet->ws64, bt->B));
+  LD_TRY(ws_alloc(net, mnet->ws, bt->B));
+  LD_TRY(validate_values(net, bt, mnet->ws, s));
+  return f64_dual_eval_impl(net, bt, rho, mnet->ws64, q, supergrad, nullptr, tie_tau, s);
 }
 
 static int check_step_args(const ld_net* net, const ld_batch* bt, const ld_state* st, const ld_opts* o) {
@@ -1428,7 +1818,8 @@ static int check_step_args(const ld_net* net, const ld_batch* bt, const ld_state
   if (st->net != net || st->B != bt->B) return fail(LD_E_STATE, "state was created for another net or batch size");
   if (bt->B == 0) return fail(LD_E_ARG, "empty batch");
   if (o->iters < 0 || o->total_iters < 1) return fail(LD_E_ARG, "iters must be >= 0 and total_iters >= 1");
-  if (o->precision != LD_FP32 && o->precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
+  if (o->precision != LD_FP32 && o->precision != LD_BF16 && o->precision != LD_FP64)
+    return fail(LD_E_ARG, "bad precision");
   if (o->init != LD_INIT_CROWN && o->init != LD_INIT_ZERO && o->init != LD_INIT_GIVEN && o->init != LD_INIT_WK)
     return fail(LD_E_ARG, "bad init");
   if (o->engine != LD_ENGINE_AUTO && o->engine != LD_ENGINE_RESIDENT && o->engine != LD_ENGINE_LAYERWISE)
@@ -1441,6 +1832,8 @@ static int check_step_args(const ld_net* net, const ld_batch* bt, const ld_state
 
 // First call on a state: dual initialisation, zeroed moments and q(rho^0).
 static int ensure_initialised(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
+  if (st->initialized && st->f64.active)
+    return fail(LD_E_STATE, "state was initialised in FP64: reset it to step in FP32/BF16");
   const int mma = o->precision == LD_BF16 ? 1 : 0;
   LD_TRY(prepare_objective(net, bt, st->ws, mma, s));
   if (!st->initialized) {
@@ -1495,7 +1888,6 @@ static int build_graph(const ld_net* net, const ld_batch* bt, ld_state* st, cons
       const Layer& L = net->L[k - 1];
       hipError_t e = hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return failed("graph capture: ", e);
-      st->capturing = true;
       if (phase == 0) {
         const EpiArgs ea = epi_phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, st->t_dev, st->adam, o, k);
         e = run_job(L.tr, B, rho[k - 1], 0, tr_mode(mma, k), ea, pick_tile(net, k - 1, 1, B, mma), st->ws, k - 1,
@@ -1506,7 +1898,6 @@ static int build_graph(const ld_net* net, const ld_batch* bt, ld_state* st, cons
       }
       hipGraph_t c = nullptr;
       const hipError_t e2 = hipStreamEndCapture(st->cap, &c);
-      st->capturing = false;
       job.push_back(c);
       if (e != hipSuccess || e2 != hipSuccess) return failed("graph capture: ", e != hipSuccess ? e : e2);
       // order the job's kernel nodes along their dependencies (a chain)
@@ -1563,6 +1954,10 @@ static int build_graph(const ld_net* net, const ld_batch* bt, ld_state* st, cons
   return LD_OK;
 }
 
+// Iterations per captured graph: an ld_step call of up to this many iterations is
+// one graph launch.
+constexpr int kGraphIters = 1000;
+
 // The ascent of one ld_step call on an initialised state, engine already chosen.
 static int step_impl(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
   if (o->iters == 0) return LD_OK;
@@ -1579,24 +1974,36 @@ static int step_impl(const ld_net* net, const ld_batch* bt, ld_state* st, const 
       return LD_OK;
     }
   }
-  const int chunk = std::min(o->iters, 100);
-  std::vector<double> key = graph_key(bt, o, net->n, chunk, net->tune_gen);
-  if (!st->gexec || key != st->gkey) {
-    destroy_graph(st);
-    hipGraph_t g = nullptr;
-    LD_TRY(build_graph(net, bt, st, o, chunk, &g));
-    st->graph = g;
-    hipError_t e = hipGraphInstantiate(&st->gexec, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      destroy_graph(st);
-      return fail(LD_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  // A call of up to kGraphIters iterations is one graph launch; a longer one
+  // replays a graph of kGraphIters iterations and ends with a graph of the rest.
+  const int full = o->iters / kGraphIters, rest = o->iters % kGraphIters;
+  auto exec_for = [&](int slot, int chunk, hipGraphExec_t* x) -> int {
+    ld_state::Graph& G = st->graphs[slot];
+    const std::vector<double> key = graph_key(bt, o, net->n, chunk, net->tune_gen);
+    if (!G.exec || key != G.key) {
+      destroy_graph(st, slot);
+      hipGraph_t g = nullptr;
+      LD_TRY(build_graph(net, bt, st, o, chunk, &g));
+      G.graph = g;
+      const hipError_t e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        destroy_graph(st, slot);
+        return fail(LD_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+      }
+      G.key = key;
     }
-    st->gkey = key;
-    st->gchunk = chunk;
+    *x = G.exec;
+    return LD_OK;
+  };
+  hipGraphExec_t x = nullptr;
+  if (full > 0) {
+    LD_TRY(exec_for(0, kGraphIters, &x));
+    for (int r = 0; r < full; ++r) LD_HIP(hipGraphLaunch(x, s));
   }
-  const int reps = o->iters / chunk;
-  for (int r = 0; r < reps; ++r) LD_HIP(hipGraphLaunch(st->gexec, s));
-  for (int i = reps * chunk; i < o->iters; ++i) LD_TRY(iteration(net, bt, st, o, s));
+  if (rest > 0) {
+    LD_TRY(exec_for(full > 0 ? 1 : 0, rest, &x));
+    LD_HIP(hipGraphLaunch(x, s));
+  }
   st->t_host += o->iters;
   LD_HIP(hipEventRecord(st->done, s));
   return LD_OK;
@@ -1702,34 +2109,24 @@ static int autotune_impl(const ld_net* net, const ld_batch* bt, const ld_opts* o
     to.engine = engine;
     return step_impl(net, bt, tmp, &to, s);
   };
-  double us_lw = 0, us_fork = 0, us_seq = 0, us_res = 0;
+  double us_lw = 0, us_res = 0;
   LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_LAYERWISE); }, s, e0, e1, 1, &us_lw));
-  // phases of eager iterations (outside a captured graph) forked or in sequence
-  auto eager = [&](int f) -> int {
-    tmp->fork = f;
-    for (int i = 0; i < 4; ++i) LD_TRY(iteration(net, bt, tmp, &to, s));
-    return LD_OK;
-  };
-  LD_TRY(time_calls([&]() { return eager(1); }, s, e0, e1, 1, &us_fork));
-  LD_TRY(time_calls([&]() { return eager(0); }, s, e0, e1, 1, &us_seq));
   LD_HIP(hipEventRecord(tmp->done, s));
   // the resident engine's BF16 form uses plain BF16 transposed products (no
   // compensated product): it is offered to AUTO for FP32 only
   if (mma == 0 && resident_shape(net, B, mma).S > 0)
     LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_RESIDENT); }, s, e0, e1, 1, &us_res));
   LD_HIP(hipStreamSynchronize(s));
-  const int fork = us_fork <= us_seq ? 1 : 0;
   const int eng = (us_res > 0 && us_res < us_lw) ? LD_ENGINE_RESIDENT : LD_ENGINE_LAYERWISE;
   std::lock_guard<std::mutex> lk(mnet->mu);
-  mnet->engines[{B, mma}] = {(double)eng, us_lw / T, us_res / T, (double)fork};
+  mnet->engines[{B, mma}] = {(double)eng, us_lw / T, us_res / T};
   return LD_OK;
 }
 
-static int tuned_engine(const ld_net* net, int B, int mma, int* fork = nullptr) {
+static int tuned_engine(const ld_net* net, int B, int mma) {
   ld_net* mnet = const_cast<ld_net*>(net);
   std::lock_guard<std::mutex> lk(mnet->mu);
   auto it = mnet->engines.find({B, mma});
-  if (fork) *fork = it == mnet->engines.end() ? 1 : (int)it->second[3];
   return it == mnet->engines.end() ? -1 : (int)it->second[0];
 }
 
@@ -1939,6 +2336,7 @@ static int check_prox_args(const ld_net* net, const ld_batch* bt, const ld_state
   if (!(o->eta0 > 0.f) || !(o->eta_end > 0.f) || !std::isfinite(o->eta0) || !std::isfinite(o->eta_end))
     return fail(LD_E_ARG, "eta0 and eta_end must be finite and > 0");
   if (!(o->mu >= 0.f && o->mu < 1.f)) return fail(LD_E_ARG, "mu must be in [0, 1)");
+  if (o->precision == LD_FP64) return fail(LD_E_UNSUPPORTED, "the proximal solver has no FP64 form");
   if (o->precision != LD_FP32 && o->precision != LD_BF16) return fail(LD_E_ARG, "bad precision");
   if (o->init != LD_INIT_CROWN && o->init != LD_INIT_ZERO && o->init != LD_INIT_GIVEN && o->init != LD_INIT_WK)
     return fail(LD_E_ARG, "bad init");
@@ -2336,13 +2734,20 @@ int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* 
   g_err.clear();
   LD_TRY(check_step_args(net, bt, st, o));
   LD_TRY(validate_values(net, bt, st->ws, s));
+  if (o->precision == LD_FP64) {
+    LD_TRY(f64_ensure_initialised(net, bt, st, o, s));
+    for (int i = 0; i < o->iters; ++i) LD_TRY(f64_iteration(net, bt, st, o, s));
+    st->t_host = st->f64.t;
+    LD_HIP(launch_fill_i32(st->t_dev, 1, st->f64.t, s));
+    LD_HIP(hipEventRecord(st->done, s));
+    return LD_OK;
+  }
   ld_opts eo = *o;
   const int mma = o->precision == LD_BF16 ? 1 : 0;
   if (eo.engine == LD_ENGINE_AUTO && bt->B > 0) {
     if (tuned_engine(net, bt->B, mma) < 0) LD_TRY(autotune_impl(net, bt, o, s));
     eo.engine = tuned_engine(net, bt->B, mma);
   }
-  (void)tuned_engine(net, bt->B, mma, &st->fork);
   LD_TRY(ensure_initialised(net, bt, st, &eo, s));
   const int rc = step_impl(net, bt, st, &eo, s);
   LD_HIP(hipEventRecord(st->done, s));
@@ -2417,7 +2822,7 @@ int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, int* c
   auto it = mnet->engines.find({B, precision == LD_BF16 ? 1 : 0});
   if (it == mnet->engines.end()) return fail(LD_E_STATE, "no tuned engine for this batch size and precision");
   *engine = (int)it->second[0];
-  *concurrent = (int)it->second[3];
+  *concurrent = 1;  // the layer jobs of a phase are independent branches of the captured graph
   *us_layerwise = it->second[1];
   *us_resident = it->second[2];
   return LD_OK;
@@ -2429,6 +2834,7 @@ int ld_state_reset(ld_state* st, hipStream_t s) {
   LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
   st->t_host = 0;
   st->initialized = false;
+  st->f64.active = false;
   st->px.ready = false;
   st->px.t = 0;
   LD_HIP(hipEventRecord(st->done, s));
@@ -2440,6 +2846,7 @@ int ld_profile_iteration(const ld_net* net, const ld_batch* bt, ld_state* st, co
   g_err.clear();
   LD_TRY(check_step_args(net, bt, st, o));
   if (reps <= 0 || !avg_us || !kinds || !n_slots || max_slots <= 0) return fail(LD_E_ARG, "bad profile arguments");
+  if (o->precision == LD_FP64) return fail(LD_E_UNSUPPORTED, "per-launch profiles cover the FP32 and BF16 engines");
   LD_TRY(ensure_initialised(net, bt, st, o, s));
   const int n = net->n, B = bt->B, mma = o->precision == LD_BF16 ? 1 : 0;
   LD_TRY(iteration(net, bt, st, o, s));  // x* of every layer in the operand precision
@@ -2498,6 +2905,17 @@ int ld_final_bound(const ld_net* net, const ld_batch* bt, const ld_state* cst, d
   const int n = net->n, B = bt->B;
   Workspace& ws = st->ws;
   LD_TRY(validate_values(net, bt, ws, s));
+  if (st->f64.active) {
+    // FP64 state: q(rho^T) and the primal point in FP64
+    Workspace64& w64 = st->f64.ws;
+    double* qf64 = q_final ? q_final : w64.qtmp;
+    std::vector<const double*> r64(st->f64.rho.begin(), st->f64.rho.end());
+    LD_TRY(f64_dual_eval_impl(net, bt, r64.data(), w64, qf64, nullptr, nullptr, tie_tau, s));
+    if (bound) LD_HIP(launch_max_f64(B, st->f64.q0, qf64, bound, s));
+    if (primal || feasible) LD_TRY(f64_primal(net, bt, w64, primal, feasible, s));
+    LD_HIP(hipEventRecord(st->done, s));
+    return LD_OK;
+  }
   double* qf = q_final ? q_final : ws.qtmp;
   std::vector<const float*> r(st->rho.begin(), st->rho.end());
   LD_TRY(dual_eval_impl(net, bt, r.data(), ws, qf, nullptr, LD_FP32, tie_tau, s));

@@ -288,4 +288,60 @@ hipError_t launch_fsb_select(int B, int n_hidden, const int* cand, const double*
 hipError_t launch_interm_collect(int C, long long start, int P, int nj, const double* bound, float* lo, float* hi,
                                  hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// FP64 engine (ld_fp64.hip): direct FP64 contractions with fused epilogues.
+// ---------------------------------------------------------------------------
+struct F64Layer {
+  int kind;                        // 0 linear, 1 conv
+  int Ci, H, W_, Co, Ho, Wo;       // input and output maps (linear: Ci = n_in, Co = n_out, 1x1)
+  int kh, kw, stride, pad;
+  int n_in, n_out;
+  const double* W;                 // conv [Co][Ci][kh][kw]; linear [n_out][n_in]
+  const double* WT;                // linear: [n_in][n_out] (coalesced forward products)
+};
+
+enum F64EpiKind : int {
+  F64_STORE = 0,      // out = scale * acc
+  F64_P0 = 1,         // box minimiser of P_0: xs, val = -(g x0*)
+  F64_INNER = 2,      // ReLU-hull minimiser of P_k: xb, xs, val = min - rho*b
+  F64_CROWN = 3,      // CROWN (or WK, wk = 1) dual from g
+  F64_ADAM = 4,       // supergradient xb_in - (acc + b) and the Adam ascent step
+  F64_SUPERGRAD = 5,  // supergradient stored (out and/or out_f)
+  F64_RELU_FWD = 6,   // y = acc + b, feasibility of y against [lo, hi], out = relu(y)
+  F64_BIAS = 7        // out = acc + b
+};
+
+struct F64Epi {
+  int kind;
+  int wk;
+  int bias_div;       // neuron index / bias_div = bias index
+  double scale;
+  double tau;
+  const double* rho;  // dual of the epilogue's layer (F64_INNER)
+  const float* lo;    // bounds of the epilogue's layer (l_0, u_0 for F64_P0)
+  const float* hi;
+  const double* bias;
+  double* xb;
+  double* xs;
+  double* val;
+  double* out;
+  float* out_f;
+  const double* xb_in;
+  double* rho_w;
+  double* m;
+  double* v;
+  double lr, bc1, bc2, beta1, beta2, omb1, omb2, eps;  // Adam step (omb = 1 - beta)
+  int* flag;
+};
+
+// g = W^T r fused with an epilogue over the n = L.n_in inputs of the layer, or the
+// epilogue alone on g = gin (n values per subdomain).
+hipError_t launch_f64_transposed(const F64Layer& L, int B, const double* r, const double* gin, int n,
+                                 const F64Epi& e, hipStream_t s);
+hipError_t launch_f64_forward(const F64Layer& L, int B, const double* x, const F64Epi& e, hipStream_t s);
+hipError_t launch_f64_widen(size_t n, const float* src, double* dst, hipStream_t s);
+hipError_t launch_f64_narrow(size_t n, const double* src, float* dst, hipStream_t s);
+hipError_t launch_f64_copy(size_t n, const double* src, double* dst, hipStream_t s);
+hipError_t launch_f64_cdot(int B, int n, const float* c, const double* y, double* out, hipStream_t s);
+
 }  // namespace ld
