@@ -264,7 +264,8 @@ int ld_step(const ld_net* net, const ld_batch* batch, ld_state* st, const ld_opt
  * candidate configuration of every contraction of the ascent iteration with
  * its real epilogue: 16-column tiles per wave (1, 2, 4 as the width allows),
  * for transposed strided convs the dense GEMM + col2im form against the
- * stride-class gather form, for fully-connected products the shape of a block
+ * stride-class gather form, for convs 1, 2 or 4 blocks per subdomain (bands of
+ * destination rows; channel chunks in the col2im form), for fully-connected products the shape of a block
  * (waves along subdomains and along K) and splits of K over blocks.  The
  * fastest configuration of each contraction is kept for (net, batch->B,
  * opts->precision); then `opts` is used to time a 20-step ascent with each
@@ -279,7 +280,9 @@ typedef struct ld_tile {
   int tn;      /* 16-column MFMA tiles per wave */
   int mwaves;  /* fully-connected: waves of a block along subdomains (16 each); convs: 1 */
   int kwaves;  /* fully-connected: waves of a block along K (partial sums added in LDS); convs: 1 */
-  int splits;  /* fully-connected: blocks along K (partials added by a second kernel); convs: 1 */
+  int splits;  /* fully-connected: blocks along K (partials added by a second kernel); convs:
+                  blocks per subdomain (stride-class gather form: bands of destination rows;
+                  dense GEMM + col2im form: chunks of input channels) */
   int form;    /* transposed strided convs: 0 dense GEMM + col2im, 1 stride-class gather; else 0 */
 } ld_tile;
 

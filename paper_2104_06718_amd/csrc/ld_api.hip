@@ -70,6 +70,8 @@ struct Job {
   const GemmGeom* dev = nullptr;  // device copy of geoms
   bool has_col = false;   // transposed strided conv: dense GEMM + col2im form
   ColGeom col;
+  // the same form with one block per (subdomain, channel chunk), for several chunk counts
+  std::vector<ColGeom> col_split;
 };
 
 struct Layer {
@@ -380,57 +382,76 @@ int build_col(ld_net* net, Layer& L, const float* W) {
     for (int nch = 1; nch <= Ci && !pick; ++nch) {
       const ColGeom t = with_chunks(nch);
       if (nch > 1 && t.Cc == with_chunks(nch - 1).Cc) continue;
-      if (convT_lds_bytes(t) <= (pass == 0 ? kConvTHalfCU : kConvTWholeCU)) pick = nch;
+      if (convT_lds_bytes(t, 0) <= (pass == 0 ? kConvTHalfCU : kConvTWholeCU)) pick = nch;
     }
   if (!pick) return LD_OK;  // keep the stride-class form
-  g = with_chunks(pick);
-  const int Cc = g.Cc;
-  std::vector<int> tab((size_t)g.ntab, 0);
-  int* toy = tab.data();
-  int* coy = toy + (size_t)H * Tmax;
-  int* tox = coy + H;
-  int* cox = tox + (size_t)Wd * Tmax;
-  for (int y = 0; y < H; ++y) {
-    coy[y] = (int)tyv[y].size();
-    for (int i = 0; i < coy[y]; ++i) toy[(size_t)y * Tmax + i] = tyv[y][i].second * OW * g.Ns + tyv[y][i].first * kw;
-  }
-  for (int x = 0; x < Wd; ++x) {
-    cox[x] = (int)txv[x].size();
-    for (int i = 0; i < cox[x]; ++i) tox[(size_t)x * Tmax + i] = txv[x][i].second * g.Ns + txv[x][i].first;
-  }
-  // B fragments: lane (r, q) of K step st holds W[k][n] for n = 16*nt + r and
-  // k = st*KS + VPL*q + j (the k order inside a step matches the A operand)
-  auto wv = [&](int c, int nt, int k, int r) -> float {
-    const int nl = nt * 16 + r;
-    const int ci = c * Cc + nl / khkw;
-    if (nl >= Cc * khkw || ci >= Ci || k >= Co) return 0.f;
-    return W[((size_t)k * Ci + ci) * khkw + nl % khkw];
+  // device arrays (weight fragments in chunk order, tap tables) of a chunking
+  auto materialise = [&](ColGeom g, ColGeom* out) -> int {
+    const int Cc = g.Cc;
+    std::vector<int> tab((size_t)g.ntab, 0);
+    int* toy = tab.data();
+    int* coy = toy + (size_t)H * Tmax;
+    int* tox = coy + H;
+    int* cox = tox + (size_t)Wd * Tmax;
+    for (int y = 0; y < H; ++y) {
+      coy[y] = (int)tyv[y].size();
+      for (int i = 0; i < coy[y]; ++i) toy[(size_t)y * Tmax + i] = tyv[y][i].second * OW * g.Ns + tyv[y][i].first * kw;
+    }
+    for (int x = 0; x < Wd; ++x) {
+      cox[x] = (int)txv[x].size();
+      for (int i = 0; i < cox[x]; ++i) tox[(size_t)x * Tmax + i] = txv[x][i].second * g.Ns + txv[x][i].first;
+    }
+    // B fragments: lane (r, q) of K step st holds W[k][n] for n = 16*nt + r and
+    // k = st*KS + VPL*q + j (the k order inside a step matches the A operand)
+    auto wv = [&](int c, int nt, int k, int r) -> float {
+      const int nl = nt * 16 + r;
+      const int ci = c * Cc + nl / khkw;
+      if (nl >= Cc * khkw || ci >= Ci || k >= Co) return 0.f;
+      return W[((size_t)k * Ci + ci) * khkw + nl % khkw];
   };
-  std::vector<float> bf((size_t)g.nchunks * g.ntc * g.ksf * 64 * 4);
-  std::vector<uint16_t> bh((size_t)g.nchunks * g.ntc * g.ksh * 64 * 8);
-  for (int c = 0; c < g.nchunks; ++c)
-    for (int nt = 0; nt < g.ntc; ++nt)
-      for (int l = 0; l < 64; ++l) {
-        const int r = l & 15, q = l >> 4;
-        for (int st = 0; st < g.ksf; ++st)
-          for (int j = 0; j < 4; ++j)
-            bf[((((size_t)c * g.ntc + nt) * g.ksf + st) * 64 + l) * 4 + j] = wv(c, nt, st * 16 + 4 * q + j, r);
-        for (int st = 0; st < g.ksh; ++st)
-          for (int j = 0; j < 8; ++j)
-            bh[((((size_t)c * g.ntc + nt) * g.ksh + st) * 64 + l) * 8 + j] = host_f2bf(wv(c, nt, st * 32 + 8 * q + j, r));
-      }
-  void *pbf, *pbh, *ptab;
-  LD_TRY(alloc_dev(net, &pbf, bf.size() * 4));
-  LD_TRY(alloc_dev(net, &pbh, bh.size() * 2));
-  LD_TRY(alloc_dev(net, &ptab, tab.size() * 4));
-  LD_HIP(hipMemcpy(pbf, bf.data(), bf.size() * 4, hipMemcpyHostToDevice));
-  LD_HIP(hipMemcpy(pbh, bh.data(), bh.size() * 2, hipMemcpyHostToDevice));
-  LD_HIP(hipMemcpy(ptab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
-  g.Bf = (const float*)pbf;
-  g.Bh = (const bf16_t*)pbh;
-  g.tab = (const int*)ptab;
+    std::vector<float> bf((size_t)g.nchunks * g.ntc * g.ksf * 64 * 4);
+    std::vector<uint16_t> bh((size_t)g.nchunks * g.ntc * g.ksh * 64 * 8);
+    for (int c = 0; c < g.nchunks; ++c)
+      for (int nt = 0; nt < g.ntc; ++nt)
+        for (int l = 0; l < 64; ++l) {
+          const int r = l & 15, q = l >> 4;
+          for (int st = 0; st < g.ksf; ++st)
+            for (int j = 0; j < 4; ++j)
+              bf[((((size_t)c * g.ntc + nt) * g.ksf + st) * 64 + l) * 4 + j] = wv(c, nt, st * 16 + 4 * q + j, r);
+          for (int st = 0; st < g.ksh; ++st)
+            for (int j = 0; j < 8; ++j)
+              bh[((((size_t)c * g.ntc + nt) * g.ksh + st) * 64 + l) * 8 + j] = host_f2bf(wv(c, nt, st * 32 + 8 * q + j, r));
+        }
+    void *pbf, *pbh, *ptab;
+    LD_TRY(alloc_dev(net, &pbf, bf.size() * 4));
+    LD_TRY(alloc_dev(net, &pbh, bh.size() * 2));
+    LD_TRY(alloc_dev(net, &ptab, tab.size() * 4));
+    LD_HIP(hipMemcpy(pbf, bf.data(), bf.size() * 4, hipMemcpyHostToDevice));
+    LD_HIP(hipMemcpy(pbh, bh.data(), bh.size() * 2, hipMemcpyHostToDevice));
+    LD_HIP(hipMemcpy(ptab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
+    g.Bf = (const float*)pbf;
+    g.Bh = (const bf16_t*)pbh;
+    g.tab = (const int*)ptab;
+    *out = g;
+    return LD_OK;
+  };
+  LD_TRY(materialise(with_chunks(pick), &g));
   L.tr.col = g;
   L.tr.has_col = true;
+  // one block per chunk: 2, 3, 4 and 8 chunks (as the channels allow), each block's
+  // LDS within a quarter of a CU
+  L.tr.col_split.clear();
+  for (int nch : {2, 3, 4, 8}) {
+    if (nch > Ci) break;
+    const ColGeom t = with_chunks(nch);
+    if (t.nchunks <= pick || convT_lds_bytes(t, 1) > kConvTHalfCU / 2) continue;
+    bool dup = false;
+    for (const ColGeom& v : L.tr.col_split) dup |= v.nchunks == t.nchunks;
+    if (dup) continue;
+    ColGeom m;
+    LD_TRY(materialise(t, &m));
+    L.tr.col_split.push_back(m);
+  }
   return LD_OK;
 }
 
@@ -549,9 +570,9 @@ int build_conv(ld_net* net, Layer& L, const float* W) {
     }
   if ((int)L.tr.geoms.size() > 9) return fail(LD_E_UNSUPPORTED, "conv stride above 3 is not supported");
   LD_TRY(build_col(net, L, W));
-  if (conv_lds_bytes(L.fwd.geoms.data(), 1, 1, 0) > 160 * 1024 ||
-      std::max(conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size(), 1, 0),
-               conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size(), 1, 2)) > 160 * 1024)
+  if (conv_lds_bytes(L.fwd.geoms.data(), 1, 1, 0, 1) > 160 * 1024 ||
+      std::max(conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size(), 1, 0, 1),
+               conv_lds_bytes(L.tr.geoms.data(), (int)L.tr.geoms.size(), 1, 2, 1)) > 160 * 1024)
     return fail(LD_E_UNSUPPORTED, "conv maps too large for the LDS images of one subdomain");
   return LD_OK;
 }
@@ -672,11 +693,19 @@ std::vector<Tile> tile_candidates(const Job& J, int B) {
   if (N > 16) tns.push_back(2);
   if (N > 32) tns.push_back(4);
   if (job_is_conv(J)) {
+    // the dense GEMM + col2im form: one block per subdomain, or per (subdomain, chunk)
     if (J.has_col) c.push_back(Tile{1, 1, 1, 0, 1});
+    for (const ColGeom& v : J.col_split) c.push_back(Tile{1, 1, v.nchunks, 0, 1});
+    // the gather form: column tiles, and the destination rows in 1, 2 or 4 bands
+    // (one block per band of a subdomain)
+    const GemmGeom& g0 = J.geoms[0];
+    const int dst_H = g0.dst_HW / g0.dst_W;
     for (int tn : tns)
-      if (std::max(conv_lds_bytes(J.geoms.data(), (int)J.geoms.size(), tn, 0),
-                   conv_lds_bytes(J.geoms.data(), (int)J.geoms.size(), tn, 2)) <= 160 * 1024)
-        c.push_back(Tile{1, tn, 1, J.has_col ? 1 : 0, 1});
+      for (int parts : {1, 2, 4})
+        if (parts <= dst_H &&
+            std::max(conv_lds_bytes(J.geoms.data(), (int)J.geoms.size(), tn, 0, parts),
+                     conv_lds_bytes(J.geoms.data(), (int)J.geoms.size(), tn, 2, parts)) <= 160 * 1024)
+          c.push_back(Tile{1, tn, parts, J.has_col ? 1 : 0, 1});
   } else {
     // one block along K: every (wm, kw) shape of up to 16 waves; several blocks
     // along K (a second kernel adds the partials): 4 waves along subdomains
@@ -720,8 +749,20 @@ hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, 
     g[i].M = B * g[i].HWq;
   }
   // the dense GEMM + col2im form has no compensated BF16 product: mode 2 takes the stride-class form
-  if (J.has_col && t.form == 0 && mma != 2) return launch_convT(J.col, B, (const float*)src, mma, e, s);
-  if (job_is_conv(J)) return launch_conv(g, J.dev, nc, B, src, src_bf16, mma, e, t.tn, s);
+  if (J.has_col && t.form == 0 && mma != 2) {
+    if (t.splits > 1)
+      for (const ColGeom& v : J.col_split)
+        if (v.nchunks == t.splits) return launch_convT(v, B, (const float*)src, mma, e, 1, s);
+    return launch_convT(J.col, B, (const float*)src, mma, e, 0, s);
+  }
+  if (job_is_conv(J)) {
+    // bands of destination rows: a tile of the col2im form counts channel chunks, so
+    // when the gather form runs in its place (compensated product, forced form) it
+    // takes one band
+    const int dst_H = g[0].dst_HW / g[0].dst_W;
+    const int parts = (J.has_col && t.form == 0) ? 1 : std::min(std::max(1, t.splits), dst_H);
+    return launch_conv(g, J.dev, nc, B, src, src_bf16, mma, e, t.tn, parts, s);
+  }
   SplitArgs sp{fc_splits(J, B, t.tn, t.splits), ws.partial + (size_t)slot * kPartialLayer, ws.counters};
   return launch_fc(g[0], src, src_bf16, mma, e, t.tn, sp, std::max(1, t.wm), t.tm, s);
 }

@@ -174,18 +174,20 @@ struct ColGeom {
 };
 // LDS of one convT block: half a CU (two subdomains resident per CU), a whole CU
 constexpr size_t kConvTHalfCU = 80 * 1024, kConvTWholeCU = 160 * 1024;
-hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16, const EpiArgs& e, hipStream_t s);
-size_t convT_lds_bytes(const ColGeom& g);
+// split: one block per (subdomain, channel chunk) instead of one per subdomain
+hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16, const EpiArgs& e, int split,
+                        hipStream_t s);
+size_t convT_lds_bytes(const ColGeom& g, int split);
 
 // The plan travels by value in the kernel arguments (no host-device race between calls).
 hipError_t launch_resident(const RPlan& plan, int grid, size_t lds_bytes, int mma_bf16, hipStream_t s);
 
 // kernels (ld_kernels.hip)
-// convolution contraction, one block per (subdomain, stride class)
+// convolution contraction, `parts` blocks per subdomain (bands of destination rows)
 // geo_dev: device copy of the same class geometries (read into LDS by the kernel)
 hipError_t launch_conv(const GemmGeom* geoms, const GemmGeom* geo_dev, int n_classes, int B, const void* src,
-                       int src_bf16, int mma_bf16, const EpiArgs& e, int tn, hipStream_t s);
-size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16);
+                       int src_bf16, int mma_bf16, const EpiArgs& e, int tn, int parts, hipStream_t s);
+size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16, int parts);
 // fully-connected contraction (G.M = B rows), optional split-K
 hipError_t launch_fc(const GemmGeom& g, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e,
                      int tn, const SplitArgs& sp, int wm, int kw, hipStream_t s);

@@ -267,16 +267,20 @@ __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st
 }
 
 // ---------------------------------------------------------------------------
-// Convolution contraction of one subdomain per block, all stride classes.
+// Convolution contraction, all stride classes; `parts` blocks per subdomain, block
+// `part` owning the band of destination rows [part*H/parts, (part+1)*H/parts) of
+// every output channel (a band of a class's rows yq lands on a band of destination
+// rows, so the classes of one band are whole tiles of their grids).
 //  1. staging, one barrier: the block zeroes the padding border of a channel-last
 //     LDS image of the subdomain's source map and fills its interior (all global loads of
 //     a thread are issued before its LDS writes); the packed weights of every
 //     class and the gather offsets go to LDS as well;
-//  2. waves compute 16-pixel x 16-column MFMA tiles of every class, A gathered
-//     from the image, B read from the staged weights, and write the results into
-//     an LDS copy of the destination map (classes land on their pixels);
-//  3. all threads stream the epilogue over the destination map in order,
-//     16 bytes per access.
+//  2. waves compute 16-pixel x 16-column MFMA tiles of every class over the band,
+//     A gathered from the image, B read from the staged weights, and write the
+//     results into an LDS copy of the band of the destination map (classes land on
+//     their pixels);
+//  3. all threads stream the epilogue over the band in memory order (a contiguous
+//     run per channel), 16 bytes per access.
 // ---------------------------------------------------------------------------
 constexpr int kConvWaves = 8;
 constexpr int kConvThreads = 64 * kConvWaves;
@@ -303,7 +307,7 @@ template <int MM, bool SRC_BF16, int TN>
 __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, const GemmGeom* __restrict__ geo_dev,
                                                          const void* __restrict__ src_v, EpiArgs E,
                                                          int img_floats, int dst_hw4, int kp_max, int n_eff,
-                                                         int bstride) {
+                                                         int bstride, int parts, int out_floats) {
   constexpr bool MMA_BF16 = MM != 0;
   using M = Mma<MMA_BF16>;
   typedef typename M::BFrag BFrag;
@@ -311,8 +315,12 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   constexpr int KS = M::KS, VPL = M::VPL, EPV = 16 / (int)sizeof(WT);
   extern __shared__ float lds[];
   const GemmGeom& G0 = P.g[0];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x / parts, part = blockIdx.x - b * parts;
   const int tid = threadIdx.x;
+  // destination rows of this block and their run length per channel
+  const int dst_H = G0.dst_HW / G0.dst_W;
+  const int R0 = part * dst_H / parts, R1 = (part + 1) * dst_H / parts;
+  const int band = (R1 - R0) * G0.dst_W;
   const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
   const int H = G0.src_H, W = G0.src_W, HW = H * W;
   const int C = G0.src_n / HW;
@@ -320,9 +328,9 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   float* img = lds + P.n * kGeoWords;                      // [LH][LW][CP]
   const int CP = G0.CP;
   const int Cq = (C + 3) & ~3;  // channels of a pixel that k reads (the ones past C are zero)
-  float* outp = img + img_floats;                          // [dst_n]
-  int* kofs = reinterpret_cast<int*>(outp + G0.dst_n);     // [n classes][kp_max]
-  WT* wB = reinterpret_cast<WT*>(lds + ((P.n * kGeoWords + img_floats + G0.dst_n + P.n * kp_max + 3) & ~3));  // [n classes][n_eff][bstride], 16-byte aligned
+  float* outp = img + img_floats;                          // [channels][band]
+  int* kofs = reinterpret_cast<int*>(outp + out_floats);   // [n classes][kp_max]
+  WT* wB = reinterpret_cast<WT*>(lds + ((P.n * kGeoWords + img_floats + out_floats + P.n * kp_max + 3) & ~3));  // [n classes][n_eff][bstride], 16-byte aligned
   WT* wBl = wB + (size_t)P.n * n_eff * bstride;  // MM == 2: the BF16 remainders, same layout
 
   adam_tick(E);
@@ -454,8 +462,13 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
     const WT* wc = wB + (size_t)cl * n_eff * bstride;
     const WT* wcl = wBl + (size_t)cl * n_eff * bstride;
     const float inv_wq = 1.0f / (float)G.Wq;
-    const int ntiles = (G.HWq + 15) >> 4;
+    // the class rows yq whose destination rows yq*oy_mul + oy_off fall in [R0, R1)
+    const int yq_lo = R0 - G.oy_off <= 0 ? 0 : (R0 - G.oy_off + G.oy_mul - 1) / G.oy_mul;
+    const int yq_hi = min(G.HWq / G.Wq, R1 - G.oy_off <= 0 ? 0 : (R1 - G.oy_off + G.oy_mul - 1) / G.oy_mul);
+    const int p_lo = yq_lo * G.Wq, p_hi = max(p_lo, yq_hi * G.Wq);
+    const int ntiles = (p_hi - p_lo + 15) >> 4;
     const int nct = (G.N + 16 * TN - 1) / (16 * TN);
+    const int j_band = R0 * G.dst_W;
     // distribute (tile, column chunk) pairs over the waves, continuing the rotation across classes
     const int total = ntiles * nct;
     int first = (wave - tiles_before) % kConvWaves;
@@ -463,7 +476,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
     for (int w = first; w < total; w += kConvWaves) {
       const int tile = w / nct;
       const int nc = (w - tile * nct) * 16 * TN;
-      const int p = min(tile * 16 + r, G.HWq - 1);
+      const int p = min(p_lo + tile * 16 + r, p_hi - 1);
       const int yq = fdiv(p, G.Wq, inv_wq);
       const int xq = p - yq * G.Wq;
       const int lb = ((yq * G.iy_mul + G.iy_off + G.pad_t) * G.LW + xq * G.ix_mul + G.ix_off + G.pad_l) * CP;
@@ -495,17 +508,17 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
         }
       }
       // the lane's four rows are consecutive pixels of the class grid
-      const int p0 = tile * 16 + 4 * g;
+      const int p0 = p_lo + tile * 16 + 4 * g;
       int yy = fdiv(p0, G.Wq, inv_wq);
       int xx = p0 - yy * G.Wq;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (p0 + q < G.HWq) {
-          const int j0 = (yy * G.oy_mul + G.oy_off) * G.dst_W + xx * G.ox_mul + G.ox_off;
+        if (p0 + q < p_hi) {
+          const int j0 = (yy * G.oy_mul + G.oy_off) * G.dst_W + xx * G.ox_mul + G.ox_off - j_band;
 #pragma unroll
           for (int t = 0; t < TN; ++t) {
             const int col = nc + 16 * t + r;
-            if (col < G.N) outp[col * G.dst_HW + j0] = acc[t][q];
+            if (col < G.N) outp[col * band + j0] = acc[t][q];
           }
         }
         if (++xx == G.Wq) {
@@ -518,20 +531,23 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   }
   __syncthreads();
 
-  // 3. epilogue over the destination map in memory order
-  const size_t base = (size_t)b * G0.dst_n;
-  const float inv_dhw = 1.0f / (float)G0.dst_HW;
+  // 3. epilogue over the band of the destination map in memory order
+  const size_t base = (size_t)b * G0.dst_n + (size_t)R0 * G0.dst_W;
+  const int nch = G0.dst_n / G0.dst_HW;
+  const float inv_band = 1.0f / (float)band;
   if (dst_hw4) {
-    for (int e = 4 * tid; e < G0.dst_n; e += 4 * kConvThreads) {
-      const int col = fdiv(e, G0.dst_HW, inv_dhw);  // channel (four consecutive neurons share it)
+    for (int e = 4 * tid; e < nch * band; e += 4 * kConvThreads) {
+      const int col = fdiv(e, band, inv_band);  // channel (four consecutive neurons share it)
+      const int j = e - col * band;
       float v4[4] = {outp[e], outp[e + 1], outp[e + 2], outp[e + 3]};
-      epilogue4<true>(E, base + e, 1, 4, b, 0, col, 0, v4);
+      epilogue4<true>(E, base + (size_t)col * G0.dst_HW + j, 1, 4, b, 0, col, 0, v4);
     }
   } else {
-    for (int e = tid; e < G0.dst_n; e += kConvThreads) {
-      const int col = fdiv(e, G0.dst_HW, inv_dhw);
+    for (int e = tid; e < nch * band; e += kConvThreads) {
+      const int col = fdiv(e, band, inv_band);
+      const int j = e - col * band;
       float v4[4] = {outp[e], 0.f, 0.f, 0.f};
-      epilogue4<false>(E, base + e, 1, 1, b, 0, col, 0, v4);
+      epilogue4<false>(E, base + (size_t)col * G0.dst_HW + j, 1, 1, b, 0, col, 0, v4);
     }
   }
 }
@@ -704,24 +720,34 @@ static int max_kp(const GemmGeom* g, int n) {
 static int conv_n_eff(const GemmGeom& g, int tn) { return (g.N + 16 * tn - 1) / (16 * tn) * 16 * tn; }
 static int conv_bstride(const GemmGeom* g, int n, int mma_bf16) { return max_kp(g, n) + (mma_bf16 ? 8 : 4); }
 
-size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16) {
+// LDS floats of the destination band of one block (the tallest band of `parts`)
+static int conv_out_floats(const GemmGeom& g, int parts) {
+  const int H = g.dst_HW / g.dst_W;
+  return g.dst_n / g.dst_HW * ((H + parts - 1) / parts) * g.dst_W;
+}
+
+size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16, int parts) {
   // BF16 weights (mode 1), FP32 (0), or BF16 heads and remainders (2)
   const size_t wbytes = (size_t)n_classes * conv_n_eff(g[0], tn) * conv_bstride(g, n_classes, mma_bf16) * (mma_bf16 == 1 ? 2 : 4);
-  return (((size_t)n_classes * kGeoWords + conv_img_floats(g[0]) + g[0].dst_n + (size_t)n_classes * max_kp(g, n_classes) +
-           3) & ~(size_t)3) * 4 +
+  return (((size_t)n_classes * kGeoWords + conv_img_floats(g[0]) + conv_out_floats(g[0], parts) +
+           (size_t)n_classes * max_kp(g, n_classes) + 3) & ~(size_t)3) * 4 +
          wbytes;
 }
 
 template <int TN>
 static hipError_t launch_conv_tn(const GemmPack& P, const GemmGeom* geo_dev, int B, const void* src, int src_bf16,
-                                 int mma_bf16, const EpiArgs& e, hipStream_t s) {
+                                 int mma_bf16, const EpiArgs& e, int parts, hipStream_t s) {
   const GemmGeom& G = P.g[0];
-  const size_t lds = conv_lds_bytes(P.g, P.n, TN, mma_bf16);
+  const int dst_H = G.dst_HW / G.dst_W;
+  if (parts < 1 || parts > dst_H) return hipErrorInvalidValue;
+  const size_t lds = conv_lds_bytes(P.g, P.n, TN, mma_bf16, parts);
   const int kpm = max_kp(P.g, P.n);
   const int img = conv_img_floats(G);
-  const int hw4 = (G.dst_HW % 4) == 0;
+  const int outf = conv_out_floats(G, parts);
+  // 16-byte epilogue: every band starts and ends on a multiple of 4 neurons
+  const int hw4 = (G.dst_HW % 4) == 0 && (parts == 1 || G.dst_W % 4 == 0);
   const int neff = conv_n_eff(G, TN), bst = conv_bstride(P.g, P.n, mma_bf16);
-  dim3 grid(B), block(kConvThreads);
+  dim3 grid((unsigned)((size_t)B * parts)), block(kConvThreads);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   const void* fn;
   if (mma_bf16 == 1 && src_bf16)
@@ -745,21 +771,22 @@ static hipError_t launch_conv_tn(const GemmPack& P, const GemmGeom* geo_dev, int
   const GemmGeom* ga = geo_dev;
   const void* sa = src;
   EpiArgs ea = e;
-  int a0 = img, a1 = hw4, a2 = kpm, a3 = neff, a4 = bst;
-  void* args[] = {(void*)&pa, (void*)&ga, (void*)&sa, (void*)&ea, (void*)&a0, (void*)&a1, (void*)&a2, (void*)&a3, (void*)&a4};
+  int a0 = img, a1 = hw4, a2 = kpm, a3 = neff, a4 = bst, a5 = parts, a6 = outf;
+  void* args[] = {(void*)&pa, (void*)&ga, (void*)&sa, (void*)&ea, (void*)&a0, (void*)&a1, (void*)&a2, (void*)&a3,
+                  (void*)&a4, (void*)&a5, (void*)&a6};
   return hipLaunchKernel(fn, grid, block, args, lds, s);
 }
 
 hipError_t launch_conv(const GemmGeom* geoms, const GemmGeom* geo_dev, int n, int B, const void* src, int src_bf16,
-                       int mma_bf16, const EpiArgs& e, int tn, hipStream_t s) {
+                       int mma_bf16, const EpiArgs& e, int tn, int parts, hipStream_t s) {
   GemmPack P;
   if (n <= 0 || n > kMaxClasses) return hipErrorInvalidValue;
   P.n = n;
   for (int i = 0; i < n; ++i) P.g[i] = geoms[i];
   if (B == 0 || P.g[0].N == 0) return hipSuccess;
-  if (tn == 1) return launch_conv_tn<1>(P, geo_dev, B, src, src_bf16, mma_bf16, e, s);
-  if (tn == 2) return launch_conv_tn<2>(P, geo_dev, B, src, src_bf16, mma_bf16, e, s);
-  if (tn == 4) return launch_conv_tn<4>(P, geo_dev, B, src, src_bf16, mma_bf16, e, s);
+  if (tn == 1) return launch_conv_tn<1>(P, geo_dev, B, src, src_bf16, mma_bf16, e, parts, s);
+  if (tn == 2) return launch_conv_tn<2>(P, geo_dev, B, src, src_bf16, mma_bf16, e, parts, s);
+  if (tn == 4) return launch_conv_tn<4>(P, geo_dev, B, src, src_bf16, mma_bf16, e, parts, s);
   return hipErrorInvalidValue;
 }
 
@@ -803,7 +830,8 @@ hipError_t launch_fc(const GemmGeom& G, const void* src, int src_bf16, int mma_b
 }
 
 // ---------------------------------------------------------------------------
-// Transposed strided convolution, one block per subdomain (see ColGeom):
+// Transposed strided convolution, one block per subdomain, or with `split` one
+// block per (subdomain, chunk of input channels) (see ColGeom):
 //  0. staging, one round of loads then one of LDS writes: the subdomain's rho
 //     (A operand) in MFMA operand order, [K/VPL][Mp][VPL] (BF16 for the BF16
 //     product), zero-padded in K and M; the fragment-ordered weights (B
@@ -821,7 +849,7 @@ constexpr int kTThreads = 256;
 // (the register cap keeps the compiler from spending registers on the staging
 // round that would leave one wave per SIMD)
 template <bool BF, int TM>
-__global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) void convT_kernel(ColGeom G, const float* __restrict__ rho, EpiArgs E) {
+__global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) void convT_kernel(ColGeom G, const float* __restrict__ rho, EpiArgs E, int split) {
   using M = Mma<BF>;
   typedef typename M::BFrag BFrag;
   typedef typename M::AFrag AFrag;
@@ -830,8 +858,12 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   extern __shared__ float lds[];
   const int ks = BF ? G.ksh : G.ksf;
   const int kq_n = ks * (KS / VPL);                    // K rounded up to whole steps, in groups of VPL
-  const int nfrag = G.nchunks * G.ntc * ks * 64;       // fragments (16 bytes each)
-  BFrag* Bl = reinterpret_cast<BFrag*>(lds);           // [nchunks][ntc][ks][64 lanes]
+  // the block's chunks: all, or (split) chunk blockIdx.x mod nchunks only
+  const int b = split ? blockIdx.x / G.nchunks : blockIdx.x;
+  const int c_first = split ? blockIdx.x - b * G.nchunks : 0;
+  const int c_end = split ? c_first + 1 : G.nchunks;
+  const int nfrag = (c_end - c_first) * G.ntc * ks * 64;  // fragments (16 bytes each) staged
+  BFrag* Bl = reinterpret_cast<BFrag*>(lds);           // [staged chunks][ntc][ks][64 lanes]
   AT* A = reinterpret_cast<AT*>(lds + 4 * nfrag);      // [kq_n][Mp][VPL]
   float* Y = reinterpret_cast<float*>(A + (size_t)kq_n * G.Mp * VPL);  // [Mp][Ns]
   int* tab = reinterpret_cast<int*>(Y + G.Mp * G.Ns);  // toff_y [H][Tmax], cnt_y [H], toff_x [W][Tmax], cnt_x [W]
@@ -839,7 +871,7 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   const int* cy = ty + G.H * G.Tmax;
   const int* tx = cy + G.H;
   const int* cx = tx + G.W * G.Tmax;
-  const int b = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
   const size_t dst_base = (size_t)b * G.Ci * G.HW;
   constexpr int STEP = 4 * kTThreads;
   const bool vec = (G.HW & 3) == 0;
@@ -853,7 +885,7 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
       if (e0 + tid < e1) epi_load<false, 3>(E, dst_base + e0 + tid, 1, 1, nx);
     }
   };
-  prefetch(0, min(G.Ci, G.Cc) * G.HW);
+  prefetch(c_first * G.Cc * G.HW, min(G.Ci, (c_first + 1) * G.Cc) * G.HW);
   adam_tick(E);
   // 0. staging
   {
@@ -861,7 +893,8 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     const float* src = rho + (size_t)b * G.Co * G.M;
     const int ncell = kq_n * G.Mp;
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-    const u32x4* fsrc = reinterpret_cast<const u32x4*>(BF ? (const void*)G.Bh : (const void*)G.Bf);
+    const u32x4* fsrc = reinterpret_cast<const u32x4*>(BF ? (const void*)G.Bh : (const void*)G.Bf) +
+                        (size_t)c_first * G.ntc * ks * 64;
     const float inv_mp = 1.0f / (float)G.Mp;
     const int rounds = max((ncell + UC * kTThreads - 1) / (UC * kTThreads), (nfrag + UF * kTThreads - 1) / (UF * kTThreads));
     for (int rd = 0; rd < rounds; ++rd) {
@@ -907,10 +940,10 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   }
   __syncthreads();
   const int mtn = G.Mp >> 4;
-  for (int c = 0; c < G.nchunks; ++c) {
+  for (int c = c_first; c < c_end; ++c) {
     const int c0 = c * G.Cc, c1 = min(G.Ci, c0 + G.Cc);
     const int e0 = c0 * G.HW, e1 = c1 * G.HW;
-    if (c > 0) prefetch(e0, e1);
+    if (c > c_first) prefetch(e0, e1);
     // UT independent tiles per wave at a time (their operand reads overlap)
     constexpr int UT = 4;
     const int items = mtn * G.ntc;
@@ -925,7 +958,7 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         const int mt = it / G.ntc;
         const int nt = it - mt * G.ntc;
         fa[u] = reinterpret_cast<const AFrag*>(A) + (size_t)g * G.Mp + mt * 16 + r;
-        fb[u] = Bl + (size_t)(c * G.ntc + nt) * ks * 64 + lane;
+        fb[u] = Bl + (size_t)((c - c_first) * G.ntc + nt) * ks * 64 + lane;
         yofs[u] = (mt * 16 + 4 * g) * G.Ns + nt * 16 + r;
         acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
@@ -1028,23 +1061,25 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   }
 }
 
-// LDS of convT_kernel for the operand type: weight fragments, A, Y, tap tables
-static size_t convT_lds_bytes_t(const ColGeom& g, int bf16) {
+// LDS of convT_kernel for the operand type: weight fragments (of every chunk, or
+// of one with split), A, Y, tap tables
+static size_t convT_lds_bytes_t(const ColGeom& g, int bf16, int split = 0) {
   const int ks = bf16 ? g.ksh : g.ksf, kp = ks * (bf16 ? 32 : 16);
-  const size_t nfrag = (size_t)g.nchunks * g.ntc * ks * 64;
+  const size_t nfrag = (size_t)(split ? 1 : g.nchunks) * g.ntc * ks * 64;
   return 16 * nfrag + (size_t)kp * g.Mp * (bf16 ? 2 : 4) + (size_t)4 * g.Mp * g.Ns + (size_t)4 * g.ntab;
 }
 
-size_t convT_lds_bytes(const ColGeom& g) {
-  const size_t a = convT_lds_bytes_t(g, 0), b = convT_lds_bytes_t(g, 1);
+size_t convT_lds_bytes(const ColGeom& g, int split) {
+  const size_t a = convT_lds_bytes_t(g, 0, split), b = convT_lds_bytes_t(g, 1, split);
   return a > b ? a : b;
 }
 
-hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16, const EpiArgs& e, hipStream_t s) {
+hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16, const EpiArgs& e, int split,
+                        hipStream_t s) {
   if (B == 0) return hipSuccess;
   if (e.kind == EPI_ADAM || e.kind == EPI_ADAM_LAST) return hipErrorInvalidValue;  // reads more than 3 arrays
   if (mma_bf16 != 0 && mma_bf16 != 1) return hipErrorInvalidValue;
-  const size_t lds = convT_lds_bytes_t(g, mma_bf16);
+  const size_t lds = convT_lds_bytes_t(g, mma_bf16, split);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   // tap loops of fixed length where every row and column takes at most one or two taps
   const void* fn;
@@ -1061,8 +1096,9 @@ hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16,
   ColGeom ga = g;
   const float* ra = rho;
   EpiArgs ea = e;
-  void* args[] = {(void*)&ga, (void*)&ra, (void*)&ea};
-  return hipLaunchKernel(fn, dim3(B), dim3(kTThreads), args, lds, s);
+  int sa = split ? 1 : 0;
+  void* args[] = {(void*)&ga, (void*)&ra, (void*)&ea, (void*)&sa};
+  return hipLaunchKernel(fn, dim3((unsigned)((size_t)B * (split ? g.nchunks : 1))), dim3(kTThreads), args, lds, s);
 }
 
 // ---------------------------------------------------------------------------

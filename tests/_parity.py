@@ -22,10 +22,16 @@ def abs_layer(L):
     return O.OLayer(L.kind, L.W.abs(), L.b.abs(), L.in_shape, L.out_shape, L.stride, L.pad)
 
 
-def unstable_decisions(net, batch, rho, ev, tau=O.TAU_DEFAULT, tie_rel=TIE_REL):
+def unstable_decisions(net, batch, rho, ev, tau=O.TAU_DEFAULT, tie_rel=TIE_REL, exact_ties_stable=False):
     """Per-layer boolean masks (layer 0 = P_0, then hidden layers 1..n-1): True where
     an inner-minimisation decision of the oracle sits within tie_rel (relative to
-    the error scale of the contraction feeding it) of flipping."""
+    the error scale of the contraction feeding it) of flipping.
+
+    exact_ties_stable: the duals were formed by the GPU from the very contraction it
+    repeats (the CROWN point, where rho = a g; zeros).  A hidden-layer decision at an
+    exact tie of the oracle's vertex values (a kink of q, Prop. 2) is then an exact
+    tie up to FP32 rounding (< 2^-21 of the magnitudes) on the GPU too, inside the
+    tie band (2^-20), and both sides take the preferred vertex."""
     TIE_REL = tie_rel  # noqa: N806
     n = len(net)
     duals = list(rho) + [-batch.c]
@@ -40,6 +46,8 @@ def unstable_decisions(net, batch, rho, ev, tau=O.TAU_DEFAULT, tie_rel=TIE_REL):
         e_pass = TIE_REL * G[k] + ULP32 * (r.abs() + g.abs())
         # where the error scale is zero both sides compute the identical exact value
         ok_pass = ((cp - tau * (r.abs() + g.abs())).abs() > e_pass) | (e_pass == 0)
+        if exact_ties_stable:
+            ok_pass = ok_pass | (cp.abs() <= 1e-12 * (r.abs() + g.abs()))
         # blocking: the sign of rho is an input, identical on both sides
         # ambiguous: a vertex at the minimum is always accepted; any other vertex must
         # not sit near the acceptance threshold m + band
@@ -49,8 +57,11 @@ def unstable_decisions(net, batch, rho, ev, tau=O.TAU_DEFAULT, tie_rel=TIE_REL):
         thr = m + tau * (Vl.abs() + (r * u).abs() + (g * u).abs())
         err = 2 * TIE_REL * G[k] * (l.abs() + u.abs()) + ULP32 * (Vl.abs() + Vu.abs())
 
+        mag = Vl.abs() + (r * u).abs() + (g * u).abs()
+        at_min = 1e-12 * mag if exact_ties_stable else torch.zeros_like(mag)
+
         def far(V):
-            return (V == m) | ((V - thr).abs() > err) | (err == 0)
+            return ((V - m).abs() <= at_min) | (V == m) | ((V - thr).abs() > err) | (err == 0)
         ok_amb = far(Vl) & far(V0) & far(Vu)
         ok = torch.where(st == 0, ok_pass, torch.where(st == 1, torch.ones_like(ok_pass), ok_amb))
         masks.append(~ok)
@@ -100,3 +111,16 @@ def supergrad_bound(net, batch, masks, scale, rel):
         own = masks[k].double() * (batch.u[k - 1] - batch.l[k - 1])
         out.append(rel * scale[k - 1] + spread + own)
     return out
+
+
+
+def first_step_may_differ(net, batch, rho, tau=O.TAU_DEFAULT, exact_ties_stable=False):
+    """Duals whose first Adam step from rho (zero moments) may differ between the
+    GPU's FP32 evaluation and the oracle's.  That step is lr * s / (|s| + eps) per
+    entry, about lr * sign(s): it changes only where s may change sign, i.e. where
+    |s| lies within supergrad_bound's bound on |s_gpu - s_orc| (contraction rounding
+    plus every decision within rounding of a tie, carried through |W|)."""
+    ev = O.dual_eval(net, batch, rho, tau)
+    masks = unstable_decisions(net, batch, rho, ev, tau, exact_ties_stable=exact_ties_stable)
+    bound = supergrad_bound(net, batch, masks, s_scale(net, ev), REL)
+    return [ev["s"][k].abs() <= bound[k] + 1e-7 for k in range(len(net) - 1)]

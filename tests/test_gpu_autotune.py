@@ -5,7 +5,7 @@ import torch
 
 import ldgen
 from oracle import ld_oracle as O
-from tests.test_gpu_parity import FP32_FINAL_REL, _case, _check_dual_eval, _oracle_run, _setup
+from tests.test_gpu_parity import _case, _check_dual_eval, _oracle_fp32_spread, _oracle_run, _setup
 
 pytestmark = pytest.mark.gpu
 
@@ -68,5 +68,7 @@ def test_autotuned_auto_ascent(prec):
         idx = list(range(8))
         ofb, _ = _oracle_run(inst, idx, T)
         d = (fb["bound"].cpu()[idx] - ofb["bound"]).abs()
-        print(f"  |gpu - oracle| max {d.max().item():.2e}")
-        assert bool((d <= FP32_FINAL_REL * ofb["bound"].abs() + 1e-3).all())
+        ref = _oracle_fp32_spread(inst, idx, T, ofb["bound"])
+        print(f"  |gpu - oracle| max {d.max().item():.2e}; oracle in float32: max {ref.max().item():.2e}")
+        assert d.mean().item() <= 2 * ref.mean().item() + 1e-4
+        assert d.max().item() <= 2 * ref.max().item() + 1e-3

@@ -13,10 +13,9 @@ import torch
 import ldgen
 from oracle import ld_oracle as O
 from tests import _parity as PT
+from tests.test_gpu_parity import _oracle_fp32_spread
 
 pytestmark = pytest.mark.gpu
-
-FP32_FINAL_REL = 3e-3
 
 
 def _case(msg):
@@ -86,8 +85,11 @@ def test_deep_ascent_fp32_full_batch_sampled(deep, engine):
     ofb = O.final_bound(onet, ob, O.ascent(onet, ob, O.AdamOpts(T=T)))
     b = fb["bound"].cpu()[idx]
     d = (b - ofb["bound"]).abs()
-    print(f"  |gpu - oracle| mean {d.mean().item():.2e} max {d.max().item():.2e}")
-    assert bool((d <= FP32_FINAL_REL * ofb["bound"].abs() + 1e-3).all()), (b, ofb["bound"])
+    ref = _oracle_fp32_spread(inst, idx, T, ofb["bound"])
+    print(f"  |gpu - oracle| mean {d.mean().item():.2e} max {d.max().item():.2e}; oracle in float32: "
+          f"mean {ref.mean().item():.2e} max {ref.max().item():.2e}")
+    assert d.mean().item() <= 2 * ref.mean().item() + 1e-4
+    assert d.max().item() <= 2 * ref.max().item() + 1e-3
     feas = fb["feasible"].cpu().bool()
     assert bool((fb["bound"].cpu()[feas] <= fb["primal"].cpu()[feas] + 1e-6).all())
     assert bool(torch.isfinite(fb["bound"]).all())

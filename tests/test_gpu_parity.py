@@ -125,10 +125,20 @@ def _oracle_run(inst, idx, T, lr0=1e-2, lr_end=1e-4):
 
 
 # The ascent is a non-smooth, sign-like (Adam) iteration: a rounding-level difference
-# at a near-tie flips a vertex and moves the trajectory by O(step).  Running the
-# oracle itself in float32 moves its final bound by up to ~2e-3 relative at these
-# shapes (500 steps), so the FP32 path is held to that arithmetic's own spread.
-FP32_FINAL_REL = 3e-3
+# at a near-tie flips a vertex and moves the trajectory by O(step).  The FP32 path is
+# held to the spread of FP32 arithmetic itself: the oracle's own algorithm run with
+# float32 tensors on the CPU departs from its FP64 run by the same amount (base net,
+# 500 steps: mean 7e-3, max 3.5e-2).  The FP64 engine is the form held to 1e-3
+# absolute per subdomain (tests/test_gpu_fp64.py).
+def _oracle_fp32_spread(inst, idx, T, fp64_bound):
+    """|bound of the oracle's algorithm in float32 - its FP64 bound| per subdomain."""
+    onet = O.net_from_specs(inst.layers)
+    ob = O.batch_from_instance(inst, idx)
+    f = torch.float32
+    net32 = [O.OLayer(L.kind, L.W.to(f), L.b.to(f), L.in_shape, L.out_shape, L.stride, L.pad) for L in onet]
+    b32 = O.OBatch(ob.l0.to(f), ob.u0.to(f), [x.to(f) for x in ob.l], [x.to(f) for x in ob.u], ob.c.to(f))
+    fb32 = O.final_bound(net32, b32, O.ascent(net32, b32, O.AdamOpts(T=T)))
+    return (fb32["bound"].double() - fp64_bound).abs()
 
 
 ENGINES = ["resident", "layerwise"]
@@ -143,7 +153,7 @@ HOST_CRASH_SKIP = "host heap corruption (cause not shown) in a run of this case;
 
 
 @pytest.mark.parametrize("engine", ENGINES)
-@pytest.mark.parametrize("name,T", [("fc_tiny", 500), ("tiny_conv", 200), ("tiny_conv2", 200), ("base", 100)])
+@pytest.mark.parametrize("name,T", [("fc_tiny", 500), ("tiny_conv", 200), ("tiny_conv2", 200), ("base", 500)])
 def test_ascent_final_bound_parity_fp32(name, T, engine):
     _case(f"ascent fp32 {name} T={T} engine={engine}")
     P, inst, net, batch = _setup(name)
@@ -152,12 +162,17 @@ def test_ascent_final_bound_parity_fp32(name, T, engine):
     fb = P.final_bound(net, batch, st)
     torch.cuda.synchronize()
     assert st.step_count() == T
-    idx = list(range(min(inst.B, 8)))
+    idx = list(range(inst.B))
     ofb, ost = _oracle_run(inst, idx, T)
     b_g = fb["bound"].cpu()[idx]
     d = (b_g - ofb["bound"]).abs()
-    print(f"  final bound |gpu - oracle|: mean {d.mean().item():.2e} max {d.max().item():.2e}")
-    assert bool((d <= FP32_FINAL_REL * ofb["bound"].abs() + 1e-3).all()), (b_g, ofb["bound"])
+    qs = torch.quantile(d, torch.tensor([0.5, 0.9], dtype=torch.float64)) if d.numel() > 1 else d.repeat(2)
+    print(f"  final bound |gpu - oracle| over {len(idx)} subdomains: mean {d.mean().item():.2e} "
+          f"p50 {qs[0].item():.2e} p90 {qs[1].item():.2e} max {d.max().item():.2e}")
+    ref = _oracle_fp32_spread(inst, idx, T, ofb["bound"])
+    print(f"  oracle's algorithm in float32 - FP64: mean {ref.mean().item():.2e} max {ref.max().item():.2e}")
+    assert d.mean().item() <= 2 * ref.mean().item() + 1e-4
+    assert d.max().item() <= 2 * ref.max().item() + 1e-3
     # soundness: never above the network value at a feasible point, nor below q(rho^T)
     feas = fb["feasible"].cpu().bool()
     prim = fb["primal"].cpu()
@@ -165,28 +180,110 @@ def test_ascent_final_bound_parity_fp32(name, T, engine):
     assert bool((fb["bound"].cpu() >= fb["q_final"].cpu() - 1e-12).all())
 
 
+@pytest.mark.parametrize("split", [True, False])
+@pytest.mark.parametrize("name", SMALL + ["base"])
+def test_primal_and_feasibility_against_oracle(name, split):
+    """ld_final_bound's primal value c^T f(x0*) and its feasibility flag (Sec. 5.1.3)
+    at the CROWN duals (0 iterations) against the oracle's at the same FP32 duals.
+    Coordinates of x0* whose P_0 decision is within rounding of a tie are
+    allowed to move the primal value by what x0* moving there can change it; the flags are
+    compared where no pre-activation lies within that distance of its bound.  Unsplit subdomains have every point of the box feasible; split ones
+    have infeasible minimisers too, so both outcomes are exercised."""
+    kw = {} if split else dict(split_frac=0.0)
+    P, inst, net, batch = _setup(name, **kw)
+    _case(f"primal and feasibility {name} split={split} B={inst.B}")
+    st = P.State(net, inst.B)
+    P.step(net, batch, st, iters=0, total_iters=10, engine="layerwise")
+    fb = {k: v.cpu() for k, v in P.final_bound(net, batch, st).items()}
+    orho = [r.cpu().double() for r in st.get_rho()]
+    torch.cuda.synchronize()
+    onet, ob = O.net_from_specs(inst.layers), O.batch_from_instance(inst)
+    ev = O.dual_eval(onet, ob, orho, need_supergrad=False)
+    p, feas = O.primal_value(onet, ob, ev["x0"])
+    # x0* may differ where a P_0 decision is within rounding of a tie: by at most
+    # u0 - l0 there, which moves every later pre-activation by at most |W| applied to it
+    dx = PT.unstable_decisions(onet, ob, orho, ev)[0].double() * (ob.u0 - ob.l0)
+    x, xa = ev["x0"], ev["x0"].abs()
+    unsure = torch.zeros(inst.B, dtype=torch.bool)
+    for k in range(len(onet) - 1):
+        A = PT.abs_layer(onet[k])
+        xh = onet[k].forward(x)
+        xha = A.forward(xa)
+        dx = A.forward(dx) - A.bias_full()
+        margin = torch.minimum(xh - ob.l[k], ob.u[k] - xh)
+        unsure |= (margin.abs() <= 1e-5 * xha + 1e-7 + dx).any(dim=1)
+        x, xa = torch.clamp(xh, min=0.0), xha
+    A = PT.abs_layer(onet[-1])
+    tol = (ob.c.abs() * (1e-5 * A.forward(xa) + A.forward(dx) - A.bias_full())).sum(dim=1) + 1e-6
+    dp = (fb["primal"] - p).abs()
+    cmp = ~unsure
+    print(f"  max |primal - oracle| / tol {(dp / tol).max().item():.2e}; feasible {int(feas.sum())} of "
+          f"{inst.B}; flags compared {int(cmp.sum())}")
+    assert bool((dp <= tol).all())
+    assert bool((fb["feasible"].bool()[cmp] == feas[cmp]).all())
+    if not split:
+        assert bool(feas.all())
+    # soundness where the GPU's point is feasible; a feasible point is present
+    fg = fb["feasible"].bool()
+    assert bool((fb["bound"][fg] <= fb["primal"][fg] + 1e-6).all())
+    if not split:
+        assert bool(fg.any())
+
+
+def _oracle_traj(onet, ob, opts, t):
+    """The oracle's state after t steps (t = 0: the initial duals)."""
+    st = O.ascent(onet, ob, opts, iters=0)
+    for _ in range(t):
+        st = O.ascent(onet, ob, opts, state=st, iters=1)
+    return st
+
+
+def _check_step(rg, ost, may, what):
+    """Every dual differing from the oracle's beyond 1e-4 relative is one whose first
+    step may differ (first_step_may_differ)."""
+    tot = allowed = 0
+    for k in range(len(rg)):
+        diff = (rg[k].cpu().double() - ost["rho"][k]).abs()
+        differ = diff > 1e-4 * (ost["rho"][k].abs() + 1e-2)
+        allowed += int(may[k].sum())
+        tot += diff.numel()
+        assert not bool((differ & ~may[k]).any()), \
+            f"{what}: layer {k + 1}: {int((differ & ~may[k]).sum())} duals differ with no near-tie behind them"
+    print(f"  {what}: duals whose step may differ {allowed} of {tot}")
+
+
+def _start_point(onet, ob, init):
+    """Duals of the first step: CROWN's and zeros (formed on the GPU by the contraction
+    its first iteration repeats), or a generic point (the oracle's duals after two
+    steps from CROWN, rounded to FP32) set by the caller."""
+    if init != "given":
+        return None, True
+    st = _oracle_traj(onet, ob, O.AdamOpts(T=50), 2)
+    return [r.float() for r in st["rho"]], False
+
+
+@pytest.mark.parametrize("init", ["crown", "zero", "given"])
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("name", ["fc_tiny", "tiny_conv", "tiny_conv2", "tiny_conv3", "tiny_conv4", "base"])
-def test_first_steps_follow_the_oracle(name, engine):
-    """The first Adam steps from the CROWN point track the oracle elementwise: ties at
-    the CROWN kinks are resolved by the same rule on both sides."""
-    _case(f"first steps {name} engine={engine}")
+def test_first_step_follows_the_oracle(name, engine, init):
+    """One Adam step from the CROWN point, from zero duals and from a generic point set
+    by the caller: the GPU's duals equal the oracle's (1e-4 relative) except where the
+    step's sign may flip because s itself is within its proven error of 0."""
+    _case(f"first step {name} engine={engine} init={init}")
     P, inst, net, batch = _setup(name)
     onet = O.net_from_specs(inst.layers)
     ob = O.batch_from_instance(inst)
-    for t in (1, 3):
-        st = P.State(net, inst.B)
-        P.step(net, batch, st, iters=t, total_iters=50, engine=engine)
-        rg = st.get_rho()
-        ost = O.ascent(onet, ob, O.AdamOpts(T=50), iters=t)
-        tot = bad = 0
-        for k in range(len(rg)):
-            diff = (rg[k].cpu().double() - ost["rho"][k]).abs()
-            scale = ost["rho"][k].abs() + 1e-2
-            bad += int((diff > 1e-4 * scale).sum())
-            tot += diff.numel()
-        print(f"  t={t}: duals differing beyond 1e-4 relative: {bad} of {tot}")
-        assert bad <= 0.02 * tot
+    rho0, exact = _start_point(onet, ob, init)
+    st = P.State(net, inst.B)
+    if rho0 is not None:
+        st.set_rho(_to_gpu(rho0))
+    P.step(net, batch, st, iters=1, total_iters=50, engine=engine, init=init)
+    rg = st.get_rho()
+    opts = O.AdamOpts(T=50, init=init)
+    r0 = [r.double() for r in rho0] if rho0 is not None else None
+    ost = O.ascent(onet, ob, opts, rho0=r0, iters=1)
+    start = r0 if r0 is not None else O.ascent(onet, ob, opts, iters=0)["rho"]
+    _check_step(rg, ost, PT.first_step_may_differ(onet, ob, start, exact_ties_stable=exact), "t=1")
 
 
 @pytest.mark.parametrize("engine", ENGINES)
@@ -258,18 +355,20 @@ def test_error_codes_on_bad_input():
 
 @pytest.mark.parametrize("name", ["tiny_conv2", "base"])
 def test_engines_agree_over_first_steps(name):
-    """Both engines perform the same iteration (summation order aside)."""
+    """Both engines perform the same iteration (summation order aside): after one
+    step from a generic point their duals differ only where the step may differ
+    from the oracle's."""
     _case(f"engines agree {name}")
     P, inst, net, batch = _setup(name)
+    onet, ob = O.net_from_specs(inst.layers), O.batch_from_instance(inst)
+    rho0, _ = _start_point(onet, ob, "given")
     out = {}
     for eng in ENGINES:
         st = P.State(net, inst.B)
-        P.step(net, batch, st, iters=3, total_iters=50, engine=eng)
+        st.set_rho(_to_gpu(rho0))
+        P.step(net, batch, st, iters=1, total_iters=50, engine=eng, init="given")
         out[eng] = st.get_rho()
-    tot = bad = 0
-    for a, b in zip(out["resident"], out["layerwise"]):
-        diff = (a - b).abs()
-        bad += int((diff > 1e-4 * (b.abs() + 1e-2)).sum())
-        tot += diff.numel()
-    print(f"  duals differing beyond 1e-4 relative: {bad} of {tot}")
-    assert bad <= 0.02 * tot
+    may = PT.first_step_may_differ(onet, ob, [r.double() for r in rho0])
+    for k, (a, b) in enumerate(zip(out["resident"], out["layerwise"])):
+        differ = ((a - b).abs() > 1e-4 * (b.abs() + 1e-2)).cpu()
+        assert not bool((differ & ~may[k]).any()), f"layer {k + 1}: {int((differ & ~may[k]).sum())}"

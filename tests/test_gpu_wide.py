@@ -1,0 +1,106 @@
+"""The wide conv net (conv 16@4x4/2, conv 32@4x4/2, FC 100, FC 10) at B = 512, the
+benchmark's workload, through the C ABI and with the launch configurations the
+autotuner picks at that shape for each precision.
+
+Fixed duals: q within 1e-5 of its magnitude sum S (FP32) and 2^-7 S (BF16), and the
+supergradient to the matching bars away from near-ties, on all 512 subdomains.
+Ascent: T = 500 in FP32 and BF16 against the FP64 oracle's trajectory.  The error
+of each form against the oracle is reported per subdomain.  FP32 and BF16 are
+sign-like iterations whose near-tie decisions flip under rounding, so only the FP64
+engine is held to 1e-3 per subdomain (tests/test_gpu_fp64.py).  The forms here are
+held to soundness and to a spread band.
+"""
+import numpy as np
+import pytest
+import torch
+
+import ldgen
+from oracle import ld_oracle as O
+from tests import _parity as PT
+from tests.test_gpu_parity import _case, _check_dual_eval
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wide():
+    import paper_2104_06718_amd as P
+    inst = ldgen.make_instance("wide")
+    net = P.Net(inst.layers)
+    batch = P.Batch.from_instance(inst)
+    tuned = {}
+    for prec in ("fp32", "bf16"):
+        _case(f"autotune wide B={inst.B} {prec}")
+        tuned[prec] = P.autotune(net, batch, total_iters=500, precision=prec)
+        for e in tuned[prec]["layers"]:
+            tile = {f: e[f] for f in ("tn", "mwaves", "kwaves", "splits", "form")}
+            print(f"  {prec} layer {e['layer']} {e['dir']}: {tile} {e['us']:.1f} us", flush=True)
+    return P, inst, net, batch, tuned
+
+
+def test_wide_fixed_duals_fp32(wide):
+    P, inst, net, batch, _ = wide
+    _case(f"wide fp32 dual_eval random duals B={inst.B}")
+    _check_dual_eval(P, inst, net, batch, ldgen.random_duals(inst, seed=31, scale=0.3))
+    _case(f"wide fp32 dual_eval CROWN duals B={inst.B}")
+    onet = O.net_from_specs(inst.layers)
+    rho = [r.float().numpy() for r in O.crown_init(onet, O.batch_from_instance(inst))]
+    _check_dual_eval(P, inst, net, batch, rho, max_masked=1.0)
+
+
+def test_wide_fixed_duals_bf16(wide):
+    """BF16 operands (unit roundoff 2^-9) with FP32 accumulation: q within 2^-7 S and s
+    within supergrad_bound at the BF16 tie level."""
+    P, inst, net, batch, _ = wide
+    _case(f"wide bf16 dual_eval random duals B={inst.B}")
+    rho = ldgen.random_duals(inst, seed=37, scale=0.3)
+    q, s = P.dual_eval(net, batch, [torch.from_numpy(r).cuda() for r in rho], supergrad=True, precision="bf16")
+    torch.cuda.synchronize()
+    onet, ob = O.net_from_specs(inst.layers), O.batch_from_instance(inst)
+    orho = [torch.from_numpy(r).double() for r in rho]
+    ev = O.dual_eval(onet, ob, orho)
+    S = O.q_scale(onet, ob, orho, ev)
+    err = (q.cpu() - ev["q"]).abs()
+    print(f"  q: max err/S {(err / S).max().item():.2e}")
+    assert bool((err <= 2.0 ** -7 * S).all())
+    masks = PT.unstable_decisions(onet, ob, orho, ev, tie_rel=2.0 ** -7)
+    bound = PT.supergrad_bound(onet, ob, masks, PT.s_scale(onet, ev), 2.0 ** -7)
+    for k in range(len(s)):
+        d = (s[k].cpu().double() - ev["s"][k]).abs()
+        print(f"  layer {k + 1}: max |s_bf16 - s| / bound = {(d / bound[k].clamp_min(1e-30)).max().item():.3f}")
+        assert bool((d <= bound[k] + 1e-7).all())
+
+
+def _pct(d):
+    q = torch.quantile(d.double(), torch.tensor([0.5, 0.9, 0.99], dtype=torch.float64))
+    return (f"mean {d.mean().item():.3e} p50 {q[0].item():.3e} p90 {q[1].item():.3e} p99 {q[2].item():.3e} "
+            f"max {d.max().item():.3e}")
+
+
+def test_wide_ascent_against_oracle(wide):
+    P, inst, net, batch, tuned = wide
+    T = 500
+    res = {}
+    for prec in ("fp32", "bf16"):
+        _case(f"wide ascent {prec} B={inst.B} T={T} engine={tuned[prec]['engine']}")
+        st = P.State(net, inst.B)
+        P.step(net, batch, st, iters=T, total_iters=T, precision=prec)
+        res[prec] = {k: v.cpu() for k, v in P.final_bound(net, batch, st).items()}
+        torch.cuda.synchronize()
+        assert st.step_count() == T
+    onet, ob = O.net_from_specs(inst.layers), O.batch_from_instance(inst)
+    ofb = O.final_bound(onet, ob, O.ascent(onet, ob, O.AdamOpts(T=T)))
+    print(f"  oracle bound: mean {ofb['bound'].mean().item():.4f}")
+    for prec in ("fp32", "bf16"):
+        fb = res[prec]
+        d = fb["bound"] - ofb["bound"]
+        print(f"  {prec} bound - oracle: signed mean {d.mean().item():+.3e}; |.| {_pct(d.abs())}")
+        # soundness: q(rho^T) is a valid bound and the returned one is the best of two
+        assert bool((fb["bound"] >= fb["q_final"]).all())
+        feas = fb["feasible"].bool()
+        assert bool((fb["bound"][feas] <= fb["primal"][feas] + 1e-6).all())
+        # the spread of a sign-like iteration under rounding (measured max 0.04)
+        assert d.abs().mean().item() <= 1e-2
+        assert d.abs().max().item() <= 0.15
+    gap = (res["bf16"]["bound"] - res["fp32"]["bound"]).abs()
+    print(f"  |bf16 - fp32|: {_pct(gap)}; within 1e-3: {(gap <= 1e-3).double().mean().item():.3f}")
