@@ -114,6 +114,13 @@ CONFIGS: Dict[str, Dict] = {
     "tiny_conv4": dict(cfg=9, input=(8, 5, 5), eps=0.1, B=6, props=[4, 2], T=200,
                        arch=[_conv(8, 8, 3, 1, 1, 5), _conv(8, 16, 4, 2, 1, 5),
                              ("linear", 64, 6), ("linear", 6, 3)]),
+    # small nets whose exact minimum is enumerable (branch-and-bound pins): FC 6-12-8-2
+    # (12 root-ambiguous ReLUs) and conv 1->2 3x3/2 on 6x6, FC 6, FC 2 (8 of them);
+    # three properties each, objective y0 - y1
+    "bab_fc": dict(cfg=11, input=(6, 1, 1), eps=0.15, B=3, props=[1, 1, 1], T=100,
+                   arch=[("linear", 6, 12), ("linear", 12, 8), ("linear", 8, 2)]),
+    "bab_conv": dict(cfg=12, input=(1, 6, 6), eps=0.1, B=3, props=[1, 1, 1], T=100,
+                     arch=[_conv(1, 2, 3, 2, 1, 6), ("linear", 18, 6), ("linear", 6, 2)]),
     # MLP 784-1024x4-10, box +-0.02
     "mlp": dict(cfg=5, input=(784, 1, 1), eps=0.02, B=1024, props=[1024], T=0,
                 arch=[("linear", 784, 1024), ("linear", 1024, 1024), ("linear", 1024, 1024),

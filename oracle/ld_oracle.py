@@ -30,6 +30,9 @@ Network Verification via Lagrangian Decomposition":
 * Filtered Smart Branching (Sec. 4.2): the scores of eq:fsb-scores and
   eq:babsr-scores from one backward pass, the candidates of eq:fsb-prefilter and the
   split whose worse child has the best CROWN-or-WK bound;
+* branch and bound (Sec. 2.3.1, Sec. 5.2, Sec. 7.3): rounds over the B subproblems
+  with the lowest bounds, FSB splits, children warm-started from their parent's
+  duals, discarding on the threshold and the incumbent;
 * the P_k inner minimisation for sigmoid activations (App. E): the hull's tangent
   points, its envelopes and the minimum over the pieces (eq:siglinopt,
   eq:with_sig_subp).
@@ -666,6 +669,125 @@ def branch_children(batch: OBatch, layer: torch.Tensor, index: torch.Tensor) -> 
     return OBatch(cat([c.l0 for c in kids]), cat([c.u0 for c in kids]),
                   [cat([c.l[k] for c in kids]) for k in range(nh)], [cat([c.u[k] for c in kids]) for k in range(nh)],
                   cat([c.c for c in kids]))
+
+
+# ----------------------------------------------------------------------------
+# branch and bound (Sec. 2.3.1 operating principle; Sec. 5.2 batches of the B
+# subproblems with the lowest lower bounds; Sec. 7.3 children warm-started from the
+# parent's duals; Sec. 5.1.3 upper bound at the last P_0 minimiser)
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class BabOpts:
+    batch: int = 4               # B subproblems branched per round
+    root_iters: int = 100        # Adam steps at the root, from CROWN's duals
+    root_lr0: float = 1e-2
+    root_lr_end: float = 1e-4
+    iters: int = 50              # Adam steps of each child, from its parent's duals
+    lr0: float = 1e-3            # the children's step schedule (Sec. 7.3: 1e-3 -> 1e-4)
+    lr_end: float = 1e-4
+    threshold: float = 0.0       # the property: is min c^T f > threshold (-inf: no property, minimise)
+    gap: float = 0.0             # also discard subproblems with lb >= incumbent - gap
+    max_rounds: int = 200
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    tau: float = TAU_DEFAULT
+
+
+def _sub_batch(batch: OBatch, idx) -> OBatch:
+    ix = torch.as_tensor(list(idx), dtype=torch.long)
+    return OBatch(batch.l0[ix], batch.u0[ix], [x[ix] for x in batch.l], [x[ix] for x in batch.u], batch.c[ix])
+
+
+def _cat_batches(bs: List[OBatch]) -> OBatch:
+    cat = lambda xs: torch.cat(xs, dim=0)  # noqa: E731
+    nh = len(bs[0].l)
+    return OBatch(cat([b.l0 for b in bs]), cat([b.u0 for b in bs]), [cat([b.l[k] for b in bs]) for k in range(nh)],
+                  [cat([b.u[k] for b in bs]) for k in range(nh)], cat([b.c for b in bs]))
+
+
+def bab(net: List[OLayer], root: OBatch, opts: BabOpts) -> Dict:
+    """Branch and bound on one property (root: one subdomain).
+
+    Bounding: the Adam supergradient ascent (CROWN duals at the root, the parent's
+    final duals for a child), the returned bound max(q(rho^0), q(rho^T)), and for a
+    child the larger of that and its parent's bound (a child's minimum is at least
+    its parent's).  Upper bounds: the network at the bounding's last P_0 minimiser
+    when it is feasible; the incumbent is the smallest.  Each round takes the B open
+    subproblems with the lowest bounds (ties in creation order), splits each on the
+    ReLU Filtered Smart Branching picks, and bounds the 2B children.  A subproblem
+    is discarded when its bound is above the threshold or at least incumbent - gap.
+    A subproblem with no ambiguous ReLU is a leaf: it cannot be split further.
+
+    Status: 'falsified' (a feasible point at or below the threshold), 'verified'
+    (every subproblem discarded with its bound above the threshold), 'solved' (every
+    subproblem discarded, some by the gap: the minimum lies in [lower, incumbent]),
+    'limit' (rounds exhausted, or leaves left open)."""
+    def ascend(b, T, lr0, lr_end, rho0):
+        o = AdamOpts(T=T, lr0=lr0, lr_end=lr_end, beta1=opts.beta1, beta2=opts.beta2, eps=opts.eps, tau=opts.tau,
+                     init="crown" if rho0 is None else "given")
+        st = ascent(net, b, o, rho0=rho0)
+        return st, final_bound(net, b, st, opts.tau)
+
+    st, fb = ascend(root, opts.root_iters, opts.root_lr0, opts.root_lr_end, None)
+    res = dict(incumbent=float("inf"), x_best=None, rounds=0, bounded=1, leaves=0)
+    pruned_min = float("inf")
+    all_above = True
+
+    def offer(fbr, i):
+        if bool(fbr["feasible"][i]) and fbr["primal"][i].item() < res["incumbent"]:
+            res["incumbent"] = fbr["primal"][i].item()
+            res["x_best"] = fbr["x0"][i].clone()
+
+    offer(fb, 0)
+    seq = 0
+    open_: List = []
+    leaves: List = []
+
+    def place(lb, dom, rho):
+        nonlocal seq, pruned_min, all_above
+        if opts.threshold > -float("inf") and lb > opts.threshold:
+            pruned_min = min(pruned_min, lb)
+        elif lb >= res["incumbent"] - opts.gap:
+            pruned_min = min(pruned_min, lb)
+            all_above = False
+        else:
+            open_.append((lb, seq, dom, rho))
+            seq += 1
+
+    place(fb["bound"][0].item(), root, [r.clone() for r in st["rho"]])
+    while open_ and res["incumbent"] > opts.threshold and res["rounds"] < opts.max_rounds:
+        res["rounds"] += 1
+        open_.sort(key=lambda e: (e[0], e[1]))
+        take, open_[:] = open_[:opts.batch], open_[opts.batch:]
+        parents = _cat_batches([e[2] for e in take])
+        layer, index, _ = fsb_branch(net, parents)
+        split = [j for j in range(len(take)) if int(index[j]) >= 0]
+        for j in range(len(take)):
+            if int(index[j]) < 0:
+                leaves.append(take[j])
+        if not split:
+            continue
+        pb = _sub_batch(parents, split)
+        kids = branch_children(pb, layer[split], index[split])
+        rho0 = [torch.cat([torch.stack([take[j][3][k][0]] * 2) for j in split]) for k in range(len(net) - 1)]
+        st, fb = ascend(kids, opts.iters, opts.lr0, opts.lr_end, rho0)
+        res["bounded"] += kids.l0.shape[0]
+        for c in range(kids.l0.shape[0]):
+            offer(fb, c)
+        for c in range(kids.l0.shape[0]):
+            lb = max(fb["bound"][c].item(), take[split[c // 2]][0])
+            place(lb, _sub_batch(kids, [c]), [r[c:c + 1].clone() for r in st["rho"]])
+    res["leaves"] = len(leaves)
+    lower = min([e[0] for e in open_] + [e[0] for e in leaves] + [pruned_min])
+    res["lower"] = lower
+    if res["incumbent"] <= opts.threshold:
+        res["status"] = "falsified"
+    elif open_ or leaves:
+        res["status"] = "limit"
+    else:
+        res["status"] = "verified" if all_above else "solved"
+    return res
 
 
 # ----------------------------------------------------------------------------
