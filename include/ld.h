@@ -388,6 +388,56 @@ int ld_branch_children(const ld_net* net, const ld_batch* batch, const int* laye
                        float* const* u_out, float* c_out, float* const* rho_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* branch and bound (Sec. 2.3.1; batches of Sec. 5.2; warm starts of Sec. 7.3) */
+/* ------------------------------------------------------------------------- */
+/* Complete verification of one property: is min c^T f(x) over the input box
+ * (and within the root's intermediate bounds) above `threshold`?
+ *  - The root is bounded by ld_step from CROWN's duals (root_iters steps,
+ *    root_lr0 -> root_lr_end) and ld_final_bound.
+ *  - Each round takes the `batch` open subproblems with the lowest lower bounds
+ *    (ties in creation order).  It splits each on the ReLU ld_fsb_branch picks
+ *    (ld_branch_children), then bounds the 2*batch children by ld_step from
+ *    their parent's final duals (iters steps, lr0 -> lr_end) and ld_final_bound.
+ *    A child's bound is the larger of that and its parent's.
+ *  - Upper bounds: the network at each bounding's last P_0 minimiser, when every
+ *    pre-activation is within its bounds (Sec. 5.1.3); the smallest is the
+ *    incumbent.
+ *  - A subproblem is discarded when its bound is above `threshold`, or at least
+ *    incumbent - gap.  One with no ambiguous ReLU left is a leaf and stays open,
+ *    unsplit.
+ * threshold = -INFINITY minimises instead: the result brackets the minimum
+ * between `lower` and `incumbent`.  The open subproblems (their bounds and warm-start duals,
+ * (2 N_h + N_h) floats each) live in a device store of max_subproblems entries
+ * that the call allocates and frees; it stops with LD_BAB_LIMIT when the store is
+ * full, after max_rounds rounds, or with leaves left open.  Synchronous. */
+enum { LD_BAB_VERIFIED = 0, LD_BAB_FALSIFIED = 1, LD_BAB_SOLVED = 2, LD_BAB_LIMIT = 3 };
+typedef struct ld_bab_opts {
+  int batch;                 /* subproblems split per round (>= 1) */
+  int root_iters, iters;     /* Adam steps at the root and for each child (>= 0) */
+  float root_lr0, root_lr_end, lr0, lr_end;
+  float beta1, beta2, eps;   /* Adam constants (as ld_opts) */
+  float threshold;           /* the property is min > threshold; -INFINITY: minimise */
+  float gap;                 /* >= 0: also discard when bound >= incumbent - gap */
+  int max_rounds;            /* >= 0 */
+  int max_subproblems;       /* capacity of the store of open subproblems (>= 1) */
+  int precision;             /* LD_FP32 or LD_BF16 contractions in the ascents */
+  float tie_tau;             /* as ld_opts */
+} ld_bab_opts;
+typedef struct ld_bab_result {
+  int status;                /* LD_BAB_* */
+  double lower;              /* lower bound on the minimum over every subproblem left */
+  double incumbent;          /* smallest network value at a feasible point (+inf if none) */
+  int rounds;
+  int leaves;                /* subproblems with no ambiguous ReLU left open */
+  long long bounded;         /* subproblems bounded, the root included */
+  long long max_open;        /* the store's peak occupancy */
+} ld_bab_result;
+/* root: a batch of one subdomain (B = 1).  result: host.  x_best: NULL or host
+ * float[n_0], receives the input of the incumbent (unchanged when none). */
+int ld_bab(const ld_net* net, const ld_batch* root, const ld_bab_opts* opts, ld_bab_result* result, float* x_best,
+           hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
 /* intermediate bounds (Sec. 2.2.3), batched over neurons (Sec. 5.2)          */
 /* ------------------------------------------------------------------------- */
 /* LD bounds on the pre-activations of a layer j: `sub` is the network of the

@@ -32,7 +32,7 @@ EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num
             "ld_state_get_rho", "ld_state_get_rho_f64", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval", "ld_dual_eval_f64",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
-            "ld_intermediate_bounds", "ld_fsb_branch", "ld_branch_children", "ld_sigmoid_hull", "ld_sigmoid_inner_min", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
+            "ld_intermediate_bounds", "ld_fsb_branch", "ld_bab", "ld_branch_children", "ld_sigmoid_hull", "ld_sigmoid_inner_min", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
 
 
 class LDError(RuntimeError):
@@ -68,6 +68,23 @@ class ld_prox_opts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("total_iters", ctypes.c_int), ("inner_iters", ctypes.c_int),
                 ("eta0", ctypes.c_float), ("eta_end", ctypes.c_float), ("mu", ctypes.c_float),
                 ("precision", ctypes.c_int), ("init", ctypes.c_int), ("tie_tau", ctypes.c_float)]
+
+
+class ld_bab_opts(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int), ("root_iters", ctypes.c_int), ("iters", ctypes.c_int),
+                ("root_lr0", ctypes.c_float), ("root_lr_end", ctypes.c_float), ("lr0", ctypes.c_float),
+                ("lr_end", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("threshold", ctypes.c_float), ("gap", ctypes.c_float), ("max_rounds", ctypes.c_int),
+                ("max_subproblems", ctypes.c_int), ("precision", ctypes.c_int), ("tie_tau", ctypes.c_float)]
+
+
+class ld_bab_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("lower", ctypes.c_double), ("incumbent", ctypes.c_double),
+                ("rounds", ctypes.c_int), ("leaves", ctypes.c_int), ("bounded", ctypes.c_longlong),
+                ("max_open", ctypes.c_longlong)]
+
+
+BAB_STATUS = {0: "verified", 1: "falsified", 2: "solved", 3: "limit"}
 
 
 class ld_tile(ctypes.Structure):
@@ -118,6 +135,7 @@ def load_library(path: Optional[str] = None):
     lib.ld_final_bound.argtypes = [V, P(ld_batch), V, V, V, V, V, ctypes.c_float, V]
     lib.ld_intermediate_bounds.argtypes = [V, P(ld_batch), P(ld_opts), I, V, V, V]
     lib.ld_fsb_branch.argtypes = [V, P(ld_batch), V, V, V, V, V]
+    lib.ld_bab.argtypes = [V, P(ld_batch), P(ld_bab_opts), P(ld_bab_result), P(ctypes.c_float), V]
     lib.ld_sigmoid_hull.argtypes = [ctypes.c_longlong, V, V, V, V, V]
     lib.ld_sigmoid_inner_min.argtypes = [ctypes.c_longlong, V, V, V, V, V, V, V, V, V, V]
     lib.ld_branch_children.argtypes = [V, P(ld_batch), V, V, P(V), V, V, P(V), P(V), V, P(V), V]
@@ -358,6 +376,24 @@ def fsb_branch(net: Net, batch: Batch, candidates=False, stream=None):
                                  ctypes.c_void_p(index.data_ptr()), ctypes.c_void_p(value.data_ptr()),
                                  ctypes.c_void_p(cand.data_ptr()) if cand is not None else None, _stream(stream)))
     return (layer, index, value, cand) if candidates else (layer, index, value)
+
+
+def bab(net: Net, root: Batch, threshold=0.0, gap=0.0, batch=64, root_iters=100, iters=50, root_lr0=1e-2,
+        root_lr_end=1e-4, lr0=1e-3, lr_end=1e-4, beta1=0.9, beta2=0.999, eps=1e-8, max_rounds=1000,
+        max_subproblems=1 << 16, precision="fp32", tau: float = TAU_DEFAULT, stream=None):
+    """Branch and bound on one property (ld_bab): root is a Batch of one subdomain.
+    Returns a dict with status ('verified', 'falsified', 'solved', 'limit'), lower,
+    incumbent, rounds, leaves, bounded, max_open and x_best (the incumbent's input,
+    a float32 CPU tensor, or None)."""
+    o = ld_bab_opts(int(batch), int(root_iters), int(iters), root_lr0, root_lr_end, lr0, lr_end, beta1, beta2, eps,
+                    float(threshold), float(gap), int(max_rounds), int(max_subproblems), _PREC[precision], tau)
+    r = ld_bab_result()
+    x = (ctypes.c_float * net.widths[0])(*([float("nan")] * net.widths[0]))
+    _check(net.lib.ld_bab(net.handle, ctypes.byref(root.struct), ctypes.byref(o), ctypes.byref(r), x,
+                          _stream(stream)))
+    xb = torch.tensor(list(x), dtype=torch.float32)
+    return dict(status=BAB_STATUS[r.status], lower=r.lower, incumbent=r.incumbent, rounds=r.rounds, leaves=r.leaves,
+                bounded=r.bounded, max_open=r.max_open, x_best=None if bool(torch.isnan(xb).all()) else xb)
 
 
 def branch_children(net: Net, batch: Batch, layer: torch.Tensor, index: torch.Tensor, rho=None, stream=None):

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_NAME = "libld_mi355x.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["csrc/ld_kernels.hip", "csrc/ld_resident.hip", "csrc/ld_fp64.hip", "csrc/ld_prox.hip", "csrc/ld_interm.hip", "csrc/ld_fsb.hip", "csrc/ld_sigmoid.hip", "csrc/ld_api.hip"]
+SOURCES = ["csrc/ld_kernels.hip", "csrc/ld_resident.hip", "csrc/ld_fp64.hip", "csrc/ld_prox.hip", "csrc/ld_interm.hip", "csrc/ld_fsb.hip", "csrc/ld_sigmoid.hip", "csrc/ld_bab.hip", "csrc/ld_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

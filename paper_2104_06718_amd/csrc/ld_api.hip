@@ -20,6 +20,7 @@
 #include <array>
 #include <functional>
 #include <map>
+#include <queue>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -2746,6 +2747,289 @@ int ld_branch_children(const ld_net* net, const ld_batch* bt, const int* layer, 
     K.width[a] = w[a];
   }
   LD_HIP(launch_branch_children(K, B, nh, layer, index, lo.data(), hi.data(), wid.data(), s));
+  return LD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// branch and bound (Sec. 2.3.1, Sec. 5.2, Sec. 7.3)
+// ---------------------------------------------------------------------------
+int ld_bab(const ld_net* net, const ld_batch* root, const ld_bab_opts* o, ld_bab_result* res, float* x_best,
+           hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_batch(net, root));
+  if (!o || !res) return fail(LD_E_ARG, "NULL argument");
+  if (root->B != 1) return fail(LD_E_ARG, "the root batch must hold one subdomain");
+  if (o->batch < 1 || o->root_iters < 0 || o->iters < 0 || o->max_rounds < 0 || o->max_subproblems < 1)
+    return fail(LD_E_ARG, "batch, max_subproblems >= 1 and iteration counts >= 0 required");
+  if (o->precision != LD_FP32 && o->precision != LD_BF16)
+    return fail(LD_E_UNSUPPORTED, "branch and bound bounds with LD_FP32 or LD_BF16");
+  if (std::isnan(o->threshold) || !(o->gap >= 0.f)) return fail(LD_E_ARG, "threshold must not be NaN, gap >= 0");
+  if (net->n - 1 > kFsbMaxHidden) return fail(LD_E_UNSUPPORTED, "more than 16 hidden layers");
+  const int n = net->n, nh = n - 1, B = o->batch, C2 = 2 * B, n0 = net->n0, nout = width(net, n);
+  const long long cap = o->max_subproblems;
+  // device memory: the store (l_k, u_k, rho_k per slot), the parents' and the
+  // children's batches, the branching decisions, the bounds, the row pairs
+  std::vector<size_t> sz;
+  auto add = [&](size_t bytes) {
+    sz.push_back(round_up(std::max<size_t>(bytes, 4), 256));
+    return sz.size() - 1;
+  };
+  std::vector<size_t> i_sl, i_su, i_sr, i_pl, i_pu, i_pr, i_cl, i_cu;
+  for (int k = 1; k <= nh; ++k) {
+    const size_t w = (size_t)width(net, k) * 4;
+    i_sl.push_back(add(cap * w));
+    i_su.push_back(add(cap * w));
+    i_sr.push_back(add(cap * w));
+    i_pl.push_back(add(B * w));
+    i_pu.push_back(add(B * w));
+    i_pr.push_back(add(B * w));
+    i_cl.push_back(add(C2 * w));
+    i_cu.push_back(add(C2 * w));
+  }
+  const size_t i_pl0 = add((size_t)B * n0 * 4), i_pu0 = add((size_t)B * n0 * 4), i_pc = add((size_t)B * nout * 4);
+  const size_t i_cl0 = add((size_t)C2 * n0 * 4), i_cu0 = add((size_t)C2 * n0 * 4), i_cc = add((size_t)C2 * nout * 4);
+  std::vector<size_t> i_crho;
+  for (int k = 1; k <= nh; ++k) i_crho.push_back(add((size_t)C2 * width(net, k) * 4));
+  const size_t i_layer = add((size_t)B * 4), i_index = add((size_t)B * 4), i_value = add((size_t)B * 8);
+  const size_t i_bound = add((size_t)C2 * 8), i_primal = add((size_t)C2 * 8), i_feas = add((size_t)C2 * 4);
+  const size_t i_pairs = add((size_t)C2 * 8);
+  std::vector<size_t> off(sz.size());
+  size_t total = 0;
+  for (size_t i = 0; i < sz.size(); ++i) {
+    off[i] = total;
+    total += sz[i];
+  }
+  struct Res {
+    void* base = nullptr;
+    ld_state* root_st = nullptr;
+    ld_state* kid_st = nullptr;
+    ~Res() {
+      ld_state_destroy(kid_st);
+      ld_state_destroy(root_st);
+      if (base) (void)hipFree(base);
+    }
+  } r;
+  if (hipMalloc(&r.base, total) != hipSuccess) return fail(LD_E_NOMEM, "branch and bound: hipMalloc of the store failed");
+  char* cb = (char*)r.base;
+  auto F = [&](size_t i) { return (float*)(cb + off[i]); };
+  LD_TRY(ld_state_create(net, 1, &r.root_st));
+  LD_TRY(ld_state_create(net, C2, &r.kid_st));
+  std::vector<const float*> pl(nh), pu(nh), cl(nh), cu(nh);
+  std::vector<float*> plw(nh), puw(nh), prw(nh), clw(nh), cuw(nh), crw(nh);
+  for (int k = 0; k < nh; ++k) {
+    plw[k] = F(i_pl[k]);
+    puw[k] = F(i_pu[k]);
+    prw[k] = F(i_pr[k]);
+    clw[k] = F(i_cl[k]);
+    cuw[k] = F(i_cu[k]);
+    crw[k] = F(i_crho[k]);
+    pl[k] = plw[k];
+    pu[k] = puw[k];
+    cl[k] = clw[k];
+    cu[k] = cuw[k];
+  }
+  ld_batch pb{B, F(i_pl0), F(i_pu0), pl.data(), pu.data(), F(i_pc)};
+  ld_batch kb{C2, F(i_cl0), F(i_cu0), cl.data(), cu.data(), F(i_cc)};
+  int2* pairs = (int2*)(cb + off[i_pairs]);
+  int* d_layer = (int*)(cb + off[i_layer]);
+  int* d_index = (int*)(cb + off[i_index]);
+  double* d_bound = (double*)(cb + off[i_bound]);
+  double* d_primal = (double*)(cb + off[i_primal]);
+  int* d_feas = (int*)(cb + off[i_feas]);
+  // packs of row moves: the store <-> a batch; the root's box and objective to a batch
+  auto pack = [&](const std::vector<const float*>& src, const std::vector<float*>& dst, const std::vector<int>& w) {
+    IntermPack K;
+    std::memset(&K, 0, sizeof(K));
+    K.n = (int)src.size();
+    for (int a = 0; a < K.n; ++a) {
+      K.src[a] = src[a];
+      K.dst[a] = dst[a];
+      K.width[a] = w[a];
+    }
+    return K;
+  };
+  std::vector<int> wst;
+  std::vector<const float*> store_src, kid_src;
+  std::vector<float*> store_dst, parent_dst;
+  for (int k = 0; k < nh; ++k) wst.insert(wst.end(), 3, width(net, k + 1));
+  for (int k = 0; k < nh; ++k) {
+    store_src.insert(store_src.end(), {F(i_sl[k]), F(i_su[k]), F(i_sr[k])});
+    store_dst.insert(store_dst.end(), {F(i_sl[k]), F(i_su[k]), F(i_sr[k])});
+    parent_dst.insert(parent_dst.end(), {plw[k], puw[k], prw[k]});
+    kid_src.insert(kid_src.end(), {clw[k], cuw[k], r.kid_st->rho[k]});
+  }
+  const IntermPack gather = pack(store_src, parent_dst, wst);   // store slot -> parent row
+  const IntermPack scatter = pack(kid_src, store_dst, wst);     // child row -> store slot
+  const IntermPack box = pack({root->l0, root->u0, root->c}, {F(i_pl0), F(i_pu0), F(i_pc)}, {n0, n0, nout});
+  std::vector<const float*> root_src;
+  for (int k = 0; k < nh; ++k) root_src.insert(root_src.end(), {root->l[k], root->u[k], r.root_st->rho[k]});
+  const IntermPack root_in = pack(root_src, store_dst, wst);   // the root to its slot
+  // row pairs to the device; synchronous, so that the host array is never read
+  // after it changes and the previous moves have finished with the device array
+  auto put_pairs = [&](const std::vector<int2>& v) -> int {
+    LD_HIP(hipMemcpyAsync(pairs, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    LD_HIP(hipStreamSynchronize(s));
+    return LD_OK;
+  };
+  ld_opts so;
+  std::memset(&so, 0, sizeof(so));
+  so.beta1 = o->beta1;
+  so.beta2 = o->beta2;
+  so.eps = o->eps;
+  so.precision = o->precision;
+  so.tie_tau = o->tie_tau;
+  so.engine = LD_ENGINE_LAYERWISE;
+  // ---- the root ----
+  so.iters = o->root_iters;
+  so.total_iters = std::max(1, o->root_iters);
+  so.lr0 = o->root_lr0;
+  so.lr_end = o->root_lr_end;
+  so.init = LD_INIT_CROWN;
+  LD_TRY(ld_step(net, root, r.root_st, &so, s));
+  LD_TRY(ld_final_bound(net, root, r.root_st, d_bound, nullptr, d_primal, d_feas, o->tie_tau, s));
+  double hb[1], hp[1];
+  int hf[1];
+  LD_HIP(hipMemcpyAsync(hb, d_bound, 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipMemcpyAsync(hp, d_primal, 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipMemcpyAsync(hf, d_feas, 4, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  std::memset(res, 0, sizeof(*res));
+  res->incumbent = INFINITY;
+  res->bounded = 1;
+  std::vector<float> xb_host((size_t)n0);
+  bool have_x = false;
+  if (hf[0] && hp[0] < res->incumbent) {
+    res->incumbent = hp[0];
+    LD_HIP(hipMemcpy(xb_host.data(), r.root_st->ws.xs[0], (size_t)n0 * 4, hipMemcpyDeviceToHost));
+    have_x = true;
+  }
+  // ---- the open subproblems: a heap on (bound, creation order) and free slots ----
+  struct Open {
+    double lb;
+    long long seq;
+    int slot;
+    bool operator<(const Open& q) const { return lb > q.lb || (lb == q.lb && seq > q.seq); }
+  };
+  std::priority_queue<Open> open;
+  std::vector<int> free_slots;
+  for (long long i = cap - 1; i >= 0; --i) free_slots.push_back((int)i);
+  long long seq = 0;
+  double pruned_min = INFINITY, leaf_min = INFINITY;
+  bool all_above = true, full = false;
+  const bool has_thr = o->threshold > -INFINITY;
+  auto keep = [&](double lb) -> bool {
+    if (has_thr && lb > o->threshold) {
+      pruned_min = std::min(pruned_min, lb);
+      return false;
+    }
+    if (lb >= res->incumbent - o->gap) {
+      pruned_min = std::min(pruned_min, lb);
+      all_above = false;
+      return false;
+    }
+    return true;
+  };
+  if (keep(hb[0])) {
+    const int slot = free_slots.back();
+    free_slots.pop_back();
+    LD_TRY(put_pairs({int2{0, slot}}));
+    LD_HIP(launch_bab_rows(root_in, pairs, 1, 0, s));
+    open.push(Open{hb[0], seq++, slot});
+  }
+  res->max_open = (long long)open.size();
+  std::vector<int> h_layer(B), h_index(B), h_feas(C2);
+  std::vector<double> h_bound(C2), h_primal(C2);
+  // ---- rounds ----
+  while (!open.empty() && res->incumbent > o->threshold && res->rounds < o->max_rounds && !full) {
+    res->rounds++;
+    std::vector<Open> par;
+    while (!open.empty() && (int)par.size() < B) {
+      par.push_back(open.top());
+      open.pop();
+    }
+    const int np = (int)par.size();
+    // the parents into the batch (rows past np repeat the first parent)
+    std::vector<int2> pv(B);
+    for (int j = 0; j < B; ++j) pv[j] = int2{par[j < np ? j : 0].slot, j};
+    LD_TRY(put_pairs(pv));
+    LD_HIP(launch_bab_rows(gather, pairs, B, 0, s));
+    LD_HIP(launch_bab_rows(box, pairs, B, 1, s));
+    for (const Open& p : par) free_slots.push_back(p.slot);
+    // split, children with their parent's duals, bound them
+    LD_TRY(ld_fsb_branch(net, &pb, d_layer, d_index, (double*)(cb + off[i_value]), nullptr, s));
+    std::vector<const float*> prc(prw.begin(), prw.end());
+    LD_TRY(ld_branch_children(net, &pb, d_layer, d_index, prc.data(), F(i_cl0), F(i_cu0), clw.data(), cuw.data(),
+                              F(i_cc), crw.data(), s));
+    std::vector<const float*> crc(crw.begin(), crw.end());
+    LD_TRY(ld_state_set_rho(r.kid_st, crc.data(), s));
+    so.iters = o->iters;
+    so.total_iters = std::max(1, o->iters);
+    so.lr0 = o->lr0;
+    so.lr_end = o->lr_end;
+    so.init = LD_INIT_GIVEN;
+    LD_TRY(ld_step(net, &kb, r.kid_st, &so, s));
+    LD_TRY(ld_final_bound(net, &kb, r.kid_st, d_bound, nullptr, d_primal, d_feas, o->tie_tau, s));
+    LD_HIP(hipMemcpyAsync(h_index.data(), d_index, (size_t)B * 4, hipMemcpyDeviceToHost, s));
+    LD_HIP(hipMemcpyAsync(h_bound.data(), d_bound, (size_t)C2 * 8, hipMemcpyDeviceToHost, s));
+    LD_HIP(hipMemcpyAsync(h_primal.data(), d_primal, (size_t)C2 * 8, hipMemcpyDeviceToHost, s));
+    LD_HIP(hipMemcpyAsync(h_feas.data(), d_feas, (size_t)C2 * 4, hipMemcpyDeviceToHost, s));
+    LD_HIP(hipStreamSynchronize(s));
+    // incumbent, then the children that stay open
+    int best = -1;
+    for (int j = 0; j < np; ++j) {
+      if (h_index[j] < 0) continue;
+      for (int c = 2 * j; c <= 2 * j + 1; ++c)
+        if (h_feas[c] && h_primal[c] < res->incumbent) {
+          res->incumbent = h_primal[c];
+          best = c;
+        }
+    }
+    if (best >= 0) {
+      LD_HIP(hipMemcpy(xb_host.data(), (const float*)r.kid_st->ws.xs[0] + (size_t)best * n0, (size_t)n0 * 4,
+                       hipMemcpyDeviceToHost));
+      have_x = true;
+    }
+    std::vector<int2> sv;
+    for (int j = 0; j < np; ++j) {
+      if (h_index[j] < 0) {  // no ambiguous ReLU left: a leaf
+        res->leaves++;
+        leaf_min = std::min(leaf_min, par[j].lb);
+        continue;
+      }
+      res->bounded += 2;
+      for (int c = 2 * j; c <= 2 * j + 1; ++c) {
+        const double lb = std::max(h_bound[c], par[j].lb);
+        if (!keep(lb)) continue;
+        if (free_slots.empty()) {
+          full = true;
+          pruned_min = std::min(pruned_min, lb);  // dropped unexplored: still counts in the lower bound
+          all_above = false;
+          continue;
+        }
+        const int slot = free_slots.back();
+        free_slots.pop_back();
+        sv.push_back(int2{c, slot});
+        open.push(Open{lb, seq++, slot});
+      }
+    }
+    if (!sv.empty()) {
+      LD_TRY(put_pairs(sv));
+      LD_HIP(launch_bab_rows(scatter, pairs, (int)sv.size(), 0, s));
+    }
+    res->max_open = std::max(res->max_open, (long long)open.size());
+  }
+  double lower = std::min(pruned_min, leaf_min);
+  const bool left_open = !open.empty();
+  for (; !open.empty(); open.pop()) lower = std::min(lower, open.top().lb);
+  res->lower = lower;
+  if (res->incumbent <= o->threshold)
+    res->status = LD_BAB_FALSIFIED;
+  else if (left_open || res->leaves > 0 || full)
+    res->status = LD_BAB_LIMIT;
+  else
+    res->status = all_above ? LD_BAB_VERIFIED : LD_BAB_SOLVED;
+  if (x_best && have_x) std::memcpy(x_best, xb_host.data(), (size_t)n0 * 4);
+  LD_HIP(hipStreamSynchronize(s));
   return LD_OK;
 }
 

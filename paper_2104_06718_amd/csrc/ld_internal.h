@@ -289,6 +289,9 @@ hipError_t launch_fsb_select(int B, int n_hidden, const int* cand, const double*
                              int* layer, int* index, double* value, hipStream_t s);
 hipError_t launch_interm_collect(int C, long long start, int P, int nj, const double* bound, float* lo, float* hi,
                                  hipStream_t s);
+// branch and bound (ld_bab.hip): for each of `count` pairs, row pairs[p].x of every
+// array of K (row 0 with broadcast) to row pairs[p].y of its destination
+hipError_t launch_bab_rows(const IntermPack& K, const int2* pairs, int count, int broadcast, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // FP64 engine (ld_fp64.hip): direct FP64 contractions with fused epilogues.
