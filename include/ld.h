@@ -191,6 +191,19 @@ int ld_init_duals(const ld_net* net, const ld_batch* batch, int init, int precis
 int ld_dual_eval(const ld_net* net, const ld_batch* batch, const float* const* rho,
                  double* q, float* const* supergrad, int precision, float tie_tau,
                  hipStream_t stream);
+/* As ld_dual_eval (LD_FP32 or LD_BF16), for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It allocates nothing: its workspace is a 64 MiB array of the
+ * library in each device's memory, held for the life of the process (the call
+ * returns LD_E_NOMEM, with the size it needs, for a batch whose workspace does not
+ * fit: about 137 KB per subdomain of the wide conv net).  Every call on a device
+ * shares that device's array and leaves its contents behind; calls that overlap
+ * on one device (several streams or threads) race.  Fully-connected products run
+ * without split-K, so results can differ from ld_dual_eval's in summation order.
+ * With validation on (ld_set_validation) the call synchronises `stream`; turn it
+ * off to capture the call in a graph. */
+int ld_dual_eval_noalloc(const ld_net* net, const ld_batch* batch, const float* const* rho, double* q,
+                         float* const* supergrad, int precision, float tie_tau, hipStream_t stream);
 /* As ld_dual_eval in FP64 with FP64 duals: rho host array of n-1 device pointers
  * double [B, n_k]; supergrad (optional) double [B, n_k].  Same workspace rules. */
 int ld_dual_eval_f64(const ld_net* net, const ld_batch* batch, const double* const* rho, double* q,

@@ -29,7 +29,7 @@ _ENGINE = {"auto": LD_ENGINE_AUTO, "resident": LD_ENGINE_RESIDENT, "layerwise": 
 
 EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num_layers",
             "ld_set_validation", "ld_state_create", "ld_state_destroy", "ld_state_set_rho",
-            "ld_state_get_rho", "ld_state_get_rho_f64", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval", "ld_dual_eval_f64",
+            "ld_state_get_rho", "ld_state_get_rho_f64", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval", "ld_dual_eval_noalloc", "ld_dual_eval_f64",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
             "ld_intermediate_bounds", "ld_fsb_branch", "ld_bab", "ld_branch_children", "ld_sigmoid_hull", "ld_sigmoid_inner_min", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
@@ -126,6 +126,7 @@ def load_library(path: Optional[str] = None):
     lib.ld_init_duals.argtypes = [V, P(ld_batch), I, I, P(V), V]
     lib.ld_dual_eval.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
     lib.ld_dual_eval_f64.argtypes = [V, P(ld_batch), P(V), V, P(V), ctypes.c_float, V]
+    lib.ld_dual_eval_noalloc.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
     lib.ld_step.argtypes = [V, P(ld_batch), V, P(ld_opts), V]
     lib.ld_autotune.argtypes = [V, P(ld_batch), P(ld_opts), V]
     lib.ld_tuned_config.argtypes = [V, I, I, I, I, P(ld_tile), P(ctypes.c_double)]
@@ -315,6 +316,18 @@ def dual_eval(net: Net, batch: Batch, rho: List[torch.Tensor], supergrad=True, p
     _check(net.lib.ld_dual_eval(net.handle, ctypes.byref(batch.struct), _ptrs(rho), ctypes.c_void_p(q.data_ptr()),
                                 sp, _PREC[precision], ctypes.c_float(tau), _stream(stream)))
     return q, s
+
+
+def dual_eval_noalloc(net: Net, batch: Batch, rho: List[torch.Tensor], q: torch.Tensor,
+                      supergrad: Optional[List[torch.Tensor]] = None, precision="fp32", tau: float = TAU_DEFAULT,
+                      stream=None):
+    """ld_dual_eval_noalloc into caller-given outputs: q (float64 [B]) and, if given,
+    supergrad (float32 [B, n_k] per hidden layer).  The library allocates nothing."""
+    rho = [_dev_f32(r, "rho") for r in rho]
+    sp = _ptrs([_dev_f32(t, "supergrad") for t in supergrad]) if supergrad is not None else None
+    _check(net.lib.ld_dual_eval_noalloc(net.handle, ctypes.byref(batch.struct), _ptrs(rho),
+                                        ctypes.c_void_p(q.data_ptr()), sp, _PREC[precision], ctypes.c_float(tau),
+                                        _stream(stream)))
 
 
 def dual_eval_f64(net: Net, batch: Batch, rho: List[torch.Tensor], supergrad=True, tau: float = TAU_DEFAULT,

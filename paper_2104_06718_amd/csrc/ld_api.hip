@@ -728,6 +728,9 @@ std::vector<Tile> tile_candidates(const Job& J, int B) {
 // kernel repeats: the duals start exactly on kinks of the dual (Prop. 2), so the
 // first iteration must see the very same coefficients as the initialisation.
 thread_local int g_form_override = -1;
+// Set while a caller's workspace has no split-K scratch (the allocation-free dual
+// evaluation): fully-connected products then run unsplit.
+thread_local int g_no_split = 0;
 
 Tile pick_tile(const ld_net* net, int layer, int dir, int B, int mma) {
   ld_net* mnet = const_cast<ld_net*>(net);
@@ -764,7 +767,8 @@ hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, 
     const int parts = (J.has_col && t.form == 0) ? 1 : std::min(std::max(1, t.splits), dst_H);
     return launch_conv(g, J.dev, nc, B, src, src_bf16, mma, e, t.tn, parts, s);
   }
-  SplitArgs sp{fc_splits(J, B, t.tn, t.splits), ws.partial + (size_t)slot * kPartialLayer, ws.counters};
+  SplitArgs sp{g_no_split ? 1 : fc_splits(J, B, t.tn, t.splits),
+               ws.partial ? ws.partial + (size_t)slot * kPartialLayer : nullptr, ws.counters};
   return launch_fc(g[0], src, src_bf16, mma, e, t.tn, sp, std::max(1, t.wm), t.tm, s);
 }
 
@@ -806,7 +810,7 @@ int check_batch(const ld_net* net, const ld_batch* bt) {
 
 int validate_values(const ld_net* net, const ld_batch* bt, Workspace& ws, hipStream_t s) {
   if (!g_validate || bt->B == 0) return LD_OK;
-  LD_HIP(hipMemsetAsync(ws.bad, 0, 4, s));
+  LD_HIP(launch_fill_i32(ws.bad, 1, 0, s));
   LD_HIP(launch_validate(bt->B, net->n0, bt->l0, bt->u0, ws.bad, s));
   for (int k = 1; k <= net->n - 1; ++k) LD_HIP(launch_validate(bt->B, width(net, k), bt->l[k - 1], bt->u[k - 1], ws.bad, s));
   LD_HIP(launch_validate(bt->B, width(net, net->n), bt->c, bt->c, ws.bad, s));
@@ -1514,6 +1518,68 @@ int run_resident(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_o
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free dual evaluation: one array per device, held for
+// the life of the process.  Host code never uses the array's name as an address:
+// its device address comes from hipGetSymbolAddress, once per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// The scratch address of the current device (looked up on its first use).
+static int scratch_address(void** out) {
+  int dev = 0;
+  LD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LD_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(LD_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LD_OK;
+}
+
+// The buffers of a dual evaluation of B subdomains carved from `base` (the layout
+// of ws_alloc without the forward-pass activations and the split-K scratch);
+// *need receives the bytes the layout takes.
+static int ws_carve(const ld_net* net, Workspace& ws, int B, char* base, size_t cap, size_t* need) {
+  const int n = net->n;
+  size_t total = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = total;
+    total += round_up(std::max<size_t>(bytes, 1), 256);
+    return o;
+  };
+  std::vector<size_t> oxs, oxb, oval;
+  for (int k = 0; k <= n - 2; ++k) oxs.push_back(take((size_t)B * width(net, k) * 4));
+  for (int k = 0; k <= n - 1; ++k) oxb.push_back(take(k == 0 ? 4 : (size_t)B * width(net, k) * 4));
+  for (int k = 0; k <= n - 1; ++k) oval.push_back(take((size_t)B * width(net, k) * 8));
+  const size_t ogc = take((size_t)B * width(net, n - 1) * 4), ocb = take((size_t)B * 8);
+  const size_t oq = take((size_t)B * 8), ofl = take((size_t)B * 4), obad = take(4);
+  *need = total;
+  if (total > cap) return LD_OK;
+  ws = Workspace();
+  ws.B = B;
+  ws.xs.assign(n - 1, nullptr);
+  ws.xb.assign(n, nullptr);
+  ws.val.assign(n, nullptr);
+  for (int k = 0; k <= n - 2; ++k) ws.xs[k] = base + oxs[k];
+  for (int k = 1; k <= n - 1; ++k) ws.xb[k] = (float*)(base + oxb[k]);
+  for (int k = 0; k <= n - 1; ++k) ws.val[k] = (double*)(base + oval[k]);
+  ws.gconst = (float*)(base + ogc);
+  ws.cb = (double*)(base + ocb);
+  ws.qtmp = (double*)(base + oq);
+  ws.flag = (int*)(base + ofl);
+  ws.bad = (int*)(base + obad);
+  return LD_OK;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1836,6 +1902,34 @@ int ld_dual_eval(const ld_net* net, const ld_batch* bt, const float* const* rho,
     return f64_dual_eval_impl(net, bt, r.data(), w, q, nullptr, supergrad, tie_tau, s);
   }
   return dual_eval_impl(net, bt, rho, mnet->ws, q, supergrad, precision, tie_tau, s);
+}
+
+int ld_dual_eval_noalloc(const ld_net* net, const ld_batch* bt, const float* const* rho, double* q,
+                         float* const* supergrad, int precision, float tie_tau, hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_batch(net, bt));
+  if (!rho) return fail(LD_E_ARG, "rho is NULL");
+  if (precision != LD_FP32 && precision != LD_BF16) return fail(LD_E_ARG, "precision must be LD_FP32 or LD_BF16");
+  if (!(tie_tau >= 0.f) || !std::isfinite(tie_tau)) return fail(LD_E_ARG, "tie_tau must be finite and >= 0");
+  if (bt->B == 0) return LD_OK;
+  for (int k = 0; k < net->n - 1; ++k) {
+    if (!rho[k]) return fail(LD_E_ARG, "rho[k] is NULL");
+    if (!aligned16(rho[k])) return fail(LD_E_ARG, "rho[k] must be 16-byte aligned");
+    if (supergrad && supergrad[k] && !aligned16(supergrad[k])) return fail(LD_E_ARG, "supergrad[k] must be 16-byte aligned");
+  }
+  void* base = nullptr;
+  LD_TRY(scratch_address(&base));
+  Workspace ws;
+  size_t need = 0;
+  LD_TRY(ws_carve(net, ws, bt->B, (char*)base, kScratchBytes, &need));
+  if (need > kScratchBytes)
+    return fail(LD_E_NOMEM, "the batch needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                                std::to_string(kScratchBytes) + " the allocation-free dual evaluation holds");
+  LD_TRY(validate_values(net, bt, ws, s));
+  g_no_split = 1;
+  const int rc = dual_eval_impl(net, bt, rho, ws, q, supergrad, precision, tie_tau, s);
+  g_no_split = 0;
+  return rc;
 }
 
 int ld_dual_eval_f64(const ld_net* net, const ld_batch* bt, const double* const* rho, double* q,
