@@ -57,6 +57,12 @@ def parse():
                     help="for rocprofv3: one 64 MiB device copy (counter calibration), then --reps ascent "
                          "iterations launched without the graph; prints the per-launch averages")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--profile-summary", metavar="DIR", default=None,
+                    help="no GPU: read the rocprofv3 outputs of --profile-only runs under DIR (T: --kernel-trace "
+                         "--stats; F: --pmc FETCH_SIZE; W: --pmc WRITE_SIZE; M: --pmc of the MFMA counters, "
+                         "optional), print the per-launch markdown summary and, with --write-traffic, store the "
+                         "calibrated bytes per launch in profiles/traffic.json")
+    ap.add_argument("--write-traffic", action="store_true")
     ap.add_argument("--engine", choices=["auto", "layerwise", "resident"], default="auto")
     ap.add_argument("--solver", choices=["ld", "prox", "interm", "fsb", "sigmoid", "bab"], default="ld",
                     help="ld: Adam supergradient ascent (the headline line); prox: the proximal solver; "
@@ -637,6 +643,99 @@ def split_shares(B, props):
     return share
 
 
+def profile_summary(a):
+    """Per-launch summary of the counter and trace runs of `bench.py --profile-only`:
+    the last 6 x (reps + 1) launches of the library's contraction kernels are one
+    iteration's slots (101..103, 301..303 for the 4-layer nets), each a warm-up and
+    `reps` timed launches; the first of each group is dropped.  HBM bytes are
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the counters read
+    for the 1 GiB device copy the profile mode starts with."""
+    import csv
+    import collections
+    import ldgen
+    d = a.profile_summary
+    prec = os.path.basename(os.path.normpath(d)).split("_")[-1]
+    inst = make_workload(ldgen, a.config, a.B)
+    B = inst.B
+    n = len(inst.layers)
+    slots = [100 + k for k in range(1, n)] + [300 + k for k in range(1, n)]
+    per = a.reps + 1
+    keep = ("conv_plane", "convT", "fc_kernel", "fc_split")
+
+    def groups(rows, key):
+        rows = sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
+        rows = [r for r in rows if any(k in r["Kernel_Name"] for k in keep)][-len(slots) * per:]
+        out = {}
+        for i, sl in enumerate(slots):
+            g = rows[i * per + 1:(i + 1) * per]
+            out[sl] = (g[0]["Kernel_Name"].split("(")[0].replace("void ld::", ""), [key(r) for r in g])
+        return out
+
+    def counters(sub):
+        path = os.path.join(d, sub, "run_counter_collection.csv")
+        if not os.path.exists(path):
+            return None, None
+        by = collections.defaultdict(lambda: collections.defaultdict(float))
+        meta, copy = {}, {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                did = int(r["Dispatch_Id"])
+                by[did][r["Counter_Name"]] += float(r["Counter_Value"])
+                meta[did] = r
+                if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= (1 << 17):
+                    copy[r["Counter_Name"]] = copy.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        rows = [dict(meta[i], **{"_c": by[i]}) for i in meta]
+        return groups(rows, lambda r: r["_c"]), copy
+
+    with open(os.path.join(d, "T", "run_kernel_trace.csv")) as fh:
+        tr = groups(list(csv.DictReader(fh)), lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    F, cf = counters("F")
+    W, cw = counters("W")
+    M, _ = counters("M")
+    gib = 1 << 30
+    ff = gib / (cf["FETCH_SIZE"] * 1024) if cf else None
+    fw = gib / (cw["WRITE_SIZE"] * 1024) if cw else None
+    print(f"Counter calibration (1 GiB device copy): FETCH_SIZE x {ff:.4f}, WRITE_SIZE x {fw:.4f} (x 1024 bytes).\n")
+    print("| slot | kernel | trace us/launch | HBM read MB | HBM write MB | floor share MB | frac of HBM (floor share / trace) "
+          "| traffic / floor share | MFMA util % | MFMA TFLOP/s (algorithmic) |")
+    print("|---|---|---|---|---|---|---|---|---|---|")
+    rec = {}
+    tot_t = tot_b = tot_f = 0.0
+    for sl in slots:
+        name, ts = tr[sl]
+        us = sum(ts) / len(ts)
+        rd = sum(c["FETCH_SIZE"] for c in F[sl][1]) / len(F[sl][1]) * 1024 * ff if F else float("nan")
+        wr = sum(c["WRITE_SIZE"] for c in W[sl][1]) / len(W[sl][1]) * 1024 * fw if W else float("nan")
+        share = floor_share(inst, sl, B)
+        _, flops = layer_slot_cost(inst, sl, B, prec)
+        mf = sum(c.get("MfmaUtil", 0.0) for c in M[sl][1]) / len(M[sl][1]) if M else float("nan")
+        print(f"| {sl} | {name} | {us:.2f} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | {share / 1e6:.2f} | "
+              f"{share / (us * 1e-6) / 1e9 / PEAK_HBM_GBS:.3f} | {(rd + wr) / share:.2f} | {mf:.2f} | "
+              f"{flops / (us * 1e-6) / 1e12:.1f} |")
+        tot_t += us
+        tot_b += rd + wr
+        tot_f += share
+        kname = name.split("<")[0]
+        rec[f"{a.config}/B={B}/{prec}/{kname}/slot{sl}"] = {"kernel": name, "bytes_per_launch": rd + wr,
+                                                              "fetch_bytes": rd, "write_bytes": wr}
+    print(f"\nIteration: {tot_t:.1f} us over the {len(slots)} launches, {tot_b / 1e6:.1f} MB of HBM traffic against a "
+          f"floor of {tot_f / 1e6:.1f} MB ({tot_b / tot_f:.2f}x); floor / time = "
+          f"{tot_f / (tot_t * 1e-6) / 1e9 / PEAK_HBM_GBS:.3f} of HBM.")
+    if a.write_traffic:
+        path = os.path.join(ROOT, "profiles", "traffic.json")
+        old = {}
+        if os.path.exists(path):
+            with open(path) as fh:
+                old = json.load(fh)
+        ks = old.get("kernels", {}) if old.get("src_hash") == src_hash() else {}
+        ks.update(rec)
+        with open(path, "w") as fh:
+            json.dump({"src_hash": src_hash(),
+                       "note": "bytes per launch = FETCH_SIZE*fetch_factor + WRITE_SIZE*write_factor (KiB -> "
+                               "bytes), from the counter runs of bench.py --profile-only; valid for the sources "
+                               "with this hash", "kernels": ks}, fh, indent=1)
+
+
 def make_workload(ldgen, config, B):
     """The configuration's instance; with B, one GPU's share of it: for a config of
     several properties, B subdomains split over the properties in proportion to
@@ -651,6 +750,9 @@ def make_workload(ldgen, config, B):
 
 def main():
     a = parse()
+    if a.profile_summary:
+        profile_summary(a)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the subdomain batch would be "
               f"sharded across GPUs with no communication until a final all-gather, which is not built.",
