@@ -54,13 +54,13 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=512, help="subdomains timed on the host oracle")
     ap.add_argument("--quick", action="store_true", help="skip the equal-bound search (profiling runs)")
     ap.add_argument("--profile-only", choices=["fp32", "bf16"], default=None,
-                    help="for rocprofv3: one 64 MiB device copy (counter calibration), then --reps ascent "
+                    help="for rocprofv3: one 1 GiB device copy (counter calibration), then --reps ascent "
                          "iterations launched without the graph; prints the per-launch averages")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--profile-summary", metavar="DIR", default=None,
                     help="no GPU: read the rocprofv3 outputs of --profile-only runs under DIR (T: --kernel-trace "
-                         "--stats; F: --pmc FETCH_SIZE; W: --pmc WRITE_SIZE; M: --pmc of the MFMA counters, "
-                         "optional), print the per-launch markdown summary and, with --write-traffic, store the "
+                         "--stats; F: --pmc FETCH_SIZE; W: --pmc WRITE_SIZE; M, optional: --pmc SQ_INSTS_VALU_MFMA_MOPS_BF16 "
+                         "SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CU_CYCLES), print the per-launch markdown summary and, with --write-traffic, store the "
                          "calibrated bytes per launch in profiles/traffic.json")
     ap.add_argument("--write-traffic", action="store_true")
     ap.add_argument("--engine", choices=["auto", "layerwise", "resident"], default="auto")
@@ -697,7 +697,7 @@ def profile_summary(a):
     fw = gib / (cw["WRITE_SIZE"] * 1024) if cw else None
     print(f"Counter calibration (1 GiB device copy): FETCH_SIZE x {ff:.4f}, WRITE_SIZE x {fw:.4f} (x 1024 bytes).\n")
     print("| slot | kernel | trace us/launch | HBM read MB | HBM write MB | floor share MB | frac of HBM (floor share / trace) "
-          "| traffic / floor share | MFMA util % | MFMA TFLOP/s (algorithmic) |")
+          "| traffic / floor share | MFMA TFLOP/s (algorithmic) | MFMA TFLOP/s (executed) | MFMA busy / CU busy |")
     print("|---|---|---|---|---|---|---|---|---|---|")
     rec = {}
     tot_t = tot_b = tot_f = 0.0
@@ -708,10 +708,18 @@ def profile_summary(a):
         wr = sum(c["WRITE_SIZE"] for c in W[sl][1]) / len(W[sl][1]) * 1024 * fw if W else float("nan")
         share = floor_share(inst, sl, B)
         _, flops = layer_slot_cost(inst, sl, B, prec)
-        mf = sum(c.get("MfmaUtil", 0.0) for c in M[sl][1]) / len(M[sl][1]) if M else float("nan")
+        if M:
+            # MOPS counters count MFMA work in units of 512 flops
+            ex = sum((c.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) + c.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)) * 512
+                     for c in M[sl][1]) / len(M[sl][1])
+            busy = sum(c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for c in M[sl][1]) / max(
+                1.0, sum(c.get("SQ_BUSY_CU_CYCLES", 0.0) for c in M[sl][1]))
+            ex_s, busy_s = f"{ex / (us * 1e-6) / 1e12:.1f}", f"{busy:.3f}"
+        else:
+            ex_s = busy_s = "n/a"
         print(f"| {sl} | {name} | {us:.2f} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | {share / 1e6:.2f} | "
-              f"{share / (us * 1e-6) / 1e9 / PEAK_HBM_GBS:.3f} | {(rd + wr) / share:.2f} | {mf:.2f} | "
-              f"{flops / (us * 1e-6) / 1e12:.1f} |")
+              f"{share / (us * 1e-6) / 1e9 / PEAK_HBM_GBS:.3f} | {(rd + wr) / share:.2f} | "
+              f"{flops / (us * 1e-6) / 1e12:.1f} | {ex_s} | {busy_s} |")
         tot_t += us
         tot_b += rd + wr
         tot_f += share
@@ -925,10 +933,12 @@ def main():
     if not a.no_cpu_baseline:
         cb, idx, ob = cpu_baseline(inst, T, a.cpu_sample)
         out["cpu_baseline"] = cb
-        for p, r in (("fp32", res32), ("bf16", res16), ("fp64", res64)):
-            dd = r["fb"]["bound"].cpu()[idx] - ob
+        # the BF16 form may run more iterations: compare it with the oracle at its own count
+        ob16 = ob if T16 == T else cpu_baseline(inst, T16, a.cpu_sample)[2]
+        for p, r, o, t in (("fp32", res32, ob, T), ("bf16", res16, ob16, T16), ("fp64", res64, ob, T)):
+            dd = r["fb"]["bound"].cpu()[idx] - o
             out[p]["minus_oracle"] = {"mean": dd.mean().item(), "abs": pct(dd.abs()),
-                                      "subdomains": len(idx), "oracle_iters": T}
+                                      "subdomains": len(idx), "oracle_iters": t}
     print(json.dumps(out), flush=True)
 
 
