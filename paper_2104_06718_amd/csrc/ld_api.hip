@@ -990,7 +990,9 @@ int iteration(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts
 
 void destroy_graph(ld_state* st, int i) {
   ld_state::Graph& G = st->graphs[i];
-  if (G.exec && st->done) (void)hipEventSynchronize(st->done);
+  // a graph exec is released only once the whole device is idle (its launches and
+  // whatever the runtime still does on their behalf on other streams are over)
+  if (G.exec) (void)hipDeviceSynchronize();
   if (G.exec) (void)hipGraphExecDestroy(G.exec);
   if (G.graph) (void)hipGraphDestroy(G.graph);
   G.exec = nullptr;
@@ -1775,6 +1777,7 @@ int ld_state_create(const ld_net* net, int B, ld_state** out) {
 void ld_state_destroy(ld_state* st) {
   if (!st) return;
   if (st->done) (void)hipEventSynchronize(st->done);
+  if (st->graphs[0].exec || st->graphs[1].exec) (void)hipDeviceSynchronize();
   destroy_graph(st, 0);
   destroy_graph(st, 1);
   if (st->cap) (void)hipStreamDestroy(st->cap);

@@ -18,6 +18,16 @@
 namespace ld {
 
 constexpr int kMaxClasses = 9;
+
+// f(std::integral_constant<int, i>) for i = 0..N-1, unrolled at compile time (arrays
+// indexed by i stay in registers)
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (N > 0) {
+    static_for<N - 1>(f);
+    f(std::integral_constant<int, N - 1>{});
+  }
+}
 struct GemmPack {
   int n;
   GemmGeom g[kMaxClasses];
@@ -321,6 +331,9 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   const int dst_H = G0.dst_HW / G0.dst_W;
   const int R0 = part * dst_H / parts, R1 = (part + 1) * dst_H / parts;
   const int band = (R1 - R0) * G0.dst_W;
+  // LDS row stride of a channel of the band: 4 floats of padding spread the 16
+  // channels an MFMA tile writes at once over distinct banks
+  const int bandp = band + 4;
   const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
   const int H = G0.src_H, W = G0.src_W, HW = H * W;
   const int C = G0.src_n / HW;
@@ -334,74 +347,104 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   WT* wBl = wB + (size_t)P.n * n_eff * bstride;  // MM == 2: the BF16 remainders, same layout
 
   adam_tick(E);
-  for (int i = tid; i < P.n * kGeoWords; i += kConvThreads) {
-    const int c = i / kGeoWords, w = i - c * kGeoWords;
-    if (w * 4 < (int)sizeof(GemmGeom)) geo[i] = reinterpret_cast<const int*>(geo_dev + c)[w];
-  }
-  // 1a. source map into the image interior: loads first, then LDS writes
-  {
-    const size_t sbase = (size_t)b * G0.src_n;
-    const float inv_w = 1.0f / (float)W, inv_h = 1.0f / (float)H;
-    if ((W & 3) == 0) {
-      const int n4 = G0.src_n >> 2;
-      constexpr int U = 4;
-      for (int i0 = tid; i0 < n4; i0 += U * kConvThreads) {
-        float v[U][4];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = i0 + u * kConvThreads;
-          if (i < n4) {
-            if (SRC_BF16) {
-              const uint2 raw = *reinterpret_cast<const uint2*>((const bf16_t*)src_v + sbase + 4 * (size_t)i);
-              v[u][0] = bf2f((bf16_t)(raw.x & 0xffffu));
-              v[u][1] = bf2f((bf16_t)(raw.x >> 16));
-              v[u][2] = bf2f((bf16_t)(raw.y & 0xffffu));
-              v[u][3] = bf2f((bf16_t)(raw.y >> 16));
-            } else {
-              const float4 f = *reinterpret_cast<const float4*>((const float*)src_v + sbase + 4 * (size_t)i);
-              v[u][0] = f.x;
-              v[u][1] = f.y;
-              v[u][2] = f.z;
-              v[u][3] = f.w;
-            }
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = i0 + u * kConvThreads;
-          if (i < n4) {
-            const int e = 4 * i;
-            const int row = fdiv(e, W, inv_w);  // c*H + y
-            const int x = e - row * W;
-            const int c = fdiv(row, H, inv_h);
-            const int y = row - c * H;
-            float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP + c;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) d[q * CP] = v[u][q];
-            if (c == C - 1)  // the padding channels of these pixels
-              for (int cc = C; cc < Cq; ++cc)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) d[q * CP + cc - c] = 0.f;
-          }
-        }
-      }
+  // 1. staging.  A thread's first round of global loads (its geometry word, up to U
+  //    float4 of the source map, its gather offset and weight vectors of every
+  //    class) is issued before any LDS write, so the block waits for one memory
+  //    latency; larger maps and weight sets continue in further rounds.
+  const size_t sbase = (size_t)b * G0.src_n;
+  const float inv_w = 1.0f / (float)W, inv_h = 1.0f / (float)H;
+  const bool vec_img = (W & 3) == 0;
+  const int n4 = G0.src_n >> 2;
+  constexpr int U = 4;
+  auto load_img4 = [&](int i, float (&v)[4]) __attribute__((always_inline)) {
+    if (SRC_BF16) {
+      const uint2 raw = *reinterpret_cast<const uint2*>((const bf16_t*)src_v + sbase + 4 * (size_t)i);
+      v[0] = bf2f((bf16_t)(raw.x & 0xffffu));
+      v[1] = bf2f((bf16_t)(raw.x >> 16));
+      v[2] = bf2f((bf16_t)(raw.y & 0xffffu));
+      v[3] = bf2f((bf16_t)(raw.y >> 16));
     } else {
-      for (int e = tid; e < G0.src_n; e += kConvThreads) {
-        const float v = SRC_BF16 ? bf2f(((const bf16_t*)src_v)[sbase + e]) : ((const float*)src_v)[sbase + e];
-        const int row = fdiv(e, W, inv_w);
-        const int x = e - row * W;
-        const int c = fdiv(row, H, inv_h);
-        const int y = row - c * H;
-        float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP;
-        d[c] = v;
-        if (c == C - 1)
-          for (int cc = C; cc < Cq; ++cc) d[cc] = 0.f;
-      }
+      const float4 f = *reinterpret_cast<const float4*>((const float*)src_v + sbase + 4 * (size_t)i);
+      v[0] = f.x;
+      v[1] = f.y;
+      v[2] = f.z;
+      v[3] = f.w;
     }
+  };
+  auto store_img4 = [&](int i, const float (&v)[4]) __attribute__((always_inline)) {
+    const int e = 4 * i;
+    const int row = fdiv(e, W, inv_w);  // c*H + y
+    const int x = e - row * W;
+    const int c = fdiv(row, H, inv_h);
+    const int y = row - c * H;
+    float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP + c;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[q * CP] = v[q];
+    if (c == C - 1)  // the padding channels of these pixels
+      for (int cc = C; cc < Cq; ++cc)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q * CP + cc - c] = 0.f;
+  };
+  // (a) the first round of loads
+  const int ngeo = P.n * kGeoWords;
+  int gword = 0;
+  if (tid < ngeo) {
+    const int c = tid / kGeoWords, w = tid - c * kGeoWords;
+    if (w * 4 < (int)sizeof(GemmGeom)) gword = reinterpret_cast<const int*>(geo_dev + c)[w];
   }
-  // 1b. zero the padding border (disjoint from the interior)
+  float v0[U][4];
+  if (vec_img) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (tid + u * kConvThreads < n4) load_img4(tid + u * kConvThreads, v0[u]);
+  }
+  // gather offsets and weight vectors of a group of up to kStageClasses classes
+  constexpr int kStageClasses = 4;
+  int kv[kStageClasses];
+  u32x4 wh[kStageClasses], wl[kStageClasses];
+  auto load_classes = [&](int c0) __attribute__((always_inline)) {
+    static_for<kStageClasses>([&](auto ci) __attribute__((always_inline)) {
+      constexpr int i = decltype(ci)::value;
+      const int c = c0 + i;
+      if (c < P.n) {
+        const GemmGeom& G = P.g[c];
+        if (tid < G.Kp) kv[i] = G.ktab_cl[tid];
+        const int vr = G.Kp / EPV;
+        if (tid < n_eff * vr) {
+          wh[i] = reinterpret_cast<const u32x4*>(MMA_BF16 ? (const void*)G.Bh : (const void*)G.Bf)[tid];
+          if (MM == 2) wl[i] = reinterpret_cast<const u32x4*>(G.Bhl)[tid];
+        }
+      }
+    });
+  };
+  auto store_classes = [&](int c0) __attribute__((always_inline)) {
+    static_for<kStageClasses>([&](auto ci) __attribute__((always_inline)) {
+      constexpr int i = decltype(ci)::value;
+      const int c = c0 + i;
+      if (c < P.n) {
+        const GemmGeom& G = P.g[c];
+        if (tid < G.Kp) kofs[c * kp_max + tid] = kv[i];
+        const int vr = G.Kp / EPV;
+        if (tid < n_eff * vr) {
+          const int row = tid / vr, v = tid - row * vr;
+          const size_t o = ((size_t)c * n_eff + row) * bstride + v * EPV;
+          *reinterpret_cast<u32x4*>(wB + o) = wh[i];
+          if (MM == 2) *reinterpret_cast<u32x4*>(wBl + o) = wl[i];
+        }
+      }
+    });
+  };
+  load_classes(0);
+  // (b) their LDS writes, and the zero border of the image (disjoint from the interior:
+  //     border pixels, all Cq channels; the CP - Cq floats past them are never read)
+  if (tid < ngeo) geo[tid] = gword;
+  if (vec_img) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (tid + u * kConvThreads < n4) store_img4(tid + u * kConvThreads, v0[u]);
+  }
+  store_classes(0);
   {
-    // border pixels, all Cq channels (the CP - Cq floats past them are never read)
     const float inv_lw = 1.0f / (float)G0.LW;
     const int c4 = Cq >> 2;
     for (int e = tid; e < G0.LH * G0.LW * c4; e += kConvThreads) {
@@ -411,22 +454,53 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
         *reinterpret_cast<float4*>(img + pix * CP + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
-  // 1c. gather offsets and weights of every class
+  // (c) further rounds
+  for (int c0 = kStageClasses; c0 < P.n; c0 += kStageClasses) {
+    load_classes(c0);
+    store_classes(c0);
+  }
+  for (int i = tid + kConvThreads; i < ngeo; i += kConvThreads) {
+    const int c = i / kGeoWords, w = i - c * kGeoWords;
+    if (w * 4 < (int)sizeof(GemmGeom)) geo[i] = reinterpret_cast<const int*>(geo_dev + c)[w];
+  }
+  if (vec_img) {
+    for (int i0 = tid + U * kConvThreads; i0 < n4; i0 += U * kConvThreads) {
+      float v[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * kConvThreads < n4) load_img4(i0 + u * kConvThreads, v[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * kConvThreads < n4) store_img4(i0 + u * kConvThreads, v[u]);
+    }
+  } else {
+    for (int e = tid; e < G0.src_n; e += kConvThreads) {
+      const float v = SRC_BF16 ? bf2f(((const bf16_t*)src_v)[sbase + e]) : ((const float*)src_v)[sbase + e];
+      const int row = fdiv(e, W, inv_w);
+      const int x = e - row * W;
+      const int c = fdiv(row, H, inv_h);
+      const int y = row - c * H;
+      float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP;
+      d[c] = v;
+      if (c == C - 1)
+        for (int cc = C; cc < Cq; ++cc) d[cc] = 0.f;
+    }
+  }
   for (int c = 0; c < P.n; ++c) {
     const GemmGeom& G = P.g[c];
-    for (int k = tid; k < G.Kp; k += kConvThreads) kofs[c * kp_max + k] = G.ktab_cl[k];
+    for (int k = tid + kConvThreads; k < G.Kp; k += kConvThreads) kofs[c * kp_max + k] = G.ktab_cl[k];
     const int vr = G.Kp / EPV;
     const float inv_vr = 1.0f / (float)vr;
     const uint4* srcw = reinterpret_cast<const uint4*>(MMA_BF16 ? (const void*)G.Bh : (const void*)G.Bf);
     const uint4* srcl = reinterpret_cast<const uint4*>(G.Bhl);
-    for (int e = tid; e < n_eff * vr; e += kConvThreads) {
+    for (int e = tid + kConvThreads; e < n_eff * vr; e += kConvThreads) {
       const int row = fdiv(e, vr, inv_vr);
       const int v = e - row * vr;
       const size_t o = ((size_t)c * n_eff + row) * bstride + v * EPV;
       const uint4 w = srcw[(size_t)row * vr + v];
       if (MM == 2) {
-        const uint4 wl = srcl[(size_t)row * vr + v];
-        *reinterpret_cast<uint4*>(wBl + o) = wl;
+        const uint4 wlo = srcl[(size_t)row * vr + v];
+        *reinterpret_cast<uint4*>(wBl + o) = wlo;
       }
       *reinterpret_cast<uint4*>(wB + o) = w;
     }
@@ -469,61 +543,81 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
     const int ntiles = (p_hi - p_lo + 15) >> 4;
     const int nct = (G.N + 16 * TN - 1) / (16 * TN);
     const int j_band = R0 * G.dst_W;
-    // distribute (tile, column chunk) pairs over the waves, continuing the rotation across classes
-    const int total = ntiles * nct;
+    // distribute (pair of tiles, column chunk) items over the waves, continuing the
+    // rotation across classes; a wave multiplies two 16-pixel tiles against each
+    // weight fragment it reads (the second tile of an odd count is empty)
+    const int npairs = (ntiles + 1) >> 1;
+    const int total = npairs * nct;
     int first = (wave - tiles_before) % kConvWaves;
     if (first < 0) first += kConvWaves;
     for (int w = first; w < total; w += kConvWaves) {
-      const int tile = w / nct;
-      const int nc = (w - tile * nct) * 16 * TN;
-      const int p = min(p_lo + tile * 16 + r, p_hi - 1);
-      const int yq = fdiv(p, G.Wq, inv_wq);
-      const int xq = p - yq * G.Wq;
-      const int lb = ((yq * G.iy_mul + G.iy_off + G.pad_t) * G.LW + xq * G.ix_mul + G.ix_off + G.pad_l) * CP;
-      f32x4 acc[TN];
+      const int pair = w / nct;
+      const int nc = (w - pair * nct) * 16 * TN;
+      int lb[2];
 #pragma unroll
-      for (int t = 0; t < TN; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+      for (int m = 0; m < 2; ++m) {
+        const int p = min(p_lo + (2 * pair + m) * 16 + r, p_hi - 1);
+        const int yq = fdiv(p, G.Wq, inv_wq);
+        const int xq = p - yq * G.Wq;
+        lb[m] = ((yq * G.iy_mul + G.iy_off + G.pad_t) * G.LW + xq * G.ix_mul + G.ix_off + G.pad_l) * CP;
+      }
+      f32x4 acc[2][TN];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int t = 0; t < TN; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
       for (int k0 = 0; k0 < G.K; k0 += KS) {
         const int kl = k0 + VPL * g;
-        float a[VPL];
         // each group of 4 consecutive k is 4 channels of one tap: 16-byte aligned
         // and contiguous (VPL = 8 may span two taps)
+        int ofs[VPL / 4];
 #pragma unroll
-        for (int j = 0; j < VPL; j += 4) {
-          const float4 v = *reinterpret_cast<const float4*>(img + lb + ko[kl + j]);
-          a[j] = v.x;
-          a[j + 1] = v.y;
-          a[j + 2] = v.z;
-          a[j + 3] = v.w;
-        }
+        for (int j = 0; j < VPL; j += 4) ofs[j / 4] = ko[kl + j];
+        float a[2][VPL];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int j = 0; j < VPL; j += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(img + lb[m] + ofs[j / 4]);
+            a[m][j] = v.x;
+            a[m][j + 1] = v.y;
+            a[m][j + 2] = v.z;
+            a[m][j + 3] = v.w;
+          }
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
           const size_t wo = (size_t)(nc + 16 * t + r) * bstride + kl;
           const BFrag bf = *reinterpret_cast<const BFrag*>(wc + wo);
-          if constexpr (MM == 2)
-            M::mma3(a, bf, *reinterpret_cast<const BFrag*>(wcl + wo), acc[t]);
-          else
-            M::mma(a, bf, acc[t]);
-        }
-      }
-      // the lane's four rows are consecutive pixels of the class grid
-      const int p0 = p_lo + tile * 16 + 4 * g;
-      int yy = fdiv(p0, G.Wq, inv_wq);
-      int xx = p0 - yy * G.Wq;
+          if constexpr (MM == 2) {
+            const BFrag bfl = *reinterpret_cast<const BFrag*>(wcl + wo);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (p0 + q < p_hi) {
-          const int j0 = (yy * G.oy_mul + G.oy_off) * G.dst_W + xx * G.ox_mul + G.ox_off - j_band;
+            for (int m = 0; m < 2; ++m) M::mma3(a[m], bf, bfl, acc[m][t]);
+          } else {
 #pragma unroll
-          for (int t = 0; t < TN; ++t) {
-            const int col = nc + 16 * t + r;
-            if (col < G.N) outp[col * band + j0] = acc[t][q];
+            for (int m = 0; m < 2; ++m) M::mma(a[m], bf, acc[m][t]);
           }
         }
-        if (++xx == G.Wq) {
-          xx = 0;
-          ++yy;
+      }
+      // the lane's four rows of a tile are consecutive pixels of the class grid
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int p0 = p_lo + (2 * pair + m) * 16 + 4 * g;
+        int yy = fdiv(p0, G.Wq, inv_wq);
+        int xx = p0 - yy * G.Wq;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (p0 + q < p_hi) {
+            const int j0 = (yy * G.oy_mul + G.oy_off) * G.dst_W + xx * G.ox_mul + G.ox_off - j_band;
+#pragma unroll
+            for (int t = 0; t < TN; ++t) {
+              const int col = nc + 16 * t + r;
+              if (col < G.N) outp[col * bandp + j0] = acc[m][t][q];
+            }
+          }
+          if (++xx == G.Wq) {
+            xx = 0;
+            ++yy;
+          }
         }
       }
     }
@@ -539,14 +633,15 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
     for (int e = 4 * tid; e < nch * band; e += 4 * kConvThreads) {
       const int col = fdiv(e, band, inv_band);  // channel (four consecutive neurons share it)
       const int j = e - col * band;
-      float v4[4] = {outp[e], outp[e + 1], outp[e + 2], outp[e + 3]};
+      const float4 o4 = *reinterpret_cast<const float4*>(outp + col * bandp + j);
+      float v4[4] = {o4.x, o4.y, o4.z, o4.w};
       epilogue4<true>(E, base + (size_t)col * G0.dst_HW + j, 1, 4, b, 0, col, 0, v4);
     }
   } else {
     for (int e = tid; e < nch * band; e += kConvThreads) {
       const int col = fdiv(e, band, inv_band);
       const int j = e - col * band;
-      float v4[4] = {outp[e], 0.f, 0.f, 0.f};
+      float v4[4] = {outp[col * bandp + j], 0.f, 0.f, 0.f};
       epilogue4<false>(E, base + (size_t)col * G0.dst_HW + j, 1, 1, b, 0, col, 0, v4);
     }
   }
@@ -720,10 +815,11 @@ static int max_kp(const GemmGeom* g, int n) {
 static int conv_n_eff(const GemmGeom& g, int tn) { return (g.N + 16 * tn - 1) / (16 * tn) * 16 * tn; }
 static int conv_bstride(const GemmGeom* g, int n, int mma_bf16) { return max_kp(g, n) + (mma_bf16 ? 8 : 4); }
 
-// LDS floats of the destination band of one block (the tallest band of `parts`)
+// LDS floats of the destination band of one block (the tallest band of `parts`,
+// each channel's row padded by 4 floats)
 static int conv_out_floats(const GemmGeom& g, int parts) {
   const int H = g.dst_HW / g.dst_W;
-  return g.dst_n / g.dst_HW * ((H + parts - 1) / parts) * g.dst_W;
+  return g.dst_n / g.dst_HW * (((H + parts - 1) / parts) * g.dst_W + 4);
 }
 
 size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16, int parts) {
