@@ -69,6 +69,9 @@ def parse():
                          "interm: LD intermediate bounds of one layer; fsb: branching decisions; "
                          "sigmoid: the sigmoid inner minimisation; bab: branch-and-bound rounds")
     ap.add_argument("--layer", type=int, default=2, help="interm: layer j whose pre-activations are bounded")
+    ap.add_argument("--interm-copy", action="store_true",
+                    help="interm: chunks that are not whole subdomains, so every problem gets a copy of its "
+                         "subdomain's bound rows (the layout without shared rows, for comparison)")
     return ap.parse_args()
 
 
@@ -358,7 +361,7 @@ def main_interm(a, P, inst):
     batch = P.Batch(t(inst.l0), t(inst.u0), [t(x) for x in inst.l[:j - 1]], [t(x) for x in inst.u[:j - 1]],
                     torch.zeros(Bs, nj, device="cuda"))
     nprob = 2 * nj * Bs
-    chunk = 8192
+    chunk = 8192 - 4 if a.interm_copy else 8192
     res = {}
     for prec in ("fp32", "bf16"):
         for _ in range(a.warmup):  # includes the autotuner's run for the chunk sizes
@@ -418,7 +421,8 @@ def main_interm(a, P, inst):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{a.config} conv net 3x32x32, pre-activation bounds of layer {j} ({nj} neurons) "
-                               f"for {Bs} subdomains: {nprob} LD problems (+-e_i), T={T}, chunks of {chunk}",
+                               f"for {Bs} subdomains: {nprob} LD problems (+-e_i), T={T}, chunks of {chunk}, "
+                               f"bound rows {'copied per problem' if a.interm_copy else 'shared per subdomain'}",
                    "subdomains": Bs, "layer": j, "problems": nprob, "iters": T},
         "bf16": {"value": nprob / (res["bf16"]["ms"] / 1000.0), "ms_per_step": res["bf16"]["ms"]},
         "mean_width": {p: (res[p]["hi"] - res[p]["lo"]).double().mean().item() for p in res},

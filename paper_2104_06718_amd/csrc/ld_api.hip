@@ -32,6 +32,10 @@ namespace {
 
 thread_local std::string g_err;
 thread_local int g_validate = 1;
+// Subdomains that share one row of the batch's bounds (l_0, u_0, l_k, u_k): the
+// intermediate-bound problems of one subdomain read its rows in place (1: one row
+// per subdomain).  Set only around the internal calls of ld_intermediate_bounds.
+thread_local int g_row_div = 1;
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -785,6 +789,7 @@ EpiArgs epi0() {
   std::memset(&e, 0, sizeof(e));
   e.scale = 1.f;
   e.bias_div = 1;
+  e.row_div = g_row_div;
   return e;
 }
 
@@ -896,7 +901,7 @@ int phase_a(const ld_net* net, const ld_batch* bt, const float* const* rho, Work
   const int k = n - 1;
   LD_HIP(launch_inner_min_const(B, width(net, k), ws.gconst, rho[k - 1], bt->l[k - 1], bt->u[k - 1],
                                 net->L[k - 1].bias, bias_div(net, k), tau, ws.xb[k],
-                                want_val ? ws.val[k] : nullptr, nullptr, nullptr, 0, 0, 0, 0, 0, 0, s));
+                                want_val ? ws.val[k] : nullptr, nullptr, nullptr, 0, 0, 0, 0, 0, 0, g_row_div, s));
   return LD_OK;
 }
 
@@ -939,7 +944,8 @@ int init_impl(const ld_net* net, const ld_batch* bt, int init, int mma, float* c
   }
   const int wk = init == LD_INIT_WK ? 1 : 0;
   LD_TRY(prepare_objective(net, bt, ws, mma, s));
-  LD_HIP(launch_crown_const(B, width(net, n - 1), ws.gconst, bt->l[n - 2], bt->u[n - 2], rho[n - 2], wk, s));
+  LD_HIP(launch_crown_const(B, width(net, n - 1), ws.gconst, bt->l[n - 2], bt->u[n - 2], rho[n - 2], wk, g_row_div,
+                            s));
   for (int k = n - 1; k >= 2; --k) {
     // rho_{k-1} from g_{k-1} = W_k^T rho_k
     const Layer& L = net->L[k - 1];
@@ -1021,6 +1027,7 @@ std::vector<double> graph_key(const ld_batch* bt, const ld_opts* o, int n, int c
   k.push_back(o->tie_tau);
   k.push_back(chunk);
   k.push_back(net_tune_gen);
+  k.push_back(g_row_div);
   return k;
 }
 
@@ -2253,7 +2260,7 @@ static int autotune_impl(const ld_net* net, const ld_batch* bt, const ld_opts* o
   LD_HIP(hipEventRecord(tmp->done, s));
   // the resident engine's BF16 form uses plain BF16 transposed products (no
   // compensated product): it is offered to AUTO for FP32 only
-  if (mma == 0 && resident_shape(net, B, mma).S > 0)
+  if (mma == 0 && g_row_div == 1 && resident_shape(net, B, mma).S > 0)
     LD_TRY(time_calls([&]() { return run_engine(LD_ENGINE_RESIDENT); }, s, e0, e1, 1, &us_res));
   LD_HIP(hipStreamSynchronize(s));
   const int eng = (us_res > 0 && us_res < us_lw) ? LD_ENGINE_RESIDENT : LD_ENGINE_LAYERWISE;
@@ -2589,8 +2596,21 @@ int ld_intermediate_bounds(const ld_net* sub, const ld_batch* bt, const ld_opts*
   const int nj = width(sub, n);
   const long long P = 2LL * nj;
   const long long total = (long long)B * P;
-  const long long C = std::min<long long>(max_problems > 0 ? max_problems : 8192, total);
-  // one chunk's expanded batch and its bounds
+  const long long cmax = max_problems > 0 ? max_problems : 8192;
+  // The 2 n_j problems of a subdomain read its bound rows in place when chunks hold
+  // whole subdomains (FP32/BF16 layer-wise engine): each chunk's batch points at the
+  // rows of its first subdomain and every kernel maps problem p to row p / P.
+  // Otherwise every problem of a chunk gets a copy of its subdomain's rows.
+  bool share = o->precision != LD_FP64 && o->engine != LD_ENGINE_RESIDENT && P <= cmax &&
+               (max_problems <= 0 || max_problems % P == 0);
+  const long long C = std::min<long long>(share ? cmax / P * P : cmax, total);
+  // a chunk after the first starts at a subdomain's rows: they must stay 16-byte aligned
+  if (share && C < total) {
+    bool al = sub->n0 % 4 == 0;
+    for (int k = 1; k <= n - 1; ++k) al = al && width(sub, k) % 4 == 0;
+    share = al;
+  }
+  // one chunk's expanded batch (or only its objectives) and its bounds
   std::vector<int> widths = {sub->n0, sub->n0};
   for (int k = 1; k <= n - 1; ++k) {
     widths.push_back(width(sub, k));
@@ -2600,18 +2620,20 @@ int ld_intermediate_bounds(const ld_net* sub, const ld_batch* bt, const ld_opts*
   size_t total_bytes = 0;
   for (int w : widths) {
     off.push_back(total_bytes);
-    total_bytes += round_up((size_t)C * w * 4, 256);
+    total_bytes += share ? 0 : round_up((size_t)C * w * 4, 256);
   }
   const size_t off_c = total_bytes;
   total_bytes += round_up((size_t)C * nj * 4, 256);
   const size_t off_b = total_bytes;
   total_bytes += round_up((size_t)C * 8, 256);
+  const size_t off_bad = total_bytes;
+  total_bytes += 256;
   void* base = nullptr;
   if (hipMalloc(&base, total_bytes) != hipSuccess) return fail(LD_E_NOMEM, "intermediate bounds: hipMalloc failed");
   char* cb = (char*)base;
   IntermPack K;
   std::memset(&K, 0, sizeof(K));
-  K.n = (int)widths.size();
+  K.n = share ? 0 : (int)widths.size();
   std::vector<const float*> srcs = {bt->l0, bt->u0};
   for (int k = 1; k <= n - 1; ++k) {
     srcs.push_back(bt->l[k - 1]);
@@ -2624,13 +2646,37 @@ int ld_intermediate_bounds(const ld_net* sub, const ld_batch* bt, const ld_opts*
   }
   K.c = (float*)(cb + off_c);
   double* bound = (double*)(cb + off_b);
-  std::vector<const float*> dl, du;
-  for (int k = 1; k <= n - 1; ++k) {
-    dl.push_back(K.dst[2 * k]);
-    du.push_back(K.dst[2 * k + 1]);
-  }
   ld_state* states[2] = {nullptr, nullptr};  // full chunks, the tail chunk
   int rc = LD_OK;
+  if (share && g_validate) {
+    // the caller's rows are read in place: check them once (the chunks skip it)
+    int* bad = (int*)(cb + off_bad);
+    hipError_t e = launch_fill_i32(bad, 1, 0, s);
+    if (e == hipSuccess) e = launch_validate(B, sub->n0, bt->l0, bt->u0, bad, s);
+    for (int k = 1; k <= n - 1 && e == hipSuccess; ++k)
+      e = launch_validate(B, width(sub, k), bt->l[k - 1], bt->u[k - 1], bad, s);
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+      rc = fail(LD_E_DEVICE, std::string("intermediate bounds: ") + hipGetErrorString(e));
+    else if (h)
+      rc = fail(LD_E_NUMERIC, "batch holds a non-finite value or a lower bound above its upper bound");
+  }
+  // the internal calls read shared rows (and skip the validation done above)
+  struct ShareScope {
+    int div0, val0;
+    ShareScope(bool on, int div) : div0(g_row_div), val0(g_validate) {
+      if (on) {
+        g_row_div = div;
+        g_validate = 0;
+      }
+    }
+    ~ShareScope() {
+      g_row_div = div0;
+      g_validate = val0;
+    }
+  } scope(share, (int)P);
   for (long long start = 0; start < total && rc == LD_OK; start += C) {
     const int cc = (int)std::min<long long>(C, total - start);
     hipError_t e = launch_interm_expand(K, cc, start, (int)P, nj, s);
@@ -2638,10 +2684,25 @@ int ld_intermediate_bounds(const ld_net* sub, const ld_batch* bt, const ld_opts*
       rc = fail(LD_E_DEVICE, std::string("interm_expand: ") + hipGetErrorString(e));
       break;
     }
+    std::vector<const float*> dl, du;
     ld_batch cbt;
     cbt.B = cc;
-    cbt.l0 = K.dst[0];
-    cbt.u0 = K.dst[1];
+    if (share) {
+      const long long b0 = start / P;  // the chunk's first subdomain
+      cbt.l0 = bt->l0 + b0 * sub->n0;
+      cbt.u0 = bt->u0 + b0 * sub->n0;
+      for (int k = 1; k <= n - 1; ++k) {
+        dl.push_back(bt->l[k - 1] + b0 * width(sub, k));
+        du.push_back(bt->u[k - 1] + b0 * width(sub, k));
+      }
+    } else {
+      cbt.l0 = K.dst[0];
+      cbt.u0 = K.dst[1];
+      for (int k = 1; k <= n - 1; ++k) {
+        dl.push_back(K.dst[2 * k]);
+        du.push_back(K.dst[2 * k + 1]);
+      }
+    }
     cbt.l = dl.data();
     cbt.u = du.data();
     cbt.c = K.c;
@@ -3155,6 +3216,8 @@ int ld_sigmoid_inner_min(long long count, const float* rho, const float* g, cons
 int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* o, hipStream_t s) {
   g_err.clear();
   LD_TRY(check_step_args(net, bt, st, o));
+  if (g_row_div > 1 && (o->precision == LD_FP64 || o->engine == LD_ENGINE_RESIDENT))
+    return fail(LD_E_UNSUPPORTED, "shared bound rows need the FP32/BF16 layer-wise engine");
   LD_TRY(validate_values(net, bt, st->ws, s));
   if (o->precision == LD_FP64) {
     LD_TRY(f64_ensure_initialised(net, bt, st, o, s));

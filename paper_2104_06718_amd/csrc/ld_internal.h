@@ -87,6 +87,11 @@ struct EpiArgs {
   float* adam_w;
   double lr0, lr_end, beta1, beta2, eps;
   int total;
+  // lo/hi rows shared by row_div consecutive subdomains (1: one row per subdomain):
+  // the bounds of subdomain b are row b / row_div, rows of lohi_len floats (the
+  // destination width, set by the launcher)
+  int row_div;
+  int lohi_len;
 };
 
 // Launch-time configuration of one contraction: tn 16-column MFMA tiles per wave;
@@ -196,9 +201,9 @@ hipError_t launch_inner_min_const(int B, int n, const float* g, const float* rho
                                   const float* hi, const float* bias, int bias_hw, float tau, float* xb,
                                   double* val, int* t_dev, float* adam_scalars, double lr0,
                                   double lr_end, int total, double beta1, double beta2, double eps,
-                                  hipStream_t s);
+                                  int row_div, hipStream_t s);
 hipError_t launch_crown_const(int B, int n, const float* g, const float* lo, const float* hi,
-                              float* rho, int wk, hipStream_t s);
+                              float* rho, int wk, int row_div, hipStream_t s);
 hipError_t launch_reduce_q(int B, int n_arrays, const double* const* arrays, const int* sizes,
                            const double* cb, double* q, hipStream_t s);
 hipError_t launch_cdot(int B, int n, const float* c, const float* y, const float* bias, int bias_div, double* out,

@@ -110,6 +110,15 @@ __device__ __forceinline__ f32x4 ld4v(const float* __restrict__ p, size_t i0, si
   return f32x4{t[0], t[1], t[2], t[3]};
 }
 
+// Index of element i0 (subdomain i0 / lohi_len) in the bound arrays lo/hi, whose
+// rows may be shared by row_div consecutive subdomains.
+__device__ __forceinline__ size_t lohi_index(const EpiArgs& E, size_t i0) {
+  if (E.row_div <= 1) return i0;
+  const size_t n = (size_t)E.lohi_len;
+  const size_t b = i0 / n;
+  return (b / (size_t)E.row_div) * n + (i0 - b * n);
+}
+
 // NA: arrays an epilogue of this launch may read (kinds that read more are not
 // launched with NA < 6; the members past NA stay zero)
 template <bool VEC, int NA = 6>
@@ -118,15 +127,17 @@ __device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st,
     case EPI_P0:
     case EPI_CROWN:
     case EPI_WK:
-    case EPI_RELU_FWD:
-      in.a0 = ld4v<VEC>(E.lo, i0, st, nv);
-      in.a1 = ld4v<VEC>(E.hi, i0, st, nv);
-      break;
-    case EPI_INNER_MIN:
+    case EPI_RELU_FWD: {
+      const size_t il = lohi_index(E, i0);
+      in.a0 = ld4v<VEC>(E.lo, il, st, nv);
+      in.a1 = ld4v<VEC>(E.hi, il, st, nv);
+    } break;
+    case EPI_INNER_MIN: {
+      const size_t il = lohi_index(E, i0);
       in.a0 = ld4v<VEC>(E.rho, i0, st, nv);
-      in.a1 = ld4v<VEC>(E.lo, i0, st, nv);
-      in.a2 = ld4v<VEC>(E.hi, i0, st, nv);
-      break;
+      in.a1 = ld4v<VEC>(E.lo, il, st, nv);
+      in.a2 = ld4v<VEC>(E.hi, il, st, nv);
+    } break;
     case EPI_ADAM:
       if (NA >= 4) {
         in.a0 = ld4v<VEC>(E.rho_w, i0, st, nv);
@@ -137,12 +148,13 @@ __device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st,
       break;
     case EPI_ADAM_LAST:
       if (NA >= 6) {
+        const size_t il = lohi_index(E, i0);
         in.a0 = ld4v<VEC>(E.rho_w, i0, st, nv);
         in.a1 = ld4v<VEC>(E.m, i0, st, nv);
         in.a2 = ld4v<VEC>(E.v, i0, st, nv);
         in.a3 = ld4v<VEC>(E.gc, i0, st, nv);
-        in.a4 = ld4v<VEC>(E.lo, i0, st, nv);
-        in.a5 = ld4v<VEC>(E.hi, i0, st, nv);
+        in.a4 = ld4v<VEC>(E.lo, il, st, nv);
+        in.a5 = ld4v<VEC>(E.hi, il, st, nv);
       }
       break;
     case EPI_SUPERGRAD:
@@ -867,6 +879,7 @@ static hipError_t launch_conv_tn(const GemmPack& P, const GemmGeom* geo_dev, int
   const GemmGeom* ga = geo_dev;
   const void* sa = src;
   EpiArgs ea = e;
+  ea.lohi_len = G.dst_n;
   int a0 = img, a1 = hw4, a2 = kpm, a3 = neff, a4 = bst, a5 = parts, a6 = outf;
   void* args[] = {(void*)&pa, (void*)&ga, (void*)&sa, (void*)&ea, (void*)&a0, (void*)&a1, (void*)&a2, (void*)&a3,
                   (void*)&a4, (void*)&a5, (void*)&a6};
@@ -887,8 +900,10 @@ hipError_t launch_conv(const GemmGeom* geoms, const GemmGeom* geo_dev, int n, in
 }
 
 template <int TN>
-static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e,
+static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e_in,
                                const SplitArgs& sp, int wm, int kw, hipStream_t s) {
+  EpiArgs e = e_in;
+  e.lohi_len = G.dst_n;
   if ((wm != 1 && wm != 2 && wm != 4) || (kw != 1 && kw != 2 && kw != 4 && kw != 8) || wm * kw > 16)
     return hipErrorInvalidValue;
   const int mt = 16 * wm;
@@ -1192,6 +1207,7 @@ hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16,
   ColGeom ga = g;
   const float* ra = rho;
   EpiArgs ea = e;
+  ea.lohi_len = g.Ci * g.HW;  // the destination map per subdomain
   int sa = split ? 1 : 0;
   void* args[] = {(void*)&ga, (void*)&ra, (void*)&ea, (void*)&sa};
   return hipLaunchKernel(fn, dim3((unsigned)((size_t)B * (split ? g.nchunks : 1))), dim3(kTThreads), args, lds, s);
@@ -1208,7 +1224,7 @@ __global__ void inner_min_const_kernel(int B, int n, const float* __restrict__ g
                                        const float* __restrict__ bias, int bias_hw, float tau,
                                        float* __restrict__ xb, double* __restrict__ val, int* t_dev,
                                        float* adam, double lr0, double lr_end, int total, double beta1,
-                                       double beta2, double eps) {
+                                       double beta2, double eps, int row_div) {
   const size_t total_n = (size_t)B * n;
   if (t_dev != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
     const int t = *t_dev + 1;
@@ -1223,25 +1239,28 @@ __global__ void inner_min_const_kernel(int B, int n, const float* __restrict__ g
   }
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total_n; i += (size_t)gridDim.x * blockDim.x) {
     const int j = (int)(i % n);
+    const size_t il = row_div > 1 ? (i / n / row_div) * n + j : i;  // the subdomain's bound row
     if (val != nullptr) {
       double xbd, xd, v;
       const double r = rho[i];
-      inner_min<double>(r, g[i], lo[i], hi[i], (double)tau, xbd, xd, v);
+      inner_min<double>(r, g[i], lo[il], hi[il], (double)tau, xbd, xd, v);
       val[i] = v - r * (double)bias[j / bias_hw];
       xb[i] = (float)xbd;
     } else {
       float xbf, xf, v;
-      inner_min<float>(rho[i], g[i], lo[i], hi[i], tau, xbf, xf, v);
+      inner_min<float>(rho[i], g[i], lo[il], hi[il], tau, xbf, xf, v);
       xb[i] = xbf;
     }
   }
 }
 
 __global__ void crown_const_kernel(int B, int n, const float* __restrict__ g, const float* __restrict__ lo,
-                                   const float* __restrict__ hi, float* __restrict__ rho, int wk) {
+                                   const float* __restrict__ hi, float* __restrict__ rho, int wk, int row_div) {
   const size_t total_n = (size_t)B * n;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total_n; i += (size_t)gridDim.x * blockDim.x)
-    rho[i] = crown_dual(g[i], lo[i], hi[i], wk != 0);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total_n; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t il = row_div > 1 ? (i / n / row_div) * n + i % n : i;  // the subdomain's bound row
+    rho[i] = crown_dual(g[i], lo[il], hi[il], wk != 0);
+  }
 }
 
 // q[b] = cb[b] + sum over arrays of sum_j arr[b, j]; fixed summation order (FP64).
@@ -1318,15 +1337,16 @@ static unsigned grid_for(size_t n) {
 hipError_t launch_inner_min_const(int B, int n, const float* g, const float* rho, const float* lo,
                                   const float* hi, const float* bias, int bias_hw, float tau, float* xb,
                                   double* val, int* t_dev, float* adam, double lr0, double lr_end, int total,
-                                  double beta1, double beta2, double eps, hipStream_t s) {
+                                  double beta1, double beta2, double eps, int row_div, hipStream_t s) {
   hipLaunchKernelGGL(inner_min_const_kernel, dim3(grid_for((size_t)B * n)), dim3(256), 0, s, B, n, g, rho, lo, hi,
-                     bias, bias_hw, tau, xb, val, t_dev, adam, lr0, lr_end, total, beta1, beta2, eps);
+                     bias, bias_hw, tau, xb, val, t_dev, adam, lr0, lr_end, total, beta1, beta2, eps, row_div);
   return hipGetLastError();
 }
 
 hipError_t launch_crown_const(int B, int n, const float* g, const float* lo, const float* hi, float* rho, int wk,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(crown_const_kernel, dim3(grid_for((size_t)B * n)), dim3(256), 0, s, B, n, g, lo, hi, rho, wk);
+                              int row_div, hipStream_t s) {
+  hipLaunchKernelGGL(crown_const_kernel, dim3(grid_for((size_t)B * n)), dim3(256), 0, s, B, n, g, lo, hi, rho, wk,
+                     row_div);
   return hipGetLastError();
 }
 
