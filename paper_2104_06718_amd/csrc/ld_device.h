@@ -125,6 +125,12 @@ struct Mma<true> {
       al[j] = (__bf16)(a[j] - (float)ah[j]);
     }
   }
+  // the same three terms with the operand already split (head ah, remainder al)
+  __device__ static void mma3_frag(const AFrag& ah, const AFrag& al, const BFrag& bh, const BFrag& bl, f32x4& c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  }
   __device__ static void mma3(const float (&a)[8], const BFrag& bh, const BFrag& bl, f32x4& c) {
     bf16x8 ah, al;
     split(a, ah, al);

@@ -318,8 +318,6 @@ __device__ __forceinline__ int fdiv(int e, int d, float inv) {
   return q;
 }
 
-// LDS words holding the class geometries (copied from device memory at staging)
-constexpr int kGeoWords = (int)((sizeof(GemmGeom) + 15) / 16 * 4);
 
 // MM: operands of the product: 0 FP32, 1 BF16, 2 compensated BF16 (FP32 source)
 // The LDS image is channel-last ([LH][LW][CP]) and k runs (tap, channel) with the
@@ -349,20 +347,33 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   const int wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
   const int H = G0.src_H, W = G0.src_W, HW = H * W;
   const int C = G0.src_n / HW;
-  int* geo = reinterpret_cast<int*>(lds);                  // [n classes][kGeoWords]
-  float* img = lds + P.n * kGeoWords;                      // [LH][LW][CP]
+  // the source map, channel-last [LH][LW][CP]: FP32 (MM == 0), or BF16 heads in the
+  // first half of the same area (MM == 1) and BF16 remainders in its second half
+  // (MM == 2), split once here instead of at every use in the products
+  float* img = lds;
+  bf16_t* imgh = reinterpret_cast<bf16_t*>(img);
+  bf16_t* imgl = imgh + img_floats;
   const int CP = G0.CP;
   const int Cq = (C + 3) & ~3;  // channels of a pixel that k reads (the ones past C are zero)
   float* outp = img + img_floats;                          // [channels][band]
   int* kofs = reinterpret_cast<int*>(outp + out_floats);   // [n classes][kp_max]
-  WT* wB = reinterpret_cast<WT*>(lds + ((P.n * kGeoWords + img_floats + out_floats + P.n * kp_max + 3) & ~3));  // [n classes][n_eff][bstride], 16-byte aligned
+  WT* wB = reinterpret_cast<WT*>(lds + ((img_floats + out_floats + P.n * kp_max + 3) & ~3));  // [n classes][n_eff][bstride], 16-byte aligned
   WT* wBl = wB + (size_t)P.n * n_eff * bstride;  // MM == 2: the BF16 remainders, same layout
+  auto put = [&](int idx, float v) __attribute__((always_inline)) {
+    if constexpr (MM == 0) {
+      img[idx] = v;
+    } else {
+      const __bf16 h = (__bf16)v;
+      imgh[idx] = __builtin_bit_cast(bf16_t, h);
+      if constexpr (MM == 2) imgl[idx] = __builtin_bit_cast(bf16_t, (__bf16)(v - (float)h));
+    }
+  };
 
   adam_tick(E);
-  // 1. staging.  A thread's first round of global loads (its geometry word, up to U
-  //    float4 of the source map, its gather offset and weight vectors of every
-  //    class) is issued before any LDS write, so the block waits for one memory
-  //    latency; larger maps and weight sets continue in further rounds.
+  // 1. staging.  A thread's first round of global loads (up to U float4 of the
+  //    source map, its gather offset and weight vectors of every class) is issued
+  //    before any LDS write, so the block waits for one memory latency; larger maps
+  //    and weight sets continue in further rounds.
   const size_t sbase = (size_t)b * G0.src_n;
   const float inv_w = 1.0f / (float)W, inv_h = 1.0f / (float)H;
   const bool vec_img = (W & 3) == 0;
@@ -389,21 +400,15 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
     const int x = e - row * W;
     const int c = fdiv(row, H, inv_h);
     const int y = row - c * H;
-    float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP + c;
+    const int d = ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP + c;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) d[q * CP] = v[q];
+    for (int q = 0; q < 4; ++q) put(d + q * CP, v[q]);
     if (c == C - 1)  // the padding channels of these pixels
       for (int cc = C; cc < Cq; ++cc)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d[q * CP + cc - c] = 0.f;
+        for (int q = 0; q < 4; ++q) put(d + q * CP + cc - c, 0.f);
   };
   // (a) the first round of loads
-  const int ngeo = P.n * kGeoWords;
-  int gword = 0;
-  if (tid < ngeo) {
-    const int c = tid / kGeoWords, w = tid - c * kGeoWords;
-    if (w * 4 < (int)sizeof(GemmGeom)) gword = reinterpret_cast<const int*>(geo_dev + c)[w];
-  }
   float v0[U][4];
   if (vec_img) {
 #pragma unroll
@@ -449,7 +454,6 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   load_classes(0);
   // (b) their LDS writes, and the zero border of the image (disjoint from the interior:
   //     border pixels, all Cq channels; the CP - Cq floats past them are never read)
-  if (tid < ngeo) geo[tid] = gword;
   if (vec_img) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -462,18 +466,20 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
     for (int e = tid; e < G0.LH * G0.LW * c4; e += kConvThreads) {
       const int pix = e / c4, q = e - pix * c4;
       const int yy = fdiv(pix, G0.LW, inv_lw), xx = pix - yy * G0.LW;
-      if (yy < G0.pad_t || yy >= G0.pad_t + H || xx < G0.pad_l || xx >= G0.pad_l + W)
-        *reinterpret_cast<float4*>(img + pix * CP + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (yy < G0.pad_t || yy >= G0.pad_t + H || xx < G0.pad_l || xx >= G0.pad_l + W) {
+        if constexpr (MM == 0) {
+          *reinterpret_cast<float4*>(img + pix * CP + 4 * q) = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+          *reinterpret_cast<uint2*>(imgh + pix * CP + 4 * q) = make_uint2(0u, 0u);
+          if constexpr (MM == 2) *reinterpret_cast<uint2*>(imgl + pix * CP + 4 * q) = make_uint2(0u, 0u);
+        }
+      }
     }
   }
   // (c) further rounds
   for (int c0 = kStageClasses; c0 < P.n; c0 += kStageClasses) {
     load_classes(c0);
     store_classes(c0);
-  }
-  for (int i = tid + kConvThreads; i < ngeo; i += kConvThreads) {
-    const int c = i / kGeoWords, w = i - c * kGeoWords;
-    if (w * 4 < (int)sizeof(GemmGeom)) geo[i] = reinterpret_cast<const int*>(geo_dev + c)[w];
   }
   if (vec_img) {
     for (int i0 = tid + U * kConvThreads; i0 < n4; i0 += U * kConvThreads) {
@@ -492,10 +498,10 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       const int x = e - row * W;
       const int c = fdiv(row, H, inv_h);
       const int y = row - c * H;
-      float* d = img + ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP;
-      d[c] = v;
+      const int d = ((y + G0.pad_t) * G0.LW + x + G0.pad_l) * CP;
+      put(d + c, v);
       if (c == C - 1)
-        for (int cc = C; cc < Cq; ++cc) d[cc] = 0.f;
+        for (int cc = C; cc < Cq; ++cc) put(d + cc, 0.f);
     }
   }
   for (int c = 0; c < P.n; ++c) {
@@ -519,31 +525,31 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   }
   __syncthreads();
 
-  // 2. MFMA tiles of every class into the LDS destination map (class geometry
-  //    read from LDS, uniform across the block)
+  // 2. MFMA tiles of every class into the LDS destination map
   int tiles_before = 0;
   for (int cl = 0; cl < P.n; ++cl) {
-    const GemmGeom* Gl = reinterpret_cast<const GemmGeom*>(geo + cl * kGeoWords);
+    // the class geometry from the kernel arguments (uniform: scalar loads)
+    const GemmGeom& Gl = P.g[cl];
     struct {
       int HWq, Wq, iy_mul, iy_off, ix_mul, ix_off, pad_t, pad_l, LW, K, N, dst_HW, dst_W, oy_mul, oy_off, ox_mul, ox_off;
     } G;
-    G.HWq = __builtin_amdgcn_readfirstlane(Gl->HWq);
-    G.Wq = __builtin_amdgcn_readfirstlane(Gl->Wq);
-    G.iy_mul = __builtin_amdgcn_readfirstlane(Gl->iy_mul);
-    G.iy_off = __builtin_amdgcn_readfirstlane(Gl->iy_off);
-    G.ix_mul = __builtin_amdgcn_readfirstlane(Gl->ix_mul);
-    G.ix_off = __builtin_amdgcn_readfirstlane(Gl->ix_off);
-    G.pad_t = __builtin_amdgcn_readfirstlane(Gl->pad_t);
-    G.pad_l = __builtin_amdgcn_readfirstlane(Gl->pad_l);
-    G.LW = __builtin_amdgcn_readfirstlane(Gl->LW);
-    G.K = __builtin_amdgcn_readfirstlane(Gl->K);
-    G.N = __builtin_amdgcn_readfirstlane(Gl->N);
-    G.dst_HW = __builtin_amdgcn_readfirstlane(Gl->dst_HW);
-    G.dst_W = __builtin_amdgcn_readfirstlane(Gl->dst_W);
-    G.oy_mul = __builtin_amdgcn_readfirstlane(Gl->oy_mul);
-    G.oy_off = __builtin_amdgcn_readfirstlane(Gl->oy_off);
-    G.ox_mul = __builtin_amdgcn_readfirstlane(Gl->ox_mul);
-    G.ox_off = __builtin_amdgcn_readfirstlane(Gl->ox_off);
+    G.HWq = Gl.HWq;
+    G.Wq = Gl.Wq;
+    G.iy_mul = Gl.iy_mul;
+    G.iy_off = Gl.iy_off;
+    G.ix_mul = Gl.ix_mul;
+    G.ix_off = Gl.ix_off;
+    G.pad_t = Gl.pad_t;
+    G.pad_l = Gl.pad_l;
+    G.LW = Gl.LW;
+    G.K = Gl.K;
+    G.N = Gl.N;
+    G.dst_HW = Gl.dst_HW;
+    G.dst_W = Gl.dst_W;
+    G.oy_mul = Gl.oy_mul;
+    G.oy_off = Gl.oy_off;
+    G.ox_mul = Gl.ox_mul;
+    G.ox_off = Gl.ox_off;
     const int* ko = kofs + cl * kp_max;
     const WT* wc = wB + (size_t)cl * n_eff * bstride;
     const WT* wcl = wBl + (size_t)cl * n_eff * bstride;
@@ -585,28 +591,51 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
         int ofs[VPL / 4];
 #pragma unroll
         for (int j = 0; j < VPL; j += 4) ofs[j / 4] = ko[kl + j];
-        float a[2][VPL];
+        if constexpr (MM == 0) {
+          float a[2][VPL];
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+          for (int m = 0; m < 2; ++m)
 #pragma unroll
-          for (int j = 0; j < VPL; j += 4) {
-            const float4 v = *reinterpret_cast<const float4*>(img + lb[m] + ofs[j / 4]);
-            a[m][j] = v.x;
-            a[m][j + 1] = v.y;
-            a[m][j + 2] = v.z;
-            a[m][j + 3] = v.w;
-          }
+            for (int j = 0; j < VPL; j += 4) {
+              const float4 v = *reinterpret_cast<const float4*>(img + lb[m] + ofs[j / 4]);
+              a[m][j] = v.x;
+              a[m][j + 1] = v.y;
+              a[m][j + 2] = v.z;
+              a[m][j + 3] = v.w;
+            }
 #pragma unroll
-        for (int t = 0; t < TN; ++t) {
-          const size_t wo = (size_t)(nc + 16 * t + r) * bstride + kl;
-          const BFrag bf = *reinterpret_cast<const BFrag*>(wc + wo);
-          if constexpr (MM == 2) {
-            const BFrag bfl = *reinterpret_cast<const BFrag*>(wcl + wo);
-#pragma unroll
-            for (int m = 0; m < 2; ++m) M::mma3(a[m], bf, bfl, acc[m][t]);
-          } else {
+          for (int t = 0; t < TN; ++t) {
+            const size_t wo = (size_t)(nc + 16 * t + r) * bstride + kl;
+            const BFrag bf = *reinterpret_cast<const BFrag*>(wc + wo);
 #pragma unroll
             for (int m = 0; m < 2; ++m) M::mma(a[m], bf, acc[m][t]);
+          }
+        } else {
+          // BF16 fragments straight from the split map: two runs of 4 channels
+          bf16x8 ah[2], al[2];
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            const uint2 h0 = *reinterpret_cast<const uint2*>(imgh + lb[m] + ofs[0]);
+            const uint2 h1 = *reinterpret_cast<const uint2*>(imgh + lb[m] + ofs[1]);
+            ah[m] = __builtin_bit_cast(bf16x8, u32x4{h0.x, h0.y, h1.x, h1.y});
+            if constexpr (MM == 2) {
+              const uint2 l0 = *reinterpret_cast<const uint2*>(imgl + lb[m] + ofs[0]);
+              const uint2 l1 = *reinterpret_cast<const uint2*>(imgl + lb[m] + ofs[1]);
+              al[m] = __builtin_bit_cast(bf16x8, u32x4{l0.x, l0.y, l1.x, l1.y});
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < TN; ++t) {
+            const size_t wo = (size_t)(nc + 16 * t + r) * bstride + kl;
+            const BFrag bf = *reinterpret_cast<const BFrag*>(wc + wo);
+            if constexpr (MM == 2) {
+              const BFrag bfl = *reinterpret_cast<const BFrag*>(wcl + wo);
+#pragma unroll
+              for (int m = 0; m < 2; ++m) M::mma3_frag(ah[m], al[m], bf, bfl, acc[m][t]);
+            } else {
+#pragma unroll
+              for (int m = 0; m < 2; ++m) M::mma_frag(ah[m], bf, acc[m][t]);
+            }
           }
         }
       }
@@ -837,7 +866,7 @@ static int conv_out_floats(const GemmGeom& g, int parts) {
 size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16, int parts) {
   // BF16 weights (mode 1), FP32 (0), or BF16 heads and remainders (2)
   const size_t wbytes = (size_t)n_classes * conv_n_eff(g[0], tn) * conv_bstride(g, n_classes, mma_bf16) * (mma_bf16 == 1 ? 2 : 4);
-  return (((size_t)n_classes * kGeoWords + conv_img_floats(g[0]) + conv_out_floats(g[0], parts) +
+  return (((size_t)conv_img_floats(g[0]) + conv_out_floats(g[0], parts) +
            (size_t)n_classes * max_kp(g, n_classes) + 3) & ~(size_t)3) * 4 +
          wbytes;
 }
