@@ -335,6 +335,10 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   constexpr int KS = M::KS, VPL = M::VPL, EPV = 16 / (int)sizeof(WT);
   extern __shared__ float lds[];
   const GemmGeom& G0 = P.g[0];
+  // the scalars of the staging, loaded together ahead of everything else (the pin
+  // emits no instruction)
+  asm volatile("" ::"s"(G0.src_n), "s"(G0.src_H), "s"(G0.src_W), "s"(G0.CP), "s"(G0.LW), "s"(G0.LH),
+               "s"(G0.pad_t), "s"(G0.pad_l), "s"(G0.dst_HW), "s"(G0.dst_W), "s"(P.n), "s"(src_v));
   const int b = blockIdx.x / parts, part = blockIdx.x - b * parts;
   const int tid = threadIdx.x;
   // destination rows of this block and their run length per channel
@@ -369,7 +373,6 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
     }
   };
 
-  adam_tick(E);
   // 1. staging.  A thread's first round of global loads (up to U float4 of the
   //    source map, its gather offset and weight vectors of every class) is issued
   //    before any LDS write, so the block waits for one memory latency; larger maps
@@ -408,28 +411,35 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
 #pragma unroll
         for (int q = 0; q < 4; ++q) put(d + q * CP + cc - c, 0.f);
   };
-  // (a) the first round of loads
-  float v0[U][4];
-  if (vec_img) {
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (tid + u * kConvThreads < n4) load_img4(tid + u * kConvThreads, v0[u]);
-  }
-  // gather offsets and weight vectors of a group of up to kStageClasses classes
+  // gather offsets and weight vectors of a group of up to kStageClasses classes;
+  // the group's scalars (pointers, lengths) are read first, unconditionally, so
+  // their loads from the kernel arguments are issued together
   constexpr int kStageClasses = 4;
-  int kv[kStageClasses];
+  int kv[kStageClasses], kp[kStageClasses];
+  const int* kt[kStageClasses];
+  const u32x4* wsrc[kStageClasses];
+  const u32x4* wlsrc[kStageClasses];
   u32x4 wh[kStageClasses], wl[kStageClasses];
+  auto class_scalars = [&](int c0) __attribute__((always_inline)) {
+    static_for<kStageClasses>([&](auto ci) __attribute__((always_inline)) {
+      constexpr int i = decltype(ci)::value;
+      const GemmGeom& G = P.g[min(c0 + i, kMaxClasses - 1)];  // in bounds; unused past P.n
+      kp[i] = G.Kp;
+      kt[i] = G.ktab_cl;
+      wsrc[i] = reinterpret_cast<const u32x4*>(MMA_BF16 ? (const void*)G.Bh : (const void*)G.Bf);
+      wlsrc[i] = reinterpret_cast<const u32x4*>(G.Bhl);
+      // keep the scalar loads here, ahead of the branches below (no instruction)
+      asm volatile("" ::"s"(kp[i]), "s"(kt[i]), "s"(wsrc[i]), "s"(wlsrc[i]));
+    });
+  };
   auto load_classes = [&](int c0) __attribute__((always_inline)) {
     static_for<kStageClasses>([&](auto ci) __attribute__((always_inline)) {
       constexpr int i = decltype(ci)::value;
-      const int c = c0 + i;
-      if (c < P.n) {
-        const GemmGeom& G = P.g[c];
-        if (tid < G.Kp) kv[i] = G.ktab_cl[tid];
-        const int vr = G.Kp / EPV;
-        if (tid < n_eff * vr) {
-          wh[i] = reinterpret_cast<const u32x4*>(MMA_BF16 ? (const void*)G.Bh : (const void*)G.Bf)[tid];
-          if (MM == 2) wl[i] = reinterpret_cast<const u32x4*>(G.Bhl)[tid];
+      if (c0 + i < P.n) {
+        if (tid < kp[i]) kv[i] = kt[i][tid];
+        if (tid < n_eff * (kp[i] / EPV)) {
+          wh[i] = wsrc[i][tid];
+          if (MM == 2) wl[i] = wlsrc[i][tid];
         }
       }
     });
@@ -439,9 +449,8 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       constexpr int i = decltype(ci)::value;
       const int c = c0 + i;
       if (c < P.n) {
-        const GemmGeom& G = P.g[c];
-        if (tid < G.Kp) kofs[c * kp_max + tid] = kv[i];
-        const int vr = G.Kp / EPV;
+        if (tid < kp[i]) kofs[c * kp_max + tid] = kv[i];
+        const int vr = kp[i] / EPV;
         if (tid < n_eff * vr) {
           const int row = tid / vr, v = tid - row * vr;
           const size_t o = ((size_t)c * n_eff + row) * bstride + v * EPV;
@@ -451,7 +460,16 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       }
     });
   };
+  // (a) the first round of loads
+  class_scalars(0);
+  float v0[U][4];
+  if (vec_img) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (tid + u * kConvThreads < n4) load_img4(tid + u * kConvThreads, v0[u]);
+  }
   load_classes(0);
+  adam_tick(E);
   // (b) their LDS writes, and the zero border of the image (disjoint from the interior:
   //     border pixels, all Cq channels; the CP - Cq floats past them are never read)
   if (vec_img) {
@@ -478,6 +496,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   }
   // (c) further rounds
   for (int c0 = kStageClasses; c0 < P.n; c0 += kStageClasses) {
+    class_scalars(c0);
     load_classes(c0);
     store_classes(c0);
   }
