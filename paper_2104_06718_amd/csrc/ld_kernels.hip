@@ -120,20 +120,23 @@ __device__ __forceinline__ size_t lohi_index(const EpiArgs& E, size_t i0) {
 }
 
 // NA: arrays an epilogue of this launch may read (kinds that read more are not
-// launched with NA < 6; the members past NA stay zero)
-template <bool VEC, int NA = 6>
-__device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st, int nv, EpiIn& in) {
+// launched with NA < 6; the members past NA stay zero). SHIFT: the caller's
+// elements lie in one subdomain, whose bound rows sit lohi_shift elements from i0.
+template <bool VEC, int NA = 6, bool SHIFT = false>
+__device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st, int nv, EpiIn& in,
+                                         ptrdiff_t lohi_shift = 0) {
+  const auto lohi_at = [&](size_t i) { return SHIFT ? (size_t)((ptrdiff_t)i + lohi_shift) : lohi_index(E, i); };
   switch (E.kind) {
     case EPI_P0:
     case EPI_CROWN:
     case EPI_WK:
     case EPI_RELU_FWD: {
-      const size_t il = lohi_index(E, i0);
+      const size_t il = lohi_at(i0);
       in.a0 = ld4v<VEC>(E.lo, il, st, nv);
       in.a1 = ld4v<VEC>(E.hi, il, st, nv);
     } break;
     case EPI_INNER_MIN: {
-      const size_t il = lohi_index(E, i0);
+      const size_t il = lohi_at(i0);
       in.a0 = ld4v<VEC>(E.rho, i0, st, nv);
       in.a1 = ld4v<VEC>(E.lo, il, st, nv);
       in.a2 = ld4v<VEC>(E.hi, il, st, nv);
@@ -148,7 +151,7 @@ __device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st,
       break;
     case EPI_ADAM_LAST:
       if (NA >= 6) {
-        const size_t il = lohi_index(E, i0);
+        const size_t il = lohi_at(i0);
         in.a0 = ld4v<VEC>(E.rho_w, i0, st, nv);
         in.a1 = ld4v<VEC>(E.m, i0, st, nv);
         in.a2 = ld4v<VEC>(E.v, i0, st, nv);
@@ -1032,6 +1035,8 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   const int* cx = tx + G.W * G.Tmax;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
   const size_t dst_base = (size_t)b * G.Ci * G.HW;
+  // the subdomain's bound rows, shared by row_div consecutive subdomains
+  const ptrdiff_t lshift = (ptrdiff_t)(b / max(E.row_div, 1) - b) * E.lohi_len;
   constexpr int STEP = 4 * kTThreads;
   const bool vec = (G.HW & 3) == 0;
   // operands of the thread's first epilogue group of a chunk: for the first
@@ -1039,62 +1044,69 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   EpiIn nx{};
   auto prefetch = [&](int e0, int e1) {
     if (vec) {
-      if (e0 + 4 * tid < e1) epi_load<true, 3>(E, dst_base + e0 + 4 * tid, 1, 4, nx);
+      if (e0 + 4 * tid < e1) epi_load<true, 3, true>(E, dst_base + e0 + 4 * tid, 1, 4, nx, lshift);
     } else {
-      if (e0 + tid < e1) epi_load<false, 3>(E, dst_base + e0 + tid, 1, 1, nx);
+      if (e0 + tid < e1) epi_load<false, 3, true>(E, dst_base + e0 + tid, 1, 1, nx, lshift);
     }
   };
   prefetch(c_first * G.Cc * G.HW, min(G.Ci, (c_first + 1) * G.Cc) * G.HW);
   adam_tick(E);
-  // 0. staging
+  // 0. staging: K groups holding channels of rho are gathered (every load of a
+  // round in flight before the LDS writes; the index is clamped into the map and
+  // the value masked), the groups of the K padding are zero-filled
   {
-    constexpr int UC = 4, UF = 8;
+    constexpr int UC = 16 / VPL, UF = 8;  // 16 gathered values per thread and round
     const float* src = rho + (size_t)b * G.Co * G.M;
     const int ncell = kq_n * G.Mp;
-    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    const int ncell_r = min(ncell, ((G.Co + VPL - 1) / VPL) * G.Mp);
     const u32x4* fsrc = reinterpret_cast<const u32x4*>(BF ? (const void*)G.Bh : (const void*)G.Bf) +
                         (size_t)c_first * G.ntc * ks * 64;
     const float inv_mp = 1.0f / (float)G.Mp;
-    const int rounds = max((ncell + UC * kTThreads - 1) / (UC * kTThreads), (nfrag + UF * kTThreads - 1) / (UF * kTThreads));
-    for (int rd = 0; rd < rounds; ++rd) {
+    const int rounds = max((ncell_r + UC * kTThreads - 1) / (UC * kTThreads), (nfrag + UF * kTThreads - 1) / (UF * kTThreads));
+    // one round: every load in flight (indexes clamped into the arrays), then the
+    // LDS writes (the first round is straight-line code, so no wait carries over
+    // from a later round's registers)
+    const auto round = [&](const int rd) __attribute__((always_inline)) {
       float v[UC][VPL];
+      int kqs[UC], ms[UC];
       u32x4 f[UF];
       int tv = 0;
+      static_for<UC>([&](auto uc) __attribute__((always_inline)) {
+        constexpr int u = decltype(uc)::value;
+        const int cell = min((rd * UC + u) * kTThreads + tid, ncell_r - 1);
+        kqs[u] = fdiv(cell, G.Mp, inv_mp);
+        ms[u] = cell - kqs[u] * G.Mp;
+        const float* s0 = src + (unsigned)min(ms[u], G.M - 1);
 #pragma unroll
-      for (int u = 0; u < UC; ++u) {
-        const int cell = (rd * UC + u) * kTThreads + tid;
-        if (cell < ncell) {
-          const int kq = fdiv(cell, G.Mp, inv_mp), m = cell - kq * G.Mp;
-#pragma unroll
-          for (int j = 0; j < VPL; ++j) {
-            const int k = kq * VPL + j;
-            v[u][j] = (k < G.Co && m < G.M) ? src[(size_t)k * G.M + m] : 0.f;
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < UF; ++u) {
+        for (int j = 0; j < VPL; ++j) v[u][j] = s0[(unsigned)(min(kqs[u] * VPL + j, G.Co - 1) * G.M)];
+      });
+      static_for<UF>([&](auto uf) __attribute__((always_inline)) {
+        constexpr int u = decltype(uf)::value;
         const int i = (rd * UF + u) * kTThreads + tid;
         if (i < nfrag) f[u] = fsrc[i];
-      }
+      });
       if (rd == 0 && tid < G.ntab) tv = G.tab[tid];
-#pragma unroll
-      for (int u = 0; u < UC; ++u) {
+      if (rd == 0)
+        for (int i = ncell_r + tid; i < ncell; i += kTThreads) *reinterpret_cast<AFrag*>(A + (size_t)i * VPL) = AFrag{};
+      static_for<UC>([&](auto uc) __attribute__((always_inline)) {
+        constexpr int u = decltype(uc)::value;
         const int cell = (rd * UC + u) * kTThreads + tid;
-        if (cell < ncell) {
+        if (cell < ncell_r) {
           AFrag a;
 #pragma unroll
-          for (int j = 0; j < VPL; ++j) a[j] = (AT)v[u][j];
+          for (int j = 0; j < VPL; ++j) a[j] = (kqs[u] * VPL + j < G.Co && ms[u] < G.M) ? (AT)v[u][j] : (AT)0.f;
           *reinterpret_cast<AFrag*>(A + (size_t)cell * VPL) = a;
         }
-      }
-#pragma unroll
-      for (int u = 0; u < UF; ++u) {
+      });
+      static_for<UF>([&](auto uf) __attribute__((always_inline)) {
+        constexpr int u = decltype(uf)::value;
         const int i = (rd * UF + u) * kTThreads + tid;
         if (i < nfrag) reinterpret_cast<u32x4*>(Bl)[i] = f[u];
-      }
+      });
       if (rd == 0 && tid < G.ntab) tab[tid] = tv;
-    }
+    };
+    round(0);
+    for (int rd = 1; rd < rounds; ++rd) round(rd);
     for (int i = tid + kTThreads; i < G.ntab; i += kTThreads) tab[i] = G.tab[i];
   }
   __syncthreads();
@@ -1142,7 +1154,7 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     if (vec) {
       for (int e = e0 + 4 * tid; e < e1; e += STEP) {
         const EpiIn cur = nx;
-        if (e + STEP < e1) epi_load<true, 3>(E, dst_base + e + STEP, 1, 4, nx);
+        if (e + STEP < e1) epi_load<true, 3, true>(E, dst_base + e + STEP, 1, 4, nx, lshift);
         const int ci = fdiv(e, G.HW, G.inv_HW);
         const int rem = e - ci * G.HW;
         int y = fdiv(rem, G.W, G.inv_W);
@@ -1201,7 +1213,7 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     } else {
       for (int e = e0 + tid; e < e1; e += kTThreads) {
         const EpiIn cur = nx;
-        if (e + kTThreads < e1) epi_load<false, 3>(E, dst_base + e + kTThreads, 1, 1, nx);
+        if (e + kTThreads < e1) epi_load<false, 3, true>(E, dst_base + e + kTThreads, 1, 1, nx, lshift);
         const int ci = fdiv(e, G.HW, G.inv_HW);
         const int rem = e - ci * G.HW;
         const int y = fdiv(rem, G.W, G.inv_W);
