@@ -57,6 +57,14 @@ def parse():
                     help="for rocprofv3: one 1 GiB device copy (counter calibration), then --reps ascent "
                          "iterations launched without the graph; prints the per-launch averages")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--pin-tiles", metavar="FILE", default=None,
+                    help="after tuning, pin every contraction to the configuration that the bench line in this "
+                         "file (JSON, or a markdown summary with the line in a json block) reports for the "
+                         "precision (its 'tuned' entry), so that separate counter runs time the same kernels")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="start with the 1 GiB device copy of --profile-only (counter calibration), so that "
+                         "--profile-summary can read counter runs of the bench line itself: its last "
+                         "contraction launches are the BF16 per-launch timing of one iteration")
     ap.add_argument("--profile-summary", metavar="DIR", default=None,
                     help="no GPU: read the rocprofv3 outputs of --profile-only runs under DIR (T: --kernel-trace "
                          "--stats; F: --pmc FETCH_SIZE; W: --pmc WRITE_SIZE; M, optional: --pmc SQ_INSTS_VALU_MFMA_MOPS_BF16 "
@@ -205,6 +213,20 @@ def run_form(P, net, batch, st, iters, prec, steps, warmup, engine="auto"):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return dict(ms_per_step=e0.elapsed_time(e1) / steps, wall_ms_per_step=1000 * wall / steps, fb=fb)
+
+
+def pin_tiles(P, net, batch, prec, path):
+    """Tune (net, B, prec), then pin each contraction's configuration to the one the
+    bench line in `path` reports: a JSON file, or a markdown summary that holds the
+    line in a ```json block."""
+    with open(path) as fh:
+        text = fh.read()
+    if "```json" in text:
+        text = text.split("```json", 1)[1].split("```", 1)[0]
+    d = json.loads(text)
+    P.autotune(net, batch, precision=prec)
+    for lay in d["tuned"][prec]["layers"]:
+        P.set_tuned_config(net, batch.B, prec, lay["layer"], lay["dir"], lay)
 
 
 def cpu_baseline(inst, T, sample):
@@ -648,12 +670,13 @@ def split_shares(B, props):
 
 
 def profile_summary(a):
-    """Per-launch summary of the counter and trace runs of `bench.py --profile-only`:
-    the last 6 x (reps + 1) launches of the library's contraction kernels are one
-    iteration's slots (101..103, 301..303 for the 4-layer nets), each a warm-up and
-    `reps` timed launches; the first of each group is dropped.  HBM bytes are
-    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the counters read
-    for the 1 GiB device copy the profile mode starts with."""
+    """Per-launch summary of the counter and trace runs of `bench.py --profile-only`
+    (or of the bench line with --calibrate-copy, whose last contraction launches are
+    its BF16 per-launch timing): the last 6 x (reps + 1) launches of the library's
+    contraction kernels are one iteration's slots (101..103, 301..303 for the
+    4-layer nets), each a warm-up and `reps` timed launches; the first of each group
+    is dropped.  HBM bytes are FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by
+    what the counters read for the 1 GiB device copy the run starts with."""
     import csv
     import collections
     import ldgen
@@ -680,14 +703,15 @@ def profile_summary(a):
         if not os.path.exists(path):
             return None, None
         by = collections.defaultdict(lambda: collections.defaultdict(float))
-        meta, copy = {}, {}
+        meta = {}
         with open(path) as fh:
             for r in csv.DictReader(fh):
                 did = int(r["Dispatch_Id"])
                 by[did][r["Counter_Name"]] += float(r["Counter_Value"])
                 meta[did] = r
-                if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= (1 << 17):
-                    copy[r["Counter_Name"]] = copy.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        # the calibration: the largest device copy of the run (the 1 GiB copy)
+        cps = [i for i in meta if "copyBuffer" in meta[i]["Kernel_Name"] and int(meta[i]["Grid_Size"]) >= (1 << 17)]
+        copy = dict(by[max(cps, key=lambda i: int(meta[i]["Grid_Size"]))]) if cps else {}
         rows = [dict(meta[i], **{"_c": by[i]}) for i in meta]
         return groups(rows, lambda r: r["_c"]), copy
 
@@ -696,6 +720,12 @@ def profile_summary(a):
     F, cf = counters("F")
     W, cw = counters("W")
     M, _ = counters("M")
+    # every run must have timed the same kernel in each slot (pin the tiles across runs)
+    for nm, X in (("F", F), ("W", W), ("M", M)):
+        if X:
+            for sl in slots:
+                if X[sl][0] != tr[sl][0]:
+                    print(f"WARNING: slot {sl}: run {nm} launched {X[sl][0]}, the trace run {tr[sl][0]}")
     gib = 1 << 30
     ff = gib / (cf["FETCH_SIZE"] * 1024) if cf else None
     fw = gib / (cw["WRITE_SIZE"] * 1024) if cw else None
@@ -797,7 +827,7 @@ def main():
         main_bab(a, P, inst)
         return
 
-    if a.profile_only:
+    if a.profile_only or a.calibrate_copy:
         # counter calibration: a 1 GiB device copy (far larger than L2 and the MALL)
         x = torch.ones(256 << 20, device="cuda", dtype=torch.float32)
         y = torch.empty_like(x)
@@ -805,6 +835,7 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
+    if a.profile_only:
         stp = P.State(net, B)
         if a.solver == "prox":
             P.autotune(net, batch, precision=a.profile_only)
@@ -813,6 +844,8 @@ def main():
             slots = P.prox_profile_iteration(net, batch, stp, reps=a.reps, total_iters=Tp, precision=a.profile_only)
             name = lambda info, k: prox_kernel_name(info, k, inst, a.profile_only)  # noqa: E731
         else:
+            if a.pin_tiles:
+                pin_tiles(P, net, batch, a.profile_only, a.pin_tiles)
             P.step(net, batch, stp, iters=2, total_iters=T, precision=a.profile_only)
             slots = P.profile_iteration(net, batch, stp, reps=a.reps, total_iters=T, precision=a.profile_only)
             name = lambda info, k: kernel_name(info, k, inst, a.profile_only)  # noqa: E731
@@ -823,6 +856,9 @@ def main():
                           "tuned": info}), flush=True)
         return
 
+    if a.pin_tiles:
+        for prec in ("fp32", "bf16"):
+            pin_tiles(P, net, batch, prec, a.pin_tiles)
     st = P.State(net, B)
     res32 = run_form(P, net, batch, st, T, "fp32", a.steps, a.warmup, a.engine)
     b32 = res32["fb"]["bound"].clone()
