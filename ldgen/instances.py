@@ -114,6 +114,10 @@ CONFIGS: Dict[str, Dict] = {
     "tiny_conv4": dict(cfg=9, input=(8, 5, 5), eps=0.1, B=6, props=[4, 2], T=200,
                        arch=[_conv(8, 8, 3, 1, 1, 5), _conv(8, 16, 4, 2, 1, 5),
                              ("linear", 64, 6), ("linear", 6, 3)]),
+    # a transposed strided conv whose operand staging takes several rounds (36 channels,
+    # ragged in the BF16 and FP32 K groups, on an 11x11 map: 121 positions)
+    "tiny_conv5": dict(cfg=10, input=(2, 22, 22), eps=0.05, B=3, props=[2, 1], T=100,
+                       arch=[_conv(2, 36, 4, 2, 1, 22), ("linear", 4356, 8), ("linear", 8, 3)]),
     # small nets whose exact minimum is enumerable (branch-and-bound pins): FC 6-12-8-2
     # (12 root-ambiguous ReLUs) and conv 1->2 3x3/2 on 6x6, FC 6, FC 2 (8 of them);
     # three properties each, objective y0 - y1

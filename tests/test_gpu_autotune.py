@@ -10,7 +10,7 @@ from tests.test_gpu_parity import _case, _check_dual_eval, _oracle_fp32_spread, 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("name", ["base", "tiny_conv2", "tiny_conv3", "tiny_conv4"])
+@pytest.mark.parametrize("name", ["base", "tiny_conv2", "tiny_conv3", "tiny_conv4", "tiny_conv5"])
 def test_every_candidate_configuration_matches_oracle(name):
     P, inst, net, batch = _setup(name)
     rho = ldgen.random_duals(inst, seed=17, scale=0.3)

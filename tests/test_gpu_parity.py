@@ -13,7 +13,7 @@ from tests import _parity as PT
 
 pytestmark = pytest.mark.gpu
 
-SMALL = ["fc_tiny", "tiny_conv", "tiny_conv2", "tiny_conv3", "tiny_conv4"]
+SMALL = ["fc_tiny", "tiny_conv", "tiny_conv2", "tiny_conv3", "tiny_conv4", "tiny_conv5"]
 
 
 def _lib():
