@@ -35,7 +35,10 @@ Network Verification via Lagrangian Decomposition":
   duals, discarding on the threshold and the incumbent;
 * the P_k inner minimisation for sigmoid activations (App. E): the hull's tangent
   points, its envelopes and the minimum over the pieces (eq:siglinopt,
-  eq:with_sig_subp).
+  eq:with_sig_subp);
+* a rounding margin for dual values whose coefficients W_k^T rho_k are formed with
+  single-precision products (the paper computes exactly): Higham's dot-product bound
+  times the largest feasible |x| of each inner minimisation.
 
 Readings where the paper is silent (all listed in the design doc):
 * Adam uses beta1=0.9, beta2=0.999, eps=1e-8 with bias correction, as ascent.
@@ -57,7 +60,9 @@ per-neuron Planet LP optimum), and branching in tests/test_oracle_fsb_pins.py (b
 sensitivity of an independent WK bound, chord gap, brute-force candidate search; the
 s_FSB formula itself is "parity unpinned" beyond its support and sign), and the
 sigmoid inner minimisation in tests/test_oracle_sigmoid_pins.py (sampled convex
-hull, dense search, weak duality).  The final
+hull, dense search, weak duality), and the rounding margin in
+tests/test_oracle_margin_pins.py (dense conv matrices, a hand-worked net, and the
+errors of single-precision coefficients computed by torch, which it must cover).  The final
 bound after T Adam steps has no value printed in the paper: "parity unpinned"
 beyond those inequalities.
 """
@@ -251,6 +256,55 @@ def q_scale(net: List[OLayer], batch: OBatch, rho: List[torch.Tensor], ev: Dict)
     for k in range(1, n + 1):
         S = S + (duals[k - 1] * net[k - 1].bias_full()).abs().sum(dim=1)
     return S
+
+
+# ----------------------------------------------------------------------------
+# rounding margin of a dual value whose coefficients are formed with FP32
+# products (a reading: the paper's q is exact arithmetic)
+# ----------------------------------------------------------------------------
+U32 = 2.0 ** -24
+
+
+def abs_layer(L: OLayer) -> OLayer:
+    """The layer with every weight replaced by its magnitude (same shapes)."""
+    return OLayer(L.kind, L.W.abs(), L.b, L.in_shape, L.out_shape, L.stride, L.pad)
+
+
+def dot_terms(L: OLayer) -> int:
+    """Most terms of one coefficient's dot product (W^T r)_j: every output (fully
+    connected); for a conv, per output channel the taps that can reach one input
+    position, ceil(kh / stride) x ceil(kw / stride)."""
+    if L.kind == "linear":
+        return int(L.W.shape[0])
+    s = L.stride
+    return int(L.W.shape[0] * (-(-L.W.shape[2] // s)) * (-(-L.W.shape[3] // s)))
+
+
+def rounding_margin(net: List[OLayer], batch: OBatch, rho: List[torch.Tensor]) -> torch.Tensor:
+    """How far q computed from single-precision coefficients g_{k-1} = W_k^T rho_k
+    (k = 1..n, rho_n = -c) can sit above the exact q(rho), per subdomain.
+
+    A K-term dot product rounded in single precision errs by at most
+    gamma_K |W|^T |r|, gamma_K = K u / (1 - K u), u = 2^-24 (Higham's bound);
+    g_{k-1} enters one inner minimisation multiplied by x_{k-1}, and replacing the
+    coefficient moves that minimum by at most sum_j |error_j| max|x_{k-1,j}| over
+    the feasible set: max(|l0|, |u0|) on the input box (eq:box_bounds_sol), max(0, u)
+    after a ReLU (eq:min-pk).  Subnormals flushed to zero add at most 2 K 2^-126 per
+    coefficient."""
+    n = len(net)
+    duals = list(rho) + [-batch.c]
+    m = torch.zeros(batch.c.shape[0], dtype=DT)
+    for k in range(1, n + 1):
+        L = net[k - 1]
+        K = dot_terms(L)
+        gamma = K * U32 / (1.0 - K * U32)
+        t = abs_layer(L).transposed(duals[k - 1].abs())
+        if k == 1:
+            xm = torch.maximum(batch.l0.abs(), batch.u0.abs())
+        else:
+            xm = batch.u[k - 2].clamp(min=0.0)
+        m = m + ((gamma * t + 2.0 * K * 2.0 ** -126) * xm).sum(dim=1)
+    return m
 
 
 # ----------------------------------------------------------------------------

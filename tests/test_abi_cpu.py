@@ -98,6 +98,7 @@ def test_null_arguments_rejected(lib):
     assert lib.ld_state_create(None, 4, ctypes.byref(ctypes.c_void_p())) == -1
     assert lib.ld_prox_step(None, None, None, None, None) == -1
     assert lib.ld_prox_get_step(None, ctypes.byref(ctypes.c_int())) == -1
+    assert lib.ld_rounding_margin(None, None, None, None, None) == -1
     assert "NULL" in lib.ld_last_error().decode()
 
 
