@@ -209,6 +209,30 @@ int ld_dual_eval_noalloc(const ld_net* net, const ld_batch* batch, const float* 
 int ld_dual_eval_f64(const ld_net* net, const ld_batch* batch, const double* const* rho, double* q,
                      double* const* supergrad, float tie_tau, hipStream_t stream);
 
+/* Rounding margin of the FP32-operand dual value (ld_dual_eval with LD_FP32, and
+ * ld_final_bound): margin[b] (device double [B]) bounds how far the value it
+ * returns can sit above the exact q(rho) at the same FP32 duals, so
+ * q - margin is a lower bound of q(rho) and, by weak duality (Sec. 3.1), of the
+ * subdomain's minimum even with the products' rounding counted.  The paper works
+ * in exact arithmetic; every coefficient g_{k-1} = W_k^T rho_k (and the constant
+ * -W_n^T c) is a dot product of K terms rounded in single precision, which errs by
+ * at most gamma_K |W_k|^T |rho_k| with gamma_K = K u / (1 - K u), u = 2^-24
+ * (Higham's bound, any summation order, with or without fused multiply-adds); it
+ * enters one inner minimisation (eq:box_bounds_sol, eq:min-pk) multiplied by
+ * x_{k-1}, whose feasible |x| is at most max(|l0|, |u0|) on the input box and
+ * max(0, u) after a ReLU.  So
+ *   margin[b] = sum_k sum_j (gamma_K (|W_k|^T |rho_k|)_j + 2 K 2^-126) max|x_{k-1,j}|
+ * with K the layer's outputs (fully connected) or, for a conv, Co ceil(kh/stride)
+ * ceil(kw/stride) (the taps that reach one input position), evaluated in
+ * FP64 from the FP64 copies of the weights.  The rest of q (inner minimisation
+ * values, bias terms, c . b_n) is formed from FP32 values in FP64 and its rounding,
+ * below 2^-40 of q's terms, is not counted; the margin's own FP64 sums are
+ * covered by widening it by 2^-30.  rho: host array of n-1 device pointers
+ * [B, n_k].  With B = 0 it does nothing (margin may be NULL).  Uses the net's
+ * workspace, like ld_dual_eval. */
+int ld_rounding_margin(const ld_net* net, const ld_batch* batch, const float* const* rho, double* margin,
+                       hipStream_t stream);
+
 /* ------------------------------------------------------------------------- */
 /* ascent (Algorithm 1 with Adam)                                             */
 /* ------------------------------------------------------------------------- */

@@ -6,7 +6,7 @@ Python binding of the C ABI in include/ld.h: ``Net``, ``Batch``, ``State``,
 torch.autograd.Function.
 """
 from .binding import (Batch, LDDual, LDError, Net, State, TAU_DEFAULT, dual_eval, dual_eval_f64,  # noqa: F401
-                      dual_eval_noalloc,
+                      dual_eval_noalloc, rounding_margin,
                       final_bound, bab, branch_children, fsb_branch, init_duals, intermediate_bounds, ld_dual,
                       load_library, profile_iteration, prox_profile_iteration, prox_step, sigmoid_hull,
                       sigmoid_inner_min, set_validation, step, autotune, tuning_info, tile_candidates,

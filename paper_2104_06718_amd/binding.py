@@ -29,7 +29,7 @@ _ENGINE = {"auto": LD_ENGINE_AUTO, "resident": LD_ENGINE_RESIDENT, "layerwise": 
 
 EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num_layers",
             "ld_set_validation", "ld_state_create", "ld_state_destroy", "ld_state_set_rho",
-            "ld_state_get_rho", "ld_state_get_rho_f64", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval", "ld_dual_eval_noalloc", "ld_dual_eval_f64",
+            "ld_state_get_rho", "ld_state_get_rho_f64", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval", "ld_dual_eval_noalloc", "ld_dual_eval_f64", "ld_rounding_margin",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
             "ld_intermediate_bounds", "ld_fsb_branch", "ld_bab", "ld_branch_children", "ld_sigmoid_hull", "ld_sigmoid_inner_min", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
@@ -127,6 +127,7 @@ def load_library(path: Optional[str] = None):
     lib.ld_dual_eval.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
     lib.ld_dual_eval_f64.argtypes = [V, P(ld_batch), P(V), V, P(V), ctypes.c_float, V]
     lib.ld_dual_eval_noalloc.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
+    lib.ld_rounding_margin.argtypes = [V, P(ld_batch), P(V), V, V]
     lib.ld_step.argtypes = [V, P(ld_batch), V, P(ld_opts), V]
     lib.ld_autotune.argtypes = [V, P(ld_batch), P(ld_opts), V]
     lib.ld_tuned_config.argtypes = [V, I, I, I, I, P(ld_tile), P(ctypes.c_double)]
@@ -344,6 +345,16 @@ def dual_eval_f64(net: Net, batch: Batch, rho: List[torch.Tensor], supergrad=Tru
     _check(net.lib.ld_dual_eval_f64(net.handle, ctypes.byref(batch.struct), _ptrs(list(rho)),
                                     ctypes.c_void_p(q.data_ptr()), sp, ctypes.c_float(tau), _stream(stream)))
     return q, s
+
+
+def rounding_margin(net: Net, batch: Batch, rho: List[torch.Tensor], stream=None) -> torch.Tensor:
+    """Per-subdomain bound (float64 [B]) on how far the FP32-operand dual value at
+    rho can exceed the exact q(rho) (ld_rounding_margin)."""
+    m = torch.empty(batch.B, device="cuda", dtype=torch.float64)
+    rho = [_dev_f32(r, "rho") for r in rho]
+    _check(net.lib.ld_rounding_margin(net.handle, ctypes.byref(batch.struct), _ptrs(rho),
+                                      ctypes.c_void_p(m.data_ptr()), _stream(stream)))
+    return m
 
 
 def step(net: Net, batch: Batch, state: State, iters: int, total_iters: Optional[int] = None, lr0=1e-2,

@@ -1958,6 +1958,46 @@ int ld_dual_eval_f64(const ld_net* net, const ld_batch* bt, const double* const*
   return f64_dual_eval_impl(net, bt, rho, mnet->ws64, q, supergrad, nullptr, tie_tau, s);
 }
 
+int ld_rounding_margin(const ld_net* net, const ld_batch* bt, const float* const* rho, double* margin,
+                       hipStream_t s) {
+  g_err.clear();
+  LD_TRY(check_batch(net, bt));
+  if (!rho) return fail(LD_E_ARG, "rho is NULL");
+  if (bt->B == 0) return LD_OK;
+  if (!margin) return fail(LD_E_ARG, "margin is NULL");
+  for (int k = 0; k < net->n - 1; ++k)
+    if (!rho[k]) return fail(LD_E_ARG, "rho[k] is NULL");
+  ld_net* mnet = const_cast<ld_net*>(net);
+  LD_TRY(ws_alloc(net, mnet->ws, bt->B));
+  LD_TRY(validate_values(net, bt, mnet->ws, s));
+  const int n = net->n, B = bt->B;
+  const double u = std::ldexp(1.0, -24);
+  std::vector<const double*> arrs;
+  std::vector<int> sz;
+  for (int k = 1; k <= n; ++k) {
+    const Layer& L = net->L[k - 1];
+    const F64Layer& F = L.f64;
+    // most terms of one coefficient's dot product: the layer's outputs (fully
+    // connected); for a conv, per output channel the taps that reach one input
+    // position, ceil(kh / stride) x ceil(kw / stride)
+    const double K = F.kind == 0 ? (double)F.n_out
+                                 : (double)F.Co * ((F.kh + F.stride - 1) / F.stride) * ((F.kw + F.stride - 1) / F.stride);
+    if (K * u >= 0.5) return fail(LD_E_UNSUPPORTED, "dot products too long for the rounding bound");
+    // (the margin's own FP64 sums of non-negative terms err by far less than 2^-30)
+    const double gamma = K * u / (1.0 - K * u) * (1.0 + std::ldexp(1.0, -30));
+    const double tiny = 2.0 * K * std::ldexp(1.0, -126);  // flushed subnormal products and sums
+    const float* r = k < n ? rho[k - 1] : bt->c;
+    const float* lo = k == 1 ? bt->l0 : bt->l[k - 2];
+    const float* hi = k == 1 ? bt->u0 : bt->u[k - 2];
+    double* out = mnet->ws.val[k - 1];
+    LD_HIP(launch_f64_abs_margin(F, B, r, width(net, k - 1), lo, hi, k == 1 ? 1 : 0, gamma, tiny, out, s));
+    arrs.push_back(out);
+    sz.push_back(width(net, k - 1));
+  }
+  LD_HIP(launch_reduce_q(B, (int)arrs.size(), arrs.data(), sz.data(), nullptr, margin, s));
+  return LD_OK;
+}
+
 static int check_step_args(const ld_net* net, const ld_batch* bt, const ld_state* st, const ld_opts* o) {
   LD_TRY(check_batch(net, bt));
   if (!st || !o) return fail(LD_E_ARG, "state/opts is NULL");

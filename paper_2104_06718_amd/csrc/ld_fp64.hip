@@ -125,6 +125,48 @@ __global__ void __launch_bounds__(256) f64_transposed_kernel(F64Layer L, const d
   f64_epilogue(e, b, j, idx, g);
 }
 
+// Rounding margin of one coefficient map: for input j of the layer,
+// out[b][j] = (gamma * sum_i |W[i][j]| |r[b][i]| + tiny) * xmax[b][j], with xmax the
+// largest |x_j| on the feasible set of the minimisation the coefficient enters:
+// max(|lo|, |hi|) for the input box (box = 1), max(0, hi) after a ReLU (box = 0).
+// The same tap walk as f64_transposed_kernel, on absolute values, in FP64.
+// Grid (ceil(n/256), B).
+__global__ void __launch_bounds__(256) f64_abs_margin_kernel(F64Layer L, const float* __restrict__ r, int n,
+                                                             const float* __restrict__ lo,
+                                                             const float* __restrict__ hi, int box, double gamma,
+                                                             double tiny, double* __restrict__ out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int b = blockIdx.y;
+  if (j >= n) return;
+  const size_t idx = (size_t)b * n + j;
+  const float* rb = r + (size_t)b * L.n_out;
+  double t = 0.0;
+  if (L.kind == 0) {
+    for (int i = 0; i < L.n_out; ++i) t += fabs(L.W[(size_t)i * L.n_in + j]) * fabs((double)rb[i]);
+  } else {
+    const int HW = L.H * L.W_;
+    const int ci = j / HW, rem = j - ci * HW;
+    const int y = rem / L.W_, x = rem - (rem / L.W_) * L.W_;
+    const int ky0 = (y + L.pad) % L.stride, kx0 = (x + L.pad) % L.stride;
+    for (int co = 0; co < L.Co; ++co) {
+      const double* wc = L.W + ((size_t)co * L.Ci + ci) * L.kh * L.kw;
+      const float* rc = rb + (size_t)co * L.Ho * L.Wo;
+      for (int ky = ky0; ky < L.kh; ky += L.stride) {
+        const int oy = (y + L.pad - ky) / L.stride;
+        if (y + L.pad - ky < 0 || oy >= L.Ho) continue;
+        for (int kx = kx0; kx < L.kw; kx += L.stride) {
+          const int ox = (x + L.pad - kx) / L.stride;
+          if (x + L.pad - kx < 0 || ox >= L.Wo) continue;
+          t += fabs(wc[ky * L.kw + kx]) * fabs((double)rc[oy * L.Wo + ox]);
+        }
+      }
+    }
+  }
+  const double l = (double)lo[idx], h = (double)hi[idx];
+  const double xm = box ? fmax(fabs(l), fabs(h)) : fmax(0.0, h);
+  out[idx] = (gamma * t + tiny) * xm;
+}
+
 // Forward product of a conv layer: y[b][i] = sum W[co][ci][ky][kx] x[b][ci][iy][ix].
 // Grid (ceil(n_out/256), B).
 __global__ void __launch_bounds__(256) f64_forward_conv_kernel(F64Layer L, const double* __restrict__ x, F64Epi e) {
@@ -219,6 +261,16 @@ hipError_t launch_f64_transposed(const F64Layer& L, int B, const double* r, cons
   if (gin == nullptr && L.kind != 0 && (L.stride < 1 || L.pad < 0)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(f64_transposed_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)B), dim3(256), 0, s, L, r,
                      gin, n, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_f64_abs_margin(const F64Layer& L, int B, const float* r, int n, const float* lo, const float* hi,
+                                 int box, double gamma, double tiny, double* out, hipStream_t s) {
+  if (B == 0 || n == 0) return hipSuccess;
+  if (r == nullptr || lo == nullptr || hi == nullptr || out == nullptr || n != L.n_in) return hipErrorInvalidValue;
+  if (L.kind != 0 && (L.stride < 1 || L.pad < 0)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(f64_abs_margin_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)B), dim3(256), 0, s, L, r, n,
+                     lo, hi, box, gamma, tiny, out);
   return hipGetLastError();
 }
 

@@ -349,6 +349,9 @@ struct F64Epi {
 hipError_t launch_f64_transposed(const F64Layer& L, int B, const double* r, const double* gin, int n,
                                  const F64Epi& e, hipStream_t s);
 hipError_t launch_f64_forward(const F64Layer& L, int B, const double* x, const F64Epi& e, hipStream_t s);
+// out[b][j] = (gamma * (|W|^T |r|)[b][j] + tiny) * xmax[b][j]; xmax = max(|lo|, |hi|) (box) or max(0, hi)
+hipError_t launch_f64_abs_margin(const F64Layer& L, int B, const float* r, int n, const float* lo, const float* hi,
+                                 int box, double gamma, double tiny, double* out, hipStream_t s);
 hipError_t launch_f64_widen(size_t n, const float* src, double* dst, hipStream_t s);
 hipError_t launch_f64_narrow(size_t n, const double* src, float* dst, hipStream_t s);
 hipError_t launch_f64_copy(size_t n, const double* src, double* dst, hipStream_t s);

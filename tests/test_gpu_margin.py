@@ -1,0 +1,72 @@
+"""The rounding margin of the FP32-operand dual value (ld_rounding_margin) through
+the C ABI: the oracle's (rounding_margin, pinned in
+tests/test_oracle_margin_pins.py) widened by the library's 2^-30, to 1e-12 relative, and covering the GPU's own
+error: at fixed duals and after an ascent, |q_gpu - q_exact| <= margin for every
+subdomain, so q_gpu - margin is a lower bound of the exact dual value."""
+import pytest
+import torch
+
+import ldgen
+from oracle import ld_oracle as O
+from tests.test_gpu_parity import SMALL, _case, _setup, _to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(P, net, batch, onet, ob, rho32, q_gpu):
+    m = P.rounding_margin(net, batch, _to_gpu(rho32)).cpu()
+    orho = [torch.from_numpy(r).double() for r in rho32]
+    mo = O.rounding_margin(onet, ob, orho)
+    # the library widens its margin by 2^-30 against the rounding of its own FP64 sums
+    lo, hi = mo * (1.0 + 2.0 ** -30 - 1e-12), mo * (1.0 + 2.0 ** -30 + 1e-12)
+    assert bool(((m >= lo) & (m <= hi)).all()), f"margin mismatch {((m - mo) / mo).abs().max()}"
+    q = O.dual_eval(onet, ob, orho, need_supergrad=False)["q"]
+    err = (q_gpu.cpu() - q).abs()
+    print(f"  margin / |q| up to {(m / q.abs().clamp(min=1e-30)).max().item():.2e}; "
+          f"error / margin up to {(err / m).max().item():.3f}", flush=True)
+    assert bool((err <= m).all()), f"error {err.max().item():.3e} above margin"
+
+
+@pytest.mark.parametrize("name", SMALL + ["base"])
+def test_margin_at_fixed_duals(name):
+    P, inst, net, batch = _setup(name)
+    onet = O.net_from_specs(inst.layers)
+    ob = O.batch_from_instance(inst)
+    for seed, scale in ((21, 0.3), (22, 30.0)):
+        _case(f"rounding margin {name} B={inst.B} seed={seed} scale={scale}")
+        rho = ldgen.random_duals(inst, seed=seed, scale=scale)
+        q, _ = P.dual_eval(net, batch, _to_gpu(rho), supergrad=False, precision="fp32")
+        _check(P, net, batch, onet, ob, rho, q)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("name", ["tiny_conv", "base"])
+def test_margin_after_ascent(name, prec):
+    _case(f"rounding margin after 100 steps {name} {prec}")
+    P, inst, net, batch = _setup(name)
+    st = P.State(net, inst.B)
+    P.step(net, batch, st, iters=100, total_iters=100, precision=prec)
+    fb = P.final_bound(net, batch, st)
+    rho = [r.cpu().numpy() for r in st.get_rho()]
+    _check(P, net, batch, O.net_from_specs(inst.layers), O.batch_from_instance(inst), rho, fb["q_final"])
+
+
+def test_margin_wide_sample():
+    idx = list(range(0, 512, 8))
+    _case(f"rounding margin wide net, {len(idx)} of 512 subdomains")
+    P, inst, net, batch = _setup("wide")
+    sub = inst.subset(idx)
+    sb = P.Batch.from_instance(sub)
+    rho = ldgen.random_duals(sub, seed=23, scale=0.3)
+    q, _ = P.dual_eval(net, sb, _to_gpu(rho), supergrad=False, precision="fp32")
+    _check(P, net, sb, O.net_from_specs(sub.layers), O.batch_from_instance(sub), rho, q)
+
+
+def test_margin_empty_batch_and_null_arguments():
+    _case("rounding margin: B = 0 and NULL arguments")
+    P, inst, net, batch = _setup("tiny_conv")
+    empty = P.Batch.from_instance(inst.subset([]))
+    m = P.rounding_margin(net, empty, [torch.zeros((0, a.shape[1]), device="cuda") for a in inst.l])
+    assert m.shape == (0,)
+    rc = net.lib.ld_rounding_margin(net.handle, None, None, None, None)
+    assert rc != 0
