@@ -862,6 +862,10 @@ def main():
     st = P.State(net, B)
     res32 = run_form(P, net, batch, st, T, "fp32", a.steps, a.warmup, a.engine)
     b32 = res32["fb"]["bound"].clone()
+    # rounding margin of the FP32-operand value at rho^T (after the timed runs)
+    m32 = P.rounding_margin(net, batch, st.get_rho())
+    q32 = res32["fb"]["q_final"]
+    margin = {"max": m32.max().item(), "max_over_abs_q": (m32 / q32.abs().clamp(min=1e-30)).max().item()}
 
     # BF16 form: iterations needed to reach the FP32 form's bound (mean gap <= 1e-3):
     # bracketed upward from T in steps of 50, then bisected down to 5 iterations
@@ -958,7 +962,7 @@ def main():
         "config": {"workload": f"{a.config} conv net 3x32x32, B={B}, T={T} (bf16: T={T16}), 1 property, "
                                f"5% random ReLU splits per subdomain", "B": B, "iters": T, "bf16_iters": T16},
         "fp32": {"value": B / (res32["ms_per_step"] / 1000.0), "ms_per_step": res32["ms_per_step"],
-                 "mean_bound": b32.mean().item()},
+                 "mean_bound": b32.mean().item(), "rounding_margin_at_rhoT": margin},
         "bf16": {"value": value, "ms_per_step": res16["ms_per_step"], "mean_bound": b16.mean().item(),
                  "equal_bound": equal,
                  "equal_bound_criterion": "mean over subdomains of (fp32 bound - bf16 bound) <= 1e-3",
