@@ -157,6 +157,20 @@ int ld_state_get_step(const ld_state* st, hipStream_t stream, int* t);
  * Buffers, tuned tiles and the captured graph are kept, so a bounding run can be
  * repeated on new subdomain data of the same shape without allocation. */
 int ld_state_reset(ld_state* st, hipStream_t stream);
+/* Keep the ascent's best dual value (optional).  Every dual value q(rho^t) is a
+ * lower bound of the subdomain's minimum (weak duality, Sec. 3.1); with `on`, each
+ * later step t of ld_step (FP32 or BF16, layer-wise engine: LD_ENGINE_AUTO takes
+ * it, LD_FP64 and LD_ENGINE_RESIDENT return LD_E_UNSUPPORTED) also evaluates
+ * q(rho^{t-1}) at the duals it starts from, as ld_dual_eval does with FP32
+ * operands (in buffers of its own, beside the step's transposed products; the
+ * ascent itself is unchanged), and keeps per subdomain the largest value and
+ * that t.  Turning it on starts an empty record (value -inf, step 0), and so do
+ * ld_state_reset and ld_state_set_rho while it is on; `on` = 0 stops it and keeps
+ * the record.  Each tracked step costs one more FP32 dual evaluation. */
+int ld_state_set_tracking(ld_state* st, int on, hipStream_t stream);
+/* The record of ld_state_set_tracking: best_q (device double [B], may be NULL)
+ * and best_t (device int [B], may be NULL).  LD_E_STATE if tracking was never on. */
+int ld_state_get_best(const ld_state* st, double* best_q, int* best_t, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* dual initialisation (Prop. 2)                                              */

@@ -29,7 +29,8 @@ _ENGINE = {"auto": LD_ENGINE_AUTO, "resident": LD_ENGINE_RESIDENT, "layerwise": 
 
 EXPORTED = ["ld_create_net", "ld_destroy_net", "ld_net_layer_width", "ld_net_num_layers",
             "ld_set_validation", "ld_state_create", "ld_state_destroy", "ld_state_set_rho",
-            "ld_state_get_rho", "ld_state_get_rho_f64", "ld_state_get_step", "ld_state_reset", "ld_init_duals", "ld_dual_eval", "ld_dual_eval_noalloc", "ld_dual_eval_f64", "ld_rounding_margin",
+            "ld_state_get_rho", "ld_state_get_rho_f64", "ld_state_get_step", "ld_state_reset",
+            "ld_state_set_tracking", "ld_state_get_best", "ld_init_duals", "ld_dual_eval", "ld_dual_eval_noalloc", "ld_dual_eval_f64", "ld_rounding_margin",
             "ld_step", "ld_autotune", "ld_tuned_config", "ld_tuned_engine", "ld_tile_candidates",
             "ld_set_tuned_config", "ld_profile_iteration",
             "ld_intermediate_bounds", "ld_fsb_branch", "ld_bab", "ld_branch_children", "ld_sigmoid_hull", "ld_sigmoid_inner_min", "ld_prox_step", "ld_prox_get_step", "ld_prox_profile_iteration", "ld_final_bound", "ld_last_error"]
@@ -122,6 +123,8 @@ def load_library(path: Optional[str] = None):
     lib.ld_state_get_rho_f64.argtypes = [V, P(V), V]
     lib.ld_state_get_step.argtypes = [V, V, P(I)]
     lib.ld_state_reset.argtypes = [V, V]
+    lib.ld_state_set_tracking.argtypes = [V, I, V]
+    lib.ld_state_get_best.argtypes = [V, V, V, V]
     lib.ld_profile_iteration.argtypes = [V, P(ld_batch), V, P(ld_opts), I, P(ctypes.c_double), P(I), I, P(I), V]
     lib.ld_init_duals.argtypes = [V, P(ld_batch), I, I, P(V), V]
     lib.ld_dual_eval.argtypes = [V, P(ld_batch), P(V), V, P(V), I, ctypes.c_float, V]
@@ -281,6 +284,18 @@ class State:
 
     def reset(self, stream=None):
         _check(self.lib.ld_state_reset(self.handle, _stream(stream)))
+
+    def set_tracking(self, on: bool = True, stream=None):
+        """Keep the ascent's best dual value from now on (ld_state_set_tracking)."""
+        _check(self.lib.ld_state_set_tracking(self.handle, int(bool(on)), _stream(stream)))
+
+    def best(self, stream=None):
+        """(best_q float64 [B], best_t int32 [B]) of the tracked steps (ld_state_get_best)."""
+        q = torch.empty(self.B, device="cuda", dtype=torch.float64)
+        t = torch.empty(self.B, device="cuda", dtype=torch.int32)
+        _check(self.lib.ld_state_get_best(self.handle, ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                          _stream(stream)))
+        return q, t
 
     def step_count(self, stream=None) -> int:
         t = ctypes.c_int()

@@ -179,6 +179,14 @@ struct ld_state {
   };
   Graph graphs[2];
   int t_host = 0;       // Adam steps enqueued so far (mirrors *t_dev)
+  // the ascent's best dual value (ld_state_set_tracking): per subdomain the largest
+  // q(rho^{t-1}) of the tracked steps t and that t (device [B])
+  bool track = false;
+  void* track_base = nullptr;
+  double* best_q = nullptr;
+  int* best_t = nullptr;
+  int* track_step = nullptr;  // the state's step count, advanced by each tracked step
+  Workspace tws;              // the tracked values' own evaluation buffers
   // recorded after the last work enqueued on the state's memory and graphs; waited
   // on before a graph is replaced or the state is freed (a graph exec or a
   // buffer must not be released while kernels that use it are in flight)
@@ -1790,6 +1798,8 @@ void ld_state_destroy(ld_state* st) {
   if (st->cap) (void)hipStreamDestroy(st->cap);
   if (st->done) (void)hipEventDestroy(st->done);
   if (st->ws.base) (void)hipFree(st->ws.base);
+  if (st->track_base) (void)hipFree(st->track_base);
+  if (st->tws.base) (void)hipFree(st->tws.base);
   if (st->px.base) (void)hipFree(st->px.base);
   if (st->f64.base) (void)hipFree(st->f64.base);
   if (st->f64.ws.base) (void)hipFree(st->f64.ws.base);
@@ -1811,6 +1821,13 @@ int ld_state_set_rho(ld_state* st, const float* const* rho, hipStream_t s) {
   LD_HIP(hipMemsetAsync(st->t_dev, 0, 4, s));
   st->t_host = 0;
   st->initialized = false;  // q(rho^0) is computed by the next ld_step (init = LD_INIT_GIVEN)
+  if (st->track) {  // a new ascent starts a new record
+    if (st->B > 0) {
+      LD_HIP(launch_fill_f64(st->best_q, (size_t)st->B, -INFINITY, s));
+      LD_HIP(launch_fill_i32(st->best_t, (size_t)st->B, 0, s));
+    }
+    LD_HIP(launch_fill_i32(st->track_step, 1, 0, s));
+  }
   st->f64.active = false;
   st->px.ready = false;     // the proximal solver restarts its primal iterates from these duals
   st->px.t = 0;
@@ -2069,12 +2086,34 @@ static int build_graph(const ld_net* net, const ld_batch* bt, ld_state* st, cons
     release();
     return fail(LD_E_DEVICE, std::string(what) + hipGetErrorString(e));
   };
+  // phase A: the transposed products (n-1 jobs) and, when the state keeps its best
+  // value, one more job: q at the duals the step starts from, with FP32 operands in
+  // a workspace of its own, and the record; phase B: forward products and Adam
+  const int jobs_a = st->track ? n : n - 1;
+  auto jobs_in = [&](int phase) { return phase == 0 ? jobs_a : n - 1; };
   for (int phase = 0; phase < 2; ++phase)
-    for (int k = 1; k <= n - 1; ++k) {
-      const Layer& L = net->L[k - 1];
+    for (int k = 1; k <= jobs_in(phase); ++k) {
+      const Layer& L = net->L[std::min(k, n - 1) - 1];
       hipError_t e = hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return failed("graph capture: ", e);
-      if (phase == 0) {
+      if (phase == 0 && k == n) {
+        // as ld_dual_eval with FP32 operands, with the state's constants (-W_n^T c and
+        // c . b_n, formed when the state was initialised)
+        e = launch_inc_i32(st->track_step, st->cap);
+        Workspace& tw = st->tws;
+        tw.gconst = st->ws.gconst;
+        if (e == hipSuccess &&
+            phase_a(net, bt, rho.data(), tw, 0, o->tie_tau, 1, nullptr, nullptr, nullptr, st->cap) != LD_OK)
+          e = hipErrorUnknown;
+        std::vector<const double*> arrs;
+        std::vector<int> sz;
+        for (int j = 0; j <= n - 1; ++j) {
+          arrs.push_back(tw.val[j]);
+          sz.push_back(width(net, j));
+        }
+        if (e == hipSuccess) e = launch_reduce_q(B, (int)arrs.size(), arrs.data(), sz.data(), st->ws.cb, tw.qtmp, st->cap);
+        if (e == hipSuccess) e = launch_best_update(B, tw.qtmp, st->best_q, st->best_t, st->track_step, st->cap);
+      } else if (phase == 0) {
         const EpiArgs ea = epi_phase_a(net, bt, rho.data(), st->ws, mma, o->tie_tau, 0, st->t_dev, st->adam, o, k);
         e = run_job(L.tr, B, rho[k - 1], 0, tr_mode(mma, k), ea, pick_tile(net, k - 1, 1, B, mma), st->ws, k - 1,
                     st->cap);
@@ -2122,15 +2161,16 @@ static int build_graph(const ld_net* net, const ld_batch* bt, ld_state* st, cons
   for (int it = 0; it < chunk && e == hipSuccess; ++it)
     for (int phase = 0; phase < 2 && e == hipSuccess; ++phase) {
       last.clear();
-      for (int j = 0; j < n - 1 && e == hipSuccess; ++j) {
+      const int base = phase == 0 ? 0 : jobs_a;
+      for (int j = 0; j < jobs_in(phase) && e == hipSuccess; ++j) {
         std::vector<hipGraphNode_t> deps = before;
-        for (const hipKernelNodeParams& kp : chain[phase * (n - 1) + j]) {
+        for (const hipKernelNodeParams& kp : chain[base + j]) {
           hipGraphNode_t node = nullptr;
           e = hipGraphAddKernelNode(&node, g, deps.empty() ? nullptr : deps.data(), deps.size(), &kp);
           if (e != hipSuccess) break;
           deps.assign(1, node);
         }
-        if (e == hipSuccess && !chain[phase * (n - 1) + j].empty()) last.push_back(deps[0]);
+        if (e == hipSuccess && !chain[base + j].empty()) last.push_back(deps[0]);
       }
       before = last;
     }
@@ -2165,7 +2205,8 @@ static int step_impl(const ld_net* net, const ld_batch* bt, ld_state* st, const 
   const int full = o->iters / kGraphIters, rest = o->iters % kGraphIters;
   auto exec_for = [&](int slot, int chunk, hipGraphExec_t* x) -> int {
     ld_state::Graph& G = st->graphs[slot];
-    const std::vector<double> key = graph_key(bt, o, net->n, chunk, net->tune_gen);
+    std::vector<double> key = graph_key(bt, o, net->n, chunk, net->tune_gen);
+    key.push_back(st->track ? 1.0 : 0.0);
     if (!G.exec || key != G.key) {
       destroy_graph(st, slot);
       hipGraph_t g = nullptr;
@@ -3258,6 +3299,8 @@ int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* 
   LD_TRY(check_step_args(net, bt, st, o));
   if (g_row_div > 1 && (o->precision == LD_FP64 || o->engine == LD_ENGINE_RESIDENT))
     return fail(LD_E_UNSUPPORTED, "shared bound rows need the FP32/BF16 layer-wise engine");
+  if (st->track && (o->precision == LD_FP64 || o->engine == LD_ENGINE_RESIDENT))
+    return fail(LD_E_UNSUPPORTED, "keeping the best value needs the FP32/BF16 layer-wise engine");
   LD_TRY(validate_values(net, bt, st->ws, s));
   if (o->precision == LD_FP64) {
     LD_TRY(f64_ensure_initialised(net, bt, st, o, s));
@@ -3271,7 +3314,7 @@ int ld_step(const ld_net* net, const ld_batch* bt, ld_state* st, const ld_opts* 
   const int mma = o->precision == LD_BF16 ? 1 : 0;
   if (eo.engine == LD_ENGINE_AUTO && bt->B > 0) {
     if (tuned_engine(net, bt->B, mma) < 0) LD_TRY(autotune_impl(net, bt, o, s));
-    eo.engine = tuned_engine(net, bt->B, mma);
+    eo.engine = st->track ? LD_ENGINE_LAYERWISE : tuned_engine(net, bt->B, mma);
   }
   LD_TRY(ensure_initialised(net, bt, st, &eo, s));
   const int rc = step_impl(net, bt, st, &eo, s);
@@ -3353,6 +3396,43 @@ int ld_tuned_engine(const ld_net* net, int B, int precision, int* engine, int* c
   return LD_OK;
 }
 
+int ld_state_set_tracking(ld_state* st, int on, hipStream_t s) {
+  g_err.clear();
+  if (!st) return fail(LD_E_ARG, "state is NULL");
+  if (on && !st->track_base) {
+    const size_t qb = round_up((size_t)std::max(st->B, 1) * 8, 256);
+    const size_t tb = round_up((size_t)std::max(st->B, 1) * 4, 256);
+    if (hipMalloc(&st->track_base, qb + tb + 256) != hipSuccess) {
+      st->track_base = nullptr;
+      return fail(LD_E_NOMEM, "tracking hipMalloc failed");
+    }
+    st->best_q = (double*)st->track_base;
+    st->best_t = (int*)((char*)st->track_base + qb);
+    st->track_step = (int*)((char*)st->track_base + qb + tb);
+  }
+  if (on) {
+    LD_TRY(ws_alloc(st->net, st->tws, st->B));
+    if (st->B > 0) {
+      LD_HIP(launch_fill_f64(st->best_q, (size_t)st->B, -INFINITY, s));
+      LD_HIP(launch_fill_i32(st->best_t, (size_t)st->B, 0, s));
+    }
+    LD_HIP(launch_fill_i32(st->track_step, 1, st->t_host, s));
+  }
+  st->track = on != 0;
+  LD_HIP(hipEventRecord(st->done, s));
+  return LD_OK;
+}
+
+int ld_state_get_best(const ld_state* st, double* best_q, int* best_t, hipStream_t s) {
+  g_err.clear();
+  if (!st) return fail(LD_E_ARG, "state is NULL");
+  if (!st->track_base) return fail(LD_E_STATE, "the state never kept its best value (ld_state_set_tracking)");
+  if (st->B == 0) return LD_OK;
+  if (best_q) LD_HIP(hipMemcpyAsync(best_q, st->best_q, (size_t)st->B * 8, hipMemcpyDeviceToDevice, s));
+  if (best_t) LD_HIP(hipMemcpyAsync(best_t, st->best_t, (size_t)st->B * 4, hipMemcpyDeviceToDevice, s));
+  return LD_OK;
+}
+
 int ld_state_reset(ld_state* st, hipStream_t s) {
   g_err.clear();
   if (!st) return fail(LD_E_ARG, "state is NULL");
@@ -3360,6 +3440,13 @@ int ld_state_reset(ld_state* st, hipStream_t s) {
   st->t_host = 0;
   st->initialized = false;
   st->f64.active = false;
+  if (st->track) {  // a new ascent starts a new record
+    if (st->B > 0) {
+      LD_HIP(launch_fill_f64(st->best_q, (size_t)st->B, -INFINITY, s));
+      LD_HIP(launch_fill_i32(st->best_t, (size_t)st->B, 0, s));
+    }
+    LD_HIP(launch_fill_i32(st->track_step, 1, 0, s));
+  }
   st->px.ready = false;
   st->px.t = 0;
   LD_HIP(hipEventRecord(st->done, s));

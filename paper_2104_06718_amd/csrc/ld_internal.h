@@ -211,8 +211,13 @@ hipError_t launch_cdot(int B, int n, const float* c, const float* y, const float
 hipError_t launch_validate(int B, int n, const float* lo, const float* hi, int* bad, hipStream_t s);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int* p, size_t n, int v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
 hipError_t launch_copy_f32(float* dst, const float* src, size_t n, hipStream_t s);
 hipError_t launch_max_f64(int B, const double* a, const double* b, double* out, hipStream_t s);
+// best_q[b], best_t[b] <- q[b], *step where q[b] > best_q[b]
+hipError_t launch_best_update(int B, const double* q, double* best_q, int* best_t, const int* step, hipStream_t s);
+// *c += 1 (one thread)
+hipError_t launch_inc_i32(int* c, hipStream_t s);
 
 // proximal solver (ld_prox.hip).  One block of the block-coordinate Frank-Wolfe
 // sweep, layer k: B part over layer k (nB = n_k, 0 for k = 0), A part over layer

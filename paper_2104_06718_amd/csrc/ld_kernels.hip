@@ -1376,12 +1376,30 @@ __global__ void validate_kernel(size_t total, const float* __restrict__ lo, cons
 __global__ void fill_f32_kernel(float* p, size_t n, float v) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
+__global__ void fill_f64_kernel(double* p, size_t n, double v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
 __global__ void fill_i32_kernel(int* p, size_t n, int v) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 __global__ void copy_f32_kernel(float* __restrict__ d, const float* __restrict__ s, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) d[i] = s[i];
 }
+// The largest dual value of the tracked steps and its step: q (the value at the
+// duals a step starts from) against best_q; *step holds the step's number.
+__global__ void best_update_kernel(int B, const double* __restrict__ q, double* __restrict__ best_q,
+                                   int* __restrict__ best_t, const int* __restrict__ step) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  const double v = q[b];
+  if (v > best_q[b]) {
+    best_q[b] = v;
+    best_t[b] = *step;
+  }
+}
+
+__global__ void inc_i32_kernel(int* c) { *c += 1; }
+
 __global__ void max_f64_kernel(int B, const double* a, const double* b, double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < B) out[i] = a[i] > b[i] ? a[i] : b[i];
@@ -1440,6 +1458,11 @@ hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s) {
   hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int* p, size_t n, int v, hipStream_t s) {
   hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
@@ -1448,6 +1471,17 @@ hipError_t launch_copy_f32(float* dst, const float* src, size_t n, hipStream_t s
   hipLaunchKernelGGL(copy_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n);
   return hipGetLastError();
 }
+hipError_t launch_best_update(int B, const double* q, double* best_q, int* best_t, const int* step, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(best_update_kernel, dim3((B + 255) / 256), dim3(256), 0, s, B, q, best_q, best_t, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_inc_i32(int* c, hipStream_t s) {
+  hipLaunchKernelGGL(inc_i32_kernel, dim3(1), dim3(1), 0, s, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_max_f64(int B, const double* a, const double* b, double* out, hipStream_t s) {
   hipLaunchKernelGGL(max_f64_kernel, dim3((B + 255) / 256), dim3(256), 0, s, B, a, b, out);
   return hipGetLastError();
