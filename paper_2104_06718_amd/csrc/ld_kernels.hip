@@ -119,14 +119,18 @@ __device__ __forceinline__ size_t lohi_index(const EpiArgs& E, size_t i0) {
   return (b / (size_t)E.row_div) * n + (i0 - b * n);
 }
 
+// EK: the epilogue kind of a launch fixed at compile time (-1: read from E.kind);
+// with kEkNoVal the per-neuron values are not written (E.want_val == 0).
+constexpr int kEkKind = 63, kEkNoVal = 64;
+
 // NA: arrays an epilogue of this launch may read (kinds that read more are not
 // launched with NA < 6; the members past NA stay zero). SHIFT: the caller's
 // elements lie in one subdomain, whose bound rows sit lohi_shift elements from i0.
-template <bool VEC, int NA = 6, bool SHIFT = false>
+template <bool VEC, int NA = 6, bool SHIFT = false, int EK = -1>
 __device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st, int nv, EpiIn& in,
                                          ptrdiff_t lohi_shift = 0) {
   const auto lohi_at = [&](size_t i) { return SHIFT ? (size_t)((ptrdiff_t)i + lohi_shift) : lohi_index(E, i); };
-  switch (E.kind) {
+  switch (EK >= 0 ? (EK & kEkKind) : E.kind) {
     case EPI_P0:
     case EPI_CROWN:
     case EPI_WK:
@@ -168,10 +172,13 @@ __device__ __forceinline__ void epi_load(const EpiArgs& E, size_t i0, size_t st,
   }
 }
 
-template <bool VEC>
+template <bool VEC, int EK = -1>
 __device__ __forceinline__ void epi_finish(const EpiArgs& E, size_t i0, size_t st, int nv, int b0, int bstep, int col,
                                            int cstep, const float (&acc)[4], const EpiIn& in) {
-  switch (E.kind) {
+  const int kind = EK >= 0 ? (EK & kEkKind) : E.kind;
+  // the values of P0 and P_k are skipped in the ascent (EK carries kEkNoVal)
+  const bool want_val = EK >= 0 && (EK & kEkNoVal) ? false : E.want_val != 0;
+  switch (kind) {
     case EPI_STORE: {
       float o[4];
 #pragma unroll
@@ -183,14 +190,14 @@ __device__ __forceinline__ void epi_finish(const EpiArgs& E, size_t i0, size_t s
 #pragma unroll
       for (int q = 0; q < 4; ++q) x[q] = acc[q] >= 0.f ? in.a1[q] : in.a0[q];
       st4_xs<VEC>(E, i0, st, nv, x);
-      if (E.want_val)
+      if (want_val)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if (VEC || q < nv) E.val[i0 + q * st] = -(double)acc[q] * (double)x[q];
     } break;
     case EPI_INNER_MIN: {
       float xb[4], x[4];
-      if (E.want_val) {
+      if (want_val) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           double xbd, xd, val;
@@ -221,7 +228,7 @@ __device__ __forceinline__ void epi_finish(const EpiArgs& E, size_t i0, size_t s
         m[q] = in.a1[q];
         v[q] = in.a2[q];
       }
-      if (E.kind == EPI_ADAM_LAST) {
+      if (kind == EPI_ADAM_LAST) {
         // inner minimisation of the last hidden layer from its constant coefficient
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -283,12 +290,12 @@ __device__ __forceinline__ void epi_finish(const EpiArgs& E, size_t i0, size_t s
   }
 }
 
-template <bool VEC>
+template <bool VEC, int EK = -1>
 __device__ __forceinline__ void epilogue4(const EpiArgs& E, size_t i0, size_t st, int nv, int b0, int bstep, int col,
                                           int cstep, const float (&acc)[4]) {
   EpiIn in{};
-  epi_load<VEC>(E, i0, st, nv, in);
-  epi_finish<VEC>(E, i0, st, nv, b0, bstep, col, cstep, acc, in);
+  epi_load<VEC, 6, false, EK>(E, i0, st, nv, in);
+  epi_finish<VEC, EK>(E, i0, st, nv, b0, bstep, col, cstep, acc, in);
 }
 
 // ---------------------------------------------------------------------------
@@ -326,7 +333,7 @@ __device__ __forceinline__ int fdiv(int e, int d, float inv) {
 // The LDS image is channel-last ([LH][LW][CP]) and k runs (tap, channel) with the
 // channels padded to a multiple of 4, so every 4 consecutive k of a lane are one
 // 16-byte LDS read.
-template <int MM, bool SRC_BF16, int TN>
+template <int MM, bool SRC_BF16, int TN, int EK = -1>
 __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, const GemmGeom* __restrict__ geo_dev,
                                                          const void* __restrict__ src_v, EpiArgs E,
                                                          int img_floats, int dst_hw4, int kp_max, int n_eff,
@@ -698,14 +705,14 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       const int j = e - col * band;
       const float4 o4 = *reinterpret_cast<const float4*>(outp + col * bandp + j);
       float v4[4] = {o4.x, o4.y, o4.z, o4.w};
-      epilogue4<true>(E, base + (size_t)col * G0.dst_HW + j, 1, 4, b, 0, col, 0, v4);
+      epilogue4<true, EK>(E, base + (size_t)col * G0.dst_HW + j, 1, 4, b, 0, col, 0, v4);
     }
   } else {
     for (int e = tid; e < nch * band; e += kConvThreads) {
       const int col = fdiv(e, band, inv_band);
       const int j = e - col * band;
       float v4[4] = {outp[col * bandp + j], 0.f, 0.f, 0.f};
-      epilogue4<false>(E, base + (size_t)col * G0.dst_HW + j, 1, 1, b, 0, col, 0, v4);
+      epilogue4<false, EK>(E, base + (size_t)col * G0.dst_HW + j, 1, 1, b, 0, col, 0, v4);
     }
   }
 }
@@ -721,7 +728,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
 // fc_split_reduce adds the partials in split order, then runs the epilogue
 // (deterministic, no cross-block synchronisation).
 // ---------------------------------------------------------------------------
-template <int TN, int MM, bool SRC_BF16>
+template <int TN, int MM, bool SRC_BF16, int EK = -1>
 __global__ __launch_bounds__(1024) void fc_kernel(GemmGeom G, const void* __restrict__ src_v, EpiArgs E, SplitArgs S,
                                                   int wm, int kw) {
   using M = Mma<(MM != 0)>;
@@ -834,9 +841,9 @@ __global__ __launch_bounds__(1024) void fc_kernel(GemmGeom G, const void* __rest
     float v4[4] = {acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
     const size_t i0 = (size_t)sub * G.dst_n + j;
     if (vec_out && nv == 4)
-      epilogue4<true>(E, i0, 1, 4, sub, 0, j, 1, v4);
+      epilogue4<true, EK>(E, i0, 1, 4, sub, 0, j, 1, v4);
     else
-      epilogue4<false>(E, i0, 1, nv, sub, 0, j, 1, v4);
+      epilogue4<false, EK>(E, i0, 1, nv, sub, 0, j, 1, v4);
   }
 }
 
@@ -893,6 +900,16 @@ size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16, in
          wbytes;
 }
 
+// The kernel of a contraction with its epilogue kind fixed at compile time for the
+// kinds of the ascent iteration (the code of the other kinds is left out, which
+// keeps the kernel small in the instruction cache), else the general one.
+template <int MM, bool SRC, int TN>
+static const void* conv_fn(int kind, int want_val) {
+  if (kind == EPI_INNER_MIN && !want_val) return (const void*)conv_plane_kernel<MM, SRC, TN, EPI_INNER_MIN | kEkNoVal>;
+  if (kind == EPI_ADAM) return (const void*)conv_plane_kernel<MM, SRC, TN, EPI_ADAM>;
+  return (const void*)conv_plane_kernel<MM, SRC, TN>;
+}
+
 template <int TN>
 static hipError_t launch_conv_tn(const GemmPack& P, const GemmGeom* geo_dev, int B, const void* src, int src_bf16,
                                  int mma_bf16, const EpiArgs& e, int parts, hipStream_t s) {
@@ -910,13 +927,13 @@ static hipError_t launch_conv_tn(const GemmPack& P, const GemmGeom* geo_dev, int
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   const void* fn;
   if (mma_bf16 == 1 && src_bf16)
-    fn = (const void*)conv_plane_kernel<1, true, TN>;
+    fn = conv_fn<1, true, TN>(e.kind, e.want_val);
   else if (mma_bf16 == 1)
-    fn = (const void*)conv_plane_kernel<1, false, TN>;
+    fn = conv_fn<1, false, TN>(e.kind, e.want_val);
   else if (mma_bf16 == 2 && !src_bf16)
-    fn = (const void*)conv_plane_kernel<2, false, TN>;
+    fn = conv_fn<2, false, TN>(e.kind, e.want_val);
   else if (mma_bf16 == 0 && !src_bf16)
-    fn = (const void*)conv_plane_kernel<0, false, TN>;
+    fn = conv_fn<0, false, TN>(e.kind, e.want_val);
   else
     return hipErrorInvalidValue;
   // the channel-last map: 16-byte pixels, every channel k reads inside the pixel
@@ -950,6 +967,14 @@ hipError_t launch_conv(const GemmGeom* geoms, const GemmGeom* geo_dev, int n, in
   return hipErrorInvalidValue;
 }
 
+template <int TN, int MM, bool SRC>
+static const void* fc_fn(int kind, int want_val) {
+  if (kind == EPI_INNER_MIN && !want_val) return (const void*)fc_kernel<TN, MM, SRC, EPI_INNER_MIN | kEkNoVal>;
+  if (kind == EPI_ADAM) return (const void*)fc_kernel<TN, MM, SRC, EPI_ADAM>;
+  if (kind == EPI_ADAM_LAST) return (const void*)fc_kernel<TN, MM, SRC, EPI_ADAM_LAST>;
+  return (const void*)fc_kernel<TN, MM, SRC>;
+}
+
 template <int TN>
 static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16, int mma_bf16, const EpiArgs& e_in,
                                const SplitArgs& sp, int wm, int kw, hipStream_t s) {
@@ -961,17 +986,24 @@ static hipError_t launch_fc_tn(const GemmGeom& G, const void* src, int src_bf16,
   const int gx = (G.M + mt - 1) / mt, gy = (G.N + 16 * TN - 1) / (16 * TN);  // subdomain blocks, neuron blocks
   dim3 grid(gx, gy, sp.splits), block(64 * wm * kw);
   const size_t lds = (size_t)(kw - 1) * wm * TN * 4 * 64 * 4;
-  if (mma_bf16 == 1) {
-    if (src_bf16)
-      hipLaunchKernelGGL((fc_kernel<TN, 1, true>), grid, block, lds, s, G, src, e, sp, wm, kw);
-    else
-      hipLaunchKernelGGL((fc_kernel<TN, 1, false>), grid, block, lds, s, G, src, e, sp, wm, kw);
-  } else if (mma_bf16 == 2) {
-    if (src_bf16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((fc_kernel<TN, 2, false>), grid, block, lds, s, G, src, e, sp, wm, kw);
-  } else {
-    if (src_bf16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((fc_kernel<TN, 0, false>), grid, block, lds, s, G, src, e, sp, wm, kw);
+  const void* fn;
+  if (mma_bf16 == 1)
+    fn = src_bf16 ? fc_fn<TN, 1, true>(e.kind, e.want_val) : fc_fn<TN, 1, false>(e.kind, e.want_val);
+  else if (mma_bf16 == 2 && !src_bf16)
+    fn = fc_fn<TN, 2, false>(e.kind, e.want_val);
+  else if (mma_bf16 == 0 && !src_bf16)
+    fn = fc_fn<TN, 0, false>(e.kind, e.want_val);
+  else
+    return hipErrorInvalidValue;
+  {
+    GemmGeom ga = G;
+    const void* sa = src;
+    EpiArgs ea = e;
+    SplitArgs spa = sp;
+    int a0 = wm, a1 = kw;
+    void* args[] = {(void*)&ga, (void*)&sa, (void*)&ea, (void*)&spa, (void*)&a0, (void*)&a1};
+    const hipError_t le = hipLaunchKernel(fn, grid, block, args, lds, s);
+    if (le != hipSuccess) return le;
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess || sp.splits <= 1) return err;
@@ -1010,7 +1042,7 @@ constexpr int kTThreads = 256;
 
 // (the register cap keeps the compiler from spending registers on the staging
 // round that would leave one wave per SIMD)
-template <bool BF, int TM>
+template <bool BF, int TM, int EK = -1>
 __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) void convT_kernel(ColGeom G, const float* __restrict__ rho, EpiArgs E, int split) {
   using M = Mma<BF>;
   typedef typename M::BFrag BFrag;
@@ -1044,9 +1076,9 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   EpiIn nx{};
   auto prefetch = [&](int e0, int e1) {
     if (vec) {
-      if (e0 + 4 * tid < e1) epi_load<true, 3, true>(E, dst_base + e0 + 4 * tid, 1, 4, nx, lshift);
+      if (e0 + 4 * tid < e1) epi_load<true, 3, true, EK>(E, dst_base + e0 + 4 * tid, 1, 4, nx, lshift);
     } else {
-      if (e0 + tid < e1) epi_load<false, 3, true>(E, dst_base + e0 + tid, 1, 1, nx, lshift);
+      if (e0 + tid < e1) epi_load<false, 3, true, EK>(E, dst_base + e0 + tid, 1, 1, nx, lshift);
     }
   };
   prefetch(c_first * G.Cc * G.HW, min(G.Ci, (c_first + 1) * G.Cc) * G.HW);
@@ -1154,7 +1186,7 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     if (vec) {
       for (int e = e0 + 4 * tid; e < e1; e += STEP) {
         const EpiIn cur = nx;
-        if (e + STEP < e1) epi_load<true, 3, true>(E, dst_base + e + STEP, 1, 4, nx, lshift);
+        if (e + STEP < e1) epi_load<true, 3, true, EK>(E, dst_base + e + STEP, 1, 4, nx, lshift);
         const int ci = fdiv(e, G.HW, G.inv_HW);
         const int rem = e - ci * G.HW;
         int y = fdiv(rem, G.W, G.inv_W);
@@ -1208,12 +1240,12 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             }
           }
         }
-        epi_finish<true>(E, dst_base + e, 1, 4, b, 0, ci, 0, v4, cur);
+        epi_finish<true, EK>(E, dst_base + e, 1, 4, b, 0, ci, 0, v4, cur);
       }
     } else {
       for (int e = e0 + tid; e < e1; e += kTThreads) {
         const EpiIn cur = nx;
-        if (e + kTThreads < e1) epi_load<false, 3, true>(E, dst_base + e + kTThreads, 1, 1, nx, lshift);
+        if (e + kTThreads < e1) epi_load<false, 3, true, EK>(E, dst_base + e + kTThreads, 1, 1, nx, lshift);
         const int ci = fdiv(e, G.HW, G.inv_HW);
         const int rem = e - ci * G.HW;
         const int y = fdiv(rem, G.W, G.inv_W);
@@ -1225,7 +1257,7 @@ __global__ __launch_bounds__(kTThreads) __attribute__((amdgpu_waves_per_eu(4))) 
           for (int ib = 0; ib < cx[x]; ++ib) sum += Y[oy + tx[x * G.Tmax + ib]];
         }
         float v4[4] = {sum, 0.f, 0.f, 0.f};
-        epi_finish<false>(E, dst_base + e, 1, 1, b, 0, ci, 0, v4, cur);
+        epi_finish<false, EK>(E, dst_base + e, 1, 1, b, 0, ci, 0, v4, cur);
       }
     }
     __syncthreads();
@@ -1245,6 +1277,13 @@ size_t convT_lds_bytes(const ColGeom& g, int split) {
   return a > b ? a : b;
 }
 
+template <bool BF, int TM>
+static const void* convT_fn(int kind, int want_val) {
+  if (kind == EPI_P0 && !want_val) return (const void*)convT_kernel<BF, TM, EPI_P0 | kEkNoVal>;
+  if (kind == EPI_INNER_MIN && !want_val) return (const void*)convT_kernel<BF, TM, EPI_INNER_MIN | kEkNoVal>;
+  return (const void*)convT_kernel<BF, TM>;
+}
+
 hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16, const EpiArgs& e, int split,
                         hipStream_t s) {
   if (B == 0) return hipSuccess;
@@ -1255,11 +1294,11 @@ hipError_t launch_convT(const ColGeom& g, int B, const float* rho, int mma_bf16,
   // tap loops of fixed length where every row and column takes at most one or two taps
   const void* fn;
   if (g.Tmax == 1)
-    fn = mma_bf16 ? (const void*)convT_kernel<true, 1> : (const void*)convT_kernel<false, 1>;
+    fn = mma_bf16 ? convT_fn<true, 1>(e.kind, e.want_val) : convT_fn<false, 1>(e.kind, e.want_val);
   else if (g.Tmax == 2)
-    fn = mma_bf16 ? (const void*)convT_kernel<true, 2> : (const void*)convT_kernel<false, 2>;
+    fn = mma_bf16 ? convT_fn<true, 2>(e.kind, e.want_val) : convT_fn<false, 2>(e.kind, e.want_val);
   else
-    fn = mma_bf16 ? (const void*)convT_kernel<true, 0> : (const void*)convT_kernel<false, 0>;
+    fn = mma_bf16 ? convT_fn<true, 0>(e.kind, e.want_val) : convT_fn<false, 0>(e.kind, e.want_val);
   if (lds > 64 * 1024) {
     hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (err != hipSuccess) return err;
