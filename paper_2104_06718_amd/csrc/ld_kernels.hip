@@ -371,7 +371,9 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   const int Cq = (C + 3) & ~3;  // channels of a pixel that k reads (the ones past C are zero)
   float* outp = img + img_floats;                          // [channels][band]
   int* kofs = reinterpret_cast<int*>(outp + out_floats);   // [n classes][kp_max]
-  WT* wB = reinterpret_cast<WT*>(lds + ((img_floats + out_floats + P.n * kp_max + 3) & ~3));  // [n classes][n_eff][bstride], 16-byte aligned
+  // per class {first pixel, pixel end, MFMA items, items of the classes before}, 16-byte aligned
+  int* ctab = reinterpret_cast<int*>(lds + ((img_floats + out_floats + P.n * kp_max + 3) & ~3));
+  WT* wB = reinterpret_cast<WT*>(ctab + 4 * P.n);  // [n classes][n_eff][bstride], 16-byte aligned
   WT* wBl = wB + (size_t)P.n * n_eff * bstride;  // MM == 2: the BF16 remainders, same layout
   auto put = [&](int idx, float v) __attribute__((always_inline)) {
     if constexpr (MM == 0) {
@@ -480,14 +482,9 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   }
   load_classes(0);
   adam_tick(E);
-  // (b) their LDS writes, and the zero border of the image (disjoint from the interior:
-  //     border pixels, all Cq channels; the CP - Cq floats past them are never read)
-  if (vec_img) {
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (tid + u * kConvThreads < n4) store_img4(tid + u * kConvThreads, v0[u]);
-  }
-  store_classes(0);
+  // (b) while the loads are in flight: the zero border of the image (disjoint from
+  //     the interior: border pixels, all Cq channels; the CP - Cq floats past them are
+  //     never read), and the table of the MFMA items of every class (one thread)
   {
     const float inv_lw = 1.0f / (float)G0.LW;
     const int c4 = Cq >> 2;
@@ -504,7 +501,30 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
       }
     }
   }
-  // (c) further rounds
+  if (tid == 0) {
+    int before = 0;
+    for (int cl = 0; cl < P.n; ++cl) {
+      const GemmGeom& Gc = P.g[cl];
+      // the class rows yq whose destination rows yq*oy_mul + oy_off fall in [R0, R1)
+      const int yq_lo = R0 - Gc.oy_off <= 0 ? 0 : (R0 - Gc.oy_off + Gc.oy_mul - 1) / Gc.oy_mul;
+      const int yq_hi = min(Gc.HWq / Gc.Wq, R1 - Gc.oy_off <= 0 ? 0 : (R1 - Gc.oy_off + Gc.oy_mul - 1) / Gc.oy_mul);
+      const int p_lo = yq_lo * Gc.Wq, p_hi = max(p_lo, yq_hi * Gc.Wq);
+      const int ntiles = (p_hi - p_lo + 15) >> 4;
+      const int nct = (Gc.N + 16 * TN - 1) / (16 * TN);
+      // items: (pair of tiles, column chunk)
+      const int total = ((ntiles + 1) >> 1) * nct;
+      *reinterpret_cast<int4*>(ctab + 4 * cl) = make_int4(p_lo, p_hi, total, before);
+      before += total;
+    }
+  }
+  // (c) the LDS writes of the first round
+  if (vec_img) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (tid + u * kConvThreads < n4) store_img4(tid + u * kConvThreads, v0[u]);
+  }
+  store_classes(0);
+  // (d) further rounds
   for (int c0 = kStageClasses; c0 < P.n; c0 += kStageClasses) {
     class_scalars(c0);
     load_classes(c0);
@@ -554,9 +574,16 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   }
   __syncthreads();
 
-  // 2. MFMA tiles of every class into the LDS destination map
-  int tiles_before = 0;
+  // 2. MFMA tiles of every class into the LDS destination map; items (pair of tiles,
+  //    column chunk) are dealt to the waves continuing the rotation across classes,
+  //    and a wave skips the classes that hold none of its items
   for (int cl = 0; cl < P.n; ++cl) {
+    const int4 ct = *reinterpret_cast<const int4*>(ctab + 4 * cl);
+    const int p_lo = __builtin_amdgcn_readfirstlane(ct.x), p_hi = __builtin_amdgcn_readfirstlane(ct.y);
+    const int total = __builtin_amdgcn_readfirstlane(ct.z), tiles_before = __builtin_amdgcn_readfirstlane(ct.w);
+    int first = (wave - tiles_before) % kConvWaves;
+    if (first < 0) first += kConvWaves;
+    if (first >= total) continue;
     // the class geometry from the kernel arguments (uniform: scalar loads)
     const GemmGeom& Gl = P.g[cl];
     struct {
@@ -583,20 +610,10 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
     const WT* wc = wB + (size_t)cl * n_eff * bstride;
     const WT* wcl = wBl + (size_t)cl * n_eff * bstride;
     const float inv_wq = 1.0f / (float)G.Wq;
-    // the class rows yq whose destination rows yq*oy_mul + oy_off fall in [R0, R1)
-    const int yq_lo = R0 - G.oy_off <= 0 ? 0 : (R0 - G.oy_off + G.oy_mul - 1) / G.oy_mul;
-    const int yq_hi = min(G.HWq / G.Wq, R1 - G.oy_off <= 0 ? 0 : (R1 - G.oy_off + G.oy_mul - 1) / G.oy_mul);
-    const int p_lo = yq_lo * G.Wq, p_hi = max(p_lo, yq_hi * G.Wq);
-    const int ntiles = (p_hi - p_lo + 15) >> 4;
     const int nct = (G.N + 16 * TN - 1) / (16 * TN);
     const int j_band = R0 * G.dst_W;
-    // distribute (pair of tiles, column chunk) items over the waves, continuing the
-    // rotation across classes; a wave multiplies two 16-pixel tiles against each
-    // weight fragment it reads (the second tile of an odd count is empty)
-    const int npairs = (ntiles + 1) >> 1;
-    const int total = npairs * nct;
-    int first = (wave - tiles_before) % kConvWaves;
-    if (first < 0) first += kConvWaves;
+    // a wave multiplies two 16-pixel tiles against each weight fragment it reads
+    // (the second tile of an odd count is empty)
     for (int w = first; w < total; w += kConvWaves) {
       const int pair = w / nct;
       const int nc = (w - pair * nct) * 16 * TN;
@@ -691,7 +708,6 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
         }
       }
     }
-    tiles_before += total;
   }
   __syncthreads();
 
@@ -895,8 +911,8 @@ static int conv_out_floats(const GemmGeom& g, int parts) {
 size_t conv_lds_bytes(const GemmGeom* g, int n_classes, int tn, int mma_bf16, int parts) {
   // BF16 weights (mode 1), FP32 (0), or BF16 heads and remainders (2)
   const size_t wbytes = (size_t)n_classes * conv_n_eff(g[0], tn) * conv_bstride(g, n_classes, mma_bf16) * (mma_bf16 == 1 ? 2 : 4);
-  return (((size_t)conv_img_floats(g[0]) + conv_out_floats(g[0], parts) +
-           (size_t)n_classes * max_kp(g, n_classes) + 3) & ~(size_t)3) * 4 +
+  return ((((size_t)conv_img_floats(g[0]) + conv_out_floats(g[0], parts) +
+            (size_t)n_classes * max_kp(g, n_classes) + 3) & ~(size_t)3) + 4 * (size_t)n_classes) * 4 +
          wbytes;
 }
 
