@@ -574,6 +574,17 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   }
   __syncthreads();
 
+  // the operands of the thread's first epilogue group, in flight during the products
+  // (the epilogue reads and writes them only in that thread, after the products)
+  const size_t base = (size_t)b * G0.dst_n + (size_t)R0 * G0.dst_W;
+  const int nch = G0.dst_n / G0.dst_HW;
+  const float inv_band = 1.0f / (float)band;
+  EpiIn pre{};
+  if (dst_hw4 && 4 * tid < nch * band) {
+    const int col = fdiv(4 * tid, band, inv_band);
+    const int j = 4 * tid - col * band;
+    epi_load<true, 6, false, EK>(E, base + (size_t)col * G0.dst_HW + j, 1, 4, pre);
+  }
   // 2. MFMA tiles of every class into the LDS destination map; items (pair of tiles,
   //    column chunk) are dealt to the waves continuing the rotation across classes,
   //    and a wave skips the classes that hold none of its items
@@ -712,16 +723,16 @@ __global__ __launch_bounds__(kConvThreads) void conv_plane_kernel(GemmPack P, co
   __syncthreads();
 
   // 3. epilogue over the band of the destination map in memory order
-  const size_t base = (size_t)b * G0.dst_n + (size_t)R0 * G0.dst_W;
-  const int nch = G0.dst_n / G0.dst_HW;
-  const float inv_band = 1.0f / (float)band;
   if (dst_hw4) {
     for (int e = 4 * tid; e < nch * band; e += 4 * kConvThreads) {
       const int col = fdiv(e, band, inv_band);  // channel (four consecutive neurons share it)
       const int j = e - col * band;
       const float4 o4 = *reinterpret_cast<const float4*>(outp + col * bandp + j);
       float v4[4] = {o4.x, o4.y, o4.z, o4.w};
-      epilogue4<true, EK>(E, base + (size_t)col * G0.dst_HW + j, 1, 4, b, 0, col, 0, v4);
+      const size_t i0 = base + (size_t)col * G0.dst_HW + j;
+      EpiIn in = pre;
+      if (e != 4 * tid) epi_load<true, 6, false, EK>(E, i0, 1, 4, in);
+      epi_finish<true, EK>(E, i0, 1, 4, b, 0, col, 0, v4, in);
     }
   } else {
     for (int e = tid; e < nch * band; e += kConvThreads) {
