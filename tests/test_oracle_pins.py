@@ -531,3 +531,35 @@ def test_best_bound_not_below_initial():
     fb = O.final_bound(net, batch, st)
     assert bool((fb["bound"] >= st["q0"]).all())
     assert bool((fb["bound"] >= fb["q_final"]).all())
+
+
+def test_subdomains_do_not_interact():
+    """The ascent of a batch equals each subdomain's ascent alone (the dual of
+    eq:nonprox_problem separates over subdomains; the GPU's batching relies on it)."""
+    inst, net, batch = _setup("tiny_conv")
+    opts = O.AdamOpts(T=30)
+    full = O.ascent(net, batch, opts)
+    fb = O.final_bound(net, batch, full)
+    for b in (0, inst.B // 2, inst.B - 1):
+        sub = O.batch_from_instance(inst, [b])
+        one = O.ascent(net, sub, opts)
+        for a, c in zip(full["rho"], one["rho"]):
+            assert torch.allclose(a[b:b + 1], c, rtol=0, atol=1e-9)
+        ob = O.final_bound(net, sub, one)
+        assert abs(fb["bound"][b].item() - ob["bound"][0].item()) <= 1e-9
+
+
+def test_given_duals_are_used_as_given():
+    """An ascent from caller-given duals equal to the CROWN duals is the CROWN ascent,
+    and one from other given duals starts there (q0 is their dual value)."""
+    inst, net, batch = _setup("tiny_conv")
+    rho0 = O.crown_init(net, batch)
+    a = O.ascent(net, batch, O.AdamOpts(T=20))
+    g = O.ascent(net, batch, O.AdamOpts(T=20, init="given"), rho0=rho0)
+    for x, y in zip(a["rho"], g["rho"]):
+        assert torch.equal(x, y)
+    other = [0.5 * r for r in rho0]
+    h = O.ascent(net, batch, O.AdamOpts(T=20, init="given"), rho0=other, iters=0)
+    assert torch.equal(h["q0"], O.dual_eval(net, batch, other, need_supergrad=False)["q"])
+    for x, y in zip(h["rho"], other):
+        assert torch.equal(x, y)
