@@ -75,6 +75,11 @@ struct Job {
   const GemmGeom* dev = nullptr;  // device copy of geoms
   bool has_col = false;   // transposed strided conv: dense GEMM + col2im form
   ColGeom col;
+  // the same form with more, smaller channel chunks looped in one block (LDS within a
+  // quarter of a CU), for the BF16 operands: such a block shares a CU with the
+  // compensated products of the phase's other layers
+  bool has_col_q = false;
+  ColGeom col_q;
   // the same form with one block per (subdomain, channel chunk), for several chunk counts
   std::vector<ColGeom> col_split;
 };
@@ -451,6 +456,13 @@ int build_col(ld_net* net, Layer& L, const float* W) {
   LD_TRY(materialise(with_chunks(pick), &g));
   L.tr.col = g;
   L.tr.has_col = true;
+  for (int nch = pick + 1; nch <= Ci; ++nch) {
+    const ColGeom t = with_chunks(nch);
+    if (t.Cc == with_chunks(nch - 1).Cc || convT_lds_bytes(t, 0) > kConvTHalfCU / 2) continue;
+    LD_TRY(materialise(t, &L.tr.col_q));
+    L.tr.has_col_q = true;
+    break;
+  }
   // one block per chunk: 2, 3, 4 and 8 chunks (as the channels allow), each block's
   // LDS within a quarter of a CU
   L.tr.col_split.clear();
@@ -769,7 +781,7 @@ hipError_t run_job(const Job& J, int B, const void* src, int src_bf16, int mma, 
     if (t.splits > 1)
       for (const ColGeom& v : J.col_split)
         if (v.nchunks == t.splits) return launch_convT(v, B, (const float*)src, mma, e, 1, s);
-    return launch_convT(J.col, B, (const float*)src, mma, e, 0, s);
+    return launch_convT(mma == 1 && J.has_col_q ? J.col_q : J.col, B, (const float*)src, mma, e, 0, s);
   }
   if (job_is_conv(J)) {
     // bands of destination rows: a tile of the col2im form counts channel chunks, so
