@@ -456,7 +456,7 @@ int build_col(ld_net* net, Layer& L, const float* W) {
   LD_TRY(materialise(with_chunks(pick), &g));
   L.tr.col = g;
   L.tr.has_col = true;
-  for (int nch = pick + 1; nch <= Ci; ++nch) {
+  for (int nch = pick + 1; nch <= Ci && convT_lds_bytes(g, 0) > kConvTHalfCU / 2; ++nch) {
     const ColGeom t = with_chunks(nch);
     if (t.Cc == with_chunks(nch - 1).Cc || convT_lds_bytes(t, 0) > kConvTHalfCU / 2) continue;
     LD_TRY(materialise(t, &L.tr.col_q));
